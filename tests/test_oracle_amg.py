@@ -1,0 +1,267 @@
+"""Pins of the oracle's smoothed-aggregation AMG (Sec. 4.1 preconditioner).
+
+The paper fixes smoothed aggregation, 1+1 symmetric Gauss-Seidel and a
+Hermitian AMG_k; the remaining choices are readings (oracle/amg.c header).
+These tests check every reading against an independent statement of it:
+parallel-round versions of the greedy algorithms, dense linear algebra for
+the transfer and Galerkin operators, and operator properties of the V-cycle.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import shortest_path
+
+import oracle
+from paper_1204_5125_amd import inputs
+
+
+def fmix32(h):
+    h = np.uint64(h) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(16)
+    h = (h * np.uint64(0x85EBCA6B)) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(13)
+    h = (h * np.uint64(0xC2B2AE35)) & np.uint64(0xFFFFFFFF)
+    h ^= h >> np.uint64(16)
+    return int(h)
+
+
+def keys(n, salt):
+    s = (0x9E3779B9 * salt) & 0xFFFFFFFF
+    return [(fmix32(i ^ s) << 32) | i for i in range(n)]
+
+
+def neighbours(A):
+    A = sp.csr_matrix(A)
+    return [[j for j in A.indices[A.indptr[i]:A.indptr[i + 1]] if j != i] for i in range(A.shape[0])]
+
+
+def parallel_mis2(nb, key):
+    """Rounds: an undecided node joins when its key is the largest among the
+    undecided nodes within distance 2; nodes within distance 2 of a new root
+    are removed."""
+    n = len(nb)
+    state = [0] * n  # 0 undecided, 1 root, 2 removed
+    while any(s == 0 for s in state):
+        ball2 = []
+        for i in range(n):
+            b = {i} | set(nb[i])
+            for j in nb[i]:
+                b |= set(nb[j])
+            ball2.append(b)
+        new = [i for i in range(n) if state[i] == 0 and
+               all(key[i] >= key[j] for j in ball2[i] if state[j] == 0)]
+        for i in new:
+            state[i] = 1
+        for i in new:
+            for j in ball2[i]:
+                if state[j] == 0:
+                    state[j] = 2
+    return sorted(i for i in range(n) if state[i] == 1)
+
+
+def jones_plassmann(nb, key):
+    n = len(nb)
+    col = [-1] * n
+    while any(c < 0 for c in col):
+        ready = [i for i in range(n) if col[i] < 0 and
+                 all(col[j] >= 0 or key[j] < key[i] for j in nb[i])]
+        for i in ready:
+            used = {col[j] for j in nb[i] if col[j] >= 0}
+            c = 0
+            while c in used:
+                c += 1
+            col[i] = c
+    return col
+
+
+def hierarchy_cases():
+    m2 = oracle.Mesh(2, (17, 17), (5.0, 5.0), mu=0.8)
+    m3 = oracle.Mesh(3, (6, 6, 6), (5.0, 5.0, 5.0), mu=0.6, bdir=np.ones(3) / np.sqrt(3))
+    return [(m2, inputs.random_phase_state(m2.n, seed=0)),
+            (m3, inputs.random_phase_state(m3.n, seed=1))]
+
+
+@pytest.fixture(scope="module")
+def hierarchies():
+    out = []
+    for m, psi in hierarchy_cases():
+        out.append((m, psi, oracle.Amg.for_state(m, psi, max_coarse=10)))
+    return out
+
+
+def test_aggregation_invariants(hierarchies):
+    """Aggregates partition the nodes, roots are pairwise at distance >= 3, every
+    node lies within distance 2 of its root, and numbering follows the roots."""
+    for m, psi, amg in hierarchies:
+        assert amg.nlev >= 3
+        for l, L in enumerate(amg.levels[:-1]):
+            agg, root, n, nc = L["agg"], L["root"], L["n"], L["nc"]
+            assert agg.min() >= 0 and agg.max() == nc - 1
+            assert np.all(np.diff(root) > 0)
+            assert np.array_equal(agg[root], np.arange(nc))
+            G = L["A"].copy()
+            G.setdiag(0)
+            G.eliminate_zeros()
+            G = sp.csr_matrix((np.ones(G.nnz), G.indices, G.indptr), shape=G.shape)
+            D = shortest_path(G, unweighted=True, indices=root)
+            Dr = D[:, root]
+            np.fill_diagonal(Dr, np.inf)
+            assert Dr.min() >= 3
+            assert np.all(D[agg, np.arange(n)] <= 2)
+            assert np.all(D.min(axis=0) <= 2)
+
+
+def test_mis2_greedy_equals_parallel_rounds(hierarchies):
+    """The serial greedy (decreasing key) roots equal the roots of the parallel
+    rounds with the same hash priorities, on every level."""
+    for m, psi, amg in hierarchies:
+        for l, L in enumerate(amg.levels[:-1]):
+            if L["n"] > 400:
+                continue
+            nb = neighbours(L["A"])
+            roots = parallel_mis2(nb, keys(L["n"], l + 1))
+            assert roots == list(L["root"])
+
+
+def test_aggregate_assignment_rules(hierarchies):
+    """Phase A: neighbours of a root join it.  Phase B: the rest join the
+    phase-A neighbour whose root has the largest key."""
+    for m, psi, amg in hierarchies:
+        for l, L in enumerate(amg.levels[:-1]):
+            nb = neighbours(L["A"])
+            key = keys(L["n"], l + 1)
+            root = set(L["root"].tolist())
+            rootA = {}
+            for i in range(L["n"]):
+                if i in root:
+                    rootA[i] = i
+                else:
+                    rs = [j for j in nb[i] if j in root]
+                    assert len(rs) <= 1
+                    if rs:
+                        rootA[i] = rs[0]
+            root_of = np.full(L["n"], -1)
+            for i in range(L["n"]):
+                if i in rootA:
+                    root_of[i] = rootA[i]
+                else:
+                    cands = [rootA[j] for j in nb[i] if j in rootA]
+                    root_of[i] = max(cands, key=lambda r: key[r])
+            idx = {r: a for a, r in enumerate(L["root"])}
+            assert np.array_equal(L["agg"], np.array([idx[r] for r in root_of]))
+
+
+def test_colouring_proper_and_greedy(hierarchies):
+    """Level 0 of a grid: red-black parity; coarser levels: proper colourings
+    equal to Jones-Plassmann rounds with the colour priorities."""
+    for m, psi, amg in hierarchies:
+        L0 = amg.levels[0]
+        idx = np.stack(np.unravel_index(np.arange(m.n), m.N[::-1])[::-1], axis=1)
+        assert np.array_equal(L0["color"], idx.sum(axis=1) % 2)
+        for l, L in enumerate(amg.levels):
+            A = sp.coo_matrix(L["A"])
+            off = A.row != A.col
+            assert np.all(L["color"][A.row[off]] != L["color"][A.col[off]])
+            assert L["ncolors"] == L["color"].max() + 1
+            if l > 0 and L["n"] <= 400:
+                assert jones_plassmann(neighbours(L["A"]), keys(L["n"], l + 101)) == list(L["color"])
+
+
+def test_transfer_and_galerkin_operators(hierarchies):
+    """P = T - omega D^-1 A T with T = 1/sqrt(|a|) on the aggregates and
+    omega = (4/3)/max_i sum_j |A_ij|/A_ii; R = P^H; A_{l+1} = R A P exactly
+    Hermitian with real diagonal; pattern of P = pattern of T u A T."""
+    for m, psi, amg in hierarchies:
+        for l, L in enumerate(amg.levels[:-1]):
+            A = L["A"].toarray()
+            n, nc = L["n"], L["nc"]
+            T = np.zeros((n, nc))
+            sizes = np.bincount(L["agg"], minlength=nc)
+            T[np.arange(n), L["agg"]] = 1 / np.sqrt(sizes[L["agg"]])
+            d = np.diag(A).real
+            rho = (np.abs(A).sum(axis=1) / d).max()
+            assert L["omega"] == pytest.approx(4 / 3 / rho, rel=1e-14)
+            P = T - (L["omega"] / d)[:, None] * (A @ T)
+            np.testing.assert_allclose(L["P"].toarray(), P, rtol=1e-12, atol=1e-13)
+            struct = ((np.abs(A) > 0).astype(int) @ (T > 0).astype(int) + (T > 0)) > 0
+            assert np.array_equal(L["P"].toarray() != 0, struct) or \
+                np.array_equal(sp.csr_matrix(struct.astype(float)).indices, L["P"].indices)
+            assert np.array_equal(L["R"].toarray(), L["P"].toarray().conj().T)
+            Ac = amg.levels[l + 1]["A"].toarray()
+            np.testing.assert_allclose(Ac, P.conj().T @ A @ P, rtol=1e-11, atol=1e-12 * np.abs(Ac).max())
+            assert np.array_equal(Ac, Ac.conj().T)
+
+
+def test_sgs_is_symmetric_gauss_seidel(hierarchies):
+    """One sweep from x = 0 equals (D+U)^-1 D (D+L)^-1 b in the colour order,
+    the symmetric Gauss-Seidel operator."""
+    m, psi, amg = hierarchies[0]
+    for l in (0, 1):
+        L = amg.levels[l]
+        A = L["A"].toarray()
+        perm = np.argsort(L["color"], kind="stable")
+        Ap = A[np.ix_(perm, perm)]
+        Dg = np.diag(np.diag(Ap))
+        Lo, Up = np.tril(Ap, -1), np.triu(Ap, 1)
+        S = np.linalg.solve(Dg + Up, Dg @ np.linalg.inv(Dg + Lo))
+        b = inputs.random_complex(L["n"], seed=l)
+        x = amg.sgs(l, np.zeros(L["n"]), b)
+        np.testing.assert_allclose(x[perm], S @ b[perm], rtol=1e-11, atol=1e-12)
+
+
+def vcycle_matrix(amg, n, cycles=1):
+    cols = []
+    for k in range(n):
+        e = np.zeros(n, complex)
+        e[k] = 1.0
+        cols.append(amg.solve(e, cycles))
+    return np.array(cols).T
+
+
+def test_vcycle_hermitian_positive_definite_contracting():
+    """AMG_1 is Hermitian (Sec. 4.1) and positive definite; the two-level
+    error propagator I - V H contracts."""
+    m = oracle.Mesh(2, (9, 9), (5.0, 5.0), mu=0.8)
+    psi = inputs.random_phase_state(m.n, seed=0)
+    amg = oracle.Amg.for_state(m, psi, max_coarse=20)
+    assert amg.nlev == 2
+    H = m.hmat(psi).toarray()
+    V = vcycle_matrix(amg, m.n)
+    assert np.abs(V - V.conj().T).max() < 1e-13 * np.abs(V).max()
+    assert np.linalg.eigvalsh(0.5 * (V + V.conj().T)).min() > 0
+    rho = np.abs(np.linalg.eigvals(np.eye(m.n) - V @ H)).max()
+    assert rho < 0.5
+
+
+def test_single_level_is_exact_inverse():
+    """A hierarchy with one level solves the coarse problem by Cholesky, i.e.
+    applies H^-1 exactly."""
+    m = oracle.Mesh(2, (6, 6), (5.0, 5.0), mu=0.8)
+    psi = inputs.random_phase_state(m.n, seed=2)
+    amg = oracle.Amg.for_state(m, psi, max_coarse=64)
+    assert amg.nlev == 1
+    H = m.hmat(psi).toarray()
+    b = inputs.random_complex(m.n, seed=3)
+    np.testing.assert_allclose(amg.solve(b), np.linalg.solve(H, b), rtol=1e-12, atol=1e-12)
+
+
+def test_cycles_converge_to_inverse():
+    """R_k -> R_inf = H^-1 D as k grows (eq. prec1; the paper's k = 10 is R_inf
+    to machine precision)."""
+    m = oracle.Mesh(2, (17, 17), (5.0, 5.0), mu=0.8)
+    psi = inputs.random_phase_state(m.n, seed=4)
+    amg = oracle.Amg.for_state(m, psi, max_coarse=10)
+    H = m.hmat(psi).toarray()
+    b = inputs.random_complex(m.n, seed=5)
+    ref = np.linalg.solve(H, b)
+    errs = [np.linalg.norm(amg.solve(b, k) - ref) / np.linalg.norm(ref) for k in (1, 2, 5, 40)]
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[3] < 1e-12
+
+
+def test_singular_preconditioner_detected():
+    """psi = 0 with A = 0 makes H singular (Sec. 4.1): the coarse Cholesky fails."""
+    m = oracle.Mesh(2, (9, 9), (5.0, 5.0), mu=0.0)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Amg.for_state(m, np.zeros(m.n))
+    assert e.value.code == oracle.ORC_ERR_SINGULAR
