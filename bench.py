@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Jacobian-solve benchmark on one MI355X.
+
+Workload (one "step"): the 2D 1025 x 1025 grid (1,050,625 nodes), side 10,
+uniform field mu = 1 along z, psi0 = 0.9 exp(i theta) with theta ~ U[0, 2 pi)
+from seed 0; four Newton steps from psi0, each one preconditioned MINRES solve
+of the Jacobian system to relative residual 1e-10 (preconditioner numeric
+setup, MINRES, update, GL residual).  The hierarchy's grid-only part is built
+once during warm-up.  The headline value uses the FP32 V-cycle under the FP64
+outer iteration; the all-FP64 path is timed beside it.
+
+Prints one JSON line.  Roofline: the dominant kernel's algorithmic bytes per
+launch over its HIP-event-measured average duration in an identical timed
+pass.  cpu_baseline: the plain C oracle on this host, one Newton step of the
+same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Jacobian solves/s + HBM GB/s at 1M nodes, FP32-precond vs FP64 at 1e-10"
+HBM_PEAK_GBS = 8000.0
+N_AXIS = (1025, 1025)
+SIDE = (10.0, 10.0)
+MU = 1.0
+NEWTON_STEPS = 4
+RTOL = 1e-10
+KERNEL_NAMES = {1: "k_minres_japply", 2: "k_l0_sgs", 3: "k_l0_residual", 4: "k_csr_spmv (level 0)",
+                5: "k_minres_vupdate", 6: "k_minres_wx", 7: "k_gl_residual"}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+MAX_COARSE = 512
+
+
+def run_steps(glnk, torch, mesh, psi0, psi, handle, precision, steps):
+    infos = []
+    for _ in range(steps):
+        psi.copy_(psi0)
+        rc, info = glnk.gl_newton_solve(mesh, psi, fixed_steps=NEWTON_STEPS, krylov_rtol=RTOL,
+                                        krylov_max_iter=4000, poll_every=16, precision=precision,
+                                        max_coarse=MAX_COARSE, precond=handle)
+        infos.append(info)
+    return infos
+
+
+def timed(glnk, torch, mesh, psi0, psi, handle, precision, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = run_steps(glnk, torch, mesh, psi0, psi, handle, precision, steps)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, infos
+
+
+def cpu_baseline():
+    """One Newton step (preconditioner setup + MINRES to 1e-10 + update) of the
+    same workload with the serial C oracle."""
+    import numpy as np
+
+    import oracle
+    from paper_1204_5125_amd import inputs
+    m = oracle.Mesh(2, N_AXIS, SIDE, mu=MU)
+    psi0 = inputs.random_phase_state(m.n, seed=0)
+    t0 = time.perf_counter()
+    psi, info = oracle.newton(m, psi0, fixed_steps=1, krylov_rtol=RTOL, krylov_max_iter=4000,
+                              max_coarse=MAX_COARSE)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one Newton step (AMG setup + MINRES to 1e-10, {info['krylov_iters'][0]} "
+                      f"iterations) on the same 1025x1025 grid from the same psi0: {dt:.1f} s, "
+                      f"serial C (one host core)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernel", type=int, default=2,
+                    help="internal kernel id for the roofline (see gl_profile_start)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is a design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1204_5125_amd import glnk, inputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    mesh = glnk.Mesh(2, N_AXIS, SIDE, mu=MU)
+    psi0 = torch.from_numpy(inputs.random_phase_state(mesh.n, seed=0)).cuda()
+    psi = torch.empty_like(psi0)
+    h32, h64 = glnk.PrecondHandle(mesh), glnk.PrecondHandle(mesh)
+
+    log(f"[bench] grid {N_AXIS} n={mesh.n}; warm-up {args.warmup} step(s)")
+    run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, max(1, args.warmup))
+    run_steps(glnk, torch, mesh, psi0, psi, h64, glnk.GL_FP64, max(1, args.warmup))
+
+    log(f"[bench] timing {args.steps} step(s), FP32 preconditioner")
+    t32, info32 = timed(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, args.steps)
+    final_res32 = info32[-1]["res"][-1]
+    log(f"[bench] FP32: {t32:.3f} s, krylov iterations {info32[-1]['krylov_iters']}")
+    log(f"[bench] timing {args.steps} step(s), FP64 preconditioner")
+    t64, info64 = timed(glnk, torch, mesh, psi0, psi, h64, glnk.GL_FP64, args.steps)
+    log(f"[bench] FP64: {t64:.3f} s, krylov iterations {info64[-1]['krylov_iters']}")
+
+    solves = NEWTON_STEPS * args.steps
+    value = solves / t32
+
+    # roofline of the dominant kernel: an identical pass with its launches timed by HIP events
+    log(f"[bench] profiling kernel {args.profile_kernel} ({KERNEL_NAMES.get(args.profile_kernel)})")
+    glnk.gl_profile_start(args.profile_kernel)
+    run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, args.steps)
+    ms, nbytes, launches = glnk.gl_profile_stop()
+    avg_ms = ms / max(1, launches)
+    achieved = (nbytes / max(1, launches)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+
+    iters32 = info32[-1]["krylov_iters"]
+    iters64 = info64[-1]["krylov_iters"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (outer) / f32 (V-cycle)",
+        "data": "synthetic: seeded random-phase psi0 on a uniform grid",
+        "config": {"workload": "2D 1025x1025 grid (1,050,625 nodes), side 10, mu 1.0 along z; "
+                               "4 Newton steps from psi0 = 0.9 exp(i theta), seed 0, each one "
+                               "Jacobian solve by MINRES + R_1 (SA-AMG V-cycle) to rtol 1e-10",
+                   "nodes": mesh.n, "newton_steps": NEWTON_STEPS, "precond": "fp32",
+                   "amg_max_coarse": MAX_COARSE},
+        "krylov_iters_per_solve": iters32,
+        "final_gl_residual": final_res32,
+        "fp64_precond": {"value": solves / t64, "unit": "solves/s", "ms_per_step": 1e3 * t64 / args.steps,
+                         "krylov_iters_per_solve": iters64},
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES.get(args.profile_kernel),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * avg_ms, "launches": launches,
+                     "bytes_per_launch": nbytes / max(1, launches)},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle, one Newton step)")
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

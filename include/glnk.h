@@ -1,0 +1,234 @@
+/*
+ * glnk -- Jacobian solves for the discretised extreme type-II Ginzburg-Landau
+ * problem on one AMD MI355X (gfx950).
+ *
+ * Method: N. Schloemer, W. Vanroose, "An optimal linear solver for the
+ * Jacobian system of the extreme type-II Ginzburg-Landau problem".
+ *   - discretisation (Sec. 3): Voronoi volumes |V_i| (D = diag|V_i|), edge
+ *     coefficients alpha_jk, link variables U_jk, Hermitian K-hat with
+ *     K = D^-1 K-hat (Remark on K = D^-1 K-hat);
+ *   - GL_i(psi) = (K psi)_i - psi_i (1 - |psi_i|^2)          (eq. discr ginla)
+ *   - (J(psi) phi)_i = (K phi)_i + (2|psi_i|^2 - 1) phi_i + psi_i^2 conj(phi_i)
+ *                                               (discrete Jacobian, Sec. 3)
+ *   - Newton: J(psi) dpsi = -GL(psi)                      (eq. Newton system)
+ *   - MINRES in <u,v>_R = Re sum |V_i| conj(u_i) v_i       (Sec. 4, eq. disc inner2)
+ *   - preconditioner R_k = AMG_k(K-hat + 2 D |psi|^2, D .) (eq. prec2),
+ *     smoothed aggregation, 1 pre + 1 post symmetric Gauss-Seidel (Sec. 4.1).
+ *
+ * Conventions shared by every call:
+ *   - Vectors are DEVICE pointers to n complex numbers stored as interleaved
+ *     (re, im) doubles (the layout of torch.complex128 / std::complex<double>),
+ *     node order x fastest, then y, then z.  The caller owns them; they must be
+ *     8-byte aligned and must not alias unless a call says so.
+ *   - Handles (gl_mesh, gl_precond) are owned by the library and freed by the
+ *     matching *_destroy call.  Only *_create / *_setup calls allocate device
+ *     memory; apply and solve calls allocate nothing.
+ *   - stream is a hipStream_t (NULL = the default stream).  Calls enqueue work
+ *     on it; calls that return host scalars (norms, solve info) synchronise it.
+ *   - Every call returns a gl_status; arguments are validated before any work
+ *     is enqueued; gl_last_error() returns a description of the last failure
+ *     of the calling thread.
+ */
+#ifndef GLNK_H
+#define GLNK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GL_OK = 0,
+    GL_ERR_INVALID_ARGUMENT = 1,
+    GL_ERR_HIP = 2,
+    GL_ERR_OUT_OF_MEMORY = 3,
+    GL_ERR_NOT_CONVERGED = 4,  /* iteration limit reached; outputs still written */
+    GL_ERR_BREAKDOWN = 5,      /* MINRES: <v, M^-1 v> < 0 or NaN */
+    GL_ERR_NONFINITE = 6,      /* NaN / Inf in an input or a residual */
+    GL_ERR_SINGULAR = 7,       /* preconditioner matrix not positive definite */
+    GL_ERR_UNSUPPORTED = 8
+} gl_status;
+
+typedef enum { GL_FP64 = 0, GL_FP32 = 1 } gl_precision;
+
+typedef struct gl_mesh gl_mesh;
+typedef struct gl_precond gl_precond;
+typedef void *gl_stream;
+
+/* --------------------------------------------------------------- mesh --
+ * Tensor grid of n_axis[0] x n_axis[1] (x n_axis[2]) nodes on the box
+ * [-side/2, side/2]^dim, i.e. a Voronoi tessellation whose Delaunay dual is a
+ * structured simplicial mesh (Sec. 3).  |V_i| is the Voronoi cell clipped to
+ * the box; alpha_jk follows the Corollary on simplex edge coefficients
+ * (2D: 1/2 cot of the opposite angle summed over both triangles; 3D: dual
+ * facet area over edge length).  The vector potential is linear:
+ *   potential == 0:  A(r) = mu/2 (b_dir x r)        (uniform field mu b_dir)
+ *   potential == 1:  A(r) = a_matrix r               (3x3 row-major)
+ * and U_jk = exp(-i (x_j - x_k) . A((x_j + x_k)/2)), the link variable of
+ * Sec. 3 (exact for linear A).  In 2D, r = (x, y, 0). */
+typedef struct {
+    int dim;            /* 2 or 3 */
+    int64_t n_axis[3];  /* nodes per axis, >= 2 each (n_axis[2] ignored in 2D) */
+    double side[3];     /* side lengths, > 0 */
+    int potential;      /* 0 or 1, see above */
+    double mu;          /* field strength (potential == 0) */
+    double b_dir[3];    /* field direction (potential == 0), need not be unit */
+    double a_matrix[9]; /* potential == 1 */
+} gl_grid_desc;
+
+/* Build the grid and its link variables on the device.  Errors:
+ * INVALID_ARGUMENT (dim, sizes, sides, more than 2^31 - 2 nodes),
+ * OUT_OF_MEMORY, HIP. */
+gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mesh **out);
+
+/* Replace mu (potential == 0) and recompute the link variables: the
+ * continuation parameter of Sec. 4 (numerical parameter continuation). */
+gl_status gl_mesh_set_field(gl_mesh *mesh, double mu, gl_stream stream);
+
+/* Number of nodes n. */
+gl_status gl_mesh_num_nodes(const gl_mesh *mesh, int64_t *n);
+
+/* Copy the forward-edge link variables of one axis to host memory: entry i
+ * (n complex doubles) is U_jk for k = i, j = i + stride(axis); entries of
+ * nodes on the upper face of that axis are 0.  Synchronous. */
+gl_status gl_mesh_export_links(const gl_mesh *mesh, int axis, void *host_out);
+
+void gl_mesh_destroy(gl_mesh *mesh);
+
+/* ------------------------------------------------------- operators ----- */
+
+/* out = GL(psi) (eq. discr ginla).  out may be NULL (norm only).  If norm_D
+ * (host pointer) is non-NULL it receives ||GL(psi)||_D = sqrt(<GL, GL>_R) and
+ * the stream is synchronised.  psi and out must not alias. */
+gl_status gl_residual(const gl_mesh *mesh, const void *psi, void *out, double *norm_D,
+                      gl_stream stream);
+
+/* out = J(psi) phi (discrete Jacobian, Sec. 3).  out aliases neither input. */
+gl_status gl_jacobian_apply(const gl_mesh *mesh, const void *psi, const void *phi, void *out,
+                            gl_stream stream);
+
+/* --------------------------------------------------- preconditioner ---- */
+typedef struct {
+    gl_precision precision; /* storage and arithmetic of the V-cycle */
+    int cycles;             /* k in R_k (>= 1; 1 is the paper's choice) */
+    int max_coarse;         /* coarsening stops at <= max_coarse rows (default 64) */
+    int max_levels;         /* <= 16 */
+} gl_amg_opts;
+
+/* Set up R_k(psi) = AMG_k(H, D .), H = K-hat + 2 D |psi|^2 (eq. prec2).
+ * *inout == NULL: build the hierarchy (aggregation, colours, sparsity patterns:
+ * they depend only on the grid) and its values.  *inout != NULL (a handle from
+ * an earlier call on the same mesh): recompute only the values for the new psi
+ * (opts may then be NULL; a different precision or cycle count is applied).
+ * Errors: SINGULAR (coarsest operator not positive definite, e.g. psi = 0 and
+ * A = 0), UNSUPPORTED (a coarse row longer than the setup kernels handle),
+ * OUT_OF_MEMORY, HIP. */
+gl_status gl_precond_setup(const gl_mesh *mesh, const void *psi, const gl_amg_opts *opts,
+                           gl_precond **inout, gl_stream stream);
+
+/* z = R_k r = AMG_k(H, D r): k V-cycles from zero on H x = D r.  r and z are
+ * length-n complex vectors and must not alias. */
+gl_status gl_precond_apply(const gl_precond *pre, const void *r, void *z, gl_stream stream);
+
+/* Hierarchy summary.  sizes[l], nnz[l], ncolors[l] for l < *nlev
+ * (arrays of at least 16 entries; any may be NULL). */
+gl_status gl_precond_info(const gl_precond *pre, int *nlev, int64_t *sizes, int64_t *nnz,
+                          int *ncolors);
+
+/* Export one array of level l to host memory (synchronous), for bit-exact
+ * comparisons.  what: 0 aggregate of each node (int32, n_l), 1 roots (int32,
+ * n_{l+1}), 2 colours (int32, n_l), 3 A row pointers (int32, n_l + 1),
+ * 4 A columns (int32, nnz), 5 A values (complex double, nnz), 6 P row
+ * pointers, 7 P columns, 8 P values, 9 R row pointers, 10 R columns,
+ * 11 R values.  Level 0's A is the stencil H and is exported in CSR form with
+ * ascending columns.  *bytes: in = capacity, out = size needed; a NULL
+ * host_buf only queries the size.  Values are exported in double precision
+ * whatever the storage precision. */
+gl_status gl_precond_export(const gl_precond *pre, int level, int what, void *host_buf,
+                            size_t *bytes);
+
+void gl_precond_destroy(gl_precond *pre);
+
+/* ----------------------------------------------------- Jacobian solve -- */
+typedef struct {
+    double rtol;       /* stop when ||b - J x||_{M^-1} <= rtol ||b||_{M^-1} */
+    int max_iter;      /* total MINRES iterations */
+    int poll_every;    /* iterations between host convergence checks (>= 1) */
+    double inner_rtol; /* FP32 preconditioner only: the solve is an FP64 iterative
+                          refinement whose inner MINRES solves (fixed FP32
+                          V-cycle) each reduce the residual by this factor;
+                          0 = 1e-5 */
+} gl_krylov_opts;
+
+typedef struct {
+    int iterations;
+    int converged;
+    double eta0;     /* ||b||_{M^-1} */
+    double res_est;  /* |eta| / eta0 at exit */
+    double res_true; /* ||b - J x||_D / ||b||_D at exit */
+} gl_krylov_info;
+
+/* Solve J(psi) x = b by preconditioned MINRES in <.,.>_R with x0 = 0
+ * (Sec. 4).  With an FP32 preconditioner the solve is an FP64 iterative
+ * refinement: r = b - J x in FP64, MINRES on J d = r to inner_rtol, x += d,
+ * until ||r||_{M^-1} <= rtol ||b||_{M^-1} (info->iterations sums the inner
+ * MINRES iterations).  pre == NULL: no preconditioner; otherwise a handle set up for
+ * the same psi.  x is written even when the iteration limit is reached
+ * (returns NOT_CONVERGED).  BREAKDOWN if <v, M^-1 v> becomes negative or NaN.
+ * The stream is synchronised; info may be NULL. */
+gl_status gl_jacobian_solve(const gl_mesh *mesh, const void *psi, const gl_precond *pre,
+                            const void *b, void *x, const gl_krylov_opts *opts,
+                            gl_krylov_info *info, gl_stream stream);
+
+/* ------------------------------------------------------------- Newton -- */
+typedef struct {
+    double tol;       /* stop when ||GL(psi)||_D < tol */
+    int max_steps;    /* <= 63 */
+    int fixed_steps;  /* > 0: exactly this many steps, tol ignored */
+    int use_precond;  /* 0: unpreconditioned MINRES */
+    gl_krylov_opts krylov;
+    gl_amg_opts amg;
+} gl_newton_opts;
+
+typedef struct {
+    int steps;
+    int converged;
+    double res[64];         /* ||GL(psi_k)||_D, k = 0 .. steps */
+    int krylov_iters[64];   /* MINRES iterations of step k */
+} gl_newton_info;
+
+/* Newton for GL(psi) = 0 starting from psi_inout (eq. Newton system):
+ * per step, set up R_k(psi), solve J(psi) dpsi = -GL(psi), psi += dpsi.
+ * psi_inout is overwritten with the last iterate.  pre_inout (nullable):
+ * a preconditioner handle of this mesh to reuse (only its values are
+ * recomputed), or a pointer to NULL that receives the handle built on the
+ * first step (then owned by the caller); with pre_inout == NULL the hierarchy
+ * is built and freed inside the call.  NOT_CONVERGED if tol is not reached
+ * within max_steps (fixed_steps == 0); NONFINITE if a residual becomes
+ * NaN/Inf.  Synchronous. */
+gl_status gl_newton_solve(const gl_mesh *mesh, void *psi_inout, const gl_newton_opts *opts,
+                          gl_precond **pre_inout, gl_newton_info *info, gl_stream stream);
+
+/* -------------------------------------------------------- diagnostics -- */
+/* Per-kernel timing for roofline reports.  Between gl_profile_start(id) and
+ * gl_profile_stop, every launch of the selected internal kernel is bracketed
+ * by HIP events on its stream; stop synchronises the device and returns the
+ * summed kernel time (ms), the summed algorithmic bytes of those launches
+ * (each array the kernel must touch counted once) and the launch count.
+ * id: 1 MINRES Jacobian apply (+ fused dot), 2 level-0 Gauss-Seidel colour
+ * sweep, 3 level-0 residual, 4 level-0 restriction / prolongation, 5 MINRES
+ * v update, 6 MINRES w/x update, 7 GL residual.  Not thread-safe; for
+ * benchmarking only (the events add a small gap between kernels). */
+gl_status gl_profile_start(int kernel_id);
+gl_status gl_profile_stop(double *ms_total, double *bytes_total, int64_t *launches);
+
+/* ------------------------------------------------------------- errors -- */
+const char *gl_status_string(gl_status s);
+const char *gl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -90,7 +90,7 @@ def lib():
         L.orc_minres_generic.argtypes = [C.c_int64, vp, _OP, vp, _OP, vp, vp, vp, C.c_double,
                                          C.c_int, vp, C.POINTER(_KInfo)]
         L.orc_newton.argtypes = [C.POINTER(_Mesh), vp, C.c_double, C.c_int, C.c_int, C.c_double,
-                                 C.c_int, C.c_int, C.c_int, C.POINTER(_NInfo)]
+                                 C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_NInfo)]
         _lib = L
     return _lib
 
@@ -310,12 +310,12 @@ def minres_generic(w, A, b, minv=None, rtol=1e-10, max_iter=1000):
 
 
 def newton(mesh, psi0, tol=1e-10, max_steps=50, fixed_steps=0, krylov_rtol=1e-10,
-           krylov_max_iter=1000, use_amg=True, cycles=1):
+           krylov_max_iter=1000, use_amg=True, cycles=1, max_coarse=64):
     """Newton for GL(psi) = 0 with MINRES + R_k inner solves (Sec. 2, Sec. 4)."""
     psi = _c128(psi0).copy()
     ni = _NInfo()
     rc = lib().orc_newton(mesh._p, _ptr(psi), tol, max_steps, fixed_steps, krylov_rtol,
-                          krylov_max_iter, int(use_amg), cycles, C.byref(ni))
+                          krylov_max_iter, int(use_amg), cycles, max_coarse, C.byref(ni))
     info = {"status": rc, "steps": ni.steps, "converged": bool(ni.converged),
             "res": list(ni.res[:ni.steps + 1]), "krylov_iters": list(ni.krylov_iters[:ni.steps])}
     return psi, info

@@ -129,7 +129,7 @@ int orc_minres(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycle
 /* ----------------------------------------------------------- Newton --- */
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               orc_newton_info *info)
+               int max_coarse, orc_newton_info *info)
 {
     const int64_t n = m->n;
     cplx *r = malloc((size_t)n * sizeof(cplx)), *b = malloc((size_t)n * sizeof(cplx));
@@ -150,7 +150,7 @@ int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixe
         if (use_amg) {
             orc_hmat_values(m, psi, hv);
             int grid_N_dim = m->dim;
-            rc = orc_amg_build(n, m->rp, m->ci, hv, grid_N_dim, m->N, 64, 16, &amg);
+            rc = orc_amg_build(n, m->rp, m->ci, hv, grid_N_dim, m->N, max_coarse, 16, &amg);
             if (rc != ORC_OK) break;
         }
         for (int64_t i = 0; i < n; ++i) b[i] = -r[i];

@@ -137,6 +137,6 @@ typedef struct {
 
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               orc_newton_info *info);
+               int max_coarse, orc_newton_info *info);
 
 #endif

@@ -1,0 +1,1109 @@
+// Setup of the smoothed-aggregation preconditioner R_k = AMG_k(H, D .) with
+// H = K-hat + 2 D |psi|^2 (Sec. 4.1, eq. prec2; smoothed aggregation with
+// 1 + 1 symmetric Gauss-Seidel steps).  The paper leaves the aggregation and
+// smoothing parameters open; this library fixes them as follows:
+//   strength     every structural off-diagonal entry (theta = 0), so the
+//                integer part of the hierarchy depends only on the grid
+//   priorities   key_l(i) = (fmix32(i ^ 0x9E3779B9 (l + 1)), i), fmix32 the
+//                MurmurHash3 finaliser
+//   roots        distance-2 maximal independent set, computed in parallel
+//                rounds: an undecided node becomes a root when its key is the
+//                largest among undecided nodes within distance 2 (this equals
+//                the serial greedy choice in decreasing key order)
+//   assignment   neighbours of a root join it; the remaining nodes join the
+//                aggregate of their assigned neighbour with the largest root key
+//   numbering    aggregates in ascending root index
+//   prolongator  P = T - omega D^-1 A T, T = 1/sqrt|a|, omega = (4/3) / max_i
+//                sum_j |A_ij| / A_ii; R = P^H; A_{l+1} = R A P (upper triangle,
+//                mirrored; real diagonal)
+//   colours      level 0: red-black parity of the grid; coarser: Jones-Plassmann
+//                rounds with keys of salt l + 101 (equal to greedy colouring in
+//                decreasing key order)
+//   coarsest     dense Cholesky
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+
+#include "amg.h"
+#include "stencil.h"
+
+namespace glk {
+
+// ------------------------------------------------------------ scan ----
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ __launch_bounds__(kBlock) void k_scan_tile(const int *__restrict__ in, int *__restrict__ out,
+                                                      int *__restrict__ bsum, int n)
+{
+    __shared__ int sm[kBlock];
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems], t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        t += v[k];
+    }
+    sm[threadIdx.x] = t;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        const int add = threadIdx.x >= (unsigned)o ? sm[threadIdx.x - o] : 0;
+        __syncthreads();
+        sm[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int ex = sm[threadIdx.x] - t;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < n) out[base + k] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = sm[kBlock - 1];
+}
+
+__global__ void k_scan_add(int *out, const int *boff, int n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] += boff[i / kScanTile];
+}
+
+// exclusive scan of in[0..n) into out; returns the total (synchronises s)
+static int64_t scan_excl(const int *in, int *out, int n, hipStream_t s)
+{
+    if (n <= 0) return 0;
+    const int nb = (n + kScanTile - 1) / kScanTile;
+    DevBuf<int> bsum(nb), boff(nb);
+    k_scan_tile<<<nb, kBlock, 0, s>>>(in, out, bsum.get(), n);
+    GLK_CHECK_LAUNCH();
+    if (nb > 1) {
+        scan_excl(bsum.get(), boff.get(), nb, s);
+        k_scan_add<<<blocks_for(n), kBlock, 0, s>>>(out, boff.get(), n);
+        GLK_CHECK_LAUNCH();
+    }
+    int last_out = 0, last_in = 0;
+    GLK_HIP(hipMemcpyAsync(&last_out, out + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    GLK_HIP(hipMemcpyAsync(&last_in, in + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    GLK_HIP(hipStreamSynchronize(s));
+    return (int64_t)last_out + last_in;
+}
+
+// ---------------------------------------------------------- keys ------
+__device__ __forceinline__ uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__device__ __forceinline__ unsigned long long keyof(int i, unsigned salt)
+{
+    const uint32_t s = 0x9E3779B9u * salt;
+    return ((unsigned long long)fmix32((uint32_t)i ^ s) << 32) | (uint32_t)i;
+}
+
+// insert v into the ascending unique list buf[0..u); false on overflow
+__device__ __forceinline__ bool sorted_insert(int *buf, int &u, int v)
+{
+    int lo = 0, hi = u;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (buf[mid] < v) lo = mid + 1; else hi = mid;
+    }
+    if (lo < u && buf[lo] == v) return true;
+    if (u == kMaxRow) return false;
+    for (int t = u; t > lo; --t) buf[t] = buf[t - 1];
+    buf[lo] = v;
+    ++u;
+    return true;
+}
+
+__device__ __forceinline__ int find_col(const int *ci, int b, int e, int col)
+{
+    while (b < e) {
+        const int mid = (b + e) >> 1;
+        if (ci[mid] < col) b = mid + 1; else e = mid;
+    }
+    return b;
+}
+
+// ------------------------------------------------- level-0 CSR -------
+template <int DIM>
+__global__ void k_l0_count(Geom g, int *cnt)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    int k = 1;
+    for (int a = 0; a < DIM; ++a) k += (c[a] > 0) + (c[a] < g.N[a] - 1);
+    cnt[i] = k;
+}
+
+// columns ascending: lower neighbours (largest stride first), i, upper neighbours
+template <int DIM>
+__global__ void k_l0_cols(Geom g, const int *rp, int *ci)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    int st[3] = {1, g.N[0], g.N[0] * g.N[1]};
+    int p = rp[i];
+    for (int a = DIM - 1; a >= 0; --a)
+        if (c[a] > 0) ci[p++] = i - st[a];
+    ci[p++] = i;
+    for (int a = 0; a < DIM; ++a)
+        if (c[a] < g.N[a] - 1) ci[p++] = i + st[a];
+}
+
+// H = K-hat + 2 D |psi|^2 in the same entry order
+template <int DIM>
+__global__ void k_l0_values(GeomT<double> g, const int *rp, const double2 *__restrict__ U,
+                            const double2 *__restrict__ psi, double2 *v, double *diag)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    double s[3];
+    const double d = node_volume<DIM, double>(g, c, s);
+    int st[3] = {1, g.N[0], g.N[0] * g.N[1]};
+    const size_t n = (size_t)g.n;
+    int p = rp[i];
+    double asum = 0.0;
+    for (int a = DIM - 1; a >= 0; --a)
+        if (c[a] > 0) {
+            const double al = d * s[a] * g.inv_h2[a];
+            v[p++] = cscale(U[a * n + (i - st[a])], -al);
+        }
+    const int pd = p++;
+    for (int a = 0; a < DIM; ++a) {
+        const double al = d * s[a] * g.inv_h2[a];
+        if (c[a] < g.N[a] - 1) v[p++] = cscale(cconj(U[a * n + i]), -al);
+        asum += al * ((c[a] > 0) + (c[a] < g.N[a] - 1));
+    }
+    const double dg = asum + 2.0 * d * cabs2(psi[i]);
+    v[pd] = make_double2(dg, 0.0);
+    diag[i] = dg;
+}
+
+// --------------------------------------------------------- MIS-2 -----
+__global__ void k_fill_int(int *a, int n, int val)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = val;
+}
+
+__global__ void k_mis_m1(int n, const int *rp, const int *ci, const int *state, unsigned salt,
+                         unsigned long long *m1)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long best = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        if (state[j] == 0) best = max(best, keyof(j, salt) + 1ull);
+    }
+    m1[i] = best;
+}
+
+__global__ void k_mis_select(int n, const int *rp, const int *ci, const unsigned long long *m1,
+                             int *state, unsigned salt)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n || state[i] != 0) return;
+    unsigned long long best = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) best = max(best, m1[ci[p]]);
+    if (best == keyof(i, salt) + 1ull) state[i] = 1;
+}
+
+__global__ void k_mis_near(int n, const int *rp, const int *ci, const int *state, int *near1)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int r = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) r |= (state[ci[p]] == 1);
+    near1[i] = r;
+}
+
+__global__ void k_mis_remove(int n, const int *rp, const int *ci, const int *near1, int *state,
+                             int *remaining)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n || state[i] != 0) return;
+    int r = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) r |= near1[ci[p]];
+    if (r) state[i] = 2;
+    else atomicAdd(remaining, 1);
+}
+
+__global__ void k_agg_phase_a(int n, const int *rp, const int *ci, const int *state, unsigned salt,
+                              int *rootA)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (state[i] == 1) { rootA[i] = i; return; }
+    int best = -1;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        if (j != i && state[j] == 1 && (best < 0 || keyof(j, salt) > keyof(best, salt))) best = j;
+    }
+    rootA[i] = best;
+}
+
+__global__ void k_agg_phase_b(int n, const int *rp, const int *ci, const int *rootA, unsigned salt,
+                              int *root, int *err)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int best = rootA[i];
+    if (best < 0) {
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const int j = ci[p];
+            if (j == i) continue;
+            const int r = rootA[j];
+            if (r >= 0 && (best < 0 || keyof(r, salt) > keyof(best, salt))) best = r;
+        }
+        if (best < 0) atomicOr(err, 1);
+    }
+    root[i] = best;
+}
+
+__global__ void k_root_flags(int n, const int *state, int *flag)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) flag[i] = (state[i] == 1);
+}
+
+__global__ void k_agg_number(int n, const int *root, const int *id, const int *state, int *agg,
+                             int *rootlist, int *aggsize)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int r = root[i];
+    const int a = r >= 0 ? id[r] : 0;
+    agg[i] = a;
+    if (state[i] == 1) rootlist[id[i]] = i;
+    atomicAdd(&aggsize[a], 1);
+}
+
+// ------------------------------------------------------ patterns -----
+__global__ void k_p_pattern(int n, const int *rp, const int *ci, const int *agg, const int *prp,
+                            int *cnt, int *pci, int *err)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int buf[kMaxRow];
+    int u = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (!sorted_insert(buf, u, agg[ci[p]])) { atomicOr(err, 2); return; }
+    if (pci) {
+        const int o = prp[i];
+        for (int t = 0; t < u; ++t) pci[o + t] = buf[t];
+    } else {
+        cnt[i] = u;
+    }
+}
+
+__global__ void k_col_count(int nnz, const int *col, int *cnt)
+{
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p < nnz) atomicAdd(&cnt[col[p]], 1);
+}
+
+__global__ void k_transpose_fill(int n, const int *prp, const int *pci, const int *rrp, int *fill,
+                                 int *rci, int *rsrc)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int p = prp[i]; p < prp[i + 1]; ++p) {
+        const int a = pci[p];
+        const int q = rrp[a] + atomicAdd(&fill[a], 1);
+        rci[q] = i;
+        rsrc[q] = p;
+    }
+}
+
+__global__ void k_sort_rows(int nr, const int *rrp, int *rci, int *rsrc)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nr) return;
+    const int b = rrp[r], e = rrp[r + 1];
+    for (int p = b + 1; p < e; ++p) {
+        const int kc = rci[p], ks = rsrc[p];
+        int q = p - 1;
+        while (q >= b && rci[q] > kc) {
+            rci[q + 1] = rci[q];
+            rsrc[q + 1] = rsrc[q];
+            --q;
+        }
+        rci[q + 1] = kc;
+        rsrc[q + 1] = ks;
+    }
+}
+
+// pattern of R A P, row by row
+__global__ void k_rap_pattern(int nc, const int *rrp, const int *rci, const int *arp, const int *aci,
+                              const int *prp, const int *pci, const int *crp, int *cnt, int *cci,
+                              int *err)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    int buf[kMaxRow];
+    int u = 0;
+    for (int p = rrp[I]; p < rrp[I + 1]; ++p) {
+        const int i = rci[p];
+        for (int q = arp[i]; q < arp[i + 1]; ++q) {
+            const int j = aci[q];
+            for (int s = prp[j]; s < prp[j + 1]; ++s)
+                if (!sorted_insert(buf, u, pci[s])) { atomicOr(err, 4); return; }
+        }
+    }
+    if (cci) {
+        const int o = crp[I];
+        for (int t = 0; t < u; ++t) cci[o + t] = buf[t];
+    } else {
+        cnt[I] = u;
+    }
+}
+
+// --------------------------------------------------------- colours ----
+template <int DIM>
+__global__ void k_parity_colour(Geom g, int *col)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    col[i] = (c[0] + c[1] + c[2]) & 1;
+}
+
+__global__ void k_jp_ready(int n, const int *rp, const int *ci, const int *col, unsigned salt, int *ready)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int r = 0;
+    if (col[i] < 0) {
+        r = 1;
+        const unsigned long long k = keyof(i, salt);
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const int j = ci[p];
+            if (j != i && col[j] < 0 && keyof(j, salt) > k) { r = 0; break; }
+        }
+    }
+    ready[i] = r;
+}
+
+__global__ void k_jp_colour(int n, const int *rp, const int *ci, const int *ready, int *col,
+                            int *remaining, int *err)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    if (!ready[i]) {
+        if (col[i] < 0) atomicAdd(remaining, 1);
+        return;
+    }
+    unsigned long long used[4] = {0, 0, 0, 0};
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        const int c = (j != i) ? col[j] : -1;
+        if (c >= 0 && c < 256) used[c >> 6] |= 1ull << (c & 63);
+    }
+    int c = 0;
+    while (c < 256 && (used[c >> 6] >> (c & 63) & 1ull)) ++c;
+    if (c == 256) atomicOr(err, 8);
+    col[i] = c;
+}
+
+__global__ void k_colour_hist(int n, const int *col, int *hist)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&hist[col[i]], 1);
+}
+
+__global__ void k_flag_eq(int n, const int *col, int c, int *flag)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) flag[i] = (col[i] == c);
+}
+
+__global__ void k_scatter_colour(int n, const int *col, int c, const int *pos, int *dst)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && col[i] == c) dst[pos[i]] = i;
+}
+
+// --------------------------------------------------------- numeric ----
+__global__ void k_diag(int n, const int *rp, const int *ci, const double2 *v, double *diag)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int p = find_col(ci, rp[i], rp[i + 1], i);
+    diag[i] = (p < rp[i + 1] && ci[p] == i) ? v[p].x : 0.0;
+}
+
+// rho = max_i sum_j |A_ij| / A_ii (positive doubles order like their bit patterns)
+__global__ void k_rho(int n, const int *rp, const double2 *v, const double *diag, unsigned long long *rho)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) s += hypot(v[p].x, v[p].y);
+    s /= diag[i];
+    atomicMax(rho, (unsigned long long)__double_as_longlong(s));
+}
+
+__global__ void k_p_values(int n, const int *arp, const int *aci, const double2 *av, const double *diag,
+                           const int *agg, const int *aggsize, const double *rho, const int *prp,
+                           const int *pci, double2 *pv)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double omega = (4.0 / 3.0) / *rho;
+    const double dii = diag[i];
+    const int ai = agg[i];
+    for (int p = prp[i]; p < prp[i + 1]; ++p) {
+        const int a = pci[p];
+        const double ta = 1.0 / sqrt((double)aggsize[a]);
+        double2 at = make_double2(0.0, 0.0);
+        for (int q = arp[i]; q < arp[i + 1]; ++q)
+            if (agg[aci[q]] == a) at = cadd(at, cscale(av[q], ta));
+        const double t0 = (ai == a) ? ta : 0.0;
+        const double f = omega / dii;
+        pv[p] = make_double2(t0 - f * at.x, -f * at.y);
+    }
+}
+
+__global__ void k_r_values(int nnz, const int *rsrc, const double2 *pv, double2 *rv)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q < nnz) rv[q] = cconj(pv[rsrc[q]]);
+}
+
+// upper triangle (J >= I) of R A P, products accumulated in ascending order
+__global__ void k_rap_upper(int nc, const int *rrp, const int *rci, const double2 *rv, const int *arp,
+                            const int *aci, const double2 *av, const int *prp, const int *pci,
+                            const double2 *pv, const int *crp, const int *cci, double2 *cv)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    const int cb = crp[I], ce = crp[I + 1];
+    for (int t = cb; t < ce; ++t) cv[t] = make_double2(0.0, 0.0);
+    for (int p = rrp[I]; p < rrp[I + 1]; ++p) {
+        const int i = rci[p];
+        const double2 r = rv[p];
+        for (int q = arp[i]; q < arp[i + 1]; ++q) {
+            const double2 ra = cmul(r, av[q]);
+            const int j = aci[q];
+            for (int s = prp[j]; s < prp[j + 1]; ++s) {
+                const int J = pci[s];
+                if (J < I) continue;
+                const int t = find_col(cci, cb, ce, J);
+                if (t < ce && cci[t] == J) cv[t] = cadd(cv[t], cmul(ra, pv[s]));
+            }
+        }
+    }
+}
+
+__global__ void k_rap_mirror(int nc, const int *crp, const int *cci, double2 *cv)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    for (int t = crp[I]; t < crp[I + 1]; ++t) {
+        const int J = cci[t];
+        if (J > I) break;
+        if (J == I) { cv[t].y = 0.0; break; }
+        const int u = find_col(cci, crp[J], crp[J + 1], I);
+        cv[t] = (u < crp[J + 1] && cci[u] == I) ? cconj(cv[u]) : make_double2(0.0, 0.0);
+    }
+}
+
+__global__ void k_to_f32c(int n, const double2 *a, float2 *b)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+
+__global__ void k_to_f32r(int n, const double *a, float *b)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_dense_from_csr(int n, const int *rp, const int *ci, const double2 *v, double2 *M)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    for (int j = 0; j < n; ++j) M[(size_t)i * n + j] = make_double2(0.0, 0.0);
+    for (int p = rp[i]; p < rp[i + 1]; ++p) M[(size_t)i * n + ci[p]] = v[p];
+}
+
+// In-place Cholesky M = L L^H (row-major, one work-group); upper part zeroed.
+// status = 1 if a pivot is not positive relative to the largest diagonal.
+__global__ __launch_bounds__(kBlock) void k_cholesky(int n, double2 *M, int *status)
+{
+    __shared__ double dmax, ljj;
+    __shared__ int bad;
+    if (threadIdx.x == 0) {
+        double m = 0.0;
+        for (int i = 0; i < n; ++i) m = fmax(m, fabs(M[(size_t)i * n + i].x));
+        dmax = m;
+        bad = 0;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        if (threadIdx.x == 0) {
+            double d = M[(size_t)j * n + j].x;
+            for (int k = 0; k < j; ++k) d -= cabs2(M[(size_t)j * n + k]);
+            if (!(d > 1e-12 * dmax)) bad = 1;
+            else {
+                ljj = sqrt(d);
+                M[(size_t)j * n + j] = make_double2(ljj, 0.0);
+            }
+        }
+        __syncthreads();
+        if (bad) break;
+        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+            double2 s = M[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s = csub(s, cmul(M[(size_t)i * n + k], cconj(M[(size_t)j * n + k])));
+            M[(size_t)i * n + j] = cscale(s, 1.0 / ljj);
+        }
+        __syncthreads();
+    }
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+        const int i = t / n, j = t % n;
+        if (j > i) M[t] = make_double2(0.0, 0.0);
+    }
+    if (threadIdx.x == 0) *status = bad;
+}
+
+// Column j of (L L^H)^-1 (one work-group per column), stored row-major.
+__global__ __launch_bounds__(kBlock) void k_chol_inverse(int n, const double2 *__restrict__ Lf, double2 *inv)
+{
+    __shared__ double2 y[kMaxDense];
+    const int j = blockIdx.x;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    for (int k = j; k < n; ++k) {  // L y = e_j
+        const double2 yk = cscale(y[k], 1.0 / Lf[(size_t)k * n + k].x);
+        __syncthreads();
+        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] = csub(y[i], cmul(Lf[(size_t)i * n + k], yk));
+        if (threadIdx.x == 0) y[k] = yk;
+        __syncthreads();
+    }
+    for (int k = n - 1; k >= 0; --k) {  // L^H x = y
+        const double2 yk = cscale(y[k], 1.0 / Lf[(size_t)k * n + k].x);
+        __syncthreads();
+        for (int i = threadIdx.x; i < k; i += blockDim.x) y[i] = csub(y[i], cmulc(Lf[(size_t)k * n + i], yk));
+        if (threadIdx.x == 0) y[k] = yk;
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) inv[(size_t)i * n + j] = y[i];
+}
+
+// ------------------------------------------------- colour renumbering --
+__global__ void k_iperm(int n, const int *perm, int *iperm)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r < n) iperm[perm[r]] = r;
+}
+
+// length of old row rowperm[r] (identity when rowperm is NULL)
+__global__ void k_perm_count(int nrows, const int *rowperm, const int *rp, int *cnt)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    const int o = rowperm ? rowperm[r] : r;
+    cnt[r] = rp[o + 1] - rp[o];
+}
+
+// row r of the copy = old row rowperm[r] with columns relabelled by colmap
+__global__ void k_perm_fill(int nrows, const int *rowperm, const int *rp, const int *ci, const int *colmap,
+                            const int *nrp, int *nci, int *map)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    const int o = rowperm ? rowperm[r] : r;
+    int q = nrp[r];
+    for (int p = rp[o]; p < rp[o + 1]; ++p, ++q) {
+        nci[q] = colmap ? colmap[ci[p]] : ci[p];
+        map[q] = p;
+    }
+}
+
+__global__ void k_gather_c(int nnz, const int *map, const double2 *src, double2 *d64, float2 *d32)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= nnz) return;
+    const double2 v = src[map[q]];
+    d64[q] = v;
+    d32[q] = make_float2((float)v.x, (float)v.y);
+}
+
+__global__ void k_gather_r(int n, const int *perm, const double *src, double *d64, float *d32)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= n) return;
+    const double v = src[perm[r]];
+    d64[r] = v;
+    d32[r] = (float)v;
+}
+
+// ------------------------------------------------------------- host ---
+static int read_int(const int *d, hipStream_t s)
+{
+    int h = 0;
+    GLK_HIP(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s));
+    GLK_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+static void check_err(const DevBuf<int> &err, hipStream_t s, const char *what)
+{
+    const int e = read_int(err.get(), s);
+    if (e & 2 || e & 4) fail(GL_ERR_UNSUPPORTED, std::string(what) + ": a coarse row exceeds the setup row limit");
+    if (e & 8) fail(GL_ERR_UNSUPPORTED, std::string(what) + ": more than 256 colours");
+    if (e) fail(GL_ERR_HIP, std::string(what) + ": aggregation left a node unassigned");
+}
+
+// CSR pattern (rp from counts, then columns) helper
+static void alloc_rowptr(Csr &M, const int *cnt, hipStream_t s)
+{
+    M.rp.alloc((size_t)M.n + 1);
+    const int64_t nnz = scan_excl(cnt, M.rp.get(), M.n, s);
+    if (nnz > INT32_MAX - 1) fail(GL_ERR_UNSUPPORTED, "sparse matrix too large");
+    M.nnz = (int)nnz;
+    GLK_HIP(hipMemcpyAsync(M.rp.get() + M.n, &M.nnz, sizeof(int), hipMemcpyHostToDevice, s));
+    GLK_HIP(hipStreamSynchronize(s));
+    M.ci.alloc((size_t)std::max(1, M.nnz));
+}
+
+static void colour_level(gl_precond *pre, int l, hipStream_t s)
+{
+    Level &L = pre->L[l];
+    const int n = L.n, nb = blocks_for(n);
+    L.color.alloc(n);
+    const gl_mesh *m = pre->mesh;
+    if (l == 0) {
+        if (m->g.dim == 2) k_parity_colour<2><<<nb, kBlock, 0, s>>>(m->g, L.color.get());
+        else k_parity_colour<3><<<nb, kBlock, 0, s>>>(m->g, L.color.get());
+        GLK_CHECK_LAUNCH();
+        L.ncolors = n > 1 ? 2 : 1;
+    } else {
+        DevBuf<int> ready(n), cnt(1), err(1);
+        GLK_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
+        k_fill_int<<<nb, kBlock, 0, s>>>(L.color.get(), n, -1);
+        const unsigned salt = (unsigned)(l + 101);
+        for (int round = 0;; ++round) {
+            if (round > n + 1) fail(GL_ERR_HIP, "colouring did not terminate");
+            GLK_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
+            k_jp_ready<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.color.get(), salt, ready.get());
+            k_jp_colour<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), ready.get(), L.color.get(),
+                                              cnt.get(), err.get());
+            GLK_CHECK_LAUNCH();
+            if (read_int(cnt.get(), s) == 0) break;
+        }
+        check_err(err, s, "colouring");
+        // number of colours
+        DevBuf<int> hist(257);
+        GLK_HIP(hipMemsetAsync(hist.get(), 0, 257 * sizeof(int), s));
+        k_colour_hist<<<nb, kBlock, 0, s>>>(n, L.color.get(), hist.get());
+        GLK_CHECK_LAUNCH();
+        std::vector<int> h = to_host(hist.get(), 257, s);
+        int nc = 0;
+        for (int c = 0; c < 257; ++c)
+            if (h[c]) nc = c + 1;
+        L.ncolors = nc;
+        // rows grouped by colour
+        L.cperm.alloc(n);
+        L.coff.assign(nc + 1, 0);
+        DevBuf<int> flag(n), pos(n);
+        for (int c = 0; c < nc; ++c) {
+            L.coff[c + 1] = L.coff[c] + h[c];
+            k_flag_eq<<<nb, kBlock, 0, s>>>(n, L.color.get(), c, flag.get());
+            scan_excl(flag.get(), pos.get(), n, s);
+            k_scatter_colour<<<nb, kBlock, 0, s>>>(n, L.color.get(), c, pos.get(), L.cperm.get() + L.coff[c]);
+            GLK_CHECK_LAUNCH();
+        }
+    }
+}
+
+// aggregation of level l; returns the number of aggregates
+static int aggregate_level(gl_precond *pre, int l, hipStream_t s)
+{
+    Level &L = pre->L[l];
+    const int n = L.n, nb = blocks_for(n);
+    const int *rp = L.A.rp.get(), *ci = L.A.ci.get();
+    const unsigned salt = (unsigned)(l + 1);
+    DevBuf<int> state(n), near1(n), cnt(1), err(1), rootA(n), rootB(n), flag(n), id(n);
+    DevBuf<unsigned long long> m1(n);
+    k_fill_int<<<nb, kBlock, 0, s>>>(state.get(), n, 0);
+    GLK_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
+    for (int round = 0;; ++round) {
+        if (round > n + 1) fail(GL_ERR_HIP, "aggregation did not terminate");
+        GLK_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
+        k_mis_m1<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), salt, m1.get());
+        k_mis_select<<<nb, kBlock, 0, s>>>(n, rp, ci, m1.get(), state.get(), salt);
+        k_mis_near<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), near1.get());
+        k_mis_remove<<<nb, kBlock, 0, s>>>(n, rp, ci, near1.get(), state.get(), cnt.get());
+        GLK_CHECK_LAUNCH();
+        if (read_int(cnt.get(), s) == 0) break;
+    }
+    k_agg_phase_a<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), salt, rootA.get());
+    k_agg_phase_b<<<nb, kBlock, 0, s>>>(n, rp, ci, rootA.get(), salt, rootB.get(), err.get());
+    k_root_flags<<<nb, kBlock, 0, s>>>(n, state.get(), flag.get());
+    GLK_CHECK_LAUNCH();
+    check_err(err, s, "aggregation");
+    const int nc = (int)scan_excl(flag.get(), id.get(), n, s);
+    L.nc = nc;
+    L.agg.alloc(n);
+    L.root.alloc(std::max(1, nc));
+    L.aggsize.alloc(std::max(1, nc));
+    GLK_HIP(hipMemsetAsync(L.aggsize.get(), 0, sizeof(int) * std::max(1, nc), s));
+    k_agg_number<<<nb, kBlock, 0, s>>>(n, rootB.get(), id.get(), state.get(), L.agg.get(), L.root.get(),
+                                       L.aggsize.get());
+    GLK_CHECK_LAUNCH();
+    return nc;
+}
+
+static void transfer_patterns(gl_precond *pre, int l, hipStream_t s)
+{
+    Level &L = pre->L[l];
+    Level &Nx = pre->L[l + 1];
+    const int n = L.n, nc = L.nc, nb = blocks_for(n), nbc = blocks_for(nc);
+    DevBuf<int> cnt(std::max(n, nc)), err(1);
+    GLK_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
+    // P: n x nc
+    L.P.n = n;
+    L.P.m = nc;
+    k_p_pattern<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.agg.get(), nullptr, cnt.get(),
+                                      nullptr, err.get());
+    GLK_CHECK_LAUNCH();
+    check_err(err, s, "prolongator pattern");
+    alloc_rowptr(L.P, cnt.get(), s);
+    k_p_pattern<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.agg.get(), L.P.rp.get(), nullptr,
+                                      L.P.ci.get(), err.get());
+    // R = P^H: nc x n
+    L.R.n = nc;
+    L.R.m = n;
+    GLK_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int) * nc, s));
+    k_col_count<<<blocks_for(L.P.nnz), kBlock, 0, s>>>(L.P.nnz, L.P.ci.get(), cnt.get());
+    GLK_CHECK_LAUNCH();
+    alloc_rowptr(L.R, cnt.get(), s);
+    L.rsrc.alloc(std::max(1, L.R.nnz));
+    DevBuf<int> fill(nc);
+    GLK_HIP(hipMemsetAsync(fill.get(), 0, sizeof(int) * nc, s));
+    k_transpose_fill<<<nb, kBlock, 0, s>>>(n, L.P.rp.get(), L.P.ci.get(), L.R.rp.get(), fill.get(),
+                                           L.R.ci.get(), L.rsrc.get());
+    k_sort_rows<<<nbc, kBlock, 0, s>>>(nc, L.R.rp.get(), L.R.ci.get(), L.rsrc.get());
+    GLK_CHECK_LAUNCH();
+    // A_{l+1} = R A P pattern
+    Nx.n = nc;
+    Nx.A.n = nc;
+    Nx.A.m = nc;
+    k_rap_pattern<<<nbc, kBlock, 0, s>>>(nc, L.R.rp.get(), L.R.ci.get(), L.A.rp.get(), L.A.ci.get(),
+                                         L.P.rp.get(), L.P.ci.get(), nullptr, cnt.get(), nullptr, err.get());
+    GLK_CHECK_LAUNCH();
+    check_err(err, s, "Galerkin pattern");
+    alloc_rowptr(Nx.A, cnt.get(), s);
+    k_rap_pattern<<<nbc, kBlock, 0, s>>>(nc, L.R.rp.get(), L.R.ci.get(), L.A.rp.get(), L.A.ci.get(),
+                                         L.P.rp.get(), L.P.ci.get(), Nx.A.rp.get(), nullptr, Nx.A.ci.get(),
+                                         err.get());
+    GLK_CHECK_LAUNCH();
+}
+
+static void alloc_values(gl_precond *pre)
+{
+    for (int l = 0; l < pre->nlev; ++l) {
+        Level &L = pre->L[l];
+        L.A.v64.alloc(std::max(1, L.A.nnz));
+        L.A.v32.alloc(std::max(1, L.A.nnz));
+        L.diag64.alloc(L.n);
+        L.diag32.alloc(L.n);
+        L.b64.alloc(L.n);
+        L.x64.alloc(L.n);
+        L.r64.alloc(L.n);
+        L.b32.alloc(L.n);
+        L.x32.alloc(L.n);
+        L.r32.alloc(L.n);
+        if (l < pre->nlev - 1) {
+            L.P.v64.alloc(std::max(1, L.P.nnz));
+            L.P.v32.alloc(std::max(1, L.P.nnz));
+            L.R.v64.alloc(std::max(1, L.R.nnz));
+            L.R.v32.alloc(std::max(1, L.R.nnz));
+            L.rho.alloc(1);
+        }
+    }
+    const int nl = pre->L[pre->nlev - 1].n;
+    pre->cfac.alloc((size_t)nl * nl);
+    pre->cinv64.alloc((size_t)nl * nl);
+    pre->cinv32.alloc((size_t)nl * nl);
+    pre->status.alloc(1);
+    const int n0 = pre->L[0].n;
+    pre->cyc_r.alloc(n0);
+    pre->vin.alloc(n0);
+}
+
+// copy of M with rows taken in the order rowperm and columns relabelled by colmap
+static void permuted_copy(const Csr &M, const int *rowperm, const int *colmap, Csr &out, DevBuf<int> &map,
+                          hipStream_t s)
+{
+    out.n = M.n;
+    out.m = M.m;
+    DevBuf<int> cnt(std::max(1, M.n));
+    k_perm_count<<<blocks_for(M.n), kBlock, 0, s>>>(M.n, rowperm, M.rp.get(), cnt.get());
+    GLK_CHECK_LAUNCH();
+    alloc_rowptr(out, cnt.get(), s);
+    map.alloc(std::max(1, out.nnz));
+    k_perm_fill<<<blocks_for(M.n), kBlock, 0, s>>>(M.n, rowperm, M.rp.get(), M.ci.get(), colmap, out.rp.get(),
+                                                   out.ci.get(), map.get());
+    GLK_CHECK_LAUNCH();
+    out.v64.alloc(std::max(1, out.nnz));
+    out.v32.alloc(std::max(1, out.nnz));
+}
+
+// the colour-ordered copies the V-cycle works on
+static void build_apply_copies(gl_precond *pre, hipStream_t s)
+{
+    for (int l = 1; l < pre->nlev; ++l) {
+        Level &L = pre->L[l];
+        L.perm.alloc(L.n);
+        GLK_HIP(hipMemcpyAsync(L.perm.get(), L.cperm.get(), sizeof(int) * L.n, hipMemcpyDeviceToDevice, s));
+        L.iperm.alloc(L.n);
+        k_iperm<<<blocks_for(L.n), kBlock, 0, s>>>(L.n, L.perm.get(), L.iperm.get());
+        GLK_CHECK_LAUNCH();
+        L.dg64.alloc(L.n);
+        L.dg32.alloc(L.n);
+    }
+    for (int l = 0; l < pre->nlev; ++l) {
+        Level &L = pre->L[l];
+        const int *rowp = l >= 1 ? L.perm.get() : nullptr;
+        const int *colp = l >= 1 ? L.iperm.get() : nullptr;
+        if (l >= 1) permuted_copy(L.A, rowp, colp, L.Aa, L.amap, s);
+        if (l + 1 < pre->nlev) {
+            Level &Nx = pre->L[l + 1];
+            permuted_copy(L.P, rowp, Nx.iperm.get(), L.Pa, L.pmap, s);
+            permuted_copy(L.R, Nx.perm.get(), colp, L.Ra, L.rmap, s);
+        }
+    }
+    GLK_HIP(hipStreamSynchronize(s));
+}
+
+void precond_symbolic(gl_precond *pre, hipStream_t s)
+{
+    const gl_mesh *m = pre->mesh;
+    const int n0 = m->g.n, nb0 = blocks_for(n0);
+    Level &L0 = pre->L[0];
+    L0.n = n0;
+    L0.A.n = L0.A.m = n0;
+    {
+        DevBuf<int> cnt(n0);
+        if (m->g.dim == 2) k_l0_count<2><<<nb0, kBlock, 0, s>>>(m->g, cnt.get());
+        else k_l0_count<3><<<nb0, kBlock, 0, s>>>(m->g, cnt.get());
+        GLK_CHECK_LAUNCH();
+        alloc_rowptr(L0.A, cnt.get(), s);
+        if (m->g.dim == 2) k_l0_cols<2><<<nb0, kBlock, 0, s>>>(m->g, L0.A.rp.get(), L0.A.ci.get());
+        else k_l0_cols<3><<<nb0, kBlock, 0, s>>>(m->g, L0.A.rp.get(), L0.A.ci.get());
+        GLK_CHECK_LAUNCH();
+    }
+    const int max_levels = std::min(pre->opts.max_levels, kMaxLevels);
+    int l = 0;
+    for (;;) {
+        colour_level(pre, l, s);
+        Level &L = pre->L[l];
+        if (L.n <= pre->opts.max_coarse || l == max_levels - 1) break;
+        const int nc = aggregate_level(pre, l, s);
+        if ((double)nc > 0.85 * (double)L.n) {
+            L.agg.release();
+            L.root.release();
+            L.aggsize.release();
+            L.nc = 0;
+            break;
+        }
+        transfer_patterns(pre, l, s);
+        ++l;
+    }
+    pre->nlev = l + 1;
+    if (pre->L[l].n > kMaxDense)
+        fail(GL_ERR_UNSUPPORTED, "coarsest level too large for the dense solve");
+    alloc_values(pre);
+    build_apply_copies(pre, s);
+    bottom_descriptors(pre, s);
+    GLK_HIP(hipStreamSynchronize(s));
+}
+
+void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
+{
+    const gl_mesh *m = pre->mesh;
+    Level &L0 = pre->L[0];
+    const int n0 = L0.n;
+    const GeomT<double> g = geom_t<double>(m->g);
+    if (m->g.dim == 2)
+        k_l0_values<2><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), m->U64.get(), psi, L0.A.v64.get(), L0.diag64.get());
+    else
+        k_l0_values<3><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), m->U64.get(), psi, L0.A.v64.get(), L0.diag64.get());
+    GLK_CHECK_LAUNCH();
+    for (int l = 0; l + 1 < pre->nlev; ++l) {
+        Level &L = pre->L[l];
+        Level &Nx = pre->L[l + 1];
+        const int n = L.n, nb = blocks_for(n);
+        if (l > 0) {
+            k_diag<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get());
+        }
+        GLK_HIP(hipMemsetAsync(L.rho.get(), 0, sizeof(double), s));
+        k_rho<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.v64.get(), L.diag64.get(),
+                                    reinterpret_cast<unsigned long long *>(L.rho.get()));
+        k_p_values<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(),
+                                         L.agg.get(), L.aggsize.get(), L.rho.get(), L.P.rp.get(),
+                                         L.P.ci.get(), L.P.v64.get());
+        k_r_values<<<blocks_for(L.R.nnz), kBlock, 0, s>>>(L.R.nnz, L.rsrc.get(), L.P.v64.get(), L.R.v64.get());
+        const int nbc = blocks_for(L.nc);
+        k_rap_upper<<<nbc, kBlock, 0, s>>>(L.nc, L.R.rp.get(), L.R.ci.get(), L.R.v64.get(), L.A.rp.get(),
+                                           L.A.ci.get(), L.A.v64.get(), L.P.rp.get(), L.P.ci.get(),
+                                           L.P.v64.get(), Nx.A.rp.get(), Nx.A.ci.get(), Nx.A.v64.get());
+        k_rap_mirror<<<nbc, kBlock, 0, s>>>(L.nc, Nx.A.rp.get(), Nx.A.ci.get(), Nx.A.v64.get());
+        GLK_CHECK_LAUNCH();
+    }
+    const int last = pre->nlev - 1;
+    Level &Lc = pre->L[last];
+    if (last > 0)
+        k_diag<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Lc.A.rp.get(), Lc.A.ci.get(), Lc.A.v64.get(), Lc.diag64.get());
+    // level 0 in single precision (its stencil diagonal; the CSR copy serves export only)
+    k_to_f32r<<<blocks_for(n0), kBlock, 0, s>>>(n0, L0.diag64.get(), L0.diag32.get());
+    // colour-ordered copies for the V-cycle, FP64 and rounded to FP32
+    for (int l = 0; l < pre->nlev; ++l) {
+        Level &L = pre->L[l];
+        if (l >= 1) {
+            k_gather_c<<<blocks_for(L.Aa.nnz), kBlock, 0, s>>>(L.Aa.nnz, L.amap.get(), L.A.v64.get(),
+                                                               L.Aa.v64.get(), L.Aa.v32.get());
+            k_gather_r<<<blocks_for(L.n), kBlock, 0, s>>>(L.n, L.perm.get(), L.diag64.get(), L.dg64.get(),
+                                                          L.dg32.get());
+        }
+        if (l < last) {
+            k_gather_c<<<blocks_for(L.Pa.nnz), kBlock, 0, s>>>(L.Pa.nnz, L.pmap.get(), L.P.v64.get(),
+                                                               L.Pa.v64.get(), L.Pa.v32.get());
+            k_gather_c<<<blocks_for(L.Ra.nnz), kBlock, 0, s>>>(L.Ra.nnz, L.rmap.get(), L.R.v64.get(),
+                                                               L.Ra.v64.get(), L.Ra.v32.get());
+        }
+        GLK_CHECK_LAUNCH();
+    }
+    // coarsest: Cholesky in FP64 (positive definiteness check), then the inverse
+    // in the V-cycle's row order, applied as a dense product
+    const Csr &Mc = last > 0 ? Lc.Aa : Lc.A;
+    k_dense_from_csr<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Mc.rp.get(), Mc.ci.get(), Mc.v64.get(),
+                                                         pre->cfac.get());
+    k_cholesky<<<1, kBlock, 0, s>>>(Lc.n, pre->cfac.get(), pre->status.get());
+    GLK_CHECK_LAUNCH();
+    if (read_int(pre->status.get(), s))
+        fail(GL_ERR_SINGULAR, "gl_precond_setup: coarsest operator is not positive definite");
+    k_chol_inverse<<<Lc.n, kBlock, 0, s>>>(Lc.n, pre->cfac.get(), pre->cinv64.get());
+    k_to_f32c<<<blocks_for((int64_t)Lc.n * Lc.n), kBlock, 0, s>>>(Lc.n * Lc.n, pre->cinv64.get(), pre->cinv32.get());
+    GLK_CHECK_LAUNCH();
+}
+
+}  // namespace glk
+
+using namespace glk;
+
+extern "C" {
+
+gl_status gl_precond_setup(const gl_mesh *mesh, const void *psi, const gl_amg_opts *opts,
+                           gl_precond **inout, gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !psi || !inout) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: NULL argument");
+        hipStream_t s = as_stream(stream);
+        gl_precond *pre = *inout;
+        if (pre && pre->mesh != mesh)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: handle belongs to another mesh");
+        if (!pre && !opts) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: opts required for a new handle");
+        if (opts) {
+            if (opts->precision != GL_FP64 && opts->precision != GL_FP32)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: precision");
+            if (opts->cycles < 1 || opts->cycles > 1000)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: cycles must be in 1..1000");
+            if (opts->max_coarse < 1 || opts->max_coarse > kMaxDense)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: max_coarse must be in 1..2048");
+            if (opts->max_levels < 1 || opts->max_levels > kMaxLevels)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: max_levels must be in 1..16");
+        }
+        if (!pre) {
+            pre = new gl_precond();
+            try {
+                static std::atomic<uint64_t> next_uid{1};
+                pre->uid = next_uid++;
+                pre->mesh = mesh;
+                pre->opts = *opts;
+                precond_symbolic(pre, s);
+                precond_numeric(pre, (const double2 *)psi, s);
+            } catch (...) {
+                delete pre;
+                throw;
+            }
+            *inout = pre;
+        } else {
+            if (opts) {
+                if (opts->max_coarse != pre->opts.max_coarse || opts->max_levels != pre->opts.max_levels)
+                    fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: hierarchy limits differ from the handle's");
+                pre->opts.precision = opts->precision;
+                pre->opts.cycles = opts->cycles;
+            }
+            precond_numeric(pre, (const double2 *)psi, s);
+        }
+    });
+}
+
+gl_status gl_precond_info(const gl_precond *pre, int *nlev, int64_t *sizes, int64_t *nnz, int *ncolors)
+{
+    return guarded([&] {
+        if (!pre) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_info: NULL handle");
+        if (nlev) *nlev = pre->nlev;
+        for (int l = 0; l < pre->nlev; ++l) {
+            if (sizes) sizes[l] = pre->L[l].n;
+            if (nnz) nnz[l] = pre->L[l].A.nnz;
+            if (ncolors) ncolors[l] = pre->L[l].ncolors;
+        }
+    });
+}
+
+gl_status gl_precond_export(const gl_precond *pre, int level, int what, void *host_buf, size_t *bytes)
+{
+    return guarded([&] {
+        if (!pre || !bytes) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_export: NULL argument");
+        if (level < 0 || level >= pre->nlev) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_export: level");
+        const Level &L = pre->L[level];
+        const bool last = level == pre->nlev - 1;
+        if (last && ((what >= 6 && what <= 11) || what == 0 || what == 1))
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_export: the coarsest level has no transfer operators");
+        const void *src = nullptr;
+        size_t need = 0;
+        switch (what) {
+        case 0: src = L.agg.get(); need = sizeof(int) * L.n; break;
+        case 1: src = L.root.get(); need = sizeof(int) * L.nc; break;
+        case 2: src = L.color.get(); need = sizeof(int) * L.n; break;
+        case 3: src = L.A.rp.get(); need = sizeof(int) * (L.n + 1); break;
+        case 4: src = L.A.ci.get(); need = sizeof(int) * L.A.nnz; break;
+        case 5: src = L.A.v64.get(); need = sizeof(double2) * L.A.nnz; break;
+        case 6: src = L.P.rp.get(); need = sizeof(int) * (L.n + 1); break;
+        case 7: src = L.P.ci.get(); need = sizeof(int) * L.P.nnz; break;
+        case 8: src = L.P.v64.get(); need = sizeof(double2) * L.P.nnz; break;
+        case 9: src = L.R.rp.get(); need = sizeof(int) * (L.nc + 1); break;
+        case 10: src = L.R.ci.get(); need = sizeof(int) * L.R.nnz; break;
+        case 11: src = L.R.v64.get(); need = sizeof(double2) * L.R.nnz; break;
+        default: fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_export: unknown array");
+        }
+        if (!host_buf) { *bytes = need; return; }
+        if (*bytes < need) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_export: buffer too small");
+        *bytes = need;
+        GLK_HIP(hipDeviceSynchronize());
+        if (need) GLK_HIP(hipMemcpy(host_buf, src, need, hipMemcpyDeviceToHost));
+    });
+}
+
+void gl_precond_destroy(gl_precond *pre) { delete pre; }
+
+}  // extern "C"

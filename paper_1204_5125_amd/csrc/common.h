@@ -1,0 +1,307 @@
+// Internal declarations of libglnk: error handling, device buffers, complex
+// arithmetic on double2 / float2, wave64 reductions and the deterministic
+// last-block finalisation used by every fused dot product.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/glnk.h"
+
+namespace glk {
+
+// ------------------------------------------------------------ errors ----
+struct Error {
+    gl_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(gl_status s, const std::string &msg);
+void set_last_error(const std::string &msg);
+
+#define GLK_HIP(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            ::glk::fail(e_ == hipErrorOutOfMemory ? GL_ERR_OUT_OF_MEMORY : GL_ERR_HIP,   \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+#define GLK_CHECK_LAUNCH() GLK_HIP(hipGetLastError())
+
+// Run body, translating internal errors into a gl_status (no exception ever
+// crosses the C ABI).
+template <class F>
+gl_status guarded(F &&body)
+{
+    try {
+        body();
+        return GL_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return GL_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        set_last_error("unexpected internal error");
+        return GL_ERR_HIP;
+    }
+}
+
+// ---------------------------------------------------- device buffers ----
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t count = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t c) { alloc(c); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), count(o.count) { o.p = nullptr; o.count = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept
+    {
+        if (this != &o) { release(); p = o.p; count = o.count; o.p = nullptr; o.count = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t c)
+    {
+        release();
+        count = c;
+        if (c) GLK_HIP(hipMalloc(&p, c * sizeof(T)));
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
+    }
+    T *get() const { return p; }
+};
+
+template <class T>
+std::vector<T> to_host(const T *d, size_t count, hipStream_t s)
+{
+    std::vector<T> h(count);
+    if (count) {
+        GLK_HIP(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, s));
+        GLK_HIP(hipStreamSynchronize(s));
+    }
+    return h;
+}
+
+template <class T>
+void to_device(T *d, const std::vector<T> &h, hipStream_t s)
+{
+    if (!h.empty()) {
+        GLK_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        GLK_HIP(hipStreamSynchronize(s));
+    }
+}
+
+// ------------------------------------------------- complex on device ----
+template <class T> struct cx;
+template <> struct cx<double> { using t = double2; };
+template <> struct cx<float> { using t = float2; };
+template <class T> using C = typename cx<T>::t;
+
+template <class T> __host__ __device__ __forceinline__ C<T> mk(T re, T im) { C<T> r; r.x = re; r.y = im; return r; }
+template <class V> __host__ __device__ __forceinline__ V cadd(V a, V b) { a.x += b.x; a.y += b.y; return a; }
+template <class V> __host__ __device__ __forceinline__ V csub(V a, V b) { a.x -= b.x; a.y -= b.y; return a; }
+template <class V, class T> __host__ __device__ __forceinline__ V cscale(V a, T s) { a.x *= s; a.y *= s; return a; }
+// a * b
+template <class V> __host__ __device__ __forceinline__ V cmul(V a, V b)
+{
+    V r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+// conj(a) * b
+template <class V> __host__ __device__ __forceinline__ V cmulc(V a, V b)
+{
+    V r;
+    r.x = a.x * b.x + a.y * b.y;
+    r.y = a.x * b.y - a.y * b.x;
+    return r;
+}
+template <class V> __host__ __device__ __forceinline__ V cconj(V a) { a.y = -a.y; return a; }
+// Re(conj(a) b)
+template <class V> __host__ __device__ __forceinline__ auto redot(V a, V b) { return a.x * b.x + a.y * b.y; }
+template <class V> __host__ __device__ __forceinline__ auto cabs2(V a) { return a.x * a.x + a.y * a.y; }
+
+__device__ __forceinline__ double2 widen(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ double2 widen(double2 a) { return a; }
+template <class T> __device__ __forceinline__ C<T> narrow(double2 a);
+template <> __device__ __forceinline__ double2 narrow<double>(double2 a) { return a; }
+template <> __device__ __forceinline__ float2 narrow<float>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+
+// ----------------------------------------------------- launch shapes ----
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+
+inline int blocks_for(int64_t n, int bs = kBlock) { return (int)((n + bs - 1) / bs); }
+
+// Work-groups of one dispatch are handed to the 8 XCDs round-robin; renumber
+// them so that each XCD walks one contiguous range of tiles, which keeps the
+// neighbouring rows of a stencil in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    int q = nb / kXcds, r = nb % kXcds;
+    int x = b % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
+// ------------------------------------------------------- reductions ----
+template <class T> __device__ __forceinline__ T wave_sum(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Sum over the block (blockDim.x a multiple of 64, <= 1024); result valid in
+// thread 0.  Fixed combination order, so the result is reproducible.
+__device__ __forceinline__ double block_sum(double v, double *sm)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) sm[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (w == 0) {
+        r = lane < nw ? sm[lane] : 0.0;
+        r = wave_sum(r);
+    }
+    return r;
+}
+
+// Per-dispatch reduction slot: one partial per block.  A producer kernel
+// stores its block sums; a one-work-group finalize kernel that follows in the
+// same stream adds them in block order (fixed tree), so totals are
+// reproducible and no counter is contended.
+struct RedSlot {
+    double *partials;
+};
+
+__device__ __forceinline__ void block_reduce_store(double part, RedSlot slot, double *sm)
+{
+    const double bs = block_sum(part, sm);
+    if (threadIdx.x == 0) slot.partials[blockIdx.x] = bs;
+}
+
+// ------------------------------------------------------- grid geometry --
+// Tensor grid: nodes i = c0 + N0 (c1 + N1 c2).  |V_i| = prod_a e_a with
+// e_a = h_a (interior) or h_a / 2 (boundary); the edge coefficient along axis
+// a at node i is alpha_a = |V_i| s_a / h_a^2, s_a = 2 on a boundary of axis a
+// (so alpha_a = prod_{b != a} e_b / h_a, the dual-facet area over the edge length).
+struct Geom {
+    int dim;
+    int N[3];
+    int n;
+    double h[3];
+    double inv_h2[3];
+};
+
+template <class T>
+struct GeomT {
+    int N[3];
+    int n;
+    T h[3];
+    T inv_h2[3];
+};
+
+template <class T> inline GeomT<T> geom_t(const Geom &g)
+{
+    GeomT<T> r;
+    for (int a = 0; a < 3; ++a) {
+        r.N[a] = g.N[a];
+        r.h[a] = (T)g.h[a];
+        r.inv_h2[a] = (T)g.inv_h2[a];
+    }
+    r.n = g.n;
+    return r;
+}
+
+}  // namespace glk
+
+// --------------------------------------------------- public handles ----
+namespace glk {
+struct GraphEntry {
+    uint64_t key[6];
+    hipGraphExec_t exec;
+};
+}  // namespace glk
+
+struct gl_mesh {
+    glk::Geom g;
+    gl_grid_desc desc;
+    double amat[9];
+    glk::DevBuf<double2> U64;  // [axis][n] forward-edge link variables
+    glk::DevBuf<float2> U32;
+    // reductions
+    glk::DevBuf<double> partials;
+    glk::DevBuf<double> dscal;       // device scalar results
+    double *hscal = nullptr;         // pinned host mirror
+    // Krylov workspace (allocated with the mesh so that solves allocate nothing)
+    glk::DevBuf<double2> work;       // kWorkVecs * n
+    glk::DevBuf<char> kscal;         // Krylov scalar state
+    hipStream_t ws = nullptr;        // Krylov work stream (graph capture)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<glk::GraphEntry> graphs;
+    ~gl_mesh();
+};
+
+namespace glk {
+// ------------------------------------------------------------ profiling -
+// Event-bracketed launches of one selected kernel (see gl_profile_start).
+struct Profiler {
+    int kernel = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double bytes = 0.0;
+};
+Profiler &profiler();
+enum ProfId {
+    PROF_MINRES_JAPPLY = 1, PROF_L0_SWEEP = 2, PROF_L0_RESIDUAL = 3, PROF_L0_TRANSFER = 4,
+    PROF_VUPDATE = 5, PROF_WX = 6, PROF_GL = 7
+};
+
+template <class F>
+void prof_launch(int id, double bytes, hipStream_t s, F &&launch)
+{
+    Profiler &p = profiler();
+    if (p.kernel != id) {
+        launch();
+        return;
+    }
+    if (p.used == p.ev.size()) {
+        hipEvent_t a, b;
+        GLK_HIP(hipEventCreate(&a));
+        GLK_HIP(hipEventCreate(&b));
+        p.ev.emplace_back(a, b);
+    }
+    auto &e = p.ev[p.used++];
+    GLK_HIP(hipEventRecord(e.first, s));
+    launch();
+    GLK_HIP(hipEventRecord(e.second, s));
+    p.bytes += bytes;
+}
+
+// number of grid edges (axis-neighbour pairs)
+inline double grid_edges(const Geom &g)
+{
+    double e = 0.0;
+    for (int a = 0; a < g.dim; ++a) e += (double)g.n / g.N[a] * (g.N[a] - 1);
+    return e;
+}
+
+constexpr int kWorkVecs = 11;
+constexpr int kMaxSlots = 4;  // independent reduction slots per mesh
+RedSlot red_slot(const gl_mesh *m, int k);
+hipStream_t as_stream(gl_stream s);
+}  // namespace glk

@@ -1,0 +1,397 @@
+// Grid construction, link variables, GL residual and Jacobian apply.
+//   link variables : Sec. 3, U_jk = exp(-i int e.A), midpoint rule (exact for linear A)
+//   GL residual    : eq. discr ginla, GL_i = (K psi)_i - psi_i (1 - |psi_i|^2)
+//   Jacobian apply : discrete Jacobian of Sec. 3
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "amg.h"
+#include "stencil.h"
+
+namespace glk {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+[[noreturn]] void fail(gl_status s, const std::string &msg) { throw Error{s, msg}; }
+
+hipStream_t as_stream(gl_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+Profiler &profiler()
+{
+    static Profiler p;
+    return p;
+}
+
+RedSlot red_slot(const gl_mesh *m, int k)
+{
+    const size_t per = m->partials.count / kMaxSlots;
+    return RedSlot{m->partials.get() + per * k};
+}
+
+__global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ partials, int nparts, int mode,
+                                                   KrylovScalars *ks, double *out, const int *gate)
+{
+    if (gate && *gate == 0) return;
+    __shared__ double sm[1024 / 64];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partials[k];
+    s = block_sum(s, sm);
+    if (threadIdx.x == 0) {
+        if (mode == FIN_STORE) *out = s;
+        else minres_finalize(ks, mode, s);
+    }
+}
+
+void launch_finalize(const double *partials, int nparts, int mode, KrylovScalars *ks, double *out,
+                     const int *gate, hipStream_t s)
+{
+    k_finalize<<<1, 1024, 0, s>>>(partials, nparts, mode, ks, out, gate);
+    GLK_CHECK_LAUNCH();
+}
+
+struct Potential {
+    double m[9];
+    double L[3];
+};
+
+// A(r) = m r evaluated at the edge midpoint, phase = h_a A_a, U = exp(-i phase)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_links(Geom g, Potential pot, double2 *__restrict__ U64,
+                                                  float2 *__restrict__ U32)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    double x[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < DIM; ++a) x[a] = -0.5 * pot.L[a] + (double)c[a] * g.h[a];
+    const size_t n = (size_t)g.n;
+    for (int a = 0; a < DIM; ++a) {
+        double2 u = make_double2(0.0, 0.0);
+        if (c[a] < g.N[a] - 1) {
+            double m[3] = {x[0], x[1], x[2]};
+            m[a] += 0.5 * g.h[a];
+            const double Aa = pot.m[3 * a + 0] * m[0] + pot.m[3 * a + 1] * m[1] + pot.m[3 * a + 2] * m[2];
+            const double ph = g.h[a] * Aa;
+            double s, co;
+            sincos(ph, &s, &co);
+            u = make_double2(co, -s);
+        }
+        U64[a * n + i] = u;
+        U32[a * n + i] = make_float2((float)u.x, (float)u.y);
+    }
+}
+
+static void compute_amat(const gl_grid_desc &d, double mu, double out[9])
+{
+    if (d.potential == 1) {
+        std::memcpy(out, d.a_matrix, sizeof(double) * 9);
+        return;
+    }
+    double b[3] = {d.b_dir[0], d.b_dir[1], d.b_dir[2]};
+    double nb = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    for (double &v : b) v /= nb;
+    // A(r) = mu/2 (b x r)
+    const double cr[9] = {0.0, -b[2], b[1], b[2], 0.0, -b[0], -b[1], b[0], 0.0};
+    for (int k = 0; k < 9; ++k) out[k] = 0.5 * mu * cr[k];
+}
+
+static void launch_links(gl_mesh *m, hipStream_t s)
+{
+    Potential pot;
+    std::memcpy(pot.m, m->amat, sizeof(pot.m));
+    for (int a = 0; a < 3; ++a) pot.L[a] = m->desc.side[a];
+    const int nb = blocks_for(m->g.n);
+    if (m->g.dim == 2)
+        k_links<2><<<nb, kBlock, 0, s>>>(m->g, pot, m->U64.get(), m->U32.get());
+    else
+        k_links<3><<<nb, kBlock, 0, s>>>(m->g, pot, m->U64.get(), m->U32.get());
+    GLK_CHECK_LAUNCH();
+}
+
+// ------------------------------------------------------- GL residual ---
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_gl_residual(GeomT<double> g, const double2 *__restrict__ psi,
+                                                        const double2 *__restrict__ U,
+                                                        double2 *__restrict__ out, RedSlot slot)
+{
+    __shared__ double sm[kBlock / 64];
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    double part = 0.0;
+    if (i < g.n) {
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        const double2 p = psi[i];
+        double d, asum;
+        const double2 kp = khat_node<DIM, double>(g, i, c, psi, U, p, d, asum);
+        const double a2 = cabs2(p);
+        const double2 r = csub(cscale(kp, 1.0 / d), cscale(p, 1.0 - a2));
+        if (out) out[i] = r;
+        part = d * cabs2(r);
+    }
+    block_reduce_store(part, slot, sm);
+}
+
+void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
+                         hipStream_t s)
+{
+    const int nb = blocks_for(m->g.n);
+    const GeomT<double> g = geom_t<double>(m->g);
+    const double bytes = 16.0 * m->g.n * (out ? 2 : 1) + 16.0 * grid_edges(m->g);
+    prof_launch(PROF_GL, bytes, s, [&] {
+        if (m->g.dim == 2)
+            k_gl_residual<2><<<nb, kBlock, 0, s>>>(g, psi, m->U64.get(), out, red_slot(m, 0));
+        else
+            k_gl_residual<3><<<nb, kBlock, 0, s>>>(g, psi, m->U64.get(), out, red_slot(m, 0));
+    });
+    GLK_CHECK_LAUNCH();
+    launch_finalize(red_slot(m, 0).partials, nb, FIN_STORE, nullptr, dresult, nullptr, s);
+}
+
+// ---------------------------------------------------- Jacobian apply ---
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_jacobian(GeomT<double> g, const double2 *__restrict__ psi,
+                                                     const double2 *__restrict__ phi,
+                                                     const double2 *__restrict__ U,
+                                                     double2 *__restrict__ out)
+{
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    const double2 f = phi[i];
+    double d, asum;
+    const double2 kf = khat_node<DIM, double>(g, i, c, phi, U, f, d, asum);
+    const double2 p = psi[i];
+    const double2 p2 = cmul(p, p);
+    const double2 r = cadd(cadd(cscale(kf, 1.0 / d), cscale(f, 2.0 * cabs2(p) - 1.0)),
+                           cmul(p2, cconj(f)));
+    out[i] = r;
+}
+
+void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, double2 *out,
+                      hipStream_t s)
+{
+    const int nb = blocks_for(m->g.n);
+    const GeomT<double> g = geom_t<double>(m->g);
+    if (m->g.dim == 2)
+        k_jacobian<2><<<nb, kBlock, 0, s>>>(g, psi, phi, m->U64.get(), out);
+    else
+        k_jacobian<3><<<nb, kBlock, 0, s>>>(g, psi, phi, m->U64.get(), out);
+    GLK_CHECK_LAUNCH();
+}
+
+// y = D x
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_scale_volume(GeomT<double> g, const double2 *__restrict__ x,
+                                                         double2 *__restrict__ y)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    double sf[3];
+    y[i] = cscale(x[i], node_volume<DIM, double>(g, c, sf));
+}
+
+void scale_by_volume(const gl_mesh *m, const double2 *x, double2 *y, hipStream_t s)
+{
+    const GeomT<double> g = geom_t<double>(m->g);
+    if (m->g.dim == 2) k_scale_volume<2><<<blocks_for(m->g.n), kBlock, 0, s>>>(g, x, y);
+    else k_scale_volume<3><<<blocks_for(m->g.n), kBlock, 0, s>>>(g, x, y);
+    GLK_CHECK_LAUNCH();
+}
+
+}  // namespace glk
+
+gl_mesh::~gl_mesh()
+{
+    if (ws) (void)hipStreamSynchronize(ws);
+    for (auto &e : graphs) (void)hipGraphExecDestroy(e.exec);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ws) (void)hipStreamDestroy(ws);
+    if (hscal) (void)hipHostFree(hscal);
+}
+
+using namespace glk;
+
+extern "C" {
+
+const char *gl_status_string(gl_status s)
+{
+    switch (s) {
+    case GL_OK: return "ok";
+    case GL_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case GL_ERR_HIP: return "HIP runtime error";
+    case GL_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case GL_ERR_NOT_CONVERGED: return "not converged";
+    case GL_ERR_BREAKDOWN: return "Krylov breakdown";
+    case GL_ERR_NONFINITE: return "non-finite value";
+    case GL_ERR_SINGULAR: return "singular preconditioner matrix";
+    case GL_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *gl_last_error(void) { return g_last_error.c_str(); }
+
+gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mesh **out)
+{
+    return guarded([&] {
+        if (!desc || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: NULL argument");
+        *out = nullptr;
+        if (desc->dim != 2 && desc->dim != 3)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: dim must be 2 or 3");
+        if (desc->potential != 0 && desc->potential != 1)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: potential must be 0 or 1");
+        int64_t n = 1;
+        for (int a = 0; a < desc->dim; ++a) {
+            if (desc->n_axis[a] < 2 || desc->n_axis[a] > (int64_t)1 << 30)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: n_axis out of range");
+            if (!(desc->side[a] > 0.0) || !std::isfinite(desc->side[a]))
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: side must be positive");
+            n *= desc->n_axis[a];
+            if (n > ((int64_t)1 << 31) - 2)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: too many nodes");
+        }
+        if (desc->potential == 0) {
+            const double *b = desc->b_dir;
+            if (!(b[0] * b[0] + b[1] * b[1] + b[2] * b[2] > 0.0))
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: b_dir is zero");
+            if (!std::isfinite(desc->mu)) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: mu");
+        }
+        hipStream_t s = as_stream(stream);
+        gl_mesh *m = new gl_mesh();
+        try {
+            m->desc = *desc;
+            m->g.dim = desc->dim;
+            m->g.n = (int)n;
+            for (int a = 0; a < 3; ++a) {
+                if (a < desc->dim) {
+                    m->g.N[a] = (int)desc->n_axis[a];
+                    m->g.h[a] = desc->side[a] / (double)(desc->n_axis[a] - 1);
+                    m->g.inv_h2[a] = 1.0 / (m->g.h[a] * m->g.h[a]);
+                } else {
+                    m->g.N[a] = 1;
+                    m->g.h[a] = 1.0;
+                    m->g.inv_h2[a] = 1.0;
+                }
+            }
+            compute_amat(*desc, desc->mu, m->amat);
+            m->U64.alloc((size_t)desc->dim * n);
+            m->U32.alloc((size_t)desc->dim * n);
+            const size_t per = (size_t)blocks_for(n) + 64;
+            m->partials.alloc(per * kMaxSlots);
+            m->dscal.alloc(64);
+            m->work.alloc((size_t)kWorkVecs * n);
+            m->kscal.alloc(4096);
+            GLK_HIP(hipHostMalloc(&m->hscal, 64 * sizeof(double), hipHostMallocDefault));
+            GLK_HIP(hipStreamCreateWithFlags(&m->ws, hipStreamNonBlocking));
+            GLK_HIP(hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
+            GLK_HIP(hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming));
+            GLK_HIP(hipMemsetAsync(m->dscal.get(), 0, 64 * sizeof(double), s));
+            launch_links(m, s);
+            GLK_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
+gl_status gl_mesh_set_field(gl_mesh *mesh, double mu, gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_set_field: NULL mesh");
+        if (mesh->desc.potential != 0)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_set_field: mesh has a matrix potential");
+        if (!std::isfinite(mu)) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_set_field: mu");
+        mesh->desc.mu = mu;
+        compute_amat(mesh->desc, mu, mesh->amat);
+        launch_links(mesh, as_stream(stream));
+    });
+}
+
+gl_status gl_mesh_num_nodes(const gl_mesh *mesh, int64_t *n)
+{
+    return guarded([&] {
+        if (!mesh || !n) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_num_nodes: NULL argument");
+        *n = mesh->g.n;
+    });
+}
+
+gl_status gl_mesh_export_links(const gl_mesh *mesh, int axis, void *host_out)
+{
+    return guarded([&] {
+        if (!mesh || !host_out) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_export_links: NULL argument");
+        if (axis < 0 || axis >= mesh->g.dim) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_export_links: axis");
+        GLK_HIP(hipDeviceSynchronize());
+        GLK_HIP(hipMemcpy(host_out, mesh->U64.get() + (size_t)axis * mesh->g.n,
+                          sizeof(double2) * (size_t)mesh->g.n, hipMemcpyDeviceToHost));
+    });
+}
+
+void gl_mesh_destroy(gl_mesh *mesh) { delete mesh; }
+
+gl_status gl_residual(const gl_mesh *mesh, const void *psi, void *out, double *norm_D, gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !psi) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual: NULL mesh or psi");
+        if (out == psi) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual: out aliases psi");
+        hipStream_t s = as_stream(stream);
+        gl_residual_enqueue(mesh, (const double2 *)psi, (double2 *)out, mesh->dscal.get(), s);
+        if (norm_D) {
+            GLK_HIP(hipMemcpyAsync(mesh->hscal, mesh->dscal.get(), sizeof(double), hipMemcpyDeviceToHost, s));
+            GLK_HIP(hipStreamSynchronize(s));
+            *norm_D = std::sqrt(mesh->hscal[0]);
+        }
+    });
+}
+
+gl_status gl_profile_start(int kernel_id)
+{
+    return guarded([&] {
+        if (kernel_id < 1 || kernel_id > 7) fail(GL_ERR_INVALID_ARGUMENT, "gl_profile_start: kernel id");
+        Profiler &p = profiler();
+        p.kernel = kernel_id;
+        p.used = 0;
+        p.bytes = 0.0;
+    });
+}
+
+gl_status gl_profile_stop(double *ms_total, double *bytes_total, int64_t *launches)
+{
+    return guarded([&] {
+        Profiler &p = profiler();
+        GLK_HIP(hipDeviceSynchronize());
+        double ms = 0.0;
+        for (size_t k = 0; k < p.used; ++k) {
+            float t = 0.f;
+            GLK_HIP(hipEventElapsedTime(&t, p.ev[k].first, p.ev[k].second));
+            ms += t;
+        }
+        if (ms_total) *ms_total = ms;
+        if (bytes_total) *bytes_total = p.bytes;
+        if (launches) *launches = (int64_t)p.used;
+        p.kernel = 0;
+        p.used = 0;
+        p.bytes = 0.0;
+    });
+}
+
+gl_status gl_jacobian_apply(const gl_mesh *mesh, const void *psi, const void *phi, void *out,
+                            gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !psi || !phi || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_jacobian_apply: NULL argument");
+        if (out == psi || out == phi) fail(GL_ERR_INVALID_ARGUMENT, "gl_jacobian_apply: out aliases an input");
+        jacobian_enqueue(mesh, (const double2 *)psi, (const double2 *)phi, (double2 *)out, as_stream(stream));
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Node-centred application of K-hat on the tensor grid (discrete kinetic
+// energy operator, Sec. 3): for node i and each axis a with lower neighbour
+// k = i - s_a and upper neighbour j = i + s_a,
+//   (K-hat x)_i = sum_a alpha_a [ (x_i - U_a[k] x_k) + (x_i - conj(U_a[i]) x_j) ]
+// where U_a[k] is the link variable of the forward edge leaving node k along
+// axis a (stored [axis][n]).  |V_i| and alpha_a are computed from the node's
+// position, so the operator streams only x and the link variables.
+#pragma once
+
+#include "common.h"
+
+namespace glk {
+
+template <int DIM>
+__device__ __forceinline__ void node_coords(const int *N, int i, int c[3])
+{
+    c[0] = i % N[0];
+    int t = i / N[0];
+    if (DIM == 3) {
+        c[1] = t % N[1];
+        c[2] = t / N[1];
+    } else {
+        c[1] = t;
+        c[2] = 0;
+    }
+}
+
+// |V_i| and the boundary factors s_a (1 interior, 2 boundary) of node c.
+template <int DIM, class T>
+__device__ __forceinline__ T node_volume(const GeomT<T> &g, const int c[3], T s[3])
+{
+    T d = (T)1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        bool bnd = (c[a] == 0) || (c[a] == g.N[a] - 1);
+        s[a] = bnd ? (T)2 : (T)1;
+        d *= bnd ? (T)0.5 * g.h[a] : g.h[a];
+    }
+    return d;
+}
+
+// Returns (K-hat x)_i; d = |V_i|, asum = K-hat_ii = sum of alpha over the
+// edges at i.  x_i is passed in (already loaded by the caller).
+template <int DIM, class T>
+__device__ __forceinline__ C<T> khat_node(const GeomT<T> &g, int i, const int c[3],
+                                          const C<T> *__restrict__ x,
+                                          const C<T> *__restrict__ U, C<T> xi, T &d, T &asum)
+{
+    T s[3];
+    d = node_volume<DIM, T>(g, c, s);
+    C<T> acc = mk<T>(0, 0);
+    asum = 0;
+    int stride = 1;
+    const size_t n = (size_t)g.n;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T al = d * s[a] * g.inv_h2[a];
+        if (c[a] > 0) {
+            const C<T> u = U[a * n + (i - stride)];
+            const C<T> xk = x[i - stride];
+            acc = csub(acc, cscale(cmul(u, xk), al));
+            asum += al;
+        }
+        if (c[a] < g.N[a] - 1) {
+            const C<T> u = U[a * n + i];
+            const C<T> xj = x[i + stride];
+            acc = csub(acc, cscale(cmulc(u, xj), al));
+            asum += al;
+        }
+        stride *= g.N[a];
+    }
+    return cadd(acc, cscale(xi, asum));
+}
+
+// Off-diagonal part only: sum_{j != i} K-hat_ij x_j.
+template <int DIM, class T>
+__device__ __forceinline__ C<T> khat_offdiag(const GeomT<T> &g, int i, const int c[3],
+                                             const C<T> *__restrict__ x,
+                                             const C<T> *__restrict__ U)
+{
+    T s[3];
+    const T d = node_volume<DIM, T>(g, c, s);
+    C<T> acc = mk<T>(0, 0);
+    int stride = 1;
+    const size_t n = (size_t)g.n;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T al = d * s[a] * g.inv_h2[a];
+        if (c[a] > 0) acc = csub(acc, cscale(cmul(U[a * n + (i - stride)], x[i - stride]), al));
+        if (c[a] < g.N[a] - 1) acc = csub(acc, cscale(cmulc(U[a * n + i], x[i + stride]), al));
+        stride *= g.N[a];
+    }
+    return acc;
+}
+
+}  // namespace glk

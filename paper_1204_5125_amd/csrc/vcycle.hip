@@ -1,0 +1,728 @@
+// Application of the preconditioner R_k = AMG_k(H, D .) (eq. prec2): k
+// V-cycles from zero on H x = v with one symmetric Gauss-Seidel sweep before
+// and after the coarse correction (Sec. 4.1).  A symmetric sweep visits the
+// colours 0 .. C-1 and then C-2 .. 0; on level 0 (red-black, red = even index
+// sum) that is red, black, red.  Every kernel is templated on the storage and
+// arithmetic type (double or float); the input v and the output z are FP64.
+//
+// Level 0 needs seven stencil passes instead of nine because a Gauss-Seidel
+// update of a red node does not read the node's previous value:
+//   - the first red update from x = 0 is x_r = b_r / H_rr, folded into the
+//     black update that follows (which evaluates it for its red neighbours);
+//   - after the coarse correction only the black values x_b + (P x_c)_b are
+//     read (by the first red update), so the prolongation is folded into it;
+//   - after the pre-smoothing sweep the red residual is zero (the last update
+//     made it so), and only black residuals are formed.
+#include <cstring>
+#include <type_traits>
+
+#include "amg.h"
+#include "stencil.h"
+
+namespace glk {
+
+#define GATE()                               \
+    if (gate && *gate == 0) return
+
+template <class T> __device__ __forceinline__ C<T> load_b(const double2 *v, const C<T> *b, int i)
+{
+    if constexpr (std::is_same<T, double>::value) return v[i];
+    else return b[i];
+}
+
+// pre-smoothing, black pass from zero; FP32 also stores b = round(v)
+template <int DIM, class T>
+__global__ __launch_bounds__(kBlock) void k_l0_pre_black(GeomT<T> g, const double2 *__restrict__ v,
+                                                         C<T> *__restrict__ b, C<T> *__restrict__ x,
+                                                         const C<T> *__restrict__ U,
+                                                         const T *__restrict__ hd, const int *gate)
+{
+    GATE();
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    const C<T> bi = narrow<T>(v[i]);
+    if constexpr (std::is_same<T, float>::value) b[i] = bi;
+    if (((c[0] + c[1] + c[2]) & 1) == 0) return;
+    T s[3];
+    const T d = node_volume<DIM, T>(g, c, s);
+    C<T> off = mk<T>(0, 0);
+    int stride = 1;
+    const size_t n = (size_t)g.n;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T al = d * s[a] * g.inv_h2[a];
+        if (c[a] > 0) {
+            const int k = i - stride;
+            const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
+            off = csub(off, cscale(cmul(U[a * n + k], xk), al));
+        }
+        if (c[a] < g.N[a] - 1) {
+            const int k = i + stride;
+            const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
+            off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
+        }
+        stride *= g.N[a];
+    }
+    x[i] = cscale(csub(bi, off), (T)1 / hd[i]);
+}
+
+// x_i = (b_i - sum_{j != i} H_ij x_j) / H_ii on one colour
+template <int DIM, class T>
+__global__ __launch_bounds__(kBlock) void k_l0_sweep(GeomT<T> g, int colour, const double2 *__restrict__ v,
+                                                     const C<T> *__restrict__ b, C<T> *__restrict__ x,
+                                                     const C<T> *__restrict__ U, const T *__restrict__ hd,
+                                                     const int *gate)
+{
+    GATE();
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    if (((c[0] + c[1] + c[2]) & 1) != colour) return;
+    const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+    x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+}
+
+// r = b - H x on black nodes, 0 on red nodes
+template <int DIM, class T>
+__global__ __launch_bounds__(kBlock) void k_l0_residual(GeomT<T> g, const double2 *__restrict__ v,
+                                                        const C<T> *__restrict__ b, const C<T> *__restrict__ x,
+                                                        const C<T> *__restrict__ U, const T *__restrict__ hd,
+                                                        C<T> *__restrict__ r, const int *gate)
+{
+    GATE();
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    if (((c[0] + c[1] + c[2]) & 1) == 0) {
+        r[i] = mk<T>(0, 0);
+        return;
+    }
+    const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+    r[i] = csub(csub(load_b<T>(v, b, i), cscale(x[i], hd[i])), off);
+}
+
+// r = v - H z on every node, FP64 (between cycles of R_k, k > 1)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_l0_residual_full(GeomT<double> g, const double2 *__restrict__ v,
+                                                             const double2 *__restrict__ z,
+                                                             const double2 *__restrict__ U,
+                                                             const double *__restrict__ hd,
+                                                             double2 *__restrict__ r, const int *gate)
+{
+    GATE();
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    const double2 off = khat_offdiag<DIM, double>(g, i, c, z, U);
+    r[i] = csub(csub(v[i], cscale(z[i], hd[i])), off);
+}
+
+// (P x_c)_k for one fine row
+template <class T>
+__device__ __forceinline__ C<T> prolong_row(const int *__restrict__ prp, const int *__restrict__ pci,
+                                            const C<T> *__restrict__ pv, const C<T> *__restrict__ xc, int k)
+{
+    C<T> s = mk<T>(0, 0);
+    for (int p = prp[k]; p < prp[k + 1]; ++p) s = cadd(s, cmul(pv[p], xc[pci[p]]));
+    return s;
+}
+
+// post-smoothing, first red pass with the coarse correction of the black neighbours
+template <int DIM, class T>
+__global__ __launch_bounds__(kBlock) void k_l0_post_red(GeomT<T> g, const double2 *__restrict__ v,
+                                                        const C<T> *__restrict__ b, C<T> *__restrict__ x,
+                                                        const C<T> *__restrict__ U, const T *__restrict__ hd,
+                                                        const int *__restrict__ prp, const int *__restrict__ pci,
+                                                        const C<T> *__restrict__ pv, const C<T> *__restrict__ xc,
+                                                        const int *gate)
+{
+    GATE();
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    if (((c[0] + c[1] + c[2]) & 1) != 0) return;
+    T s[3];
+    const T d = node_volume<DIM, T>(g, c, s);
+    C<T> off = mk<T>(0, 0);
+    int stride = 1;
+    const size_t n = (size_t)g.n;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T al = d * s[a] * g.inv_h2[a];
+        if (c[a] > 0) {
+            const int k = i - stride;
+            const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
+            off = csub(off, cscale(cmul(U[a * n + k], xk), al));
+        }
+        if (c[a] < g.N[a] - 1) {
+            const int k = i + stride;
+            const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
+            off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
+        }
+        stride *= g.N[a];
+    }
+    x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+}
+
+// last red pass; z = x (ADD: z += x) on every node and partial sums of Re<vdot, z>
+template <int DIM, class T, int ADD>
+__global__ __launch_bounds__(kBlock) void k_l0_last(GeomT<T> g, const double2 *__restrict__ v,
+                                                    const C<T> *__restrict__ b, C<T> *__restrict__ x,
+                                                    const C<T> *__restrict__ U, const T *__restrict__ hd,
+                                                    double2 *__restrict__ z, const double2 *__restrict__ vdot,
+                                                    RedSlot slot, int want_dot, const int *gate)
+{
+    GATE();
+    __shared__ double sm[kBlock / 64];
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    double part = 0.0;
+    if (i < g.n) {
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        C<T> xi;
+        if (((c[0] + c[1] + c[2]) & 1) == 0) {
+            const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+            xi = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+            x[i] = xi;
+        } else {
+            xi = x[i];
+        }
+        double2 zi = widen(xi);
+        if (ADD) zi = cadd(z[i], zi);
+        z[i] = zi;
+        if (want_dot) part = redot(vdot[i], zi);
+    }
+    if (want_dot) block_reduce_store(part, slot, sm);
+}
+
+// --------------------------------------------------------------- CSR ---
+// LPR lanes of one wave share a row; partial sums are combined by shuffles.
+template <class T, int LPR>
+__device__ __forceinline__ C<T> lanes_sum(C<T> s)
+{
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+        s.x += __shfl_xor(s.x, o, 64);
+        s.y += __shfl_xor(s.y, o, 64);
+    }
+    return s;
+}
+
+// Gauss-Seidel update of the rows row0 .. row0 + count - 1 (one colour)
+template <class T, int LPR>
+__global__ __launch_bounds__(kBlock) void k_csr_sgs(const int *__restrict__ rp, const int *__restrict__ ci,
+                                                    const C<T> *__restrict__ v, const T *__restrict__ diag,
+                                                    int row0, int count,
+                                                    const C<T> *__restrict__ b, C<T> *__restrict__ x,
+                                                    const int *gate)
+{
+    GATE();
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int r = t / LPR, lane = t % LPR;
+    const bool act = r < count;
+    const int i = row0 + (act ? r : 0);
+    C<T> s = mk<T>(0, 0);
+    if (act)
+        for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) {
+            const int j = ci[p];
+            if (j != i) s = cadd(s, cmul(v[p], x[j]));
+        }
+    s = lanes_sum<T, LPR>(s);
+    if (act && lane == 0) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
+}
+
+// r = b - A x
+template <class T, int LPR>
+__global__ __launch_bounds__(kBlock) void k_csr_residual(int n, const int *__restrict__ rp,
+                                                         const int *__restrict__ ci, const C<T> *__restrict__ v,
+                                                         const C<T> *__restrict__ b, const C<T> *__restrict__ x,
+                                                         C<T> *__restrict__ r, const int *gate)
+{
+    GATE();
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int i = t / LPR, lane = t % LPR;
+    const bool act = i < n;
+    C<T> s = mk<T>(0, 0);
+    if (act)
+        for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
+    s = lanes_sum<T, LPR>(s);
+    if (act && lane == 0) r[i] = csub(b[i], s);
+}
+
+// y = A x (ADD = 0) or y += A x (ADD = 1)
+template <class T, int LPR, int ADD>
+__global__ __launch_bounds__(kBlock) void k_csr_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                     const C<T> *__restrict__ v, const C<T> *__restrict__ x,
+                                                     C<T> *__restrict__ y, const int *gate)
+{
+    GATE();
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int i = t / LPR, lane = t % LPR;
+    const bool act = i < n;
+    C<T> s = mk<T>(0, 0);
+    if (act)
+        for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
+    s = lanes_sum<T, LPR>(s);
+    if (act && lane == 0) y[i] = ADD ? cadd(y[i], s) : s;
+}
+
+template <class T>
+__global__ void k_fill_zero(int n, C<T> *x, const int *gate)
+{
+    GATE();
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = mk<T>(0, 0);
+}
+
+template <class T>
+__global__ void k_narrow(int n, const double2 *v, C<T> *b, const int *gate)
+{
+    GATE();
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) b[i] = narrow<T>(v[i]);
+}
+
+// z = x (ADD = 0) or z += x (ADD = 1); partial sums of Re<vdot, z>
+template <class T, int ADD>
+__global__ __launch_bounds__(kBlock) void k_output(int n, const C<T> *__restrict__ x,
+                                                   const double2 *__restrict__ vdot, double2 *__restrict__ z,
+                                                   RedSlot slot, int want_dot, const int *gate)
+{
+    GATE();
+    __shared__ double sm[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double part = 0.0;
+    if (i < n) {
+        double2 zi = widen(x[i]);
+        if (ADD) zi = cadd(z[i], zi);
+        z[i] = zi;
+        if (want_dot) part = redot(vdot[i], zi);
+    }
+    if (want_dot) block_reduce_store(part, slot, sm);
+}
+
+// x = M b for the dense row-major inverse of the coarsest operator (a wave per row)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dense_apply(int n, const C<T> *__restrict__ M,
+                                                        const C<T> *__restrict__ b, C<T> *__restrict__ x,
+                                                        const int *gate)
+{
+    GATE();
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int i = t / 64, lane = t % 64;
+    const bool act = i < n;
+    C<T> s = mk<T>(0, 0);
+    if (act)
+        for (int j = lane; j < n; j += 64) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
+    s = lanes_sum<T, 64>(s);
+    if (act && lane == 0) x[i] = s;
+}
+
+// ------------------------------------------------------------ bottom ---
+// Every level from D.first down to the coarsest, in one work-group of
+// kBottomThreads threads: the same V-cycle steps as the multi-kernel levels,
+// separated by work-group barriers, and the dense Cholesky solve.
+constexpr int kBottomThreads = 1024;
+constexpr int kBottomLpr = 8;
+
+template <class T>
+__device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int colour)
+{
+    const int cnt = L.coff[colour + 1] - L.coff[colour];
+    const int row0 = L.coff[colour];
+    const int per = kBottomThreads / kBottomLpr;
+    const int lane = threadIdx.x % kBottomLpr;
+    for (int base = 0; base < cnt; base += per) {
+        const int r = base + threadIdx.x / kBottomLpr;
+        const bool act = r < cnt;
+        const int i = row0 + (act ? r : 0);
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int p = L.rp[i] + lane; p < L.rp[i + 1]; p += kBottomLpr) {
+                const int j = L.ci[p];
+                if (j != i) s = cadd(s, cmul(L.v[p], L.x[j]));
+            }
+        s = lanes_sum<T, kBottomLpr>(s);
+        if (act && lane == 0) L.x[i] = cscale(csub(L.b[i], s), (T)1 / L.diag[i]);
+    }
+}
+
+// MODE 0: y = M x, 1: y += M x, 2: y = b - M x
+template <class T, int MODE>
+__device__ __forceinline__ void bottom_rows_spmv(int nrows, const int *rp, const int *ci, const C<T> *v,
+                                                 const C<T> *x, const C<T> *b, C<T> *y)
+{
+    const int per = kBottomThreads / kBottomLpr;
+    const int lane = threadIdx.x % kBottomLpr;
+    for (int base = 0; base < nrows; base += per) {
+        const int i = base + threadIdx.x / kBottomLpr;
+        const bool act = i < nrows;
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int p = rp[i] + lane; p < rp[i + 1]; p += kBottomLpr) s = cadd(s, cmul(v[p], x[ci[p]]));
+        s = lanes_sum<T, kBottomLpr>(s);
+        if (act && lane == 0) {
+            if (MODE == 0) y[i] = s;
+            else if (MODE == 1) y[i] = cadd(y[i], s);
+            else y[i] = csub(b[i], s);
+        }
+    }
+}
+
+// y = M b for a dense row-major n x n matrix
+template <class T>
+__device__ __forceinline__ void bottom_dense(int n, const C<T> *M, const C<T> *b, C<T> *y)
+{
+    const int per = kBottomThreads / kBottomLpr;
+    const int lane = threadIdx.x % kBottomLpr;
+    for (int base = 0; base < n; base += per) {
+        const int i = base + threadIdx.x / kBottomLpr;
+        const bool act = i < n;
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int j = lane; j < n; j += kBottomLpr) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
+        s = lanes_sum<T, kBottomLpr>(s);
+        if (act && lane == 0) y[i] = s;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L)
+{
+    for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
+        bottom_rows_sgs<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t);
+        __syncthreads();
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomDesc<T> *__restrict__ Dp, const int *gate)
+{
+    GATE();
+    const BottomDesc<T> &D = *Dp;
+    for (int l = D.first; l < D.last; ++l) {
+        const BottomLevel<T> &L = D.L[l];
+        for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = mk<T>(0, 0);
+        __syncthreads();
+        bottom_sgs<T>(L);
+        bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, L.x, L.b, L.r);
+        __syncthreads();
+        bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, L.r, nullptr, D.L[l + 1].b);
+        __syncthreads();
+    }
+    // coarsest level: x = A^-1 b with the dense inverse
+    {
+        const BottomLevel<T> &Lc = D.L[D.last];
+        bottom_dense<T>(Lc.n, D.cinv, Lc.b, Lc.x);
+        __syncthreads();
+    }
+    for (int l = D.last - 1; l >= D.first; --l) {
+        const BottomLevel<T> &L = D.L[l];
+        bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, L.x);
+        __syncthreads();
+        bottom_sgs<T>(L);
+    }
+}
+
+// ---------------------------------------------------------------- host -
+template <class T> static C<T> *vec_b(Level &L);
+template <class T> static C<T> *vec_x(Level &L);
+template <class T> static C<T> *vec_r(Level &L);
+template <> double2 *vec_b<double>(Level &L) { return L.b64.get(); }
+template <> double2 *vec_x<double>(Level &L) { return L.x64.get(); }
+template <> double2 *vec_r<double>(Level &L) { return L.r64.get(); }
+template <> float2 *vec_b<float>(Level &L) { return L.b32.get(); }
+template <> float2 *vec_x<float>(Level &L) { return L.x32.get(); }
+template <> float2 *vec_r<float>(Level &L) { return L.r32.get(); }
+template <class T> static const C<T> *vals(const Csr &M);
+template <> const double2 *vals<double>(const Csr &M) { return M.v64.get(); }
+template <> const float2 *vals<float>(const Csr &M) { return M.v32.get(); }
+// level-0 diagonal (natural order) and the colour-ordered diagonal of l >= 1
+template <class T> static const T *diag(const Level &L);
+template <> const double *diag<double>(const Level &L) { return L.diag64.get(); }
+template <> const float *diag<float>(const Level &L) { return L.diag32.get(); }
+template <class T> static const T *dgn(const Level &L);
+template <> const double *dgn<double>(const Level &L) { return L.dg64.get(); }
+template <> const float *dgn<float>(const Level &L) { return L.dg32.get(); }
+template <class T> static const C<T> *links(const gl_mesh *m);
+template <> const double2 *links<double>(const gl_mesh *m) { return m->U64.get(); }
+template <> const float2 *links<float>(const gl_mesh *m) { return m->U32.get(); }
+template <class T> static const C<T> *cinv(const gl_precond *p);
+template <> const double2 *cinv<double>(const gl_precond *p) { return p->cinv64.get(); }
+template <> const float2 *cinv<float>(const gl_precond *p) { return p->cinv32.get(); }
+template <class T> static const BottomDesc<T> *bdesc(const gl_precond *p);
+template <> const BottomDesc<double> *bdesc<double>(const gl_precond *p)
+{
+    return reinterpret_cast<const BottomDesc<double> *>(p->bdesc64.get());
+}
+template <> const BottomDesc<float> *bdesc<float>(const gl_precond *p)
+{
+    return reinterpret_cast<const BottomDesc<float> *>(p->bdesc32.get());
+}
+
+static int lanes_for(const Csr &M)
+{
+    const double avg = M.n ? (double)M.nnz / M.n : 1.0;
+    if (avg <= 2.5) return 1;
+    if (avg <= 5.0) return 2;
+    if (avg <= 10.0) return 4;
+    if (avg <= 20.0) return 8;
+    if (avg <= 40.0) return 16;
+    return 32;
+}
+
+// dispatch a CSR kernel over LPR in {1, 2, 4, 8, 16, 32}
+#define GLK_LPR_SWITCH(lpr, ...)                              \
+    switch (lpr) {                                            \
+    case 1: { constexpr int LPR = 1; __VA_ARGS__; } break;    \
+    case 2: { constexpr int LPR = 2; __VA_ARGS__; } break;    \
+    case 4: { constexpr int LPR = 4; __VA_ARGS__; } break;    \
+    case 8: { constexpr int LPR = 8; __VA_ARGS__; } break;    \
+    case 16: { constexpr int LPR = 16; __VA_ARGS__; } break;  \
+    default: { constexpr int LPR = 32; __VA_ARGS__; } break;  \
+    }
+
+template <class T>
+static void csr_spmv(const Csr &M, const C<T> *x, C<T> *y, bool add, const int *gate, hipStream_t s)
+{
+    const int lpr = lanes_for(M);
+    const int nb = blocks_for((int64_t)M.n * lpr);
+    GLK_LPR_SWITCH(lpr, {
+        if (add) k_csr_spmv<T, LPR, 1><<<nb, kBlock, 0, s>>>(M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate);
+        else k_csr_spmv<T, LPR, 0><<<nb, kBlock, 0, s>>>(M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate);
+    });
+}
+
+template <class T>
+static void csr_sgs(Level &L, const int *gate, hipStream_t s)
+{
+    const int lpr = lanes_for(L.Aa);
+    for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
+        const int c = t < L.ncolors ? t : 2 * L.ncolors - 2 - t;
+        const int cnt = L.coff[c + 1] - L.coff[c];
+        if (cnt == 0) continue;
+        const int nb = blocks_for((int64_t)cnt * lpr);
+        GLK_LPR_SWITCH(lpr, {
+            k_csr_sgs<T, LPR><<<nb, kBlock, 0, s>>>(L.Aa.rp.get(), L.Aa.ci.get(), vals<T>(L.Aa), dgn<T>(L),
+                                                    L.coff[c], cnt, vec_b<T>(L), vec_x<T>(L), gate);
+        });
+    }
+}
+
+template <class T>
+static void csr_residual(Level &L, const int *gate, hipStream_t s)
+{
+    const int lpr = lanes_for(L.Aa);
+    const int nb = blocks_for((int64_t)L.n * lpr);
+    GLK_LPR_SWITCH(lpr, {
+        k_csr_residual<T, LPR><<<nb, kBlock, 0, s>>>(L.n, L.Aa.rp.get(), L.Aa.ci.get(), vals<T>(L.Aa),
+                                                     vec_b<T>(L), vec_x<T>(L), vec_r<T>(L), gate);
+    });
+}
+
+template <int DIM, class T>
+static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
+                        const int *gate, KrylovScalars *ks, int mode, int add, hipStream_t s)
+{
+    gl_precond *pre = const_cast<gl_precond *>(cpre);
+    const gl_mesh *m = pre->mesh;
+    const GeomT<T> g = geom_t<T>(m->g);
+    const C<T> *U = links<T>(m);
+    const RedSlot slot = red_slot(m, 1);
+    Level &L0 = pre->L[0];
+    const int n0 = L0.n, nb0 = blocks_for(n0);
+    const int nl = pre->nlev;
+    const bool f32 = std::is_same<T, float>::value;
+    C<T> *b0 = f32 ? vec_b<T>(L0) : (C<T> *)v;
+    C<T> *x0 = vec_x<T>(L0);
+    const int want = ks != nullptr;
+    if (nl == 1) {
+        k_narrow<T><<<nb0, kBlock, 0, s>>>(n0, v, vec_b<T>(L0), gate);
+        k_dense_apply<T><<<blocks_for((int64_t)n0 * 64), kBlock, 0, s>>>(n0, cinv<T>(pre), vec_b<T>(L0), x0, gate);
+        if (add) k_output<T, 1><<<nb0, kBlock, 0, s>>>(n0, x0, vdot, z, slot, want, gate);
+        else k_output<T, 0><<<nb0, kBlock, 0, s>>>(n0, x0, vdot, z, slot, want, gate);
+        GLK_CHECK_LAUNCH();
+        if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, s);
+        return;
+    }
+    const T *hd = diag<T>(L0);
+    Level &L1 = pre->L[1];
+    // algorithmic bytes of the level-0 kernels (each array touched once)
+    const double sz = sizeof(C<T>), szr = sizeof(T), E = grid_edges(m->g), nn = n0, mc = 0.5 * nn;
+    const double b_pre = nn * 16 + (f32 ? nn * sz : 0) + nn * szr + E * sz + mc * sz;
+    const double b_sweep = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz;
+    const double b_resid = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz + nn * sz;
+    const double b_post = b_sweep + (nn + 1 + L0.Pa.nnz) * 4.0 + L0.Pa.nnz * sz + L0.nc * sz;
+    const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
+    const double b_restr = (L0.nc + 1 + L0.Ra.nnz) * 4.0 + L0.Ra.nnz * sz + nn * sz + L0.nc * sz;
+    // level 0, down: red (from zero, folded) + black, red, black residual, restriction
+    prof_launch(PROF_L0_SWEEP, b_pre, s, [&] {
+        k_l0_pre_black<DIM, T><<<nb0, kBlock, 0, s>>>(g, v, vec_b<T>(L0), x0, U, hd, gate);
+    });
+    prof_launch(PROF_L0_SWEEP, b_sweep, s, [&] {
+        k_l0_sweep<DIM, T><<<nb0, kBlock, 0, s>>>(g, 0, v, b0, x0, U, hd, gate);
+    });
+    prof_launch(PROF_L0_RESIDUAL, b_resid, s, [&] {
+        k_l0_residual<DIM, T><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, vec_r<T>(L0), gate);
+    });
+    prof_launch(PROF_L0_TRANSFER, b_restr, s, [&] {
+        csr_spmv<T>(L0.Ra, vec_r<T>(L0), vec_b<T>(L1), false, gate, s);
+    });
+    GLK_CHECK_LAUNCH();
+    // multi-kernel coarse levels, down
+    const int nb_first = pre->bottom;
+    for (int l = 1; l < nb_first; ++l) {
+        Level &L = pre->L[l];
+        k_fill_zero<T><<<blocks_for(L.n), kBlock, 0, s>>>(L.n, vec_x<T>(L), gate);
+        csr_sgs<T>(L, gate, s);
+        csr_residual<T>(L, gate, s);
+        csr_spmv<T>(L.Ra, vec_r<T>(L), vec_b<T>(pre->L[l + 1]), false, gate, s);
+        GLK_CHECK_LAUNCH();
+    }
+    // small levels and the coarsest solve in one work-group, or the coarsest
+    // solve alone as a dense product over many work-groups
+    if (pre->bottom < nl - 1) {
+        k_bottom<T><<<1, kBottomThreads, 0, s>>>(bdesc<T>(pre), gate);
+    } else {
+        Level &Lc = pre->L[nl - 1];
+        k_dense_apply<T><<<blocks_for((int64_t)Lc.n * 64), kBlock, 0, s>>>(Lc.n, cinv<T>(pre), vec_b<T>(Lc),
+                                                                           vec_x<T>(Lc), gate);
+    }
+    GLK_CHECK_LAUNCH();
+    // multi-kernel coarse levels, up
+    for (int l = nb_first - 1; l >= 1; --l) {
+        Level &L = pre->L[l];
+        csr_spmv<T>(L.Pa, vec_x<T>(pre->L[l + 1]), vec_x<T>(L), true, gate, s);
+        csr_sgs<T>(L, gate, s);
+        GLK_CHECK_LAUNCH();
+    }
+    // level 0, up: red with the coarse correction, black, red + output
+    prof_launch(PROF_L0_SWEEP, b_post, s, [&] {
+        k_l0_post_red<DIM, T><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, L0.Pa.rp.get(), L0.Pa.ci.get(),
+                                                     vals<T>(L0.Pa), vec_x<T>(L1), gate);
+    });
+    prof_launch(PROF_L0_SWEEP, b_sweep, s, [&] {
+        k_l0_sweep<DIM, T><<<nb0, kBlock, 0, s>>>(g, 1, v, b0, x0, U, hd, gate);
+    });
+    prof_launch(PROF_L0_SWEEP, b_last, s, [&] {
+        if (add) k_l0_last<DIM, T, 1><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, z, vdot, slot, want, gate);
+        else k_l0_last<DIM, T, 0><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, z, vdot, slot, want, gate);
+    });
+    GLK_CHECK_LAUNCH();
+    if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, s);
+}
+
+template <int DIM, class T>
+static void vcycle_k(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
+                     KrylovScalars *ks, int mode, hipStream_t s)
+{
+    const int k = pre->opts.cycles;
+    if (k <= 1) {
+        vcycle_once<DIM, T>(pre, v, v, z, gate, ks, mode, 0, s);
+        return;
+    }
+    // x <- x + V(v - H x), k times from x = 0
+    const gl_mesh *m = pre->mesh;
+    const GeomT<double> g = geom_t<double>(m->g);
+    const int nb0 = blocks_for(pre->L[0].n);
+    vcycle_once<DIM, T>(pre, v, v, z, gate, nullptr, 0, 0, s);
+    for (int c = 1; c < k; ++c) {
+        k_l0_residual_full<DIM><<<nb0, kBlock, 0, s>>>(g, v, z, m->U64.get(), pre->L[0].diag64.get(),
+                                                       pre->cyc_r.get(), gate);
+        GLK_CHECK_LAUNCH();
+        const bool lastc = (c == k - 1);
+        vcycle_once<DIM, T>(pre, pre->cyc_r.get(), v, z, gate, lastc ? ks : nullptr, mode, 1, s);
+    }
+}
+
+void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
+                    KrylovScalars *ks, int mode, hipStream_t s)
+{
+    const bool f32 = pre->opts.precision == GL_FP32;
+    if (pre->mesh->g.dim == 2) {
+        if (f32) vcycle_k<2, float>(pre, v, z, gate, ks, mode, s);
+        else vcycle_k<2, double>(pre, v, z, gate, ks, mode, s);
+    } else {
+        if (f32) vcycle_k<3, float>(pre, v, z, gate, ks, mode, s);
+        else vcycle_k<3, double>(pre, v, z, gate, ks, mode, s);
+    }
+}
+
+// Device descriptors of the bottom levels (pointers fixed after setup).
+template <class T>
+static void fill_bottom(gl_precond *pre, BottomDesc<T> &D)
+{
+    std::memset(&D, 0, sizeof(D));
+    D.first = pre->bottom;
+    D.last = pre->nlev - 1;
+    D.cinv = cinv<T>(pre);
+    for (int l = 1; l < pre->nlev; ++l) {
+        Level &L = pre->L[l];
+        BottomLevel<T> &B = D.L[l];
+        B.n = L.n;
+        B.nc = L.nc;
+        B.ncolors = L.ncolors;
+        B.rp = L.Aa.rp.get();
+        B.ci = L.Aa.ci.get();
+        B.v = vals<T>(L.Aa);
+        B.diag = dgn<T>(L);
+        for (int c = 0; c <= L.ncolors && c <= kMaxColors && c < (int)L.coff.size(); ++c) B.coff[c] = L.coff[c];
+        if (l + 1 < pre->nlev) {
+            B.prp = L.Pa.rp.get();
+            B.pci = L.Pa.ci.get();
+            B.pv = vals<T>(L.Pa);
+            B.rrp = L.Ra.rp.get();
+            B.rci = L.Ra.ci.get();
+            B.rv = vals<T>(L.Ra);
+        }
+        B.b = vec_b<T>(L);
+        B.x = vec_x<T>(L);
+        B.r = vec_r<T>(L);
+    }
+}
+
+void bottom_descriptors(gl_precond *pre, hipStream_t s)
+{
+    // first level of the bottom kernel: the smallest l >= 1 from which every
+    // level fits (size and colour count); a single-level hierarchy is just the
+    // dense solve on level 0
+    int first = pre->nlev - 1;
+    for (int l = pre->nlev - 2; l >= 1; --l) {
+        const Level &L = pre->L[l];
+        if (L.n > kBottomRows || L.ncolors > kMaxColors) break;
+        first = l;
+    }
+    pre->bottom = first;
+    BottomDesc<double> d64;
+    BottomDesc<float> d32;
+    fill_bottom<double>(pre, d64);
+    fill_bottom<float>(pre, d32);
+    pre->bdesc64.alloc(sizeof(d64));
+    pre->bdesc32.alloc(sizeof(d32));
+    GLK_HIP(hipMemcpyAsync(pre->bdesc64.get(), &d64, sizeof(d64), hipMemcpyHostToDevice, s));
+    GLK_HIP(hipMemcpyAsync(pre->bdesc32.get(), &d32, sizeof(d32), hipMemcpyHostToDevice, s));
+    GLK_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace glk
+
+using namespace glk;
+
+extern "C" gl_status gl_precond_apply(const gl_precond *pre, const void *r, void *z, gl_stream stream)
+{
+    return guarded([&] {
+        if (!pre || !r || !z) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_apply: NULL argument");
+        if (r == z) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_apply: r and z alias");
+        hipStream_t s = as_stream(stream);
+        // R_k r = AMG_k(H, D r)
+        double2 *vin = const_cast<gl_precond *>(pre)->vin.get();
+        scale_by_volume(pre->mesh, (const double2 *)r, vin, s);
+        vcycle_enqueue(pre, vin, (double2 *)z, nullptr, nullptr, 0, s);
+    });
+}

@@ -1,0 +1,329 @@
+"""ctypes binding of libglnk.so (include/glnk.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Vectors are torch.complex128 tensors on the GPU (contiguous); the
+current torch stream is passed to the library unless a stream is given.
+The binding raises if the shared library has not been built.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libglnk.so")
+
+GL_OK = 0
+STATUS = {0: "GL_OK", 1: "GL_ERR_INVALID_ARGUMENT", 2: "GL_ERR_HIP", 3: "GL_ERR_OUT_OF_MEMORY",
+          4: "GL_ERR_NOT_CONVERGED", 5: "GL_ERR_BREAKDOWN", 6: "GL_ERR_NONFINITE",
+          7: "GL_ERR_SINGULAR", 8: "GL_ERR_UNSUPPORTED"}
+GL_FP64, GL_FP32 = 0, 1
+
+# gl_precond_export array identifiers
+EXPORT = {"agg": 0, "root": 1, "color": 2, "A_rp": 3, "A_ci": 4, "A_v": 5, "P_rp": 6, "P_ci": 7,
+          "P_v": 8, "R_rp": 9, "R_ci": 10, "R_v": 11}
+
+EXPORTED_SYMBOLS = [
+    "gl_mesh_create_grid", "gl_mesh_set_field", "gl_mesh_num_nodes", "gl_mesh_export_links",
+    "gl_mesh_destroy", "gl_residual", "gl_jacobian_apply", "gl_precond_setup", "gl_precond_apply",
+    "gl_precond_info", "gl_precond_export", "gl_precond_destroy", "gl_jacobian_solve",
+    "gl_newton_solve", "gl_profile_start", "gl_profile_stop", "gl_status_string", "gl_last_error",
+]
+
+
+class GlnkError(RuntimeError):
+    def __init__(self, code, what, detail=""):
+        super().__init__(f"{what}: {STATUS.get(code, code)} {detail}".strip())
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_axis", C.c_int64 * 3), ("side", C.c_double * 3),
+                ("potential", C.c_int), ("mu", C.c_double), ("b_dir", C.c_double * 3),
+                ("a_matrix", C.c_double * 9)]
+
+
+class AmgOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("cycles", C.c_int), ("max_coarse", C.c_int),
+                ("max_levels", C.c_int)]
+
+
+class KrylovOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("poll_every", C.c_int),
+                ("inner_rtol", C.c_double)]
+
+
+class KrylovInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("eta0", C.c_double),
+                ("res_est", C.c_double), ("res_true", C.c_double)]
+
+
+class NewtonOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_steps", C.c_int), ("fixed_steps", C.c_int),
+                ("use_precond", C.c_int), ("krylov", KrylovOpts), ("amg", AmgOpts)]
+
+
+class NewtonInfo(C.Structure):
+    _fields_ = [("steps", C.c_int), ("converged", C.c_int), ("res", C.c_double * 64),
+                ("krylov_iters", C.c_int * 64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libglnk.so; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libglnk.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    vp, st = C.c_void_p, C.c_int
+    P = C.POINTER
+    L.gl_mesh_create_grid.argtypes = [P(GridDesc), vp, P(vp)]
+    L.gl_mesh_set_field.argtypes = [vp, C.c_double, vp]
+    L.gl_mesh_num_nodes.argtypes = [vp, P(C.c_int64)]
+    L.gl_mesh_export_links.argtypes = [vp, C.c_int, vp]
+    L.gl_mesh_destroy.argtypes = [vp]
+    L.gl_mesh_destroy.restype = None
+    L.gl_residual.argtypes = [vp, vp, vp, P(C.c_double), vp]
+    L.gl_jacobian_apply.argtypes = [vp, vp, vp, vp, vp]
+    L.gl_precond_setup.argtypes = [vp, vp, P(AmgOpts), P(vp), vp]
+    L.gl_precond_apply.argtypes = [vp, vp, vp, vp]
+    L.gl_precond_info.argtypes = [vp, P(C.c_int), P(C.c_int64), P(C.c_int64), P(C.c_int)]
+    L.gl_precond_export.argtypes = [vp, C.c_int, C.c_int, vp, P(C.c_size_t)]
+    L.gl_precond_destroy.argtypes = [vp]
+    L.gl_precond_destroy.restype = None
+    L.gl_jacobian_solve.argtypes = [vp, vp, vp, vp, vp, P(KrylovOpts), P(KrylovInfo), vp]
+    L.gl_newton_solve.argtypes = [vp, vp, P(NewtonOpts), P(vp), P(NewtonInfo), vp]
+    L.gl_profile_start.argtypes = [C.c_int]
+    L.gl_profile_stop.argtypes = [P(C.c_double), P(C.c_double), P(C.c_int64)]
+    L.gl_status_string.argtypes = [st]
+    L.gl_status_string.restype = C.c_char_p
+    L.gl_last_error.argtypes = []
+    L.gl_last_error.restype = C.c_char_p
+    for name in EXPORTED_SYMBOLS:
+        if name not in ("gl_mesh_destroy", "gl_precond_destroy", "gl_status_string", "gl_last_error"):
+            getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+def _check(rc, what, allow=()):
+    if rc != GL_OK and rc not in allow:
+        raise GlnkError(rc, what, lib().gl_last_error().decode())
+    return rc
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _vec(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError(f"{name}: expected a complex128 CUDA tensor")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: expected a contiguous tensor of {n} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """gl_mesh handle: a tensor grid with its link variables on the GPU."""
+
+    def __init__(self, dim, n_axis, side, mu=0.0, b_dir=(0.0, 0.0, 1.0), a_matrix=None, stream=None):
+        d = GridDesc()
+        d.dim = dim
+        for a in range(3):
+            d.n_axis[a] = int(n_axis[a]) if a < len(n_axis) else 1
+            d.side[a] = float(side[a]) if a < len(side) else 1.0
+        d.mu = mu
+        for a in range(3):
+            d.b_dir[a] = b_dir[a]
+        if a_matrix is not None:
+            d.potential = 1
+            for k, v in enumerate(np.asarray(a_matrix, dtype=np.float64).ravel()):
+                d.a_matrix[k] = v
+        h = C.c_void_p()
+        _check(lib().gl_mesh_create_grid(C.byref(d), _stream(stream), C.byref(h)), "gl_mesh_create_grid")
+        self._h = h
+        self.dim = dim
+        self.shape = tuple(int(v) for v in n_axis[:dim])
+        nn = C.c_int64()
+        _check(lib().gl_mesh_num_nodes(h, C.byref(nn)), "gl_mesh_num_nodes")
+        self.n = nn.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_field(self, mu, stream=None):
+        _check(lib().gl_mesh_set_field(self._h, mu, _stream(stream)), "gl_mesh_set_field")
+
+    def export_links(self, axis):
+        out = np.empty(self.n, dtype=np.complex128)
+        _check(lib().gl_mesh_export_links(self._h, axis, out.ctypes.data_as(C.c_void_p)),
+               "gl_mesh_export_links")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gl_mesh_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def gl_mesh_create_grid(dim, n_axis, side, **kw):
+    return Mesh(dim, n_axis, side, **kw)
+
+
+def gl_residual(mesh, psi, out=None, norm=True, stream=None):
+    """out = GL(psi); returns ||GL(psi)||_D when norm is True."""
+    nd = C.c_double()
+    _check(lib().gl_residual(mesh.handle, _vec(psi, mesh.n, "psi"),
+                             _vec(out, mesh.n, "out") if out is not None else None,
+                             C.byref(nd) if norm else None, _stream(stream)), "gl_residual")
+    return nd.value if norm else None
+
+
+def gl_jacobian_apply(mesh, psi, phi, out, stream=None):
+    """out = J(psi) phi."""
+    _check(lib().gl_jacobian_apply(mesh.handle, _vec(psi, mesh.n, "psi"), _vec(phi, mesh.n, "phi"),
+                                   _vec(out, mesh.n, "out"), _stream(stream)), "gl_jacobian_apply")
+
+
+class Precond:
+    """gl_precond handle: R_k(psi) = AMG_k(K-hat + 2 D |psi|^2, D .)."""
+
+    def __init__(self, mesh, psi, precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16,
+                 stream=None):
+        self.mesh = mesh
+        o = AmgOpts(precision, cycles, max_coarse, max_levels)
+        h = C.c_void_p()
+        _check(lib().gl_precond_setup(mesh.handle, _vec(psi, mesh.n, "psi"), C.byref(o), C.byref(h),
+                                      _stream(stream)), "gl_precond_setup")
+        self._h = h
+        self.opts = o
+
+    @property
+    def handle(self):
+        return self._h
+
+    def update(self, psi, precision=None, cycles=None, stream=None):
+        """Recompute the values for a new psi (the hierarchy is kept)."""
+        o = AmgOpts(self.opts.precision if precision is None else precision,
+                    self.opts.cycles if cycles is None else cycles, self.opts.max_coarse,
+                    self.opts.max_levels)
+        h = self._h
+        _check(lib().gl_precond_setup(self.mesh.handle, _vec(psi, self.mesh.n, "psi"), C.byref(o),
+                                      C.byref(h), _stream(stream)), "gl_precond_setup")
+        self.opts = o
+
+    def apply(self, r, z, stream=None):
+        _check(lib().gl_precond_apply(self._h, _vec(r, self.mesh.n, "r"), _vec(z, self.mesh.n, "z"),
+                                      _stream(stream)), "gl_precond_apply")
+
+    def info(self):
+        nlev = C.c_int()
+        sizes = (C.c_int64 * 16)()
+        nnz = (C.c_int64 * 16)()
+        nc = (C.c_int * 16)()
+        _check(lib().gl_precond_info(self._h, C.byref(nlev), sizes, nnz, nc), "gl_precond_info")
+        k = nlev.value
+        return {"nlev": k, "sizes": list(sizes[:k]), "nnz": list(nnz[:k]), "ncolors": list(nc[:k])}
+
+    def export(self, level, what):
+        code = EXPORT[what] if isinstance(what, str) else int(what)
+        nbytes = C.c_size_t(0)
+        _check(lib().gl_precond_export(self._h, level, code, None, C.byref(nbytes)), "gl_precond_export")
+        dtype = np.complex128 if code in (5, 8, 11) else np.int32
+        out = np.empty(nbytes.value // np.dtype(dtype).itemsize, dtype=dtype)
+        _check(lib().gl_precond_export(self._h, level, code, out.ctypes.data_as(C.c_void_p),
+                                       C.byref(nbytes)), "gl_precond_export")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.gl_precond_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def gl_profile_start(kernel_id):
+    _check(lib().gl_profile_start(kernel_id), "gl_profile_start")
+
+
+def gl_profile_stop():
+    """Returns (kernel ms summed, algorithmic bytes summed, launches)."""
+    ms, by, nl = C.c_double(), C.c_double(), C.c_int64()
+    _check(lib().gl_profile_stop(C.byref(ms), C.byref(by), C.byref(nl)), "gl_profile_stop")
+    return ms.value, by.value, nl.value
+
+
+def gl_precond_setup(mesh, psi, **kw):
+    return Precond(mesh, psi, **kw)
+
+
+def gl_precond_apply(pre, r, z, stream=None):
+    pre.apply(r, z, stream)
+
+
+def gl_jacobian_solve(mesh, psi, pre, b, x, rtol=1e-10, max_iter=1000, poll_every=8, inner_rtol=0.0,
+                      stream=None, raise_on_fail=True):
+    """Solve J(psi) x = b by preconditioned MINRES; returns (status, info dict)."""
+    o = KrylovOpts(rtol, max_iter, poll_every, inner_rtol)
+    ki = KrylovInfo()
+    rc = lib().gl_jacobian_solve(mesh.handle, _vec(psi, mesh.n, "psi"),
+                                 pre.handle if pre is not None else None, _vec(b, mesh.n, "b"),
+                                 _vec(x, mesh.n, "x"), C.byref(o), C.byref(ki), _stream(stream))
+    if raise_on_fail:
+        _check(rc, "gl_jacobian_solve", allow=(4,))
+    return rc, {"iterations": ki.iterations, "converged": bool(ki.converged), "eta0": ki.eta0,
+                "res_est": ki.res_est, "res_true": ki.res_true}
+
+
+class PrecondHandle:
+    """Owner of a gl_precond built inside gl_newton_solve (reused across calls)."""
+
+    def __init__(self, mesh):
+        self.mesh = mesh
+        self._h = C.c_void_p()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h and _lib is not None:
+            _lib.gl_precond_destroy(self._h)
+        self._h = C.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+
+def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
+                    krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
+                    precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, precond=None,
+                    stream=None, raise_on_fail=True):
+    """Newton for GL(psi) = 0 in place; returns (status, info dict).  precond:
+    an optional PrecondHandle whose hierarchy is reused (and filled on first use)."""
+    o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
+                   KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol),
+                   AmgOpts(precision, cycles, max_coarse, max_levels))
+    ni = NewtonInfo()
+    rc = lib().gl_newton_solve(mesh.handle, _vec(psi, mesh.n, "psi"), C.byref(o),
+                               C.byref(precond._h) if precond is not None else None, C.byref(ni),
+                               _stream(stream))
+    if raise_on_fail:
+        _check(rc, "gl_newton_solve", allow=(4,))
+    return rc, {"steps": ni.steps, "converged": bool(ni.converged), "res": list(ni.res[:ni.steps + 1]),
+                "krylov_iters": list(ni.krylov_iters[:ni.steps])}

@@ -1,0 +1,278 @@
+"""GPU path vs the FP64 oracle, element by element, through the C-ABI.
+
+Sizes: several tiles of 256 nodes with ragged tails, 2D and 3D, plus the
+33 x 33 config-0 grid.  Tolerances: integer and index arrays bit-exact;
+FP64 outputs within 1e-12 (operators) / 1e-10 (solves) relative; FP32
+preconditioner outputs within 1e-5 relative to the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_5125_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = [
+    # dim, N, side, mu, bdir
+    (2, (33, 33), (5.0, 5.0), 0.8, (0, 0, 1)),
+    (2, (37, 23), (6.0, 4.0), 1.1, (0, 0, 1)),
+    (3, (9, 9, 9), (5.0, 5.0, 5.0), 0.6, (1, 1, 1)),
+    (3, (7, 5, 11), (3.0, 2.0, 4.0), 0.9, (0.3, -0.5, 1.0)),
+]
+IDS = ["2d-33x33", "2d-37x23", "3d-9^3", "3d-7x5x11"]
+
+
+@pytest.fixture(scope="module")
+def glnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_5125_amd import glnk as g
+    g.lib()
+    return g
+
+
+def unit(b):
+    b = np.asarray(b, float)
+    return b / np.linalg.norm(b)
+
+
+def make_pair(glnk, case):
+    dim, N, side, mu, bdir = case
+    b = unit(bdir)
+    m_gpu = glnk.Mesh(dim, N, side, mu=mu, b_dir=b)
+    m_orc = oracle.Mesh(dim, N, side, mu=mu, bdir=b)
+    return m_gpu, m_orc
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_link_variables(glnk, case):
+    mg, mo = make_pair(glnk, case)
+    dim, N = case[0], case[1]
+    off = 0
+    for a in range(dim):
+        u = mg.export_links(a)
+        idx = np.stack(np.unravel_index(np.arange(mo.n), N[::-1])[::-1], axis=1)
+        lower = np.nonzero(idx[:, a] < N[a] - 1)[0]
+        ne_a = lower.size
+        assert np.array_equal(mo.ek[off:off + ne_a], lower)
+        assert np.abs(u[lower] - mo.U[off:off + ne_a]).max() < 1e-14
+        assert np.all(u[idx[:, a] == N[a] - 1] == 0)
+        off += ne_a
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_residual_and_jacobian(glnk, case):
+    mg, mo = make_pair(glnk, case)
+    psi = inputs.random_complex(mo.n, seed=1) * 0.8
+    phi = inputs.random_complex(mo.n, seed=2)
+    out = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    nrm = glnk.gl_residual(mg, dev(psi), out)
+    ref = mo.gl(psi)
+    assert relerr(host(out), ref) < 1e-12
+    assert nrm == pytest.approx(mo.norm(ref), rel=1e-12)
+    jo = torch.empty_like(out)
+    glnk.gl_jacobian_apply(mg, dev(psi), dev(phi), jo)
+    assert relerr(host(jo), mo.jac(psi, phi)) < 1e-12
+
+
+def test_residual_norm_only_and_errors(glnk):
+    mg, mo = make_pair(glnk, CASES[0])
+    psi = dev(inputs.random_phase_state(mo.n, seed=0))
+    n1 = glnk.gl_residual(mg, psi, None)
+    assert n1 == pytest.approx(mo.norm(mo.gl(host(psi))), rel=1e-12)
+    with pytest.raises(glnk.GlnkError) as e:
+        glnk.gl_residual(mg, psi, psi)
+    assert e.value.code == 1
+    with pytest.raises(glnk.GlnkError):
+        glnk.Mesh(4, (3, 3, 3), (1.0, 1.0, 1.0))
+    with pytest.raises(glnk.GlnkError):
+        glnk.Mesh(2, (1, 5), (1.0, 1.0))
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_hierarchy_bit_exact(glnk, case):
+    """Aggregates, roots, colours and every sparsity pattern equal the oracle's
+    bit for bit; values within 1e-12."""
+    mg, mo = make_pair(glnk, case)
+    psi = inputs.random_phase_state(mo.n, seed=3)
+    pre = glnk.Precond(mg, dev(psi))
+    amg = oracle.Amg.for_state(mo, psi)
+    info = pre.info()
+    assert info["nlev"] == amg.nlev
+    for l, L in enumerate(amg.levels):
+        assert info["sizes"][l] == L["n"]
+        assert np.array_equal(pre.export(l, "color"), L["color"])
+        assert np.array_equal(pre.export(l, "A_rp"), L["A"].indptr)
+        assert np.array_equal(pre.export(l, "A_ci"), L["A"].indices)
+        assert relerr(pre.export(l, "A_v"), L["A"].data) < 1e-12
+        if l < amg.nlev - 1:
+            assert np.array_equal(pre.export(l, "agg"), L["agg"])
+            assert np.array_equal(pre.export(l, "root"), L["root"])
+            for M in ("P", "R"):
+                assert np.array_equal(pre.export(l, M + "_rp"), L[M].indptr)
+                assert np.array_equal(pre.export(l, M + "_ci"), L[M].indices)
+                assert relerr(pre.export(l, M + "_v"), L[M].data) < 1e-12
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+def test_vcycle(glnk, case):
+    """R_1 r = AMG_1(H, D r): FP64 within 1e-11, FP32 within 1e-5."""
+    mg, mo = make_pair(glnk, case)
+    psi = inputs.random_phase_state(mo.n, seed=4)
+    r = inputs.random_complex(mo.n, seed=5)
+    amg = oracle.Amg.for_state(mo, psi)
+    ref = amg.precond(mo, r)
+    z = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    pre = glnk.Precond(mg, dev(psi))
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-11
+    pre.update(dev(psi), precision=glnk.GL_FP32)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-5
+    # k = 3 cycles
+    pre.update(dev(psi), precision=glnk.GL_FP64, cycles=3)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), amg.precond(mo, r, cycles=3)) < 1e-11
+
+
+@pytest.mark.parametrize("case", CASES, ids=IDS)
+@pytest.mark.parametrize("precond", [True, False], ids=["R1", "none"])
+def test_minres_iterates(glnk, case, precond):
+    """Fixed-k iterates equal the oracle's; to rtol 1e-10 the iteration count
+    agrees within 1 and the solution within 1e-8."""
+    mg, mo = make_pair(glnk, case)
+    psi = inputs.random_phase_state(mo.n, seed=6)
+    b = inputs.random_complex(mo.n, seed=7)
+    amg = oracle.Amg.for_state(mo, psi) if precond else None
+    pre = glnk.Precond(mg, dev(psi)) if precond else None
+    x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    for k in (1, 2, 5):
+        xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=0.0, max_iter=k)
+        rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=0.0, max_iter=k, poll_every=2)
+        assert ig["iterations"] == k == io["iterations"]
+        assert relerr(host(x), xo) < 1e-9
+        assert ig["res_est"] == pytest.approx(io["eta"] / io["eta0"], rel=1e-8)
+    xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-10, max_iter=2000)
+    rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=2000)
+    assert io["converged"] and ig["converged"]
+    assert abs(ig["iterations"] - io["iterations"]) <= 1
+    assert relerr(host(x), xo) < 1e-8
+    assert ig["res_true"] < 1e-9
+
+
+def test_minres_not_converged_and_zero_rhs(glnk):
+    mg, mo = make_pair(glnk, CASES[0])
+    psi = dev(inputs.random_phase_state(mo.n, seed=8))
+    x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    rc, info = glnk.gl_jacobian_solve(mg, psi, None, dev(inputs.random_complex(mo.n, 9)), x,
+                                      rtol=1e-14, max_iter=3)
+    assert rc == 4 and info["iterations"] == 3 and not info["converged"]
+    rc, info = glnk.gl_jacobian_solve(mg, psi, None, torch.zeros_like(x), x)
+    assert rc == 0 and info["iterations"] == 0
+    assert torch.count_nonzero(x).item() == 0
+
+
+def test_singular_preconditioner(glnk):
+    mg = glnk.Mesh(2, (9, 9), (5.0, 5.0), mu=0.0)
+    with pytest.raises(glnk.GlnkError) as e:
+        glnk.Precond(mg, torch.zeros(81, dtype=torch.complex128, device="cuda"))
+    assert e.value.code == 7
+
+
+def test_newton_config0(glnk):
+    """Config 0: 33 x 33, side 5, mu 0.8, psi0 = 0.9 exp(i theta); Newton +
+    MINRES(R_1, 1e-10) to ||GL||_D < 1e-10.  Step-by-step residual history and
+    Krylov counts follow the oracle's trajectory."""
+    case = CASES[0]
+    mg, mo = make_pair(glnk, case)
+    psi0 = inputs.random_phase_state(mo.n, seed=0)
+    pso, io = oracle.newton(mo, psi0, tol=1e-10, max_steps=50, krylov_rtol=1e-10)
+    psi = dev(psi0)
+    rc, ig = glnk.gl_newton_solve(mg, psi, tol=1e-10, max_steps=50, krylov_rtol=1e-10)
+    assert rc == 0 and ig["converged"] and io["converged"]
+    assert ig["steps"] == io["steps"]
+    for a, b in zip(ig["krylov_iters"], io["krylov_iters"]):
+        assert abs(a - b) <= 1
+    for a, b in list(zip(ig["res"], io["res"]))[:-1]:
+        assert a == pytest.approx(b, rel=1e-6)
+    ps = host(psi)
+    chi = np.angle(np.vdot(ps, pso)) if np.abs(pso).max() > 1e-8 else 0.0
+    assert np.abs(ps * np.exp(1j * chi) - pso).max() < 1e-8
+    # FP32 preconditioner reaches the same tolerance
+    psi = dev(psi0)
+    rc, i32 = glnk.gl_newton_solve(mg, psi, tol=1e-10, max_steps=50, precision=glnk.GL_FP32)
+    assert rc == 0 and i32["converged"]
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2]], ids=["2d-33x33", "3d-9^3"])
+def test_fp32_preconditioned_solve_reaches_fp64_accuracy(glnk, case):
+    """FP32 V-cycle under FP64 refinement: the solution matches the FP64
+    oracle solve to the 1e-10 level and the true residual is below 1e-9."""
+    mg, mo = make_pair(glnk, case)
+    psi = inputs.random_phase_state(mo.n, seed=10)
+    b = inputs.random_complex(mo.n, seed=11)
+    amg = oracle.Amg.for_state(mo, psi)
+    xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-12, max_iter=2000)
+    pre = glnk.Precond(mg, dev(psi), precision=glnk.GL_FP32)
+    x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=2000)
+    assert rc == 0 and info["converged"]
+    assert info["res_true"] < 1e-9
+    assert relerr(host(x), xo) < 1e-8
+
+
+def test_repeated_solves_bitwise_identical(glnk):
+    """Deterministic reductions and graph replay: two solves give identical bits."""
+    mg, mo = make_pair(glnk, CASES[1])
+    psi = dev(inputs.random_phase_state(mo.n, seed=12))
+    b = dev(inputs.random_complex(mo.n, seed=13))
+    pre = glnk.Precond(mg, psi)
+    x1 = torch.empty_like(b)
+    x2 = torch.empty_like(b)
+    rc1, i1 = glnk.gl_jacobian_solve(mg, psi, pre, b, x1, rtol=1e-10)
+    rc2, i2 = glnk.gl_jacobian_solve(mg, psi, pre, b, x2, rtol=1e-10)
+    assert i1["iterations"] == i2["iterations"]
+    assert torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("max_coarse", [64, 512])
+def test_vcycle_and_solve_deeper_hierarchy(glnk, max_coarse):
+    """129 x 129 grid: a coarse level above 512 rows (multi-kernel sweeps), the
+    single-work-group bottom levels and the dense coarsest solve, FP64 and FP32;
+    then MINRES counts and solutions against the oracle."""
+    mg = glnk.Mesh(2, (129, 129), (10.0, 10.0), mu=1.0)
+    mo = oracle.Mesh(2, (129, 129), (10.0, 10.0), mu=1.0)
+    psi = inputs.random_phase_state(mo.n, seed=14)
+    r = inputs.random_complex(mo.n, seed=15)
+    amg = oracle.Amg.for_state(mo, psi, max_coarse=max_coarse)
+    pre = glnk.Precond(mg, dev(psi), max_coarse=max_coarse)
+    assert pre.info()["sizes"] == [L["n"] for L in amg.levels]
+    z = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    pre.apply(dev(r), z)
+    ref = amg.precond(mo, r)
+    assert relerr(host(z), ref) < 1e-11
+    pre.update(dev(psi), precision=glnk.GL_FP32)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-5
+    pre.update(dev(psi), precision=glnk.GL_FP64)
+    xo, io, _ = oracle.minres(mo, psi, r, amg=amg, rtol=1e-10, max_iter=3000)
+    rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(r), z, rtol=1e-10, max_iter=3000)
+    assert io["converged"] and ig["converged"]
+    assert abs(ig["iterations"] - io["iterations"]) <= 1
+    assert relerr(host(z), xo) < 1e-8
