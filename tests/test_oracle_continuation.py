@@ -1,0 +1,40 @@
+"""Pins of the oracle's secant predictor and natural continuation (Sec. 4,
+numerical parameter continuation)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import continuation as oc
+from paper_1204_5125_amd import inputs
+
+
+def test_secant_ignores_a_global_phase():
+    """Solutions are gauge orbits (Sec. 2): a previous state that differs only
+    by a global phase predicts no change."""
+    m = oracle.Mesh(2, (9, 9), (5.0, 5.0), mu=0.4)
+    psi = inputs.random_complex(m.n, seed=1)
+    pred = oc.secant_predict(m, psi, np.exp(0.7j) * psi, 1.0)
+    np.testing.assert_allclose(pred, psi, rtol=1e-13, atol=1e-13)
+
+
+def test_secant_exact_for_affine_family():
+    """For psi(mu) = a + mu b with a common phase, the secant step lands on
+    psi(mu_next) for any step ratio."""
+    m = oracle.Mesh(2, (7, 7), (5.0, 5.0), mu=0.0)
+    rng = np.random.default_rng(2)
+    a, b = rng.uniform(1, 2, m.n), rng.uniform(0, 1, m.n)
+    mu0, mu1, mu2 = 0.1, 0.25, 0.32
+    pred = oc.secant_predict(m, a + mu1 * b, a + mu0 * b, (mu2 - mu1) / (mu1 - mu0))
+    np.testing.assert_allclose(pred, a + mu2 * b, rtol=1e-13)
+
+
+def test_continuation_from_constant_state():
+    """mu = 0, psi = 1 is a solution; each continuation step reaches the Newton
+    tolerance and the energy F/|Omega| rises from -1/2 as mu grows."""
+    recs, psi = oc.continuation(2, (17, 17), (8.0, 8.0), (0, 0, 1), np.ones(289, complex), 0.0, 0.05, 4)
+    assert recs[0]["newton_steps"] == 0
+    assert all(r["status"] == 0 and r["res"] < 1e-10 for r in recs)
+    assert [r["predictor"] for r in recs[1:]] == ["constant", "secant", "secant", "secant"]
+    m = oracle.Mesh(2, (17, 17), (8.0, 8.0), mu=recs[-1]["mu"])
+    f = m.energy(psi) / 64.0
+    assert -0.5 < f < 0.0
