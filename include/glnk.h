@@ -109,6 +109,16 @@ gl_status gl_residual(const gl_mesh *mesh, const void *psi, void *out, double *n
 gl_status gl_jacobian_apply(const gl_mesh *mesh, const void *psi, const void *phi, void *out,
                             gl_stream stream);
 
+/* Secant predictor of natural-parameter continuation in mu (Sec. 4,
+ * numerical parameter continuation):
+ *   out = psi_m + ratio (psi_m - e^{i chi} psi_prev),  chi = arg <psi_prev, psi_m>
+ * with <u, v> = sum |V_i| conj(u_i) v_i.  The phase factor aligns the gauge of
+ * the previous solution with psi_m (solutions are orbits e^{i chi} psi, Sec. 2);
+ * ratio = (mu_{m+1} - mu_m) / (mu_m - mu_{m-1}).  If <psi_prev, psi_m> = 0 the
+ * factor is 1.  out aliases neither input. */
+gl_status gl_secant_predict(const gl_mesh *mesh, const void *psi_m, const void *psi_prev, double ratio,
+                            void *out, gl_stream stream);
+
 /* --------------------------------------------------- preconditioner ---- */
 typedef struct {
     gl_precision precision; /* storage and arithmetic of the V-cycle */

@@ -44,6 +44,13 @@ struct Level {
     DevBuf<int> amap, pmap, rmap;   // value of entry q = value of entry map[q] of A, P, R
     DevBuf<double> dg64;            // diagonal in the new order (l >= 1)
     DevBuf<float> dg32;
+    // Aa once more, each colour as a padded row-major block (ELL): row r of
+    // colour c has ewidth[c] entries at eoff[c] + (r - coff[c]) * ewidth[c];
+    // padding entries point at the row itself with value 0
+    std::vector<int> ewidth, eoff;
+    DevBuf<int> eci, emap;          // emap: entry of Aa, or -1 for padding
+    DevBuf<double2> ev64;
+    DevBuf<float2> ev32;
     // V-cycle vectors (new order on levels >= 1)
     DevBuf<double2> b64, x64, r64;
     DevBuf<float2> b32, x32, r32;

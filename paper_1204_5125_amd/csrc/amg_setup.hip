@@ -644,6 +644,29 @@ __global__ void k_gather_c(int nnz, const int *map, const double2 *src, double2 
     d32[q] = make_float2((float)v.x, (float)v.y);
 }
 
+// padded block of one colour (rows row0 .. row0 + count - 1 of Aa)
+__global__ void k_ell_fill(int row0, int count, int W, const int *rp, const int *ci, int *eci, int *emap)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= count) return;
+    const int i = row0 + r;
+    const int b = rp[i], len = rp[i + 1] - rp[i];
+    for (int k = 0; k < W; ++k) {
+        eci[(size_t)r * W + k] = k < len ? ci[b + k] : i;
+        emap[(size_t)r * W + k] = k < len ? b + k : -1;
+    }
+}
+
+__global__ void k_ell_values(int n, const int *emap, const double2 *src, double2 *d64, float2 *d32)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n) return;
+    const int p = emap[q];
+    const double2 v = p >= 0 ? src[p] : make_double2(0.0, 0.0);
+    d64[q] = v;
+    d32[q] = make_float2((float)v.x, (float)v.y);
+}
+
 __global__ void k_gather_r(int n, const int *perm, const double *src, double *d64, float *d32)
 {
     const int r = blockIdx.x * kBlock + threadIdx.x;
@@ -889,6 +912,31 @@ static void build_apply_copies(gl_precond *pre, hipStream_t s)
             permuted_copy(L.P, rowp, Nx.iperm.get(), L.Pa, L.pmap, s);
             permuted_copy(L.R, Nx.perm.get(), colp, L.Ra, L.rmap, s);
         }
+        if (l >= 1) {
+            // padded colour blocks for the Gauss-Seidel sweeps
+            std::vector<int> rp = to_host(L.Aa.rp.get(), (size_t)L.n + 1, s);
+            L.ewidth.assign(L.ncolors, 0);
+            L.eoff.assign(L.ncolors + 1, 0);
+            for (int c = 0; c < L.ncolors; ++c) {
+                int w = 1;
+                for (int r = L.coff[c]; r < L.coff[c + 1]; ++r) w = std::max(w, rp[r + 1] - rp[r]);
+                L.ewidth[c] = w;
+                L.eoff[c + 1] = L.eoff[c] + w * (L.coff[c + 1] - L.coff[c]);
+            }
+            const int ne = std::max(1, L.eoff[L.ncolors]);
+            L.eci.alloc(ne);
+            L.emap.alloc(ne);
+            L.ev64.alloc(ne);
+            L.ev32.alloc(ne);
+            for (int c = 0; c < L.ncolors; ++c) {
+                const int cnt = L.coff[c + 1] - L.coff[c];
+                if (cnt == 0) continue;
+                k_ell_fill<<<blocks_for(cnt), kBlock, 0, s>>>(L.coff[c], cnt, L.ewidth[c], L.Aa.rp.get(),
+                                                             L.Aa.ci.get(), L.eci.get() + L.eoff[c],
+                                                             L.emap.get() + L.eoff[c]);
+                GLK_CHECK_LAUNCH();
+            }
+        }
     }
     GLK_HIP(hipStreamSynchronize(s));
 }
@@ -982,6 +1030,10 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
                                                                L.Aa.v64.get(), L.Aa.v32.get());
             k_gather_r<<<blocks_for(L.n), kBlock, 0, s>>>(L.n, L.perm.get(), L.diag64.get(), L.dg64.get(),
                                                           L.dg32.get());
+            const int ne = L.eoff.empty() ? 0 : L.eoff.back();
+            if (ne > 0)
+                k_ell_values<<<blocks_for(ne), kBlock, 0, s>>>(ne, L.emap.get(), L.Aa.v64.get(), L.ev64.get(),
+                                                               L.ev32.get());
         }
         if (l < last) {
             k_gather_c<<<blocks_for(L.Pa.nnz), kBlock, 0, s>>>(L.Pa.nnz, L.pmap.get(), L.P.v64.get(),

@@ -184,6 +184,55 @@ void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, 
     GLK_CHECK_LAUNCH();
 }
 
+// partial sums of Re and Im of sum |V_i| conj(u_i) v_i
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_cdot(GeomT<double> g, const double2 *__restrict__ u,
+                                                 const double2 *__restrict__ v, RedSlot sre, RedSlot sim)
+{
+    __shared__ double sm[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double pre = 0.0, pim = 0.0;
+    if (i < g.n) {
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        double sf[3];
+        const double d = node_volume<DIM, double>(g, c, sf);
+        const double2 p = cmulc(u[i], v[i]);
+        pre = d * p.x;
+        pim = d * p.y;
+    }
+    block_reduce_store(pre, sre, sm);
+    block_reduce_store(pim, sim, sm);
+}
+
+// out = psi + ratio (psi - e^{i chi} prev), e^{i chi} = ip / |ip|
+__global__ __launch_bounds__(kBlock) void k_secant(int n, const double2 *__restrict__ psi,
+                                                   const double2 *__restrict__ prev, const double *ip,
+                                                   double ratio, double2 *__restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double a = hypot(ip[0], ip[1]);
+    const double2 ph = a > 0.0 ? make_double2(ip[0] / a, ip[1] / a) : make_double2(1.0, 0.0);
+    const double2 p = psi[i];
+    out[i] = cadd(p, cscale(csub(p, cmul(ph, prev[i])), ratio));
+}
+
+void secant_enqueue(const gl_mesh *m, const double2 *psi, const double2 *prev, double ratio, double2 *out,
+                    hipStream_t s)
+{
+    const int nb = blocks_for(m->g.n);
+    const GeomT<double> g = geom_t<double>(m->g);
+    if (m->g.dim == 2) k_cdot<2><<<nb, kBlock, 0, s>>>(g, prev, psi, red_slot(m, 2), red_slot(m, 3));
+    else k_cdot<3><<<nb, kBlock, 0, s>>>(g, prev, psi, red_slot(m, 2), red_slot(m, 3));
+    GLK_CHECK_LAUNCH();
+    double *ip = m->dscal.get() + 2;
+    launch_finalize(red_slot(m, 2).partials, nb, FIN_STORE, nullptr, ip, nullptr, s);
+    launch_finalize(red_slot(m, 3).partials, nb, FIN_STORE, nullptr, ip + 1, nullptr, s);
+    k_secant<<<nb, kBlock, 0, s>>>(m->g.n, psi, prev, ip, ratio, out);
+    GLK_CHECK_LAUNCH();
+}
+
 // y = D x
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_scale_volume(GeomT<double> g, const double2 *__restrict__ x,
@@ -350,6 +399,18 @@ gl_status gl_residual(const gl_mesh *mesh, const void *psi, void *out, double *n
             GLK_HIP(hipStreamSynchronize(s));
             *norm_D = std::sqrt(mesh->hscal[0]);
         }
+    });
+}
+
+gl_status gl_secant_predict(const gl_mesh *mesh, const void *psi_m, const void *psi_prev, double ratio,
+                            void *out, gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !psi_m || !psi_prev || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_secant_predict: NULL argument");
+        if (out == psi_m || out == psi_prev) fail(GL_ERR_INVALID_ARGUMENT, "gl_secant_predict: out aliases an input");
+        if (!std::isfinite(ratio)) fail(GL_ERR_INVALID_ARGUMENT, "gl_secant_predict: ratio");
+        secant_enqueue(mesh, (const double2 *)psi_m, (const double2 *)psi_prev, ratio, (double2 *)out,
+                       as_stream(stream));
     });
 }
 

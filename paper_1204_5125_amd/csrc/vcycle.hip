@@ -237,6 +237,32 @@ __global__ __launch_bounds__(kBlock) void k_csr_sgs(const int *__restrict__ rp, 
     if (act && lane == 0) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
 }
 
+// Gauss-Seidel update of one colour stored as a padded block (ELL, width W).
+// The gate flag is loaded alongside the data and checked only before the
+// store, so its latency overlaps the row loads.
+template <class T, int LPR>
+__global__ __launch_bounds__(kBlock) void k_ell_sgs(const int *__restrict__ eci, const C<T> *__restrict__ ev,
+                                                    int W, const T *__restrict__ diag, int row0, int count,
+                                                    const C<T> *__restrict__ b, C<T> *__restrict__ x,
+                                                    const int *gate)
+{
+    const int go = gate ? *gate : 1;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int r = t / LPR, lane = t % LPR;
+    const bool act = r < count;
+    const int i = row0 + (act ? r : 0);
+    C<T> s = mk<T>(0, 0);
+    if (act) {
+        const size_t base = (size_t)r * W;
+        for (int k = lane; k < W; k += LPR) {
+            const int j = eci[base + k];
+            if (j != i) s = cadd(s, cmul(ev[base + k], x[j]));
+        }
+    }
+    s = lanes_sum<T, LPR>(s);
+    if (act && lane == 0 && go) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
+}
+
 // r = b - A x
 template <class T, int LPR>
 __global__ __launch_bounds__(kBlock) void k_csr_residual(int n, const int *__restrict__ rp,
@@ -499,17 +525,22 @@ static void csr_spmv(const Csr &M, const C<T> *x, C<T> *y, bool add, const int *
     });
 }
 
+template <class T> static const C<T> *evals(const Level &L);
+template <> const double2 *evals<double>(const Level &L) { return L.ev64.get(); }
+template <> const float2 *evals<float>(const Level &L) { return L.ev32.get(); }
+
 template <class T>
 static void csr_sgs(Level &L, const int *gate, hipStream_t s)
 {
-    const int lpr = lanes_for(L.Aa);
     for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
         const int c = t < L.ncolors ? t : 2 * L.ncolors - 2 - t;
         const int cnt = L.coff[c + 1] - L.coff[c];
         if (cnt == 0) continue;
+        const int W = L.ewidth[c];
+        const int lpr = W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16;
         const int nb = blocks_for((int64_t)cnt * lpr);
         GLK_LPR_SWITCH(lpr, {
-            k_csr_sgs<T, LPR><<<nb, kBlock, 0, s>>>(L.Aa.rp.get(), L.Aa.ci.get(), vals<T>(L.Aa), dgn<T>(L),
+            k_ell_sgs<T, LPR><<<nb, kBlock, 0, s>>>(L.eci.get() + L.eoff[c], evals<T>(L) + L.eoff[c], W, dgn<T>(L),
                                                     L.coff[c], cnt, vec_b<T>(L), vec_x<T>(L), gate);
         });
     }

@@ -25,7 +25,8 @@ EXPORT = {"agg": 0, "root": 1, "color": 2, "A_rp": 3, "A_ci": 4, "A_v": 5, "P_rp
 
 EXPORTED_SYMBOLS = [
     "gl_mesh_create_grid", "gl_mesh_set_field", "gl_mesh_num_nodes", "gl_mesh_export_links",
-    "gl_mesh_destroy", "gl_residual", "gl_jacobian_apply", "gl_precond_setup", "gl_precond_apply",
+    "gl_mesh_destroy", "gl_residual", "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
+    "gl_precond_apply",
     "gl_precond_info", "gl_precond_export", "gl_precond_destroy", "gl_jacobian_solve",
     "gl_newton_solve", "gl_profile_start", "gl_profile_stop", "gl_status_string", "gl_last_error",
 ]
@@ -89,6 +90,7 @@ def lib():
     L.gl_mesh_destroy.restype = None
     L.gl_residual.argtypes = [vp, vp, vp, P(C.c_double), vp]
     L.gl_jacobian_apply.argtypes = [vp, vp, vp, vp, vp]
+    L.gl_secant_predict.argtypes = [vp, vp, vp, C.c_double, vp, vp]
     L.gl_precond_setup.argtypes = [vp, vp, P(AmgOpts), P(vp), vp]
     L.gl_precond_apply.argtypes = [vp, vp, vp, vp]
     L.gl_precond_info.argtypes = [vp, P(C.c_int), P(C.c_int64), P(C.c_int64), P(C.c_int)]
@@ -196,6 +198,12 @@ def gl_jacobian_apply(mesh, psi, phi, out, stream=None):
     """out = J(psi) phi."""
     _check(lib().gl_jacobian_apply(mesh.handle, _vec(psi, mesh.n, "psi"), _vec(phi, mesh.n, "phi"),
                                    _vec(out, mesh.n, "out"), _stream(stream)), "gl_jacobian_apply")
+
+
+def gl_secant_predict(mesh, psi_m, psi_prev, ratio, out, stream=None):
+    """out = psi_m + ratio (psi_m - e^{i chi} psi_prev), chi = arg <psi_prev, psi_m>."""
+    _check(lib().gl_secant_predict(mesh.handle, _vec(psi_m, mesh.n, "psi_m"), _vec(psi_prev, mesh.n, "psi_prev"),
+                                   float(ratio), _vec(out, mesh.n, "out"), _stream(stream)), "gl_secant_predict")
 
 
 class Precond:
