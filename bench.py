@@ -42,12 +42,15 @@ MAX_COARSE = 512
 
 
 def run_steps(glnk, torch, mesh, psi0, psi, handle, precision, steps):
+    # both precisions stop on the true residual (FP64: a restart when the
+    # recurrence estimate and the true residual part; FP32: refinement)
+    inner = RTOL if precision == glnk.GL_FP64 else 0.0
     infos = []
     for _ in range(steps):
         psi.copy_(psi0)
         rc, info = glnk.gl_newton_solve(mesh, psi, fixed_steps=NEWTON_STEPS, krylov_rtol=RTOL,
-                                        krylov_max_iter=4000, poll_every=16, precision=precision,
-                                        max_coarse=MAX_COARSE, precond=handle)
+                                        krylov_max_iter=8000, poll_every=16, precision=precision,
+                                        inner_rtol=inner, max_coarse=MAX_COARSE, precond=handle)
         infos.append(info)
     return infos
 

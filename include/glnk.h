@@ -166,10 +166,12 @@ typedef struct {
     double rtol;       /* stop when ||b - J x||_{M^-1} <= rtol ||b||_{M^-1} */
     int max_iter;      /* total MINRES iterations */
     int poll_every;    /* iterations between host convergence checks (>= 1) */
-    double inner_rtol; /* FP32 preconditioner only: the solve is an FP64 iterative
-                          refinement whose inner MINRES solves (fixed FP32
-                          V-cycle) each reduce the residual by this factor;
-                          0 = 1e-5 */
+    double inner_rtol; /* > 0: the solve is an FP64 iterative refinement whose
+                          inner MINRES solves each reduce the residual by this
+                          factor, stopped on the true residual; 0 = a single
+                          MINRES run stopped on its recurrence estimate with an
+                          FP64 preconditioner (or none), refinement with 1e-5
+                          with an FP32 one */
 } gl_krylov_opts;
 
 typedef struct {
@@ -181,10 +183,10 @@ typedef struct {
 } gl_krylov_info;
 
 /* Solve J(psi) x = b by preconditioned MINRES in <.,.>_R with x0 = 0
- * (Sec. 4).  With an FP32 preconditioner the solve is an FP64 iterative
- * refinement: r = b - J x in FP64, MINRES on J d = r to inner_rtol, x += d,
- * until ||r||_{M^-1} <= rtol ||b||_{M^-1} (info->iterations sums the inner
- * MINRES iterations).  pre == NULL: no preconditioner; otherwise a handle set up for
+ * (Sec. 4).  With an FP32 preconditioner, or inner_rtol > 0, the solve is an
+ * FP64 iterative refinement: r = b - J x in FP64, MINRES on J d = r to
+ * inner_rtol, x += d, until the true ||r||_{M^-1} <= rtol ||b||_{M^-1}
+ * (info->iterations sums the inner MINRES iterations).  pre == NULL: no preconditioner; otherwise a handle set up for
  * the same psi.  x is written even when the iteration limit is reached
  * (returns NOT_CONVERGED).  BREAKDOWN if <v, M^-1 v> becomes negative or NaN.
  * The stream is synchronised; info may be NULL. */

@@ -402,7 +402,8 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
     int iters = 0;
     bool converged = false;
     double eta0 = 0.0, res_est = 0.0;
-    if (!pre || pre->opts.precision == GL_FP64) {
+    const bool fp64 = !pre || pre->opts.precision == GL_FP64;
+    if (fp64 && o.inner_rtol <= 0.0) {
         Ksolve k = make_ksolve(m, psi, pre, b, x);
         ksolve_init<DIM>(k, o.rtol, o.max_iter, s);
         ksolve_iterate<DIM>(k, o.max_iter, poll, s, h);
@@ -412,8 +413,10 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
         res_est = h.eta0 > 0 ? std::fabs(h.eta) / h.eta0 : 0.0;
         if (h.status) st = (gl_status)h.status;
     } else {
-        // FP32 V-cycle: iterative refinement in FP64 around MINRES solves with a
-        // fixed (rounded) preconditioner, each to a moderate relative tolerance
+        // iterative refinement in FP64 around MINRES solves, each to the inner
+        // tolerance (FP32 V-cycle: a fixed rounded preconditioner, whose
+        // rounding caps what one MINRES run attains), stopped on the true
+        // residual in the preconditioner norm
         const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5;
         double2 *d = m->work.get() + 9 * (size_t)n, *r = m->work.get() + 10 * (size_t)n;
         k_copy<<<nb, kBlock, 0, s>>>(n, r, b);

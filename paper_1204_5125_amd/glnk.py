@@ -307,15 +307,20 @@ class PrecondHandle:
 
     @property
     def handle(self):
+        if self._h is None:
+            self._h = C.c_void_p()
         return self._h
 
     def close(self):
         if self._h and _lib is not None:
             _lib.gl_precond_destroy(self._h)
-        self._h = C.c_void_p()
+        self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: ctypes may be gone
+            pass
 
 
 def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
@@ -329,7 +334,7 @@ def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_preco
                    AmgOpts(precision, cycles, max_coarse, max_levels))
     ni = NewtonInfo()
     rc = lib().gl_newton_solve(mesh.handle, _vec(psi, mesh.n, "psi"), C.byref(o),
-                               C.byref(precond._h) if precond is not None else None, C.byref(ni),
+                               C.byref(precond.handle) if precond is not None else None, C.byref(ni),
                                _stream(stream))
     if raise_on_fail:
         _check(rc, "gl_newton_solve", allow=(4,))
