@@ -82,9 +82,109 @@ def cpu_baseline():
                       f"serial C (one host core)"}
 
 
+def newton_rounds(batch, psis, max_rounds, tag, **kw):
+    """Batched Newton one lock-step round per call (the same work as one call
+    with max_steps = max_rounds, with a progress line per round)."""
+    solves = iters = 0
+    infos = None
+    for r in range(max_rounds):
+        rc, infos = batch.newton_solve(psis, max_steps=1, raise_on_fail=False, **kw)
+        n = sum(i["steps"] for i in infos)
+        if n == 0:
+            break
+        solves += n
+        iters += sum(sum(i["krylov_iters"]) for i in infos)
+        sec = batch.stats()["seconds"]
+        log(f"[bench] {tag} round {r + 1}: {n} solves, {iters} iterations so far; "
+            f"setup {sec['setup']:.2f} s, solve {sec['solve']:.2f} s")
+    conv = sum(1 for i in infos if i["res"][-1] < kw["tol"])
+    return solves, iters, conv
+
+
+def bench_batch(args):
+    """Batched continuation: 64 instances on 2D grids of 129^2, 257^2 or 513^2
+    nodes (drawn with seed 0), side 10, mu_k = 2k/63, FP32 V-cycle under FP64
+    outer iterations.  Untimed: autotuning of the tiles per grid size and the
+    warm start (Newton from psi = 1 at mu_k).  Timed: `steps` continuation
+    steps of dmu = 0.02 (secant predictor after the first), each one batched
+    Newton solve of all instances."""
+    import numpy as np
+    import torch
+
+    from paper_1204_5125_amd import autotune, glnk
+    torch.cuda.set_device(0)
+    count, side, dmu = 64, 10.0, 0.02
+    sizes = np.random.default_rng(0).choice([129, 257, 513], count)
+    mus = [2.0 * k / (count - 1) for k in range(count)]
+    meshes = [glnk.Mesh(2, (int(N), int(N)), (side, side), mu=mu) for N, mu in zip(sizes, mus)]
+    psis = [torch.ones(m.n, dtype=torch.complex128, device="cuda") for m in meshes]
+    kw = dict(tol=1e-10, krylov_rtol=1e-10, poll_every=16, precision=glnk.GL_FP32,
+              max_coarse=args.batch_max_coarse)
+    batch = glnk.Batch(meshes)
+    tiles = {}
+    for N in sorted(set(int(v) for v in sizes)):
+        i = int(np.nonzero(sizes == N)[0][0])
+        tiles[N] = autotune.tune(meshes[i], psis[i], precision=glnk.GL_FP32, max_coarse=args.batch_max_coarse,
+                                 cache=args.tile_cache, log=log)
+        log(f"[bench] tiles for {N}^2: lane_shift {tiles[N][0]}, bottom_rows {tiles[N][1]}")
+    for i, N in enumerate(sizes):
+        batch.set_tiles(*tiles[int(N)], index=i)
+    log(f"[bench] warm start of {count} instances, sizes "
+        f"{ {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))} }")
+    t0 = time.perf_counter()
+    ws, wi, wc = newton_rounds(batch, psis, 40, "warm start", krylov_max_iter=4000, **kw)
+    log(f"[bench] warm start: {time.perf_counter() - t0:.2f} s, {ws} solves, converged {wc}/{count}")
+    prev = [p.clone() for p in psis]
+    pred = [torch.empty_like(p) for p in psis]
+    mu_now = list(mus)
+    solves = iters = conv = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(args.steps):
+        for i, m in enumerate(meshes):
+            m.set_field(mu_now[i] + dmu)
+            if step == 0:
+                pred[i].copy_(psis[i])
+            else:
+                glnk.gl_secant_predict(m, psis[i], prev[i], 1.0, pred[i])
+        s_, i_, c_ = newton_rounds(batch, pred, 15, f"step {step + 1}", krylov_max_iter=1000, **kw)
+        solves += s_
+        iters += i_
+        conv += c_
+        for i in range(count):
+            prev[i].copy_(psis[i])
+            psis[i].copy_(pred[i])
+            mu_now[i] += dmu
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = batch.stats()
+    out = {
+        "metric": "batched Jacobian solves/s (continuation, 64 instances)",
+        "value": solves / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (outer) / f32 (V-cycle)",
+        "data": "synthetic: 64 continuation instances, grid sizes drawn with seed 0",
+        "config": {"workload": "64 instances, 2D grids of 129^2 / 257^2 / 513^2 nodes (seed 0), side 10, "
+                               "mu_k = 2k/63, continuation steps of 0.02 with the secant predictor, "
+                               "Newton to 1e-10, MINRES to 1e-10, FP32 V-cycle",
+                   "sizes": {str(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))},
+                   "tiles": {str(k): list(v) for k, v in tiles.items()},
+                   "amg_max_coarse": args.batch_max_coarse},
+        "jacobian_solves": solves, "minres_iterations": iters,
+        "dispatches_per_graph": st["dispatches_per_graph"], "groups": st["groups"],
+        "converged_fraction": conv / (count * args.steps),
+        "warm_start": {"solves": ws, "iterations": wi, "converged": wc},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["jacobian", "batch"], default="jacobian",
+                    help="jacobian: the 1M-node Jacobian solves (headline); batch: batched continuation")
+    ap.add_argument("--batch-max-coarse", type=int, default=64)
+    ap.add_argument("--tile-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "glnk_tiles.json"))
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -95,6 +195,10 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
               "decomposition is a design, not a build", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        bench_batch(args)
+        return
 
     import torch
 

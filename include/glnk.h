@@ -55,6 +55,7 @@ typedef enum { GL_FP64 = 0, GL_FP32 = 1 } gl_precision;
 
 typedef struct gl_mesh gl_mesh;
 typedef struct gl_precond gl_precond;
+typedef struct gl_batch gl_batch;
 typedef void *gl_stream;
 
 /* --------------------------------------------------------------- mesh --
@@ -161,6 +162,24 @@ gl_status gl_precond_export(const gl_precond *pre, int level, int what, void *ho
 
 void gl_precond_destroy(gl_precond *pre);
 
+/* Launch-shape choices of the V-cycle (no effect on what is computed beyond
+ * the order of rounding in row sums):
+ *   lane_shift: lanes that share one row in the sparse kernels of levels >= 1
+ *     = the built-in rule (about one lane per 2.5 stored entries of the row)
+ *     times 2^lane_shift, clamped to 1 .. 32; -2 .. 2, default 0;
+ *   bottom_rows: levels >= 1 with at most this many rows (and at most 64
+ *     colours), and all coarser ones, run inside one work-group; 0 = default
+ *     512, at most 65536.
+ * Chosen by the autotuner per grid shape; cached iteration graphs of the
+ * handle are rebuilt on their next use. */
+typedef struct {
+    int lane_shift;
+    int bottom_rows;
+} gl_tiles;
+
+gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles);
+gl_status gl_precond_get_tiles(const gl_precond *pre, gl_tiles *tiles);
+
 /* ----------------------------------------------------- Jacobian solve -- */
 typedef struct {
     double rtol;       /* stop when ||b - J x||_{M^-1} <= rtol ||b||_{M^-1} */
@@ -222,6 +241,42 @@ typedef struct {
  * NaN/Inf.  Synchronous. */
 gl_status gl_newton_solve(const gl_mesh *mesh, void *psi_inout, const gl_newton_opts *opts,
                           gl_precond **pre_inout, gl_newton_info *info, gl_stream stream);
+
+/* -------------------------------------------------------------- batch -- */
+/* Many independent instances (each a mesh with its own grid and field, e.g.
+ * the members of a continuation sweep) solved together.  The batch holds one
+ * preconditioner per instance.  Instances whose launch sequences have the
+ * same shape (same grid size and options) run every kernel of a MINRES
+ * iteration as ONE dispatch for all of them (grid: work-groups x instances);
+ * the iterations of all instances between two convergence checks are one
+ * captured HIP graph, replayed with a single launch.  Instances that have
+ * converged are skipped by device-side flags.  meshes: count distinct mesh
+ * handles that must outlive the batch; 1 <= count <= 4096. */
+gl_status gl_batch_create(int count, gl_mesh *const *meshes, gl_batch **out);
+
+/* Newton (as gl_newton_solve) on every instance at once: psi_inout[i] is the
+ * start and receives the result of instance i; infos (nullable) receives
+ * count gl_newton_info records.  The preconditioner options and tile choices
+ * apply to all instances.  Steps run in lock-step: one residual per instance,
+ * one preconditioner setup, then the Jacobian solves of all unconverged
+ * instances together.  Returns NOT_CONVERGED if any instance missed tol
+ * (fixed_steps == 0), else the first failing status.  Synchronous. */
+gl_status gl_batch_newton_solve(gl_batch *batch, void *const *psi_inout, const gl_newton_opts *opts,
+                                gl_newton_info *infos, gl_stream stream);
+
+/* Tile choices for instance `index` (-1: all); applied to its preconditioner
+ * now if it exists, and at its creation otherwise. */
+gl_status gl_batch_set_tiles(gl_batch *batch, int index, const gl_tiles *tiles);
+
+/* Statistics of the last gl_batch_newton_solve: graph launches, the most
+ * batched kernel dispatches per iteration pair (summed over the groups that
+ * ran together), the most instance groups that ran together, and host wall
+ * seconds (seconds[3], nullable) spent in residuals, preconditioner setups and
+ * Krylov solves.  Any output may be NULL. */
+gl_status gl_batch_stats(const gl_batch *batch, int64_t *graph_launches, int64_t *dispatches_per_graph,
+                         int *groups, double *seconds);
+
+void gl_batch_destroy(gl_batch *batch);
 
 /* -------------------------------------------------------- diagnostics -- */
 /* Per-kernel timing for roofline reports.  Between gl_profile_start(id) and

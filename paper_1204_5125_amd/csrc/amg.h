@@ -6,6 +6,7 @@
 #pragma once
 
 #include "common.h"
+#include "launch.h"
 
 namespace glk {
 
@@ -169,7 +170,12 @@ __device__ __forceinline__ void minres_finalize(KrylovScalars *ks, int mode, dou
 // Sum nparts block partials in a fixed order (one work-group) and act on the
 // total: store it to *out (FIN_STORE) or update the Krylov scalars.
 void launch_finalize(const double *partials, int nparts, int mode, KrylovScalars *ks, double *out,
-                     const int *gate, hipStream_t s);
+                     const int *gate, const Launch &L);
+inline void launch_finalize(const double *partials, int nparts, int mode, KrylovScalars *ks, double *out,
+                            const int *gate, hipStream_t s)
+{
+    launch_finalize(partials, nparts, mode, ks, out, gate, Launch{s});
+}
 
 }  // namespace glk
 
@@ -179,6 +185,8 @@ struct gl_precond {
     gl_amg_opts opts{};
     int nlev = 0;
     int bottom = 0;                // first level handled by the bottom kernel
+    int bottom_rows = glk::kBottomRows;  // tile choices (gl_precond_set_tiles)
+    int lane_shift = 0;
     glk::Level L[glk::kMaxLevels];
     glk::DevBuf<double2> cfac;     // Cholesky factor of the coarsest operator
     glk::DevBuf<double2> cinv64;   // its inverse, applied as a dense product
@@ -195,7 +203,7 @@ namespace glk {
 // kernel that writes z also reduces Re<v, z> and the total is handed to
 // minres_finalize(ks, mode, total).
 void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
-                    KrylovScalars *ks, int mode, hipStream_t s);
+                    KrylovScalars *ks, int mode, const Launch &L);
 void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
                          hipStream_t s);
 void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, double2 *out,
@@ -203,4 +211,5 @@ void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, 
 void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s);
 void scale_by_volume(const gl_mesh *m, const double2 *x, double2 *y, hipStream_t s);
 void bottom_descriptors(gl_precond *pre, hipStream_t s);
+uint64_t new_precond_uid();
 }  // namespace glk

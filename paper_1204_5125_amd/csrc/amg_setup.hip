@@ -544,21 +544,34 @@ __global__ void k_dense_from_csr(int n, const int *rp, const int *ci, const doub
 
 // In-place Cholesky M = L L^H (row-major, one work-group); upper part zeroed.
 // status = 1 if a pivot is not positive relative to the largest diagonal.
-__global__ __launch_bounds__(kBlock) void k_cholesky(int n, double2 *M, int *status)
+// Cholesky factor of the Hermitian coarsest operator, in place (lower
+// triangle, row-major), left-looking one column at a time; the pivot's sum
+// and each row's dot product run in parallel (status 1: not positive
+// definite relative to the largest diagonal entry).
+__global__ __launch_bounds__(1024) void k_cholesky(int n, double2 *M, int *status)
 {
+    __shared__ double sm[1024 / 64];
     __shared__ double dmax, ljj;
     __shared__ int bad;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(M[(size_t)i * n + i].x));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int i = 0; i < n; ++i) m = fmax(m, fabs(M[(size_t)i * n + i].x));
-        dmax = m;
+        double r = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sm[w]);
+        dmax = r;
         bad = 0;
     }
     __syncthreads();
     for (int j = 0; j < n; ++j) {
+        const double2 *Lj = M + (size_t)j * n;
+        double p = 0.0;
+        for (int k = threadIdx.x; k < j; k += blockDim.x) p += cabs2(Lj[k]);
+        p = block_sum(p, sm);
         if (threadIdx.x == 0) {
-            double d = M[(size_t)j * n + j].x;
-            for (int k = 0; k < j; ++k) d -= cabs2(M[(size_t)j * n + k]);
+            const double d = Lj[j].x - p;
             if (!(d > 1e-12 * dmax)) bad = 1;
             else {
                 ljj = sqrt(d);
@@ -568,8 +581,9 @@ __global__ __launch_bounds__(kBlock) void k_cholesky(int n, double2 *M, int *sta
         __syncthreads();
         if (bad) break;
         for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
-            double2 s = M[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) s = csub(s, cmul(M[(size_t)i * n + k], cconj(M[(size_t)j * n + k])));
+            const double2 *Li = M + (size_t)i * n;
+            double2 s = Li[j];
+            for (int k = 0; k < j; ++k) s = csub(s, cmul(Li[k], cconj(Lj[k])));
             M[(size_t)i * n + j] = cscale(s, 1.0 / ljj);
         }
         __syncthreads();
@@ -1048,7 +1062,7 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
     const Csr &Mc = last > 0 ? Lc.Aa : Lc.A;
     k_dense_from_csr<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Mc.rp.get(), Mc.ci.get(), Mc.v64.get(),
                                                          pre->cfac.get());
-    k_cholesky<<<1, kBlock, 0, s>>>(Lc.n, pre->cfac.get(), pre->status.get());
+    k_cholesky<<<1, 1024, 0, s>>>(Lc.n, pre->cfac.get(), pre->status.get());
     GLK_CHECK_LAUNCH();
     if (read_int(pre->status.get(), s))
         fail(GL_ERR_SINGULAR, "gl_precond_setup: coarsest operator is not positive definite");
@@ -1060,6 +1074,14 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
 }  // namespace glk
 
 using namespace glk;
+
+namespace glk {
+uint64_t new_precond_uid()
+{
+    static std::atomic<uint64_t> next{1};
+    return next++;
+}
+}  // namespace glk
 
 extern "C" {
 
@@ -1086,8 +1108,7 @@ gl_status gl_precond_setup(const gl_mesh *mesh, const void *psi, const gl_amg_op
         if (!pre) {
             pre = new gl_precond();
             try {
-                static std::atomic<uint64_t> next_uid{1};
-                pre->uid = next_uid++;
+                pre->uid = new_precond_uid();
                 pre->mesh = mesh;
                 pre->opts = *opts;
                 precond_symbolic(pre, s);
@@ -1153,6 +1174,31 @@ gl_status gl_precond_export(const gl_precond *pre, int level, int what, void *ho
         *bytes = need;
         GLK_HIP(hipDeviceSynchronize());
         if (need) GLK_HIP(hipMemcpy(host_buf, src, need, hipMemcpyDeviceToHost));
+    });
+}
+
+gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles)
+{
+    return guarded([&] {
+        if (!pre || !tiles) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: NULL argument");
+        if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 || tiles->bottom_rows > 65536)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536");
+        const int rows = tiles->bottom_rows ? tiles->bottom_rows : kBottomRows;
+        if (rows == pre->bottom_rows && tiles->lane_shift == pre->lane_shift) return;
+        pre->bottom_rows = rows;
+        pre->lane_shift = tiles->lane_shift;
+        pre->uid = new_precond_uid();  // captured graphs of the old shape are stale
+        hipStream_t s = pre->mesh->ws;
+        bottom_descriptors(pre, s);
+    });
+}
+
+gl_status gl_precond_get_tiles(const gl_precond *pre, gl_tiles *tiles)
+{
+    return guarded([&] {
+        if (!pre || !tiles) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_get_tiles: NULL argument");
+        tiles->lane_shift = pre->lane_shift;
+        tiles->bottom_rows = pre->bottom_rows;
     });
 }
 

@@ -188,10 +188,10 @@ struct RedSlot {
     double *partials;
 };
 
-__device__ __forceinline__ void block_reduce_store(double part, RedSlot slot, double *sm)
+__device__ __forceinline__ void block_reduce_store(double part, RedSlot slot, double *sm, int bx)
 {
     const double bs = block_sum(part, sm);
-    if (threadIdx.x == 0) slot.partials[blockIdx.x] = bs;
+    if (threadIdx.x == 0) slot.partials[bx] = bs;
 }
 
 // ------------------------------------------------------- grid geometry --

@@ -18,6 +18,7 @@
 //   5. finalize: the Givens recurrence (minres_finalize)
 // The w / x update of the last iteration is applied after the loop.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -33,112 +34,132 @@ __global__ void k_ks_init_running(KrylovScalars *ks)
     ks->wx_valid = 0;
 }
 
-__global__ void k_ks_init(KrylovScalars *ks, double rtol, int max_iter)
-{
-    ks->rtol = rtol;
-    ks->max_iter = max_iter;
-    ks->running = 1;
-    ks->wx_valid = 0;
-    ks->iter = 0;
-    ks->status = 0;
-    ks->converged = 0;
-    ks->delta = 0.0;
-}
+struct KsInit {
+    KrylovScalars *ks;
+    double rtol;
+    int max_iter;
+    __device__ void operator()(int, int) const
+    {
+        if (threadIdx.x != 0) return;
+        ks->rtol = rtol;
+        ks->max_iter = max_iter;
+        ks->running = 1;
+        ks->wx_valid = 0;
+        ks->iter = 0;
+        ks->status = 0;
+        ks->converged = 0;
+        ks->delta = 0.0;
+    }
+};
 
 // v = D b, v_prev = w = w_prev = x = 0
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_minres_init(GeomT<double> g, const double2 *__restrict__ b,
-                                                        double2 *__restrict__ v, double2 *__restrict__ vp,
-                                                        double2 *__restrict__ w, double2 *__restrict__ wp,
-                                                        double2 *__restrict__ x)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int c[3];
-    node_coords<DIM>(g.N, i, c);
-    double sf[3];
-    const double d = node_volume<DIM, double>(g, c, sf);
-    const double2 zero = make_double2(0.0, 0.0);
-    v[i] = cscale(b[i], d);
-    vp[i] = zero;
-    w[i] = zero;
-    wp[i] = zero;
-    x[i] = zero;
-}
-
-// no preconditioner: M^-1 = I in <.,.>_R, i.e. z = D^-1 v in the scaled form,
-// with the partial sums of gamma^2 = Re<v, z>
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_unprec(GeomT<double> g, const double2 *__restrict__ v,
-                                                   double2 *__restrict__ z, const int *gate, RedSlot slot)
-{
-    if (gate && *gate == 0) return;
-    __shared__ double sm[kBlock / 64];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double part = 0.0;
-    if (i < g.n) {
+struct MinresInit {
+    GeomT<double> g;
+    const double2 *b;
+    double2 *v, *vp, *w, *wp, *x;
+    __device__ void operator()(int bx, int) const
+    {
+        const int i = bx * kBlock + threadIdx.x;
+        if (i >= g.n) return;
         int c[3];
         node_coords<DIM>(g.N, i, c);
         double sf[3];
         const double d = node_volume<DIM, double>(g, c, sf);
-        const double2 vi = v[i];
-        const double2 zi = cscale(vi, 1.0 / d);
-        z[i] = zi;
-        part = redot(vi, zi);
+        const double2 zero = make_double2(0.0, 0.0);
+        v[i] = cscale(b[i], d);
+        vp[i] = zero;
+        w[i] = zero;
+        wp[i] = zero;
+        x[i] = zero;
     }
-    block_reduce_store(part, slot, sm);
-}
+};
+
+// no preconditioner: M^-1 = I in <.,.>_R, i.e. z = D^-1 v in the scaled form,
+// with the partial sums of gamma^2 = Re<v, z>
+template <int DIM>
+struct Unprec {
+    GeomT<double> g;
+    const double2 *v;
+    double2 *z;
+    const int *gate;
+    RedSlot slot;
+    __device__ void operator()(int bx, int) const
+    {
+        if (gate && *gate == 0) return;
+        __shared__ double sm[kBlock / 64];
+        const int i = bx * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < g.n) {
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            double sf[3];
+            const double d = node_volume<DIM, double>(g, c, sf);
+            const double2 vi = v[i];
+            const double2 zi = cscale(vi, 1.0 / d);
+            z[i] = zi;
+            part = redot(vi, zi);
+        }
+        block_reduce_store(part, slot, sm, bx);
+    }
+};
 
 // w / x update of the previous iteration (when iter >= 1) and q = D J (z / gamma)
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_minres_japply(GeomT<double> g, const double2 *__restrict__ psi,
-                                                          const double2 *__restrict__ z,
-                                                          const double2 *__restrict__ U,
-                                                          double2 *__restrict__ q,
-                                                          const double2 *__restrict__ zprev,
-                                                          const double2 *__restrict__ w,
-                                                          double2 *__restrict__ wp, double2 *__restrict__ x,
-                                                          const KrylovScalars *ks, RedSlot slot)
-{
-    if (ks->running == 0) return;
-    __shared__ double sm[kBlock / 64];
-    const double ig = 1.0 / ks->gamma;
-    const bool upd = ks->iter >= 1;
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    double part = 0.0;
-    if (i < g.n) {
-        if (upd) {
-            const double2 zp = cscale(zprev[i], ks->wx_inv_gamma);
-            const double2 wn = cscale(csub(csub(zp, cscale(wp[i], ks->wx_a3)), cscale(w[i], ks->wx_a2)),
-                                      1.0 / ks->wx_a1);
-            wp[i] = wn;
-            x[i] = cadd(x[i], cscale(wn, ks->wx_coef));
+struct MinresJapply {
+    GeomT<double> g;
+    const double2 *psi, *z, *U;
+    double2 *q;
+    const double2 *zprev, *w;
+    double2 *wp, *x;
+    const KrylovScalars *ks;
+    RedSlot slot;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        if (ks->running == 0) return;
+        __shared__ double sm[kBlock / 64];
+        const double ig = 1.0 / ks->gamma;
+        const bool upd = ks->iter >= 1;
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < g.n) {
+            if (upd) {
+                const double2 zp = cscale(zprev[i], ks->wx_inv_gamma);
+                const double2 wn = cscale(csub(csub(zp, cscale(wp[i], ks->wx_a3)), cscale(w[i], ks->wx_a2)),
+                                          1.0 / ks->wx_a1);
+                wp[i] = wn;
+                x[i] = cadd(x[i], cscale(wn, ks->wx_coef));
+            }
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            const double2 zi = z[i];
+            double d, asum;
+            const double2 kz = khat_node<DIM, double>(g, i, c, z, U, zi, d, asum);
+            const double2 zn = cscale(zi, ig);
+            const double2 p = psi[i];
+            const double2 react = cadd(cscale(zn, 2.0 * cabs2(p) - 1.0), cmul(cmul(p, p), cconj(zn)));
+            const double2 qi = cadd(cscale(kz, ig), cscale(react, d));
+            q[i] = qi;
+            part = redot(qi, zn);
         }
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
-        const double2 zi = z[i];
-        double d, asum;
-        const double2 kz = khat_node<DIM, double>(g, i, c, z, U, zi, d, asum);
-        const double2 zn = cscale(zi, ig);
-        const double2 p = psi[i];
-        const double2 react = cadd(cscale(zn, 2.0 * cabs2(p) - 1.0), cmul(cmul(p, p), cconj(zn)));
-        const double2 qi = cadd(cscale(kz, ig), cscale(react, d));
-        q[i] = qi;
-        part = redot(qi, zn);
+        block_reduce_store(part, slot, sm, bx);
     }
-    block_reduce_store(part, slot, sm);
-}
+};
 
-__global__ __launch_bounds__(kBlock) void k_minres_vupdate(int n, const double2 *__restrict__ q,
-                                                           const double2 *__restrict__ v,
-                                                           double2 *__restrict__ vp, const KrylovScalars *ks)
-{
-    if (ks->running == 0) return;
-    const double a = ks->delta / ks->gamma, b = ks->gamma / ks->gamma_prev;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    vp[i] = csub(csub(q[i], cscale(v[i], a)), cscale(vp[i], b));
-}
+struct MinresVupdate {
+    int n;
+    const double2 *q, *v;
+    double2 *vp;
+    const KrylovScalars *ks;
+    __device__ void operator()(int bx, int) const
+    {
+        if (ks->running == 0) return;
+        const double a = ks->delta / ks->gamma, b = ks->gamma / ks->gamma_prev;
+        const int i = bx * kBlock + threadIdx.x;
+        if (i >= n) return;
+        vp[i] = csub(csub(q[i], cscale(v[i], a)), cscale(vp[i], b));
+    }
+};
 
 // the pending w / x update after the last iteration
 __global__ __launch_bounds__(kBlock) void k_minres_wx(int n, const double2 *__restrict__ z,
@@ -176,8 +197,8 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(GeomT<double> g, const
         pr = d * cabs2(csub(bi, jx));
         pb = d * cabs2(bi);
     }
-    block_reduce_store(pr, s1, sm);
-    block_reduce_store(pb, s2, sm);
+    block_reduce_store(pr, s1, sm, blockIdx.x);
+    block_reduce_store(pb, s2, sm, blockIdx.x);
 }
 
 // psi -= dx
@@ -261,45 +282,41 @@ static Ksolve make_ksolve(const gl_mesh *m, const double2 *psi, const gl_precond
 
 // x = 0, v = D rhs, z = M^-1 v, gamma_1, eta_0
 template <int DIM>
-static void ksolve_init(const Ksolve &k, double rtol, int max_iter, hipStream_t s)
+static void ksolve_init(const Ksolve &k, double rtol, int max_iter, const Launch &L)
 {
     const gl_mesh *m = k.m;
     const int n = m->g.n, nb = blocks_for(n);
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
-    k_ks_init<<<1, 1, 0, s>>>(ks, rtol, max_iter);
-    k_minres_init<DIM><<<nb, kBlock, 0, s>>>(g, k.rhs, k.v, k.vp, k.w, k.wp, k.x);
-    GLK_CHECK_LAUNCH();
+    L.run<KsInit, 64>(1, KsInit{ks, rtol, max_iter});
+    L.run(nb, MinresInit<DIM>{g, k.rhs, k.v, k.vp, k.w, k.wp, k.x});
     if (k.pre) {
-        vcycle_enqueue(k.pre, k.v, k.z, nullptr, ks, FIN_MINRES_INIT, s);
+        vcycle_enqueue(k.pre, k.v, k.z, nullptr, ks, FIN_MINRES_INIT, L);
     } else {
-        k_unprec<DIM><<<nb, kBlock, 0, s>>>(g, k.v, k.z, nullptr, red_slot(m, 1));
-        launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_INIT, ks, nullptr, nullptr, s);
+        L.run(nb, Unprec<DIM>{g, k.v, k.z, nullptr, red_slot(m, 1)});
+        launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_INIT, ks, nullptr, nullptr, L);
     }
-    GLK_CHECK_LAUNCH();
 }
 
 template <int DIM>
-static void enqueue_iteration(Ksolve &k, hipStream_t s)
+static void enqueue_iteration(Ksolve &k, const Launch &L)
 {
     const gl_mesh *m = k.m;
     const int n = m->g.n, nb = blocks_for(n);
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
     const int *gate = &ks->running;
-    prof_launch(PROF_MINRES_JAPPLY, (48.0 * n + 16.0 * grid_edges(m->g)) + 96.0 * n, s, [&] {
-        k_minres_japply<DIM><<<nb, kBlock, 0, s>>>(g, k.psi, k.z, m->U64.get(), k.q, k.zn, k.w, k.wp, k.x, ks,
-                                                   red_slot(m, 0));
+    prof_launch(PROF_MINRES_JAPPLY, (48.0 * n + 16.0 * grid_edges(m->g)) + 96.0 * n, L, [&] {
+        L.run(nb, MinresJapply<DIM>{g, k.psi, k.z, m->U64.get(), k.q, k.zn, k.w, k.wp, k.x, ks, red_slot(m, 0)});
     });
-    launch_finalize(red_slot(m, 0).partials, nb, FIN_DELTA, ks, nullptr, gate, s);
-    prof_launch(PROF_VUPDATE, 64.0 * n, s, [&] { k_minres_vupdate<<<nb, kBlock, 0, s>>>(n, k.q, k.v, k.vp, ks); });
+    launch_finalize(red_slot(m, 0).partials, nb, FIN_DELTA, ks, nullptr, gate, L);
+    prof_launch(PROF_VUPDATE, 64.0 * n, L, [&] { L.run(nb, MinresVupdate{n, k.q, k.v, k.vp, ks}); });
     if (k.pre) {
-        vcycle_enqueue(k.pre, k.vp, k.zn, gate, ks, FIN_MINRES_STEP, s);
+        vcycle_enqueue(k.pre, k.vp, k.zn, gate, ks, FIN_MINRES_STEP, L);
     } else {
-        k_unprec<DIM><<<nb, kBlock, 0, s>>>(g, k.vp, k.zn, gate, red_slot(m, 1));
-        launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_STEP, ks, nullptr, gate, s);
+        L.run(nb, Unprec<DIM>{g, k.vp, k.zn, gate, red_slot(m, 1)});
+        launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_STEP, ks, nullptr, gate, L);
     }
-    GLK_CHECK_LAUNCH();
     std::swap(k.v, k.vp);
     std::swap(k.z, k.zn);
     std::swap(k.w, k.wp);
@@ -318,8 +335,8 @@ static hipGraphExec_t iteration_graph(Ksolve k, hipStream_t s)
     hipGraph_t graph = nullptr;
     GLK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
-        enqueue_iteration<DIM>(k, s);
-        enqueue_iteration<DIM>(k, s);
+        enqueue_iteration<DIM>(k, Launch{s});
+        enqueue_iteration<DIM>(k, Launch{s});
     } catch (...) {
         hipGraph_t dummy = nullptr;
         (void)hipStreamEndCapture(s, &dummy);
@@ -358,7 +375,7 @@ static void ksolve_iterate(Ksolve k, int max_iter, int poll, hipStream_t s, Kryl
             for (int t = 0; t < std::max(1, poll / 2) && launched < max_iter; ++t, launched += 2)
                 GLK_HIP(hipGraphLaunch(exec, s));
         } else {
-            for (int t = 0; t < poll && launched < max_iter; ++t, ++launched) enqueue_iteration<DIM>(k, s);
+            for (int t = 0; t < poll && launched < max_iter; ++t, ++launched) enqueue_iteration<DIM>(k, Launch{s});
         }
     }
     if (h.wx_valid && h.iter >= 1) {
@@ -405,7 +422,7 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
     const bool fp64 = !pre || pre->opts.precision == GL_FP64;
     if (fp64 && o.inner_rtol <= 0.0) {
         Ksolve k = make_ksolve(m, psi, pre, b, x);
-        ksolve_init<DIM>(k, o.rtol, o.max_iter, s);
+        ksolve_init<DIM>(k, o.rtol, o.max_iter, Launch{s});
         ksolve_iterate<DIM>(k, o.max_iter, poll, s, h);
         iters = h.iter;
         converged = h.converged;
@@ -424,7 +441,7 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
         Ksolve k = make_ksolve(m, psi, pre, r, d);
         double eta_first = 0.0;
         for (int outer = 0; outer < 64; ++outer) {
-            ksolve_init<DIM>(k, inner, 0, s);
+            ksolve_init<DIM>(k, inner, 0, Launch{s});
             read_scalars(m, &h, s);
             if (h.status) { st = (gl_status)h.status; break; }
             if (outer == 0) eta_first = h.eta0;
@@ -557,5 +574,651 @@ gl_status gl_newton_solve(const gl_mesh *mesh, void *psi_inout, const gl_newton_
     if (!pre_inout) gl_precond_destroy(pre);
     return g != GL_OK ? g : rc;
 }
+
+}  // extern "C"
+
+// ================================================================ batch ===
+// Many instances in lock-step.  Every kernel of a MINRES iteration is a step
+// struct; recording one iteration pair per instance and zipping the records of
+// instances with identical launch shapes gives one batched dispatch per step
+// (grid: work-groups x instances).  One captured graph holds the iteration
+// pair of every group (groups on parallel branches); it is replayed between
+// host convergence checks, and converged instances idle on their flags.
+namespace glk {
+
+struct BatchScalars {
+    KrylovScalars ks;
+    double res2;
+};
+
+__global__ void k_gather_scalars(const KrylovScalars *const *ks, const double *const *ds, BatchScalars *out,
+                                 int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    out[i].ks = *ks[i];
+    out[i].res2 = *ds[i];
+}
+
+__global__ void k_ks_stop(KrylovScalars *ks)
+{
+    ks->running = 0;
+    ks->wx_valid = 0;
+    ks->iter = 0;
+    ks->status = 0;
+}
+
+// A zipped step sequence: the steps of the first member and, per step, the
+// byte offset of the packed argument array (one struct per member).
+struct Zip {
+    std::vector<Step> steps;
+    std::vector<size_t> off;
+    int count = 0;
+};
+
+static bool same_shape(const std::vector<Step> &a, const std::vector<Step> &b)
+{
+    if (a.size() != b.size()) return false;
+    for (size_t p = 0; p < a.size(); ++p)
+        if (a[p].many != b[p].many || a[p].nbx != b[p].nbx || a[p].args.size() != b[p].args.size()) return false;
+    return true;
+}
+
+// Append the packed arguments of recs (same shape) to buf; returns the zip.
+static Zip zip_records(const std::vector<std::vector<Step>> &recs, std::vector<unsigned char> &buf)
+{
+    Zip z;
+    z.count = (int)recs.size();
+    z.steps = recs[0];
+    for (auto &st : z.steps) st.args.clear();
+    z.off.resize(recs[0].size());
+    for (size_t p = 0; p < recs[0].size(); ++p) {
+        size_t o = (buf.size() + 255) & ~(size_t)255;
+        const size_t sz = recs[0][p].args.size();
+        buf.resize(o + sz * recs.size());
+        for (size_t i = 0; i < recs.size(); ++i) std::memcpy(buf.data() + o + i * sz, recs[i][p].args.data(), sz);
+        z.off[p] = o;
+    }
+    return z;
+}
+
+static void launch_zip(const Zip &z, const unsigned char *dev, hipStream_t s)
+{
+    for (size_t p = 0; p < z.steps.size(); ++p) z.steps[p].many(dev + z.off[p], z.steps[p].nbx, z.count, s);
+    GLK_CHECK_LAUNCH();
+}
+
+// A captured iteration pair for a subset of one group's instances.
+struct GroupGraph {
+    std::vector<uint64_t> key;
+    std::vector<int> members;
+    hipGraphExec_t exec = nullptr;
+    DevBuf<unsigned char> args;
+    int64_t dispatches = 0;
+};
+
+// Instances whose iteration pairs have the same launch shape; each group
+// replays its graph on its own stream, so groups run concurrently.
+struct BatchGroup {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::vector<GroupGraph> cache;  // most recent last
+};
+
+}  // namespace glk
+
+struct gl_batch {
+    std::vector<gl_mesh *> meshes;
+    std::vector<gl_precond *> pre;
+    std::vector<gl_tiles> tiles;
+    hipStream_t s = nullptr;
+    std::vector<glk::BatchGroup> groups;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    int64_t dispatches = 0;  // batched dispatches per iteration pair (all groups)
+    int ngroups = 0;
+    glk::DevBuf<const glk::KrylovScalars *> ks_ptr;
+    glk::DevBuf<const double *> ds_ptr;
+    glk::DevBuf<glk::BatchScalars> gathered;
+    glk::BatchScalars *host_sc = nullptr;
+    glk::DevBuf<unsigned char> init_args;
+    unsigned char *staging = nullptr;
+    size_t staging_cap = 0;
+    int64_t graph_launches = 0;
+    double seconds[3] = {0.0, 0.0, 0.0};  // residuals, preconditioner setups, Krylov solves
+    ~gl_batch();
+};
+
+namespace glk {
+
+static KrylovScalars *kscal_of(const gl_mesh *m) { return reinterpret_cast<KrylovScalars *>(m->kscal.get()); }
+
+static void batch_gather(gl_batch *B)
+{
+    const int N = (int)B->meshes.size();
+    k_gather_scalars<<<blocks_for(N, 64), 64, 0, B->s>>>(B->ks_ptr.get(), B->ds_ptr.get(), B->gathered.get(), N);
+    GLK_CHECK_LAUNCH();
+    GLK_HIP(hipMemcpyAsync(B->host_sc, B->gathered.get(), sizeof(BatchScalars) * N, hipMemcpyDeviceToHost, B->s));
+    GLK_HIP(hipStreamSynchronize(B->s));
+}
+
+// Krylov buffers of instance i: x = dx (W8) for a single run, d (W9) with rhs
+// r_ref (W10) in refinement; otherwise rhs = GL (W7).
+static Ksolve batch_ksolve(gl_batch *B, double2 *const *psi, int i, bool refine, bool use_pre)
+{
+    const gl_mesh *m = B->meshes[i];
+    const size_t n = (size_t)m->g.n;
+    double2 *W = m->work.get();
+    return make_ksolve(m, psi[i], use_pre ? B->pre[i] : nullptr, refine ? W + 10 * n : W + 7 * n,
+                       refine ? W + 9 * n : W + 8 * n);
+}
+
+// Group instances by the shape of a recorded sequence; rec(i, out) records one.
+template <class Rec>
+static void group_records(const std::vector<int> &members, Rec &&rec, std::vector<std::vector<int>> &groups,
+                          std::vector<std::vector<std::vector<Step>>> &records)
+{
+    for (int i : members) {
+        std::vector<Step> r;
+        rec(i, r);
+        size_t g = 0;
+        for (; g < groups.size(); ++g)
+            if (same_shape(records[g][0], r)) break;
+        if (g == groups.size()) {
+            groups.emplace_back();
+            records.emplace_back();
+        }
+        groups[g].push_back(i);
+        records[g].push_back(std::move(r));
+    }
+}
+
+// Record, zip and run a sequence for the given instances directly (not captured).
+template <class Rec>
+static void batch_run_direct(gl_batch *B, const std::vector<int> &members, Rec &&rec)
+{
+    if (members.empty()) return;
+    std::vector<std::vector<int>> groups;
+    std::vector<std::vector<std::vector<Step>>> records;
+    group_records(members, rec, groups, records);
+    std::vector<unsigned char> buf;
+    std::vector<Zip> zips;
+    for (auto &r : records) zips.push_back(zip_records(r, buf));
+    // the previous contents of the staging buffer were consumed by a copy that
+    // completed before the last synchronisation of B->s
+    if (buf.size() > B->staging_cap) {
+        if (B->staging) (void)hipHostFree(B->staging);
+        B->staging = nullptr;
+        B->staging_cap = 0;
+        GLK_HIP(hipHostMalloc(&B->staging, buf.size(), hipHostMallocDefault));
+        B->staging_cap = buf.size();
+    }
+    if (buf.size() > B->init_args.count) B->init_args.alloc(buf.size());
+    std::memcpy(B->staging, buf.data(), buf.size());
+    GLK_HIP(hipMemcpyAsync(B->init_args.get(), B->staging, buf.size(), hipMemcpyHostToDevice, B->s));
+    for (auto &z : zips) launch_zip(z, B->init_args.get(), B->s);
+}
+
+static void record_iterations(gl_batch *B, double2 *const *psi, int i, bool refine, bool use_pre,
+                              std::vector<Step> &out)
+{
+    Launch L{nullptr, &out};
+    Ksolve k = batch_ksolve(B, psi, i, refine, use_pre);
+    if (B->meshes[i]->g.dim == 2) {
+        enqueue_iteration<2>(k, L);
+        enqueue_iteration<2>(k, L);
+    } else {
+        enqueue_iteration<3>(k, L);
+        enqueue_iteration<3>(k, L);
+    }
+}
+
+static GroupGraph build_group_graph(gl_batch *B, BatchGroup &G, const std::vector<int> &members,
+                                    const std::vector<std::vector<Step>> &recs, std::vector<uint64_t> key)
+{
+    GroupGraph gg;
+    gg.key = std::move(key);
+    gg.members = members;
+    std::vector<unsigned char> buf;
+    Zip z = zip_records(recs, buf);
+    gg.dispatches = (int64_t)z.steps.size();
+    gg.args.alloc(buf.size());
+    GLK_HIP(hipMemcpy(gg.args.get(), buf.data(), buf.size(), hipMemcpyHostToDevice));
+    hipGraph_t graph = nullptr;
+    GLK_HIP(hipStreamBeginCapture(G.s, hipStreamCaptureModeThreadLocal));
+    try {
+        launch_zip(z, gg.args.get(), G.s);
+    } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(G.s, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        throw;
+    }
+    GLK_HIP(hipStreamEndCapture(G.s, &graph));
+    hipError_t e = hipGraphInstantiate(&gg.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    GLK_HIP(e);
+    return gg;
+}
+
+// Replay iteration pairs until no instance runs (or max_iter iterations).
+// The running instances are grouped by launch shape; a group's graph covers
+// a set of instances that contains its running ones and is rebuilt for the
+// running subset once at most half of its instances still run (finished
+// instances idle on their flags, but their work-groups are still launched).
+static void batch_iterate(gl_batch *B, double2 *const *psi, bool refine, bool use_pre, int max_iter, int poll)
+{
+    const int N = (int)B->meshes.size();
+    batch_gather(B);
+    std::vector<int> running;
+    for (int i = 0; i < N; ++i)
+        if (B->host_sc[i].ks.running) running.push_back(i);
+    if (running.empty()) return;
+    // shapes of the running instances
+    std::vector<std::vector<int>> gm;
+    std::vector<std::vector<std::vector<Step>>> grec;
+    group_records(running, [&](int i, std::vector<Step> &r) { record_iterations(B, psi, i, refine, use_pre, r); },
+                  gm, grec);
+    const int G = (int)gm.size();
+    while ((int)B->groups.size() < G) {
+        BatchGroup bg;
+        GLK_HIP(hipStreamCreateWithFlags(&bg.s, hipStreamNonBlocking));
+        GLK_HIP(hipEventCreateWithFlags(&bg.fork, hipEventDisableTiming));
+        GLK_HIP(hipEventCreateWithFlags(&bg.join, hipEventDisableTiming));
+        B->groups.push_back(std::move(bg));
+    }
+    auto key_of = [&](const std::vector<int> &mem) {
+        std::vector<uint64_t> key{(uint64_t)refine, (uint64_t)use_pre};
+        for (int i : mem) {
+            const gl_precond *p = use_pre ? B->pre[i] : nullptr;
+            key.push_back((uint64_t)i);
+            key.push_back((uint64_t)(uintptr_t)psi[i]);
+            key.push_back(p ? p->uid : 0);
+            key.push_back(p ? (uint64_t)(p->opts.precision * 4096 + p->opts.cycles) : 0);
+        }
+        return key;
+    };
+    // graph of group g for the member subset `mem`
+    auto graph_for = [&](int g, const std::vector<int> &mem) -> GroupGraph & {
+        BatchGroup &bg = B->groups[g];
+        std::vector<uint64_t> key = key_of(mem);
+        for (size_t c = 0; c < bg.cache.size(); ++c)
+            if (bg.cache[c].key == key) return bg.cache[c];
+        std::vector<std::vector<Step>> recs;
+        for (int i : mem)
+            for (size_t k = 0; k < gm[g].size(); ++k)
+                if (gm[g][k] == i) recs.push_back(grec[g][k]);
+        if (bg.cache.size() >= 8) {
+            (void)hipGraphExecDestroy(bg.cache.front().exec);
+            bg.cache.erase(bg.cache.begin());
+        }
+        bg.cache.push_back(build_group_graph(B, bg, mem, recs, std::move(key)));
+        return bg.cache.back();
+    };
+    std::vector<GroupGraph *> cur(G);
+    int64_t disp = 0;
+    for (int g = 0; g < G; ++g) {
+        cur[g] = &graph_for(g, gm[g]);
+        disp += cur[g]->dispatches;
+    }
+    B->dispatches = std::max(B->dispatches, disp);
+    B->ngroups = std::max(B->ngroups, G);
+    int launched = 0;
+    for (;;) {
+        // one window: every group's graph poll / 2 times on its own stream
+        const int reps = std::max(1, poll / 2);
+        for (int g = 0; g < G; ++g) {
+            if (!cur[g]) continue;
+            BatchGroup &bg = B->groups[g];
+            GLK_HIP(hipEventRecord(bg.fork, B->s));
+            GLK_HIP(hipStreamWaitEvent(bg.s, bg.fork, 0));
+            for (int t = 0; t < reps && launched + 2 * t < max_iter; ++t) {
+                GLK_HIP(hipGraphLaunch(cur[g]->exec, bg.s));
+                ++B->graph_launches;
+            }
+            GLK_HIP(hipEventRecord(bg.join, bg.s));
+            GLK_HIP(hipStreamWaitEvent(B->s, bg.join, 0));
+        }
+        launched += 2 * reps;
+        batch_gather(B);
+        if (launched >= max_iter) break;
+        bool any = false;
+        for (int g = 0; g < G; ++g) {
+            if (!cur[g]) continue;
+            std::vector<int> still;
+            for (int i : cur[g]->members)
+                if (B->host_sc[i].ks.running) still.push_back(i);
+            if (still.empty()) {
+                cur[g] = nullptr;
+                continue;
+            }
+            any = true;
+            if (2 * still.size() <= cur[g]->members.size()) cur[g] = &graph_for(g, still);
+        }
+        if (!any) break;
+    }
+}
+
+// pending w / x update of instance i after its run stopped (roles by parity)
+static void batch_flush(gl_batch *B, double2 *const *psi, int i, bool refine, bool use_pre)
+{
+    const KrylovScalars &h = B->host_sc[i].ks;
+    if (!(h.wx_valid && h.iter >= 1)) return;
+    Ksolve kk = batch_ksolve(B, psi, i, refine, use_pre);
+    if (h.iter & 1) {
+        std::swap(kk.v, kk.vp);
+        std::swap(kk.z, kk.zn);
+        std::swap(kk.w, kk.wp);
+    }
+    const int n = B->meshes[i]->g.n;
+    k_minres_wx<<<blocks_for(n), kBlock, 0, B->s>>>(n, kk.zn, kk.w, kk.wp, kk.x, kscal_of(B->meshes[i]));
+    GLK_CHECK_LAUNCH();
+}
+
+static void batch_init(gl_batch *B, double2 *const *psi, const std::vector<int> &members, bool refine,
+                       bool use_pre, double rtol, int max_iter)
+{
+    batch_run_direct(B, members, [&](int i, std::vector<Step> &r) {
+        Launch L{nullptr, &r};
+        Ksolve k = batch_ksolve(B, psi, i, refine, use_pre);
+        if (B->meshes[i]->g.dim == 2) ksolve_init<2>(k, rtol, max_iter, L);
+        else ksolve_init<3>(k, rtol, max_iter, L);
+    });
+}
+
+// Solve J(psi_i) dx_i = GL(psi_i) for the instances in `act`; iters, st per instance.
+static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int> &act, const gl_newton_opts &o,
+                        std::vector<int> &iters, std::vector<gl_status> &st)
+{
+    const gl_krylov_opts &ko = o.krylov;
+    const bool use_pre = o.use_precond != 0;
+    const bool fp32 = use_pre && o.amg.precision == GL_FP32;
+    const bool refine = fp32 || ko.inner_rtol > 0.0;
+    const int poll = std::max(1, ko.poll_every);
+    for (int i : act) iters[i] = 0;
+    if (!refine) {
+        batch_init(B, psi, act, false, use_pre, ko.rtol, ko.max_iter);
+        batch_iterate(B, psi, false, use_pre, ko.max_iter, poll);
+        for (int i : act) {
+            const KrylovScalars &h = B->host_sc[i].ks;
+            batch_flush(B, psi, i, false, use_pre);
+            iters[i] = h.iter;
+            if (h.status) st[i] = (gl_status)h.status;
+        }
+        return;
+    }
+    const double inner = ko.inner_rtol > 0.0 ? ko.inner_rtol : 1e-5;
+    std::vector<double> eta_first(B->meshes.size(), 0.0);
+    for (int i : act) {
+        const gl_mesh *m = B->meshes[i];
+        const int n = m->g.n;
+        double2 *W = m->work.get();
+        k_copy<<<blocks_for(n), kBlock, 0, B->s>>>(n, W + 10 * (size_t)n, W + 7 * (size_t)n);
+        k_zero<<<blocks_for(n), kBlock, 0, B->s>>>(n, W + 8 * (size_t)n);
+        GLK_CHECK_LAUNCH();
+    }
+    std::vector<int> solving = act;
+    for (int outer = 0; outer < 64 && !solving.empty(); ++outer) {
+        batch_init(B, psi, solving, true, use_pre, inner, 0);
+        batch_gather(B);
+        std::vector<int> next;
+        for (int i : solving) {
+            const KrylovScalars &h = B->host_sc[i].ks;
+            if (h.status) { st[i] = (gl_status)h.status; continue; }
+            if (outer == 0) eta_first[i] = h.eta0;
+            if (h.eta0 <= ko.rtol * eta_first[i] || h.eta0 == 0.0) continue;  // converged
+            if (iters[i] >= ko.max_iter) continue;
+            const double rt = std::max(inner, ko.rtol * eta_first[i] / h.eta0);
+            KrylovScalars *ks = kscal_of(B->meshes[i]);
+            k_ks_set<<<1, 1, 0, B->s>>>(ks, rt, ko.max_iter - iters[i]);
+            k_ks_init_running<<<1, 1, 0, B->s>>>(ks);
+            GLK_CHECK_LAUNCH();
+            next.push_back(i);
+        }
+        solving.swap(next);
+        if (solving.empty()) break;
+        batch_iterate(B, psi, true, use_pre, ko.max_iter, poll);
+        for (int i : solving) {
+            const KrylovScalars &h = B->host_sc[i].ks;
+            batch_flush(B, psi, i, true, use_pre);
+            iters[i] += h.iter;
+            if (h.status) st[i] = (gl_status)h.status;
+            const gl_mesh *m = B->meshes[i];
+            const int n = m->g.n;
+            double2 *W = m->work.get();
+            k_add<<<blocks_for(n), kBlock, 0, B->s>>>(n, W + 8 * (size_t)n, W + 9 * (size_t)n);
+            const GeomT<double> g = geom_t<double>(m->g);
+            if (m->g.dim == 2)
+                k_residual_vec<2><<<blocks_for(n), kBlock, 0, B->s>>>(g, psi[i], W + 8 * (size_t)n,
+                                                                       W + 7 * (size_t)n, m->U64.get(),
+                                                                       W + 10 * (size_t)n);
+            else
+                k_residual_vec<3><<<blocks_for(n), kBlock, 0, B->s>>>(g, psi[i], W + 8 * (size_t)n,
+                                                                       W + 7 * (size_t)n, m->U64.get(),
+                                                                       W + 10 * (size_t)n);
+            GLK_CHECK_LAUNCH();
+        }
+        std::vector<int> keep;
+        for (int i : solving)
+            if (st[i] == GL_OK) keep.push_back(i);
+        solving.swap(keep);
+    }
+}
+
+static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_opts &o, gl_newton_info *infos)
+{
+    const int N = (int)B->meshes.size();
+    std::vector<gl_newton_info> ni(N);
+    std::memset(ni.data(), 0, sizeof(gl_newton_info) * N);
+    std::vector<gl_status> st(N, GL_OK);
+    std::vector<char> active(N, 1);
+    std::vector<double> res(N, 0.0);
+    std::vector<int> iters(N, 0);
+    for (int i = 0; i < N; ++i) k_ks_stop<<<1, 1, 0, B->s>>>(kscal_of(B->meshes[i]));
+    GLK_CHECK_LAUNCH();
+    auto residuals = [&]() {
+        for (int i = 0; i < N; ++i) {
+            if (!active[i]) continue;
+            gl_mesh *m = B->meshes[i];
+            gl_residual_enqueue(m, psi[i], m->work.get() + 7 * (size_t)m->g.n, m->dscal.get(), B->s);
+        }
+        batch_gather(B);
+        for (int i = 0; i < N; ++i)
+            if (active[i]) res[i] = std::sqrt(B->host_sc[i].res2);
+    };
+    using clk = std::chrono::steady_clock;
+    auto since = [](clk::time_point t) { return std::chrono::duration<double>(clk::now() - t).count(); };
+    auto t0 = clk::now();
+    residuals();
+    B->seconds[0] += since(t0);
+    for (int i = 0; i < N; ++i) ni[i].res[0] = res[i];
+    for (int k = 0;; ++k) {
+        std::vector<int> act;
+        for (int i = 0; i < N; ++i) {
+            if (!active[i]) continue;
+            bool stop;
+            if (!std::isfinite(res[i])) { st[i] = GL_ERR_NONFINITE; stop = true; }
+            else if (o.fixed_steps > 0) stop = (k == o.fixed_steps);
+            else stop = res[i] < o.tol || k == o.max_steps;
+            if (stop) active[i] = 0;
+            else act.push_back(i);
+        }
+        if (act.empty()) break;
+        t0 = clk::now();
+        if (o.use_precond) {
+            for (int i : act) {
+                const bool fresh = B->pre[i] == nullptr;
+                gl_status ps = gl_precond_setup(B->meshes[i], psi[i], &o.amg, &B->pre[i], B->s);
+                if (ps == GL_OK && fresh) ps = gl_precond_set_tiles(B->pre[i], &B->tiles[i]);
+                if (ps != GL_OK) {
+                    st[i] = ps;
+                    active[i] = 0;
+                }
+            }
+            std::vector<int> keep;
+            for (int i : act)
+                if (active[i]) keep.push_back(i);
+            act.swap(keep);
+            if (act.empty()) break;
+        }
+        B->seconds[1] += since(t0);
+        t0 = clk::now();
+        batch_solve(B, psi, act, o, iters, st);
+        for (int i : act) {
+            if (st[i] != GL_OK && st[i] != GL_ERR_NOT_CONVERGED) {
+                active[i] = 0;
+                continue;
+            }
+            st[i] = GL_OK;
+            gl_mesh *m = B->meshes[i];
+            const int n = m->g.n;
+            k_sub<<<blocks_for(n), kBlock, 0, B->s>>>(n, psi[i], m->work.get() + 8 * (size_t)n);
+            GLK_CHECK_LAUNCH();
+            ni[i].krylov_iters[k] = iters[i];
+            ni[i].steps = k + 1;
+        }
+        B->seconds[2] += since(t0);
+        t0 = clk::now();
+        residuals();
+        B->seconds[0] += since(t0);
+        for (int i : act)
+            if (active[i]) ni[i].res[k + 1] = res[i];
+    }
+    gl_status rc = GL_OK;
+    for (int i = 0; i < N; ++i) {
+        ni[i].converged = std::isfinite(ni[i].res[ni[i].steps]) && ni[i].res[ni[i].steps] < o.tol;
+        if (rc == GL_OK && st[i] != GL_OK) rc = st[i];
+    }
+    if (rc == GL_OK && o.fixed_steps == 0)
+        for (int i = 0; i < N; ++i)
+            if (!ni[i].converged) rc = GL_ERR_NOT_CONVERGED;
+    if (infos) std::memcpy(infos, ni.data(), sizeof(gl_newton_info) * N);
+    return rc;
+}
+
+}  // namespace glk
+
+gl_batch::~gl_batch()
+{
+    (void)hipDeviceSynchronize();
+    for (auto &g : groups) {
+        for (auto &gg : g.cache)
+            if (gg.exec) (void)hipGraphExecDestroy(gg.exec);
+        if (g.s) (void)hipStreamDestroy(g.s);
+        if (g.fork) (void)hipEventDestroy(g.fork);
+        if (g.join) (void)hipEventDestroy(g.join);
+    }
+    for (gl_precond *p : pre) gl_precond_destroy(p);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (s) (void)hipStreamDestroy(s);
+    if (host_sc) (void)hipHostFree(host_sc);
+    if (staging) (void)hipHostFree(staging);
+}
+
+extern "C" {
+
+gl_status gl_batch_create(int count, gl_mesh *const *meshes, gl_batch **out)
+{
+    return guarded([&] {
+        if (!meshes || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_create: NULL argument");
+        if (count < 1 || count > 4096) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_create: count must be in 1..4096");
+        for (int i = 0; i < count; ++i) {
+            if (!meshes[i]) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_create: NULL mesh");
+            for (int j = 0; j < i; ++j)
+                if (meshes[j] == meshes[i]) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_create: repeated mesh");
+        }
+        gl_batch *B = new gl_batch();
+        try {
+            B->meshes.assign(meshes, meshes + count);
+            B->pre.assign(count, nullptr);
+            B->tiles.assign(count, gl_tiles{0, 0});
+            GLK_HIP(hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking));
+            GLK_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
+            GLK_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
+            std::vector<const KrylovScalars *> kp(count);
+            std::vector<const double *> dp(count);
+            for (int i = 0; i < count; ++i) {
+                kp[i] = kscal_of(meshes[i]);
+                dp[i] = meshes[i]->dscal.get();
+            }
+            B->ks_ptr.alloc(count);
+            B->ds_ptr.alloc(count);
+            B->gathered.alloc(count);
+            GLK_HIP(hipMemcpy(B->ks_ptr.get(), kp.data(), sizeof(void *) * count, hipMemcpyHostToDevice));
+            GLK_HIP(hipMemcpy(B->ds_ptr.get(), dp.data(), sizeof(void *) * count, hipMemcpyHostToDevice));
+            GLK_HIP(hipHostMalloc(&B->host_sc, sizeof(BatchScalars) * count, hipHostMallocDefault));
+        } catch (...) {
+            delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+gl_status gl_batch_newton_solve(gl_batch *batch, void *const *psi_inout, const gl_newton_opts *opts,
+                                gl_newton_info *infos, gl_stream stream)
+{
+    gl_status rc = GL_OK;
+    gl_status g = guarded([&] {
+        if (!batch || !psi_inout || !opts) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: NULL argument");
+        const int N = (int)batch->meshes.size();
+        for (int i = 0; i < N; ++i) {
+            if (!psi_inout[i]) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: NULL psi");
+            for (int j = 0; j < i; ++j)
+                if (psi_inout[j] == psi_inout[i]) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: repeated psi");
+        }
+        check_krylov_opts(&opts->krylov, "gl_batch_newton_solve");
+        if (opts->max_steps < 0 || opts->max_steps > 63 || opts->fixed_steps < 0 || opts->fixed_steps > 63)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: steps must be in 0..63");
+        if (profiler().kernel != 0) fail(GL_ERR_UNSUPPORTED, "gl_batch_newton_solve: not under gl_profile_start");
+        hipStream_t s = as_stream(stream);
+        batch->graph_launches = 0;
+        batch->dispatches = 0;
+        batch->ngroups = 0;
+        for (double &v : batch->seconds) v = 0.0;
+        GLK_HIP(hipEventRecord(batch->ev_in, s));
+        GLK_HIP(hipStreamWaitEvent(batch->s, batch->ev_in, 0));
+        rc = batch_newton(batch, reinterpret_cast<double2 *const *>(psi_inout), *opts, infos);
+        GLK_HIP(hipEventRecord(batch->ev_out, batch->s));
+        GLK_HIP(hipStreamWaitEvent(s, batch->ev_out, 0));
+        if (rc != GL_OK) set_last_error(std::string("gl_batch_newton_solve: ") + gl_status_string(rc));
+    });
+    return g != GL_OK ? g : rc;
+}
+
+gl_status gl_batch_set_tiles(gl_batch *batch, int index, const gl_tiles *tiles)
+{
+    return guarded([&] {
+        if (!batch || !tiles) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_set_tiles: NULL argument");
+        const int N = (int)batch->meshes.size();
+        if (index < -1 || index >= N) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_set_tiles: index");
+        for (int i = 0; i < N; ++i) {
+            if (index >= 0 && i != index) continue;
+            if (batch->pre[i]) {
+                gl_status r = gl_precond_set_tiles(batch->pre[i], tiles);
+                if (r != GL_OK) fail(r, gl_last_error());
+            } else if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 ||
+                       tiles->bottom_rows > 65536) {
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536");
+            }
+            batch->tiles[i] = *tiles;
+        }
+    });
+}
+
+gl_status gl_batch_stats(const gl_batch *batch, int64_t *graph_launches, int64_t *dispatches_per_graph,
+                         int *groups, double *seconds)
+{
+    return guarded([&] {
+        if (!batch) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_stats: NULL handle");
+        if (graph_launches) *graph_launches = batch->graph_launches;
+        if (dispatches_per_graph) *dispatches_per_graph = batch->dispatches;
+        if (groups) *groups = batch->ngroups;
+        if (seconds)
+            for (int k = 0; k < 3; ++k) seconds[k] = batch->seconds[k];
+    });
+}
+
+void gl_batch_destroy(gl_batch *batch) { delete batch; }
 
 }  // extern "C"

@@ -31,25 +31,30 @@ RedSlot red_slot(const gl_mesh *m, int k)
     return RedSlot{m->partials.get() + per * k};
 }
 
-__global__ __launch_bounds__(1024) void k_finalize(const double *__restrict__ partials, int nparts, int mode,
-                                                   KrylovScalars *ks, double *out, const int *gate)
-{
-    if (gate && *gate == 0) return;
-    __shared__ double sm[1024 / 64];
-    double s = 0.0;
-    for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partials[k];
-    s = block_sum(s, sm);
-    if (threadIdx.x == 0) {
-        if (mode == FIN_STORE) *out = s;
-        else minres_finalize(ks, mode, s);
+struct Finalize {
+    const double *partials;
+    int nparts, mode;
+    KrylovScalars *ks;
+    double *out;
+    const int *gate;
+    __device__ void operator()(int, int) const
+    {
+        if (gate && *gate == 0) return;
+        __shared__ double sm[1024 / 64];
+        double s = 0.0;
+        for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partials[k];
+        s = block_sum(s, sm);
+        if (threadIdx.x == 0) {
+            if (mode == FIN_STORE) *out = s;
+            else minres_finalize(ks, mode, s);
+        }
     }
-}
+};
 
 void launch_finalize(const double *partials, int nparts, int mode, KrylovScalars *ks, double *out,
-                     const int *gate, hipStream_t s)
+                     const int *gate, const Launch &L)
 {
-    k_finalize<<<1, 1024, 0, s>>>(partials, nparts, mode, ks, out, gate);
-    GLK_CHECK_LAUNCH();
+    L.run<Finalize, 1024>(1, Finalize{partials, nparts, mode, ks, out, gate});
 }
 
 struct Potential {
@@ -132,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_gl_residual(GeomT<double> g, const d
         if (out) out[i] = r;
         part = d * cabs2(r);
     }
-    block_reduce_store(part, slot, sm);
+    block_reduce_store(part, slot, sm, blockIdx.x);
 }
 
 void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
@@ -201,8 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_cdot(GeomT<double> g, const double2 
         pre = d * p.x;
         pim = d * p.y;
     }
-    block_reduce_store(pre, sre, sm);
-    block_reduce_store(pim, sim, sm);
+    block_reduce_store(pre, sre, sm, blockIdx.x);
+    block_reduce_store(pim, sim, sm, blockIdx.x);
 }
 
 // out = psi + ratio (psi - e^{i chi} prev), e^{i chi} = ip / |ip|
@@ -343,6 +348,7 @@ gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mes
             GLK_HIP(hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
             GLK_HIP(hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming));
             GLK_HIP(hipMemsetAsync(m->dscal.get(), 0, 64 * sizeof(double), s));
+            GLK_HIP(hipMemsetAsync(m->kscal.get(), 0, 4096, s));
             launch_links(m, s);
             GLK_HIP(hipStreamSynchronize(s));
         } catch (...) {

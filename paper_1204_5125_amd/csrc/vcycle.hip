@@ -32,95 +32,115 @@ template <class T> __device__ __forceinline__ C<T> load_b(const double2 *v, cons
 
 // pre-smoothing, black pass from zero; FP32 also stores b = round(v)
 template <int DIM, class T>
-__global__ __launch_bounds__(kBlock) void k_l0_pre_black(GeomT<T> g, const double2 *__restrict__ v,
-                                                         C<T> *__restrict__ b, C<T> *__restrict__ x,
-                                                         const C<T> *__restrict__ U,
-                                                         const T *__restrict__ hd, const int *gate)
-{
-    GATE();
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int c[3];
-    node_coords<DIM>(g.N, i, c);
-    const C<T> bi = narrow<T>(v[i]);
-    if constexpr (std::is_same<T, float>::value) b[i] = bi;
-    if (((c[0] + c[1] + c[2]) & 1) == 0) return;
-    T s[3];
-    const T d = node_volume<DIM, T>(g, c, s);
-    C<T> off = mk<T>(0, 0);
-    int stride = 1;
-    const size_t n = (size_t)g.n;
+struct L0PreBlack {
+    GeomT<T> g;
+    const double2 *v;
+    C<T> *b, *x;
+    const C<T> *U;
+    const T *hd;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE();
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        const C<T> bi = narrow<T>(v[i]);
+        if constexpr (std::is_same<T, float>::value) b[i] = bi;
+        if (((c[0] + c[1] + c[2]) & 1) == 0) return;
+        T s[3];
+        const T d = node_volume<DIM, T>(g, c, s);
+        C<T> off = mk<T>(0, 0);
+        int stride = 1;
+        const size_t n = (size_t)g.n;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const T al = d * s[a] * g.inv_h2[a];
-        if (c[a] > 0) {
-            const int k = i - stride;
-            const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
-            off = csub(off, cscale(cmul(U[a * n + k], xk), al));
+        for (int a = 0; a < DIM; ++a) {
+            const T al = d * s[a] * g.inv_h2[a];
+            if (c[a] > 0) {
+                const int k = i - stride;
+                const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
+                off = csub(off, cscale(cmul(U[a * n + k], xk), al));
+            }
+            if (c[a] < g.N[a] - 1) {
+                const int k = i + stride;
+                const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
+                off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
+            }
+            stride *= g.N[a];
         }
-        if (c[a] < g.N[a] - 1) {
-            const int k = i + stride;
-            const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
-            off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
-        }
-        stride *= g.N[a];
+        x[i] = cscale(csub(bi, off), (T)1 / hd[i]);
     }
-    x[i] = cscale(csub(bi, off), (T)1 / hd[i]);
-}
+};
 
 // x_i = (b_i - sum_{j != i} H_ij x_j) / H_ii on one colour
 template <int DIM, class T>
-__global__ __launch_bounds__(kBlock) void k_l0_sweep(GeomT<T> g, int colour, const double2 *__restrict__ v,
-                                                     const C<T> *__restrict__ b, C<T> *__restrict__ x,
-                                                     const C<T> *__restrict__ U, const T *__restrict__ hd,
-                                                     const int *gate)
-{
-    GATE();
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int c[3];
-    node_coords<DIM>(g.N, i, c);
-    if (((c[0] + c[1] + c[2]) & 1) != colour) return;
-    const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-    x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
-}
+struct L0Sweep {
+    GeomT<T> g;
+    int colour;
+    const double2 *v;
+    const C<T> *b;
+    C<T> *x;
+    const C<T> *U;
+    const T *hd;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE();
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        if (((c[0] + c[1] + c[2]) & 1) != colour) return;
+        const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+        x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+    }
+};
 
 // r = b - H x on black nodes, 0 on red nodes
 template <int DIM, class T>
-__global__ __launch_bounds__(kBlock) void k_l0_residual(GeomT<T> g, const double2 *__restrict__ v,
-                                                        const C<T> *__restrict__ b, const C<T> *__restrict__ x,
-                                                        const C<T> *__restrict__ U, const T *__restrict__ hd,
-                                                        C<T> *__restrict__ r, const int *gate)
-{
-    GATE();
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int c[3];
-    node_coords<DIM>(g.N, i, c);
-    if (((c[0] + c[1] + c[2]) & 1) == 0) {
-        r[i] = mk<T>(0, 0);
-        return;
+struct L0Residual {
+    GeomT<T> g;
+    const double2 *v;
+    const C<T> *b, *x, *U;
+    const T *hd;
+    C<T> *r;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE();
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        if (((c[0] + c[1] + c[2]) & 1) == 0) {
+            r[i] = mk<T>(0, 0);
+            return;
+        }
+        const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+        r[i] = csub(csub(load_b<T>(v, b, i), cscale(x[i], hd[i])), off);
     }
-    const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-    r[i] = csub(csub(load_b<T>(v, b, i), cscale(x[i], hd[i])), off);
-}
+};
 
 // r = v - H z on every node, FP64 (between cycles of R_k, k > 1)
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_l0_residual_full(GeomT<double> g, const double2 *__restrict__ v,
-                                                             const double2 *__restrict__ z,
-                                                             const double2 *__restrict__ U,
-                                                             const double *__restrict__ hd,
-                                                             double2 *__restrict__ r, const int *gate)
-{
-    GATE();
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int c[3];
-    node_coords<DIM>(g.N, i, c);
-    const double2 off = khat_offdiag<DIM, double>(g, i, c, z, U);
-    r[i] = csub(csub(v[i], cscale(z[i], hd[i])), off);
-}
+struct L0ResidualFull {
+    GeomT<double> g;
+    const double2 *v, *z, *U;
+    const double *hd;
+    double2 *r;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE();
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        const double2 off = khat_offdiag<DIM, double>(g, i, c, z, U);
+        r[i] = csub(csub(v[i], cscale(z[i], hd[i])), off);
+    }
+};
 
 // (P x_c)_k for one fine row
 template <class T>
@@ -134,72 +154,87 @@ __device__ __forceinline__ C<T> prolong_row(const int *__restrict__ prp, const i
 
 // post-smoothing, first red pass with the coarse correction of the black neighbours
 template <int DIM, class T>
-__global__ __launch_bounds__(kBlock) void k_l0_post_red(GeomT<T> g, const double2 *__restrict__ v,
-                                                        const C<T> *__restrict__ b, C<T> *__restrict__ x,
-                                                        const C<T> *__restrict__ U, const T *__restrict__ hd,
-                                                        const int *__restrict__ prp, const int *__restrict__ pci,
-                                                        const C<T> *__restrict__ pv, const C<T> *__restrict__ xc,
-                                                        const int *gate)
-{
-    GATE();
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int c[3];
-    node_coords<DIM>(g.N, i, c);
-    if (((c[0] + c[1] + c[2]) & 1) != 0) return;
-    T s[3];
-    const T d = node_volume<DIM, T>(g, c, s);
-    C<T> off = mk<T>(0, 0);
-    int stride = 1;
-    const size_t n = (size_t)g.n;
+struct L0PostRed {
+    GeomT<T> g;
+    const double2 *v;
+    const C<T> *b;
+    C<T> *x;
+    const C<T> *U;
+    const T *hd;
+    const int *prp, *pci;
+    const C<T> *pv, *xc;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE();
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        if (((c[0] + c[1] + c[2]) & 1) != 0) return;
+        T s[3];
+        const T d = node_volume<DIM, T>(g, c, s);
+        C<T> off = mk<T>(0, 0);
+        int stride = 1;
+        const size_t n = (size_t)g.n;
 #pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        const T al = d * s[a] * g.inv_h2[a];
-        if (c[a] > 0) {
-            const int k = i - stride;
-            const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
-            off = csub(off, cscale(cmul(U[a * n + k], xk), al));
+        for (int a = 0; a < DIM; ++a) {
+            const T al = d * s[a] * g.inv_h2[a];
+            if (c[a] > 0) {
+                const int k = i - stride;
+                const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
+                off = csub(off, cscale(cmul(U[a * n + k], xk), al));
+            }
+            if (c[a] < g.N[a] - 1) {
+                const int k = i + stride;
+                const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
+                off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
+            }
+            stride *= g.N[a];
         }
-        if (c[a] < g.N[a] - 1) {
-            const int k = i + stride;
-            const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
-            off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
-        }
-        stride *= g.N[a];
+        x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
     }
-    x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
-}
+};
 
 // last red pass; z = x (ADD: z += x) on every node and partial sums of Re<vdot, z>
 template <int DIM, class T, int ADD>
-__global__ __launch_bounds__(kBlock) void k_l0_last(GeomT<T> g, const double2 *__restrict__ v,
-                                                    const C<T> *__restrict__ b, C<T> *__restrict__ x,
-                                                    const C<T> *__restrict__ U, const T *__restrict__ hd,
-                                                    double2 *__restrict__ z, const double2 *__restrict__ vdot,
-                                                    RedSlot slot, int want_dot, const int *gate)
-{
-    GATE();
-    __shared__ double sm[kBlock / 64];
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    double part = 0.0;
-    if (i < g.n) {
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
-        C<T> xi;
-        if (((c[0] + c[1] + c[2]) & 1) == 0) {
-            const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-            xi = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
-            x[i] = xi;
-        } else {
-            xi = x[i];
+struct L0Last {
+    GeomT<T> g;
+    const double2 *v;
+    const C<T> *b;
+    C<T> *x;
+    const C<T> *U;
+    const T *hd;
+    double2 *z;
+    const double2 *vdot;
+    RedSlot slot;
+    int want_dot;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE();
+        __shared__ double sm[kBlock / 64];
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < g.n) {
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            C<T> xi;
+            if (((c[0] + c[1] + c[2]) & 1) == 0) {
+                const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+                xi = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+                x[i] = xi;
+            } else {
+                xi = x[i];
+            }
+            double2 zi = widen(xi);
+            if (ADD) zi = cadd(z[i], zi);
+            z[i] = zi;
+            if (want_dot) part = redot(vdot[i], zi);
         }
-        double2 zi = widen(xi);
-        if (ADD) zi = cadd(z[i], zi);
-        z[i] = zi;
-        if (want_dot) part = redot(vdot[i], zi);
+        if (want_dot) block_reduce_store(part, slot, sm, bx);
     }
-    if (want_dot) block_reduce_store(part, slot, sm);
-}
+};
 
 // --------------------------------------------------------------- CSR ---
 // LPR lanes of one wave share a row; partial sums are combined by shuffles.
@@ -214,141 +249,156 @@ __device__ __forceinline__ C<T> lanes_sum(C<T> s)
     return s;
 }
 
-// Gauss-Seidel update of the rows row0 .. row0 + count - 1 (one colour)
-template <class T, int LPR>
-__global__ __launch_bounds__(kBlock) void k_csr_sgs(const int *__restrict__ rp, const int *__restrict__ ci,
-                                                    const C<T> *__restrict__ v, const T *__restrict__ diag,
-                                                    int row0, int count,
-                                                    const C<T> *__restrict__ b, C<T> *__restrict__ x,
-                                                    const int *gate)
-{
-    GATE();
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int r = t / LPR, lane = t % LPR;
-    const bool act = r < count;
-    const int i = row0 + (act ? r : 0);
-    C<T> s = mk<T>(0, 0);
-    if (act)
-        for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) {
-            const int j = ci[p];
-            if (j != i) s = cadd(s, cmul(v[p], x[j]));
-        }
-    s = lanes_sum<T, LPR>(s);
-    if (act && lane == 0) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
-}
-
 // Gauss-Seidel update of one colour stored as a padded block (ELL, width W).
 // The gate flag is loaded alongside the data and checked only before the
 // store, so its latency overlaps the row loads.
 template <class T, int LPR>
-__global__ __launch_bounds__(kBlock) void k_ell_sgs(const int *__restrict__ eci, const C<T> *__restrict__ ev,
-                                                    int W, const T *__restrict__ diag, int row0, int count,
-                                                    const C<T> *__restrict__ b, C<T> *__restrict__ x,
-                                                    const int *gate)
-{
-    const int go = gate ? *gate : 1;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int r = t / LPR, lane = t % LPR;
-    const bool act = r < count;
-    const int i = row0 + (act ? r : 0);
-    C<T> s = mk<T>(0, 0);
-    if (act) {
-        const size_t base = (size_t)r * W;
-        for (int k = lane; k < W; k += LPR) {
-            const int j = eci[base + k];
-            if (j != i) s = cadd(s, cmul(ev[base + k], x[j]));
+struct EllSgs {
+    const int *eci;
+    const C<T> *ev;
+    int W;
+    const T *diag;
+    int row0, count;
+    const C<T> *b;
+    C<T> *x;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        const int go = gate ? *gate : 1;
+        const int t = bx * kBlock + threadIdx.x;
+        const int r = t / LPR, lane = t % LPR;
+        const bool act = r < count;
+        const int i = row0 + (act ? r : 0);
+        C<T> s = mk<T>(0, 0);
+        if (act) {
+            const size_t base = (size_t)r * W;
+            for (int k = lane; k < W; k += LPR) {
+                const int j = eci[base + k];
+                if (j != i) s = cadd(s, cmul(ev[base + k], x[j]));
+            }
         }
+        s = lanes_sum<T, LPR>(s);
+        if (act && lane == 0 && go) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
     }
-    s = lanes_sum<T, LPR>(s);
-    if (act && lane == 0 && go) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
-}
+};
 
 // r = b - A x
 template <class T, int LPR>
-__global__ __launch_bounds__(kBlock) void k_csr_residual(int n, const int *__restrict__ rp,
-                                                         const int *__restrict__ ci, const C<T> *__restrict__ v,
-                                                         const C<T> *__restrict__ b, const C<T> *__restrict__ x,
-                                                         C<T> *__restrict__ r, const int *gate)
-{
-    GATE();
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int i = t / LPR, lane = t % LPR;
-    const bool act = i < n;
-    C<T> s = mk<T>(0, 0);
-    if (act)
-        for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
-    s = lanes_sum<T, LPR>(s);
-    if (act && lane == 0) r[i] = csub(b[i], s);
-}
+struct CsrResidual {
+    int n;
+    const int *rp, *ci;
+    const C<T> *v, *b, *x;
+    C<T> *r;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const int t = bx * kBlock + threadIdx.x;
+        const int i = t / LPR, lane = t % LPR;
+        const bool act = i < n;
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
+        s = lanes_sum<T, LPR>(s);
+        if (act && lane == 0) r[i] = csub(b[i], s);
+    }
+};
 
 // y = A x (ADD = 0) or y += A x (ADD = 1)
 template <class T, int LPR, int ADD>
-__global__ __launch_bounds__(kBlock) void k_csr_spmv(int n, const int *__restrict__ rp, const int *__restrict__ ci,
-                                                     const C<T> *__restrict__ v, const C<T> *__restrict__ x,
-                                                     C<T> *__restrict__ y, const int *gate)
-{
-    GATE();
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int i = t / LPR, lane = t % LPR;
-    const bool act = i < n;
-    C<T> s = mk<T>(0, 0);
-    if (act)
-        for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
-    s = lanes_sum<T, LPR>(s);
-    if (act && lane == 0) y[i] = ADD ? cadd(y[i], s) : s;
-}
+struct CsrSpmv {
+    int n;
+    const int *rp, *ci;
+    const C<T> *v, *x;
+    C<T> *y;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const int t = bx * kBlock + threadIdx.x;
+        const int i = t / LPR, lane = t % LPR;
+        const bool act = i < n;
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
+        s = lanes_sum<T, LPR>(s);
+        if (act && lane == 0) y[i] = ADD ? cadd(y[i], s) : s;
+    }
+};
 
 template <class T>
-__global__ void k_fill_zero(int n, C<T> *x, const int *gate)
-{
-    GATE();
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] = mk<T>(0, 0);
-}
+struct FillZero {
+    int n;
+    C<T> *x;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const int i = bx * kBlock + threadIdx.x;
+        if (i < n) x[i] = mk<T>(0, 0);
+    }
+};
 
 template <class T>
-__global__ void k_narrow(int n, const double2 *v, C<T> *b, const int *gate)
-{
-    GATE();
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) b[i] = narrow<T>(v[i]);
-}
+struct Narrow {
+    int n;
+    const double2 *v;
+    C<T> *b;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const int i = bx * kBlock + threadIdx.x;
+        if (i < n) b[i] = narrow<T>(v[i]);
+    }
+};
 
 // z = x (ADD = 0) or z += x (ADD = 1); partial sums of Re<vdot, z>
 template <class T, int ADD>
-__global__ __launch_bounds__(kBlock) void k_output(int n, const C<T> *__restrict__ x,
-                                                   const double2 *__restrict__ vdot, double2 *__restrict__ z,
-                                                   RedSlot slot, int want_dot, const int *gate)
-{
-    GATE();
-    __shared__ double sm[kBlock / 64];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double part = 0.0;
-    if (i < n) {
-        double2 zi = widen(x[i]);
-        if (ADD) zi = cadd(z[i], zi);
-        z[i] = zi;
-        if (want_dot) part = redot(vdot[i], zi);
+struct Output {
+    int n;
+    const C<T> *x;
+    const double2 *vdot;
+    double2 *z;
+    RedSlot slot;
+    int want_dot;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        __shared__ double sm[kBlock / 64];
+        const int i = bx * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < n) {
+            double2 zi = widen(x[i]);
+            if (ADD) zi = cadd(z[i], zi);
+            z[i] = zi;
+            if (want_dot) part = redot(vdot[i], zi);
+        }
+        if (want_dot) block_reduce_store(part, slot, sm, bx);
     }
-    if (want_dot) block_reduce_store(part, slot, sm);
-}
+};
 
 // x = M b for the dense row-major inverse of the coarsest operator (a wave per row)
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_dense_apply(int n, const C<T> *__restrict__ M,
-                                                        const C<T> *__restrict__ b, C<T> *__restrict__ x,
-                                                        const int *gate)
-{
-    GATE();
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int i = t / 64, lane = t % 64;
-    const bool act = i < n;
-    C<T> s = mk<T>(0, 0);
-    if (act)
-        for (int j = lane; j < n; j += 64) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
-    s = lanes_sum<T, 64>(s);
-    if (act && lane == 0) x[i] = s;
-}
+struct DenseApply {
+    int n;
+    const C<T> *M, *b;
+    C<T> *x;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const int t = bx * kBlock + threadIdx.x;
+        const int i = t / 64, lane = t % 64;
+        const bool act = i < n;
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int j = lane; j < n; j += 64) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
+        s = lanes_sum<T, 64>(s);
+        if (act && lane == 0) x[i] = s;
+    }
+};
 
 // ------------------------------------------------------------ bottom ---
 // Every level from D.first down to the coarsest, in one work-group of
@@ -428,33 +478,37 @@ __device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L)
 }
 
 template <class T>
-__global__ __launch_bounds__(kBottomThreads) void k_bottom(const BottomDesc<T> *__restrict__ Dp, const int *gate)
-{
-    GATE();
-    const BottomDesc<T> &D = *Dp;
-    for (int l = D.first; l < D.last; ++l) {
-        const BottomLevel<T> &L = D.L[l];
-        for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = mk<T>(0, 0);
-        __syncthreads();
-        bottom_sgs<T>(L);
-        bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, L.x, L.b, L.r);
-        __syncthreads();
-        bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, L.r, nullptr, D.L[l + 1].b);
-        __syncthreads();
-    }
-    // coarsest level: x = A^-1 b with the dense inverse
+struct Bottom {
+    const BottomDesc<T> *Dp;
+    const int *gate;
+    __device__ void operator()(int, int) const
     {
-        const BottomLevel<T> &Lc = D.L[D.last];
-        bottom_dense<T>(Lc.n, D.cinv, Lc.b, Lc.x);
-        __syncthreads();
+        GATE();
+        const BottomDesc<T> &D = *Dp;
+        for (int l = D.first; l < D.last; ++l) {
+            const BottomLevel<T> &L = D.L[l];
+            for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = mk<T>(0, 0);
+            __syncthreads();
+            bottom_sgs<T>(L);
+            bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, L.x, L.b, L.r);
+            __syncthreads();
+            bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, L.r, nullptr, D.L[l + 1].b);
+            __syncthreads();
+        }
+        // coarsest level: x = A^-1 b with the dense inverse
+        {
+            const BottomLevel<T> &Lc = D.L[D.last];
+            bottom_dense<T>(Lc.n, D.cinv, Lc.b, Lc.x);
+            __syncthreads();
+        }
+        for (int l = D.last - 1; l >= D.first; --l) {
+            const BottomLevel<T> &L = D.L[l];
+            bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, L.x);
+            __syncthreads();
+            bottom_sgs<T>(L);
+        }
     }
-    for (int l = D.last - 1; l >= D.first; --l) {
-        const BottomLevel<T> &L = D.L[l];
-        bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, L.x);
-        __syncthreads();
-        bottom_sgs<T>(L);
-    }
-}
+};
 
 // ---------------------------------------------------------------- host -
 template <class T> static C<T> *vec_b(Level &L);
@@ -492,15 +546,19 @@ template <> const BottomDesc<float> *bdesc<float>(const gl_precond *p)
     return reinterpret_cast<const BottomDesc<float> *>(p->bdesc32.get());
 }
 
-static int lanes_for(const Csr &M)
+// lanes per row: about one lane per 2.5 entries, scaled by 2^shift, in 1 .. 32
+static int shifted(int lpr, int shift)
+{
+    while (shift > 0 && lpr < 32) { lpr *= 2; --shift; }
+    while (shift < 0 && lpr > 1) { lpr /= 2; ++shift; }
+    return lpr;
+}
+
+static int lanes_for(const Csr &M, int shift)
 {
     const double avg = M.n ? (double)M.nnz / M.n : 1.0;
-    if (avg <= 2.5) return 1;
-    if (avg <= 5.0) return 2;
-    if (avg <= 10.0) return 4;
-    if (avg <= 20.0) return 8;
-    if (avg <= 40.0) return 16;
-    return 32;
+    const int lpr = avg <= 2.5 ? 1 : avg <= 5.0 ? 2 : avg <= 10.0 ? 4 : avg <= 20.0 ? 8 : avg <= 40.0 ? 16 : 32;
+    return shifted(lpr, shift);
 }
 
 // dispatch a CSR kernel over LPR in {1, 2, 4, 8, 16, 32}
@@ -515,13 +573,14 @@ static int lanes_for(const Csr &M)
     }
 
 template <class T>
-static void csr_spmv(const Csr &M, const C<T> *x, C<T> *y, bool add, const int *gate, hipStream_t s)
+static void csr_spmv(const Csr &M, const C<T> *x, C<T> *y, bool add, int shift, const int *gate,
+                     const Launch &L)
 {
-    const int lpr = lanes_for(M);
+    const int lpr = lanes_for(M, shift);
     const int nb = blocks_for((int64_t)M.n * lpr);
     GLK_LPR_SWITCH(lpr, {
-        if (add) k_csr_spmv<T, LPR, 1><<<nb, kBlock, 0, s>>>(M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate);
-        else k_csr_spmv<T, LPR, 0><<<nb, kBlock, 0, s>>>(M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate);
+        if (add) L.run(nb, CsrSpmv<T, LPR, 1>{M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate});
+        else L.run(nb, CsrSpmv<T, LPR, 0>{M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate});
     });
 }
 
@@ -530,36 +589,36 @@ template <> const double2 *evals<double>(const Level &L) { return L.ev64.get(); 
 template <> const float2 *evals<float>(const Level &L) { return L.ev32.get(); }
 
 template <class T>
-static void csr_sgs(Level &L, const int *gate, hipStream_t s)
+static void csr_sgs(Level &Lv, int shift, const int *gate, const Launch &L)
 {
-    for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
-        const int c = t < L.ncolors ? t : 2 * L.ncolors - 2 - t;
-        const int cnt = L.coff[c + 1] - L.coff[c];
+    for (int t = 0; t < 2 * Lv.ncolors - 1; ++t) {
+        const int c = t < Lv.ncolors ? t : 2 * Lv.ncolors - 2 - t;
+        const int cnt = Lv.coff[c + 1] - Lv.coff[c];
         if (cnt == 0) continue;
-        const int W = L.ewidth[c];
-        const int lpr = W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16;
+        const int W = Lv.ewidth[c];
+        const int lpr = shifted(W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16, shift);
         const int nb = blocks_for((int64_t)cnt * lpr);
         GLK_LPR_SWITCH(lpr, {
-            k_ell_sgs<T, LPR><<<nb, kBlock, 0, s>>>(L.eci.get() + L.eoff[c], evals<T>(L) + L.eoff[c], W, dgn<T>(L),
-                                                    L.coff[c], cnt, vec_b<T>(L), vec_x<T>(L), gate);
+            L.run(nb, EllSgs<T, LPR>{Lv.eci.get() + Lv.eoff[c], evals<T>(Lv) + Lv.eoff[c], W, dgn<T>(Lv),
+                                     Lv.coff[c], cnt, vec_b<T>(Lv), vec_x<T>(Lv), gate});
         });
     }
 }
 
 template <class T>
-static void csr_residual(Level &L, const int *gate, hipStream_t s)
+static void csr_residual(Level &Lv, int shift, const int *gate, const Launch &L)
 {
-    const int lpr = lanes_for(L.Aa);
-    const int nb = blocks_for((int64_t)L.n * lpr);
+    const int lpr = lanes_for(Lv.Aa, shift);
+    const int nb = blocks_for((int64_t)Lv.n * lpr);
     GLK_LPR_SWITCH(lpr, {
-        k_csr_residual<T, LPR><<<nb, kBlock, 0, s>>>(L.n, L.Aa.rp.get(), L.Aa.ci.get(), vals<T>(L.Aa),
-                                                     vec_b<T>(L), vec_x<T>(L), vec_r<T>(L), gate);
+        L.run(nb, CsrResidual<T, LPR>{Lv.n, Lv.Aa.rp.get(), Lv.Aa.ci.get(), vals<T>(Lv.Aa), vec_b<T>(Lv),
+                                      vec_x<T>(Lv), vec_r<T>(Lv), gate});
     });
 }
 
 template <int DIM, class T>
 static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
-                        const int *gate, KrylovScalars *ks, int mode, int add, hipStream_t s)
+                        const int *gate, KrylovScalars *ks, int mode, int add, const Launch &L)
 {
     gl_precond *pre = const_cast<gl_precond *>(cpre);
     const gl_mesh *m = pre->mesh;
@@ -574,12 +633,11 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     C<T> *x0 = vec_x<T>(L0);
     const int want = ks != nullptr;
     if (nl == 1) {
-        k_narrow<T><<<nb0, kBlock, 0, s>>>(n0, v, vec_b<T>(L0), gate);
-        k_dense_apply<T><<<blocks_for((int64_t)n0 * 64), kBlock, 0, s>>>(n0, cinv<T>(pre), vec_b<T>(L0), x0, gate);
-        if (add) k_output<T, 1><<<nb0, kBlock, 0, s>>>(n0, x0, vdot, z, slot, want, gate);
-        else k_output<T, 0><<<nb0, kBlock, 0, s>>>(n0, x0, vdot, z, slot, want, gate);
-        GLK_CHECK_LAUNCH();
-        if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, s);
+        L.run(nb0, Narrow<T>{n0, v, vec_b<T>(L0), gate});
+        L.run(blocks_for((int64_t)n0 * 64), DenseApply<T>{n0, cinv<T>(pre), vec_b<T>(L0), x0, gate});
+        if (add) L.run(nb0, Output<T, 1>{n0, x0, vdot, z, slot, want, gate});
+        else L.run(nb0, Output<T, 0>{n0, x0, vdot, z, slot, want, gate});
+        if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, L);
         return;
     }
     const T *hd = diag<T>(L0);
@@ -593,95 +651,88 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
     const double b_restr = (L0.nc + 1 + L0.Ra.nnz) * 4.0 + L0.Ra.nnz * sz + nn * sz + L0.nc * sz;
     // level 0, down: red (from zero, folded) + black, red, black residual, restriction
-    prof_launch(PROF_L0_SWEEP, b_pre, s, [&] {
-        k_l0_pre_black<DIM, T><<<nb0, kBlock, 0, s>>>(g, v, vec_b<T>(L0), x0, U, hd, gate);
+    prof_launch(PROF_L0_SWEEP, b_pre, L, [&] {
+        L.run(nb0, L0PreBlack<DIM, T>{g, v, vec_b<T>(L0), x0, U, hd, gate});
     });
-    prof_launch(PROF_L0_SWEEP, b_sweep, s, [&] {
-        k_l0_sweep<DIM, T><<<nb0, kBlock, 0, s>>>(g, 0, v, b0, x0, U, hd, gate);
+    prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
+        L.run(nb0, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
     });
-    prof_launch(PROF_L0_RESIDUAL, b_resid, s, [&] {
-        k_l0_residual<DIM, T><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, vec_r<T>(L0), gate);
+    prof_launch(PROF_L0_RESIDUAL, b_resid, L, [&] {
+        L.run(nb0, L0Residual<DIM, T>{g, v, b0, x0, U, hd, vec_r<T>(L0), gate});
     });
-    prof_launch(PROF_L0_TRANSFER, b_restr, s, [&] {
-        csr_spmv<T>(L0.Ra, vec_r<T>(L0), vec_b<T>(L1), false, gate, s);
+    prof_launch(PROF_L0_TRANSFER, b_restr, L, [&] {
+        csr_spmv<T>(L0.Ra, vec_r<T>(L0), vec_b<T>(L1), false, 0, gate, L);
     });
-    GLK_CHECK_LAUNCH();
     // multi-kernel coarse levels, down
     const int nb_first = pre->bottom;
+    const int sh = pre->lane_shift;
     for (int l = 1; l < nb_first; ++l) {
-        Level &L = pre->L[l];
-        k_fill_zero<T><<<blocks_for(L.n), kBlock, 0, s>>>(L.n, vec_x<T>(L), gate);
-        csr_sgs<T>(L, gate, s);
-        csr_residual<T>(L, gate, s);
-        csr_spmv<T>(L.Ra, vec_r<T>(L), vec_b<T>(pre->L[l + 1]), false, gate, s);
-        GLK_CHECK_LAUNCH();
+        Level &Lv = pre->L[l];
+        L.run(blocks_for(Lv.n), FillZero<T>{Lv.n, vec_x<T>(Lv), gate});
+        csr_sgs<T>(Lv, sh, gate, L);
+        csr_residual<T>(Lv, sh, gate, L);
+        csr_spmv<T>(Lv.Ra, vec_r<T>(Lv), vec_b<T>(pre->L[l + 1]), false, sh, gate, L);
     }
     // small levels and the coarsest solve in one work-group, or the coarsest
     // solve alone as a dense product over many work-groups
     if (pre->bottom < nl - 1) {
-        k_bottom<T><<<1, kBottomThreads, 0, s>>>(bdesc<T>(pre), gate);
+        L.run<Bottom<T>, kBottomThreads>(1, Bottom<T>{bdesc<T>(pre), gate});
     } else {
         Level &Lc = pre->L[nl - 1];
-        k_dense_apply<T><<<blocks_for((int64_t)Lc.n * 64), kBlock, 0, s>>>(Lc.n, cinv<T>(pre), vec_b<T>(Lc),
-                                                                           vec_x<T>(Lc), gate);
+        L.run(blocks_for((int64_t)Lc.n * 64), DenseApply<T>{Lc.n, cinv<T>(pre), vec_b<T>(Lc), vec_x<T>(Lc), gate});
     }
-    GLK_CHECK_LAUNCH();
     // multi-kernel coarse levels, up
     for (int l = nb_first - 1; l >= 1; --l) {
-        Level &L = pre->L[l];
-        csr_spmv<T>(L.Pa, vec_x<T>(pre->L[l + 1]), vec_x<T>(L), true, gate, s);
-        csr_sgs<T>(L, gate, s);
-        GLK_CHECK_LAUNCH();
+        Level &Lv = pre->L[l];
+        csr_spmv<T>(Lv.Pa, vec_x<T>(pre->L[l + 1]), vec_x<T>(Lv), true, sh, gate, L);
+        csr_sgs<T>(Lv, sh, gate, L);
     }
     // level 0, up: red with the coarse correction, black, red + output
-    prof_launch(PROF_L0_SWEEP, b_post, s, [&] {
-        k_l0_post_red<DIM, T><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, L0.Pa.rp.get(), L0.Pa.ci.get(),
-                                                     vals<T>(L0.Pa), vec_x<T>(L1), gate);
+    prof_launch(PROF_L0_SWEEP, b_post, L, [&] {
+        L.run(nb0, L0PostRed<DIM, T>{g, v, b0, x0, U, hd, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<T>(L0.Pa),
+                                     vec_x<T>(L1), gate});
     });
-    prof_launch(PROF_L0_SWEEP, b_sweep, s, [&] {
-        k_l0_sweep<DIM, T><<<nb0, kBlock, 0, s>>>(g, 1, v, b0, x0, U, hd, gate);
+    prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
+        L.run(nb0, L0Sweep<DIM, T>{g, 1, v, b0, x0, U, hd, gate});
     });
-    prof_launch(PROF_L0_SWEEP, b_last, s, [&] {
-        if (add) k_l0_last<DIM, T, 1><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, z, vdot, slot, want, gate);
-        else k_l0_last<DIM, T, 0><<<nb0, kBlock, 0, s>>>(g, v, b0, x0, U, hd, z, vdot, slot, want, gate);
+    prof_launch(PROF_L0_SWEEP, b_last, L, [&] {
+        if (add) L.run(nb0, L0Last<DIM, T, 1>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
+        else L.run(nb0, L0Last<DIM, T, 0>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
     });
-    GLK_CHECK_LAUNCH();
-    if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, s);
+    if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, L);
 }
 
 template <int DIM, class T>
 static void vcycle_k(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
-                     KrylovScalars *ks, int mode, hipStream_t s)
+                     KrylovScalars *ks, int mode, const Launch &L)
 {
     const int k = pre->opts.cycles;
     if (k <= 1) {
-        vcycle_once<DIM, T>(pre, v, v, z, gate, ks, mode, 0, s);
+        vcycle_once<DIM, T>(pre, v, v, z, gate, ks, mode, 0, L);
         return;
     }
     // x <- x + V(v - H x), k times from x = 0
     const gl_mesh *m = pre->mesh;
     const GeomT<double> g = geom_t<double>(m->g);
     const int nb0 = blocks_for(pre->L[0].n);
-    vcycle_once<DIM, T>(pre, v, v, z, gate, nullptr, 0, 0, s);
+    vcycle_once<DIM, T>(pre, v, v, z, gate, nullptr, 0, 0, L);
     for (int c = 1; c < k; ++c) {
-        k_l0_residual_full<DIM><<<nb0, kBlock, 0, s>>>(g, v, z, m->U64.get(), pre->L[0].diag64.get(),
-                                                       pre->cyc_r.get(), gate);
-        GLK_CHECK_LAUNCH();
+        L.run(nb0, L0ResidualFull<DIM>{g, v, z, m->U64.get(), pre->L[0].diag64.get(), pre->cyc_r.get(), gate});
         const bool lastc = (c == k - 1);
-        vcycle_once<DIM, T>(pre, pre->cyc_r.get(), v, z, gate, lastc ? ks : nullptr, mode, 1, s);
+        vcycle_once<DIM, T>(pre, pre->cyc_r.get(), v, z, gate, lastc ? ks : nullptr, mode, 1, L);
     }
 }
 
 void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
-                    KrylovScalars *ks, int mode, hipStream_t s)
+                    KrylovScalars *ks, int mode, const Launch &L)
 {
     const bool f32 = pre->opts.precision == GL_FP32;
     if (pre->mesh->g.dim == 2) {
-        if (f32) vcycle_k<2, float>(pre, v, z, gate, ks, mode, s);
-        else vcycle_k<2, double>(pre, v, z, gate, ks, mode, s);
+        if (f32) vcycle_k<2, float>(pre, v, z, gate, ks, mode, L);
+        else vcycle_k<2, double>(pre, v, z, gate, ks, mode, L);
     } else {
-        if (f32) vcycle_k<3, float>(pre, v, z, gate, ks, mode, s);
-        else vcycle_k<3, double>(pre, v, z, gate, ks, mode, s);
+        if (f32) vcycle_k<3, float>(pre, v, z, gate, ks, mode, L);
+        else vcycle_k<3, double>(pre, v, z, gate, ks, mode, L);
     }
 }
 
@@ -726,7 +777,7 @@ void bottom_descriptors(gl_precond *pre, hipStream_t s)
     int first = pre->nlev - 1;
     for (int l = pre->nlev - 2; l >= 1; --l) {
         const Level &L = pre->L[l];
-        if (L.n > kBottomRows || L.ncolors > kMaxColors) break;
+        if (L.n > pre->bottom_rows || L.ncolors > kMaxColors) break;
         first = l;
     }
     pre->bottom = first;
@@ -754,6 +805,6 @@ extern "C" gl_status gl_precond_apply(const gl_precond *pre, const void *r, void
         // R_k r = AMG_k(H, D r)
         double2 *vin = const_cast<gl_precond *>(pre)->vin.get();
         scale_by_volume(pre->mesh, (const double2 *)r, vin, s);
-        vcycle_enqueue(pre, vin, (double2 *)z, nullptr, nullptr, 0, s);
+        vcycle_enqueue(pre, vin, (double2 *)z, nullptr, nullptr, 0, Launch{s});
     });
 }

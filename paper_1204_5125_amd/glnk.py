@@ -28,8 +28,11 @@ EXPORTED_SYMBOLS = [
     "gl_mesh_destroy", "gl_residual", "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
     "gl_precond_apply",
     "gl_precond_info", "gl_precond_export", "gl_precond_destroy", "gl_jacobian_solve",
-    "gl_newton_solve", "gl_profile_start", "gl_profile_stop", "gl_status_string", "gl_last_error",
+    "gl_newton_solve", "gl_precond_set_tiles", "gl_precond_get_tiles", "gl_batch_create",
+    "gl_batch_newton_solve", "gl_batch_set_tiles", "gl_batch_stats", "gl_batch_destroy",
+    "gl_profile_start", "gl_profile_stop", "gl_status_string", "gl_last_error",
 ]
+_VOID = ("gl_mesh_destroy", "gl_precond_destroy", "gl_batch_destroy", "gl_status_string", "gl_last_error")
 
 
 class GlnkError(RuntimeError):
@@ -62,6 +65,10 @@ class KrylovInfo(C.Structure):
 class NewtonOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_steps", C.c_int), ("fixed_steps", C.c_int),
                 ("use_precond", C.c_int), ("krylov", KrylovOpts), ("amg", AmgOpts)]
+
+
+class Tiles(C.Structure):
+    _fields_ = [("lane_shift", C.c_int), ("bottom_rows", C.c_int)]
 
 
 class NewtonInfo(C.Structure):
@@ -99,6 +106,14 @@ def lib():
     L.gl_precond_destroy.restype = None
     L.gl_jacobian_solve.argtypes = [vp, vp, vp, vp, vp, P(KrylovOpts), P(KrylovInfo), vp]
     L.gl_newton_solve.argtypes = [vp, vp, P(NewtonOpts), P(vp), P(NewtonInfo), vp]
+    L.gl_precond_set_tiles.argtypes = [vp, P(Tiles)]
+    L.gl_precond_get_tiles.argtypes = [vp, P(Tiles)]
+    L.gl_batch_create.argtypes = [C.c_int, P(vp), P(vp)]
+    L.gl_batch_newton_solve.argtypes = [vp, P(vp), P(NewtonOpts), P(NewtonInfo), vp]
+    L.gl_batch_set_tiles.argtypes = [vp, C.c_int, P(Tiles)]
+    L.gl_batch_stats.argtypes = [vp, P(C.c_int64), P(C.c_int64), P(C.c_int), P(C.c_double)]
+    L.gl_batch_destroy.argtypes = [vp]
+    L.gl_batch_destroy.restype = None
     L.gl_profile_start.argtypes = [C.c_int]
     L.gl_profile_stop.argtypes = [P(C.c_double), P(C.c_double), P(C.c_int64)]
     L.gl_status_string.argtypes = [st]
@@ -106,7 +121,7 @@ def lib():
     L.gl_last_error.argtypes = []
     L.gl_last_error.restype = C.c_char_p
     for name in EXPORTED_SYMBOLS:
-        if name not in ("gl_mesh_destroy", "gl_precond_destroy", "gl_status_string", "gl_last_error"):
+        if name not in _VOID:
             getattr(L, name).restype = st
     _lib = L
     return L
@@ -340,3 +355,74 @@ def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_preco
         _check(rc, "gl_newton_solve", allow=(4,))
     return rc, {"steps": ni.steps, "converged": bool(ni.converged), "res": list(ni.res[:ni.steps + 1]),
                 "krylov_iters": list(ni.krylov_iters[:ni.steps])}
+
+
+def _newton_info(ni):
+    return {"steps": ni.steps, "converged": bool(ni.converged), "res": list(ni.res[:ni.steps + 1]),
+            "krylov_iters": list(ni.krylov_iters[:ni.steps])}
+
+
+def gl_precond_set_tiles(pre, lane_shift=0, bottom_rows=0):
+    _check(lib().gl_precond_set_tiles(pre.handle, C.byref(Tiles(lane_shift, bottom_rows))),
+           "gl_precond_set_tiles")
+
+
+def gl_precond_get_tiles(pre):
+    t = Tiles()
+    _check(lib().gl_precond_get_tiles(pre.handle, C.byref(t)), "gl_precond_get_tiles")
+    return {"lane_shift": t.lane_shift, "bottom_rows": t.bottom_rows}
+
+
+class Batch:
+    """gl_batch: Newton on many meshes at once (one preconditioner each)."""
+
+    def __init__(self, meshes):
+        self.meshes = list(meshes)
+        arr = (C.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
+        h = C.c_void_p()
+        _check(lib().gl_batch_create(len(self.meshes), arr, C.byref(h)), "gl_batch_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_tiles(self, lane_shift=0, bottom_rows=0, index=-1):
+        _check(lib().gl_batch_set_tiles(self._h, index, C.byref(Tiles(lane_shift, bottom_rows))),
+               "gl_batch_set_tiles")
+
+    def newton_solve(self, psis, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
+                     krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
+                     precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, stream=None,
+                     raise_on_fail=True):
+        """Newton on every instance in place (psis[i] on meshes[i]); returns
+        (status, [info dict per instance])."""
+        if len(psis) != len(self.meshes):
+            raise ValueError("one psi per mesh")
+        ptrs = (C.c_void_p * len(psis))(*[_vec(p, m.n, "psi") for p, m in zip(psis, self.meshes)])
+        o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
+                       KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol),
+                       AmgOpts(precision, cycles, max_coarse, max_levels))
+        infos = (NewtonInfo * len(psis))()
+        rc = lib().gl_batch_newton_solve(self._h, ptrs, C.byref(o), infos, _stream(stream))
+        if raise_on_fail:
+            _check(rc, "gl_batch_newton_solve", allow=(4,))
+        return rc, [_newton_info(ni) for ni in infos]
+
+    def stats(self):
+        a, b, g = C.c_int64(), C.c_int64(), C.c_int()
+        sec = (C.c_double * 3)()
+        _check(lib().gl_batch_stats(self._h, C.byref(a), C.byref(b), C.byref(g), sec), "gl_batch_stats")
+        return {"graph_launches": a.value, "dispatches_per_graph": b.value, "groups": g.value,
+                "seconds": {"residual": sec[0], "setup": sec[1], "solve": sec[2]}}
+
+    def close(self):
+        if self._h and _lib is not None:
+            _lib.gl_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: ctypes may be gone
+            pass
