@@ -30,8 +30,9 @@ SIDE = (10.0, 10.0)
 MU = 1.0
 NEWTON_STEPS = 4
 RTOL = 1e-10
-KERNEL_NAMES = {1: "k_minres_japply", 2: "k_l0_sgs", 3: "k_l0_residual", 4: "k_csr_spmv (level 0)",
-                5: "k_minres_vupdate", 6: "k_minres_wx", 7: "k_gl_residual"}
+KERNEL_NAMES = {1: "MinresJapply", 2: "L0 Gauss-Seidel sweeps (L0PreBlack, L0Sweep, L0PostRed, L0Last)",
+                3: "L0Residual", 4: "CsrSpmv (level-0 restriction)", 5: "MinresVupdate", 6: "k_minres_wx",
+                7: "k_gl_residual", 8: "EllSgs (Gauss-Seidel colour sweep, levels >= 1)"}
 
 
 def log(msg):
@@ -178,17 +179,91 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_continuation(args):
+    """Learned predictor (config: 2D 513^2, side 8, mu 0 -> 2): a seeded
+    training sweep (steps 0.01 +- U(0.002)), U-Net training (4 levels, 32 base
+    channels) on pairs (psi_i, psi_{i+s}), s = 1..3, then the canonical sweep
+    mu = 0, 0.02, ..., 2 twice: secant start, and learned start with the
+    secant as fallback (whichever start has the smaller GL residual)."""
+    import numpy as np
+    import torch
+
+    from paper_1204_5125_amd import continuation, glnk, inputs, predictor
+    torch.cuda.set_device(0)
+    N, side, levels, base = 513, 8.0, 4, 32
+    mesh = glnk.Mesh(2, (N, N), (side, side), mu=0.0)
+    ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
+    common = dict(tol=1e-10, krylov_rtol=1e-10, krylov_max_iter=3000, max_newton=25, max_coarse=64,
+                  poll_every=16)
+
+    def progress(tag):
+        def cb(rec, _):
+            if int(round(rec["mu"] / 0.02)) % 10 == 0 or rec["status"] != 0:
+                log(f"[bench] {tag}: mu {rec['mu']:.4f} newton {rec['newton_steps']} "
+                    f"krylov {sum(rec['krylov_iters'])} status {rec['status']} ({rec['predictor']})")
+        return cb
+
+    mus_train = inputs.sweep_mus(2.0, 0.01, 0.002, seed=0)
+    t0 = time.perf_counter()
+    recs, states = predictor.sweep(mesh, mus_train, ones, precision=glnk.GL_FP64, callback=progress("train sweep"),
+                                   **common)
+    t_sweep = time.perf_counter() - t0
+    log(f"[bench] training sweep: {len(states)} states in {t_sweep:.1f} s")
+    pairs = predictor.make_pairs(mesh, states)
+    net = glnk.UNet(levels, base)
+    net.set_params(predictor.init_params(levels, base, seed=0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = predictor.train(net, mesh, pairs, epochs=args.epochs, batch=4, lr=1e-3, lr_end=5e-5, seed=0,
+                           log=lambda m: log(f"{m} ({time.perf_counter() - t0:.1f} s)"))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    mus = [0.02 * k for k in range(101)]
+    runs = {}
+    for name, prec, learned in [("fp64_secant", glnk.GL_FP64, False), ("fp64_learned", glnk.GL_FP64, True)]:
+        pred = predictor.LearnedPredictor(net, mesh) if learned else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs, _, _ = continuation.continuation_path(mesh, ones, mus, precision=prec, predictor=pred,
+                                                    callback=progress(name), **common)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        runs[name] = {"seconds": dt, "steps": len(recs) - 1,
+                      "newton_steps": sum(r["newton_steps"] for r in recs[1:]),
+                      "krylov_iterations": sum(sum(r["krylov_iters"]) for r in recs[1:]),
+                      "failed": sum(r["status"] != 0 for r in recs), "reached_mu": recs[-1]["mu"]}
+        if pred is not None:
+            runs[name]["starts"] = pred.used
+        log(f"[bench] {name}: {runs[name]}")
+    base_run, best = runs["fp64_secant"], runs["fp64_learned"]
+    out = {
+        "metric": "continuation speedup: learned start (secant fallback) vs secant start",
+        "value": base_run["seconds"] / best["seconds"], "unit": "x", "n_gpus": 1, "steps": 100, "warmup": 0,
+        "ms_per_step": 1e3 * best["seconds"] / max(1, best["steps"]), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (solver) / bf16 (U-Net, f32 accumulation)",
+        "data": "synthetic: continuation of psi = 1 from mu = 0 on a uniform grid; training states from a seeded sweep",
+        "config": {"workload": "2D 513x513 grid, side 8, mu 0 -> 2 in steps of 0.02 (Newton to 1e-10); U-Net 4 levels, "
+                               "32 base channels, BF16 / FP32 accumulation",
+                   "training_states": len(states), "training_pairs": len(pairs), "epochs": args.epochs},
+        "runs": runs, "training": {"sweep_seconds": t_sweep, "train_seconds": t_train,
+                                   "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["jacobian", "batch"], default="jacobian",
-                    help="jacobian: the 1M-node Jacobian solves (headline); batch: batched continuation")
+    ap.add_argument("--workload", choices=["jacobian", "batch", "continuation"], default="jacobian",
+                    help="jacobian: the 1M-node Jacobian solves (headline); batch: batched continuation; "
+                         "continuation: learned vs secant predictor")
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch-max-coarse", type=int, default=64)
     ap.add_argument("--tile-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "glnk_tiles.json"))
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-kernel", type=int, default=2,
+    ap.add_argument("--profile-kernel", type=int, default=8,
                     help="internal kernel id for the roofline (see gl_profile_start)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -198,6 +273,9 @@ def main():
 
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "continuation":
+        bench_continuation(args)
         return
 
     import torch
@@ -225,13 +303,23 @@ def main():
     solves = NEWTON_STEPS * args.steps
     value = solves / t32
 
-    # roofline of the dominant kernel: an identical pass with its launches timed by HIP events
-    log(f"[bench] profiling kernel {args.profile_kernel} ({KERNEL_NAMES.get(args.profile_kernel)})")
-    glnk.gl_profile_start(args.profile_kernel)
-    run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, args.steps)
-    ms, nbytes, launches = glnk.gl_profile_stop()
-    avg_ms = ms / max(1, launches)
-    achieved = (nbytes / max(1, launches)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+    # roofline: an identical pass per kernel class with its launches timed by
+    # HIP events on the stream they run on.  The coarse-level Gauss-Seidel
+    # sweeps take the most GPU time (latency-bound small launches); the
+    # level-0 sweeps move the most bytes.
+    def profile(kid):
+        log(f"[bench] profiling kernel {kid} ({KERNEL_NAMES.get(kid)})")
+        glnk.gl_profile_start(kid)
+        run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, 1)
+        ms, nbytes, launches = glnk.gl_profile_stop()
+        avg_ms = ms / max(1, launches)
+        achieved = (nbytes / max(1, launches)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
+        return {"bound": "hbm", "kernel": KERNEL_NAMES.get(kid), "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": 1e3 * avg_ms,
+                "launches": launches, "bytes_per_launch": nbytes / max(1, launches),
+                "kernel_ms_per_step": ms}
+    roof = profile(args.profile_kernel)
+    roof_l0 = profile(2) if args.profile_kernel != 2 else roof
 
     iters32 = info32[-1]["krylov_iters"]
     iters64 = info64[-1]["krylov_iters"]
@@ -257,11 +345,8 @@ def main():
         "final_gl_residual": final_res32,
         "fp64_precond": {"value": solves / t64, "unit": "solves/s", "ms_per_step": 1e3 * t64 / args.steps,
                          "krylov_iters_per_solve": iters64},
-        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES.get(args.profile_kernel),
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": 1e3 * avg_ms, "launches": launches,
-                     "bytes_per_launch": nbytes / max(1, launches)},
+        "roofline": roof,
+        "roofline_level0": roof_l0,
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, one Newton step)")

@@ -56,6 +56,7 @@ typedef enum { GL_FP64 = 0, GL_FP32 = 1 } gl_precision;
 typedef struct gl_mesh gl_mesh;
 typedef struct gl_precond gl_precond;
 typedef struct gl_batch gl_batch;
+typedef struct gl_unet gl_unet;
 typedef void *gl_stream;
 
 /* --------------------------------------------------------------- mesh --
@@ -278,6 +279,51 @@ gl_status gl_batch_stats(const gl_batch *batch, int64_t *graph_launches, int64_t
 
 void gl_batch_destroy(gl_batch *batch);
 
+/* --------------------------------------------------- learned predictor -- */
+/* A convolutional U-Net that predicts the Newton start psi(mu + dmu) from
+ * psi(mu) on a square 2D grid (a learned alternative to the secant step of
+ * the continuation in Sec. 4).  Input planes (Re psi, Im psi, mu, 50 dmu);
+ * `levels` levels of two 3x3 convolutions + SiLU with base_channels * 2^l
+ * channels, vertex subsampling down, linear vertex interpolation up with
+ * skip concatenation, a 1x1 head to (o_re, o_im);
+ * psi_pred = psi + dmu (o_re + i o_im).  BF16 weights and activations, FP32
+ * accumulation on the matrix cores.  The grid needs 2^(levels-1) k + 1 nodes
+ * per axis.  levels 1..6; base_channels a multiple of 32. */
+gl_status gl_unet_create(int levels, int base_channels, gl_unet **out);
+gl_status gl_unet_num_params(const gl_unet *unet, int64_t *n);
+
+/* Parameters: one FP32 vector (host memory), per convolution the weights
+ * W[c_out][ky][kx][c_in] (ky, kx = 0..2 for the offsets -1..1) then the bias
+ * b[c_out], layers in execution order (encoder levels, decoder levels from
+ * the coarsest, head W[2][c] then b[2]).  set_params also resets the Adam
+ * moments and step count.  Both synchronise the device. */
+gl_status gl_unet_set_params(gl_unet *unet, const float *host_params);
+gl_status gl_unet_get_params(const gl_unet *unet, float *host_params);
+
+/* psi_out = network prediction of psi at mu + dmu (device vectors of the
+ * mesh's n nodes; must not alias).  Stream-ordered. */
+gl_status gl_unet_predict(gl_unet *unet, const gl_mesh *mesh, const void *psi, double mu, double dmu,
+                          void *psi_out, gl_stream stream);
+
+/* Loss of one pair and (host_grad != NULL) the parameter gradient:
+ * L = sum_i d_i |o_i - (t_i - psi_i) / dmu|^2 / sum_i d_i, with the target
+ * already aligned to psi in phase (gl_secant_predict(mesh, psi, target, -1,
+ * out) aligns it).  Synchronous. */
+gl_status gl_unet_loss_grad(gl_unet *unet, const gl_mesh *mesh, const void *psi, double mu, double dmu,
+                            const void *target, double *loss, float *host_grad, gl_stream stream);
+
+typedef struct {
+    double lr, beta1, beta2, eps;
+} gl_adam_opts;
+
+/* One Adam step (Kingma-Ba, bias-corrected) on the mean loss of `count`
+ * aligned pairs; *loss (nullable) receives that mean.  Synchronous. */
+gl_status gl_unet_train_step(gl_unet *unet, const gl_mesh *mesh, int count, const void *const *psi,
+                             const double *mu, const double *dmu, const void *const *target,
+                             const gl_adam_opts *opts, double *loss, gl_stream stream);
+
+void gl_unet_destroy(gl_unet *unet);
+
 /* -------------------------------------------------------- diagnostics -- */
 /* Per-kernel timing for roofline reports.  Between gl_profile_start(id) and
  * gl_profile_stop, every launch of the selected internal kernel is bracketed
@@ -286,7 +332,8 @@ void gl_batch_destroy(gl_batch *batch);
  * (each array the kernel must touch counted once) and the launch count.
  * id: 1 MINRES Jacobian apply (+ fused dot), 2 level-0 Gauss-Seidel colour
  * sweep, 3 level-0 residual, 4 level-0 restriction / prolongation, 5 MINRES
- * v update, 6 MINRES w/x update, 7 GL residual.  Not thread-safe; for
+ * v update, 6 MINRES w/x update, 7 GL residual, 8 Gauss-Seidel colour
+ * sweep of a level >= 1.  Not thread-safe; for
  * benchmarking only (the events add a small gap between kernels). */
 gl_status gl_profile_start(int kernel_id);
 gl_status gl_profile_stop(double *ms_total, double *bytes_total, int64_t *launches);

@@ -268,7 +268,7 @@ struct Profiler {
 Profiler &profiler();
 enum ProfId {
     PROF_MINRES_JAPPLY = 1, PROF_L0_SWEEP = 2, PROF_L0_RESIDUAL = 3, PROF_L0_TRANSFER = 4,
-    PROF_VUPDATE = 5, PROF_WX = 6, PROF_GL = 7
+    PROF_VUPDATE = 5, PROF_WX = 6, PROF_GL = 7, PROF_COARSE_SWEEP = 8
 };
 
 template <class F>

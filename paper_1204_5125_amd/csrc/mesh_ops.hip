@@ -423,7 +423,7 @@ gl_status gl_secant_predict(const gl_mesh *mesh, const void *psi_m, const void *
 gl_status gl_profile_start(int kernel_id)
 {
     return guarded([&] {
-        if (kernel_id < 1 || kernel_id > 7) fail(GL_ERR_INVALID_ARGUMENT, "gl_profile_start: kernel id");
+        if (kernel_id < 1 || kernel_id > 8) fail(GL_ERR_INVALID_ARGUMENT, "gl_profile_start: kernel id");
         Profiler &p = profiler();
         p.kernel = kernel_id;
         p.used = 0;

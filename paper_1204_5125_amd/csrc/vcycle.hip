@@ -598,9 +598,14 @@ static void csr_sgs(Level &Lv, int shift, const int *gate, const Launch &L)
         const int W = Lv.ewidth[c];
         const int lpr = shifted(W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16, shift);
         const int nb = blocks_for((int64_t)cnt * lpr);
-        GLK_LPR_SWITCH(lpr, {
-            L.run(nb, EllSgs<T, LPR>{Lv.eci.get() + Lv.eoff[c], evals<T>(Lv) + Lv.eoff[c], W, dgn<T>(Lv),
-                                     Lv.coff[c], cnt, vec_b<T>(Lv), vec_x<T>(Lv), gate});
+        // algorithmic bytes: the colour's padded rows (index + value), one
+        // x value per stored entry, b and the diagonal of each row, x written
+        const double bytes = (double)cnt * W * (4.0 + 2.0 * sizeof(C<T>)) + cnt * (2.0 * sizeof(C<T>) + sizeof(T));
+        prof_launch(PROF_COARSE_SWEEP, bytes, L, [&] {
+            GLK_LPR_SWITCH(lpr, {
+                L.run(nb, EllSgs<T, LPR>{Lv.eci.get() + Lv.eoff[c], evals<T>(Lv) + Lv.eoff[c], W, dgn<T>(Lv),
+                                         Lv.coff[c], cnt, vec_b<T>(Lv), vec_x<T>(Lv), gate});
+            });
         });
     }
 }

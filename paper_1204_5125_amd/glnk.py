@@ -30,9 +30,12 @@ EXPORTED_SYMBOLS = [
     "gl_precond_info", "gl_precond_export", "gl_precond_destroy", "gl_jacobian_solve",
     "gl_newton_solve", "gl_precond_set_tiles", "gl_precond_get_tiles", "gl_batch_create",
     "gl_batch_newton_solve", "gl_batch_set_tiles", "gl_batch_stats", "gl_batch_destroy",
+    "gl_unet_create", "gl_unet_num_params", "gl_unet_set_params", "gl_unet_get_params", "gl_unet_predict",
+    "gl_unet_loss_grad", "gl_unet_train_step", "gl_unet_destroy",
     "gl_profile_start", "gl_profile_stop", "gl_status_string", "gl_last_error",
 ]
-_VOID = ("gl_mesh_destroy", "gl_precond_destroy", "gl_batch_destroy", "gl_status_string", "gl_last_error")
+_VOID = ("gl_mesh_destroy", "gl_precond_destroy", "gl_batch_destroy", "gl_unet_destroy", "gl_status_string",
+         "gl_last_error")
 
 
 class GlnkError(RuntimeError):
@@ -69,6 +72,10 @@ class NewtonOpts(C.Structure):
 
 class Tiles(C.Structure):
     _fields_ = [("lane_shift", C.c_int), ("bottom_rows", C.c_int)]
+
+
+class AdamOpts(C.Structure):
+    _fields_ = [("lr", C.c_double), ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double)]
 
 
 class NewtonInfo(C.Structure):
@@ -114,6 +121,16 @@ def lib():
     L.gl_batch_stats.argtypes = [vp, P(C.c_int64), P(C.c_int64), P(C.c_int), P(C.c_double)]
     L.gl_batch_destroy.argtypes = [vp]
     L.gl_batch_destroy.restype = None
+    L.gl_unet_create.argtypes = [C.c_int, C.c_int, P(vp)]
+    L.gl_unet_num_params.argtypes = [vp, P(C.c_int64)]
+    L.gl_unet_set_params.argtypes = [vp, vp]
+    L.gl_unet_get_params.argtypes = [vp, vp]
+    L.gl_unet_predict.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp]
+    L.gl_unet_loss_grad.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, P(C.c_double), vp, vp]
+    L.gl_unet_train_step.argtypes = [vp, vp, C.c_int, P(vp), P(C.c_double), P(C.c_double), P(vp), P(AdamOpts),
+                                     P(C.c_double), vp]
+    L.gl_unet_destroy.argtypes = [vp]
+    L.gl_unet_destroy.restype = None
     L.gl_profile_start.argtypes = [C.c_int]
     L.gl_profile_stop.argtypes = [P(C.c_double), P(C.c_double), P(C.c_int64)]
     L.gl_status_string.argtypes = [st]
@@ -419,6 +436,84 @@ class Batch:
     def close(self):
         if self._h and _lib is not None:
             _lib.gl_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: ctypes may be gone
+            pass
+
+
+def unet_layer_shapes(levels, base, in_ch=4, out_ch=2):
+    """(c_in, c_out, k) of the library's U-Net layers, in parameter order."""
+    shapes, c = [], in_ch
+    for l in range(levels):
+        shapes += [(c, base << l, 3), (base << l, base << l, 3)]
+        c = base << l
+    for l in range(levels - 2, -1, -1):
+        shapes += [(c + (base << l), base << l, 3), (base << l, base << l, 3)]
+        c = base << l
+    shapes.append((c, out_ch, 1))
+    return shapes
+
+
+class UNet:
+    """gl_unet: the learned continuation predictor."""
+
+    def __init__(self, levels=4, base=32):
+        h = C.c_void_p()
+        _check(lib().gl_unet_create(levels, base, C.byref(h)), "gl_unet_create")
+        self._h = h
+        self.levels, self.base = levels, base
+        n = C.c_int64()
+        _check(lib().gl_unet_num_params(h, C.byref(n)), "gl_unet_num_params")
+        self.n_params = n.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        if theta.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters")
+        _check(lib().gl_unet_set_params(self._h, theta.ctypes.data_as(C.c_void_p)), "gl_unet_set_params")
+
+    def get_params(self):
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().gl_unet_get_params(self._h, out.ctypes.data_as(C.c_void_p)), "gl_unet_get_params")
+        return out
+
+    def predict(self, mesh, psi, mu, dmu, out, stream=None):
+        _check(lib().gl_unet_predict(self._h, mesh.handle, _vec(psi, mesh.n, "psi"), mu, dmu,
+                                     _vec(out, mesh.n, "out"), _stream(stream)), "gl_unet_predict")
+
+    def loss_grad(self, mesh, psi, mu, dmu, target, want_grad=True, stream=None):
+        loss = C.c_double()
+        g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
+        _check(lib().gl_unet_loss_grad(self._h, mesh.handle, _vec(psi, mesh.n, "psi"), mu, dmu,
+                                       _vec(target, mesh.n, "target"), C.byref(loss),
+                                       g.ctypes.data_as(C.c_void_p) if g is not None else None,
+                                       _stream(stream)), "gl_unet_loss_grad")
+        return loss.value, g
+
+    def train_step(self, mesh, psis, mus, dmus, targets, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   stream=None):
+        k = len(psis)
+        pp = (C.c_void_p * k)(*[_vec(p, mesh.n, "psi") for p in psis])
+        tt = (C.c_void_p * k)(*[_vec(t, mesh.n, "target") for t in targets])
+        mm = (C.c_double * k)(*mus)
+        dd = (C.c_double * k)(*dmus)
+        loss = C.c_double()
+        _check(lib().gl_unet_train_step(self._h, mesh.handle, k, pp, mm, dd, tt,
+                                        C.byref(AdamOpts(lr, beta1, beta2, eps)), C.byref(loss),
+                                        _stream(stream)), "gl_unet_train_step")
+        return loss.value
+
+    def close(self):
+        if self._h and _lib is not None:
+            _lib.gl_unet_destroy(self._h)
         self._h = None
 
     def __del__(self):

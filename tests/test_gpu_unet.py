@@ -1,0 +1,125 @@
+"""The HIP U-Net (BF16 weights/activations, FP32 accumulation) against the
+FP64 oracle: forward output, loss, parameter gradient, Adam update, and a
+short training run.  Tolerances follow BF16 storage (8 significant bits):
+outputs and gradients within a few per cent in the L2 norm."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import continuation as oc
+from oracle import unet as U
+from paper_1204_5125_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LEVELS, BASE, N, SIDE = 3, 32, 17, 4.0
+
+
+@pytest.fixture(scope="module")
+def glnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_5125_amd import glnk as g
+    g.lib()
+    return g
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def pair(seed, mu=0.6):
+    mo = oracle.Mesh(2, (N, N), (SIDE, SIDE), mu=mu)
+    psi = inputs.random_phase_state(mo.n, seed=seed)
+    tgt = psi * (1.0 + 0.03 * inputs.random_complex(mo.n, seed=seed + 100)) * np.exp(0.4j)
+    tgt = oc.secant_predict(mo, psi, tgt, -1.0)  # aligned to psi
+    return mo, psi, tgt
+
+
+def params(glnk, seed=7):
+    shapes = glnk.unet_layer_shapes(LEVELS, BASE)
+    assert shapes == U.layer_specs(LEVELS, BASE)
+    return inputs.unet_init(shapes, seed=seed, head_scale=1.0)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_forward_matches_oracle(glnk):
+    mo, psi, _ = pair(1)
+    theta = params(glnk)
+    net = glnk.UNet(LEVELS, BASE)
+    assert net.n_params == U.num_params(U.layer_specs(LEVELS, BASE))
+    net.set_params(theta)
+    assert np.array_equal(net.get_params(), theta)
+    mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
+    out = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    net.predict(mg, dev(psi), 0.6, 0.02, out)
+    og = (host(out) - psi) / 0.02
+    oo = U.predict(theta.astype(np.float64), U.layer_specs(LEVELS, BASE), LEVELS, psi, 0.6, 0.02, N)
+    oo = (oo - psi) / 0.02
+    assert rel(og, oo) < 3e-2
+
+
+def test_loss_and_gradient_match_oracle(glnk):
+    mo, psi, tgt = pair(2)
+    theta = params(glnk, seed=8)
+    specs = U.layer_specs(LEVELS, BASE)
+    net = glnk.UNet(LEVELS, BASE)
+    net.set_params(theta)
+    mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
+    Lg, gg = net.loss_grad(mg, dev(psi), 0.6, 0.02, dev(tgt))
+    Lo, go = U.loss_and_grad(theta.astype(np.float64), specs, LEVELS, psi, 0.6, 0.02, tgt,
+                             U.volumes(N, SIDE), N)
+    assert Lg == pytest.approx(Lo, rel=3e-2)
+    cos = gg @ go / (np.linalg.norm(gg) * np.linalg.norm(go))
+    assert cos > 0.995 and rel(gg, go) < 0.1
+    # layer by layer (weights and bias of each convolution)
+    o = 0
+    for ci, co, k in specs:
+        nw = co * k * k * ci
+        assert rel(gg[o:o + nw], go[o:o + nw]) < 0.15
+        o += nw + co
+
+
+def test_adam_step_matches_oracle_update(glnk):
+    mo, psi, tgt = pair(3)
+    theta = params(glnk, seed=9)
+    net = glnk.UNet(LEVELS, BASE)
+    net.set_params(theta)
+    mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
+    _, g = net.loss_grad(mg, dev(psi), 0.6, 0.02, dev(tgt))
+    net.train_step(mg, [dev(psi)], [0.6], [0.02], [dev(tgt)], lr=1e-3)
+    th1 = net.get_params()
+    m, v = np.zeros(theta.size), np.zeros(theta.size)
+    want = U.adam_step(theta.astype(np.float64), m, v, g.astype(np.float64), 1, lr=1e-3)
+    assert np.abs(th1 - want).max() < 1e-3 * 1e-3
+
+
+def test_training_reduces_the_loss(glnk):
+    """A learnable target (the derivative (0.5 - 0.3i) psi): 60 Adam steps on
+    four pairs halve the loss."""
+    def learnable(seed, mu):
+        mo = oracle.Mesh(2, (N, N), (SIDE, SIDE), mu=mu)
+        psi = inputs.random_phase_state(mo.n, seed=seed)
+        return mo, psi, psi + 0.02 * (0.5 - 0.3j) * psi
+
+    pairs = [learnable(10 + k, 0.5 + 0.1 * k) for k in range(4)]
+    net = glnk.UNet(LEVELS, BASE)
+    net.set_params(params(glnk, seed=11) * 0.5)
+    mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
+    ps = [dev(p) for _, p, _ in pairs]
+    ts = [dev(t) for _, _, t in pairs]
+    mus = [0.5 + 0.1 * k for k in range(4)]
+    first = net.train_step(mg, ps, mus, [0.02] * 4, ts, lr=2e-3)
+    for _ in range(60):
+        last = net.train_step(mg, ps, mus, [0.02] * 4, ts, lr=2e-3)
+    assert last < 0.5 * first
