@@ -9,20 +9,23 @@ pseudo-arclength).  This module states the network in plain numpy, in the
 order the computation is defined, so that the GPU kernels can be checked
 value by value:
 
-  input channels  x = (Re psi, Im psi, mu, 50 dmu) on an N x N vertex grid
-                  (N = 2^(levels-1) m + 1);
+  base start      psi_b: the secant step psi + r (psi - e^{i chi} psi_prev)
+                  of the continuation (Sec. 4), or psi itself without history;
+  input channels  x = (Re psi, Im psi, Re s, Im s, mu, 50 dmu) with the base
+                  step's slope s = (psi_b - psi) / dmu, on an N x N vertex
+                  grid (N = 2^(levels-1) m + 1);
   encoder level l two 3x3 convolutions (zero padding), each followed by
                   SiLU(z) = z / (1 + exp(-z)); channels base * 2^l; between
                   levels vertex subsampling (keep every other node);
   decoder         linear vertex interpolation to the finer grid, channel
                   concatenation [upsampled, skip], two 3x3 conv + SiLU;
   head            1x1 convolution to 2 channels o = (o_re, o_im);
-  prediction      psi_pred = psi + dmu (o_re + i o_im).
+  prediction      psi_pred = psi_b + dmu (o_re + i o_im): the network corrects
+                  the base step (a zero network is the secant predictor).
 
-Loss of one pair (psi, target) at (mu, dmu), the target already phase-aligned
-to psi: L = sum_i d_i |o_i - (t_i - psi_i) / dmu|^2 / sum_i d_i, i.e. the
-D-weighted mean squared error of the predicted derivative, which equals
-||D^(1/2) (psi_pred - t)||^2 / (dmu^2 sum d).
+Loss of one sample (psi, psi_b, target) at (mu, dmu), the target already
+phase-aligned to psi: L = sum_i d_i |o_i - (t_i - psi_b,i) / dmu|^2 / sum_i d_i,
+i.e. ||D^(1/2) (psi_pred - t)||^2 / (dmu^2 sum d).
 
 Parameters: one flat vector; per layer the weights W[co, ky, kx, ci]
 (row-major, ky/kx = 0..2 for offsets -1..1) followed by the bias b[co]; the
@@ -32,7 +35,7 @@ corrected moments.
 import numpy as np
 
 
-def layer_specs(levels, base, in_ch=4, out_ch=2):
+def layer_specs(levels, base, in_ch=6, out_ch=2):
     """(c_in, c_out, kernel) of every convolution in execution order."""
     specs = []
     ch = [base * 2 ** l for l in range(levels)]
@@ -148,9 +151,10 @@ def up_backward(dy):
     return dx
 
 
-def input_planes(psi, mu, dmu, N):
+def input_planes(psi, psi_b, mu, dmu, N):
     p = psi.reshape(N, N)
-    return np.stack([p.real, p.imag, np.full((N, N), mu), np.full((N, N), 50.0 * dmu)])
+    sl = ((psi_b - psi) / dmu).reshape(N, N)
+    return np.stack([p.real, p.imag, sl.real, sl.imag, np.full((N, N), mu), np.full((N, N), 50.0 * dmu)])
 
 
 def forward(theta, specs, levels, x, keep=False):
@@ -218,9 +222,9 @@ def backward(theta, specs, levels, tape, do):
     return np.concatenate([np.concatenate([g[0].ravel(), g[1].ravel()]) for g in grads])
 
 
-def loss_and_grad_output(o, psi, target, dmu, vol, N):
-    """Loss of one aligned pair and dL/do (2, N, N)."""
-    want = (target - psi).reshape(N, N) / dmu
+def loss_and_grad_output(o, psi_b, target, dmu, vol, N):
+    """Loss of one aligned sample and dL/do (2, N, N)."""
+    want = (target - psi_b).reshape(N, N) / dmu
     r = o[0] + 1j * o[1] - want
     w = vol.reshape(N, N)
     sw = w.sum()
@@ -229,16 +233,16 @@ def loss_and_grad_output(o, psi, target, dmu, vol, N):
     return L, do
 
 
-def predict(theta, specs, levels, psi, mu, dmu, N):
-    """psi_pred = psi + dmu (o_re + i o_im)."""
-    o = forward(theta, specs, levels, input_planes(psi, mu, dmu, N))
-    return psi + dmu * (o[0] + 1j * o[1]).ravel()
+def predict(theta, specs, levels, psi, psi_b, mu, dmu, N):
+    """psi_pred = psi_b + dmu (o_re + i o_im)."""
+    o = forward(theta, specs, levels, input_planes(psi, psi_b, mu, dmu, N))
+    return psi_b + dmu * (o[0] + 1j * o[1]).ravel()
 
 
-def loss_and_grad(theta, specs, levels, psi, mu, dmu, target, vol, N):
-    """Loss of one pair and the flat parameter gradient."""
-    o, tape = forward(theta, specs, levels, input_planes(psi, mu, dmu, N), keep=True)
-    L, do = loss_and_grad_output(o, psi, target, dmu, vol, N)
+def loss_and_grad(theta, specs, levels, psi, psi_b, mu, dmu, target, vol, N):
+    """Loss of one sample and the flat parameter gradient."""
+    o, tape = forward(theta, specs, levels, input_planes(psi, psi_b, mu, dmu, N), keep=True)
+    L, do = loss_and_grad_output(o, psi_b, target, dmu, vol, N)
     return L, backward(theta, specs, levels, tape, do)
 
 

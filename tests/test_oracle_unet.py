@@ -11,9 +11,9 @@ def rng(seed):
 
 
 def test_parameter_count_of_the_4_level_32_channel_net():
-    # 9 (4*32 + 32*32 + 32*64 + 64^2 + 64*128 + 128^2 + 128*256 + 256^2
+    # 9 (6*32 + 32*32 + 32*64 + 64^2 + 64*128 + 128^2 + 128*256 + 256^2
     #    + 384*128 + 128^2 + 192*64 + 64^2 + 96*32 + 32^2) + 32*2 + biases
-    w = 9 * (4 * 32 + 32 * 32 + 32 * 64 + 64 * 64 + 64 * 128 + 128 * 128 + 128 * 256 + 256 * 256
+    w = 9 * (6 * 32 + 32 * 32 + 32 * 64 + 64 * 64 + 64 * 128 + 128 * 128 + 128 * 256 + 256 * 256
              + 384 * 128 + 128 * 128 + 192 * 64 + 64 * 64 + 96 * 32 + 32 * 32) + 32 * 2
     b = 32 + 32 + 64 + 64 + 128 + 128 + 256 + 256 + 128 + 128 + 64 + 64 + 32 + 32 + 2
     assert U.num_params(U.layer_specs(4, 32)) == w + b
@@ -62,33 +62,35 @@ def test_gradient_matches_finite_differences(levels, base, N):
     specs = U.layer_specs(levels, base)
     theta = 0.3 * r.standard_normal(U.num_params(specs))
     psi = r.standard_normal(N * N) + 1j * r.standard_normal(N * N)
+    psb = psi + 0.02 * (r.standard_normal(N * N) + 1j * r.standard_normal(N * N))
     tgt = psi + 0.02 * (r.standard_normal(N * N) + 1j * r.standard_normal(N * N))
     vol = U.volumes(N, 4.0)
-    L, g = U.loss_and_grad(theta, specs, levels, psi, 0.7, 0.02, tgt, vol, N)
+    L, g = U.loss_and_grad(theta, specs, levels, psi, psb, 0.7, 0.02, tgt, vol, N)
     idx = r.choice(theta.size, 60, replace=False)
     eps = 1e-6
     for k in idx:
         tp, tm = theta.copy(), theta.copy()
         tp[k] += eps
         tm[k] -= eps
-        Lp, _ = U.loss_and_grad(tp, specs, levels, psi, 0.7, 0.02, tgt, vol, N)
-        Lm, _ = U.loss_and_grad(tm, specs, levels, psi, 0.7, 0.02, tgt, vol, N)
+        Lp, _ = U.loss_and_grad(tp, specs, levels, psi, psb, 0.7, 0.02, tgt, vol, N)
+        Lm, _ = U.loss_and_grad(tm, specs, levels, psi, psb, 0.7, 0.02, tgt, vol, N)
         fd = (Lp - Lm) / (2 * eps)
         assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-8 * max(1.0, abs(L)))
 
 
-def test_loss_zero_at_exact_derivative_and_prediction_form():
+def test_loss_zero_at_exact_correction_and_prediction_form():
     N = 5
     r = rng(3)
     psi = r.standard_normal(N * N) + 1j * r.standard_normal(N * N)
-    tgt = psi + 0.02 * (1 + 2j)
+    psb = psi + 0.02 * (0.5 - 1j)
+    tgt = psb + 0.02 * (1 + 2j)
     o = np.stack([np.full((N, N), 1.0), np.full((N, N), 2.0)])
-    L, do = U.loss_and_grad_output(o, psi, tgt, 0.02, U.volumes(N, 2.0), N)
+    L, do = U.loss_and_grad_output(o, psb, tgt, 0.02, U.volumes(N, 2.0), N)
     assert L == pytest.approx(0.0, abs=1e-20) and np.abs(do).max() < 1e-12
     specs = U.layer_specs(2, 4)
     theta = np.zeros(U.num_params(specs))
-    # a zero network predicts no change: the constant predictor
-    assert np.array_equal(U.predict(theta, specs, 2, psi, 0.3, 0.02, N), psi)
+    # a zero network returns the base step (the secant predictor)
+    assert np.array_equal(U.predict(theta, specs, 2, psi, psb, 0.3, 0.02, N), psb)
 
 
 def test_adam_first_step_and_bias_correction():
