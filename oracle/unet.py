@@ -24,8 +24,10 @@ value by value:
                   the base step (a zero network is the secant predictor).
 
 Loss of one sample (psi, psi_b, target) at (mu, dmu), the target already
-phase-aligned to psi: L = sum_i d_i |o_i - (t_i - psi_b,i) / dmu|^2 / sum_i d_i,
-i.e. ||D^(1/2) (psi_pred - t)||^2 / (dmu^2 sum d).
+phase-aligned to psi, with w = (t - psi_b) / dmu the correction to learn:
+L = sum_i d_i |o_i - w_i|^2 / sum_i d_i |w_i|^2 = ||D^(1/2)(psi_pred - t)||^2 /
+||D^(1/2)(psi_b - t)||^2, the squared error relative to that of the base
+start (so every sample weighs the same; 1 for a zero network).
 
 Parameters: one flat vector; per layer the weights W[co, ky, kx, ci]
 (row-major, ky/kx = 0..2 for offsets -1..1) followed by the bias b[co]; the
@@ -227,7 +229,7 @@ def loss_and_grad_output(o, psi_b, target, dmu, vol, N):
     want = (target - psi_b).reshape(N, N) / dmu
     r = o[0] + 1j * o[1] - want
     w = vol.reshape(N, N)
-    sw = w.sum()
+    sw = (w * np.abs(want) ** 2).sum()
     L = float((w * np.abs(r) ** 2).sum() / sw)
     do = np.stack([2.0 * w * r.real / sw, 2.0 * w * r.imag / sw])
     return L, do
