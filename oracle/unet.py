@@ -25,9 +25,10 @@ value by value:
 
 Loss of one sample (psi, psi_b, target) at (mu, dmu), the target already
 phase-aligned to psi, with w = (t - psi_b) / dmu the correction to learn:
-L = sum_i d_i |o_i - w_i|^2 / sum_i d_i |w_i|^2 = ||D^(1/2)(psi_pred - t)||^2 /
-||D^(1/2)(psi_b - t)||^2, the squared error relative to that of the base
-start (so every sample weighs the same; 1 for a zero network).
+L = sum_i d_i |o_i - w_i|^2 / (sum_i d_i |w_i|^2 + EPS sum_i d_i), i.e.
+||D^(1/2)(psi_pred - t)||^2 relative to ||D^(1/2)(psi_b - t)||^2 (so every
+sample weighs about the same; just below 1 for a zero network), the floor EPS
+keeping samples whose base start is already exact from dominating.
 
 Parameters: one flat vector; per layer the weights W[co, ky, kx, ci]
 (row-major, ky/kx = 0..2 for offsets -1..1) followed by the bias b[co]; the
@@ -224,12 +225,15 @@ def backward(theta, specs, levels, tape, do):
     return np.concatenate([np.concatenate([g[0].ravel(), g[1].ravel()]) for g in grads])
 
 
+EPS = 1e-4
+
+
 def loss_and_grad_output(o, psi_b, target, dmu, vol, N):
     """Loss of one aligned sample and dL/do (2, N, N)."""
     want = (target - psi_b).reshape(N, N) / dmu
     r = o[0] + 1j * o[1] - want
     w = vol.reshape(N, N)
-    sw = (w * np.abs(want) ** 2).sum()
+    sw = (w * np.abs(want) ** 2).sum() + EPS * w.sum()
     L = float((w * np.abs(r) ** 2).sum() / sw)
     do = np.stack([2.0 * w * r.real / sw, 2.0 * w * r.imag / sw])
     return L, do
