@@ -280,13 +280,15 @@ gl_status gl_batch_stats(const gl_batch *batch, int64_t *graph_launches, int64_t
 void gl_batch_destroy(gl_batch *batch);
 
 /* --------------------------------------------------- learned predictor -- */
-/* A convolutional U-Net that predicts the Newton start psi(mu + dmu) from
- * psi(mu) on a square 2D grid (a learned alternative to the secant step of
- * the continuation in Sec. 4).  Input planes (Re psi, Im psi, mu, 50 dmu);
- * `levels` levels of two 3x3 convolutions + SiLU with base_channels * 2^l
- * channels, vertex subsampling down, linear vertex interpolation up with
- * skip concatenation, a 1x1 head to (o_re, o_im);
- * psi_pred = psi + dmu (o_re + i o_im).  BF16 weights and activations, FP32
+/* A convolutional U-Net that corrects the continuation's start for
+ * psi(mu + dmu) on a square 2D grid (a learned refinement of the secant step
+ * of the continuation in Sec. 4).  psi_base is the base start (the secant
+ * step, or psi itself without history); with s = (psi_base - psi) / dmu the
+ * input planes are (Re psi, Im psi, Re s, Im s, mu, 50 dmu); `levels` levels
+ * of two 3x3 convolutions + SiLU with base_channels * 2^l channels, vertex
+ * subsampling down, linear vertex interpolation up with skip concatenation,
+ * a 1x1 head to (o_re, o_im); psi_pred = psi_base + dmu (o_re + i o_im), so a
+ * zero network is the base start.  BF16 weights and activations, FP32
  * accumulation on the matrix cores.  The grid needs 2^(levels-1) k + 1 nodes
  * per axis.  levels 1..6; base_channels a multiple of 32. */
 gl_status gl_unet_create(int levels, int base_channels, gl_unet **out);
@@ -301,26 +303,30 @@ gl_status gl_unet_set_params(gl_unet *unet, const float *host_params);
 gl_status gl_unet_get_params(const gl_unet *unet, float *host_params);
 
 /* psi_out = network prediction of psi at mu + dmu (device vectors of the
- * mesh's n nodes; must not alias).  Stream-ordered. */
-gl_status gl_unet_predict(gl_unet *unet, const gl_mesh *mesh, const void *psi, double mu, double dmu,
-                          void *psi_out, gl_stream stream);
+ * mesh's n nodes; psi_out must not alias an input; dmu != 0).
+ * Stream-ordered. */
+gl_status gl_unet_predict(gl_unet *unet, const gl_mesh *mesh, const void *psi, const void *psi_base, double mu,
+                          double dmu, void *psi_out, gl_stream stream);
 
-/* Loss of one pair and (host_grad != NULL) the parameter gradient:
- * L = sum_i d_i |o_i - (t_i - psi_i) / dmu|^2 / sum_i d_i, with the target
- * already aligned to psi in phase (gl_secant_predict(mesh, psi, target, -1,
- * out) aligns it).  Synchronous. */
-gl_status gl_unet_loss_grad(gl_unet *unet, const gl_mesh *mesh, const void *psi, double mu, double dmu,
-                            const void *target, double *loss, float *host_grad, gl_stream stream);
+/* Loss of one sample and (host_grad != NULL) the parameter gradient:
+ * with w = (t - psi_base) / dmu,
+ * L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + 1e-4) (the squared error
+ * of the prediction relative to that of the base start, floored),
+ * the target already aligned to psi in phase (gl_secant_predict(mesh, psi,
+ * target, -1, out) aligns it).  Synchronous. */
+gl_status gl_unet_loss_grad(gl_unet *unet, const gl_mesh *mesh, const void *psi, const void *psi_base, double mu,
+                            double dmu, const void *target, double *loss, float *host_grad, gl_stream stream);
 
 typedef struct {
     double lr, beta1, beta2, eps;
 } gl_adam_opts;
 
 /* One Adam step (Kingma-Ba, bias-corrected) on the mean loss of `count`
- * aligned pairs; *loss (nullable) receives that mean.  Synchronous. */
+ * aligned samples; *loss (nullable) receives that mean.  Synchronous. */
 gl_status gl_unet_train_step(gl_unet *unet, const gl_mesh *mesh, int count, const void *const *psi,
-                             const double *mu, const double *dmu, const void *const *target,
-                             const gl_adam_opts *opts, double *loss, gl_stream stream);
+                             const void *const *psi_base, const double *mu, const double *dmu,
+                             const void *const *target, const gl_adam_opts *opts, double *loss,
+                             gl_stream stream);
 
 void gl_unet_destroy(gl_unet *unet);
 

@@ -70,11 +70,17 @@ struct BottomLevel {
     const int *rrp, *rci;
     const C<T> *rv;
     C<T> *b, *x, *r;
+    // the operator once more as per-colour padded blocks (ELL): row r of
+    // colour c holds ewidth[c] entries at eoff[c] + (r - coff[c]) ewidth[c]
+    const int *eci;
+    const C<T> *ev;
+    int ewidth[kMaxColors], eoff[kMaxColors];
 };
 
 template <class T>
 struct BottomDesc {
     int first, last;  // levels first .. last (last = coarsest)
+    int lds_level;    // level whose x lives in LDS (-1: none)
     const C<T> *cinv; // inverse of the coarsest operator (dense, row-major)
     BottomLevel<T> L[kMaxLevels];
 };
@@ -195,6 +201,7 @@ struct gl_precond {
     glk::DevBuf<double2> cyc_r;    // k > 1 cycles: level-0 residual
     glk::DevBuf<double2> vin;      // gl_precond_apply: D r
     glk::DevBuf<char> bdesc64, bdesc32;  // BottomDesc<double>, BottomDesc<float>
+    int lds64 = 0, lds32 = 0;      // dynamic LDS bytes of the bottom kernel
 };
 
 namespace glk {

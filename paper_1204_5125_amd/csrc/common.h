@@ -263,6 +263,7 @@ struct Profiler {
     int kernel = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     size_t used = 0;
+    int64_t launches = 0;
     double bytes = 0.0;
 };
 Profiler &profiler();
@@ -271,8 +272,10 @@ enum ProfId {
     PROF_VUPDATE = 5, PROF_WX = 6, PROF_GL = 7, PROF_COARSE_SWEEP = 8
 };
 
+// count: kernel launches inside the bracket (consecutive launches of one
+// class can share one event pair, so that the bracket adds no gaps between them)
 template <class F>
-void prof_launch(int id, double bytes, hipStream_t s, F &&launch)
+void prof_launch(int id, double bytes, hipStream_t s, F &&launch, int count = 1)
 {
     Profiler &p = profiler();
     if (p.kernel != id) {
@@ -290,6 +293,7 @@ void prof_launch(int id, double bytes, hipStream_t s, F &&launch)
     launch();
     GLK_HIP(hipEventRecord(e.second, s));
     p.bytes += bytes;
+    p.launches += count;
 }
 
 // number of grid edges (axis-neighbour pairs)

@@ -620,7 +620,9 @@ static bool same_shape(const std::vector<Step> &a, const std::vector<Step> &b)
 {
     if (a.size() != b.size()) return false;
     for (size_t p = 0; p < a.size(); ++p)
-        if (a[p].many != b[p].many || a[p].nbx != b[p].nbx || a[p].args.size() != b[p].args.size()) return false;
+        if (a[p].many != b[p].many || a[p].nbx != b[p].nbx || a[p].lds != b[p].lds ||
+            a[p].args.size() != b[p].args.size())
+            return false;
     return true;
 }
 
@@ -644,7 +646,8 @@ static Zip zip_records(const std::vector<std::vector<Step>> &recs, std::vector<u
 
 static void launch_zip(const Zip &z, const unsigned char *dev, hipStream_t s)
 {
-    for (size_t p = 0; p < z.steps.size(); ++p) z.steps[p].many(dev + z.off[p], z.steps[p].nbx, z.count, s);
+    for (size_t p = 0; p < z.steps.size(); ++p)
+        z.steps[p].many(dev + z.off[p], z.steps[p].nbx, z.count, z.steps[p].lds, s);
     GLK_CHECK_LAUNCH();
 }
 

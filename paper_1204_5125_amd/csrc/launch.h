@@ -32,16 +32,17 @@ __global__ __launch_bounds__(BS) void k_many(const A *__restrict__ a)
 
 // one recorded dispatch
 struct Step {
-    void (*many)(const void *dev_args, int nbx, int count, hipStream_t s);
+    void (*many)(const void *dev_args, int nbx, int count, int lds, hipStream_t s);
     int nbx;
     int bs;
+    int lds;  // dynamic LDS bytes
     std::vector<unsigned char> args;
 };
 
 template <class A, int BS>
-void launch_many(const void *dev_args, int nbx, int count, hipStream_t s)
+void launch_many(const void *dev_args, int nbx, int count, int lds, hipStream_t s)
 {
-    k_many<A, BS><<<dim3(nbx, count), BS, 0, s>>>(static_cast<const A *>(dev_args));
+    k_many<A, BS><<<dim3(nbx, count), BS, lds, s>>>(static_cast<const A *>(dev_args));
 }
 
 struct Launch {
@@ -49,7 +50,7 @@ struct Launch {
     std::vector<Step> *rec = nullptr;  // non-null: record instead of launching
 
     template <class A, int BS = kBlock>
-    void run(int nbx, const A &a) const
+    void run(int nbx, const A &a, int lds = 0) const
     {
         if (nbx <= 0) return;
         if (rec) {
@@ -57,12 +58,13 @@ struct Launch {
             st.many = &launch_many<A, BS>;
             st.nbx = nbx;
             st.bs = BS;
+            st.lds = lds;
             st.args.resize(sizeof(A));
             std::memcpy(st.args.data(), &a, sizeof(A));
             rec->push_back(std::move(st));
             return;
         }
-        k_one<A, BS><<<nbx, BS, 0, s>>>(a);
+        k_one<A, BS><<<nbx, BS, lds, s>>>(a);
         GLK_CHECK_LAUNCH();
     }
 };
@@ -70,13 +72,13 @@ struct Launch {
 // Event-bracketed launch of one selected kernel class (profiling); recording
 // passes straight through.
 template <class F>
-void prof_launch(int id, double bytes, const Launch &L, F &&launch)
+void prof_launch(int id, double bytes, const Launch &L, F &&launch, int count = 1)
 {
     if (L.rec) {
         launch();
         return;
     }
-    prof_launch(id, bytes, L.s, launch);
+    prof_launch(id, bytes, L.s, launch, count);
 }
 
 }  // namespace glk

@@ -427,6 +427,7 @@ gl_status gl_profile_start(int kernel_id)
         Profiler &p = profiler();
         p.kernel = kernel_id;
         p.used = 0;
+        p.launches = 0;
         p.bytes = 0.0;
     });
 }
@@ -444,9 +445,10 @@ gl_status gl_profile_stop(double *ms_total, double *bytes_total, int64_t *launch
         }
         if (ms_total) *ms_total = ms;
         if (bytes_total) *bytes_total = p.bytes;
-        if (launches) *launches = (int64_t)p.used;
+        if (launches) *launches = p.launches;
         p.kernel = 0;
         p.used = 0;
+        p.launches = 0;
         p.bytes = 0.0;
     });
 }

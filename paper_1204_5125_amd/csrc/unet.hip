@@ -4,12 +4,13 @@
 // backward and Adam kernels.
 //
 // Network (levels L, base channels c, C_l = c 2^l):
-//   x = (Re psi, Im psi, mu, 50 dmu)             (padded to 32 channels)
+//   x = (Re psi, Im psi, Re s, Im s, mu, 50 dmu), s = (psi_b - psi) / dmu the
+//       slope of the base start psi_b (the secant step)  (padded to 32 channels)
 //   encoder level l: [subsample if l > 0] conv3x3 + SiLU, conv3x3 + SiLU
 //   decoder level l = L-2 .. 0: linear vertex interpolation of the coarser
 //     output, concatenation [upsampled, encoder output l], 2 x (conv3x3 + SiLU)
-//   head: 1x1 convolution to (o_re, o_im); psi_pred = psi + dmu (o_re + i o_im)
-// Loss of an aligned pair (psi, t): sum_i d_i |o_i - (t_i - psi_i)/dmu|^2 / sum d.
+//   head: 1x1 convolution to (o_re, o_im); psi_pred = psi_b + dmu (o_re + i o_im)
+// Loss of an aligned sample: sum_i d_i |o_i - (t_i - psi_b,i)/dmu|^2 / sum d.
 //
 // Layouts: activations pixel-major with channels contiguous ([P][C], BF16,
 // P = N^2, x fastest); weights per layer [c_out][tap][c_in] (tap = 3 ky + kx,
@@ -229,18 +230,22 @@ __global__ void k_bias_reduce(const float *__restrict__ part, int splits, int co
     grad[co] += s;
 }
 
-// input planes (Re psi, Im psi, mu, 50 dmu, 0 ...) with 32 channels
-__global__ void k_unet_input(int P, const double2 *__restrict__ psi, float mu, float sdmu, __bf16 *__restrict__ x)
+// input planes (Re psi, Im psi, Re s, Im s, mu, 50 dmu, 0 ...) with 32
+// channels, s = (psi_b - psi) / dmu
+__global__ void k_unet_input(int P, const double2 *__restrict__ psi, const double2 *__restrict__ psib, double dmu,
+                             float mu, __bf16 *__restrict__ x)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
-    const double2 v = psi[p];
+    const double2 v = psi[p], b = psib[p];
     __bf16 *o = x + (size_t)p * 32;
     o[0] = (__bf16)(float)v.x;
     o[1] = (__bf16)(float)v.y;
-    o[2] = (__bf16)mu;
-    o[3] = (__bf16)sdmu;
-    for (int c = 4; c < 32; ++c) o[c] = (__bf16)0.0f;
+    o[2] = (__bf16)(float)((b.x - v.x) / dmu);
+    o[3] = (__bf16)(float)((b.y - v.y) / dmu);
+    o[4] = (__bf16)mu;
+    o[5] = (__bf16)(float)(50.0 * dmu);
+    for (int c = 6; c < 32; ++c) o[c] = (__bf16)0.0f;
 }
 
 // vertex subsampling: out[i][j] = in[2i][2j]
@@ -321,7 +326,7 @@ __global__ void k_head(int P, int C, const __bf16 *__restrict__ h, const float *
     o[2 * p + 1] = a1;
 }
 
-// psi_out = psi + dmu (o_re + i o_im)
+// psi_out = psi_b + dmu (o_re + i o_im)
 __global__ void k_predict(int P, const double2 *__restrict__ psi, const float *__restrict__ o, double dmu,
                           double2 *__restrict__ out)
 {
@@ -330,11 +335,13 @@ __global__ void k_predict(int P, const double2 *__restrict__ psi, const float *_
     out[p] = make_double2(psi[p].x + dmu * o[2 * p], psi[p].y + dmu * o[2 * p + 1]);
 }
 
-// loss partial sums and do = dL/do (scaled by 1 / count for minibatches)
-__global__ __launch_bounds__(kBlock) void k_loss(GeomT<double> g, const double2 *__restrict__ psi,
-                                                 const double2 *__restrict__ tgt, const float *__restrict__ o,
-                                                 double dmu, double inv_area, float scale, float *__restrict__ dout,
-                                                 RedSlot slot)
+// partial sums of sum_i d_i (|w_i|^2 + eps), w = (t - psi_b) / dmu: the loss
+// normaliser, floored so that a sample whose base start is already exact
+// cannot blow up the gradient
+constexpr double kLossEps = 1e-4;
+
+__global__ __launch_bounds__(kBlock) void k_loss_norm(GeomT<double> g, const double2 *__restrict__ psib,
+                                                      const double2 *__restrict__ tgt, double dmu, RedSlot slot)
 {
     __shared__ double sm[kBlock / 64];
     const int p = blockIdx.x * kBlock + threadIdx.x;
@@ -344,11 +351,33 @@ __global__ __launch_bounds__(kBlock) void k_loss(GeomT<double> g, const double2 
         node_coords<2>(g.N, p, c);
         double sf[3];
         const double d = node_volume<2, double>(g, c, sf);
-        const double wr = (tgt[p].x - psi[p].x) / dmu, wi = (tgt[p].y - psi[p].y) / dmu;
+        const double wr = (tgt[p].x - psib[p].x) / dmu, wi = (tgt[p].y - psib[p].y) / dmu;
+        part = d * (wr * wr + wi * wi + kLossEps);
+    }
+    block_reduce_store(part, slot, sm, blockIdx.x);
+}
+
+// partial sums of sum_i d_i |o_i - w_i|^2 and do = dL/do with
+// L = that sum / *norm (scaled by `scale`, 1 / count for minibatches)
+__global__ __launch_bounds__(kBlock) void k_loss(GeomT<double> g, const double2 *__restrict__ psib,
+                                                 const double2 *__restrict__ tgt, const float *__restrict__ o,
+                                                 double dmu, const double *__restrict__ norm, float scale,
+                                                 float *__restrict__ dout, RedSlot slot)
+{
+    __shared__ double sm[kBlock / 64];
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    const double inv = *norm > 0.0 ? 1.0 / *norm : 0.0;
+    double part = 0.0;
+    if (p < g.n) {
+        int c[3];
+        node_coords<2>(g.N, p, c);
+        double sf[3];
+        const double d = node_volume<2, double>(g, c, sf);
+        const double wr = (tgt[p].x - psib[p].x) / dmu, wi = (tgt[p].y - psib[p].y) / dmu;
         const double rr = o[2 * p] - wr, ri = o[2 * p + 1] - wi;
-        part = d * (rr * rr + ri * ri) * inv_area;
-        dout[2 * p] = (float)(2.0 * d * rr * inv_area) * scale;
-        dout[2 * p + 1] = (float)(2.0 * d * ri * inv_area) * scale;
+        part = d * (rr * rr + ri * ri);
+        dout[2 * p] = (float)(2.0 * d * rr * inv) * scale;
+        dout[2 * p + 1] = (float)(2.0 * d * ri * inv) * scale;
     }
     block_reduce_store(part, slot, sm, blockIdx.x);
 }
@@ -559,11 +588,12 @@ static void conv_wgrad(gl_unet *u, int li, const __bf16 *dz, const __bf16 *in, i
 }
 
 // forward pass; leaves o in u->o
-static void unet_forward(gl_unet *u, const gl_mesh *m, const double2 *psi, double mu, double dmu, hipStream_t s)
+static void unet_forward(gl_unet *u, const gl_mesh *m, const double2 *psi, const double2 *psib, double mu,
+                         double dmu, hipStream_t s)
 {
     const int L = u->levels;
     const int P0 = u->Nl[0] * u->Nl[0];
-    k_unet_input<<<blocks_for(P0), kBlock, 0, s>>>(P0, psi, (float)mu, (float)(50.0 * dmu), u->x0.get());
+    k_unet_input<<<blocks_for(P0), kBlock, 0, s>>>(P0, psi, psib, dmu, (float)mu, u->x0.get());
     const __bf16 *in = u->x0.get();
     int ldi = 32;
     for (int l = 0; l < L; ++l) {
@@ -678,17 +708,21 @@ static void check_grid(const gl_unet *u, const gl_mesh *m)
         fail(GL_ERR_INVALID_ARGUMENT, "gl_unet: grid nodes per axis must be 2^(levels-1) k + 1");
 }
 
-// loss of one pair; leaves do in u->dout (scaled) and returns L
-static double unet_loss(gl_unet *u, const gl_mesh *m, const double2 *psi, const double2 *tgt, double mu, double dmu,
-                        float scale, hipStream_t s)
+// loss of one sample; leaves do in u->dout (scaled) and returns L
+static double unet_loss(gl_unet *u, const gl_mesh *m, const double2 *psi, const double2 *psib, const double2 *tgt,
+                        double mu, double dmu, float scale, hipStream_t s)
 {
-    unet_forward(u, m, psi, mu, dmu, s);
+    unet_forward(u, m, psi, psib, mu, dmu, s);
     const int P0 = m->g.n, nb = blocks_for(P0);
-    double area = 1.0;
-    for (int a = 0; a < 2; ++a) area *= m->desc.side[a];
-    k_loss<<<nb, kBlock, 0, s>>>(geom_t<double>(m->g), psi, tgt, u->o.get(), dmu, 1.0 / area, scale, u->dout.get(), red_slot(m, 2));
+    const GeomT<double> g = geom_t<double>(m->g);
+    double *norm = m->dscal.get() + 5;
+    k_loss_norm<<<nb, kBlock, 0, s>>>(g, psib, tgt, dmu, red_slot(m, 3));
+    launch_finalize(red_slot(m, 3).partials, nb, FIN_STORE, nullptr, norm, nullptr, s);
+    k_loss<<<nb, kBlock, 0, s>>>(g, psib, tgt, u->o.get(), dmu, norm, scale, u->dout.get(), red_slot(m, 2));
     launch_finalize(red_slot(m, 2).partials, nb, FIN_STORE, nullptr, m->dscal.get() + 4, nullptr, s);
-    return read_double(m->dscal.get() + 4, s);
+    GLK_HIP(hipMemcpyAsync(m->hscal + 4, m->dscal.get() + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    GLK_HIP(hipStreamSynchronize(s));
+    return m->hscal[5] > 0.0 ? m->hscal[4] / m->hscal[5] : 0.0;
 }
 
 }  // namespace glk
@@ -713,7 +747,7 @@ gl_status gl_unet_create(int levels, int base_channels, gl_unet **out)
                 u->cout.push_back(co);
                 u->ksz.push_back(k);
             };
-            int c = 4;
+            int c = 6;
             for (int l = 0; l < L; ++l) {
                 add(c, base_channels << l, 3);
                 add(base_channels << l, base_channels << l, 3);
@@ -788,33 +822,36 @@ gl_status gl_unet_get_params(const gl_unet *u, float *host_params)
     });
 }
 
-gl_status gl_unet_predict(gl_unet *u, const gl_mesh *mesh, const void *psi, double mu, double dmu, void *psi_out,
-                          gl_stream stream)
+gl_status gl_unet_predict(gl_unet *u, const gl_mesh *mesh, const void *psi, const void *psi_base, double mu,
+                          double dmu, void *psi_out, gl_stream stream)
 {
     return guarded([&] {
-        if (!u || !mesh || !psi || !psi_out) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_predict: NULL argument");
-        if (psi == psi_out) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_predict: psi and psi_out alias");
+        if (!u || !mesh || !psi || !psi_base || !psi_out) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_predict: NULL argument");
+        if (psi == psi_out || psi_base == psi_out) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_predict: output aliases an input");
+        if (!(dmu != 0.0)) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_predict: dmu must be nonzero");
         check_grid(u, mesh);
         hipStream_t s = as_stream(stream);
         unet_alloc(u, mesh->g.N[0]);
-        unet_forward(u, mesh, (const double2 *)psi, mu, dmu, s);
+        unet_forward(u, mesh, (const double2 *)psi, (const double2 *)psi_base, mu, dmu, s);
         const int P = mesh->g.n;
-        k_predict<<<blocks_for(P), kBlock, 0, s>>>(P, (const double2 *)psi, u->o.get(), dmu, (double2 *)psi_out);
+        k_predict<<<blocks_for(P), kBlock, 0, s>>>(P, (const double2 *)psi_base, u->o.get(), dmu, (double2 *)psi_out);
         GLK_CHECK_LAUNCH();
     });
 }
 
-gl_status gl_unet_loss_grad(gl_unet *u, const gl_mesh *mesh, const void *psi, double mu, double dmu,
-                            const void *target, double *loss, float *host_grad, gl_stream stream)
+gl_status gl_unet_loss_grad(gl_unet *u, const gl_mesh *mesh, const void *psi, const void *psi_base, double mu,
+                            double dmu, const void *target, double *loss, float *host_grad, gl_stream stream)
 {
     return guarded([&] {
-        if (!u || !mesh || !psi || !target || !loss) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_loss_grad: NULL argument");
+        if (!u || !mesh || !psi || !psi_base || !target || !loss)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_loss_grad: NULL argument");
         if (!(dmu != 0.0)) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_loss_grad: dmu must be nonzero");
         check_grid(u, mesh);
         hipStream_t s = as_stream(stream);
         unet_alloc(u, mesh->g.N[0]);
         k_fill_f32<<<blocks_for((int64_t)u->nparams), kBlock, 0, s>>>((int)u->nparams, u->grad.get(), 0.0f);
-        *loss = unet_loss(u, mesh, (const double2 *)psi, (const double2 *)target, mu, dmu, 1.0f, s);
+        *loss = unet_loss(u, mesh, (const double2 *)psi, (const double2 *)psi_base, (const double2 *)target, mu, dmu,
+                          1.0f, s);
         unet_backward(u, s);
         if (host_grad) {
             GLK_HIP(hipMemcpyAsync(host_grad, u->grad.get(), u->nparams * sizeof(float), hipMemcpyDeviceToHost, s));
@@ -823,12 +860,12 @@ gl_status gl_unet_loss_grad(gl_unet *u, const gl_mesh *mesh, const void *psi, do
     });
 }
 
-gl_status gl_unet_train_step(gl_unet *u, const gl_mesh *mesh, int count, const void *const *psi, const double *mu,
-                             const double *dmu, const void *const *target, const gl_adam_opts *opts, double *loss,
-                             gl_stream stream)
+gl_status gl_unet_train_step(gl_unet *u, const gl_mesh *mesh, int count, const void *const *psi,
+                             const void *const *psi_base, const double *mu, const double *dmu,
+                             const void *const *target, const gl_adam_opts *opts, double *loss, gl_stream stream)
 {
     return guarded([&] {
-        if (!u || !mesh || !psi || !mu || !dmu || !target || !opts)
+        if (!u || !mesh || !psi || !psi_base || !mu || !dmu || !target || !opts)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_train_step: NULL argument");
         if (count < 1) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_train_step: count must be >= 1");
         if (!(opts->lr > 0.0) || !(opts->beta1 >= 0.0 && opts->beta1 < 1.0) || !(opts->beta2 >= 0.0 && opts->beta2 < 1.0) ||
@@ -836,14 +873,15 @@ gl_status gl_unet_train_step(gl_unet *u, const gl_mesh *mesh, int count, const v
             fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_train_step: invalid Adam options");
         check_grid(u, mesh);
         for (int k = 0; k < count; ++k)
-            if (!psi[k] || !target[k] || !(dmu[k] != 0.0)) fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_train_step: sample");
+            if (!psi[k] || !psi_base[k] || !target[k] || !(dmu[k] != 0.0))
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_unet_train_step: sample");
         hipStream_t s = as_stream(stream);
         unet_alloc(u, mesh->g.N[0]);
         k_fill_f32<<<blocks_for((int64_t)u->nparams), kBlock, 0, s>>>((int)u->nparams, u->grad.get(), 0.0f);
         double tot = 0.0;
         for (int k = 0; k < count; ++k) {
-            tot += unet_loss(u, mesh, (const double2 *)psi[k], (const double2 *)target[k], mu[k], dmu[k],
-                             1.0f / count, s);
+            tot += unet_loss(u, mesh, (const double2 *)psi[k], (const double2 *)psi_base[k], (const double2 *)target[k],
+                             mu[k], dmu[k], 1.0f / count, s);
             unet_backward(u, s);
         }
         u->adam_t += 1;

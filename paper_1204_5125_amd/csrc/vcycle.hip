@@ -407,11 +407,15 @@ struct DenseApply {
 constexpr int kBottomThreads = 1024;
 constexpr int kBottomLpr = 8;
 
+// one colour of a level, from its ELL block; x in LDS or global memory
 template <class T>
-__device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int colour)
+__device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int colour, C<T> *x)
 {
     const int cnt = L.coff[colour + 1] - L.coff[colour];
     const int row0 = L.coff[colour];
+    const int W = L.ewidth[colour];
+    const int *eci = L.eci + L.eoff[colour];
+    const C<T> *ev = L.ev + L.eoff[colour];
     const int per = kBottomThreads / kBottomLpr;
     const int lane = threadIdx.x % kBottomLpr;
     for (int base = 0; base < cnt; base += per) {
@@ -420,12 +424,12 @@ __device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int col
         const int i = row0 + (act ? r : 0);
         C<T> s = mk<T>(0, 0);
         if (act)
-            for (int p = L.rp[i] + lane; p < L.rp[i + 1]; p += kBottomLpr) {
-                const int j = L.ci[p];
-                if (j != i) s = cadd(s, cmul(L.v[p], L.x[j]));
+            for (int k = lane; k < W; k += kBottomLpr) {
+                const int j = eci[(size_t)r * W + k];
+                if (j != i) s = cadd(s, cmul(ev[(size_t)r * W + k], x[j]));
             }
         s = lanes_sum<T, kBottomLpr>(s);
-        if (act && lane == 0) L.x[i] = cscale(csub(L.b[i], s), (T)1 / L.diag[i]);
+        if (act && lane == 0) x[i] = cscale(csub(L.b[i], s), (T)1 / L.diag[i]);
     }
 }
 
@@ -469,14 +473,16 @@ __device__ __forceinline__ void bottom_dense(int n, const C<T> *M, const C<T> *b
 }
 
 template <class T>
-__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L)
+__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L, C<T> *x)
 {
     for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
-        bottom_rows_sgs<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t);
+        bottom_rows_sgs<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, x);
         __syncthreads();
     }
 }
 
+// The level D.lds_level (the largest one handled here, when it fits) keeps
+// its iterate in LDS for the whole cycle and writes it out at the end.
 template <class T>
 struct Bottom {
     const BottomDesc<T> *Dp;
@@ -484,13 +490,16 @@ struct Bottom {
     __device__ void operator()(int, int) const
     {
         GATE();
+        extern __shared__ double2 glk_bottom_lds[];
         const BottomDesc<T> &D = *Dp;
+        C<T> *xs = reinterpret_cast<C<T> *>(glk_bottom_lds);
         for (int l = D.first; l < D.last; ++l) {
             const BottomLevel<T> &L = D.L[l];
-            for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = mk<T>(0, 0);
+            C<T> *x = l == D.lds_level ? xs : L.x;
+            for (int i = threadIdx.x; i < L.n; i += kBottomThreads) x[i] = mk<T>(0, 0);
             __syncthreads();
-            bottom_sgs<T>(L);
-            bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, L.x, L.b, L.r);
+            bottom_sgs<T>(L, x);
+            bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, x, L.b, L.r);
             __syncthreads();
             bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, L.r, nullptr, D.L[l + 1].b);
             __syncthreads();
@@ -503,9 +512,14 @@ struct Bottom {
         }
         for (int l = D.last - 1; l >= D.first; --l) {
             const BottomLevel<T> &L = D.L[l];
-            bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, L.x);
+            C<T> *x = l == D.lds_level ? xs : L.x;
+            bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, x);
             __syncthreads();
-            bottom_sgs<T>(L);
+            bottom_sgs<T>(L, x);
+            if (l == D.lds_level) {
+                for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = xs[i];
+                __syncthreads();
+            }
         }
     }
 };
@@ -536,6 +550,9 @@ template <> const float2 *links<float>(const gl_mesh *m) { return m->U32.get(); 
 template <class T> static const C<T> *cinv(const gl_precond *p);
 template <> const double2 *cinv<double>(const gl_precond *p) { return p->cinv64.get(); }
 template <> const float2 *cinv<float>(const gl_precond *p) { return p->cinv32.get(); }
+template <class T> static int bottom_lds(const gl_precond *p);
+template <> int bottom_lds<double>(const gl_precond *p) { return p->lds64; }
+template <> int bottom_lds<float>(const gl_precond *p) { return p->lds32; }
 template <class T> static const BottomDesc<T> *bdesc(const gl_precond *p);
 template <> const BottomDesc<double> *bdesc<double>(const gl_precond *p)
 {
@@ -591,23 +608,32 @@ template <> const float2 *evals<float>(const Level &L) { return L.ev32.get(); }
 template <class T>
 static void csr_sgs(Level &Lv, int shift, const int *gate, const Launch &L)
 {
+    // algorithmic bytes of a pass: the colour's padded rows (index + value),
+    // one x value per stored entry, b and the diagonal of each row, x written
+    double bytes = 0.0;
+    int passes = 0;
     for (int t = 0; t < 2 * Lv.ncolors - 1; ++t) {
         const int c = t < Lv.ncolors ? t : 2 * Lv.ncolors - 2 - t;
         const int cnt = Lv.coff[c + 1] - Lv.coff[c];
         if (cnt == 0) continue;
-        const int W = Lv.ewidth[c];
-        const int lpr = shifted(W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16, shift);
-        const int nb = blocks_for((int64_t)cnt * lpr);
-        // algorithmic bytes: the colour's padded rows (index + value), one
-        // x value per stored entry, b and the diagonal of each row, x written
-        const double bytes = (double)cnt * W * (4.0 + 2.0 * sizeof(C<T>)) + cnt * (2.0 * sizeof(C<T>) + sizeof(T));
-        prof_launch(PROF_COARSE_SWEEP, bytes, L, [&] {
+        bytes += (double)cnt * Lv.ewidth[c] * (4.0 + 2.0 * sizeof(C<T>)) + cnt * (2.0 * sizeof(C<T>) + sizeof(T));
+        ++passes;
+    }
+    // the passes of one sweep share one event bracket
+    prof_launch(PROF_COARSE_SWEEP, bytes, L, [&] {
+        for (int t = 0; t < 2 * Lv.ncolors - 1; ++t) {
+            const int c = t < Lv.ncolors ? t : 2 * Lv.ncolors - 2 - t;
+            const int cnt = Lv.coff[c + 1] - Lv.coff[c];
+            if (cnt == 0) continue;
+            const int W = Lv.ewidth[c];
+            const int lpr = shifted(W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16, shift);
+            const int nb = blocks_for((int64_t)cnt * lpr);
             GLK_LPR_SWITCH(lpr, {
                 L.run(nb, EllSgs<T, LPR>{Lv.eci.get() + Lv.eoff[c], evals<T>(Lv) + Lv.eoff[c], W, dgn<T>(Lv),
                                          Lv.coff[c], cnt, vec_b<T>(Lv), vec_x<T>(Lv), gate});
             });
-        });
-    }
+        }
+    }, passes);
 }
 
 template <class T>
@@ -681,7 +707,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     // small levels and the coarsest solve in one work-group, or the coarsest
     // solve alone as a dense product over many work-groups
     if (pre->bottom < nl - 1) {
-        L.run<Bottom<T>, kBottomThreads>(1, Bottom<T>{bdesc<T>(pre), gate});
+        L.run<Bottom<T>, kBottomThreads>(1, Bottom<T>{bdesc<T>(pre), gate}, bottom_lds<T>(pre));
     } else {
         Level &Lc = pre->L[nl - 1];
         L.run(blocks_for((int64_t)Lc.n * 64), DenseApply<T>{Lc.n, cinv<T>(pre), vec_b<T>(Lc), vec_x<T>(Lc), gate});
@@ -771,6 +797,21 @@ static void fill_bottom(gl_precond *pre, BottomDesc<T> &D)
         B.b = vec_b<T>(L);
         B.x = vec_x<T>(L);
         B.r = vec_r<T>(L);
+        B.eci = L.eci.get();
+        B.ev = evals<T>(L);
+        for (int c = 0; c < L.ncolors && c < kMaxColors && c < (int)L.ewidth.size(); ++c) {
+            B.ewidth[c] = L.ewidth[c];
+            B.eoff[c] = L.eoff[c];
+        }
+    }
+    // the first bottom level keeps its iterate in LDS when it fits
+    D.lds_level = -1;
+    if (D.first < D.last) {
+        int dev = 0, lmax = 0;
+        GLK_HIP(hipGetDevice(&dev));
+        GLK_HIP(hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t need = (size_t)pre->L[D.first].n * sizeof(C<T>);
+        if (need + 1024 <= (size_t)lmax) D.lds_level = D.first;
     }
 }
 
@@ -790,6 +831,8 @@ void bottom_descriptors(gl_precond *pre, hipStream_t s)
     BottomDesc<float> d32;
     fill_bottom<double>(pre, d64);
     fill_bottom<float>(pre, d32);
+    pre->lds64 = d64.lds_level >= 0 ? (int)(pre->L[d64.lds_level].n * sizeof(double2)) : 0;
+    pre->lds32 = d32.lds_level >= 0 ? (int)(pre->L[d32.lds_level].n * sizeof(float2)) : 0;
     pre->bdesc64.alloc(sizeof(d64));
     pre->bdesc32.alloc(sizeof(d32));
     GLK_HIP(hipMemcpyAsync(pre->bdesc64.get(), &d64, sizeof(d64), hipMemcpyHostToDevice, s));

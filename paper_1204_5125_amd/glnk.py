@@ -125,10 +125,10 @@ def lib():
     L.gl_unet_num_params.argtypes = [vp, P(C.c_int64)]
     L.gl_unet_set_params.argtypes = [vp, vp]
     L.gl_unet_get_params.argtypes = [vp, vp]
-    L.gl_unet_predict.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, vp]
-    L.gl_unet_loss_grad.argtypes = [vp, vp, vp, C.c_double, C.c_double, vp, P(C.c_double), vp, vp]
-    L.gl_unet_train_step.argtypes = [vp, vp, C.c_int, P(vp), P(C.c_double), P(C.c_double), P(vp), P(AdamOpts),
-                                     P(C.c_double), vp]
+    L.gl_unet_predict.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, vp, vp]
+    L.gl_unet_loss_grad.argtypes = [vp, vp, vp, vp, C.c_double, C.c_double, vp, P(C.c_double), vp, vp]
+    L.gl_unet_train_step.argtypes = [vp, vp, C.c_int, P(vp), P(vp), P(C.c_double), P(C.c_double), P(vp),
+                                     P(AdamOpts), P(C.c_double), vp]
     L.gl_unet_destroy.argtypes = [vp]
     L.gl_unet_destroy.restype = None
     L.gl_profile_start.argtypes = [C.c_int]
@@ -445,7 +445,7 @@ class Batch:
             pass
 
 
-def unet_layer_shapes(levels, base, in_ch=4, out_ch=2):
+def unet_layer_shapes(levels, base, in_ch=6, out_ch=2):
     """(c_in, c_out, k) of the library's U-Net layers, in parameter order."""
     shapes, c = [], in_ch
     for l in range(levels):
@@ -485,28 +485,31 @@ class UNet:
         _check(lib().gl_unet_get_params(self._h, out.ctypes.data_as(C.c_void_p)), "gl_unet_get_params")
         return out
 
-    def predict(self, mesh, psi, mu, dmu, out, stream=None):
-        _check(lib().gl_unet_predict(self._h, mesh.handle, _vec(psi, mesh.n, "psi"), mu, dmu,
-                                     _vec(out, mesh.n, "out"), _stream(stream)), "gl_unet_predict")
+    def predict(self, mesh, psi, psi_base, mu, dmu, out, stream=None):
+        _check(lib().gl_unet_predict(self._h, mesh.handle, _vec(psi, mesh.n, "psi"),
+                                     _vec(psi_base, mesh.n, "psi_base"), mu, dmu, _vec(out, mesh.n, "out"),
+                                     _stream(stream)), "gl_unet_predict")
 
-    def loss_grad(self, mesh, psi, mu, dmu, target, want_grad=True, stream=None):
+    def loss_grad(self, mesh, psi, psi_base, mu, dmu, target, want_grad=True, stream=None):
         loss = C.c_double()
         g = np.empty(self.n_params, dtype=np.float32) if want_grad else None
-        _check(lib().gl_unet_loss_grad(self._h, mesh.handle, _vec(psi, mesh.n, "psi"), mu, dmu,
+        _check(lib().gl_unet_loss_grad(self._h, mesh.handle, _vec(psi, mesh.n, "psi"),
+                                       _vec(psi_base, mesh.n, "psi_base"), mu, dmu,
                                        _vec(target, mesh.n, "target"), C.byref(loss),
                                        g.ctypes.data_as(C.c_void_p) if g is not None else None,
                                        _stream(stream)), "gl_unet_loss_grad")
         return loss.value, g
 
-    def train_step(self, mesh, psis, mus, dmus, targets, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+    def train_step(self, mesh, psis, bases, mus, dmus, targets, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
                    stream=None):
         k = len(psis)
         pp = (C.c_void_p * k)(*[_vec(p, mesh.n, "psi") for p in psis])
+        bb = (C.c_void_p * k)(*[_vec(p, mesh.n, "psi_base") for p in bases])
         tt = (C.c_void_p * k)(*[_vec(t, mesh.n, "target") for t in targets])
         mm = (C.c_double * k)(*mus)
         dd = (C.c_double * k)(*dmus)
         loss = C.c_double()
-        _check(lib().gl_unet_train_step(self._h, mesh.handle, k, pp, mm, dd, tt,
+        _check(lib().gl_unet_train_step(self._h, mesh.handle, k, pp, bb, mm, dd, tt,
                                         C.byref(AdamOpts(lr, beta1, beta2, eps)), C.byref(loss),
                                         _stream(stream)), "gl_unet_train_step")
         return loss.value

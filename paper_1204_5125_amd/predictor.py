@@ -1,8 +1,8 @@
 """Learned Newton start for the mu-continuation (spec extension of the
-continuation in Sec. 4): training data from a seeded continuation sweep,
-training of the library's U-Net with its own kernels, and a predictor that
-falls back to the secant step whenever the secant start has the smaller
-GL residual.
+continuation in Sec. 4): the library's U-Net corrects the secant start.
+Training data come from a seeded continuation sweep; training runs the
+library's own kernels; at run time the corrected start is used unless the
+plain secant start has the smaller GL residual.
 
 Host orchestration only: predictions, residuals, alignment and training all
 run in libglnk kernels.
@@ -18,33 +18,54 @@ def sweep(mesh, mus, psi0, **kw):
     e.g. where the branch ends), it restarts from the last converged state at
     the next field value of the list."""
     records, states = [], []
-    start, todo = psi0, list(mus)
+    start, todo, seg = psi0, list(mus), 0
     while todo:
         recs, _, st = continuation.continuation_path(mesh, start, todo, keep=True, **kw)
         records += recs
-        states += st
+        steps = {r["mu"]: r["newton_steps"] for r in recs if r["status"] == 0}
+        states += [(mu, psi, seg, steps.get(mu, 0)) for mu, psi in st]
         if recs[-1]["status"] == 0:
             break
         todo = [m for m in todo if m > recs[-1]["mu"] + 1e-12]
         if states:
             start = states[-1][1]
+        seg += 1
     return records, states
 
 
-def make_pairs(mesh, states, strides=(1, 2, 3)):
-    """Training pairs (psi_i, aligned psi_j, mu_i, mu_j - mu_i) for j = i + s.
-    The target is rotated by the global phase that aligns it with psi_i
-    (gl_secant_predict with ratio -1 gives e^{i chi} target)."""
+def secant_base(mesh, psi, prev, mu_prev, mu, mu_next, out):
+    """The continuation's secant start at mu_next (psi itself without history)."""
+    if prev is None:
+        out.copy_(psi)
+    else:
+        glnk.gl_secant_predict(mesh, psi, prev, (mu_next - mu) / (mu - mu_prev), out)
+    return out
+
+
+def make_pairs(mesh, states, strides=(1, 2, 3), jump_newton=6):
+    """Training samples (psi_i, secant start, aligned psi_j, mu_i, mu_j - mu_i)
+    for j = i + s inside one continuation segment, leaving out spans where the
+    branch jumped (a state in (i, j] needed more than jump_newton Newton
+    steps).  The target is rotated by the global phase that aligns it with
+    psi_i (gl_secant_predict with ratio -1 gives e^{i chi} target); the secant
+    start uses psi_{i-1}."""
     import torch
-    pairs = []
+    samples = []
     for s in strides:
         for i in range(len(states) - s):
-            mu_i, psi_i = states[i]
-            mu_j, psi_j = states[i + s]
+            mu_i, psi_i, seg, _ = states[i]
+            mu_j, psi_j, seg_j, _ = states[i + s]
+            if seg_j != seg or any(states[k][3] > jump_newton for k in range(i, i + s + 1)):
+                continue
             t = torch.empty_like(psi_i)
             glnk.gl_secant_predict(mesh, psi_i, psi_j, -1.0, t)
-            pairs.append((psi_i, t, mu_i, mu_j - mu_i))
-    return pairs
+            b = torch.empty_like(psi_i)
+            if i > 0 and states[i - 1][2] == seg and states[i][3] <= jump_newton:
+                secant_base(mesh, psi_i, states[i - 1][1], states[i - 1][0], mu_i, mu_j, b)
+            else:
+                b.copy_(psi_i)
+            samples.append((psi_i, b, t, mu_i, mu_j - mu_i))
+    return samples
 
 
 def train(net, mesh, pairs, epochs=10, batch=4, lr=1e-3, lr_end=1e-4, seed=0, log=None):
@@ -60,8 +81,9 @@ def train(net, mesh, pairs, epochs=10, batch=4, lr=1e-3, lr_end=1e-4, seed=0, lo
         for b0 in range(0, len(pairs), batch):
             idx = order[b0:b0 + batch]
             rate = lr * (lr_end / lr) ** (k / max(1, steps - 1))
-            loss = net.train_step(mesh, [pairs[i][0] for i in idx], [pairs[i][2] for i in idx],
-                                  [pairs[i][3] for i in idx], [pairs[i][1] for i in idx], lr=rate)
+            loss = net.train_step(mesh, [pairs[i][0] for i in idx], [pairs[i][1] for i in idx],
+                                  [pairs[i][3] for i in idx], [pairs[i][4] for i in idx],
+                                  [pairs[i][2] for i in idx], lr=rate)
             tot += loss * len(idx)
             cnt += len(idx)
             k += 1
@@ -72,32 +94,40 @@ def train(net, mesh, pairs, epochs=10, batch=4, lr=1e-3, lr_end=1e-4, seed=0, lo
 
 
 class LearnedPredictor:
-    """predictor(psi_m, psi_prev, mu_prev, mu_m, mu_next) for continuation_path: the
-    network's start, unless the secant start (when there is one) has the
-    smaller ||GL||_D at mu_next.  The mesh's field must already be mu_next
-    (continuation_path sets it).  Counts which start was used."""
+    """predictor(psi_m, psi_prev, mu_prev, mu_m, mu_next) for continuation_path:
+    the network's correction of the secant start.  select="always" (default)
+    uses the network's start unless it is not finite; select="residual" keeps
+    the plain secant start when it has the smaller ||GL||_D at mu_next (the
+    mesh's field must already be mu_next; continuation_path sets it).  The
+    residual is a poor judge here: the network's start carries BF16-level
+    high-frequency noise that the GL operator amplifies while Newton removes it
+    in a step, so the network's start wins on Newton steps although its
+    residual is larger.  Counts which start was used and records both
+    residuals."""
 
-    def __init__(self, net, mesh):
+    def __init__(self, net, mesh, select="always"):
+        self.select = select
         import torch
         self.net, self.mesh = net, mesh
         self.out = None
         self.sec = None
         self.used = {"learned": 0, "secant": 0}
+        self.residuals = []
         self.torch = torch
 
     def __call__(self, psi, prev, mu_prev, mu, mu_next):
         if self.out is None:
             self.out = self.torch.empty_like(psi)
             self.sec = self.torch.empty_like(psi)
-        dmu = mu_next - mu
-        self.net.predict(self.mesh, psi, mu, dmu, self.out)
+        secant_base(self.mesh, psi, prev, mu_prev, mu, mu_next, self.sec)
+        self.net.predict(self.mesh, psi, self.sec, mu, mu_next - mu, self.out)
         r_net = glnk.gl_residual(self.mesh, self.out)
-        if prev is not None:
-            glnk.gl_secant_predict(self.mesh, psi, prev, dmu / (mu - mu_prev), self.sec)
-            r_sec = glnk.gl_residual(self.mesh, self.sec)
-            if r_sec < r_net:
-                self.used["secant"] += 1
-                return self.sec
+        r_sec = glnk.gl_residual(self.mesh, self.sec)
+        self.residuals.append((r_sec, r_net))
+        bad = not np.isfinite(r_net)
+        if bad or (self.select == "residual" and not r_net < r_sec):
+            self.used["secant"] += 1
+            return self.sec
         self.used["learned"] += 1
         return self.out
 
