@@ -30,8 +30,8 @@ SIDE = (10.0, 10.0)
 MU = 1.0
 NEWTON_STEPS = 4
 RTOL = 1e-10
-KERNEL_NAMES = {1: "MinresJapply", 2: "L0 Gauss-Seidel sweeps (L0PreBlack, L0Sweep, L0PostRed, L0Last)",
-                3: "L0Residual", 4: "CsrSpmv (level-0 restriction)", 5: "MinresVupdate", 6: "k_minres_wx",
+KERNEL_NAMES = {1: "MinresJapply", 2: "L0 Gauss-Seidel sweeps (L0PreBlack, L0Sweep, L0Last)",
+                3: "L0Residual", 4: "level-0 transfers (CsrSpmv restriction, L0ProlongBlack)", 5: "MinresVupdate", 6: "k_minres_wx",
                 7: "k_gl_residual", 8: "EllSgs (Gauss-Seidel colour sweep, levels >= 1)"}
 
 

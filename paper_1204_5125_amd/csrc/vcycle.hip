@@ -5,14 +5,16 @@
 // sum) that is red, black, red.  Every kernel is templated on the storage and
 // arithmetic type (double or float); the input v and the output z are FP64.
 //
-// Level 0 needs seven stencil passes instead of nine because a Gauss-Seidel
+// Level 0 needs six stencil passes instead of seven because a Gauss-Seidel
 // update of a red node does not read the node's previous value:
 //   - the first red update from x = 0 is x_r = b_r / H_rr, folded into the
 //     black update that follows (which evaluates it for its red neighbours);
-//   - after the coarse correction only the black values x_b + (P x_c)_b are
-//     read (by the first red update), so the prolongation is folded into it;
 //   - after the pre-smoothing sweep the red residual is zero (the last update
-//     made it so), and only black residuals are formed.
+//     made it so), and only black residuals are formed;
+//   - after the coarse correction only the black values x_b + (P x_c)_b are
+//     read (by the first red update), so only black nodes are prolonged.
+// On the coarser levels the zero start and the first two colour passes of the
+// pre-smoothing sweep are one dispatch for the same reason.
 #include <cstring>
 #include <type_traits>
 
@@ -152,15 +154,12 @@ __device__ __forceinline__ C<T> prolong_row(const int *__restrict__ prp, const i
     return s;
 }
 
-// post-smoothing, first red pass with the coarse correction of the black neighbours
+// coarse correction of the black nodes: x_b += (P x_c)_b (the red nodes are
+// overwritten by the red pass that follows, which reads only black values)
 template <int DIM, class T>
-struct L0PostRed {
+struct L0ProlongBlack {
     GeomT<T> g;
-    const double2 *v;
-    const C<T> *b;
     C<T> *x;
-    const C<T> *U;
-    const T *hd;
     const int *prp, *pci;
     const C<T> *pv, *xc;
     const int *gate;
@@ -171,28 +170,8 @@ struct L0PostRed {
         if (i >= g.n) return;
         int c[3];
         node_coords<DIM>(g.N, i, c);
-        if (((c[0] + c[1] + c[2]) & 1) != 0) return;
-        T s[3];
-        const T d = node_volume<DIM, T>(g, c, s);
-        C<T> off = mk<T>(0, 0);
-        int stride = 1;
-        const size_t n = (size_t)g.n;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const T al = d * s[a] * g.inv_h2[a];
-            if (c[a] > 0) {
-                const int k = i - stride;
-                const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
-                off = csub(off, cscale(cmul(U[a * n + k], xk), al));
-            }
-            if (c[a] < g.N[a] - 1) {
-                const int k = i + stride;
-                const C<T> xk = cadd(x[k], prolong_row<T>(prp, pci, pv, xc, k));
-                off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
-            }
-            stride *= g.N[a];
-        }
-        x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+        if (((c[0] + c[1] + c[2]) & 1) == 0) return;
+        x[i] = cadd(x[i], prolong_row<T>(prp, pci, pv, xc, i));
     }
 };
 
@@ -279,6 +258,44 @@ struct EllSgs {
         }
         s = lanes_sum<T, LPR>(s);
         if (act && lane == 0 && go) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
+    }
+};
+
+// The first two passes of a sweep from x = 0, and the zero start, in one
+// dispatch (rows are colour-ordered): colour 0 gets x = b / a_ii, colour 1
+// its Gauss-Seidel update from those values (evaluated on the fly from b and
+// the diagonal), every other row x = 0.  Same arithmetic as the three
+// separate steps.
+template <class T, int LPR>
+struct EllSgsStart {
+    const int *eci;  // colour-1 block
+    const C<T> *ev;
+    int W;
+    const T *diag;
+    int c1, c2, n;   // colour 0 = rows [0, c1), colour 1 = [c1, c2)
+    const C<T> *b;
+    C<T> *x;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        const int go = gate ? *gate : 1;
+        const int t = bx * kBlock + threadIdx.x;
+        const int r = t / LPR, lane = t % LPR;
+        const bool valid = r < n, one = valid && r >= c1 && r < c2;
+        C<T> s = mk<T>(0, 0);
+        if (one) {
+            const size_t base = (size_t)(r - c1) * W;
+            for (int k = lane; k < W; k += LPR) {
+                const int j = eci[base + k];
+                if (j != r && j < c1) s = cadd(s, cmul(ev[base + k], cscale(b[j], (T)1 / diag[j])));
+            }
+        }
+        s = lanes_sum<T, LPR>(s);
+        if (valid && lane == 0 && go) {
+            if (r < c1) x[r] = cscale(b[r], (T)1 / diag[r]);
+            else if (r < c2) x[r] = cscale(csub(b[r], s), (T)1 / diag[r]);
+            else x[r] = mk<T>(0, 0);
+        }
     }
 };
 
@@ -605,28 +622,47 @@ template <class T> static const C<T> *evals(const Level &L);
 template <> const double2 *evals<double>(const Level &L) { return L.ev64.get(); }
 template <> const float2 *evals<float>(const Level &L) { return L.ev32.get(); }
 
+static int ell_lanes(int W, int shift) { return shifted(W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16, shift); }
+
+// One symmetric sweep on a level >= 1: colours 0 .. C-1, then C-2 .. 0.
+// from_zero: the sweep starts from x = 0 (its first two passes and the zero
+// start are one dispatch).
 template <class T>
-static void csr_sgs(Level &Lv, int shift, const int *gate, const Launch &L)
+static void csr_sgs(Level &Lv, int shift, bool from_zero, const int *gate, const Launch &L)
 {
+    const int nco = Lv.ncolors;
+    const int t0 = from_zero ? std::min(2, 2 * nco - 1) : 0;
     // algorithmic bytes of a pass: the colour's padded rows (index + value),
     // one x value per stored entry, b and the diagonal of each row, x written
     double bytes = 0.0;
     int passes = 0;
-    for (int t = 0; t < 2 * Lv.ncolors - 1; ++t) {
-        const int c = t < Lv.ncolors ? t : 2 * Lv.ncolors - 2 - t;
+    for (int t = 0; t < 2 * nco - 1; ++t) {
+        const int c = t < nco ? t : 2 * nco - 2 - t;
         const int cnt = Lv.coff[c + 1] - Lv.coff[c];
         if (cnt == 0) continue;
         bytes += (double)cnt * Lv.ewidth[c] * (4.0 + 2.0 * sizeof(C<T>)) + cnt * (2.0 * sizeof(C<T>) + sizeof(T));
         ++passes;
     }
+    if (from_zero) passes -= t0 - 1;
     // the passes of one sweep share one event bracket
     prof_launch(PROF_COARSE_SWEEP, bytes, L, [&] {
-        for (int t = 0; t < 2 * Lv.ncolors - 1; ++t) {
-            const int c = t < Lv.ncolors ? t : 2 * Lv.ncolors - 2 - t;
+        if (from_zero) {
+            const int c1 = Lv.coff[1], c2 = nco > 1 ? Lv.coff[2] : Lv.n;
+            const int W = nco > 1 ? Lv.ewidth[1] : 1;
+            const int lpr = ell_lanes(W, shift);
+            const int nb = blocks_for((int64_t)Lv.n * lpr);
+            GLK_LPR_SWITCH(lpr, {
+                L.run(nb, EllSgsStart<T, LPR>{Lv.eci.get() + (nco > 1 ? Lv.eoff[1] : 0), evals<T>(Lv) +
+                                              (nco > 1 ? Lv.eoff[1] : 0), W, dgn<T>(Lv), c1, c2, Lv.n,
+                                              vec_b<T>(Lv), vec_x<T>(Lv), gate});
+            });
+        }
+        for (int t = t0; t < 2 * nco - 1; ++t) {
+            const int c = t < nco ? t : 2 * nco - 2 - t;
             const int cnt = Lv.coff[c + 1] - Lv.coff[c];
             if (cnt == 0) continue;
             const int W = Lv.ewidth[c];
-            const int lpr = shifted(W <= 3 ? 2 : W <= 6 ? 4 : W <= 16 ? 8 : 16, shift);
+            const int lpr = ell_lanes(W, shift);
             const int nb = blocks_for((int64_t)cnt * lpr);
             GLK_LPR_SWITCH(lpr, {
                 L.run(nb, EllSgs<T, LPR>{Lv.eci.get() + Lv.eoff[c], evals<T>(Lv) + Lv.eoff[c], W, dgn<T>(Lv),
@@ -678,7 +714,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const double b_pre = nn * 16 + (f32 ? nn * sz : 0) + nn * szr + E * sz + mc * sz;
     const double b_sweep = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz;
     const double b_resid = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz + nn * sz;
-    const double b_post = b_sweep + (nn + 1 + L0.Pa.nnz) * 4.0 + L0.Pa.nnz * sz + L0.nc * sz;
+    const double b_prol = (mc + 1 + 0.5 * L0.Pa.nnz) * 4.0 + 0.5 * L0.Pa.nnz * sz + L0.nc * sz + 2.0 * mc * sz;
     const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
     const double b_restr = (L0.nc + 1 + L0.Ra.nnz) * 4.0 + L0.Ra.nnz * sz + nn * sz + L0.nc * sz;
     // level 0, down: red (from zero, folded) + black, red, black residual, restriction
@@ -699,8 +735,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const int sh = pre->lane_shift;
     for (int l = 1; l < nb_first; ++l) {
         Level &Lv = pre->L[l];
-        L.run(blocks_for(Lv.n), FillZero<T>{Lv.n, vec_x<T>(Lv), gate});
-        csr_sgs<T>(Lv, sh, gate, L);
+        csr_sgs<T>(Lv, sh, true, gate, L);
         csr_residual<T>(Lv, sh, gate, L);
         csr_spmv<T>(Lv.Ra, vec_r<T>(Lv), vec_b<T>(pre->L[l + 1]), false, sh, gate, L);
     }
@@ -716,12 +751,17 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     for (int l = nb_first - 1; l >= 1; --l) {
         Level &Lv = pre->L[l];
         csr_spmv<T>(Lv.Pa, vec_x<T>(pre->L[l + 1]), vec_x<T>(Lv), true, sh, gate, L);
-        csr_sgs<T>(Lv, sh, gate, L);
+        csr_sgs<T>(Lv, sh, false, gate, L);
     }
     // level 0, up: red with the coarse correction, black, red + output
-    prof_launch(PROF_L0_SWEEP, b_post, L, [&] {
-        L.run(nb0, L0PostRed<DIM, T>{g, v, b0, x0, U, hd, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<T>(L0.Pa),
-                                     vec_x<T>(L1), gate});
+    // black coarse correction, then the red pass (fusing the two reads every
+    // black correction four times and was measured slower)
+    prof_launch(PROF_L0_TRANSFER, b_prol, L, [&] {
+        L.run(nb0, L0ProlongBlack<DIM, T>{g, x0, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<T>(L0.Pa), vec_x<T>(L1),
+                                          gate});
+    });
+    prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
+        L.run(nb0, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
         L.run(nb0, L0Sweep<DIM, T>{g, 1, v, b0, x0, U, hd, gate});
