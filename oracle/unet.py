@@ -27,8 +27,8 @@ Loss of one sample (psi, psi_b, target) at (mu, dmu), the target already
 phase-aligned to psi, with w = (t - psi_b) / dmu the correction to learn:
 L = sum_i d_i |o_i - w_i|^2 / (sum_i d_i |w_i|^2 + EPS sum_i d_i), i.e.
 ||D^(1/2)(psi_pred - t)||^2 relative to ||D^(1/2)(psi_b - t)||^2 (so every
-sample weighs about the same; just below 1 for a zero network), the floor EPS
-keeping samples whose base start is already exact from dominating.
+sample weighs about the same; just below 1 for a zero network), the tiny
+floor EPS only guarding the division.
 
 Parameters: one flat vector; per layer the weights W[co, ky, kx, ci]
 (row-major, ky/kx = 0..2 for offsets -1..1) followed by the bias b[co]; the
@@ -225,7 +225,7 @@ def backward(theta, specs, levels, tape, do):
     return np.concatenate([np.concatenate([g[0].ravel(), g[1].ravel()]) for g in grads])
 
 
-EPS = 1e-4
+EPS = 1e-10
 
 
 def loss_and_grad_output(o, psi_b, target, dmu, vol, N):
