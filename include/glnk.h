@@ -310,7 +310,7 @@ gl_status gl_unet_predict(gl_unet *unet, const gl_mesh *mesh, const void *psi, c
 
 /* Loss of one sample and (host_grad != NULL) the parameter gradient:
  * with w = (t - psi_base) / dmu,
- * L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + 1e-4) (the squared error
+ * L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + 1e-10) (the squared error
  * of the prediction relative to that of the base start, floored),
  * the target already aligned to psi in phase (gl_secant_predict(mesh, psi,
  * target, -1, out) aligns it).  Synchronous. */

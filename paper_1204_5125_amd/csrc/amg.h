@@ -38,6 +38,7 @@ struct Level {
     Csr P, R;
     DevBuf<int> rsrc;           // R entry q = conj(P entry rsrc[q])
     DevBuf<double> rho;         // max_i sum_j |A_ij| / A_ii (device scalar)
+    DevBuf<int> rap_tp, rap_trip;  // products (p, q, s) of each entry of A_{l+1}, upper triangle
     // Copies used by the V-cycle: levels >= 1 renumbered so that every colour
     // is one contiguous row range (new index r' = position in cperm).
     DevBuf<int> perm, iperm;        // new -> old, old -> new (l >= 1)

@@ -484,29 +484,65 @@ __global__ void k_r_values(int nnz, const int *rsrc, const double2 *pv, double2 
     if (q < nnz) rv[q] = cconj(pv[rsrc[q]]);
 }
 
-// upper triangle (J >= I) of R A P, products accumulated in ascending order
-__global__ void k_rap_upper(int nc, const int *rrp, const int *rci, const double2 *rv, const int *arp,
-                            const int *aci, const double2 *av, const int *prp, const int *pci,
-                            const double2 *pv, const int *crp, const int *cci, double2 *cv)
+// Upper triangle (J >= I) of R A P.  The products of each stored entry are
+// listed once per hierarchy (symbolic), in the order of the row traversal
+// p (R row), q (A row), s (P row), and the numeric setup sums them in that
+// order, one thread per entry.
+template <class F>
+__device__ __forceinline__ void rap_traverse(int I, const int *rrp, const int *rci, const int *arp,
+                                             const int *aci, const int *prp, const int *pci, const int *cci,
+                                             int cb, int ce, F &&f)
 {
-    const int I = blockIdx.x * kBlock + threadIdx.x;
-    if (I >= nc) return;
-    const int cb = crp[I], ce = crp[I + 1];
-    for (int t = cb; t < ce; ++t) cv[t] = make_double2(0.0, 0.0);
     for (int p = rrp[I]; p < rrp[I + 1]; ++p) {
         const int i = rci[p];
-        const double2 r = rv[p];
         for (int q = arp[i]; q < arp[i + 1]; ++q) {
-            const double2 ra = cmul(r, av[q]);
             const int j = aci[q];
             for (int s = prp[j]; s < prp[j + 1]; ++s) {
                 const int J = pci[s];
                 if (J < I) continue;
                 const int t = find_col(cci, cb, ce, J);
-                if (t < ce && cci[t] == J) cv[t] = cadd(cv[t], cmul(ra, pv[s]));
+                if (t < ce && cci[t] == J) f(t, p, q, s);
             }
         }
     }
+}
+
+__global__ void k_rap_count(int nc, const int *rrp, const int *rci, const int *arp, const int *aci,
+                            const int *prp, const int *pci, const int *crp, const int *cci, int *cnt)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    rap_traverse(I, rrp, rci, arp, aci, prp, pci, cci, crp[I], crp[I + 1],
+                 [&](int t, int, int, int) { cnt[t] += 1; });
+}
+
+__global__ void k_rap_fill(int nc, const int *rrp, const int *rci, const int *arp, const int *aci,
+                           const int *prp, const int *pci, const int *crp, const int *cci, const int *tp,
+                           int *fill, int *trip)
+{
+    const int I = blockIdx.x * kBlock + threadIdx.x;
+    if (I >= nc) return;
+    rap_traverse(I, rrp, rci, arp, aci, prp, pci, cci, crp[I], crp[I + 1], [&](int t, int p, int q, int s) {
+        const int k = tp[t] + fill[t]++;
+        trip[3 * k] = p;
+        trip[3 * k + 1] = q;
+        trip[3 * k + 2] = s;
+    });
+}
+
+// cv[t] = sum of (R_p A_q) P_s over the products of entry t (0 for J < I)
+__global__ void k_rap_values(int nnz, const int *__restrict__ tp, const int *__restrict__ trip,
+                             const double2 *__restrict__ rv, const double2 *__restrict__ av,
+                             const double2 *__restrict__ pv, double2 *__restrict__ cv)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nnz) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int k = tp[t]; k < tp[t + 1]; ++k) {
+        const double2 ra = cmul(rv[trip[3 * k]], av[trip[3 * k + 1]]);
+        acc = cadd(acc, cmul(ra, pv[trip[3 * k + 2]]));
+    }
+    cv[t] = acc;
 }
 
 __global__ void k_rap_mirror(int nc, const int *crp, const int *cci, double2 *cv)
@@ -546,8 +582,8 @@ __global__ void k_dense_from_csr(int n, const int *rp, const int *ci, const doub
 // status = 1 if a pivot is not positive relative to the largest diagonal.
 // Cholesky factor of the Hermitian coarsest operator, in place (lower
 // triangle, row-major), left-looking one column at a time; the pivot's sum
-// and each row's dot product run in parallel (status 1: not positive
-// definite relative to the largest diagonal entry).
+// runs over the work-group and each row's dot product over a wave (status 1:
+// not positive definite relative to the largest diagonal entry).
 __global__ __launch_bounds__(1024) void k_cholesky(int n, double2 *M, int *status)
 {
     __shared__ double sm[1024 / 64];
@@ -580,11 +616,31 @@ __global__ __launch_bounds__(1024) void k_cholesky(int n, double2 *M, int *statu
         }
         __syncthreads();
         if (bad) break;
-        for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
-            const double2 *Li = M + (size_t)i * n;
-            double2 s = Li[j];
-            for (int k = 0; k < j; ++k) s = csub(s, cmul(Li[k], cconj(Lj[k])));
-            M[(size_t)i * n + j] = cscale(s, 1.0 / ljj);
+        // rows below the pivot: a wave per group of four rows, the dot
+        // products over k split across the lanes
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+        for (int i0 = j + 1 + 4 * wave; i0 < n; i0 += 4 * nw) {
+            double2 acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = make_double2(0.0, 0.0);
+            for (int k = lane; k < j; k += 64) {
+                const double2 ljk = cconj(Lj[k]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u < n) acc[u] = cadd(acc[u], cmul(M[(size_t)(i0 + u) * n + k], ljk));
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                acc[u].x = wave_sum(acc[u].x);
+                acc[u].y = wave_sum(acc[u].y);
+            }
+            if (lane == 0)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u < n) {
+                        double2 &mij = M[(size_t)(i0 + u) * n + j];
+                        mij = cscale(csub(mij, acc[u]), 1.0 / ljj);
+                    }
         }
         __syncthreads();
     }
@@ -851,6 +907,25 @@ static void transfer_patterns(gl_precond *pre, int l, hipStream_t s)
                                          L.P.rp.get(), L.P.ci.get(), Nx.A.rp.get(), nullptr, Nx.A.ci.get(),
                                          err.get());
     GLK_CHECK_LAUNCH();
+    // product lists of the upper triangle for the numeric Galerkin product
+    const int nnzc = Nx.A.nnz;
+    DevBuf<int> pc(std::max(1, nnzc));
+    GLK_HIP(hipMemsetAsync(pc.get(), 0, sizeof(int) * std::max(1, nnzc), s));
+    k_rap_count<<<nbc, kBlock, 0, s>>>(nc, L.R.rp.get(), L.R.ci.get(), L.A.rp.get(), L.A.ci.get(), L.P.rp.get(),
+                                       L.P.ci.get(), Nx.A.rp.get(), Nx.A.ci.get(), pc.get());
+    GLK_CHECK_LAUNCH();
+    L.rap_tp.alloc((size_t)nnzc + 1);
+    const int64_t ntrip = scan_excl(pc.get(), L.rap_tp.get(), nnzc, s);
+    if (ntrip > (int64_t)1 << 30) fail(GL_ERR_UNSUPPORTED, "Galerkin product: too many products");
+    const int total = (int)ntrip;
+    GLK_HIP(hipMemcpyAsync(L.rap_tp.get() + nnzc, &total, sizeof(int), hipMemcpyHostToDevice, s));
+    L.rap_trip.alloc((size_t)3 * std::max<int64_t>(1, ntrip));
+    GLK_HIP(hipMemsetAsync(pc.get(), 0, sizeof(int) * std::max(1, nnzc), s));
+    k_rap_fill<<<nbc, kBlock, 0, s>>>(nc, L.R.rp.get(), L.R.ci.get(), L.A.rp.get(), L.A.ci.get(), L.P.rp.get(),
+                                      L.P.ci.get(), Nx.A.rp.get(), Nx.A.ci.get(), L.rap_tp.get(), pc.get(),
+                                      L.rap_trip.get());
+    GLK_CHECK_LAUNCH();
+    GLK_HIP(hipStreamSynchronize(s));
 }
 
 static void alloc_values(gl_precond *pre)
@@ -1024,9 +1099,9 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
                                          L.P.ci.get(), L.P.v64.get());
         k_r_values<<<blocks_for(L.R.nnz), kBlock, 0, s>>>(L.R.nnz, L.rsrc.get(), L.P.v64.get(), L.R.v64.get());
         const int nbc = blocks_for(L.nc);
-        k_rap_upper<<<nbc, kBlock, 0, s>>>(L.nc, L.R.rp.get(), L.R.ci.get(), L.R.v64.get(), L.A.rp.get(),
-                                           L.A.ci.get(), L.A.v64.get(), L.P.rp.get(), L.P.ci.get(),
-                                           L.P.v64.get(), Nx.A.rp.get(), Nx.A.ci.get(), Nx.A.v64.get());
+        k_rap_values<<<blocks_for(Nx.A.nnz), kBlock, 0, s>>>(Nx.A.nnz, L.rap_tp.get(), L.rap_trip.get(),
+                                                             L.R.v64.get(), L.A.v64.get(), L.P.v64.get(),
+                                                             Nx.A.v64.get());
         k_rap_mirror<<<nbc, kBlock, 0, s>>>(L.nc, Nx.A.rp.get(), Nx.A.ci.get(), Nx.A.v64.get());
         GLK_CHECK_LAUNCH();
     }

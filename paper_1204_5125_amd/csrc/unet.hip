@@ -336,9 +336,8 @@ __global__ void k_predict(int P, const double2 *__restrict__ psi, const float *_
 }
 
 // partial sums of sum_i d_i (|w_i|^2 + eps), w = (t - psi_b) / dmu: the loss
-// normaliser, floored so that a sample whose base start is already exact
-// cannot blow up the gradient
-constexpr double kLossEps = 1e-4;
+// normaliser (the tiny floor only guards the division)
+constexpr double kLossEps = 1e-10;
 
 __global__ __launch_bounds__(kBlock) void k_loss_norm(GeomT<double> g, const double2 *__restrict__ psib,
                                                       const double2 *__restrict__ tgt, double dmu, RedSlot slot)

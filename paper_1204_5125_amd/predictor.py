@@ -46,7 +46,8 @@ def make_pairs(mesh, states, strides=(1, 2, 3), jump_newton=6):
     """Training samples (psi_i, secant start, aligned psi_j, mu_i, mu_j - mu_i)
     for j = i + s inside one continuation segment, leaving out spans where the
     branch jumped (a state in (i, j] needed more than jump_newton Newton
-    steps).  The target is rotated by the global phase that aligns it with
+    steps) and targets that needed no Newton step (the start was already the
+    solution, e.g. the normal state psi = 0: nothing to learn).  The target is rotated by the global phase that aligns it with
     psi_i (gl_secant_predict with ratio -1 gives e^{i chi} target); the secant
     start uses psi_{i-1}."""
     import torch
@@ -56,6 +57,8 @@ def make_pairs(mesh, states, strides=(1, 2, 3), jump_newton=6):
             mu_i, psi_i, seg, _ = states[i]
             mu_j, psi_j, seg_j, _ = states[i + s]
             if seg_j != seg or any(states[k][3] > jump_newton for k in range(i, i + s + 1)):
+                continue
+            if states[i + s][3] == 0:
                 continue
             t = torch.empty_like(psi_i)
             glnk.gl_secant_predict(mesh, psi_i, psi_j, -1.0, t)
