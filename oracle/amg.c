@@ -26,8 +26,9 @@
  *                   aggregation keeps more than 0.85 n_l nodes
  *   coarse solve  : dense Cholesky of the coarsest operator
  *   colours       : level 0 of a tensor grid: parity of the index sum; otherwise
- *                   greedy by decreasing key_l' (salt l + 101), smallest colour
- *                   unused by already coloured neighbours
+ *                   greedy by decreasing colour priority (largest degree first,
+ *                   then the hash with salt l + 101, then the index), smallest
+ *                   colour unused by already coloured neighbours
  *   SGS sweep     : colours 0 .. C-1, then C-2 .. 0
  *   V-cycle       : x = SGS(0, b); r = b - A x; x += P V(R r); x = SGS(x, b)
  */
@@ -54,7 +55,14 @@ static uint64_t key_with_salt(int64_t i, uint32_t salt)
 }
 
 static uint64_t mis_key(int64_t i, int l) { return key_with_salt(i, (uint32_t)(l + 1)); }
-static uint64_t color_key(int64_t i, int l) { return key_with_salt(i, (uint32_t)(l + 101)); }
+/* colour priority: largest degree first, then the hashed key (upper 22
+ * bits), then the index: ((min(deg, 1023) << 54) | (fmix32 >> 10) << 32 | i */
+static uint64_t color_key(int64_t i, int64_t deg, int l)
+{
+    const uint32_t s = 0x9E3779B9u * (uint32_t)(l + 101);
+    const uint64_t d = (uint64_t)(deg < 1023 ? deg : 1023);
+    return (d << 54) | ((uint64_t)(fmix32((uint32_t)i ^ s) >> 10) << 32) | (uint64_t)(uint32_t)i;
+}
 
 typedef struct { uint64_t key; int64_t i; } keyed;
 
@@ -146,7 +154,17 @@ static void colour_level(orc_level *L, int l, int grid_dim, const int64_t *grid_
         return;
     }
     for (int64_t i = 0; i < n; ++i) L->color[i] = -1;
-    int64_t *ord = order_by_key(n, l, color_key);
+    keyed *kk = malloc((size_t)n * sizeof(keyed));
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t deg = 0;
+        for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p) deg += L->ci[p] != i;
+        kk[i].key = color_key(i, deg, l);
+        kk[i].i = i;
+    }
+    qsort(kk, (size_t)n, sizeof(keyed), cmp_keyed_desc);
+    int64_t *ord = malloc((size_t)n * sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) ord[i] = kk[i].i;
+    free(kk);
     int maxc = 0;
     char *used = calloc((size_t)n + 2, 1);
     for (int64_t t = 0; t < n; ++t) {

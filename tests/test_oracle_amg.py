@@ -30,6 +30,12 @@ def keys(n, salt):
     return [(fmix32(i ^ s) << 32) | i for i in range(n)]
 
 
+def colour_keys(nb, salt):
+    """Largest degree first, then the upper 22 hash bits, then the index."""
+    s = (0x9E3779B9 * salt) & 0xFFFFFFFF
+    return [(min(len(nb[i]), 1023) << 54) | ((fmix32(i ^ s) >> 10) << 32) | i for i in range(len(nb))]
+
+
 def neighbours(A):
     A = sp.csr_matrix(A)
     return [[j for j in A.indices[A.indptr[i]:A.indptr[i + 1]] if j != i] for i in range(A.shape[0])]
@@ -164,7 +170,8 @@ def test_colouring_proper_and_greedy(hierarchies):
             assert np.all(L["color"][A.row[off]] != L["color"][A.col[off]])
             assert L["ncolors"] == L["color"].max() + 1
             if l > 0 and L["n"] <= 400:
-                assert jones_plassmann(neighbours(L["A"]), keys(L["n"], l + 101)) == list(L["color"])
+                nb = neighbours(L["A"])
+                assert jones_plassmann(nb, colour_keys(nb, l + 101)) == list(L["color"])
 
 
 def test_transfer_and_galerkin_operators(hierarchies):
