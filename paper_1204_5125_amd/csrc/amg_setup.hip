@@ -382,6 +382,15 @@ __global__ void k_parity_colour(Geom g, int *col)
     col[i] = (c[0] + c[1] + c[2]) & 1;
 }
 
+// colour priority: largest degree first (number of off-diagonal entries,
+// capped at 1023), then the upper 22 bits of the hash, then the index
+__device__ __forceinline__ unsigned long long colour_key(int i, const int *rp, unsigned salt)
+{
+    const unsigned long long d = (unsigned long long)min(rp[i + 1] - rp[i] - 1, 1023);
+    return (d << 54) | ((unsigned long long)(fmix32((uint32_t)i ^ (0x9E3779B9u * salt)) >> 10) << 32) |
+           (unsigned long long)(uint32_t)i;
+}
+
 __global__ void k_jp_ready(int n, const int *rp, const int *ci, const int *col, unsigned salt, int *ready)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -389,10 +398,10 @@ __global__ void k_jp_ready(int n, const int *rp, const int *ci, const int *col, 
     int r = 0;
     if (col[i] < 0) {
         r = 1;
-        const unsigned long long k = keyof(i, salt);
+        const unsigned long long k = colour_key(i, rp, salt);
         for (int p = rp[i]; p < rp[i + 1]; ++p) {
             const int j = ci[p];
-            if (j != i && col[j] < 0 && keyof(j, salt) > k) { r = 0; break; }
+            if (j != i && col[j] < 0 && colour_key(j, rp, salt) > k) { r = 0; break; }
         }
     }
     ready[i] = r;

@@ -335,11 +335,15 @@ __global__ void k_predict(int P, const double2 *__restrict__ psi, const float *_
     out[p] = make_double2(psi[p].x + dmu * o[2 * p], psi[p].y + dmu * o[2 * p + 1]);
 }
 
-// partial sums of sum_i d_i (|w_i|^2 + eps), w = (t - psi_b) / dmu: the loss
-// normaliser (the tiny floor only guards the division)
-constexpr double kLossEps = 1e-10;
+// partial sums of the loss normaliser sum_i d_i (|w_i|^2 + kLossFloor |v_i|^2
+// + kLossEps), w = (t - psi_b) / dmu, v = (t - psi) / dmu: the base start's
+// error, floored at a fraction of the constant start's so that samples whose
+// secant start is already nearly exact cannot dominate
+constexpr double kLossFloor = 1e-2;
+constexpr double kLossEps = 1e-12;
 
-__global__ __launch_bounds__(kBlock) void k_loss_norm(GeomT<double> g, const double2 *__restrict__ psib,
+__global__ __launch_bounds__(kBlock) void k_loss_norm(GeomT<double> g, const double2 *__restrict__ psi,
+                                                      const double2 *__restrict__ psib,
                                                       const double2 *__restrict__ tgt, double dmu, RedSlot slot)
 {
     __shared__ double sm[kBlock / 64];
@@ -351,7 +355,8 @@ __global__ __launch_bounds__(kBlock) void k_loss_norm(GeomT<double> g, const dou
         double sf[3];
         const double d = node_volume<2, double>(g, c, sf);
         const double wr = (tgt[p].x - psib[p].x) / dmu, wi = (tgt[p].y - psib[p].y) / dmu;
-        part = d * (wr * wr + wi * wi + kLossEps);
+        const double vr = (tgt[p].x - psi[p].x) / dmu, vi = (tgt[p].y - psi[p].y) / dmu;
+        part = d * (wr * wr + wi * wi + kLossFloor * (vr * vr + vi * vi) + kLossEps);
     }
     block_reduce_store(part, slot, sm, blockIdx.x);
 }
@@ -715,7 +720,7 @@ static double unet_loss(gl_unet *u, const gl_mesh *m, const double2 *psi, const 
     const int P0 = m->g.n, nb = blocks_for(P0);
     const GeomT<double> g = geom_t<double>(m->g);
     double *norm = m->dscal.get() + 5;
-    k_loss_norm<<<nb, kBlock, 0, s>>>(g, psib, tgt, dmu, red_slot(m, 3));
+    k_loss_norm<<<nb, kBlock, 0, s>>>(g, psi, psib, tgt, dmu, red_slot(m, 3));
     launch_finalize(red_slot(m, 3).partials, nb, FIN_STORE, nullptr, norm, nullptr, s);
     k_loss<<<nb, kBlock, 0, s>>>(g, psib, tgt, u->o.get(), dmu, norm, scale, u->dout.get(), red_slot(m, 2));
     launch_finalize(red_slot(m, 2).partials, nb, FIN_STORE, nullptr, m->dscal.get() + 4, nullptr, s);
