@@ -25,12 +25,11 @@ value by value:
 
 Loss of one sample (psi, psi_b, target) at (mu, dmu), the target already
 phase-aligned to psi, with w = (t - psi_b) / dmu the correction to learn:
-L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + FLOOR |v_i|^2 + EPS),
-v = (t - psi) / dmu, i.e. ||D^(1/2)(psi_pred - t)||^2 relative to
-||D^(1/2)(psi_b - t)||^2 (every sample weighs about the same; just below 1
-for a zero network), floored at FLOOR times the constant start's error so
-that samples whose secant start is already nearly exact cannot dominate
-(EPS only guards the division).
+L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + EPS), i.e.
+||D^(1/2)(psi_pred - t)||^2 relative to ||D^(1/2)(psi_b - t)||^2 (every
+sample weighs about the same; just below 1 for a zero network), with an
+absolute floor EPS (in slope^2 units) so that samples whose secant start is
+already nearly exact cannot dominate.
 
 Parameters: one flat vector; per layer the weights W[co, ky, kx, ci]
 (row-major, ky/kx = 0..2 for offsets -1..1) followed by the bias b[co]; the
@@ -227,17 +226,15 @@ def backward(theta, specs, levels, tape, do):
     return np.concatenate([np.concatenate([g[0].ravel(), g[1].ravel()]) for g in grads])
 
 
-EPS = 1e-12
-FLOOR = 1e-2
+EPS = 1e-4
 
 
 def loss_and_grad_output(o, psi, psi_b, target, dmu, vol, N):
     """Loss of one aligned sample and dL/do (2, N, N)."""
     want = (target - psi_b).reshape(N, N) / dmu
-    v = (target - psi).reshape(N, N) / dmu
     r = o[0] + 1j * o[1] - want
     w = vol.reshape(N, N)
-    sw = (w * (np.abs(want) ** 2 + FLOOR * np.abs(v) ** 2 + EPS)).sum()
+    sw = (w * (np.abs(want) ** 2 + EPS)).sum()
     L = float((w * np.abs(r) ** 2).sum() / sw)
     do = np.stack([2.0 * w * r.real / sw, 2.0 * w * r.imag / sw])
     return L, do

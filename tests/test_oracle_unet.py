@@ -90,12 +90,11 @@ def test_loss_zero_at_exact_correction_and_prediction_form():
     specs = U.layer_specs(2, 4)
     theta = np.zeros(U.num_params(specs))
     # a zero network returns the base step (the secant predictor); its loss is
-    # S / (S + FLOOR V + EPS |Omega|), S = sum d |w|^2 with w = 1 + 2i and
-    # V = sum d |v|^2 with v = (0.5 - 1i) + (1 + 2i) here
+    # S / (S + EPS |Omega|), S = sum d |w|^2 with w = 1 + 2i here
     assert np.array_equal(U.predict(theta, specs, 2, psi, psb, 0.3, 0.02, N), psb)
     L0, _ = U.loss_and_grad(theta, specs, 2, psi, psb, 0.3, 0.02, tgt, U.volumes(N, 2.0), N)
-    S, V = 5.0 * 4.0, abs(1.5 + 1j) ** 2 * 4.0
-    assert L0 == pytest.approx(S / (S + U.FLOOR * V + U.EPS * 4.0), rel=1e-13)
+    S = 5.0 * 4.0
+    assert L0 == pytest.approx(S / (S + U.EPS * 4.0), rel=1e-13)
 
 
 def test_adam_first_step_and_bias_correction():
