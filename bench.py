@@ -218,6 +218,27 @@ def bench_continuation(args):
                            log=lambda m: log(f"{m} ({time.perf_counter() - t0:.1f} s)"))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    # U-Net forward throughput on the matrix cores (BF16, FP32 accumulation)
+    shapes = glnk.unet_layer_shapes(levels, base)
+    Nl = [(N - 1) // (1 << l) + 1 for l in range(levels)]
+    lvl = [l for l in range(levels) for _ in range(2)] + [l for l in range(levels - 2, -1, -1) for _ in range(2)]
+    flops = sum(2.0 * Nl[l] ** 2 * 9 * ci * co for l, (ci, co, k) in zip(lvl, shapes[:-1]))
+    flops += 2.0 * Nl[0] ** 2 * shapes[-1][0] * shapes[-1][1]
+    out_t = torch.empty_like(ones)
+    net.predict(mesh, states[1][1], states[1][1], states[1][0], 0.02, out_t)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        net.predict(mesh, states[1][1], states[1][1], states[1][0], 0.02, out_t)
+    ev1.record()
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1) / 10
+    unet_roof = {"bound": "mfma", "kernel": "U-Net forward (k_conv3x3 and transfers)",
+                 "achieved": flops / (fwd_ms * 1e-3) / 1e12, "peak": 2500.0, "unit": "TFLOP/s",
+                 "frac": flops / (fwd_ms * 1e-3) / 1e12 / 2500.0, "traffic": None,
+                 "forward_ms": fwd_ms, "flop_per_forward": flops}
+    log(f"[bench] U-Net forward: {fwd_ms:.2f} ms, {unet_roof['achieved']:.1f} TFLOP/s")
     mus = [0.02 * k for k in range(101)]
     runs = {}
     for name, prec, learned in [("fp64_secant", glnk.GL_FP64, None), ("fp64_learned", glnk.GL_FP64, "residual"),
@@ -249,7 +270,8 @@ def bench_continuation(args):
         "config": {"workload": "2D 513x513 grid, side 8, mu 0 -> 2 in steps of 0.02 (Newton to 1e-10); U-Net 4 levels, "
                                "32 base channels, BF16 / FP32 accumulation",
                    "training_states": len(states), "training_pairs": len(pairs), "epochs": args.epochs},
-        "runs": runs, "training": {"sweep_seconds": t_sweep, "train_seconds": t_train,
+        "runs": runs, "roofline": unet_roof,
+        "training": {"sweep_seconds": t_sweep, "train_seconds": t_train,
                                    "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]},
     }
     print(json.dumps(out), flush=True)
@@ -284,7 +306,11 @@ def bench_cube(args):
     psi = torch.empty_like(psi0)
     out = {}
     first = {}
+    from paper_1204_5125_amd import autotune
+    tiles = {}
     for name, prec in [("fp32", glnk.GL_FP32), ("fp64", glnk.GL_FP64)]:
+        tiles[name] = autotune.tune(mesh, psi0, precision=prec, max_coarse=MAX_COARSE, cache=args.tile_cache,
+                                    log=log)
         h = glnk.PrecondHandle(mesh)
         inner = RTOL if prec == glnk.GL_FP64 else 0.0
         kw = dict(krylov_rtol=RTOL, krylov_max_iter=8000, poll_every=16, precision=prec, inner_rtol=inner,
@@ -292,6 +318,7 @@ def bench_cube(args):
         psi.copy_(psi0)
         glnk.gl_newton_solve(mesh, psi, fixed_steps=1, **kw)  # warm-up: hierarchy + graphs
         first[name] = psi.clone()
+        glnk.gl_precond_set_tiles(h, *tiles[name])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -314,7 +341,8 @@ def bench_cube(args):
         "data": "synthetic: seeded random-phase psi0 on a uniform cube grid",
         "config": {"workload": "3D 129^3 grid (2,146,689 nodes), side 5, mu 0.6 along (1,1,1)/sqrt3; 4 Newton "
                                "steps from psi0 = 0.9 exp(i theta), seed 0, MINRES + R_1 to rtol 1e-10",
-                   "nodes": mesh.n, "amg_max_coarse": MAX_COARSE},
+                   "nodes": mesh.n, "amg_max_coarse": MAX_COARSE,
+                   "tiles": {k: list(v) for k, v in tiles.items()}},
         "fp32": out["fp32"], "fp64_precond": out["fp64"],
         "fp32_vcycle_output_rel_error": prec_err,
         "first_newton_update_fp32_vs_fp64_rel_error": upd_err,

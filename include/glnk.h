@@ -309,10 +309,9 @@ gl_status gl_unet_predict(gl_unet *unet, const gl_mesh *mesh, const void *psi, c
                           double dmu, void *psi_out, gl_stream stream);
 
 /* Loss of one sample and (host_grad != NULL) the parameter gradient:
- * with w = (t - psi_base) / dmu and v = (t - psi) / dmu,
- * L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + 0.01 |v_i|^2 + 1e-12)
- * (the squared error of the prediction relative to that of the base start,
- * floored at a hundredth of the constant start's),
+ * with w = (t - psi_base) / dmu,
+ * L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + 1e-4) (the squared error
+ * of the prediction relative to that of the base start, floored),
  * the target already aligned to psi in phase (gl_secant_predict(mesh, psi,
  * target, -1, out) aligns it).  Synchronous. */
 gl_status gl_unet_loss_grad(gl_unet *unet, const gl_mesh *mesh, const void *psi, const void *psi_base, double mu,

@@ -335,12 +335,11 @@ __global__ void k_predict(int P, const double2 *__restrict__ psi, const float *_
     out[p] = make_double2(psi[p].x + dmu * o[2 * p], psi[p].y + dmu * o[2 * p + 1]);
 }
 
-// partial sums of the loss normaliser sum_i d_i (|w_i|^2 + kLossFloor |v_i|^2
-// + kLossEps), w = (t - psi_b) / dmu, v = (t - psi) / dmu: the base start's
-// error, floored at a fraction of the constant start's so that samples whose
-// secant start is already nearly exact cannot dominate
-constexpr double kLossFloor = 1e-2;
-constexpr double kLossEps = 1e-12;
+// partial sums of the loss normaliser sum_i d_i (|w_i|^2 + kLossEps),
+// w = (t - psi_b) / dmu: the base start's error with an absolute floor (slope^2
+// units) so that samples whose secant start is already nearly exact cannot
+// dominate
+constexpr double kLossEps = 1e-4;
 
 __global__ __launch_bounds__(kBlock) void k_loss_norm(GeomT<double> g, const double2 *__restrict__ psi,
                                                       const double2 *__restrict__ psib,
@@ -355,8 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_norm(GeomT<double> g, const dou
         double sf[3];
         const double d = node_volume<2, double>(g, c, sf);
         const double wr = (tgt[p].x - psib[p].x) / dmu, wi = (tgt[p].y - psib[p].y) / dmu;
-        const double vr = (tgt[p].x - psi[p].x) / dmu, vi = (tgt[p].y - psi[p].y) / dmu;
-        part = d * (wr * wr + wi * wi + kLossFloor * (vr * vr + vi * vi) + kLossEps);
+        part = d * (wr * wr + wi * wi + kLossEps);
     }
     block_reduce_store(part, slot, sm, blockIdx.x);
 }
