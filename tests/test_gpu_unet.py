@@ -36,11 +36,13 @@ def host(t):
 
 
 def pair(seed, mu=0.6):
+    """(mesh, psi, base start, aligned target)."""
     mo = oracle.Mesh(2, (N, N), (SIDE, SIDE), mu=mu)
     psi = inputs.random_phase_state(mo.n, seed=seed)
+    psb = psi * (1.0 + 0.02 * inputs.random_complex(mo.n, seed=seed + 200))
     tgt = psi * (1.0 + 0.03 * inputs.random_complex(mo.n, seed=seed + 100)) * np.exp(0.4j)
     tgt = oc.secant_predict(mo, psi, tgt, -1.0)  # aligned to psi
-    return mo, psi, tgt
+    return mo, psi, psb, tgt
 
 
 def params(glnk, seed=7):
@@ -54,7 +56,7 @@ def rel(a, b):
 
 
 def test_forward_matches_oracle(glnk):
-    mo, psi, _ = pair(1)
+    mo, psi, psb, _ = pair(1)
     theta = params(glnk)
     net = glnk.UNet(LEVELS, BASE)
     assert net.n_params == U.num_params(U.layer_specs(LEVELS, BASE))
@@ -62,22 +64,22 @@ def test_forward_matches_oracle(glnk):
     assert np.array_equal(net.get_params(), theta)
     mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
     out = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
-    net.predict(mg, dev(psi), 0.6, 0.02, out)
-    og = (host(out) - psi) / 0.02
-    oo = U.predict(theta.astype(np.float64), U.layer_specs(LEVELS, BASE), LEVELS, psi, 0.6, 0.02, N)
-    oo = (oo - psi) / 0.02
+    net.predict(mg, dev(psi), dev(psb), 0.6, 0.02, out)
+    og = (host(out) - psb) / 0.02
+    oo = U.predict(theta.astype(np.float64), U.layer_specs(LEVELS, BASE), LEVELS, psi, psb, 0.6, 0.02, N)
+    oo = (oo - psb) / 0.02
     assert rel(og, oo) < 3e-2
 
 
 def test_loss_and_gradient_match_oracle(glnk):
-    mo, psi, tgt = pair(2)
+    mo, psi, psb, tgt = pair(2)
     theta = params(glnk, seed=8)
     specs = U.layer_specs(LEVELS, BASE)
     net = glnk.UNet(LEVELS, BASE)
     net.set_params(theta)
     mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
-    Lg, gg = net.loss_grad(mg, dev(psi), 0.6, 0.02, dev(tgt))
-    Lo, go = U.loss_and_grad(theta.astype(np.float64), specs, LEVELS, psi, 0.6, 0.02, tgt,
+    Lg, gg = net.loss_grad(mg, dev(psi), dev(psb), 0.6, 0.02, dev(tgt))
+    Lo, go = U.loss_and_grad(theta.astype(np.float64), specs, LEVELS, psi, psb, 0.6, 0.02, tgt,
                              U.volumes(N, SIDE), N)
     assert Lg == pytest.approx(Lo, rel=3e-2)
     cos = gg @ go / (np.linalg.norm(gg) * np.linalg.norm(go))
@@ -91,13 +93,13 @@ def test_loss_and_gradient_match_oracle(glnk):
 
 
 def test_adam_step_matches_oracle_update(glnk):
-    mo, psi, tgt = pair(3)
+    mo, psi, psb, tgt = pair(3)
     theta = params(glnk, seed=9)
     net = glnk.UNet(LEVELS, BASE)
     net.set_params(theta)
     mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
-    _, g = net.loss_grad(mg, dev(psi), 0.6, 0.02, dev(tgt))
-    net.train_step(mg, [dev(psi)], [0.6], [0.02], [dev(tgt)], lr=1e-3)
+    _, g = net.loss_grad(mg, dev(psi), dev(psb), 0.6, 0.02, dev(tgt))
+    net.train_step(mg, [dev(psi)], [dev(psb)], [0.6], [0.02], [dev(tgt)], lr=1e-3)
     th1 = net.get_params()
     m, v = np.zeros(theta.size), np.zeros(theta.size)
     want = U.adam_step(theta.astype(np.float64), m, v, g.astype(np.float64), 1, lr=1e-3)
@@ -105,21 +107,22 @@ def test_adam_step_matches_oracle_update(glnk):
 
 
 def test_training_reduces_the_loss(glnk):
-    """A learnable target (the derivative (0.5 - 0.3i) psi): 60 Adam steps on
-    four pairs halve the loss."""
+    """A learnable target (the correction (0.5 - 0.3i) psi of a constant
+    start): 60 Adam steps on four samples halve the loss."""
     def learnable(seed, mu):
         mo = oracle.Mesh(2, (N, N), (SIDE, SIDE), mu=mu)
         psi = inputs.random_phase_state(mo.n, seed=seed)
-        return mo, psi, psi + 0.02 * (0.5 - 0.3j) * psi
+        return mo, psi, psi, psi + 0.02 * (0.5 - 0.3j) * psi
 
     pairs = [learnable(10 + k, 0.5 + 0.1 * k) for k in range(4)]
     net = glnk.UNet(LEVELS, BASE)
     net.set_params(params(glnk, seed=11) * 0.5)
     mg = glnk.Mesh(2, (N, N), (SIDE, SIDE), mu=0.6)
-    ps = [dev(p) for _, p, _ in pairs]
-    ts = [dev(t) for _, _, t in pairs]
+    ps = [dev(p) for _, p, _, _ in pairs]
+    bs = [dev(b) for _, _, b, _ in pairs]
+    ts = [dev(t) for _, _, _, t in pairs]
     mus = [0.5 + 0.1 * k for k in range(4)]
-    first = net.train_step(mg, ps, mus, [0.02] * 4, ts, lr=2e-3)
+    first = net.train_step(mg, ps, bs, mus, [0.02] * 4, ts, lr=2e-3)
     for _ in range(60):
-        last = net.train_step(mg, ps, mus, [0.02] * 4, ts, lr=2e-3)
+        last = net.train_step(mg, ps, bs, mus, [0.02] * 4, ts, lr=2e-3)
     assert last < 0.5 * first
