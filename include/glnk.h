@@ -51,7 +51,14 @@ typedef enum {
     GL_ERR_UNSUPPORTED = 8
 } gl_status;
 
-typedef enum { GL_FP64 = 0, GL_FP32 = 1 } gl_precision;
+/* Storage and arithmetic of the V-cycle (the Krylov iteration, the GL residual
+ * and the Newton update are FP64 in every case):
+ *   GL_FP64   every level in FP64;
+ *   GL_FP32   every level and the coarsest solve in FP32;
+ *   GL_MIXED  level 0 (the fine-grid sweeps and transfers, nearly all of the
+ *             V-cycle's memory traffic) in FP32, levels >= 1 and the
+ *             coarsest solve in FP64. */
+typedef enum { GL_FP64 = 0, GL_FP32 = 1, GL_MIXED = 2 } gl_precision;
 
 typedef struct gl_mesh gl_mesh;
 typedef struct gl_precond gl_precond;
@@ -192,6 +199,14 @@ typedef struct {
                           MINRES run stopped on its recurrence estimate with an
                           FP64 preconditioner (or none), refinement with 1e-5
                           with an FP32 one */
+    double relax_rtol; /* GL_FP32 / GL_MIXED preconditioner only, > 0: one
+                          MINRES recurrence applies the FP64 V-cycle until
+                          |eta_j| <= relax_rtol eta_0 and the reduced-precision
+                          V-cycle after that (an inexact Krylov method whose
+                          operator error may grow as the residual falls), run
+                          to rtol and stopped on the true residual (restarted
+                          by refinement if that misses rtol); 0 = the reduced
+                          precision from the first iteration */
 } gl_krylov_opts;
 
 typedef struct {

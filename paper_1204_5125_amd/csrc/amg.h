@@ -70,6 +70,7 @@ struct BottomLevel {
     const C<T> *pv;
     const int *rrp, *rci;
     const C<T> *rv;
+    int pnnz, rnnz;
     C<T> *b, *x, *r;
     // the operator once more as per-colour padded blocks (ELL): row r of
     // colour c holds ewidth[c] entries at eoff[c] + (r - coff[c]) ewidth[c]
@@ -210,8 +211,11 @@ namespace glk {
 // gate (nullable): skip all work when *gate == 0.  When ks != nullptr the
 // kernel that writes z also reduces Re<v, z> and the total is handed to
 // minres_finalize(ks, mode, total).
+// prec: the precision of this application (the handle holds both).
 void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
-                    KrylovScalars *ks, int mode, const Launch &L);
+                    KrylovScalars *ks, int mode, const Launch &L, gl_precision prec);
+void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
+                    KrylovScalars *ks, int mode, const Launch &L);  // in the handle's precision
 void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
                          hipStream_t s);
 void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, double2 *out,

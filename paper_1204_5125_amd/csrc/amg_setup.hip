@@ -723,7 +723,8 @@ __global__ void k_gather_c(int nnz, const int *map, const double2 *src, double2 
     d32[q] = make_float2((float)v.x, (float)v.y);
 }
 
-// padded block of one colour (rows row0 .. row0 + count - 1 of Aa)
+// padded block of one colour (rows row0 .. row0 + count - 1 of Aa), row-major:
+// entry k of row r at r W + k
 __global__ void k_ell_fill(int row0, int count, int W, const int *rp, const int *ci, int *eci, int *emap)
 {
     const int r = blockIdx.x * kBlock + threadIdx.x;
@@ -1180,7 +1181,7 @@ gl_status gl_precond_setup(const gl_mesh *mesh, const void *psi, const gl_amg_op
             fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: handle belongs to another mesh");
         if (!pre && !opts) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: opts required for a new handle");
         if (opts) {
-            if (opts->precision != GL_FP64 && opts->precision != GL_FP32)
+            if (opts->precision != GL_FP64 && opts->precision != GL_FP32 && opts->precision != GL_MIXED)
                 fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: precision");
             if (opts->cycles < 1 || opts->cycles > 1000)
                 fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: cycles must be in 1..1000");

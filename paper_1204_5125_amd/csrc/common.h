@@ -139,6 +139,8 @@ __device__ __forceinline__ double2 widen(double2 a) { return a; }
 template <class T> __device__ __forceinline__ C<T> narrow(double2 a);
 template <> __device__ __forceinline__ double2 narrow<double>(double2 a) { return a; }
 template <> __device__ __forceinline__ float2 narrow<float>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+// complex value in the precision T, from either precision
+template <class T, class V> __device__ __forceinline__ C<T> as_c(V a) { return narrow<T>(widen(a)); }
 
 // ----------------------------------------------------- launch shapes ----
 constexpr int kBlock = 256;

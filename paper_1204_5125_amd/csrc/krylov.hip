@@ -241,6 +241,14 @@ __global__ void k_ks_set(KrylovScalars *ks, double rtol, int max_iter)
     ks->max_iter = max_iter;
 }
 
+// continue a recurrence stopped at an intermediate tolerance
+__global__ void k_ks_resume(KrylovScalars *ks, double rtol)
+{
+    ks->rtol = rtol;
+    ks->converged = 0;
+    ks->running = 1;
+}
+
 __global__ void k_zero(int n, double2 *x)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -270,6 +278,7 @@ struct Ksolve {
     const double2 *rhs;
     double2 *x;
     double2 *v, *vp, *z, *zn, *q, *w, *wp;
+    gl_precision prec;  // of the V-cycle applications
 };
 
 static Ksolve make_ksolve(const gl_mesh *m, const double2 *psi, const gl_precond *pre, const double2 *rhs,
@@ -277,7 +286,20 @@ static Ksolve make_ksolve(const gl_mesh *m, const double2 *psi, const gl_precond
 {
     const size_t n = (size_t)m->g.n;
     double2 *W = m->work.get();
-    return Ksolve{m, psi, pre, rhs, x, W, W + n, W + 2 * n, W + 3 * n, W + 4 * n, W + 5 * n, W + 6 * n};
+    return Ksolve{m,         psi,       pre,       rhs,       x,         W,
+                  W + n,     W + 2 * n, W + 3 * n, W + 4 * n, W + 5 * n, W + 6 * n,
+                  pre ? pre->opts.precision : GL_FP64};
+}
+
+// the roles of the rotating buffers after `iters` further iterations
+static Ksolve rotated(Ksolve k, int iters)
+{
+    if (iters & 1) {
+        std::swap(k.v, k.vp);
+        std::swap(k.z, k.zn);
+        std::swap(k.w, k.wp);
+    }
+    return k;
 }
 
 // x = 0, v = D rhs, z = M^-1 v, gamma_1, eta_0
@@ -291,7 +313,7 @@ static void ksolve_init(const Ksolve &k, double rtol, int max_iter, const Launch
     L.run<KsInit, 64>(1, KsInit{ks, rtol, max_iter});
     L.run(nb, MinresInit<DIM>{g, k.rhs, k.v, k.vp, k.w, k.wp, k.x});
     if (k.pre) {
-        vcycle_enqueue(k.pre, k.v, k.z, nullptr, ks, FIN_MINRES_INIT, L);
+        vcycle_enqueue(k.pre, k.v, k.z, nullptr, ks, FIN_MINRES_INIT, L, k.prec);
     } else {
         L.run(nb, Unprec<DIM>{g, k.v, k.z, nullptr, red_slot(m, 1)});
         launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_INIT, ks, nullptr, nullptr, L);
@@ -312,7 +334,7 @@ static void enqueue_iteration(Ksolve &k, const Launch &L)
     launch_finalize(red_slot(m, 0).partials, nb, FIN_DELTA, ks, nullptr, gate, L);
     prof_launch(PROF_VUPDATE, 64.0 * n, L, [&] { L.run(nb, MinresVupdate{n, k.q, k.v, k.vp, ks}); });
     if (k.pre) {
-        vcycle_enqueue(k.pre, k.vp, k.zn, gate, ks, FIN_MINRES_STEP, L);
+        vcycle_enqueue(k.pre, k.vp, k.zn, gate, ks, FIN_MINRES_STEP, L, k.prec);
     } else {
         L.run(nb, Unprec<DIM>{g, k.vp, k.zn, gate, red_slot(m, 1)});
         launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_STEP, ks, nullptr, gate, L);
@@ -329,7 +351,8 @@ static hipGraphExec_t iteration_graph(Ksolve k, hipStream_t s)
     gl_mesh *m = const_cast<gl_mesh *>(k.m);
     const uint64_t key[6] = {(uint64_t)(uintptr_t)k.psi, (uint64_t)(uintptr_t)k.rhs, (uint64_t)(uintptr_t)k.x,
                              k.pre ? k.pre->uid : 0,
-                             k.pre ? (uint64_t)(k.pre->opts.precision * 4096 + k.pre->opts.cycles) : 0, 0};
+                             k.pre ? (uint64_t)(k.prec * 4096 + k.pre->opts.cycles) : 0,
+                             (uint64_t)(uintptr_t)k.v};
     for (auto &e : m->graphs)
         if (std::memcmp(e.key, key, sizeof(key)) == 0) return e.exec;
     hipGraph_t graph = nullptr;
@@ -359,10 +382,25 @@ static hipGraphExec_t iteration_graph(Ksolve k, hipStream_t s)
     return exec;
 }
 
+// The pending w / x update of the last iteration; k0 holds the buffer roles of
+// device iteration iter0.
+static void ksolve_finish(const Ksolve &k0, int iter0, const KrylovScalars &h, hipStream_t s)
+{
+    if (!h.wx_valid || h.iter < 1) return;
+    const Ksolve kk = rotated(k0, h.iter - iter0);
+    const int n = k0.m->g.n;
+    k_minres_wx<<<blocks_for(n), kBlock, 0, s>>>(n, kk.zn, kk.w, kk.wp, kk.x,
+                                                reinterpret_cast<const KrylovScalars *>(k0.m->kscal.get()));
+    GLK_CHECK_LAUNCH();
+}
+
 // Iterate until the device flags stop (convergence, breakdown or max_iter),
-// then apply the pending w / x update of the last iteration.
+// then apply the pending w / x update of the last iteration (finish), or
+// leave it to a continuation of the same recurrence.  k holds the buffer
+// roles of device iteration iter0 (the first one this call runs).
 template <int DIM>
-static void ksolve_iterate(Ksolve k, int max_iter, int poll, hipStream_t s, KrylovScalars &h)
+static void ksolve_iterate(Ksolve k, int max_iter, int poll, hipStream_t s, KrylovScalars &h,
+                           bool finish = true, int iter0 = 0)
 {
     const bool graphs = profiler().kernel == 0;
     hipGraphExec_t exec = graphs ? iteration_graph<DIM>(k, s) : nullptr;
@@ -378,19 +416,7 @@ static void ksolve_iterate(Ksolve k, int max_iter, int poll, hipStream_t s, Kryl
             for (int t = 0; t < poll && launched < max_iter; ++t, ++launched) enqueue_iteration<DIM>(k, Launch{s});
         }
     }
-    if (h.wx_valid && h.iter >= 1) {
-        // roles after h.iter iterations: swapped when h.iter is odd
-        Ksolve kk = k0;
-        if (h.iter & 1) {
-            std::swap(kk.v, kk.vp);
-            std::swap(kk.z, kk.zn);
-            std::swap(kk.w, kk.wp);
-        }
-        const int n = k.m->g.n;
-        k_minres_wx<<<blocks_for(n), kBlock, 0, s>>>(n, kk.zn, kk.w, kk.wp, kk.x,
-                                                    reinterpret_cast<const KrylovScalars *>(k.m->kscal.get()));
-        GLK_CHECK_LAUNCH();
-    }
+    if (finish) ksolve_finish(k0, iter0, h, s);
 }
 
 template <int DIM>
@@ -433,12 +459,18 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
         // iterative refinement in FP64 around MINRES solves, each to the inner
         // tolerance (FP32 V-cycle: a fixed rounded preconditioner, whose
         // rounding caps what one MINRES run attains), stopped on the true
-        // residual in the preconditioner norm
-        const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : 1e-5;
+        // residual in the preconditioner norm.  relax: each MINRES run applies
+        // the FP64 V-cycle until its estimate reaches relax_rtol and the
+        // reduced-precision one after that (the error of an operator
+        // application may grow in inverse proportion to the residual in an
+        // inexact Krylov method), to rtol in one run
+        const bool relax = !fp64 && o.relax_rtol > 0.0;
+        const double inner = o.inner_rtol > 0.0 ? o.inner_rtol : relax ? o.rtol : 1e-5;
         double2 *d = m->work.get() + 9 * (size_t)n, *r = m->work.get() + 10 * (size_t)n;
         k_copy<<<nb, kBlock, 0, s>>>(n, r, b);
         k_zero<<<nb, kBlock, 0, s>>>(n, x);
         Ksolve k = make_ksolve(m, psi, pre, r, d);
+        if (relax) k.prec = GL_FP64;
         double eta_first = 0.0;
         for (int outer = 0; outer < 64; ++outer) {
             ksolve_init<DIM>(k, inner, 0, Launch{s});
@@ -449,10 +481,24 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
             if (h.eta0 <= o.rtol * eta_first || h.eta0 == 0.0) { converged = true; break; }
             if (iters >= o.max_iter) break;
             const double rt = std::max(inner, o.rtol * eta_first / h.eta0);
-            k_ks_set<<<1, 1, 0, s>>>(ks, rt, o.max_iter - iters);
+            const int budget = o.max_iter - iters;
+            const bool two = relax && rt < o.relax_rtol;
+            k_ks_set<<<1, 1, 0, s>>>(ks, two ? o.relax_rtol : rt, budget);
             // re-open the gate: max_iter was 0 during the norm-only start
             k_ks_init_running<<<1, 1, 0, s>>>(ks);
-            ksolve_iterate<DIM>(k, o.max_iter - iters, poll, s, h);
+            ksolve_iterate<DIM>(k, budget, poll, s, h, !two);
+            if (two) {
+                const int ia = h.iter;
+                if (h.status == 0 && h.converged && h.gamma > 0.0 && ia < budget &&
+                    std::fabs(h.eta) > rt * h.eta0) {
+                    Ksolve kb = rotated(k, ia);
+                    kb.prec = pre->opts.precision;
+                    k_ks_resume<<<1, 1, 0, s>>>(ks, rt);
+                    ksolve_iterate<DIM>(kb, budget - ia, poll, s, h, true, ia);
+                } else {
+                    ksolve_finish(k, 0, h, s);
+                }
+            }
             iters += h.iter;
             if (h.status) { st = (gl_status)h.status; break; }
             k_add<<<nb, kBlock, 0, s>>>(n, x, d);
@@ -493,7 +539,7 @@ static void check_krylov_opts(const gl_krylov_opts *o, const char *who)
 {
     if (!o) fail(GL_ERR_INVALID_ARGUMENT, std::string(who) + ": NULL options");
     if (!(o->rtol >= 0.0) || o->max_iter < 0 || o->max_iter > 100000000 || o->poll_every < 1 ||
-        !(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0))
+        !(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0) || !(o->relax_rtol >= 0.0 && o->relax_rtol < 1.0))
         fail(GL_ERR_INVALID_ARGUMENT, std::string(who) + ": invalid Krylov options");
 }
 
@@ -934,7 +980,7 @@ static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int>
 {
     const gl_krylov_opts &ko = o.krylov;
     const bool use_pre = o.use_precond != 0;
-    const bool fp32 = use_pre && o.amg.precision == GL_FP32;
+    const bool fp32 = use_pre && o.amg.precision != GL_FP64;
     const bool refine = fp32 || ko.inner_rtol > 0.0;
     const int poll = std::max(1, ko.poll_every);
     for (int i : act) iters[i] = 0;

@@ -156,12 +156,12 @@ __device__ __forceinline__ C<T> prolong_row(const int *__restrict__ prp, const i
 
 // coarse correction of the black nodes: x_b += (P x_c)_b (the red nodes are
 // overwritten by the red pass that follows, which reads only black values)
-template <int DIM, class T>
+template <int DIM, class T, class TC = T>
 struct L0ProlongBlack {
     GeomT<T> g;
     C<T> *x;
     const int *prp, *pci;
-    const C<T> *pv, *xc;
+    const C<TC> *pv, *xc;
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
@@ -171,7 +171,7 @@ struct L0ProlongBlack {
         int c[3];
         node_coords<DIM>(g.N, i, c);
         if (((c[0] + c[1] + c[2]) & 1) == 0) return;
-        x[i] = cadd(x[i], prolong_row<T>(prp, pci, pv, xc, i));
+        x[i] = cadd(x[i], as_c<T>(prolong_row<TC>(prp, pci, pv, xc, i)));
     }
 };
 
@@ -315,18 +315,19 @@ struct CsrResidual {
         const bool act = i < n;
         C<T> s = mk<T>(0, 0);
         if (act)
-            for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
+            for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], as_c<T>(x[ci[p]])));
         s = lanes_sum<T, LPR>(s);
         if (act && lane == 0) r[i] = csub(b[i], s);
     }
 };
 
-// y = A x (ADD = 0) or y += A x (ADD = 1)
-template <class T, int LPR, int ADD>
+// y = A x (ADD = 0) or y += A x (ADD = 1); x may be held in the other precision
+template <class T, int LPR, int ADD, class TX = T>
 struct CsrSpmv {
     int n;
     const int *rp, *ci;
-    const C<T> *v, *x;
+    const C<T> *v;
+    const C<TX> *x;
     C<T> *y;
     const int *gate;
     __device__ void operator()(int bx, int) const
@@ -337,7 +338,7 @@ struct CsrSpmv {
         const bool act = i < n;
         C<T> s = mk<T>(0, 0);
         if (act)
-            for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], x[ci[p]]));
+            for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], as_c<T>(x[ci[p]])));
         s = lanes_sum<T, LPR>(s);
         if (act && lane == 0) y[i] = ADD ? cadd(y[i], s) : s;
     }
@@ -420,81 +421,214 @@ struct DenseApply {
 // ------------------------------------------------------------ bottom ---
 // Every level from D.first down to the coarsest, in one work-group of
 // kBottomThreads threads: the same V-cycle steps as the multi-kernel levels,
-// separated by work-group barriers, and the dense Cholesky solve.
-constexpr int kBottomThreads = 1024;
-constexpr int kBottomLpr = 8;
+// separated by work-group barriers, and the dense solve.  One work-group
+// avoids a dispatch per colour pass; what bounds it is the latency of each
+// step's loads and the bandwidth of one compute unit, so every step gives a
+// thread whole rows (two row slots, r and r + kBottomThreads) and issues the
+// row's entry loads ahead of the products.  Measured on MI355X, a step costs
+// about 3 us even over a handful of rows (a dependent global load is about
+// 1 us away) and one compute unit streams about 20-25 GB/s, so the kernel
+// pays only for levels of a few hundred rows; the tile autotuner chooses
+// the bound (bottom_rows).
+constexpr int kBottomThreads = 512;
+constexpr int kBottomAhead = 8;   // entries of a row loaded ahead of use
 
-// one colour of a level, from its ELL block; x in LDS or global memory
+// One row of a padded block: entry k at base + k, `width` entries (0: empty
+// slot), `self` the row's own index (skipped: padding and the diagonal).
+struct EllSlot {
+    size_t base;
+    int width, self;
+};
+
+// sum over the stored entries (j != self) of a_k x_j for two row slots, the
+// entry loads of both issued ahead of the products
 template <class T>
-__device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int colour, C<T> *x)
+__device__ __forceinline__ void bottom_ell2(const int *__restrict__ eci, const C<T> *__restrict__ ev,
+                                            const EllSlot p, const EllSlot q, const C<T> *x, C<T> &sp,
+                                            C<T> &sq)
 {
-    const int cnt = L.coff[colour + 1] - L.coff[colour];
-    const int row0 = L.coff[colour];
-    const int W = L.ewidth[colour];
-    const int *eci = L.eci + L.eoff[colour];
-    const C<T> *ev = L.ev + L.eoff[colour];
-    const int per = kBottomThreads / kBottomLpr;
-    const int lane = threadIdx.x % kBottomLpr;
-    for (int base = 0; base < cnt; base += per) {
-        const int r = base + threadIdx.x / kBottomLpr;
-        const bool act = r < cnt;
-        const int i = row0 + (act ? r : 0);
-        C<T> s = mk<T>(0, 0);
-        if (act)
-            for (int k = lane; k < W; k += kBottomLpr) {
-                const int j = eci[(size_t)r * W + k];
-                if (j != i) s = cadd(s, cmul(ev[(size_t)r * W + k], x[j]));
+    sp = sq = mk<T>(0, 0);
+    const int W = max(p.width, q.width);
+    for (int k0 = 0; k0 < W; k0 += kBottomAhead) {
+        int jp[kBottomAhead], jq[kBottomAhead];
+        C<T> ap[kBottomAhead], aq[kBottomAhead];
+#pragma unroll
+        for (int u = 0; u < kBottomAhead; ++u) {
+            const int k = k0 + u;
+            jp[u] = p.self;
+            jq[u] = q.self;
+            ap[u] = aq[u] = mk<T>(0, 0);
+            if (k < p.width) {
+                const size_t e = p.base + k;
+                jp[u] = eci[e];
+                ap[u] = ev[e];
             }
-        s = lanes_sum<T, kBottomLpr>(s);
-        if (act && lane == 0) x[i] = cscale(csub(L.b[i], s), (T)1 / L.diag[i]);
-    }
-}
-
-// MODE 0: y = M x, 1: y += M x, 2: y = b - M x
-template <class T, int MODE>
-__device__ __forceinline__ void bottom_rows_spmv(int nrows, const int *rp, const int *ci, const C<T> *v,
-                                                 const C<T> *x, const C<T> *b, C<T> *y)
-{
-    const int per = kBottomThreads / kBottomLpr;
-    const int lane = threadIdx.x % kBottomLpr;
-    for (int base = 0; base < nrows; base += per) {
-        const int i = base + threadIdx.x / kBottomLpr;
-        const bool act = i < nrows;
-        C<T> s = mk<T>(0, 0);
-        if (act)
-            for (int p = rp[i] + lane; p < rp[i + 1]; p += kBottomLpr) s = cadd(s, cmul(v[p], x[ci[p]]));
-        s = lanes_sum<T, kBottomLpr>(s);
-        if (act && lane == 0) {
-            if (MODE == 0) y[i] = s;
-            else if (MODE == 1) y[i] = cadd(y[i], s);
-            else y[i] = csub(b[i], s);
+            if (k < q.width) {
+                const size_t e = q.base + k;
+                jq[u] = eci[e];
+                aq[u] = ev[e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kBottomAhead; ++u) {
+            if (jp[u] != p.self) sp = cadd(sp, cmul(ap[u], x[jp[u]]));
+            if (jq[u] != q.self) sq = cadd(sq, cmul(aq[u], x[jq[u]]));
         }
     }
 }
 
-// y = M b for a dense row-major n x n matrix
+// Gauss-Seidel update of one colour (rows of a colour are independent)
 template <class T>
-__device__ __forceinline__ void bottom_dense(int n, const C<T> *M, const C<T> *b, C<T> *y)
+__device__ __forceinline__ void bottom_colour(const BottomLevel<T> &L, int c, C<T> *x)
 {
-    const int per = kBottomThreads / kBottomLpr;
-    const int lane = threadIdx.x % kBottomLpr;
-    for (int base = 0; base < n; base += per) {
-        const int i = base + threadIdx.x / kBottomLpr;
-        const bool act = i < n;
-        C<T> s = mk<T>(0, 0);
-        if (act)
-            for (int j = lane; j < n; j += kBottomLpr) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
-        s = lanes_sum<T, kBottomLpr>(s);
-        if (act && lane == 0) y[i] = s;
+    const int cnt = L.coff[c + 1] - L.coff[c], row0 = L.coff[c], W = L.ewidth[c];
+    const int *eci = L.eci + L.eoff[c];
+    const C<T> *ev = L.ev + L.eoff[c];
+    for (int r0 = threadIdx.x; r0 < cnt; r0 += 2 * kBottomThreads) {
+        const int r1 = r0 + kBottomThreads;
+        C<T> s0, s1;
+        bottom_ell2<T>(eci, ev, EllSlot{(size_t)r0 * W, W, row0 + r0},
+                       EllSlot{(size_t)r1 * W, r1 < cnt ? W : 0, row0 + r1}, x, s0, s1);
+        x[row0 + r0] = cscale(csub(L.b[row0 + r0], s0), (T)1 / L.diag[row0 + r0]);
+        if (r1 < cnt) x[row0 + r1] = cscale(csub(L.b[row0 + r1], s1), (T)1 / L.diag[row0 + r1]);
     }
 }
 
+// one symmetric sweep: colours 0 .. C-1, then C-2 .. 0; from zero the first
+// pass is x = b / a_ii on colour 0 and every other row starts at 0
 template <class T>
-__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L, C<T> *x)
+__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L, C<T> *x, bool from_zero)
 {
-    for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
-        bottom_rows_sgs<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, x);
+    int t0 = 0;
+    if (from_zero) {
+        const int c1 = L.coff[1];
+        for (int i = threadIdx.x; i < L.n; i += kBottomThreads)
+            x[i] = i < c1 ? cscale(L.b[i], (T)1 / L.diag[i]) : mk<T>(0, 0);
         __syncthreads();
+        t0 = 1;
+    }
+    for (int t = t0; t < 2 * L.ncolors - 1; ++t) {
+        bottom_colour<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, x);
+        __syncthreads();
+    }
+}
+
+// r = b - A x on every row, from the colour blocks (row i of colour c is row
+// i - coff[c] of block c)
+template <class T>
+__device__ __forceinline__ EllSlot bottom_row_slot(const BottomLevel<T> &L, int i)
+{
+    if (i >= L.n) return EllSlot{0, 0, i};
+    int c = 0;
+    while (i >= L.coff[c + 1]) ++c;
+    return EllSlot{(size_t)L.eoff[c] + (size_t)(i - L.coff[c]) * L.ewidth[c], L.ewidth[c], i};
+}
+
+template <class T>
+__device__ __forceinline__ void bottom_residual(const BottomLevel<T> &L, const C<T> *x)
+{
+    for (int i0 = threadIdx.x; i0 < L.n; i0 += 2 * kBottomThreads) {
+        const int i1 = i0 + kBottomThreads;
+        C<T> s0, s1;
+        bottom_ell2<T>(L.eci, L.ev, bottom_row_slot(L, i0), bottom_row_slot(L, i1), x, s0, s1);
+        L.r[i0] = csub(csub(L.b[i0], s0), cscale(x[i0], L.diag[i0]));
+        if (i1 < L.n) L.r[i1] = csub(csub(L.b[i1], s1), cscale(x[i1], L.diag[i1]));
+    }
+}
+
+// CSR rows with LPR lanes per row, two rows per lane group (i and i + per),
+// kBottomAhead entries of each loaded ahead.  MODE 0: y = M x, 1: y += M x
+template <class T, int LPR, int MODE>
+__device__ __forceinline__ void bottom_csr(int nrows, const int *__restrict__ rp, const int *__restrict__ ci,
+                                           const C<T> *__restrict__ v, const C<T> *x, C<T> *y)
+{
+    const int per = kBottomThreads / LPR;
+    const int lane = threadIdx.x % LPR;
+    for (int base = 0; base < nrows; base += 2 * per) {
+        const int i0 = base + threadIdx.x / LPR, i1 = i0 + per;
+        const int b0 = i0 < nrows ? rp[i0] : 0, e0 = i0 < nrows ? rp[i0 + 1] : 0;
+        const int b1 = i1 < nrows ? rp[i1] : 0, e1 = i1 < nrows ? rp[i1 + 1] : 0;
+        const int len = max(e0 - b0, e1 - b1);
+        C<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+        for (int o = lane; o < len; o += LPR * kBottomAhead) {
+            int j0[kBottomAhead], j1[kBottomAhead];
+            C<T> a0[kBottomAhead], a1[kBottomAhead];
+#pragma unroll
+            for (int u = 0; u < kBottomAhead; ++u) {
+                const int k = o + u * LPR;
+                j0[u] = j1[u] = -1;
+                a0[u] = a1[u] = mk<T>(0, 0);
+                if (b0 + k < e0) {
+                    j0[u] = ci[b0 + k];
+                    a0[u] = v[b0 + k];
+                }
+                if (b1 + k < e1) {
+                    j1[u] = ci[b1 + k];
+                    a1[u] = v[b1 + k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBottomAhead; ++u) {
+                if (j0[u] >= 0) s0 = cadd(s0, cmul(a0[u], x[j0[u]]));
+                if (j1[u] >= 0) s1 = cadd(s1, cmul(a1[u], x[j1[u]]));
+            }
+        }
+        s0 = lanes_sum<T, LPR>(s0);
+        s1 = lanes_sum<T, LPR>(s1);
+        if (lane == 0) {
+            if (i0 < nrows) y[i0] = MODE == 0 ? s0 : cadd(y[i0], s0);
+            if (i1 < nrows) y[i1] = MODE == 0 ? s1 : cadd(y[i1], s1);
+        }
+    }
+}
+
+// lanes per row of a CSR matrix inside the bottom kernel
+template <class T, int MODE>
+__device__ __forceinline__ void bottom_spmv(int nrows, int nnz, const int *rp, const int *ci, const C<T> *v,
+                                            const C<T> *x, C<T> *y)
+{
+    if (nnz <= 6 * nrows) bottom_csr<T, 1, MODE>(nrows, rp, ci, v, x, y);
+    else if (nnz <= 24 * nrows) bottom_csr<T, 4, MODE>(nrows, rp, ci, v, x, y);
+    else bottom_csr<T, 16, MODE>(nrows, rp, ci, v, x, y);
+}
+
+// y = M b for a dense row-major n x n matrix: 16 lanes per row, two rows per
+// lane group, kBottomAhead entries of each loaded ahead
+template <class T>
+__device__ __forceinline__ void bottom_dense(int n, const C<T> *__restrict__ M, const C<T> *__restrict__ b,
+                                             C<T> *y)
+{
+    constexpr int LPR = 16;
+    const int per = kBottomThreads / LPR;
+    const int lane = threadIdx.x % LPR;
+    for (int base = 0; base < n; base += 2 * per) {
+        const int i0 = base + threadIdx.x / LPR, i1 = i0 + per;
+        const C<T> *m0 = M + (size_t)min(i0, n - 1) * n, *m1 = M + (size_t)min(i1, n - 1) * n;
+        C<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
+        for (int o = lane; o < n; o += LPR * kBottomAhead) {
+            C<T> a0[kBottomAhead], a1[kBottomAhead], bb[kBottomAhead];
+#pragma unroll
+            for (int u = 0; u < kBottomAhead; ++u) {
+                const int j = o + u * LPR;
+                a0[u] = a1[u] = bb[u] = mk<T>(0, 0);
+                if (j < n) {
+                    a0[u] = m0[j];
+                    a1[u] = m1[j];
+                    bb[u] = b[j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBottomAhead; ++u) {
+                s0 = cadd(s0, cmul(a0[u], bb[u]));
+                s1 = cadd(s1, cmul(a1[u], bb[u]));
+            }
+        }
+        s0 = lanes_sum<T, LPR>(s0);
+        s1 = lanes_sum<T, LPR>(s1);
+        if (lane == 0) {
+            if (i0 < n) y[i0] = s0;
+            if (i1 < n) y[i1] = s1;
+        }
     }
 }
 
@@ -504,7 +638,7 @@ template <class T>
 struct Bottom {
     const BottomDesc<T> *Dp;
     const int *gate;
-    __device__ void operator()(int, int) const
+    __device__ __forceinline__ void operator()(int, int) const
     {
         GATE();
         extern __shared__ double2 glk_bottom_lds[];
@@ -513,12 +647,10 @@ struct Bottom {
         for (int l = D.first; l < D.last; ++l) {
             const BottomLevel<T> &L = D.L[l];
             C<T> *x = l == D.lds_level ? xs : L.x;
-            for (int i = threadIdx.x; i < L.n; i += kBottomThreads) x[i] = mk<T>(0, 0);
+            bottom_sgs<T>(L, x, true);
+            bottom_residual<T>(L, x);
             __syncthreads();
-            bottom_sgs<T>(L, x);
-            bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, x, L.b, L.r);
-            __syncthreads();
-            bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, L.r, nullptr, D.L[l + 1].b);
+            bottom_spmv<T, 0>(L.nc, L.rnnz, L.rrp, L.rci, L.rv, L.r, D.L[l + 1].b);
             __syncthreads();
         }
         // coarsest level: x = A^-1 b with the dense inverse
@@ -530,9 +662,9 @@ struct Bottom {
         for (int l = D.last - 1; l >= D.first; --l) {
             const BottomLevel<T> &L = D.L[l];
             C<T> *x = l == D.lds_level ? xs : L.x;
-            bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, x);
+            bottom_spmv<T, 1>(L.n, L.pnnz, L.prp, L.pci, L.pv, D.L[l + 1].x, x);
             __syncthreads();
-            bottom_sgs<T>(L, x);
+            bottom_sgs<T>(L, x, false);
             if (l == D.lds_level) {
                 for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = xs[i];
                 __syncthreads();
@@ -606,15 +738,15 @@ static int lanes_for(const Csr &M, int shift)
     default: { constexpr int LPR = 32; __VA_ARGS__; } break;  \
     }
 
-template <class T>
-static void csr_spmv(const Csr &M, const C<T> *x, C<T> *y, bool add, int shift, const int *gate,
+template <class T, class TX = T>
+static void csr_spmv(const Csr &M, const C<TX> *x, C<T> *y, bool add, int shift, const int *gate,
                      const Launch &L)
 {
     const int lpr = lanes_for(M, shift);
     const int nb = blocks_for((int64_t)M.n * lpr);
     GLK_LPR_SWITCH(lpr, {
-        if (add) L.run(nb, CsrSpmv<T, LPR, 1>{M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate});
-        else L.run(nb, CsrSpmv<T, LPR, 0>{M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate});
+        if (add) L.run(nb, CsrSpmv<T, LPR, 1, TX>{M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate});
+        else L.run(nb, CsrSpmv<T, LPR, 0, TX>{M.n, M.rp.get(), M.ci.get(), vals<T>(M), x, y, gate});
     });
 }
 
@@ -683,7 +815,9 @@ static void csr_residual(Level &Lv, int shift, const int *gate, const Launch &L)
     });
 }
 
-template <int DIM, class T>
+// T: level 0 (stencil sweeps, where the bytes are); TC: levels >= 1 and the
+// coarsest solve (latency-bound: their precision costs no bandwidth)
+template <int DIM, class T, class TC>
 static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
                         const int *gate, KrylovScalars *ks, int mode, int add, const Launch &L)
 {
@@ -700,10 +834,11 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     C<T> *x0 = vec_x<T>(L0);
     const int want = ks != nullptr;
     if (nl == 1) {
-        L.run(nb0, Narrow<T>{n0, v, vec_b<T>(L0), gate});
-        L.run(blocks_for((int64_t)n0 * 64), DenseApply<T>{n0, cinv<T>(pre), vec_b<T>(L0), x0, gate});
-        if (add) L.run(nb0, Output<T, 1>{n0, x0, vdot, z, slot, want, gate});
-        else L.run(nb0, Output<T, 0>{n0, x0, vdot, z, slot, want, gate});
+        C<TC> *xc0 = vec_x<TC>(L0);
+        L.run(nb0, Narrow<TC>{n0, v, vec_b<TC>(L0), gate});
+        L.run(blocks_for((int64_t)n0 * 64), DenseApply<TC>{n0, cinv<TC>(pre), vec_b<TC>(L0), xc0, gate});
+        if (add) L.run(nb0, Output<TC, 1>{n0, xc0, vdot, z, slot, want, gate});
+        else L.run(nb0, Output<TC, 0>{n0, xc0, vdot, z, slot, want, gate});
         if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, L);
         return;
     }
@@ -714,9 +849,10 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const double b_pre = nn * 16 + (f32 ? nn * sz : 0) + nn * szr + E * sz + mc * sz;
     const double b_sweep = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz;
     const double b_resid = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz + nn * sz;
-    const double b_prol = (mc + 1 + 0.5 * L0.Pa.nnz) * 4.0 + 0.5 * L0.Pa.nnz * sz + L0.nc * sz + 2.0 * mc * sz;
+    const double szc = sizeof(C<TC>);
+    const double b_prol = (mc + 1 + 0.5 * L0.Pa.nnz) * 4.0 + 0.5 * L0.Pa.nnz * szc + L0.nc * szc + 2.0 * mc * sz;
     const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
-    const double b_restr = (L0.nc + 1 + L0.Ra.nnz) * 4.0 + L0.Ra.nnz * sz + nn * sz + L0.nc * sz;
+    const double b_restr = (L0.nc + 1 + L0.Ra.nnz) * 4.0 + L0.Ra.nnz * szc + nn * sz + L0.nc * szc;
     // level 0, down: red (from zero, folded) + black, red, black residual, restriction
     prof_launch(PROF_L0_SWEEP, b_pre, L, [&] {
         L.run(nb0, L0PreBlack<DIM, T>{g, v, vec_b<T>(L0), x0, U, hd, gate});
@@ -728,37 +864,38 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
         L.run(nb0, L0Residual<DIM, T>{g, v, b0, x0, U, hd, vec_r<T>(L0), gate});
     });
     prof_launch(PROF_L0_TRANSFER, b_restr, L, [&] {
-        csr_spmv<T>(L0.Ra, vec_r<T>(L0), vec_b<T>(L1), false, 0, gate, L);
+        csr_spmv<TC, T>(L0.Ra, vec_r<T>(L0), vec_b<TC>(L1), false, 0, gate, L);
     });
     // multi-kernel coarse levels, down
     const int nb_first = pre->bottom;
     const int sh = pre->lane_shift;
     for (int l = 1; l < nb_first; ++l) {
         Level &Lv = pre->L[l];
-        csr_sgs<T>(Lv, sh, true, gate, L);
-        csr_residual<T>(Lv, sh, gate, L);
-        csr_spmv<T>(Lv.Ra, vec_r<T>(Lv), vec_b<T>(pre->L[l + 1]), false, sh, gate, L);
+        csr_sgs<TC>(Lv, sh, true, gate, L);
+        csr_residual<TC>(Lv, sh, gate, L);
+        csr_spmv<TC>(Lv.Ra, vec_r<TC>(Lv), vec_b<TC>(pre->L[l + 1]), false, sh, gate, L);
     }
     // small levels and the coarsest solve in one work-group, or the coarsest
     // solve alone as a dense product over many work-groups
     if (pre->bottom < nl - 1) {
-        L.run<Bottom<T>, kBottomThreads>(1, Bottom<T>{bdesc<T>(pre), gate}, bottom_lds<T>(pre));
+        L.run<Bottom<TC>, kBottomThreads>(1, Bottom<TC>{bdesc<TC>(pre), gate}, bottom_lds<TC>(pre));
     } else {
         Level &Lc = pre->L[nl - 1];
-        L.run(blocks_for((int64_t)Lc.n * 64), DenseApply<T>{Lc.n, cinv<T>(pre), vec_b<T>(Lc), vec_x<T>(Lc), gate});
+        L.run(blocks_for((int64_t)Lc.n * 64),
+              DenseApply<TC>{Lc.n, cinv<TC>(pre), vec_b<TC>(Lc), vec_x<TC>(Lc), gate});
     }
     // multi-kernel coarse levels, up
     for (int l = nb_first - 1; l >= 1; --l) {
         Level &Lv = pre->L[l];
-        csr_spmv<T>(Lv.Pa, vec_x<T>(pre->L[l + 1]), vec_x<T>(Lv), true, sh, gate, L);
-        csr_sgs<T>(Lv, sh, false, gate, L);
+        csr_spmv<TC>(Lv.Pa, vec_x<TC>(pre->L[l + 1]), vec_x<TC>(Lv), true, sh, gate, L);
+        csr_sgs<TC>(Lv, sh, false, gate, L);
     }
     // level 0, up: red with the coarse correction, black, red + output
     // black coarse correction, then the red pass (fusing the two reads every
     // black correction four times and was measured slower)
     prof_launch(PROF_L0_TRANSFER, b_prol, L, [&] {
-        L.run(nb0, L0ProlongBlack<DIM, T>{g, x0, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<T>(L0.Pa), vec_x<T>(L1),
-                                          gate});
+        L.run(nb0, L0ProlongBlack<DIM, T, TC>{g, x0, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<TC>(L0.Pa),
+                                              vec_x<TC>(L1), gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
         L.run(nb0, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
@@ -773,38 +910,45 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, L);
 }
 
-template <int DIM, class T>
+template <int DIM, class T, class TC>
 static void vcycle_k(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
                      KrylovScalars *ks, int mode, const Launch &L)
 {
     const int k = pre->opts.cycles;
     if (k <= 1) {
-        vcycle_once<DIM, T>(pre, v, v, z, gate, ks, mode, 0, L);
+        vcycle_once<DIM, T, TC>(pre, v, v, z, gate, ks, mode, 0, L);
         return;
     }
     // x <- x + V(v - H x), k times from x = 0
     const gl_mesh *m = pre->mesh;
     const GeomT<double> g = geom_t<double>(m->g);
     const int nb0 = blocks_for(pre->L[0].n);
-    vcycle_once<DIM, T>(pre, v, v, z, gate, nullptr, 0, 0, L);
+    vcycle_once<DIM, T, TC>(pre, v, v, z, gate, nullptr, 0, 0, L);
     for (int c = 1; c < k; ++c) {
         L.run(nb0, L0ResidualFull<DIM>{g, v, z, m->U64.get(), pre->L[0].diag64.get(), pre->cyc_r.get(), gate});
         const bool lastc = (c == k - 1);
-        vcycle_once<DIM, T>(pre, pre->cyc_r.get(), v, z, gate, lastc ? ks : nullptr, mode, 1, L);
+        vcycle_once<DIM, T, TC>(pre, pre->cyc_r.get(), v, z, gate, lastc ? ks : nullptr, mode, 1, L);
+    }
+}
+
+void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
+                    KrylovScalars *ks, int mode, const Launch &L, gl_precision p)
+{
+    if (pre->mesh->g.dim == 2) {
+        if (p == GL_FP32) vcycle_k<2, float, float>(pre, v, z, gate, ks, mode, L);
+        else if (p == GL_MIXED) vcycle_k<2, float, double>(pre, v, z, gate, ks, mode, L);
+        else vcycle_k<2, double, double>(pre, v, z, gate, ks, mode, L);
+    } else {
+        if (p == GL_FP32) vcycle_k<3, float, float>(pre, v, z, gate, ks, mode, L);
+        else if (p == GL_MIXED) vcycle_k<3, float, double>(pre, v, z, gate, ks, mode, L);
+        else vcycle_k<3, double, double>(pre, v, z, gate, ks, mode, L);
     }
 }
 
 void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
                     KrylovScalars *ks, int mode, const Launch &L)
 {
-    const bool f32 = pre->opts.precision == GL_FP32;
-    if (pre->mesh->g.dim == 2) {
-        if (f32) vcycle_k<2, float>(pre, v, z, gate, ks, mode, L);
-        else vcycle_k<2, double>(pre, v, z, gate, ks, mode, L);
-    } else {
-        if (f32) vcycle_k<3, float>(pre, v, z, gate, ks, mode, L);
-        else vcycle_k<3, double>(pre, v, z, gate, ks, mode, L);
-    }
+    vcycle_enqueue(pre, v, z, gate, ks, mode, L, pre->opts.precision);
 }
 
 // Device descriptors of the bottom levels (pointers fixed after setup).
@@ -827,6 +971,8 @@ static void fill_bottom(gl_precond *pre, BottomDesc<T> &D)
         B.diag = dgn<T>(L);
         for (int c = 0; c <= L.ncolors && c <= kMaxColors && c < (int)L.coff.size(); ++c) B.coff[c] = L.coff[c];
         if (l + 1 < pre->nlev) {
+            B.pnnz = L.Pa.nnz;
+            B.rnnz = L.Ra.nnz;
             B.prp = L.Pa.rp.get();
             B.pci = L.Pa.ci.get();
             B.pv = vals<T>(L.Pa);

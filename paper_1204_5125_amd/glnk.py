@@ -17,7 +17,7 @@ GL_OK = 0
 STATUS = {0: "GL_OK", 1: "GL_ERR_INVALID_ARGUMENT", 2: "GL_ERR_HIP", 3: "GL_ERR_OUT_OF_MEMORY",
           4: "GL_ERR_NOT_CONVERGED", 5: "GL_ERR_BREAKDOWN", 6: "GL_ERR_NONFINITE",
           7: "GL_ERR_SINGULAR", 8: "GL_ERR_UNSUPPORTED"}
-GL_FP64, GL_FP32 = 0, 1
+GL_FP64, GL_FP32, GL_MIXED = 0, 1, 2
 
 # gl_precond_export array identifiers
 EXPORT = {"agg": 0, "root": 1, "color": 2, "A_rp": 3, "A_ci": 4, "A_v": 5, "P_rp": 6, "P_ci": 7,
@@ -57,7 +57,7 @@ class AmgOpts(C.Structure):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("poll_every", C.c_int),
-                ("inner_rtol", C.c_double)]
+                ("inner_rtol", C.c_double), ("relax_rtol", C.c_double)]
 
 
 class KrylovInfo(C.Structure):
@@ -317,9 +317,9 @@ def gl_precond_apply(pre, r, z, stream=None):
 
 
 def gl_jacobian_solve(mesh, psi, pre, b, x, rtol=1e-10, max_iter=1000, poll_every=8, inner_rtol=0.0,
-                      stream=None, raise_on_fail=True):
+                      relax_rtol=0.0, stream=None, raise_on_fail=True):
     """Solve J(psi) x = b by preconditioned MINRES; returns (status, info dict)."""
-    o = KrylovOpts(rtol, max_iter, poll_every, inner_rtol)
+    o = KrylovOpts(rtol, max_iter, poll_every, inner_rtol, relax_rtol)
     ki = KrylovInfo()
     rc = lib().gl_jacobian_solve(mesh.handle, _vec(psi, mesh.n, "psi"),
                                  pre.handle if pre is not None else None, _vec(b, mesh.n, "b"),
@@ -357,12 +357,12 @@ class PrecondHandle:
 
 def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
                     krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
-                    precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, precond=None,
+                    relax_rtol=0.0, precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, precond=None,
                     stream=None, raise_on_fail=True):
     """Newton for GL(psi) = 0 in place; returns (status, info dict).  precond:
     an optional PrecondHandle whose hierarchy is reused (and filled on first use)."""
     o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
-                   KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol),
+                   KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, relax_rtol),
                    AmgOpts(precision, cycles, max_coarse, max_levels))
     ni = NewtonInfo()
     rc = lib().gl_newton_solve(mesh.handle, _vec(psi, mesh.n, "psi"), C.byref(o),

@@ -145,6 +145,10 @@ def test_vcycle(glnk, case):
     pre.update(dev(psi), precision=glnk.GL_FP32)
     pre.apply(dev(r), z)
     assert relerr(host(z), ref) < 1e-5
+    # level 0 in FP32, coarser levels in FP64
+    pre.update(dev(psi), precision=glnk.GL_MIXED)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-5
     # k = 3 cycles
     pre.update(dev(psi), precision=glnk.GL_FP64, cycles=3)
     pre.apply(dev(r), z)
@@ -235,6 +239,14 @@ def test_fp32_preconditioned_solve_reaches_fp64_accuracy(glnk, case):
     assert rc == 0 and info["converged"]
     assert info["res_true"] < 1e-9
     assert relerr(host(x), xo) < 1e-8
+    # one recurrence: FP64 V-cycle down to 1e-3, the reduced precision after
+    for prec in (glnk.GL_FP32, glnk.GL_MIXED):
+        pre.update(dev(psi), precision=prec)
+        rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=2000,
+                                          relax_rtol=1e-3)
+        assert rc == 0 and info["converged"]
+        assert info["res_true"] < 1e-9
+        assert relerr(host(x), xo) < 1e-8
 
 
 def test_repeated_solves_bitwise_identical(glnk):
@@ -270,6 +282,14 @@ def test_vcycle_and_solve_deeper_hierarchy(glnk, max_coarse):
     pre.update(dev(psi), precision=glnk.GL_FP32)
     pre.apply(dev(r), z)
     assert relerr(host(z), ref) < 1e-5
+    # every split between multi-kernel levels and the single-work-group bottom
+    for rows in (512, 4096, 65536):
+        glnk.gl_precond_set_tiles(pre, 0, rows)
+        for prec, tol in ((glnk.GL_FP64, 1e-11), (glnk.GL_FP32, 1e-5), (glnk.GL_MIXED, 1e-5)):
+            pre.update(dev(psi), precision=prec)
+            pre.apply(dev(r), z)
+            assert relerr(host(z), ref) < tol, (rows, prec)
+    glnk.gl_precond_set_tiles(pre, 0, 0)
     pre.update(dev(psi), precision=glnk.GL_FP64)
     xo, io, _ = oracle.minres(mo, psi, r, amg=amg, rtol=1e-10, max_iter=3000)
     rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(r), z, rtol=1e-10, max_iter=3000)
