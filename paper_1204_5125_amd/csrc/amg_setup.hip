@@ -162,7 +162,7 @@ __global__ void k_l0_cols(Geom g, const int *rp, int *ci)
 
 // H = K-hat + 2 D |psi|^2 in the same entry order
 template <int DIM>
-__global__ void k_l0_values(GeomT<double> g, const int *rp, const double2 *__restrict__ U,
+__global__ void k_l0_values(GeomT<double> g, const int *rp, const LinkTab<double> U,
                             const double2 *__restrict__ psi, double2 *v, double *diag)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -171,19 +171,17 @@ __global__ void k_l0_values(GeomT<double> g, const int *rp, const double2 *__res
     node_coords<DIM>(g.N, i, c);
     double s[3];
     const double d = node_volume<DIM, double>(g, c, s);
-    int st[3] = {1, g.N[0], g.N[0] * g.N[1]};
-    const size_t n = (size_t)g.n;
     int p = rp[i];
     double asum = 0.0;
     for (int a = DIM - 1; a >= 0; --a)
         if (c[a] > 0) {
             const double al = d * s[a] * g.inv_h2[a];
-            v[p++] = cscale(U[a * n + (i - st[a])], -al);
+            v[p++] = cscale(link_u<DIM, double>(U, a, c, c[a] - 1), -al);
         }
     const int pd = p++;
     for (int a = 0; a < DIM; ++a) {
         const double al = d * s[a] * g.inv_h2[a];
-        if (c[a] < g.N[a] - 1) v[p++] = cscale(cconj(U[a * n + i]), -al);
+        if (c[a] < g.N[a] - 1) v[p++] = cscale(cconj(link_u<DIM, double>(U, a, c, c[a])), -al);
         asum += al * ((c[a] > 0) + (c[a] < g.N[a] - 1));
     }
     const double dg = asum + 2.0 * d * cabs2(psi[i]);
@@ -1090,9 +1088,11 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
     const int n0 = L0.n;
     const GeomT<double> g = geom_t<double>(m->g);
     if (m->g.dim == 2)
-        k_l0_values<2><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), m->U64.get(), psi, L0.A.v64.get(), L0.diag64.get());
+        k_l0_values<2><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), link_tab<double>(m), psi, L0.A.v64.get(),
+                                                         L0.diag64.get());
     else
-        k_l0_values<3><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), m->U64.get(), psi, L0.A.v64.get(), L0.diag64.get());
+        k_l0_values<3><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), link_tab<double>(m), psi, L0.A.v64.get(),
+                                                         L0.diag64.get());
     GLK_CHECK_LAUNCH();
     for (int l = 0; l + 1 < pre->nlev; ++l) {
         Level &L = pre->L[l];

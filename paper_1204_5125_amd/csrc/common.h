@@ -3,6 +3,8 @@
 // last-block finalisation used by every fused dot product.
 #pragma once
 
+#include <cstring>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -213,6 +215,7 @@ template <class T>
 struct GeomT {
     int N[3];
     int n;
+    int hr, npair;  // red-black pairs: ceil(N0 / 2) per x-row, hr * n / N0 in all
     T h[3];
     T inv_h2[3];
 };
@@ -226,8 +229,26 @@ template <class T> inline GeomT<T> geom_t(const Geom &g)
         r.inv_h2[a] = (T)g.inv_h2[a];
     }
     r.n = g.n;
+    r.hr = (g.N[0] + 1) / 2;
+    r.npair = r.hr * (g.n / g.N[0]);
     return r;
 }
+
+// Link variables of the linear potential A(r) = M r as factor tables.  The
+// phase of the forward edge along axis a leaving the node with coordinates c
+// is h_a A_a(midpoint) = sum_b h_a M_ab mid_b(c_b), one term per coordinate,
+// so U_a(c) = prod_b F_ab[c_b] with F_ab[j] = exp(-i h_a M_ab mid_b(j)) and
+// mid_b(j) the midpoint's coordinate b (the node's, plus h_a / 2 along a).
+// Table F_ab has N_b entries at f + off[a][b]; off[a][b] = -1 where M_ab is
+// zero for every field strength (the diagonal of the uniform-field potential,
+// components the field direction lacks, zeros of a given matrix), whose
+// factor is 1.  The offsets depend on the grid and that pattern only, so a
+// field change rewrites the values in place.
+template <class T>
+struct LinkTab {
+    const C<T> *__restrict__ f;
+    int off[3][3];
+};
 
 }  // namespace glk
 
@@ -243,8 +264,9 @@ struct gl_mesh {
     glk::Geom g;
     gl_grid_desc desc;
     double amat[9];
-    glk::DevBuf<double2> U64;  // [axis][n] forward-edge link variables
-    glk::DevBuf<float2> U32;
+    glk::DevBuf<double2> F64;  // link factor tables (glk::LinkTab), FP64 and rounded to FP32
+    glk::DevBuf<float2> F32;
+    int foff[3][3] = {};
     // reductions
     glk::DevBuf<double> partials;
     glk::DevBuf<double> dscal;       // device scalar results
@@ -257,6 +279,24 @@ struct gl_mesh {
     std::vector<glk::GraphEntry> graphs;
     ~gl_mesh();
 };
+
+namespace glk {
+template <class T> LinkTab<T> link_tab(const gl_mesh *m);
+template <> inline LinkTab<double> link_tab<double>(const gl_mesh *m)
+{
+    LinkTab<double> t;
+    t.f = m->F64.get();
+    std::memcpy(t.off, m->foff, sizeof(t.off));
+    return t;
+}
+template <> inline LinkTab<float> link_tab<float>(const gl_mesh *m)
+{
+    LinkTab<float> t;
+    t.f = m->F32.get();
+    std::memcpy(t.off, m->foff, sizeof(t.off));
+    return t;
+}
+}  // namespace glk
 
 namespace glk {
 // ------------------------------------------------------------ profiling -
@@ -298,13 +338,6 @@ void prof_launch(int id, double bytes, hipStream_t s, F &&launch, int count = 1)
     p.launches += count;
 }
 
-// number of grid edges (axis-neighbour pairs)
-inline double grid_edges(const Geom &g)
-{
-    double e = 0.0;
-    for (int a = 0; a < g.dim; ++a) e += (double)g.n / g.N[a] * (g.N[a] - 1);
-    return e;
-}
 
 constexpr int kWorkVecs = 11;
 constexpr int kMaxSlots = 4;  // independent reduction slots per mesh

@@ -108,7 +108,8 @@ struct Unprec {
 template <int DIM>
 struct MinresJapply {
     GeomT<double> g;
-    const double2 *psi, *z, *U;
+    const double2 *psi, *z;
+    LinkTab<double> U;
     double2 *q;
     const double2 *zprev, *w;
     double2 *wp, *x;
@@ -179,7 +180,7 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_true_residual(GeomT<double> g, const double2 *__restrict__ psi,
                                                           const double2 *__restrict__ x,
                                                           const double2 *__restrict__ b,
-                                                          const double2 *__restrict__ U, RedSlot s1, RedSlot s2)
+                                                          const LinkTab<double> U, RedSlot s1, RedSlot s2)
 {
     __shared__ double sm[kBlock / 64];
     const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -220,7 +221,7 @@ template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual_vec(GeomT<double> g, const double2 *__restrict__ psi,
                                                          const double2 *__restrict__ x,
                                                          const double2 *__restrict__ b,
-                                                         const double2 *__restrict__ U, double2 *__restrict__ r)
+                                                         const LinkTab<double> U, double2 *__restrict__ r)
 {
     const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= g.n) return;
@@ -328,8 +329,9 @@ static void enqueue_iteration(Ksolve &k, const Launch &L)
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
     const int *gate = &ks->running;
-    prof_launch(PROF_MINRES_JAPPLY, (48.0 * n + 16.0 * grid_edges(m->g)) + 96.0 * n, L, [&] {
-        L.run(nb, MinresJapply<DIM>{g, k.psi, k.z, m->U64.get(), k.q, k.zn, k.w, k.wp, k.x, ks, red_slot(m, 0)});
+    prof_launch(PROF_MINRES_JAPPLY, 48.0 * n + 96.0 * n, L, [&] {
+        L.run(nb, MinresJapply<DIM>{g, k.psi, k.z, link_tab<double>(m), k.q, k.zn, k.w, k.wp, k.x, ks,
+                                    red_slot(m, 0)});
     });
     launch_finalize(red_slot(m, 0).partials, nb, FIN_DELTA, ks, nullptr, gate, L);
     prof_launch(PROF_VUPDATE, 64.0 * n, L, [&] { L.run(nb, MinresVupdate{n, k.q, k.v, k.vp, ks}); });
@@ -425,7 +427,7 @@ static void true_residual(const gl_mesh *m, const double2 *psi, const double2 *x
     const int nb = blocks_for(m->g.n);
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
-    k_true_residual<DIM><<<nb, kBlock, 0, s>>>(g, psi, x, b, m->U64.get(), red_slot(m, 2), red_slot(m, 3));
+    k_true_residual<DIM><<<nb, kBlock, 0, s>>>(g, psi, x, b, link_tab<double>(m), red_slot(m, 2), red_slot(m, 3));
     GLK_CHECK_LAUNCH();
     launch_finalize(red_slot(m, 2).partials, nb, FIN_RESNUM, ks, nullptr, nullptr, s);
     launch_finalize(red_slot(m, 3).partials, nb, FIN_RESDEN, ks, nullptr, nullptr, s);
@@ -502,7 +504,7 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
             iters += h.iter;
             if (h.status) { st = (gl_status)h.status; break; }
             k_add<<<nb, kBlock, 0, s>>>(n, x, d);
-            k_residual_vec<DIM><<<nb, kBlock, 0, s>>>(g, psi, x, b, m->U64.get(), r);
+            k_residual_vec<DIM><<<nb, kBlock, 0, s>>>(g, psi, x, b, link_tab<double>(m), r);
             GLK_CHECK_LAUNCH();
         }
         eta0 = eta_first;
@@ -1038,11 +1040,11 @@ static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int>
             const GeomT<double> g = geom_t<double>(m->g);
             if (m->g.dim == 2)
                 k_residual_vec<2><<<blocks_for(n), kBlock, 0, B->s>>>(g, psi[i], W + 8 * (size_t)n,
-                                                                       W + 7 * (size_t)n, m->U64.get(),
+                                                                       W + 7 * (size_t)n, link_tab<double>(m),
                                                                        W + 10 * (size_t)n);
             else
                 k_residual_vec<3><<<blocks_for(n), kBlock, 0, B->s>>>(g, psi[i], W + 8 * (size_t)n,
-                                                                       W + 7 * (size_t)n, m->U64.get(),
+                                                                       W + 7 * (size_t)n, link_tab<double>(m),
                                                                        W + 10 * (size_t)n);
             GLK_CHECK_LAUNCH();
         }

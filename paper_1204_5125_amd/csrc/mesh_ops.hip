@@ -62,32 +62,40 @@ struct Potential {
     double L[3];
 };
 
-// A(r) = m r evaluated at the edge midpoint, phase = h_a A_a, U = exp(-i phase)
+// Factor tables of the link variables (LinkTab): entry j of F_ab is
+// exp(-i h_a M_ab mid_b(j)), mid_b(j) = -L_b/2 + j h_b (+ h_a/2 when b = a),
+// so that prod_b F_ab[c_b] = exp(-i h_a A_a(edge midpoint)) with A = M r.
+// Grid (max_b N_b / kBlock, DIM * DIM): blockIdx.y = a DIM + b.
+struct TableOffsets {
+    int off[3][3];
+};
+
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_links(Geom g, Potential pot, double2 *__restrict__ U64,
-                                                  float2 *__restrict__ U32)
+__global__ __launch_bounds__(kBlock) void k_link_tables(Geom g, Potential pot, TableOffsets t,
+                                                        double2 *__restrict__ F64, float2 *__restrict__ F32)
+{
+    const int a = blockIdx.y / DIM, b = blockIdx.y % DIM;
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (t.off[a][b] < 0 || j >= g.N[b]) return;
+    double mid = -0.5 * pot.L[b] + (double)j * g.h[b];
+    if (b == a) mid += 0.5 * g.h[a];
+    const double ph = g.h[a] * pot.m[3 * a + b] * mid;
+    double sn, cs;
+    sincos(ph, &sn, &cs);
+    const double2 u = make_double2(cs, -sn);
+    F64[t.off[a][b] + j] = u;
+    F32[t.off[a][b] + j] = make_float2((float)u.x, (float)u.y);
+}
+
+// the forward-edge links of one axis per node (0 on the axis's upper face)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_link_export(Geom g, LinkTab<double> U, int a, double2 *out)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= g.n) return;
     int c[3];
     node_coords<DIM>(g.N, i, c);
-    double x[3] = {0.0, 0.0, 0.0};
-    for (int a = 0; a < DIM; ++a) x[a] = -0.5 * pot.L[a] + (double)c[a] * g.h[a];
-    const size_t n = (size_t)g.n;
-    for (int a = 0; a < DIM; ++a) {
-        double2 u = make_double2(0.0, 0.0);
-        if (c[a] < g.N[a] - 1) {
-            double m[3] = {x[0], x[1], x[2]};
-            m[a] += 0.5 * g.h[a];
-            const double Aa = pot.m[3 * a + 0] * m[0] + pot.m[3 * a + 1] * m[1] + pot.m[3 * a + 2] * m[2];
-            const double ph = g.h[a] * Aa;
-            double s, co;
-            sincos(ph, &s, &co);
-            u = make_double2(co, -s);
-        }
-        U64[a * n + i] = u;
-        U32[a * n + i] = make_float2((float)u.x, (float)u.y);
-    }
+    out[i] = c[a] < g.N[a] - 1 ? link_u<DIM, double>(U, a, c, c[a]) : make_double2(0.0, 0.0);
 }
 
 static void compute_amat(const gl_grid_desc &d, double mu, double out[9])
@@ -109,18 +117,21 @@ static void launch_links(gl_mesh *m, hipStream_t s)
     Potential pot;
     std::memcpy(pot.m, m->amat, sizeof(pot.m));
     for (int a = 0; a < 3; ++a) pot.L[a] = m->desc.side[a];
-    const int nb = blocks_for(m->g.n);
-    if (m->g.dim == 2)
-        k_links<2><<<nb, kBlock, 0, s>>>(m->g, pot, m->U64.get(), m->U32.get());
+    TableOffsets t;
+    std::memcpy(t.off, m->foff, sizeof(t.off));
+    const int dim = m->g.dim;
+    const dim3 grid(blocks_for(std::max(m->g.N[0], std::max(m->g.N[1], m->g.N[2]))), dim * dim);
+    if (dim == 2)
+        k_link_tables<2><<<grid, kBlock, 0, s>>>(m->g, pot, t, m->F64.get(), m->F32.get());
     else
-        k_links<3><<<nb, kBlock, 0, s>>>(m->g, pot, m->U64.get(), m->U32.get());
+        k_link_tables<3><<<grid, kBlock, 0, s>>>(m->g, pot, t, m->F64.get(), m->F32.get());
     GLK_CHECK_LAUNCH();
 }
 
 // ------------------------------------------------------- GL residual ---
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_gl_residual(GeomT<double> g, const double2 *__restrict__ psi,
-                                                        const double2 *__restrict__ U,
+                                                        const LinkTab<double> U,
                                                         double2 *__restrict__ out, RedSlot slot)
 {
     __shared__ double sm[kBlock / 64];
@@ -145,12 +156,13 @@ void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, dou
 {
     const int nb = blocks_for(m->g.n);
     const GeomT<double> g = geom_t<double>(m->g);
-    const double bytes = 16.0 * m->g.n * (out ? 2 : 1) + 16.0 * grid_edges(m->g);
+    const double bytes = 16.0 * m->g.n * (out ? 2 : 1);
+    const LinkTab<double> U = link_tab<double>(m);
     prof_launch(PROF_GL, bytes, s, [&] {
         if (m->g.dim == 2)
-            k_gl_residual<2><<<nb, kBlock, 0, s>>>(g, psi, m->U64.get(), out, red_slot(m, 0));
+            k_gl_residual<2><<<nb, kBlock, 0, s>>>(g, psi, U, out, red_slot(m, 0));
         else
-            k_gl_residual<3><<<nb, kBlock, 0, s>>>(g, psi, m->U64.get(), out, red_slot(m, 0));
+            k_gl_residual<3><<<nb, kBlock, 0, s>>>(g, psi, U, out, red_slot(m, 0));
     });
     GLK_CHECK_LAUNCH();
     launch_finalize(red_slot(m, 0).partials, nb, FIN_STORE, nullptr, dresult, nullptr, s);
@@ -160,7 +172,7 @@ void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, dou
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_jacobian(GeomT<double> g, const double2 *__restrict__ psi,
                                                      const double2 *__restrict__ phi,
-                                                     const double2 *__restrict__ U,
+                                                     const LinkTab<double> U,
                                                      double2 *__restrict__ out)
 {
     const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -183,9 +195,9 @@ void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, 
     const int nb = blocks_for(m->g.n);
     const GeomT<double> g = geom_t<double>(m->g);
     if (m->g.dim == 2)
-        k_jacobian<2><<<nb, kBlock, 0, s>>>(g, psi, phi, m->U64.get(), out);
+        k_jacobian<2><<<nb, kBlock, 0, s>>>(g, psi, phi, link_tab<double>(m), out);
     else
-        k_jacobian<3><<<nb, kBlock, 0, s>>>(g, psi, phi, m->U64.get(), out);
+        k_jacobian<3><<<nb, kBlock, 0, s>>>(g, psi, phi, link_tab<double>(m), out);
     GLK_CHECK_LAUNCH();
 }
 
@@ -336,8 +348,20 @@ gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mes
                 }
             }
             compute_amat(*desc, desc->mu, m->amat);
-            m->U64.alloc((size_t)desc->dim * n);
-            m->U32.alloc((size_t)desc->dim * n);
+            // tables only where M_ab can be nonzero (the pattern of M at mu = 1)
+            double pat[9];
+            compute_amat(*desc, 1.0, pat);
+            int tot = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    m->foff[a][b] = -1;
+                    if (a < desc->dim && b < desc->dim && pat[3 * a + b] != 0.0) {
+                        m->foff[a][b] = tot;
+                        tot += m->g.N[b];
+                    }
+                }
+            m->F64.alloc(std::max(tot, 1));
+            m->F32.alloc(std::max(tot, 1));
             const size_t per = (size_t)blocks_for(n) + 64;
             m->partials.alloc(per * kMaxSlots);
             m->dscal.alloc(64);
@@ -386,8 +410,15 @@ gl_status gl_mesh_export_links(const gl_mesh *mesh, int axis, void *host_out)
         if (!mesh || !host_out) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_export_links: NULL argument");
         if (axis < 0 || axis >= mesh->g.dim) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_export_links: axis");
         GLK_HIP(hipDeviceSynchronize());
-        GLK_HIP(hipMemcpy(host_out, mesh->U64.get() + (size_t)axis * mesh->g.n,
-                          sizeof(double2) * (size_t)mesh->g.n, hipMemcpyDeviceToHost));
+        // staged in the first Krylov vector (no solve is in flight after the synchronisation)
+        double2 *stage = mesh->work.get();
+        const int nb = blocks_for(mesh->g.n);
+        if (mesh->g.dim == 2)
+            k_link_export<2><<<nb, kBlock>>>(mesh->g, link_tab<double>(mesh), axis, stage);
+        else
+            k_link_export<3><<<nb, kBlock>>>(mesh->g, link_tab<double>(mesh), axis, stage);
+        GLK_CHECK_LAUNCH();
+        GLK_HIP(hipMemcpy(host_out, stage, sizeof(double2) * (size_t)mesh->g.n, hipMemcpyDeviceToHost));
     });
 }
 

@@ -3,13 +3,32 @@
 // k = i - s_a and upper neighbour j = i + s_a,
 //   (K-hat x)_i = sum_a alpha_a [ (x_i - U_a[k] x_k) + (x_i - conj(U_a[i]) x_j) ]
 // where U_a[k] is the link variable of the forward edge leaving node k along
-// axis a (stored [axis][n]).  |V_i| and alpha_a are computed from the node's
-// position, so the operator streams only x and the link variables.
+// axis a, a product of factor-table entries (LinkTab).  |V_i| and alpha_a are
+// computed from the node's position, so the operator streams only x.
 #pragma once
 
 #include "common.h"
 
 namespace glk {
+
+// U of the forward edge along axis a whose lower node has coordinates c,
+// except c[a] -> ca
+template <int DIM, class T>
+__device__ __forceinline__ C<T> link_u(const LinkTab<T> &L, int a, const int c[3], int ca)
+{
+    C<T> u = mk<T>(1, 0);
+    bool first = true;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const int o = L.off[a][b];
+        if (o >= 0) {
+            const C<T> f = L.f[o + (a == b ? ca : c[b])];
+            u = first ? f : cmul(u, f);
+            first = false;
+        }
+    }
+    return u;
+}
 
 template <int DIM>
 __device__ __forceinline__ void node_coords(const int *N, int i, int c[3])
@@ -44,25 +63,24 @@ __device__ __forceinline__ T node_volume(const GeomT<T> &g, const int c[3], T s[
 template <int DIM, class T>
 __device__ __forceinline__ C<T> khat_node(const GeomT<T> &g, int i, const int c[3],
                                           const C<T> *__restrict__ x,
-                                          const C<T> *__restrict__ U, C<T> xi, T &d, T &asum)
+                                          const LinkTab<T> &U, C<T> xi, T &d, T &asum)
 {
     T s[3];
     d = node_volume<DIM, T>(g, c, s);
     C<T> acc = mk<T>(0, 0);
     asum = 0;
     int stride = 1;
-    const size_t n = (size_t)g.n;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const T al = d * s[a] * g.inv_h2[a];
         if (c[a] > 0) {
-            const C<T> u = U[a * n + (i - stride)];
+            const C<T> u = link_u<DIM, T>(U, a, c, c[a] - 1);
             const C<T> xk = x[i - stride];
             acc = csub(acc, cscale(cmul(u, xk), al));
             asum += al;
         }
         if (c[a] < g.N[a] - 1) {
-            const C<T> u = U[a * n + i];
+            const C<T> u = link_u<DIM, T>(U, a, c, c[a]);
             const C<T> xj = x[i + stride];
             acc = csub(acc, cscale(cmulc(u, xj), al));
             asum += al;
@@ -76,18 +94,17 @@ __device__ __forceinline__ C<T> khat_node(const GeomT<T> &g, int i, const int c[
 template <int DIM, class T>
 __device__ __forceinline__ C<T> khat_offdiag(const GeomT<T> &g, int i, const int c[3],
                                              const C<T> *__restrict__ x,
-                                             const C<T> *__restrict__ U)
+                                             const LinkTab<T> &U)
 {
     T s[3];
     const T d = node_volume<DIM, T>(g, c, s);
     C<T> acc = mk<T>(0, 0);
     int stride = 1;
-    const size_t n = (size_t)g.n;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
         const T al = d * s[a] * g.inv_h2[a];
-        if (c[a] > 0) acc = csub(acc, cscale(cmul(U[a * n + (i - stride)], x[i - stride]), al));
-        if (c[a] < g.N[a] - 1) acc = csub(acc, cscale(cmulc(U[a * n + i], x[i + stride]), al));
+        if (c[a] > 0) acc = csub(acc, cscale(cmul(link_u<DIM, T>(U, a, c, c[a] - 1), x[i - stride]), al));
+        if (c[a] < g.N[a] - 1) acc = csub(acc, cscale(cmulc(link_u<DIM, T>(U, a, c, c[a]), x[i + stride]), al));
         stride *= g.N[a];
     }
     return acc;

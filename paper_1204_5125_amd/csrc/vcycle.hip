@@ -32,42 +32,76 @@ template <class T> __device__ __forceinline__ C<T> load_b(const double2 *v, cons
     else return b[i];
 }
 
+// Level-0 colour passes run one thread per red-black pair: thread t owns the
+// nodes c0 = 2k and 2k + 1 of x-row `row` (k = t mod hr, row = t / hr), one
+// of each colour, so every thread updates a node (a thread per node would
+// leave half of them idle and need twice the waves).
+struct Pair {
+    int ie;      // index of the even node (c0 = 2k)
+    int c[3];    // its coordinates
+    bool odd;    // the odd node c0 = 2k + 1 exists
+};
+
+template <int DIM, class T>
+__device__ __forceinline__ Pair pair_at(const GeomT<T> &g, int t)
+{
+    Pair P;
+    const int row = t / g.hr, k = t - row * g.hr;
+    P.c[0] = 2 * k;
+    P.c[1] = DIM == 3 ? row % g.N[1] : row;
+    P.c[2] = DIM == 3 ? row / g.N[1] : 0;
+    P.ie = 2 * k + g.N[0] * row;
+    P.odd = 2 * k + 1 < g.N[0];
+    return P;
+}
+
+// the pair's node of colour col: offset s from the even node (false: absent)
+__device__ __forceinline__ bool pair_colour(const Pair &P, int col, int &s)
+{
+    s = (col + P.c[1] + P.c[2]) & 1;
+    return s == 0 || P.odd;
+}
+
 // pre-smoothing, black pass from zero; FP32 also stores b = round(v)
 template <int DIM, class T>
 struct L0PreBlack {
     GeomT<T> g;
     const double2 *v;
     C<T> *b, *x;
-    const C<T> *U;
+    LinkTab<T> U;
     const T *hd;
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
         GATE();
-        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
-        if (i >= g.n) return;
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
+        const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (t >= g.npair) return;
+        const Pair P = pair_at<DIM, T>(g, t);
+        if constexpr (std::is_same<T, float>::value) {
+            b[P.ie] = narrow<T>(v[P.ie]);
+            if (P.odd) b[P.ie + 1] = narrow<T>(v[P.ie + 1]);
+        }
+        int sb;
+        if (!pair_colour(P, 1, sb)) return;
+        const int i = P.ie + sb;
+        const int c[3] = {P.c[0] + sb, P.c[1], P.c[2]};
         const C<T> bi = narrow<T>(v[i]);
-        if constexpr (std::is_same<T, float>::value) b[i] = bi;
-        if (((c[0] + c[1] + c[2]) & 1) == 0) return;
         T s[3];
         const T d = node_volume<DIM, T>(g, c, s);
         C<T> off = mk<T>(0, 0);
         int stride = 1;
-        const size_t n = (size_t)g.n;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             const T al = d * s[a] * g.inv_h2[a];
             if (c[a] > 0) {
                 const int k = i - stride;
                 const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
-                off = csub(off, cscale(cmul(U[a * n + k], xk), al));
+                off = csub(off, cscale(cmul(link_u<DIM, T>(U, a, c, c[a] - 1), xk), al));
             }
             if (c[a] < g.N[a] - 1) {
                 const int k = i + stride;
                 const C<T> xk = cscale(narrow<T>(v[k]), (T)1 / hd[k]);
-                off = csub(off, cscale(cmulc(U[a * n + i], xk), al));
+                off = csub(off, cscale(cmulc(link_u<DIM, T>(U, a, c, c[a]), xk), al));
             }
             stride *= g.N[a];
         }
@@ -83,17 +117,19 @@ struct L0Sweep {
     const double2 *v;
     const C<T> *b;
     C<T> *x;
-    const C<T> *U;
+    LinkTab<T> U;
     const T *hd;
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
         GATE();
-        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
-        if (i >= g.n) return;
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
-        if (((c[0] + c[1] + c[2]) & 1) != colour) return;
+        const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (t >= g.npair) return;
+        const Pair P = pair_at<DIM, T>(g, t);
+        int sc;
+        if (!pair_colour(P, colour, sc)) return;
+        const int i = P.ie + sc;
+        const int c[3] = {P.c[0] + sc, P.c[1], P.c[2]};
         const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
         x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
     }
@@ -104,21 +140,22 @@ template <int DIM, class T>
 struct L0Residual {
     GeomT<T> g;
     const double2 *v;
-    const C<T> *b, *x, *U;
+    const C<T> *b, *x;
+    LinkTab<T> U;
     const T *hd;
     C<T> *r;
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
         GATE();
-        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
-        if (i >= g.n) return;
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
-        if (((c[0] + c[1] + c[2]) & 1) == 0) {
-            r[i] = mk<T>(0, 0);
-            return;
-        }
+        const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (t >= g.npair) return;
+        const Pair P = pair_at<DIM, T>(g, t);
+        int sb, sr;
+        if (pair_colour(P, 0, sr)) r[P.ie + sr] = mk<T>(0, 0);
+        if (!pair_colour(P, 1, sb)) return;
+        const int i = P.ie + sb;
+        const int c[3] = {P.c[0] + sb, P.c[1], P.c[2]};
         const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
         r[i] = csub(csub(load_b<T>(v, b, i), cscale(x[i], hd[i])), off);
     }
@@ -128,7 +165,8 @@ struct L0Residual {
 template <int DIM>
 struct L0ResidualFull {
     GeomT<double> g;
-    const double2 *v, *z, *U;
+    const double2 *v, *z;
+    LinkTab<double> U;
     const double *hd;
     double2 *r;
     const int *gate;
@@ -166,11 +204,12 @@ struct L0ProlongBlack {
     __device__ void operator()(int bx, int nbx) const
     {
         GATE();
-        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
-        if (i >= g.n) return;
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
-        if (((c[0] + c[1] + c[2]) & 1) == 0) return;
+        const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        if (t >= g.npair) return;
+        const Pair P = pair_at<DIM, T>(g, t);
+        int sb;
+        if (!pair_colour(P, 1, sb)) return;
+        const int i = P.ie + sb;
         x[i] = cadd(x[i], as_c<T>(prolong_row<TC>(prp, pci, pv, xc, i)));
     }
 };
@@ -182,7 +221,7 @@ struct L0Last {
     const double2 *v;
     const C<T> *b;
     C<T> *x;
-    const C<T> *U;
+    LinkTab<T> U;
     const T *hd;
     double2 *z;
     const double2 *vdot;
@@ -193,23 +232,29 @@ struct L0Last {
     {
         GATE();
         __shared__ double sm[kBlock / 64];
-        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         double part = 0.0;
-        if (i < g.n) {
-            int c[3];
-            node_coords<DIM>(g.N, i, c);
-            C<T> xi;
-            if (((c[0] + c[1] + c[2]) & 1) == 0) {
+        if (t < g.npair) {
+            const Pair P = pair_at<DIM, T>(g, t);
+            // the red node's update, then z on both nodes (even first)
+            int sr;
+            C<T> xr = mk<T>(0, 0);
+            if (pair_colour(P, 0, sr)) {
+                const int i = P.ie + sr;
+                const int c[3] = {P.c[0] + sr, P.c[1], P.c[2]};
                 const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-                xi = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
-                x[i] = xi;
-            } else {
-                xi = x[i];
+                xr = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+                x[i] = xr;
             }
-            double2 zi = widen(xi);
-            if (ADD) zi = cadd(z[i], zi);
-            z[i] = zi;
-            if (want_dot) part = redot(vdot[i], zi);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                if (q == 1 && !P.odd) break;
+                const int i = P.ie + q;
+                double2 zi = widen(q == sr ? xr : x[i]);
+                if (ADD) zi = cadd(z[i], zi);
+                z[i] = zi;
+                if (want_dot) part += redot(vdot[i], zi);
+            }
         }
         if (want_dot) block_reduce_store(part, slot, sm, bx);
     }
@@ -693,9 +738,7 @@ template <> const float *diag<float>(const Level &L) { return L.diag32.get(); }
 template <class T> static const T *dgn(const Level &L);
 template <> const double *dgn<double>(const Level &L) { return L.dg64.get(); }
 template <> const float *dgn<float>(const Level &L) { return L.dg32.get(); }
-template <class T> static const C<T> *links(const gl_mesh *m);
-template <> const double2 *links<double>(const gl_mesh *m) { return m->U64.get(); }
-template <> const float2 *links<float>(const gl_mesh *m) { return m->U32.get(); }
+
 template <class T> static const C<T> *cinv(const gl_precond *p);
 template <> const double2 *cinv<double>(const gl_precond *p) { return p->cinv64.get(); }
 template <> const float2 *cinv<float>(const gl_precond *p) { return p->cinv32.get(); }
@@ -824,7 +867,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     gl_precond *pre = const_cast<gl_precond *>(cpre);
     const gl_mesh *m = pre->mesh;
     const GeomT<T> g = geom_t<T>(m->g);
-    const C<T> *U = links<T>(m);
+    const LinkTab<T> U = link_tab<T>(m);
     const RedSlot slot = red_slot(m, 1);
     Level &L0 = pre->L[0];
     const int n0 = L0.n, nb0 = blocks_for(n0);
@@ -845,23 +888,26 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const T *hd = diag<T>(L0);
     Level &L1 = pre->L[1];
     // algorithmic bytes of the level-0 kernels (each array touched once)
-    const double sz = sizeof(C<T>), szr = sizeof(T), E = grid_edges(m->g), nn = n0, mc = 0.5 * nn;
-    const double b_pre = nn * 16 + (f32 ? nn * sz : 0) + nn * szr + E * sz + mc * sz;
-    const double b_sweep = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz;
-    const double b_resid = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + E * sz + nn * sz;
+    // (the link factor tables are a few KB and stay in cache)
+    const double sz = sizeof(C<T>), szr = sizeof(T), nn = n0, mc = 0.5 * nn;
+    const double b_pre = nn * 16 + (f32 ? nn * sz : 0) + nn * szr + mc * sz;
+    const double b_sweep = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz;
+    const double b_resid = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + nn * sz;
     const double szc = sizeof(C<TC>);
     const double b_prol = (mc + 1 + 0.5 * L0.Pa.nnz) * 4.0 + 0.5 * L0.Pa.nnz * szc + L0.nc * szc + 2.0 * mc * sz;
     const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
     const double b_restr = (L0.nc + 1 + L0.Ra.nnz) * 4.0 + L0.Ra.nnz * szc + nn * sz + L0.nc * szc;
-    // level 0, down: red (from zero, folded) + black, red, black residual, restriction
+    // level 0 (one thread per red-black pair), down: red (from zero, folded) +
+    // black, red, black residual, restriction
+    const int nbp = blocks_for(g.npair);
     prof_launch(PROF_L0_SWEEP, b_pre, L, [&] {
-        L.run(nb0, L0PreBlack<DIM, T>{g, v, vec_b<T>(L0), x0, U, hd, gate});
+        L.run(nbp, L0PreBlack<DIM, T>{g, v, vec_b<T>(L0), x0, U, hd, gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
-        L.run(nb0, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
+        L.run(nbp, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
     });
     prof_launch(PROF_L0_RESIDUAL, b_resid, L, [&] {
-        L.run(nb0, L0Residual<DIM, T>{g, v, b0, x0, U, hd, vec_r<T>(L0), gate});
+        L.run(nbp, L0Residual<DIM, T>{g, v, b0, x0, U, hd, vec_r<T>(L0), gate});
     });
     prof_launch(PROF_L0_TRANSFER, b_restr, L, [&] {
         csr_spmv<TC, T>(L0.Ra, vec_r<T>(L0), vec_b<TC>(L1), false, 0, gate, L);
@@ -894,20 +940,20 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     // black coarse correction, then the red pass (fusing the two reads every
     // black correction four times and was measured slower)
     prof_launch(PROF_L0_TRANSFER, b_prol, L, [&] {
-        L.run(nb0, L0ProlongBlack<DIM, T, TC>{g, x0, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<TC>(L0.Pa),
+        L.run(nbp, L0ProlongBlack<DIM, T, TC>{g, x0, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<TC>(L0.Pa),
                                               vec_x<TC>(L1), gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
-        L.run(nb0, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
+        L.run(nbp, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
-        L.run(nb0, L0Sweep<DIM, T>{g, 1, v, b0, x0, U, hd, gate});
+        L.run(nbp, L0Sweep<DIM, T>{g, 1, v, b0, x0, U, hd, gate});
     });
     prof_launch(PROF_L0_SWEEP, b_last, L, [&] {
-        if (add) L.run(nb0, L0Last<DIM, T, 1>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
-        else L.run(nb0, L0Last<DIM, T, 0>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
+        if (add) L.run(nbp, L0Last<DIM, T, 1>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
+        else L.run(nbp, L0Last<DIM, T, 0>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
     });
-    if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, L);
+    if (ks) launch_finalize(slot.partials, nbp, mode, ks, nullptr, gate, L);
 }
 
 template <int DIM, class T, class TC>
@@ -925,7 +971,8 @@ static void vcycle_k(const gl_precond *pre, const double2 *v, double2 *z, const 
     const int nb0 = blocks_for(pre->L[0].n);
     vcycle_once<DIM, T, TC>(pre, v, v, z, gate, nullptr, 0, 0, L);
     for (int c = 1; c < k; ++c) {
-        L.run(nb0, L0ResidualFull<DIM>{g, v, z, m->U64.get(), pre->L[0].diag64.get(), pre->cyc_r.get(), gate});
+        L.run(nb0, L0ResidualFull<DIM>{g, v, z, link_tab<double>(m), pre->L[0].diag64.get(), pre->cyc_r.get(),
+                                       gate});
         const bool lastc = (c == k - 1);
         vcycle_once<DIM, T, TC>(pre, pre->cyc_r.get(), v, z, gate, lastc ? ks : nullptr, mode, 1, L);
     }
