@@ -117,19 +117,21 @@ struct MinresJapply {
     RedSlot slot;
     __device__ void operator()(int bx, int nbx) const
     {
-        if (ks->running == 0) return;
+        // the scalars and the vectors are loaded together; the (uniform)
+        // running flag is checked before the first store
         __shared__ double sm[kBlock / 64];
+        const int running = ks->running;
         const double ig = 1.0 / ks->gamma;
         const bool upd = ks->iter >= 1;
         const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        const bool in = i < g.n;
         double part = 0.0;
-        if (i < g.n) {
+        double2 wn = make_double2(0.0, 0.0), xn = wn, qi = wn;
+        if (in) {
             if (upd) {
                 const double2 zp = cscale(zprev[i], ks->wx_inv_gamma);
-                const double2 wn = cscale(csub(csub(zp, cscale(wp[i], ks->wx_a3)), cscale(w[i], ks->wx_a2)),
-                                          1.0 / ks->wx_a1);
-                wp[i] = wn;
-                x[i] = cadd(x[i], cscale(wn, ks->wx_coef));
+                wn = cscale(csub(csub(zp, cscale(wp[i], ks->wx_a3)), cscale(w[i], ks->wx_a2)), 1.0 / ks->wx_a1);
+                xn = cadd(x[i], cscale(wn, ks->wx_coef));
             }
             int c[3];
             node_coords<DIM>(g.N, i, c);
@@ -139,9 +141,16 @@ struct MinresJapply {
             const double2 zn = cscale(zi, ig);
             const double2 p = psi[i];
             const double2 react = cadd(cscale(zn, 2.0 * cabs2(p) - 1.0), cmul(cmul(p, p), cconj(zn)));
-            const double2 qi = cadd(cscale(kz, ig), cscale(react, d));
-            q[i] = qi;
+            qi = cadd(cscale(kz, ig), cscale(react, d));
             part = redot(qi, zn);
+        }
+        if (running == 0) return;
+        if (in) {
+            if (upd) {
+                wp[i] = wn;
+                x[i] = xn;
+            }
+            q[i] = qi;
         }
         block_reduce_store(part, slot, sm, bx);
     }
@@ -154,11 +163,13 @@ struct MinresVupdate {
     const KrylovScalars *ks;
     __device__ void operator()(int bx, int) const
     {
-        if (ks->running == 0) return;
+        const int running = ks->running;
         const double a = ks->delta / ks->gamma, b = ks->gamma / ks->gamma_prev;
         const int i = bx * kBlock + threadIdx.x;
         if (i >= n) return;
-        vp[i] = csub(csub(q[i], cscale(v[i], a)), cscale(vp[i], b));
+        const double2 qi = q[i], vi = v[i], vpi = vp[i];
+        if (running == 0) return;
+        vp[i] = csub(csub(qi, cscale(vi, a)), cscale(vpi, b));
     }
 };
 

@@ -39,10 +39,13 @@ struct Finalize {
     const int *gate;
     __device__ void operator()(int, int) const
     {
-        if (gate && *gate == 0) return;
+        // the (uniform) gate flag is loaded with the partials and checked
+        // before the barrier of the block sum
+        const bool go = gate == nullptr || *gate != 0;
         __shared__ double sm[1024 / 64];
         double s = 0.0;
         for (int k = threadIdx.x; k < nparts; k += blockDim.x) s += partials[k];
+        if (!go) return;
         s = block_sum(s, sm);
         if (threadIdx.x == 0) {
             if (mode == FIN_STORE) *out = s;

@@ -26,6 +26,11 @@ namespace glk {
 #define GATE()                               \
     if (gate && *gate == 0) return
 
+// The gate flag read together with a kernel's data and checked right before
+// its stores, so that its load overlaps the others instead of delaying them;
+// the flag is uniform, so every thread takes the same branch.
+#define GATE_LOAD() const bool gate_go = gate == nullptr || *gate != 0
+
 template <class T> __device__ __forceinline__ C<T> load_b(const double2 *v, const C<T> *b, int i)
 {
     if constexpr (std::is_same<T, double>::value) return v[i];
@@ -73,13 +78,16 @@ struct L0PreBlack {
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
-        GATE();
+        GATE_LOAD();
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         if (t >= g.npair) return;
         const Pair P = pair_at<DIM, T>(g, t);
         if constexpr (std::is_same<T, float>::value) {
-            b[P.ie] = narrow<T>(v[P.ie]);
-            if (P.odd) b[P.ie + 1] = narrow<T>(v[P.ie + 1]);
+            const C<T> b0 = narrow<T>(v[P.ie]);
+            const C<T> b1 = P.odd ? narrow<T>(v[P.ie + 1]) : mk<T>(0, 0);
+            if (!gate_go) return;
+            b[P.ie] = b0;
+            if (P.odd) b[P.ie + 1] = b1;
         }
         int sb;
         if (!pair_colour(P, 1, sb)) return;
@@ -105,7 +113,9 @@ struct L0PreBlack {
             }
             stride *= g.N[a];
         }
-        x[i] = cscale(csub(bi, off), (T)1 / hd[i]);
+        const C<T> xi = cscale(csub(bi, off), (T)1 / hd[i]);
+        if (!gate_go) return;
+        x[i] = xi;
     }
 };
 
@@ -122,7 +132,7 @@ struct L0Sweep {
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
-        GATE();
+        GATE_LOAD();
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         if (t >= g.npair) return;
         const Pair P = pair_at<DIM, T>(g, t);
@@ -130,8 +140,12 @@ struct L0Sweep {
         if (!pair_colour(P, colour, sc)) return;
         const int i = P.ie + sc;
         const int c[3] = {P.c[0] + sc, P.c[1], P.c[2]};
+        const C<T> bi = load_b<T>(v, b, i);
+        const T di = hd[i];
         const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-        x[i] = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
+        const C<T> xi = cscale(csub(bi, off), (T)1 / di);
+        if (!gate_go) return;
+        x[i] = xi;
     }
 };
 
@@ -147,17 +161,25 @@ struct L0Residual {
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
-        GATE();
+        GATE_LOAD();
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         if (t >= g.npair) return;
         const Pair P = pair_at<DIM, T>(g, t);
         int sb, sr;
-        if (pair_colour(P, 0, sr)) r[P.ie + sr] = mk<T>(0, 0);
-        if (!pair_colour(P, 1, sb)) return;
+        const bool red = pair_colour(P, 0, sr), black = pair_colour(P, 1, sb);
+        C<T> ri = mk<T>(0, 0);
         const int i = P.ie + sb;
-        const int c[3] = {P.c[0] + sb, P.c[1], P.c[2]};
-        const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-        r[i] = csub(csub(load_b<T>(v, b, i), cscale(x[i], hd[i])), off);
+        if (black) {
+            const int c[3] = {P.c[0] + sb, P.c[1], P.c[2]};
+            const C<T> bi = load_b<T>(v, b, i);
+            const C<T> xi = x[i];
+            const T di = hd[i];
+            const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+            ri = csub(csub(bi, cscale(xi, di)), off);
+        }
+        if (!gate_go) return;
+        if (red) r[P.ie + sr] = mk<T>(0, 0);
+        if (black) r[i] = ri;
     }
 };
 
@@ -203,14 +225,17 @@ struct L0ProlongBlack {
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
-        GATE();
+        GATE_LOAD();
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         if (t >= g.npair) return;
         const Pair P = pair_at<DIM, T>(g, t);
         int sb;
         if (!pair_colour(P, 1, sb)) return;
         const int i = P.ie + sb;
-        x[i] = cadd(x[i], as_c<T>(prolong_row<TC>(prp, pci, pv, xc, i)));
+        const C<T> xo = x[i];
+        const C<T> xi = cadd(xo, as_c<T>(prolong_row<TC>(prp, pci, pv, xc, i)));
+        if (!gate_go) return;
+        x[i] = xi;
     }
 };
 
@@ -230,31 +255,42 @@ struct L0Last {
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
-        GATE();
+        GATE_LOAD();
         __shared__ double sm[kBlock / 64];
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        const bool in = t < g.npair;
+        const Pair P = pair_at<DIM, T>(g, in ? t : 0);
+        // the red node's update, then z on both nodes (even first); every
+        // load before the (uniform) gate check, every store after it
+        int sr;
+        const bool red = in && pair_colour(P, 0, sr);
+        C<T> xr = mk<T>(0, 0);
+        double2 zq[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
         double part = 0.0;
-        if (t < g.npair) {
-            const Pair P = pair_at<DIM, T>(g, t);
-            // the red node's update, then z on both nodes (even first)
-            int sr;
-            C<T> xr = mk<T>(0, 0);
-            if (pair_colour(P, 0, sr)) {
-                const int i = P.ie + sr;
-                const int c[3] = {P.c[0] + sr, P.c[1], P.c[2]};
-                const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-                xr = cscale(csub(load_b<T>(v, b, i), off), (T)1 / hd[i]);
-                x[i] = xr;
-            }
+        if (red) {
+            const int i = P.ie + sr;
+            const int c[3] = {P.c[0] + sr, P.c[1], P.c[2]};
+            const C<T> bi = load_b<T>(v, b, i);
+            const T di = hd[i];
+            const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+            xr = cscale(csub(bi, off), (T)1 / di);
+        }
+        if (in) {
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 if (q == 1 && !P.odd) break;
                 const int i = P.ie + q;
-                double2 zi = widen(q == sr ? xr : x[i]);
+                double2 zi = widen(red && q == sr ? xr : x[i]);
                 if (ADD) zi = cadd(z[i], zi);
-                z[i] = zi;
+                zq[q] = zi;
                 if (want_dot) part += redot(vdot[i], zi);
             }
+        }
+        if (!gate_go) return;
+        if (in) {
+            if (red) x[P.ie + sr] = xr;
+            z[P.ie] = zq[0];
+            if (P.odd) z[P.ie + 1] = zq[1];
         }
         if (want_dot) block_reduce_store(part, slot, sm, bx);
     }
@@ -293,6 +329,11 @@ struct EllSgs {
         const int r = t / LPR, lane = t % LPR;
         const bool act = r < count;
         const int i = row0 + (act ? r : 0);
+        // the row's b and diagonal are loaded before the gathers (they do not
+        // depend on them), so the store waits for one memory round trip less
+        const bool own = act && lane == 0;
+        const C<T> bi = own ? b[i] : mk<T>(0, 0);
+        const T di = own ? diag[i] : (T)1;
         C<T> s = mk<T>(0, 0);
         if (act) {
             const size_t base = (size_t)r * W;
@@ -302,7 +343,7 @@ struct EllSgs {
             }
         }
         s = lanes_sum<T, LPR>(s);
-        if (act && lane == 0 && go) x[i] = cscale(csub(b[i], s), (T)1 / diag[i]);
+        if (own && go) x[i] = cscale(csub(bi, s), (T)1 / di);
     }
 };
 
@@ -327,6 +368,9 @@ struct EllSgsStart {
         const int t = bx * kBlock + threadIdx.x;
         const int r = t / LPR, lane = t % LPR;
         const bool valid = r < n, one = valid && r >= c1 && r < c2;
+        const bool own = valid && lane == 0 && r < c2;
+        const C<T> br = own ? b[r] : mk<T>(0, 0);
+        const T dr = own ? diag[r] : (T)1;
         C<T> s = mk<T>(0, 0);
         if (one) {
             const size_t base = (size_t)(r - c1) * W;
@@ -337,8 +381,8 @@ struct EllSgsStart {
         }
         s = lanes_sum<T, LPR>(s);
         if (valid && lane == 0 && go) {
-            if (r < c1) x[r] = cscale(b[r], (T)1 / diag[r]);
-            else if (r < c2) x[r] = cscale(csub(b[r], s), (T)1 / diag[r]);
+            if (r < c1) x[r] = cscale(br, (T)1 / dr);
+            else if (r < c2) x[r] = cscale(csub(br, s), (T)1 / dr);
             else x[r] = mk<T>(0, 0);
         }
     }
@@ -354,15 +398,16 @@ struct CsrResidual {
     const int *gate;
     __device__ void operator()(int bx, int) const
     {
-        GATE();
+        GATE_LOAD();
         const int t = bx * kBlock + threadIdx.x;
         const int i = t / LPR, lane = t % LPR;
         const bool act = i < n;
+        const C<T> bi = act && lane == 0 ? b[i] : mk<T>(0, 0);
         C<T> s = mk<T>(0, 0);
         if (act)
             for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], as_c<T>(x[ci[p]])));
         s = lanes_sum<T, LPR>(s);
-        if (act && lane == 0) r[i] = csub(b[i], s);
+        if (act && lane == 0 && gate_go) r[i] = csub(bi, s);
     }
 };
 
@@ -377,15 +422,16 @@ struct CsrSpmv {
     const int *gate;
     __device__ void operator()(int bx, int) const
     {
-        GATE();
+        GATE_LOAD();
         const int t = bx * kBlock + threadIdx.x;
         const int i = t / LPR, lane = t % LPR;
         const bool act = i < n;
+        const C<T> yi = ADD && act && lane == 0 ? y[i] : mk<T>(0, 0);
         C<T> s = mk<T>(0, 0);
         if (act)
             for (int p = rp[i] + lane; p < rp[i + 1]; p += LPR) s = cadd(s, cmul(v[p], as_c<T>(x[ci[p]])));
         s = lanes_sum<T, LPR>(s);
-        if (act && lane == 0) y[i] = ADD ? cadd(y[i], s) : s;
+        if (act && lane == 0 && gate_go) y[i] = ADD ? cadd(yi, s) : s;
     }
 };
 
@@ -451,7 +497,7 @@ struct DenseApply {
     const int *gate;
     __device__ void operator()(int bx, int) const
     {
-        GATE();
+        GATE_LOAD();
         const int t = bx * kBlock + threadIdx.x;
         const int i = t / 64, lane = t % 64;
         const bool act = i < n;
@@ -459,7 +505,7 @@ struct DenseApply {
         if (act)
             for (int j = lane; j < n; j += 64) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
         s = lanes_sum<T, 64>(s);
-        if (act && lane == 0) x[i] = s;
+        if (act && lane == 0 && gate_go) x[i] = s;
     }
 };
 
