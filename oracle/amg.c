@@ -28,7 +28,8 @@
  *   colours       : level 0 of a tensor grid: parity of the index sum; otherwise
  *                   greedy by decreasing colour priority (largest degree first,
  *                   then the hash with salt l + 101, then the index), smallest
- *                   colour unused by already coloured neighbours
+ *                   colour unused by already coloured neighbours, followed by
+ *                   two iterated-greedy passes (classes in reverse order)
  *   SGS sweep     : colours 0 .. C-1, then C-2 .. 0
  *   V-cycle       : x = SGS(0, b); r = b - A x; x += P V(R r); x = SGS(x, b)
  */
@@ -55,6 +56,8 @@ static uint64_t key_with_salt(int64_t i, uint32_t salt)
 }
 
 static uint64_t mis_key(int64_t i, int l) { return key_with_salt(i, (uint32_t)(l + 1)); }
+#define ORC_RECOLOUR_PASSES 2
+
 /* colour priority: largest degree first, then the hashed key (upper 22
  * bits), then the index: ((min(deg, 1023) << 54) | (fmix32 >> 10) << 32 | i */
 static uint64_t color_key(int64_t i, int64_t deg, int l)
@@ -182,8 +185,32 @@ static void colour_level(orc_level *L, int l, int grid_dim, const int64_t *grid_
             if (cc >= 0) used[cc] = 0;
         }
     }
-    free(used);
     free(ord);
+    /* iterated greedy (Culberson): greedy once more with the vertices taken a
+     * colour class at a time, the classes in reverse order (a class is an
+     * independent set, so the order inside it does not matter); this never
+     * needs more colours than there are classes and often fewer */
+    int32_t *nw = malloc((size_t)n * sizeof(int32_t));
+    for (int pass = 0; pass < ORC_RECOLOUR_PASSES; ++pass) {
+        for (int64_t i = 0; i < n; ++i) nw[i] = -1;
+        int newmax = 0;
+        for (int32_t cls = maxc - 1; cls >= 0; --cls)
+            for (int64_t i = 0; i < n; ++i) {
+                if (L->color[i] != cls) continue;
+                for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p)
+                    if (L->ci[p] != i && nw[L->ci[p]] >= 0) used[nw[L->ci[p]]] = 1;
+                int32_t c = 0;
+                while (used[c]) ++c;
+                nw[i] = c;
+                if (c + 1 > newmax) newmax = c + 1;
+                for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p)
+                    if (nw[L->ci[p]] >= 0) used[nw[L->ci[p]]] = 0;
+            }
+        memcpy(L->color, nw, (size_t)n * sizeof(int32_t));
+        maxc = newmax;
+    }
+    free(nw);
+    free(used);
     L->ncolors = maxc;
 }
 

@@ -36,6 +36,24 @@ def colour_keys(nb, salt):
     return [(min(len(nb[i]), 1023) << 54) | ((fmix32(i ^ s) >> 10) << 32) | i for i in range(len(nb))]
 
 
+def iterated_greedy(nb, col, passes=2):
+    """Greedy again with the vertices taken a colour class at a time, the
+    classes in reverse order (Culberson's iterated greedy), `passes` times."""
+    col = list(col)
+    for _ in range(passes):
+        new = [-1] * len(nb)
+        for c in range(max(col), -1, -1):
+            for i in range(len(nb)):
+                if col[i] == c:
+                    used = {new[j] for j in nb[i]}
+                    k = 0
+                    while k in used:
+                        k += 1
+                    new[i] = k
+        col = new
+    return col
+
+
 def neighbours(A):
     A = sp.csr_matrix(A)
     return [[j for j in A.indices[A.indptr[i]:A.indptr[i + 1]] if j != i] for i in range(A.shape[0])]
@@ -159,7 +177,8 @@ def test_aggregate_assignment_rules(hierarchies):
 
 def test_colouring_proper_and_greedy(hierarchies):
     """Level 0 of a grid: red-black parity; coarser levels: proper colourings
-    equal to Jones-Plassmann rounds with the colour priorities."""
+    equal to Jones-Plassmann rounds with the colour priorities followed by two
+    iterated-greedy passes, with no more colours than the rounds alone."""
     for m, psi, amg in hierarchies:
         L0 = amg.levels[0]
         idx = np.stack(np.unravel_index(np.arange(m.n), m.N[::-1])[::-1], axis=1)
@@ -171,7 +190,9 @@ def test_colouring_proper_and_greedy(hierarchies):
             assert L["ncolors"] == L["color"].max() + 1
             if l > 0 and L["n"] <= 400:
                 nb = neighbours(L["A"])
-                assert jones_plassmann(nb, colour_keys(nb, l + 101)) == list(L["color"])
+                jp = jones_plassmann(nb, colour_keys(nb, l + 101))
+                assert iterated_greedy(nb, jp) == list(L["color"])
+                assert L["ncolors"] <= max(jp) + 1
 
 
 def test_transfer_and_galerkin_operators(hierarchies):
