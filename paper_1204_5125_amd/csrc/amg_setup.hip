@@ -382,6 +382,8 @@ __global__ void k_parity_colour(Geom g, int *col)
 
 // colour priority: largest degree first (number of off-diagonal entries,
 // capped at 1023), then the upper 22 bits of the hash, then the index
+constexpr int kRecolourPasses = 2;  // iterated-greedy passes after the colouring rounds
+
 __device__ __forceinline__ unsigned long long colour_key(int i, const int *rp, unsigned salt)
 {
     const unsigned long long d = (unsigned long long)min(rp[i + 1] - rp[i] - 1, 1023);
@@ -424,6 +426,25 @@ __global__ void k_jp_colour(int n, const int *rp, const int *ci, const int *read
     while (c < 256 && (used[c >> 6] >> (c & 63) & 1ull)) ++c;
     if (c == 256) atomicOr(err, 8);
     col[i] = c;
+}
+
+// Iterated greedy (Culberson): the rows of one colour class (an independent
+// set, so they do not see each other) take the smallest colour not yet given
+// to a neighbour in this pass; classes are visited in reverse order.
+__global__ void k_ig_class(int n, const int *rp, const int *ci, const int *old, int cls, int *nw, int *err)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n || old[i] != cls) return;
+    unsigned long long used[4] = {0, 0, 0, 0};
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        const int j = ci[p];
+        const int c = (j != i) ? nw[j] : -1;
+        if (c >= 0 && c < 256) used[c >> 6] |= 1ull << (c & 63);
+    }
+    int c = 0;
+    while (c < 256 && (used[c >> 6] >> (c & 63) & 1ull)) ++c;
+    if (c == 256) atomicOr(err, 8);
+    nw[i] = c;
 }
 
 __global__ void k_colour_hist(int n, const int *col, int *hist)
@@ -809,15 +830,32 @@ static void colour_level(gl_precond *pre, int l, hipStream_t s)
             if (read_int(cnt.get(), s) == 0) break;
         }
         check_err(err, s, "colouring");
-        // number of colours
+        // class sizes and the number of colours
         DevBuf<int> hist(257);
-        GLK_HIP(hipMemsetAsync(hist.get(), 0, 257 * sizeof(int), s));
-        k_colour_hist<<<nb, kBlock, 0, s>>>(n, L.color.get(), hist.get());
-        GLK_CHECK_LAUNCH();
-        std::vector<int> h = to_host(hist.get(), 257, s);
+        std::vector<int> h;
         int nc = 0;
-        for (int c = 0; c < 257; ++c)
-            if (h[c]) nc = c + 1;
+        auto count = [&] {
+            GLK_HIP(hipMemsetAsync(hist.get(), 0, 257 * sizeof(int), s));
+            k_colour_hist<<<nb, kBlock, 0, s>>>(n, L.color.get(), hist.get());
+            GLK_CHECK_LAUNCH();
+            h = to_host(hist.get(), 257, s);
+            nc = 0;
+            for (int c = 0; c < 257; ++c)
+                if (h[c]) nc = c + 1;
+        };
+        count();
+        // iterated greedy: never more colours, often fewer (each colour costs
+        // two dependent passes per symmetric sweep)
+        DevBuf<int> nw(n);
+        for (int pass = 0; pass < kRecolourPasses; ++pass) {
+            k_fill_int<<<nb, kBlock, 0, s>>>(nw.get(), n, -1);
+            for (int c = nc - 1; c >= 0; --c)
+                k_ig_class<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.color.get(), c, nw.get(), err.get());
+            GLK_CHECK_LAUNCH();
+            GLK_HIP(hipMemcpyAsync(L.color.get(), nw.get(), sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, s));
+            count();
+        }
+        check_err(err, s, "recolouring");
         L.ncolors = nc;
         // rows grouped by colour
         L.cperm.alloc(n);
