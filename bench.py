@@ -43,8 +43,8 @@ MAX_COARSE = 512
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "861bbc2d1c8ac2af0a4ed2d4538502b2afddaaf623452efb23668ae431b9f881",
-           8: 4545403.7, 2: 41871469.7}
+TRAFFIC = {"csrc_sha256": "2385d263d94dccd0a9567ef204010c970ba56a58633f9ec7f3db02da78231382",
+           8: 5259216.2, 2: 35026585.7}
 
 
 def csrc_fingerprint():
