@@ -13,7 +13,7 @@ import time
 
 from . import glnk
 
-CANDIDATES = [(ls, br) for ls in (-1, 0, 1) for br in (512, 2048, 8192, 16384)]
+CANDIDATES = [(ls, br) for ls in (-1, 0, 1) for br in (64, 512, 2048, 8192)]
 
 
 def _key(mesh, precision, max_coarse):

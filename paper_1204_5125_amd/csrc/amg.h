@@ -70,7 +70,6 @@ struct BottomLevel {
     const C<T> *pv;
     const int *rrp, *rci;
     const C<T> *rv;
-    int pnnz, rnnz;
     C<T> *b, *x, *r;
     // the operator once more as per-colour padded blocks (ELL): row r of
     // colour c holds ewidth[c] entries at eoff[c] + (r - coff[c]) ewidth[c]

@@ -513,213 +513,86 @@ struct DenseApply {
 // Every level from D.first down to the coarsest, in one work-group of
 // kBottomThreads threads: the same V-cycle steps as the multi-kernel levels,
 // separated by work-group barriers, and the dense solve.  One work-group
-// avoids a dispatch per colour pass; what bounds it is the latency of each
-// step's loads and the bandwidth of one compute unit, so every step gives a
-// thread whole rows (two row slots, r and r + kBottomThreads) and issues the
-// row's entry loads ahead of the products.  Measured on MI355X, a step costs
-// about 3 us even over a handful of rows (a dependent global load is about
-// 1 us away) and one compute unit streams about 20-25 GB/s, so the kernel
-// pays only for levels of a few hundred rows; the tile autotuner chooses
-// the bound (bottom_rows).
-constexpr int kBottomThreads = 512;
-constexpr int kBottomAhead = 8;   // entries of a row loaded ahead of use
+// avoids a dispatch per colour pass, but a step costs about 3 us even over a
+// handful of rows (a dependent global load is about 1 us away, measured on
+// MI355X) and one compute unit streams about 20-25 GB/s, so this pays only for
+// levels of a few hundred rows; the tile autotuner chooses the bound
+// (bottom_rows).  Eight lanes share a row, so a colour pass of such a level
+// is one round of loads.
+constexpr int kBottomThreads = 1024;
+constexpr int kBottomLpr = 8;
 
-// One row of a padded block: entry k at base + k, `width` entries (0: empty
-// slot), `self` the row's own index (skipped: padding and the diagonal).
-struct EllSlot {
-    size_t base;
-    int width, self;
-};
-
-// sum over the stored entries (j != self) of a_k x_j for two row slots, the
-// entry loads of both issued ahead of the products
+// one colour of a level, from its ELL block; x in LDS or global memory
 template <class T>
-__device__ __forceinline__ void bottom_ell2(const int *__restrict__ eci, const C<T> *__restrict__ ev,
-                                            const EllSlot p, const EllSlot q, const C<T> *x, C<T> &sp,
-                                            C<T> &sq)
+__device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int colour, C<T> *x)
 {
-    sp = sq = mk<T>(0, 0);
-    const int W = max(p.width, q.width);
-    for (int k0 = 0; k0 < W; k0 += kBottomAhead) {
-        int jp[kBottomAhead], jq[kBottomAhead];
-        C<T> ap[kBottomAhead], aq[kBottomAhead];
-#pragma unroll
-        for (int u = 0; u < kBottomAhead; ++u) {
-            const int k = k0 + u;
-            jp[u] = p.self;
-            jq[u] = q.self;
-            ap[u] = aq[u] = mk<T>(0, 0);
-            if (k < p.width) {
-                const size_t e = p.base + k;
-                jp[u] = eci[e];
-                ap[u] = ev[e];
+    const int cnt = L.coff[colour + 1] - L.coff[colour];
+    const int row0 = L.coff[colour];
+    const int W = L.ewidth[colour];
+    const int *eci = L.eci + L.eoff[colour];
+    const C<T> *ev = L.ev + L.eoff[colour];
+    const int per = kBottomThreads / kBottomLpr;
+    const int lane = threadIdx.x % kBottomLpr;
+    for (int base = 0; base < cnt; base += per) {
+        const int r = base + threadIdx.x / kBottomLpr;
+        const bool act = r < cnt;
+        const int i = row0 + (act ? r : 0);
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int k = lane; k < W; k += kBottomLpr) {
+                const int j = eci[(size_t)r * W + k];
+                if (j != i) s = cadd(s, cmul(ev[(size_t)r * W + k], x[j]));
             }
-            if (k < q.width) {
-                const size_t e = q.base + k;
-                jq[u] = eci[e];
-                aq[u] = ev[e];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kBottomAhead; ++u) {
-            if (jp[u] != p.self) sp = cadd(sp, cmul(ap[u], x[jp[u]]));
-            if (jq[u] != q.self) sq = cadd(sq, cmul(aq[u], x[jq[u]]));
-        }
+        s = lanes_sum<T, kBottomLpr>(s);
+        if (act && lane == 0) x[i] = cscale(csub(L.b[i], s), (T)1 / L.diag[i]);
     }
 }
 
-// Gauss-Seidel update of one colour (rows of a colour are independent)
-template <class T>
-__device__ __forceinline__ void bottom_colour(const BottomLevel<T> &L, int c, C<T> *x)
-{
-    const int cnt = L.coff[c + 1] - L.coff[c], row0 = L.coff[c], W = L.ewidth[c];
-    const int *eci = L.eci + L.eoff[c];
-    const C<T> *ev = L.ev + L.eoff[c];
-    for (int r0 = threadIdx.x; r0 < cnt; r0 += 2 * kBottomThreads) {
-        const int r1 = r0 + kBottomThreads;
-        C<T> s0, s1;
-        bottom_ell2<T>(eci, ev, EllSlot{(size_t)r0 * W, W, row0 + r0},
-                       EllSlot{(size_t)r1 * W, r1 < cnt ? W : 0, row0 + r1}, x, s0, s1);
-        x[row0 + r0] = cscale(csub(L.b[row0 + r0], s0), (T)1 / L.diag[row0 + r0]);
-        if (r1 < cnt) x[row0 + r1] = cscale(csub(L.b[row0 + r1], s1), (T)1 / L.diag[row0 + r1]);
-    }
-}
-
-// one symmetric sweep: colours 0 .. C-1, then C-2 .. 0; from zero the first
-// pass is x = b / a_ii on colour 0 and every other row starts at 0
-template <class T>
-__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L, C<T> *x, bool from_zero)
-{
-    int t0 = 0;
-    if (from_zero) {
-        const int c1 = L.coff[1];
-        for (int i = threadIdx.x; i < L.n; i += kBottomThreads)
-            x[i] = i < c1 ? cscale(L.b[i], (T)1 / L.diag[i]) : mk<T>(0, 0);
-        __syncthreads();
-        t0 = 1;
-    }
-    for (int t = t0; t < 2 * L.ncolors - 1; ++t) {
-        bottom_colour<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, x);
-        __syncthreads();
-    }
-}
-
-// r = b - A x on every row, from the colour blocks (row i of colour c is row
-// i - coff[c] of block c)
-template <class T>
-__device__ __forceinline__ EllSlot bottom_row_slot(const BottomLevel<T> &L, int i)
-{
-    if (i >= L.n) return EllSlot{0, 0, i};
-    int c = 0;
-    while (i >= L.coff[c + 1]) ++c;
-    return EllSlot{(size_t)L.eoff[c] + (size_t)(i - L.coff[c]) * L.ewidth[c], L.ewidth[c], i};
-}
-
-template <class T>
-__device__ __forceinline__ void bottom_residual(const BottomLevel<T> &L, const C<T> *x)
-{
-    for (int i0 = threadIdx.x; i0 < L.n; i0 += 2 * kBottomThreads) {
-        const int i1 = i0 + kBottomThreads;
-        C<T> s0, s1;
-        bottom_ell2<T>(L.eci, L.ev, bottom_row_slot(L, i0), bottom_row_slot(L, i1), x, s0, s1);
-        L.r[i0] = csub(csub(L.b[i0], s0), cscale(x[i0], L.diag[i0]));
-        if (i1 < L.n) L.r[i1] = csub(csub(L.b[i1], s1), cscale(x[i1], L.diag[i1]));
-    }
-}
-
-// CSR rows with LPR lanes per row, two rows per lane group (i and i + per),
-// kBottomAhead entries of each loaded ahead.  MODE 0: y = M x, 1: y += M x
-template <class T, int LPR, int MODE>
-__device__ __forceinline__ void bottom_csr(int nrows, const int *__restrict__ rp, const int *__restrict__ ci,
-                                           const C<T> *__restrict__ v, const C<T> *x, C<T> *y)
-{
-    const int per = kBottomThreads / LPR;
-    const int lane = threadIdx.x % LPR;
-    for (int base = 0; base < nrows; base += 2 * per) {
-        const int i0 = base + threadIdx.x / LPR, i1 = i0 + per;
-        const int b0 = i0 < nrows ? rp[i0] : 0, e0 = i0 < nrows ? rp[i0 + 1] : 0;
-        const int b1 = i1 < nrows ? rp[i1] : 0, e1 = i1 < nrows ? rp[i1 + 1] : 0;
-        const int len = max(e0 - b0, e1 - b1);
-        C<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
-        for (int o = lane; o < len; o += LPR * kBottomAhead) {
-            int j0[kBottomAhead], j1[kBottomAhead];
-            C<T> a0[kBottomAhead], a1[kBottomAhead];
-#pragma unroll
-            for (int u = 0; u < kBottomAhead; ++u) {
-                const int k = o + u * LPR;
-                j0[u] = j1[u] = -1;
-                a0[u] = a1[u] = mk<T>(0, 0);
-                if (b0 + k < e0) {
-                    j0[u] = ci[b0 + k];
-                    a0[u] = v[b0 + k];
-                }
-                if (b1 + k < e1) {
-                    j1[u] = ci[b1 + k];
-                    a1[u] = v[b1 + k];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kBottomAhead; ++u) {
-                if (j0[u] >= 0) s0 = cadd(s0, cmul(a0[u], x[j0[u]]));
-                if (j1[u] >= 0) s1 = cadd(s1, cmul(a1[u], x[j1[u]]));
-            }
-        }
-        s0 = lanes_sum<T, LPR>(s0);
-        s1 = lanes_sum<T, LPR>(s1);
-        if (lane == 0) {
-            if (i0 < nrows) y[i0] = MODE == 0 ? s0 : cadd(y[i0], s0);
-            if (i1 < nrows) y[i1] = MODE == 0 ? s1 : cadd(y[i1], s1);
-        }
-    }
-}
-
-// lanes per row of a CSR matrix inside the bottom kernel
+// MODE 0: y = M x, 1: y += M x, 2: y = b - M x
 template <class T, int MODE>
-__device__ __forceinline__ void bottom_spmv(int nrows, int nnz, const int *rp, const int *ci, const C<T> *v,
-                                            const C<T> *x, C<T> *y)
+__device__ __forceinline__ void bottom_rows_spmv(int nrows, const int *rp, const int *ci, const C<T> *v,
+                                                 const C<T> *x, const C<T> *b, C<T> *y)
 {
-    if (nnz <= 6 * nrows) bottom_csr<T, 1, MODE>(nrows, rp, ci, v, x, y);
-    else if (nnz <= 24 * nrows) bottom_csr<T, 4, MODE>(nrows, rp, ci, v, x, y);
-    else bottom_csr<T, 16, MODE>(nrows, rp, ci, v, x, y);
+    const int per = kBottomThreads / kBottomLpr;
+    const int lane = threadIdx.x % kBottomLpr;
+    for (int base = 0; base < nrows; base += per) {
+        const int i = base + threadIdx.x / kBottomLpr;
+        const bool act = i < nrows;
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int p = rp[i] + lane; p < rp[i + 1]; p += kBottomLpr) s = cadd(s, cmul(v[p], x[ci[p]]));
+        s = lanes_sum<T, kBottomLpr>(s);
+        if (act && lane == 0) {
+            if (MODE == 0) y[i] = s;
+            else if (MODE == 1) y[i] = cadd(y[i], s);
+            else y[i] = csub(b[i], s);
+        }
+    }
 }
 
-// y = M b for a dense row-major n x n matrix: 16 lanes per row, two rows per
-// lane group, kBottomAhead entries of each loaded ahead
+// y = M b for a dense row-major n x n matrix
 template <class T>
-__device__ __forceinline__ void bottom_dense(int n, const C<T> *__restrict__ M, const C<T> *__restrict__ b,
-                                             C<T> *y)
+__device__ __forceinline__ void bottom_dense(int n, const C<T> *M, const C<T> *b, C<T> *y)
 {
-    constexpr int LPR = 16;
-    const int per = kBottomThreads / LPR;
-    const int lane = threadIdx.x % LPR;
-    for (int base = 0; base < n; base += 2 * per) {
-        const int i0 = base + threadIdx.x / LPR, i1 = i0 + per;
-        const C<T> *m0 = M + (size_t)min(i0, n - 1) * n, *m1 = M + (size_t)min(i1, n - 1) * n;
-        C<T> s0 = mk<T>(0, 0), s1 = mk<T>(0, 0);
-        for (int o = lane; o < n; o += LPR * kBottomAhead) {
-            C<T> a0[kBottomAhead], a1[kBottomAhead], bb[kBottomAhead];
-#pragma unroll
-            for (int u = 0; u < kBottomAhead; ++u) {
-                const int j = o + u * LPR;
-                a0[u] = a1[u] = bb[u] = mk<T>(0, 0);
-                if (j < n) {
-                    a0[u] = m0[j];
-                    a1[u] = m1[j];
-                    bb[u] = b[j];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kBottomAhead; ++u) {
-                s0 = cadd(s0, cmul(a0[u], bb[u]));
-                s1 = cadd(s1, cmul(a1[u], bb[u]));
-            }
-        }
-        s0 = lanes_sum<T, LPR>(s0);
-        s1 = lanes_sum<T, LPR>(s1);
-        if (lane == 0) {
-            if (i0 < n) y[i0] = s0;
-            if (i1 < n) y[i1] = s1;
-        }
+    const int per = kBottomThreads / kBottomLpr;
+    const int lane = threadIdx.x % kBottomLpr;
+    for (int base = 0; base < n; base += per) {
+        const int i = base + threadIdx.x / kBottomLpr;
+        const bool act = i < n;
+        C<T> s = mk<T>(0, 0);
+        if (act)
+            for (int j = lane; j < n; j += kBottomLpr) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
+        s = lanes_sum<T, kBottomLpr>(s);
+        if (act && lane == 0) y[i] = s;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L, C<T> *x)
+{
+    for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
+        bottom_rows_sgs<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, x);
+        __syncthreads();
     }
 }
 
@@ -729,7 +602,7 @@ template <class T>
 struct Bottom {
     const BottomDesc<T> *Dp;
     const int *gate;
-    __device__ __forceinline__ void operator()(int, int) const
+    __device__ void operator()(int, int) const
     {
         GATE();
         extern __shared__ double2 glk_bottom_lds[];
@@ -738,10 +611,12 @@ struct Bottom {
         for (int l = D.first; l < D.last; ++l) {
             const BottomLevel<T> &L = D.L[l];
             C<T> *x = l == D.lds_level ? xs : L.x;
-            bottom_sgs<T>(L, x, true);
-            bottom_residual<T>(L, x);
+            for (int i = threadIdx.x; i < L.n; i += kBottomThreads) x[i] = mk<T>(0, 0);
             __syncthreads();
-            bottom_spmv<T, 0>(L.nc, L.rnnz, L.rrp, L.rci, L.rv, L.r, D.L[l + 1].b);
+            bottom_sgs<T>(L, x);
+            bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, x, L.b, L.r);
+            __syncthreads();
+            bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, L.r, nullptr, D.L[l + 1].b);
             __syncthreads();
         }
         // coarsest level: x = A^-1 b with the dense inverse
@@ -753,9 +628,9 @@ struct Bottom {
         for (int l = D.last - 1; l >= D.first; --l) {
             const BottomLevel<T> &L = D.L[l];
             C<T> *x = l == D.lds_level ? xs : L.x;
-            bottom_spmv<T, 1>(L.n, L.pnnz, L.prp, L.pci, L.pv, D.L[l + 1].x, x);
+            bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, x);
             __syncthreads();
-            bottom_sgs<T>(L, x, false);
+            bottom_sgs<T>(L, x);
             if (l == D.lds_level) {
                 for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = xs[i];
                 __syncthreads();
@@ -1064,8 +939,6 @@ static void fill_bottom(gl_precond *pre, BottomDesc<T> &D)
         B.diag = dgn<T>(L);
         for (int c = 0; c <= L.ncolors && c <= kMaxColors && c < (int)L.coff.size(); ++c) B.coff[c] = L.coff[c];
         if (l + 1 < pre->nlev) {
-            B.pnnz = L.Pa.nnz;
-            B.rnnz = L.Ra.nnz;
             B.prp = L.Pa.rp.get();
             B.pci = L.Pa.ci.get();
             B.pv = vals<T>(L.Pa);
