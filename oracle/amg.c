@@ -9,16 +9,21 @@
  * (Vanek-Mandel-Brezina smoothed aggregation with deterministic distance-2
  * maximal-independent-set aggregation):
  *   strength      : every structural off-diagonal entry (theta = 0)
- *   priorities    : key_l(i) = (fmix32(i ^ (0x9E3779B9 * (l + 1))), i),
- *                   fmix32 = MurmurHash3 32-bit finaliser; larger key first
- *   roots         : scan by decreasing key; a node becomes a root iff no root
+ *   priorities    : the smaller index first (the greedy pass of standard
+ *                   aggregation; hashed priorities gave sparser, irregular roots
+ *                   and a V-cycle that weakens as the grid is refined)
+ *   roots         : scan by ascending index; a node becomes a root iff no root
  *                   lies within graph distance 2
  *   phase A       : a non-root neighbour of a root joins that root
  *   phase B       : every other node joins the aggregate of its phase-A-assigned
- *                   neighbour whose root has the largest key (phase-A state only)
+ *                   neighbour whose root has the smallest index (phase-A state only)
  *   numbering     : aggregates ordered by ascending root index
  *   tentative P   : T(i, a) = 1 / sqrt(|a|)   (near-null-space vector 1)
- *   smoothing     : P = T - omega D^-1 A T, omega = (4/3) / max_i sum_j |A_ij| / A_ii
+ *   smoothing     : P = T - omega D^-1 A T, omega = (4/3) / rho~, rho~ the estimate of
+ *                   rho(D^-1 A) after 20 power-iteration steps from the start
+ *                   s_i = (h1_i - 1/2) + i (h2_i - 1/2), h = fmix32(i ^ salt) / 2^32
+ *                   (salts 0x2545F491, 0x6C8E9CF5): y = D^-1 A x_{k-1},
+ *                   rho_k = ||y|| / ||x_{k-1}||, x_k = y / ||y||
  *   restriction   : R = P^H
  *   Galerkin      : A_{l+1} = R A P, entries i <= j computed, A(j,i) = conj A(i,j),
  *                   diagonal real
@@ -49,13 +54,12 @@ static uint32_t fmix32(uint32_t h)
     return h;
 }
 
-static uint64_t key_with_salt(int64_t i, uint32_t salt)
+/* aggregation priority: the smaller index first */
+static uint64_t mis_key(int64_t i, int l)
 {
-    uint32_t s = 0x9E3779B9u * salt;
-    return ((uint64_t)fmix32((uint32_t)i ^ s) << 32) | (uint64_t)(uint32_t)i;
+    (void)l;
+    return ~(uint64_t)i;
 }
-
-static uint64_t mis_key(int64_t i, int l) { return key_with_salt(i, (uint32_t)(l + 1)); }
 #define ORC_RECOLOUR_PASSES 2
 
 /* colour priority: largest degree first, then the hashed key (upper 22
@@ -228,21 +232,48 @@ static double diag_re(const orc_level *L, int64_t i)
     return 0.0;
 }
 
+/* rho(D^-1 A) estimated by ORC_RHO_STEPS power-iteration steps from a fixed
+ * counter-hash start vector (the estimate PyAMG's smoothed aggregation uses
+ * in place of a bound; the Gershgorin bound over-states rho and under-smooths P) */
+#define ORC_RHO_STEPS 20
+static double rho_estimate(const orc_level *L)
+{
+    const int64_t n = L->n;
+    cplx *x = malloc((size_t)n * sizeof(cplx)), *y = malloc((size_t)n * sizeof(cplx));
+    for (int64_t i = 0; i < n; ++i) {
+        const double a = (double)fmix32((uint32_t)i ^ 0x2545F491u) / 4294967296.0 - 0.5;
+        const double b = (double)fmix32((uint32_t)i ^ 0x6C8E9CF5u) / 4294967296.0 - 0.5;
+        x[i] = a + I * b;
+    }
+    double xn = 0.0;
+    for (int64_t i = 0; i < n; ++i) xn += creal(x[i]) * creal(x[i]) + cimag(x[i]) * cimag(x[i]);
+    xn = sqrt(xn);
+    double rho = 0.0;
+    for (int k = 0; k < ORC_RHO_STEPS; ++k) {
+        double yn = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            cplx s = 0.0;
+            for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p) s += L->v[p] * x[L->ci[p]];
+            y[i] = s / diag_re(L, i);
+            yn += creal(y[i]) * creal(y[i]) + cimag(y[i]) * cimag(y[i]);
+        }
+        yn = sqrt(yn);
+        rho = yn / xn;
+        for (int64_t i = 0; i < n; ++i) x[i] = y[i] / yn;
+        xn = 1.0;
+    }
+    free(x);
+    free(y);
+    return rho;
+}
+
 static void build_p(orc_level *L)
 {
     const int64_t n = L->n, nc = L->nc;
     int64_t *size = calloc((size_t)nc, sizeof(int64_t));
     for (int64_t i = 0; i < n; ++i) size[L->agg[i]]++;
 
-    /* omega from the Gershgorin bound on rho(D^-1 A) */
-    double rho = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        double s = 0.0;
-        for (int64_t p = L->rp[i]; p < L->rp[i + 1]; ++p) s += cabs(L->v[p]);
-        s /= diag_re(L, i);
-        if (s > rho) rho = s;
-    }
-    L->omega = (4.0 / 3.0) / rho;
+    L->omega = (4.0 / 3.0) / rho_estimate(L);
 
     /* pattern: row i has the aggregates of {i} and its neighbours */
     L->prp = malloc((size_t)(n + 1) * sizeof(int64_t));
