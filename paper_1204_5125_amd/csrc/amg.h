@@ -37,7 +37,7 @@ struct Level {
     DevBuf<int> agg, root, aggsize;
     Csr P, R;
     DevBuf<int> rsrc;           // R entry q = conj(P entry rsrc[q])
-    DevBuf<double> rho;         // max_i sum_j |A_ij| / A_ii (device scalar)
+    DevBuf<double> rho;         // estimate of rho(D^-1 A) (device scalar)
     DevBuf<int> rap_tp, rap_trip;  // products (p, q, s) of each entry of A_{l+1}, upper triangle
     // Copies used by the V-cycle: levels >= 1 renumbered so that every colour
     // is one contiguous row range (new index r' = position in cperm).
@@ -199,8 +199,9 @@ struct gl_precond {
     glk::DevBuf<double2> cinv64;   // its inverse, applied as a dense product
     glk::DevBuf<float2> cinv32;
     glk::DevBuf<int> status;       // device status word of the numeric setup
-    glk::DevBuf<double2> cyc_r;    // k > 1 cycles: level-0 residual
-    glk::DevBuf<double2> vin;      // gl_precond_apply: D r
+    glk::DevBuf<double2> cyc_r;    // k > 1 cycles: level-0 residual (and a setup scratch vector)
+    glk::DevBuf<double2> vin;      // gl_precond_apply: D r (and a setup scratch vector)
+    glk::DevBuf<double> pwn;       // setup: norms of the spectral-radius estimate
     glk::DevBuf<char> bdesc64, bdesc32;  // BottomDesc<double>, BottomDesc<float>
     int lds64 = 0, lds32 = 0;      // dynamic LDS bytes of the bottom kernel
 };

@@ -4,18 +4,20 @@
 // smoothing parameters open; this library fixes them as follows:
 //   strength     every structural off-diagonal entry (theta = 0), so the
 //                integer part of the hierarchy depends only on the grid
-//   priorities   key_l(i) = (fmix32(i ^ 0x9E3779B9 (l + 1)), i), fmix32 the
-//                MurmurHash3 finaliser
+//   priorities   the smaller index first (the greedy pass of standard
+//                aggregation: regular, densely packed roots; hashed priorities
+//                left a V-cycle that weakened as the grid was refined)
 //   roots        distance-2 maximal independent set, computed in parallel
-//                rounds: an undecided node becomes a root when its key is the
-//                largest among undecided nodes within distance 2 (this equals
-//                the serial greedy choice in decreasing key order)
+//                rounds: an undecided node becomes a root when it has the
+//                smallest index among undecided nodes within distance 2 (this
+//                equals the serial greedy choice in ascending index order)
 //   assignment   neighbours of a root join it; the remaining nodes join the
-//                aggregate of their assigned neighbour with the largest root key
+//                aggregate of their assigned neighbour with the smallest root
 //   numbering    aggregates in ascending root index
-//   prolongator  P = T - omega D^-1 A T, T = 1/sqrt|a|, omega = (4/3) / max_i
-//                sum_j |A_ij| / A_ii; R = P^H; A_{l+1} = R A P (upper triangle,
-//                mirrored; real diagonal)
+//   prolongator  P = T - omega D^-1 A T, T = 1/sqrt|a|, omega = (4/3) / rho~,
+//                rho~ the estimate of rho(D^-1 A) after 20 power-iteration
+//                steps from a counter-hash start; R = P^H; A_{l+1} = R A P
+//                (upper triangle, mirrored; real diagonal)
 //   colours      level 0: red-black parity of the grid; coarser: Jones-Plassmann
 //                rounds with keys of salt l + 101 (equal to greedy colouring in
 //                decreasing key order)
@@ -99,10 +101,10 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
     return h;
 }
 
-__device__ __forceinline__ unsigned long long keyof(int i, unsigned salt)
+// aggregation priority: larger for the smaller index (0 stays free for "none")
+__device__ __forceinline__ unsigned long long keyof(int i, unsigned)
 {
-    const uint32_t s = 0x9E3779B9u * salt;
-    return ((unsigned long long)fmix32((uint32_t)i ^ s) << 32) | (uint32_t)i;
+    return (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
 }
 
 // insert v into the ascending unique list buf[0..u); false on overflow
@@ -474,15 +476,64 @@ __global__ void k_diag(int n, const int *rp, const int *ci, const double2 *v, do
     diag[i] = (p < rp[i + 1] && ci[p] == i) ? v[p].x : 0.0;
 }
 
-// rho = max_i sum_j |A_ij| / A_ii (positive doubles order like their bit patterns)
-__global__ void k_rho(int n, const int *rp, const double2 *v, const double *diag, unsigned long long *rho)
+// Spectral radius of D^-1 A by power iteration from the counter-hash start
+// s_i = (h1_i - 1/2) + i (h2_i - 1/2), h = fmix32(i ^ salt) / 2^32; the
+// normalisation of each iterate is folded into the next step.
+constexpr int kRhoSteps = 20;
+
+__global__ void k_pw_start(int n, double2 *x, RedSlot slot)
 {
+    __shared__ double sm[kBlock / 64];
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) s += hypot(v[p].x, v[p].y);
-    s /= diag[i];
-    atomicMax(rho, (unsigned long long)__double_as_longlong(s));
+    double part = 0.0;
+    if (i < n) {
+        const double a = (double)fmix32((uint32_t)i ^ 0x2545F491u) / 4294967296.0 - 0.5;
+        const double b = (double)fmix32((uint32_t)i ^ 0x6C8E9CF5u) / 4294967296.0 - 0.5;
+        x[i] = make_double2(a, b);
+        part = a * a + b * b;
+    }
+    block_reduce_store(part, slot, sm, blockIdx.x);
+}
+
+// y = D^-1 A x / ||x|| (||x||^2 in *xn2), partial sums of |y|^2
+__global__ void k_pw_step(int n, const int *rp, const int *ci, const double2 *v, const double *diag,
+                          const double2 *x, const double *xn2, double2 *y, RedSlot slot)
+{
+    __shared__ double sm[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double part = 0.0;
+    if (i < n) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int p = rp[i]; p < rp[i + 1]; ++p) acc = cadd(acc, cmul(v[p], x[ci[p]]));
+        const double2 yi = cscale(acc, 1.0 / (diag[i] * sqrt(*xn2)));
+        y[i] = yi;
+        part = cabs2(yi);
+    }
+    block_reduce_store(part, slot, sm, blockIdx.x);
+}
+
+__global__ void k_pw_rho(const double *yn2, double *rho)
+{
+    if (threadIdx.x == 0) *rho = sqrt(*yn2);
+}
+
+static void rho_estimate(gl_precond *pre, Level &L, hipStream_t s)
+{
+    const gl_mesh *m = pre->mesh;
+    const int n = L.n, nb = blocks_for(n);
+    const RedSlot slot = red_slot(m, 0);
+    double2 *x = pre->vin.get(), *y = pre->cyc_r.get();
+    double *nrm = pre->pwn.get();
+    k_pw_start<<<nb, kBlock, 0, s>>>(n, x, slot);
+    launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm, nullptr, s);
+    for (int k = 1; k <= kRhoSteps; ++k) {
+        k_pw_step<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(), x,
+                                        nrm + ((k - 1) & 1), y, slot);
+        launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm + (k & 1), nullptr, s);
+        std::swap(x, y);
+    }
+    k_pw_rho<<<1, 64, 0, s>>>(nrm + (kRhoSteps & 1), L.rho.get());
+    GLK_CHECK_LAUNCH();
 }
 
 __global__ void k_p_values(int n, const int *arp, const int *aci, const double2 *av, const double *diag,
@@ -882,15 +933,18 @@ static int aggregate_level(gl_precond *pre, int l, hipStream_t s)
     DevBuf<unsigned long long> m1(n);
     k_fill_int<<<nb, kBlock, 0, s>>>(state.get(), n, 0);
     GLK_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
+    // index priorities decide roots in waves across the grid (many rounds):
+    // the host reads the undecided count every few rounds (rounds after the
+    // last decision change nothing)
     for (int round = 0;; ++round) {
-        if (round > n + 1) fail(GL_ERR_HIP, "aggregation did not terminate");
+        if (round > n + 8) fail(GL_ERR_HIP, "aggregation did not terminate");
         GLK_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
         k_mis_m1<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), salt, m1.get());
         k_mis_select<<<nb, kBlock, 0, s>>>(n, rp, ci, m1.get(), state.get(), salt);
         k_mis_near<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), near1.get());
         k_mis_remove<<<nb, kBlock, 0, s>>>(n, rp, ci, near1.get(), state.get(), cnt.get());
         GLK_CHECK_LAUNCH();
-        if (read_int(cnt.get(), s) == 0) break;
+        if ((round & 3) == 3 && read_int(cnt.get(), s) == 0) break;
     }
     k_agg_phase_a<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), salt, rootA.get());
     k_agg_phase_b<<<nb, kBlock, 0, s>>>(n, rp, ci, rootA.get(), salt, rootB.get(), err.get());
@@ -1004,6 +1058,7 @@ static void alloc_values(gl_precond *pre)
     const int n0 = pre->L[0].n;
     pre->cyc_r.alloc(n0);
     pre->vin.alloc(n0);
+    pre->pwn.alloc(2);
 }
 
 // copy of M with rows taken in the order rowperm and columns relabelled by colmap
@@ -1139,9 +1194,7 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
         if (l > 0) {
             k_diag<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get());
         }
-        GLK_HIP(hipMemsetAsync(L.rho.get(), 0, sizeof(double), s));
-        k_rho<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.v64.get(), L.diag64.get(),
-                                    reinterpret_cast<unsigned long long *>(L.rho.get()));
+        rho_estimate(pre, L, s);
         k_p_values<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(),
                                          L.agg.get(), L.aggsize.get(), L.rho.get(), L.P.rp.get(),
                                          L.P.ci.get(), L.P.v64.get());
