@@ -43,8 +43,8 @@ MAX_COARSE = 512
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "2385d263d94dccd0a9567ef204010c970ba56a58633f9ec7f3db02da78231382",
-           8: 5259216.2, 2: 35026585.7}
+TRAFFIC = {"csrc_sha256": "462e4bc99de224acb6ada1e852bc7e5149e0b22c39eea0c81653175b5dee9ffb",
+           8: 3485808.1, 2: 32195513.2}
 
 
 def csrc_fingerprint():
@@ -83,11 +83,12 @@ def timed(glnk, torch, mesh, psi0, psi, handle, precision, steps, relax=0.0):
     return time.perf_counter() - t0, infos
 
 
-def cpu_baseline():
-    """One Newton step (preconditioner setup + MINRES to 1e-10 + update) of the
-    same workload with the serial C oracle."""
-    import numpy as np
-
+def cpu_baseline(mean_iters):
+    """The serial C oracle on a bounded sample of the same workload: the first
+    Newton step in full, then the preconditioner setup and 60 MINRES
+    iterations of the second step's system.  Scaled to solves/s for a solve of
+    `mean_iters` iterations (the mean of the GPU run): setup + mean_iters x
+    the time per iteration."""
     import oracle
     from paper_1204_5125_amd import inputs
     m = oracle.Mesh(2, N_AXIS, SIDE, mu=MU)
@@ -95,11 +96,20 @@ def cpu_baseline():
     t0 = time.perf_counter()
     psi, info = oracle.newton(m, psi0, fixed_steps=1, krylov_rtol=RTOL, krylov_max_iter=4000,
                               max_coarse=MAX_COARSE)
-    dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one Newton step (AMG setup + MINRES to 1e-10, {info['krylov_iters'][0]} "
-                      f"iterations) on the same 1025x1025 grid from the same psi0: {dt:.1f} s, "
-                      f"serial C (one host core)"}
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    amg = oracle.Amg.for_state(m, psi, max_coarse=MAX_COARSE)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, ki, _ = oracle.minres(m, psi, -m.gl(psi), amg=amg, rtol=RTOL, max_iter=60)
+    t_iter = (time.perf_counter() - t0) / max(1, ki["iterations"])
+    per_solve = t_setup + mean_iters * t_iter
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"first Newton step in full ({info['krylov_iters'][0]} MINRES iterations, {t_first:.1f} s), "
+                      f"then the setup ({t_setup:.2f} s) and {ki['iterations']} MINRES iterations "
+                      f"({t_iter * 1e3:.0f} ms each) of the second step's system, on the same 1025x1025 grid "
+                      f"from the same psi0; scaled to a solve of {mean_iters:.0f} iterations (the GPU run's "
+                      f"mean), serial C (one host core)"}
 
 
 def one_pass():
@@ -319,6 +329,48 @@ def bench_continuation(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_meshind(args):
+    """Mesh independence of R_1 (Fig. 3 protocol): J(psi = 1) x = 1 from x = 0
+    to rtol 1e-11 with one V-cycle per MINRES step, uniform field mu = 1 along
+    z; 2D squares of side 10 with N = 33 ... 1025 nodes per axis, 3D cubes of
+    side 10/sqrt(3) (circumradius 5) with N = 9 ... 129.  Reports the MINRES
+    iterations per grid with the FP64 and the FP32 V-cycle."""
+    import torch
+
+    from paper_1204_5125_amd import glnk
+    torch.cuda.set_device(0)
+    rows = []
+    grids = [(2, n, 10.0) for n in (33, 65, 129, 257, 513, 1025)] + \
+            [(3, n, 10.0 / 3 ** 0.5) for n in (9, 17, 33, 65, 129)]
+    t0 = time.perf_counter()
+    for dim, n, side in grids:
+        mesh = glnk.Mesh(dim, (n,) * dim, (side,) * dim, mu=1.0)
+        ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
+        x = torch.empty_like(ones)
+        row = {"dim": dim, "N": n, "nodes": mesh.n}
+        for name, prec in (("fp64", glnk.GL_FP64), ("fp32", glnk.GL_FP32)):
+            pre = glnk.Precond(mesh, ones, precision=prec, max_coarse=MAX_COARSE)
+            rc, info = glnk.gl_jacobian_solve(mesh, ones, pre, ones, x, rtol=1e-11, max_iter=4000, poll_every=8,
+                                              raise_on_fail=False)
+            row[name] = {"iterations": info["iterations"], "res_true": info["res_true"], "status": rc}
+        row["levels"] = pre.info()["sizes"]
+        log(f"[bench] meshind {row}")
+        rows.append(row)
+    it2 = [r["fp64"]["iterations"] for r in rows if r["dim"] == 2]
+    it3 = [r["fp64"]["iterations"] for r in rows if r["dim"] == 3]
+    out = {
+        "metric": "MINRES iterations to 1e-11 with R_1 against grid size (mesh independence)",
+        "value": max(it2[1:]) / min(it2[1:]), "unit": "max/min iterations, 2D N >= 65",
+        "n_gpus": 1, "steps": len(rows), "warmup": 0, "ms_per_step": 1e3 * (time.perf_counter() - t0) / len(rows),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64 / f32 (V-cycle)",
+        "data": "synthetic: psi = 1, b = 1 on square and cube grids",
+        "config": {"workload": "2D N = 33..1025 (side 10), 3D N = 9..129 (side 10/sqrt 3), mu 1 along z, "
+                               "x0 = 0, rtol 1e-11, one V-cycle per step, max_coarse 512"},
+        "iterations_2d_fp64": it2, "iterations_3d_fp64": it3, "grids": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_cube(args):
     """Mixed precision in 3D: cube grid 129^3 (2,146,689 nodes), side 5, mu 0.6
     along (1,1,1)/sqrt(3), psi0 random phase (seed 0); 4 Newton steps with the
@@ -409,9 +461,11 @@ def bench_cube(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["jacobian", "batch", "continuation", "cube"], default="jacobian",
+    ap.add_argument("--workload", choices=["jacobian", "batch", "continuation", "cube", "meshind"],
+                    default="jacobian",
                     help="jacobian: the 1M-node Jacobian solves (headline); batch: batched continuation; "
-                         "continuation: learned vs secant predictor; cube: 3D 129^3 mixed precision")
+                         "continuation: learned vs secant predictor; cube: 3D 129^3 mixed precision; "
+                         "meshind: R_1 iteration counts against grid size")
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch-max-coarse", type=int, default=64)
     ap.add_argument("--tile-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "glnk_tiles.json"))
@@ -441,6 +495,9 @@ def main():
         return
     if args.workload == "cube":
         bench_cube(args)
+        return
+    if args.workload == "meshind":
+        bench_meshind(args)
         return
 
     import torch
@@ -502,6 +559,23 @@ def main():
                 "kernel_ms_per_step": ms}
     roof = profile(args.profile_kernel)
     roof_l0 = profile(2) if args.profile_kernel != 2 else roof
+    # the peak measured two ways: vendor 8 TB/s, and a plain copy of the size
+    # of one level-0 FP64 vector set (256 MiB in, 256 MiB out)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        c.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * COPY_BYTES * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    for r in (roof, roof_l0):
+        r["copy_peak_gbs"] = copy_gbs
+        r["frac_of_copy"] = r["achieved"] / copy_gbs
+    del a, c
 
     iters32 = info32[-1]["krylov_iters"]
     iters64 = info64[-1]["krylov_iters"]
@@ -538,7 +612,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle, one Newton step)")
-        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"] = cpu_baseline(sum(iters64) / len(iters64))
     print(json.dumps(out), flush=True)
 
 
