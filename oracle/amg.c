@@ -31,10 +31,9 @@
  *                   aggregation keeps more than 0.85 n_l nodes
  *   coarse solve  : dense Cholesky of the coarsest operator
  *   colours       : level 0 of a tensor grid: parity of the index sum; otherwise
- *                   greedy by decreasing colour priority (largest degree first,
- *                   then the hash with salt l + 101, then the index), smallest
- *                   colour unused by already coloured neighbours, followed by
- *                   two iterated-greedy passes (classes in reverse order)
+ *                   greedy in ascending index order, smallest colour unused by
+ *                   already coloured neighbours, followed by two iterated-greedy
+ *                   passes (classes in reverse order)
  *   SGS sweep     : colours 0 .. C-1, then C-2 .. 0
  *   V-cycle       : x = SGS(0, b); r = b - A x; x += P V(R r); x = SGS(x, b)
  */
@@ -62,13 +61,14 @@ static uint64_t mis_key(int64_t i, int l)
 }
 #define ORC_RECOLOUR_PASSES 2
 
-/* colour priority: largest degree first, then the hashed key (upper 22
- * bits), then the index: ((min(deg, 1023) << 54) | (fmix32 >> 10) << 32 | i */
+/* colour priority: the smaller index first (on the regular aggregates of a
+ * grid the index order colours the coarse graphs with about half the colours
+ * of a degree or hash order) */
 static uint64_t color_key(int64_t i, int64_t deg, int l)
 {
-    const uint32_t s = 0x9E3779B9u * (uint32_t)(l + 101);
-    const uint64_t d = (uint64_t)(deg < 1023 ? deg : 1023);
-    return (d << 54) | ((uint64_t)(fmix32((uint32_t)i ^ s) >> 10) << 32) | (uint64_t)(uint32_t)i;
+    (void)deg;
+    (void)l;
+    return ~(uint64_t)i;
 }
 
 typedef struct { uint64_t key; int64_t i; } keyed;

@@ -30,10 +30,9 @@ def keys(n):
     return [n - i for i in range(n)]
 
 
-def colour_keys(nb, salt):
-    """Largest degree first, then the upper 22 hash bits, then the index."""
-    s = (0x9E3779B9 * salt) & 0xFFFFFFFF
-    return [(min(len(nb[i]), 1023) << 54) | ((fmix32(i ^ s) >> 10) << 32) | i for i in range(len(nb))]
+def colour_keys(nb):
+    """Colour priority: the smaller index first."""
+    return [len(nb) - i for i in range(len(nb))]
 
 
 def iterated_greedy(nb, col, passes=2):
@@ -204,7 +203,7 @@ def test_colouring_proper_and_greedy(hierarchies):
             assert L["ncolors"] == L["color"].max() + 1
             if l > 0 and L["n"] <= 400:
                 nb = neighbours(L["A"])
-                jp = jones_plassmann(nb, colour_keys(nb, l + 101))
+                jp = jones_plassmann(nb, colour_keys(nb))
                 assert iterated_greedy(nb, jp) == list(L["color"])
                 assert L["ncolors"] <= max(jp) + 1
 
