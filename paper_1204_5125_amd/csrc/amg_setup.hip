@@ -19,8 +19,10 @@
 //                steps from a counter-hash start; R = P^H; A_{l+1} = R A P
 //                (upper triangle, mirrored; real diagonal)
 //   colours      level 0: red-black parity of the grid; coarser: Jones-Plassmann
-//                rounds with keys of salt l + 101 (equal to greedy colouring in
-//                decreasing key order)
+//                rounds with index priorities (equal to greedy colouring in
+//                ascending index order: 4 colours on the regular coarse grids
+//                where degree or hash orders needed 7-8), then two
+//                iterated-greedy passes
 //   coarsest     dense Cholesky
 #include <algorithm>
 #include <atomic>
@@ -386,11 +388,11 @@ __global__ void k_parity_colour(Geom g, int *col)
 // capped at 1023), then the upper 22 bits of the hash, then the index
 constexpr int kRecolourPasses = 2;  // iterated-greedy passes after the colouring rounds
 
-__device__ __forceinline__ unsigned long long colour_key(int i, const int *rp, unsigned salt)
+// colour priority: the smaller index first (the rounds then reproduce the
+// serial greedy colouring in index order)
+__device__ __forceinline__ unsigned long long colour_key(int i, const int *, unsigned)
 {
-    const unsigned long long d = (unsigned long long)min(rp[i + 1] - rp[i] - 1, 1023);
-    return (d << 54) | ((unsigned long long)(fmix32((uint32_t)i ^ (0x9E3779B9u * salt)) >> 10) << 32) |
-           (unsigned long long)(uint32_t)i;
+    return (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
 }
 
 __global__ void k_jp_ready(int n, const int *rp, const int *ci, const int *col, unsigned salt, int *ready)
@@ -871,14 +873,16 @@ static void colour_level(gl_precond *pre, int l, hipStream_t s)
         GLK_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
         k_fill_int<<<nb, kBlock, 0, s>>>(L.color.get(), n, -1);
         const unsigned salt = (unsigned)(l + 101);
+        // index priorities colour in waves (many rounds): the host reads the
+        // uncoloured count every few rounds (later rounds change nothing)
         for (int round = 0;; ++round) {
-            if (round > n + 1) fail(GL_ERR_HIP, "colouring did not terminate");
+            if (round > n + 8) fail(GL_ERR_HIP, "colouring did not terminate");
             GLK_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
             k_jp_ready<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.color.get(), salt, ready.get());
             k_jp_colour<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), ready.get(), L.color.get(),
                                               cnt.get(), err.get());
             GLK_CHECK_LAUNCH();
-            if (read_int(cnt.get(), s) == 0) break;
+            if ((round & 3) == 3 && read_int(cnt.get(), s) == 0) break;
         }
         check_err(err, s, "colouring");
         // class sizes and the number of colours
