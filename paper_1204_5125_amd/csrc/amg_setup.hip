@@ -104,7 +104,7 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h)
 }
 
 // aggregation priority: larger for the smaller index (0 stays free for "none")
-__device__ __forceinline__ unsigned long long keyof(int i, unsigned)
+__device__ __forceinline__ unsigned long long keyof(int i)
 {
     return (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
 }
@@ -200,27 +200,26 @@ __global__ void k_fill_int(int *a, int n, int val)
     if (i < n) a[i] = val;
 }
 
-__global__ void k_mis_m1(int n, const int *rp, const int *ci, const int *state, unsigned salt,
-                         unsigned long long *m1)
+__global__ void k_mis_m1(int n, const int *rp, const int *ci, const int *state, unsigned long long *m1)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     unsigned long long best = 0;
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
         const int j = ci[p];
-        if (state[j] == 0) best = max(best, keyof(j, salt) + 1ull);
+        if (state[j] == 0) best = max(best, keyof(j) + 1ull);
     }
     m1[i] = best;
 }
 
 __global__ void k_mis_select(int n, const int *rp, const int *ci, const unsigned long long *m1,
-                             int *state, unsigned salt)
+                             int *state)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n || state[i] != 0) return;
     unsigned long long best = 0;
     for (int p = rp[i]; p < rp[i + 1]; ++p) best = max(best, m1[ci[p]]);
-    if (best == keyof(i, salt) + 1ull) state[i] = 1;
+    if (best == keyof(i) + 1ull) state[i] = 1;
 }
 
 __global__ void k_mis_near(int n, const int *rp, const int *ci, const int *state, int *near1)
@@ -243,8 +242,7 @@ __global__ void k_mis_remove(int n, const int *rp, const int *ci, const int *nea
     else atomicAdd(remaining, 1);
 }
 
-__global__ void k_agg_phase_a(int n, const int *rp, const int *ci, const int *state, unsigned salt,
-                              int *rootA)
+__global__ void k_agg_phase_a(int n, const int *rp, const int *ci, const int *state, int *rootA)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -252,13 +250,12 @@ __global__ void k_agg_phase_a(int n, const int *rp, const int *ci, const int *st
     int best = -1;
     for (int p = rp[i]; p < rp[i + 1]; ++p) {
         const int j = ci[p];
-        if (j != i && state[j] == 1 && (best < 0 || keyof(j, salt) > keyof(best, salt))) best = j;
+        if (j != i && state[j] == 1 && (best < 0 || keyof(j) > keyof(best))) best = j;
     }
     rootA[i] = best;
 }
 
-__global__ void k_agg_phase_b(int n, const int *rp, const int *ci, const int *rootA, unsigned salt,
-                              int *root, int *err)
+__global__ void k_agg_phase_b(int n, const int *rp, const int *ci, const int *rootA, int *root, int *err)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
@@ -268,7 +265,7 @@ __global__ void k_agg_phase_b(int n, const int *rp, const int *ci, const int *ro
             const int j = ci[p];
             if (j == i) continue;
             const int r = rootA[j];
-            if (r >= 0 && (best < 0 || keyof(r, salt) > keyof(best, salt))) best = r;
+            if (r >= 0 && (best < 0 || keyof(r) > keyof(best))) best = r;
         }
         if (best < 0) atomicOr(err, 1);
     }
@@ -384,28 +381,26 @@ __global__ void k_parity_colour(Geom g, int *col)
     col[i] = (c[0] + c[1] + c[2]) & 1;
 }
 
-// colour priority: largest degree first (number of off-diagonal entries,
-// capped at 1023), then the upper 22 bits of the hash, then the index
 constexpr int kRecolourPasses = 2;  // iterated-greedy passes after the colouring rounds
 
 // colour priority: the smaller index first (the rounds then reproduce the
 // serial greedy colouring in index order)
-__device__ __forceinline__ unsigned long long colour_key(int i, const int *, unsigned)
+__device__ __forceinline__ unsigned long long colour_key(int i)
 {
     return (unsigned long long)(0xFFFFFFFFu - (uint32_t)i);
 }
 
-__global__ void k_jp_ready(int n, const int *rp, const int *ci, const int *col, unsigned salt, int *ready)
+__global__ void k_jp_ready(int n, const int *rp, const int *ci, const int *col, int *ready)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     int r = 0;
     if (col[i] < 0) {
         r = 1;
-        const unsigned long long k = colour_key(i, rp, salt);
+        const unsigned long long k = colour_key(i);
         for (int p = rp[i]; p < rp[i + 1]; ++p) {
             const int j = ci[p];
-            if (j != i && col[j] < 0 && colour_key(j, rp, salt) > k) { r = 0; break; }
+            if (j != i && col[j] < 0 && colour_key(j) > k) { r = 0; break; }
         }
     }
     ready[i] = r;
@@ -872,13 +867,12 @@ static void colour_level(gl_precond *pre, int l, hipStream_t s)
         DevBuf<int> ready(n), cnt(1), err(1);
         GLK_HIP(hipMemsetAsync(err.get(), 0, sizeof(int), s));
         k_fill_int<<<nb, kBlock, 0, s>>>(L.color.get(), n, -1);
-        const unsigned salt = (unsigned)(l + 101);
         // index priorities colour in waves (many rounds): the host reads the
         // uncoloured count every few rounds (later rounds change nothing)
         for (int round = 0;; ++round) {
             if (round > n + 8) fail(GL_ERR_HIP, "colouring did not terminate");
             GLK_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
-            k_jp_ready<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.color.get(), salt, ready.get());
+            k_jp_ready<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.color.get(), ready.get());
             k_jp_colour<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), ready.get(), L.color.get(),
                                               cnt.get(), err.get());
             GLK_CHECK_LAUNCH();
@@ -932,7 +926,6 @@ static int aggregate_level(gl_precond *pre, int l, hipStream_t s)
     Level &L = pre->L[l];
     const int n = L.n, nb = blocks_for(n);
     const int *rp = L.A.rp.get(), *ci = L.A.ci.get();
-    const unsigned salt = (unsigned)(l + 1);
     DevBuf<int> state(n), near1(n), cnt(1), err(1), rootA(n), rootB(n), flag(n), id(n);
     DevBuf<unsigned long long> m1(n);
     k_fill_int<<<nb, kBlock, 0, s>>>(state.get(), n, 0);
@@ -943,15 +936,15 @@ static int aggregate_level(gl_precond *pre, int l, hipStream_t s)
     for (int round = 0;; ++round) {
         if (round > n + 8) fail(GL_ERR_HIP, "aggregation did not terminate");
         GLK_HIP(hipMemsetAsync(cnt.get(), 0, sizeof(int), s));
-        k_mis_m1<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), salt, m1.get());
-        k_mis_select<<<nb, kBlock, 0, s>>>(n, rp, ci, m1.get(), state.get(), salt);
+        k_mis_m1<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), m1.get());
+        k_mis_select<<<nb, kBlock, 0, s>>>(n, rp, ci, m1.get(), state.get());
         k_mis_near<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), near1.get());
         k_mis_remove<<<nb, kBlock, 0, s>>>(n, rp, ci, near1.get(), state.get(), cnt.get());
         GLK_CHECK_LAUNCH();
         if ((round & 3) == 3 && read_int(cnt.get(), s) == 0) break;
     }
-    k_agg_phase_a<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), salt, rootA.get());
-    k_agg_phase_b<<<nb, kBlock, 0, s>>>(n, rp, ci, rootA.get(), salt, rootB.get(), err.get());
+    k_agg_phase_a<<<nb, kBlock, 0, s>>>(n, rp, ci, state.get(), rootA.get());
+    k_agg_phase_b<<<nb, kBlock, 0, s>>>(n, rp, ci, rootA.get(), rootB.get(), err.get());
     k_root_flags<<<nb, kBlock, 0, s>>>(n, state.get(), flag.get());
     GLK_CHECK_LAUNCH();
     check_err(err, s, "aggregation");

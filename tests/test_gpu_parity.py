@@ -331,3 +331,25 @@ def test_continuation_matches_oracle(glnk):
     ps = host(psg)
     chi = np.angle(np.vdot(ps, pso))
     assert np.abs(ps * np.exp(1j * chi) - pso).max() < 1e-8
+
+
+def test_mesh_independent_iteration_counts(glnk):
+    """Fig. 3 protocol in 2D (psi = 1, b = 1, x0 = 0, rtol 1e-11, R_1, mu = 1,
+    side 10): the MINRES count stays flat as the grid is refined, and on the
+    smallest grid it equals the oracle's within 1."""
+    counts = []
+    for n in (65, 129, 257):
+        mg = glnk.Mesh(2, (n, n), (10.0, 10.0), mu=1.0)
+        ones = torch.ones(mg.n, dtype=torch.complex128, device="cuda")
+        x = torch.empty_like(ones)
+        pre = glnk.Precond(mg, ones, max_coarse=64)
+        rc, info = glnk.gl_jacobian_solve(mg, ones, pre, ones, x, rtol=1e-11, max_iter=500)
+        assert rc == 0 and info["res_true"] < 1e-9
+        counts.append(info["iterations"])
+        if n == 65:
+            mo = oracle.Mesh(2, (n, n), (10.0, 10.0), mu=1.0)
+            o1 = np.ones(mo.n, dtype=np.complex128)
+            amg = oracle.Amg.for_state(mo, o1, max_coarse=64)
+            _, io, _ = oracle.minres(mo, o1, o1, amg=amg, rtol=1e-11, max_iter=500)
+            assert abs(io["iterations"] - info["iterations"]) <= 1
+    assert max(counts) <= 1.25 * min(counts), counts
