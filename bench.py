@@ -43,8 +43,8 @@ MAX_COARSE = 512
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "0a62ec00e8868634674518f2e06ef2e7076ea89ea998c1d24cd5153e2797a0e5",
-           8: 3495630.7, 2: 32232705.5}
+TRAFFIC = {"csrc_sha256": "85c7ac6a563a8fb51352d2ea227cbf5b1c3a96f34f7e69ce1036bf50251fb7c0",
+           8: 3495629.5, 2: 32236277.4}
 
 
 def csrc_fingerprint():
