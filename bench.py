@@ -178,7 +178,7 @@ def bench_batch(args):
     for N in sorted(set(int(v) for v in sizes)):
         i = int(np.nonzero(sizes == N)[0][0])
         tiles[N] = autotune.tune(meshes[i], psis[i], precision=glnk.GL_FP32, max_coarse=args.batch_max_coarse,
-                                 cache=args.tile_cache, log=log)
+                                 cache=args.tile_cache, log=log, batch=True)
         log(f"[bench] tiles for {N}^2: lane_shift {tiles[N][0]}, bottom_rows {tiles[N][1]}")
     for i, N in enumerate(sizes):
         batch.set_tiles(*tiles[int(N)], index=i)
@@ -515,7 +515,8 @@ def main():
     for name, prec in (("fp32", glnk.GL_FP32), ("fp64", glnk.GL_FP64)):
         tiles[name] = autotune.tune(mesh, psi0, precision=prec, max_coarse=MAX_COARSE, cache=args.tile_cache,
                                     log=log)
-        log(f"[bench] tiles {name}: lane_shift {tiles[name][0]}, bottom_rows {tiles[name][1]}")
+        log(f"[bench] tiles {name}: lane_shift {tiles[name][0]}, bottom_rows {tiles[name][1]}, "
+            f"dense_rows {tiles[name][2]}")
     log(f"[bench] grid {N_AXIS} n={mesh.n}; warm-up {args.warmup} step(s)")
     run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, 1)
     run_steps(glnk, torch, mesh, psi0, psi, h64, glnk.GL_FP64, 1)

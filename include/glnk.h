@@ -177,12 +177,21 @@ void gl_precond_destroy(gl_precond *pre);
  *     times 2^lane_shift, clamped to 1 .. 32; -2 .. 2, default 0;
  *   bottom_rows: levels >= 1 with at most this many rows (and at most 64
  *     colours), and all coarser ones, run inside one work-group; 0 = default
- *     512, at most 65536.
+ *     512, at most 65536;
+ *   dense_rows: the first level >= 1 with at most this many rows has the
+ *     V-cycle below it (its smoothing sweeps, residual, transfers and every
+ *     coarser level: a linear map of its right-hand side) formed as an
+ *     explicit matrix at every setup, in FP64 by the bottom kernel's
+ *     arithmetic applied to the unit vectors, and applied as one dense
+ *     product; the same operator up to rounding, one dispatch in place of a
+ *     few dozen latency-bound ones.  0 = off (default), else 1 .. 4096; the
+ *     matrix takes 24 n^2 bytes (FP64 and FP32 copies).
  * Chosen by the autotuner per grid shape; cached iteration graphs of the
  * handle are rebuilt on their next use. */
 typedef struct {
     int lane_shift;
     int bottom_rows;
+    int dense_rows;
 } gl_tiles;
 
 gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles);

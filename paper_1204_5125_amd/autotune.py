@@ -4,8 +4,10 @@ For one representative instance of each grid shape it times a fixed number
 of preconditioned MINRES iterations (graph-replayed, as in the solvers) for
 every candidate tile set, keeps the fastest, and caches the choice in a JSON
 file keyed by device name, grid shape, precision and coarse-size limit.  The
-candidates change only the order of rounding in row sums (lanes per row) and
-which levels run inside the one-work-group bottom kernel.
+candidates change only the order of rounding (lanes per row; a sub-cycle
+applied as an explicit matrix) and which levels run inside the
+one-work-group bottom kernel; candidates that give the same split of the
+hierarchy are timed once.
 """
 import json
 import os
@@ -13,7 +15,36 @@ import time
 
 from . import glnk
 
-CANDIDATES = [(ls, br) for ls in (-1, 0, 1) for br in (64, 512, 2048, 8192)]
+CANDIDATES = [(ls, br, dr) for ls in (-1, 0, 1) for br in (64, 512, 2048, 8192) for dr in (0, 4096)]
+# A batch runs many instances per dispatch: the launches an explicit
+# sub-cycle saves are shared there, its matrix reads are not, so batches
+# choose among the tile sets without one.
+BATCH_CANDIDATES = [c for c in CANDIDATES if c[2] == 0]
+MAX_COLOURS = 64   # colours per level the bottom kernel handles
+DEFAULT_BOTTOM = 512
+
+
+def split(info, tiles):
+    """(lane_shift, first level of the bottom kernel, level applied as a dense
+    operator) that a preconditioner with these level sizes and colour counts
+    (`Precond.info()`) derives from `tiles`, by the rule of
+    gl_precond_set_tiles."""
+    ls, br, dr = tiles
+    sizes, colours = info["sizes"], info["ncolors"]
+    last = len(sizes) - 1
+    tail = last
+    if dr > 0:
+        for lev in range(1, last):
+            if sizes[lev] <= dr:
+                if all(c <= MAX_COLOURS for c in colours[lev:last]):
+                    tail = lev
+                break
+    first = tail
+    for lev in range(tail - 1, 0, -1):
+        if sizes[lev] > (br or DEFAULT_BOTTOM) or colours[lev] > MAX_COLOURS:
+            break
+        first = lev
+    return ls, first, tail
 
 
 def _key(mesh, precision, max_coarse):
@@ -41,27 +72,36 @@ def time_tiles(mesh, psi, pre, tiles, iters=24, reps=3):
     return best
 
 
-def tune(mesh, psi, precision=glnk.GL_FP32, max_coarse=64, cache=None, candidates=CANDIDATES,
-         log=None):
-    """Best (lane_shift, bottom_rows) for this grid shape; read from / written
-    to the JSON file `cache` when given."""
-    key = _key(mesh, precision, max_coarse)
+def tune(mesh, psi, precision=glnk.GL_FP32, max_coarse=64, cache=None, candidates=None,
+         log=None, batch=False):
+    """Best (lane_shift, bottom_rows, dense_rows) for this grid shape, among
+    `candidates` (default: CANDIDATES, or BATCH_CANDIDATES for a batch); read
+    from / written to the JSON file `cache` when given."""
+    if candidates is None:
+        candidates = BATCH_CANDIDATES if batch else CANDIDATES
+    key = _key(mesh, precision, max_coarse) + ("|batch" if batch else "")
     table = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
             table = json.load(f)
-        if key in table:
+        if key in table and len(table[key]["tiles"]) == 3:
             return tuple(table[key]["tiles"])
     pre = glnk.Precond(mesh, psi, precision=precision, max_coarse=max_coarse)
-    times = {}
+    info = pre.info()
+    times, seen = {}, {}
     for t in candidates:
+        sp = split(info, t)
+        if sp in seen:  # same launches as an earlier candidate
+            times[t] = times[seen[sp]]
+            continue
+        seen[sp] = t
         times[t] = time_tiles(mesh, psi, pre, t)
         if log:
             log(f"[autotune] {key} tiles {t}: {times[t] * 1e6:.1f} us/iteration")
     best = min(times, key=times.get)
     if cache:
         table[key] = {"tiles": list(best), "us_per_iteration": times[best] * 1e6,
-                      "default_us_per_iteration": times.get((0, 512), float("nan")) * 1e6}
+                      "default_us_per_iteration": times.get((0, 512, 0), float("nan")) * 1e6}
         os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         with open(cache, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)

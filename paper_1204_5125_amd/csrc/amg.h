@@ -15,6 +15,8 @@ constexpr int kMaxDense = 2048;   // largest coarsest level handled by the dense
 constexpr int kMaxRow = 512;      // longest row handled by the setup kernels
 constexpr int kMaxColors = 64;    // colours per level handled by the bottom kernel
 constexpr int kBottomRows = 512;  // levels up to this size go to the bottom kernel
+constexpr int kMaxTail = 4096;    // largest level whose sub-cycle is formed as a dense matrix
+constexpr int kTailCols = 512;    // columns of that matrix formed per launch
 
 struct Csr {
     int n = 0, m = 0, nnz = 0;  // rows, columns, entries
@@ -80,9 +82,10 @@ struct BottomLevel {
 
 template <class T>
 struct BottomDesc {
-    int first, last;  // levels first .. last (last = coarsest)
+    int first, last;  // levels first .. last; last: the coarsest, or the level
+                      // whose sub-cycle is an explicit matrix
     int lds_level;    // level whose x lives in LDS (-1: none)
-    const C<T> *cinv; // inverse of the coarsest operator (dense, row-major)
+    const C<T> *cinv; // dense row-major operator of level `last`
     BottomLevel<T> L[kMaxLevels];
 };
 
@@ -192,8 +195,11 @@ struct gl_precond {
     gl_amg_opts opts{};
     int nlev = 0;
     int bottom = 0;                // first level handled by the bottom kernel
+    int tail = 0;                  // level whose sub-cycle is one dense product (the coarsest if none)
     int bottom_rows = glk::kBottomRows;  // tile choices (gl_precond_set_tiles)
     int lane_shift = 0;
+    int dense_rows = 0;
+    bool has_values = false;       // a numeric setup has run
     glk::Level L[glk::kMaxLevels];
     glk::DevBuf<double2> cfac;     // Cholesky factor of the coarsest operator
     glk::DevBuf<double2> cinv64;   // its inverse, applied as a dense product
@@ -203,6 +209,15 @@ struct gl_precond {
     glk::DevBuf<double2> vin;      // gl_precond_apply: D r (and a setup scratch vector)
     glk::DevBuf<double> pwn;       // setup: norms of the spectral-radius estimate
     glk::DevBuf<char> bdesc64, bdesc32;  // BottomDesc<double>, BottomDesc<float>
+    // explicit sub-cycle of level `tail` (when above the coarsest): row-major
+    // n_tail x n_tail in the V-cycle's row order, formed by k_tail_columns
+    // from a descriptor of levels tail .. coarsest, a column per work-group
+    glk::DevBuf<double2> tinv64;
+    glk::DevBuf<float2> tinv32;
+    glk::DevBuf<double2> tws;      // per-column vectors of that formation
+    glk::DevBuf<char> tdesc64;
+    size_t tws_col = 0;            // elements per column of tws
+    int tws_cols = 0;              // columns per launch
     int lds64 = 0, lds32 = 0;      // dynamic LDS bytes of the bottom kernel
 };
 
@@ -223,5 +238,6 @@ void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, 
 void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s);
 void scale_by_volume(const gl_mesh *m, const double2 *x, double2 *y, hipStream_t s);
 void bottom_descriptors(gl_precond *pre, hipStream_t s);
+void form_tail(gl_precond *pre, hipStream_t s);  // after a numeric setup
 uint64_t new_precond_uid();
 }  // namespace glk

@@ -1242,6 +1242,8 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
     k_chol_inverse<<<Lc.n, kBlock, 0, s>>>(Lc.n, pre->cfac.get(), pre->cinv64.get());
     k_to_f32c<<<blocks_for((int64_t)Lc.n * Lc.n), kBlock, 0, s>>>(Lc.n * Lc.n, pre->cinv64.get(), pre->cinv32.get());
     GLK_CHECK_LAUNCH();
+    pre->has_values = true;
+    form_tail(pre, s);
 }
 
 }  // namespace glk
@@ -1354,15 +1356,22 @@ gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles)
 {
     return guarded([&] {
         if (!pre || !tiles) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: NULL argument");
-        if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 || tiles->bottom_rows > 65536)
-            fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536");
+        if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 || tiles->bottom_rows > 65536 ||
+            tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail)
+            fail(GL_ERR_INVALID_ARGUMENT,
+                 "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..4096");
         const int rows = tiles->bottom_rows ? tiles->bottom_rows : kBottomRows;
-        if (rows == pre->bottom_rows && tiles->lane_shift == pre->lane_shift) return;
+        if (rows == pre->bottom_rows && tiles->lane_shift == pre->lane_shift && tiles->dense_rows == pre->dense_rows)
+            return;
         pre->bottom_rows = rows;
         pre->lane_shift = tiles->lane_shift;
+        pre->dense_rows = tiles->dense_rows;
         pre->uid = new_precond_uid();  // captured graphs of the old shape are stale
         hipStream_t s = pre->mesh->ws;
+        GLK_HIP(hipStreamSynchronize(s));  // no pending use of the buffers re-made here
         bottom_descriptors(pre, s);
+        form_tail(pre, s);
+        GLK_HIP(hipStreamSynchronize(s));
     });
 }
 
@@ -1372,6 +1381,7 @@ gl_status gl_precond_get_tiles(const gl_precond *pre, gl_tiles *tiles)
         if (!pre || !tiles) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_get_tiles: NULL argument");
         tiles->lane_shift = pre->lane_shift;
         tiles->bottom_rows = pre->bottom_rows;
+        tiles->dense_rows = pre->dense_rows;
     });
 }
 

@@ -488,7 +488,13 @@ struct Output {
     }
 };
 
-// x = M b for the dense row-major inverse of the coarsest operator (a wave per row)
+// x = M b for a dense row-major operator (the coarsest inverse or an explicit
+// sub-cycle), a wave per row.  Each lane issues kDenseUnroll loads before it
+// uses any (a row of a few thousand entries is otherwise one memory round
+// trip per 64 entries); the sum still runs over j = lane, lane + 64, ... in
+// that order.
+constexpr int kDenseUnroll = 8;
+
 template <class T>
 struct DenseApply {
     int n;
@@ -502,8 +508,21 @@ struct DenseApply {
         const int i = t / 64, lane = t % 64;
         const bool act = i < n;
         C<T> s = mk<T>(0, 0);
-        if (act)
-            for (int j = lane; j < n; j += 64) s = cadd(s, cmul(M[(size_t)i * n + j], b[j]));
+        if (act) {
+            const C<T> *row = M + (size_t)i * n;
+            for (int j0 = 0; j0 < n; j0 += 64 * kDenseUnroll) {
+                C<T> m[kDenseUnroll], v[kDenseUnroll];
+#pragma unroll
+                for (int u = 0; u < kDenseUnroll; ++u) {
+                    const int j = j0 + u * 64 + lane;
+                    m[u] = j < n ? row[j] : mk<T>(0, 0);
+                    v[u] = j < n ? b[j] : mk<T>(0, 0);
+                }
+#pragma unroll
+                for (int u = 0; u < kDenseUnroll; ++u)
+                    if (j0 + u * 64 + lane < n) s = cadd(s, cmul(m[u], v[u]));
+            }
+        }
         s = lanes_sum<T, 64>(s);
         if (act && lane == 0 && gate_go) x[i] = s;
     }
@@ -524,7 +543,7 @@ constexpr int kBottomLpr = 8;
 
 // one colour of a level, from its ELL block; x in LDS or global memory
 template <class T>
-__device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int colour, C<T> *x)
+__device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int colour, const C<T> *b, C<T> *x)
 {
     const int cnt = L.coff[colour + 1] - L.coff[colour];
     const int row0 = L.coff[colour];
@@ -544,7 +563,7 @@ __device__ __forceinline__ void bottom_rows_sgs(const BottomLevel<T> &L, int col
                 if (j != i) s = cadd(s, cmul(ev[(size_t)r * W + k], x[j]));
             }
         s = lanes_sum<T, kBottomLpr>(s);
-        if (act && lane == 0) x[i] = cscale(csub(L.b[i], s), (T)1 / L.diag[i]);
+        if (act && lane == 0) x[i] = cscale(csub(b[i], s), (T)1 / L.diag[i]);
     }
 }
 
@@ -588,11 +607,39 @@ __device__ __forceinline__ void bottom_dense(int n, const C<T> *M, const C<T> *b
 }
 
 template <class T>
-__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L, C<T> *x)
+__device__ __forceinline__ void bottom_sgs(const BottomLevel<T> &L, const C<T> *b, C<T> *x)
 {
     for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
-        bottom_rows_sgs<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, x);
+        bottom_rows_sgs<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, b, x);
         __syncthreads();
+    }
+}
+
+// The V-cycle over levels D.first .. D.last in one work-group: the same
+// steps as the multi-kernel levels, then the dense operator of level D.last.
+// vec(l, k) is level l's right-hand side (k = 0), iterate (1) or residual (2).
+template <class T, class V>
+__device__ __forceinline__ void bottom_cycle(const BottomDesc<T> &D, V vec)
+{
+    for (int l = D.first; l < D.last; ++l) {
+        const BottomLevel<T> &L = D.L[l];
+        C<T> *b = vec(l, 0), *x = vec(l, 1), *r = vec(l, 2);
+        for (int i = threadIdx.x; i < L.n; i += kBottomThreads) x[i] = mk<T>(0, 0);
+        __syncthreads();
+        bottom_sgs<T>(L, b, x);
+        bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, x, b, r);
+        __syncthreads();
+        bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, r, nullptr, vec(l + 1, 0));
+        __syncthreads();
+    }
+    bottom_dense<T>(D.L[D.last].n, D.cinv, vec(D.last, 0), vec(D.last, 1));
+    __syncthreads();
+    for (int l = D.last - 1; l >= D.first; --l) {
+        const BottomLevel<T> &L = D.L[l];
+        C<T> *x = vec(l, 1);
+        bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, vec(l + 1, 1), nullptr, x);
+        __syncthreads();
+        bottom_sgs<T>(L, vec(l, 0), x);
     }
 }
 
@@ -608,34 +655,46 @@ struct Bottom {
         extern __shared__ double2 glk_bottom_lds[];
         const BottomDesc<T> &D = *Dp;
         C<T> *xs = reinterpret_cast<C<T> *>(glk_bottom_lds);
-        for (int l = D.first; l < D.last; ++l) {
+        bottom_cycle<T>(D, [&](int l, int k) -> C<T> * {
             const BottomLevel<T> &L = D.L[l];
-            C<T> *x = l == D.lds_level ? xs : L.x;
-            for (int i = threadIdx.x; i < L.n; i += kBottomThreads) x[i] = mk<T>(0, 0);
-            __syncthreads();
-            bottom_sgs<T>(L, x);
-            bottom_rows_spmv<T, 2>(L.n, L.rp, L.ci, L.v, x, L.b, L.r);
-            __syncthreads();
-            bottom_rows_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, L.r, nullptr, D.L[l + 1].b);
+            return k == 0 ? L.b : k == 1 ? (l == D.lds_level ? xs : L.x) : L.r;
+        });
+        if (D.lds_level >= 0) {
+            const BottomLevel<T> &L = D.L[D.lds_level];
+            for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = xs[i];
             __syncthreads();
         }
-        // coarsest level: x = A^-1 b with the dense inverse
-        {
-            const BottomLevel<T> &Lc = D.L[D.last];
-            bottom_dense<T>(Lc.n, D.cinv, Lc.b, Lc.x);
-            __syncthreads();
-        }
-        for (int l = D.last - 1; l >= D.first; --l) {
-            const BottomLevel<T> &L = D.L[l];
-            C<T> *x = l == D.lds_level ? xs : L.x;
-            bottom_rows_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, D.L[l + 1].x, nullptr, x);
-            __syncthreads();
-            bottom_sgs<T>(L, x);
-            if (l == D.lds_level) {
-                for (int i = threadIdx.x; i < L.n; i += kBottomThreads) L.x[i] = xs[i];
-                __syncthreads();
-            }
-        }
+    }
+};
+
+// Columns col0 .. col0 + ncols - 1 of the explicit sub-cycle of level
+// D.first: work-group c runs bottom_cycle on the unit vector e_{col0 + c}
+// with vectors of its own (ws + c * ws_col: b, x, r of each level in turn)
+// and stores the result as that column of the row-major n x n matrix out.
+template <class T>
+struct TailColumns {
+    const BottomDesc<T> *Dp;
+    C<T> *ws;
+    size_t ws_col;
+    int col0, ncols;
+    C<T> *out;
+    __device__ void operator()(int bx, int) const
+    {
+        if (bx >= ncols) return;
+        const BottomDesc<T> &D = *Dp;
+        const int n = D.L[D.first].n, j = col0 + bx;
+        C<T> *base = ws + (size_t)bx * ws_col;
+        auto vec = [&](int l, int k) -> C<T> * {
+            size_t off = 0;
+            for (int q = D.first; q < l; ++q) off += 3 * (size_t)D.L[q].n;
+            return base + off + (size_t)k * D.L[l].n;
+        };
+        C<T> *b = vec(D.first, 0);
+        for (int i = threadIdx.x; i < n; i += kBottomThreads) b[i] = mk<T>(i == j ? 1 : 0, 0);
+        __syncthreads();
+        bottom_cycle<T>(D, vec);
+        const C<T> *x = vec(D.first, 1);
+        for (int i = threadIdx.x; i < n; i += kBottomThreads) out[(size_t)i * n + j] = x[i];
     }
 };
 
@@ -660,9 +719,16 @@ template <class T> static const T *dgn(const Level &L);
 template <> const double *dgn<double>(const Level &L) { return L.dg64.get(); }
 template <> const float *dgn<float>(const Level &L) { return L.dg32.get(); }
 
+// dense operator of level pre->tail: the coarsest inverse, or the explicit sub-cycle
 template <class T> static const C<T> *cinv(const gl_precond *p);
-template <> const double2 *cinv<double>(const gl_precond *p) { return p->cinv64.get(); }
-template <> const float2 *cinv<float>(const gl_precond *p) { return p->cinv32.get(); }
+template <> const double2 *cinv<double>(const gl_precond *p)
+{
+    return p->tail < p->nlev - 1 ? p->tinv64.get() : p->cinv64.get();
+}
+template <> const float2 *cinv<float>(const gl_precond *p)
+{
+    return p->tail < p->nlev - 1 ? p->tinv32.get() : p->cinv32.get();
+}
 template <class T> static int bottom_lds(const gl_precond *p);
 template <> int bottom_lds<double>(const gl_precond *p) { return p->lds64; }
 template <> int bottom_lds<float>(const gl_precond *p) { return p->lds32; }
@@ -842,12 +908,13 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
         csr_residual<TC>(Lv, sh, gate, L);
         csr_spmv<TC>(Lv.Ra, vec_r<TC>(Lv), vec_b<TC>(pre->L[l + 1]), false, sh, gate, L);
     }
-    // small levels and the coarsest solve in one work-group, or the coarsest
-    // solve alone as a dense product over many work-groups
-    if (pre->bottom < nl - 1) {
+    // small levels and the dense operator of level `tail` (the coarsest
+    // inverse or the explicit sub-cycle) in one work-group, or that dense
+    // product alone over many work-groups
+    if (pre->bottom < pre->tail) {
         L.run<Bottom<TC>, kBottomThreads>(1, Bottom<TC>{bdesc<TC>(pre), gate}, bottom_lds<TC>(pre));
     } else {
-        Level &Lc = pre->L[nl - 1];
+        Level &Lc = pre->L[pre->tail];
         L.run(blocks_for((int64_t)Lc.n * 64),
               DenseApply<TC>{Lc.n, cinv<TC>(pre), vec_b<TC>(Lc), vec_x<TC>(Lc), gate});
     }
@@ -925,7 +992,7 @@ static void fill_bottom(gl_precond *pre, BottomDesc<T> &D)
 {
     std::memset(&D, 0, sizeof(D));
     D.first = pre->bottom;
-    D.last = pre->nlev - 1;
+    D.last = pre->tail;
     D.cinv = cinv<T>(pre);
     for (int l = 1; l < pre->nlev; ++l) {
         Level &L = pre->L[l];
@@ -969,16 +1036,60 @@ static void fill_bottom(gl_precond *pre, BottomDesc<T> &D)
 
 void bottom_descriptors(gl_precond *pre, hipStream_t s)
 {
+    const int last = pre->nlev - 1;
+    // level with an explicit sub-cycle: the first l >= 1 with at most
+    // dense_rows rows and a bottom-kernel colouring (the coarsest if none)
+    int tail = last;
+    if (pre->dense_rows > 0)
+        for (int l = 1; l < last; ++l) {
+            const Level &L = pre->L[l];
+            if (L.n <= pre->dense_rows) {
+                bool fits = true;
+                for (int q = l; q < last; ++q) fits = fits && pre->L[q].ncolors <= kMaxColors;
+                if (fits) tail = l;
+                break;
+            }
+        }
+    pre->tail = tail;
     // first level of the bottom kernel: the smallest l >= 1 from which every
-    // level fits (size and colour count); a single-level hierarchy is just the
-    // dense solve on level 0
-    int first = pre->nlev - 1;
-    for (int l = pre->nlev - 2; l >= 1; --l) {
+    // level above the tail fits (size and colour count); a single-level
+    // hierarchy is just the dense solve on level 0
+    int first = tail;
+    for (int l = tail - 1; l >= 1; --l) {
         const Level &L = pre->L[l];
         if (L.n > pre->bottom_rows || L.ncolors > kMaxColors) break;
         first = l;
     }
     pre->bottom = first;
+    if (tail < last) {
+        const int nt = pre->L[tail].n;
+        pre->tinv64.alloc((size_t)nt * nt);
+        pre->tinv32.alloc((size_t)nt * nt);
+        size_t col = 0;
+        for (int l = tail; l <= last; ++l) col += 3 * (size_t)pre->L[l].n;
+        pre->tws_col = (col + 31) / 32 * 32;
+        pre->tws_cols = std::min(nt, kTailCols);
+        pre->tws.alloc(pre->tws_col * pre->tws_cols);
+        // formation: levels tail .. coarsest with the coarsest inverse
+        BottomDesc<double> dt;
+        const int keep = pre->tail;
+        pre->tail = last;
+        const int keep_b = pre->bottom;
+        pre->bottom = tail;
+        fill_bottom<double>(pre, dt);
+        pre->tail = keep;
+        pre->bottom = keep_b;
+        dt.lds_level = -1;
+        pre->tdesc64.alloc(sizeof(dt));
+        GLK_HIP(hipMemcpyAsync(pre->tdesc64.get(), &dt, sizeof(dt), hipMemcpyHostToDevice, s));
+    } else {
+        pre->tinv64.release();
+        pre->tinv32.release();
+        pre->tws.release();
+        pre->tdesc64.release();
+        pre->tws_col = 0;
+        pre->tws_cols = 0;
+    }
     BottomDesc<double> d64;
     BottomDesc<float> d32;
     fill_bottom<double>(pre, d64);
@@ -990,6 +1101,23 @@ void bottom_descriptors(gl_precond *pre, hipStream_t s)
     GLK_HIP(hipMemcpyAsync(pre->bdesc64.get(), &d64, sizeof(d64), hipMemcpyHostToDevice, s));
     GLK_HIP(hipMemcpyAsync(pre->bdesc32.get(), &d32, sizeof(d32), hipMemcpyHostToDevice, s));
     GLK_HIP(hipStreamSynchronize(s));
+}
+
+// The explicit sub-cycle of level `tail` from the current values: FP64
+// columns, kTailCols work-groups per launch, then the FP32 copy.
+void form_tail(gl_precond *pre, hipStream_t s)
+{
+    if (!pre->has_values || pre->tail >= pre->nlev - 1) return;
+    const int nt = pre->L[pre->tail].n;
+    const auto *D = reinterpret_cast<const BottomDesc<double> *>(pre->tdesc64.get());
+    const Launch L{s};
+    for (int c0 = 0; c0 < nt; c0 += pre->tws_cols) {
+        const int nc = std::min(pre->tws_cols, nt - c0);
+        L.run<TailColumns<double>, kBottomThreads>(
+            nc, TailColumns<double>{D, pre->tws.get(), pre->tws_col, c0, nc, pre->tinv64.get()});
+    }
+    const int64_t nn = (int64_t)nt * nt;
+    L.run(blocks_for(nn), Narrow<float>{(int)nn, pre->tinv64.get(), pre->tinv32.get(), nullptr});
 }
 
 }  // namespace glk

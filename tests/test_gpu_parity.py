@@ -282,13 +282,29 @@ def test_vcycle_and_solve_deeper_hierarchy(glnk, max_coarse):
     pre.update(dev(psi), precision=glnk.GL_FP32)
     pre.apply(dev(r), z)
     assert relerr(host(z), ref) < 1e-5
-    # every split between multi-kernel levels and the single-work-group bottom
-    for rows in (512, 4096, 65536):
-        glnk.gl_precond_set_tiles(pre, 0, rows)
-        for prec, tol in ((glnk.GL_FP64, 1e-11), (glnk.GL_FP32, 1e-5), (glnk.GL_MIXED, 1e-5)):
-            pre.update(dev(psi), precision=prec)
-            pre.apply(dev(r), z)
-            assert relerr(host(z), ref) < tol, (rows, prec)
+    # every split between multi-kernel levels, the single-work-group bottom
+    # and a sub-cycle applied as an explicit matrix (none, the level above the
+    # coarsest, or every level >= 1)
+    sizes = pre.info()["sizes"]
+    for dense in (0, 512, 4096):
+        for rows in (512, 4096, 65536):
+            glnk.gl_precond_set_tiles(pre, 0, rows, dense)
+            assert glnk.gl_precond_get_tiles(pre) == {"lane_shift": 0, "bottom_rows": rows, "dense_rows": dense}
+            for prec, tol in ((glnk.GL_FP64, 1e-11), (glnk.GL_FP32, 1e-5), (glnk.GL_MIXED, 1e-5)):
+                pre.update(dev(psi), precision=prec)
+                pre.apply(dev(r), z)
+                assert relerr(host(z), ref) < tol, (dense, rows, prec, sizes)
+    with pytest.raises(glnk.GlnkError):
+        glnk.gl_precond_set_tiles(pre, 0, 0, 4097)
+    # the explicit sub-cycle with the values of a later setup (graphs keep
+    # its address), then MINRES through it against the oracle
+    glnk.gl_precond_set_tiles(pre, 0, 0, 4096)
+    pre.update(dev(psi), precision=glnk.GL_FP64)
+    xo, io, _ = oracle.minres(mo, psi, r, amg=amg, rtol=1e-10, max_iter=3000)
+    rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(r), z, rtol=1e-10, max_iter=3000)
+    assert io["converged"] and ig["converged"]
+    assert abs(ig["iterations"] - io["iterations"]) <= 1
+    assert relerr(host(z), xo) < 1e-8
     glnk.gl_precond_set_tiles(pre, 0, 0)
     pre.update(dev(psi), precision=glnk.GL_FP64)
     xo, io, _ = oracle.minres(mo, psi, r, amg=amg, rtol=1e-10, max_iter=3000)

@@ -19,9 +19,33 @@ class FakeMesh:
     dim, shape, n = 2, (65, 65), 65 * 65
 
 
+class FakePrecond:
+    INFO = {"nlev": 3, "sizes": [4225, 700, 90], "nnz": [0, 0, 0], "ncolors": [2, 4, 5]}
+
+    def __init__(self, *a, **k):
+        pass
+
+    def info(self):
+        return self.INFO
+
+
+def test_tile_split_rule():
+    """The (lane_shift, bottom level, dense level) the library derives from a
+    tile set, for the level sizes of the 1025 x 1025 hierarchy."""
+    info = {"sizes": [1050625, 175446, 19580, 2181, 252], "ncolors": [2, 4, 4, 6, 5]}
+    assert autotune.split(info, (1, 2048, 0)) == (1, 4, 4)
+    assert autotune.split(info, (1, 2048, 4096)) == (1, 3, 3)
+    assert autotune.split(info, (0, 8192, 0)) == (0, 3, 4)
+    assert autotune.split(info, (0, 65536, 4096)) == (0, 2, 3)
+    assert autotune.split(info, (0, 0, 100)) == (0, 4, 4)      # no level above the coarsest small enough
+    assert autotune.split(info, (0, 0, 200000)) == (0, 1, 1)
+    many = dict(info, ncolors=[2, 4, 4, 70, 5])                  # too many colours for the bottom kernel
+    assert autotune.split(many, (0, 8192, 4096)) == (0, 4, 4)
+
+
 def test_autotune_picks_fastest_and_caches(tmp_path, monkeypatch):
     times = {t: 1.0 + 0.1 * k for k, t in enumerate(autotune.CANDIDATES)}
-    best = (1, 2048)
+    best = (1, 2048, 0)
     times[best] = 0.5
     calls = []
 
@@ -31,10 +55,14 @@ def test_autotune_picks_fastest_and_caches(tmp_path, monkeypatch):
 
     monkeypatch.setattr(autotune, "time_tiles", fake_time)
     monkeypatch.setattr(autotune, "_key", lambda mesh, p, mc: f"dev|{mesh.shape}|{p}|{mc}")
-    monkeypatch.setattr(glnk, "Precond", lambda *a, **k: object())
+    monkeypatch.setattr(glnk, "Precond", FakePrecond)
     cache = str(tmp_path / "tiles.json")
     assert autotune.tune(FakeMesh(), None, cache=cache) == best
-    assert sorted(calls) == sorted(autotune.CANDIDATES)
+    # each distinct split timed once, by its first candidate
+    splits = [autotune.split(FakePrecond.INFO, t) for t in calls]
+    assert len(set(splits)) == len(splits)
+    assert set(splits) == {autotune.split(FakePrecond.INFO, t) for t in autotune.CANDIDATES}
+    assert len(calls) < len(autotune.CANDIDATES)
     table = json.load(open(cache))
     (entry,) = table.values()
     assert tuple(entry["tiles"]) == best
