@@ -205,6 +205,7 @@ struct gl_precond {
     glk::DevBuf<double2> cinv64;   // its inverse, applied as a dense product
     glk::DevBuf<float2> cinv32;
     glk::DevBuf<int> status;       // device status word of the numeric setup
+    glk::DevBuf<double> cdmax;     // largest diagonal entry of the coarsest operator
     glk::DevBuf<double2> cyc_r;    // k > 1 cycles: level-0 residual (and a setup scratch vector)
     glk::DevBuf<double2> vin;      // gl_precond_apply: D r (and a setup scratch vector)
     glk::DevBuf<double> pwn;       // setup: norms of the spectral-radius estimate

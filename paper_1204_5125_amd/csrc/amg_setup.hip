@@ -654,17 +654,20 @@ __global__ void k_dense_from_csr(int n, const int *rp, const int *ci, const doub
     for (int p = rp[i]; p < rp[i + 1]; ++p) M[(size_t)i * n + ci[p]] = v[p];
 }
 
-// In-place Cholesky M = L L^H (row-major, one work-group); upper part zeroed.
-// status = 1 if a pivot is not positive relative to the largest diagonal.
-// Cholesky factor of the Hermitian coarsest operator, in place (lower
-// triangle, row-major), left-looking one column at a time; the pivot's sum
-// runs over the work-group and each row's dot product over a wave (status 1:
-// not positive definite relative to the largest diagonal entry).
-__global__ __launch_bounds__(1024) void k_cholesky(int n, double2 *M, int *status)
+// Cholesky factor M = L L^H of the Hermitian coarsest operator, in place
+// (row-major, lower triangle; the upper part zeroed at the end), blocked
+// right-looking: a panel of pw columns is factored in LDS by one work-group
+// (k_chol_panel), then every work-group updates its share of the trailing
+// lower triangle with that panel (k_chol_update).  status = 1 when a pivot is
+// not positive relative to the largest diagonal entry of M (k_chol_init);
+// every later kernel returns at once then.
+constexpr int kCholLds = (65536 - 1024) / sizeof(double2);  // panel entries held in LDS
+
+int chol_panel_width(int n) { return std::max(1, std::min(32, kCholLds / std::max(n, 1))); }
+
+__global__ __launch_bounds__(1024) void k_chol_init(int n, const double2 *M, double *dmax, int *status)
 {
     __shared__ double sm[1024 / 64];
-    __shared__ double dmax, ljj;
-    __shared__ int bad;
     double m = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(M[(size_t)i * n + i].x));
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
@@ -673,58 +676,90 @@ __global__ __launch_bounds__(1024) void k_cholesky(int n, double2 *M, int *statu
     if (threadIdx.x == 0) {
         double r = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sm[w]);
-        dmax = r;
-        bad = 0;
+        *dmax = r;
+        *status = 0;
     }
+}
+
+// columns p0 .. p0 + pw - 1, rows p0 .. n - 1 (already updated by the
+// earlier panels): P[r * pw + c] = M[p0 + r][p0 + c]
+__global__ __launch_bounds__(1024) void k_chol_panel(int n, int p0, int pw, double2 *M, const double *dmaxp,
+                                                     int *status)
+{
+    __shared__ double2 P[kCholLds];
+    __shared__ double piv;
+    __shared__ int bad;
+    if (*status) return;
+    const int rows = n - p0;
+    const double dmax = *dmaxp;
+    for (int t = threadIdx.x; t < rows * pw; t += blockDim.x)
+        P[t] = M[(size_t)(p0 + t / pw) * n + p0 + t % pw];
+    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        const double2 *Lj = M + (size_t)j * n;
-        double p = 0.0;
-        for (int k = threadIdx.x; k < j; k += blockDim.x) p += cabs2(Lj[k]);
-        p = block_sum(p, sm);
+    for (int c = 0; c < pw; ++c) {
         if (threadIdx.x == 0) {
-            const double d = Lj[j].x - p;
+            const double d = P[c * pw + c].x;
             if (!(d > 1e-12 * dmax)) bad = 1;
             else {
-                ljj = sqrt(d);
-                M[(size_t)j * n + j] = make_double2(ljj, 0.0);
+                piv = sqrt(d);
+                P[c * pw + c] = make_double2(piv, 0.0);
             }
         }
         __syncthreads();
         if (bad) break;
-        // rows below the pivot: a wave per group of four rows, the dot
-        // products over k split across the lanes
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-        for (int i0 = j + 1 + 4 * wave; i0 < n; i0 += 4 * nw) {
-            double2 acc[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = make_double2(0.0, 0.0);
-            for (int k = lane; k < j; k += 64) {
-                const double2 ljk = cconj(Lj[k]);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (i0 + u < n) acc[u] = cadd(acc[u], cmul(M[(size_t)(i0 + u) * n + k], ljk));
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                acc[u].x = wave_sum(acc[u].x);
-                acc[u].y = wave_sum(acc[u].y);
-            }
-            if (lane == 0)
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (i0 + u < n) {
-                        double2 &mij = M[(size_t)(i0 + u) * n + j];
-                        mij = cscale(csub(mij, acc[u]), 1.0 / ljj);
-                    }
+        const double inv = 1.0 / piv;
+        for (int r = c + 1 + threadIdx.x; r < rows; r += blockDim.x) P[r * pw + c] = cscale(P[r * pw + c], inv);
+        __syncthreads();
+        // the panel's remaining columns c' > c, rows r >= c'
+        const int w = pw - c - 1;
+        for (int t = threadIdx.x; t < (rows - c - 1) * w; t += blockDim.x) {
+            const int r = c + 1 + t / w, q = c + 1 + t % w;
+            if (r >= q) P[r * pw + q] = csub(P[r * pw + q], cmul(P[r * pw + c], cconj(P[q * pw + c])));
         }
         __syncthreads();
     }
-    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
-        const int i = t / n, j = t % n;
-        if (j > i) M[t] = make_double2(0.0, 0.0);
+    if (bad) {
+        if (threadIdx.x == 0) *status = 1;
+        return;
     }
-    if (threadIdx.x == 0) *status = bad;
+    for (int t = threadIdx.x; t < rows * pw; t += blockDim.x) {
+        const int r = t / pw, c = t % pw;
+        if (r >= c) M[(size_t)(p0 + r) * n + p0 + c] = P[t];
+    }
+}
+
+// M[i][k] -= sum_c L[i][p0 + c] conj(L[k][p0 + c]) for p0 + pw <= k <= i < n
+__global__ void k_chol_update(int n, int p0, int pw, double2 *M, const int *status)
+{
+    if (*status) return;
+    const int b = p0 + pw;
+    const int i = b + blockIdx.y * 16 + threadIdx.y, k = b + blockIdx.x * 16 + threadIdx.x;
+    if (i >= n || k > i) return;
+    const double2 *li = M + (size_t)i * n + p0, *lk = M + (size_t)k * n + p0;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int c = 0; c < pw; ++c) acc = cadd(acc, cmul(li[c], cconj(lk[c])));
+    M[(size_t)i * n + k] = csub(M[(size_t)i * n + k], acc);
+}
+
+__global__ void k_chol_zero_upper(int n, double2 *M)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)n * n) return;
+    if (t % n > t / n) M[t] = make_double2(0.0, 0.0);
+}
+
+void cholesky(int n, double2 *M, double *dmax, int *status, hipStream_t s)
+{
+    k_chol_init<<<1, 1024, 0, s>>>(n, M, dmax, status);
+    const int pb = chol_panel_width(n);
+    for (int p0 = 0; p0 < n; p0 += pb) {
+        const int pw = std::min(pb, n - p0);
+        k_chol_panel<<<1, 1024, 0, s>>>(n, p0, pw, M, dmax, status);
+        const int m = n - p0 - pw;
+        if (m > 0) k_chol_update<<<dim3((m + 15) / 16, (m + 15) / 16), dim3(16, 16), 0, s>>>(n, p0, pw, M, status);
+    }
+    k_chol_zero_upper<<<blocks_for((int64_t)n * n), kBlock, 0, s>>>(n, M);
+    GLK_CHECK_LAUNCH();
 }
 
 // Column j of (L L^H)^-1 (one work-group per column), stored row-major.
@@ -1052,6 +1087,7 @@ static void alloc_values(gl_precond *pre)
     pre->cinv64.alloc((size_t)nl * nl);
     pre->cinv32.alloc((size_t)nl * nl);
     pre->status.alloc(1);
+    pre->cdmax.alloc(1);
     const int n0 = pre->L[0].n;
     pre->cyc_r.alloc(n0);
     pre->vin.alloc(n0);
@@ -1235,8 +1271,7 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
     const Csr &Mc = last > 0 ? Lc.Aa : Lc.A;
     k_dense_from_csr<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Mc.rp.get(), Mc.ci.get(), Mc.v64.get(),
                                                          pre->cfac.get());
-    k_cholesky<<<1, 1024, 0, s>>>(Lc.n, pre->cfac.get(), pre->status.get());
-    GLK_CHECK_LAUNCH();
+    cholesky(Lc.n, pre->cfac.get(), pre->cdmax.get(), pre->status.get(), s);
     if (read_int(pre->status.get(), s))
         fail(GL_ERR_SINGULAR, "gl_precond_setup: coarsest operator is not positive definite");
     k_chol_inverse<<<Lc.n, kBlock, 0, s>>>(Lc.n, pre->cfac.get(), pre->cinv64.get());
