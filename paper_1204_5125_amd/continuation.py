@@ -14,8 +14,12 @@ def continuation_path(mesh, psi0, mus, tol=1e-10, krylov_rtol=1e-10, krylov_max_
     values mus.  Each step predicts psi at the next mu -- secant
     psi_m + r (psi_m - e^{i chi} psi_{m-1}) with r the ratio of the steps, or
     `predictor(psi_m, psi_prev, mu_prev, mu_m, mu_next)` when given (a tensor,
-    or None for the secant; psi_prev and mu_prev are None at the first step) -- and corrects it by Newton.  A failed Newton halves the
-    step (at most max_halvings times; the halved points are extra steps).
+    or None for the secant; psi_prev and mu_prev are None at the first step) -- and corrects it by Newton.
+    When Newton fails from the predictor's start, the same step is solved
+    once more from the secant start (its fallback; the record's predictor
+    reads "custom->secant" and failed_newton_steps / failed_krylov_iters hold
+    the cost of the failed attempt).  A failed Newton halves the step (at
+    most max_halvings times; the halved points are extra steps).
     Returns (records, psi, states): states lists (mu, tensor) of every
     converged point when keep is set."""
     import torch
@@ -34,26 +38,39 @@ def continuation_path(mesh, psi0, mus, tol=1e-10, krylov_rtol=1e-10, krylov_max_
     for target_mu in mus[1:]:
         while mu < target_mu - 1e-12:
             h = target_mu - mu
+            failed_steps, failed_krylov = 0, 0
             for attempt in range(max_halvings + 1):
                 mu_next = mu + h
                 mesh.set_field(mu_next)
-                used = "constant"
+
+                def plain():
+                    if prev is not None:
+                        glnk.gl_secant_predict(mesh, psi, prev, h / dmu_prev, pred)
+                        return "secant"
+                    pred.copy_(psi)
+                    return "constant"
+
                 mu_prev = mu - dmu_prev if prev is not None else None
                 custom = predictor(psi, prev, mu_prev, mu, mu_next) if predictor is not None else None
                 if custom is not None:
                     pred.copy_(custom)
                     used = "custom"
-                elif prev is not None:
-                    glnk.gl_secant_predict(mesh, psi, prev, h / dmu_prev, pred)
-                    used = "secant"
                 else:
-                    pred.copy_(psi)
+                    used = plain()
                 rc, info = glnk.gl_newton_solve(mesh, pred, **opts)
+                if rc != 0 and used == "custom":
+                    failed_steps += info["steps"]
+                    failed_krylov += sum(info["krylov_iters"])
+                    used = "custom->" + plain()
+                    rc, info = glnk.gl_newton_solve(mesh, pred, **opts)
                 if rc == 0:
                     break
                 h *= 0.5
             rec = {"mu": mu_next, "newton_steps": info["steps"], "krylov_iters": info["krylov_iters"],
                    "res": info["res"][-1], "status": rc, "predictor": used, "dmu": h}
+            if used.startswith("custom->"):
+                rec["failed_newton_steps"] = failed_steps
+                rec["failed_krylov_iters"] = failed_krylov
             records.append(rec)
             if callback is not None:
                 callback(rec, pred)

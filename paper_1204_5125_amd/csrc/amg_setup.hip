@@ -509,6 +509,28 @@ __global__ void k_pw_step(int n, const int *rp, const int *ci, const double2 *v,
     block_reduce_store(part, slot, sm, blockIdx.x);
 }
 
+// Level 0: the same step with H applied as the stencil (link factor tables
+// and the diagonal; its CSR copy holds the same entries), so a step streams x
+// and the diagonal instead of the CSR arrays.
+template <int DIM>
+__global__ void k_pw_step_l0(GeomT<double> g, LinkTab<double> U, const double *diag, const double2 *x,
+                             const double *xn2, double2 *y, RedSlot slot)
+{
+    __shared__ double sm[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double part = 0.0;
+    if (i < g.n) {
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        const double di = diag[i];
+        const double2 acc = cadd(cscale(x[i], di), khat_offdiag<DIM, double>(g, i, c, x, U));
+        const double2 yi = cscale(acc, 1.0 / (di * sqrt(*xn2)));
+        y[i] = yi;
+        part = cabs2(yi);
+    }
+    block_reduce_store(part, slot, sm, blockIdx.x);
+}
+
 __global__ void k_pw_rho(const double *yn2, double *rho)
 {
     if (threadIdx.x == 0) *rho = sqrt(*yn2);
@@ -523,9 +545,17 @@ static void rho_estimate(gl_precond *pre, Level &L, hipStream_t s)
     double *nrm = pre->pwn.get();
     k_pw_start<<<nb, kBlock, 0, s>>>(n, x, slot);
     launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm, nullptr, s);
+    const bool l0 = &L == &pre->L[0];
+    const GeomT<double> g = geom_t<double>(m->g);
     for (int k = 1; k <= kRhoSteps; ++k) {
-        k_pw_step<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(), x,
-                                        nrm + ((k - 1) & 1), y, slot);
+        const double *xn2 = nrm + ((k - 1) & 1);
+        if (l0 && m->g.dim == 2)
+            k_pw_step_l0<2><<<nb, kBlock, 0, s>>>(g, link_tab<double>(m), L.diag64.get(), x, xn2, y, slot);
+        else if (l0)
+            k_pw_step_l0<3><<<nb, kBlock, 0, s>>>(g, link_tab<double>(m), L.diag64.get(), x, xn2, y, slot);
+        else
+            k_pw_step<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(), x, xn2,
+                                            y, slot);
         launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm + (k & 1), nullptr, s);
         std::swap(x, y);
     }

@@ -324,6 +324,30 @@ def test_secant_predictor(glnk):
     assert relerr(host(out), oc.secant_predict(mo, a, b, 0.7)) < 1e-13
 
 
+def test_continuation_falls_back_to_secant(glnk):
+    """A predicted start that Newton cannot correct (here a non-finite one,
+    which Newton rejects at its first residual) is replaced by the secant
+    start for that step: the path, its records and its final state equal the
+    secant-only path's."""
+    from paper_1204_5125_amd import continuation as gc
+    mg = glnk.Mesh(2, (33, 33), (8.0, 8.0), mu=0.0)
+    ones = torch.ones(33 * 33, dtype=torch.complex128, device="cuda")
+    r0, p0 = gc.continuation(mg, ones, 0.0, 0.05, 4)
+    calls = []
+
+    def bad(psi, prev, mu_prev, mu, mu_next):
+        calls.append(mu_next)
+        return torch.full_like(psi, float("nan")) if len(calls) == 3 else None
+
+    r1, p1 = gc.continuation(mg, ones, 0.0, 0.05, 4, predictor=bad)
+    assert len(calls) == 4 and len(r1) == len(r0) == 5
+    assert all(r["status"] == 0 for r in r1)
+    assert r1[3]["predictor"] == "custom->secant" and r1[3]["failed_newton_steps"] == 0
+    assert [r["predictor"] for r in r1[1:3] + r1[4:]] == [r["predictor"] for r in r0[1:3] + r0[4:]]
+    assert [r["newton_steps"] for r in r1] == [r["newton_steps"] for r in r0]
+    assert torch.equal(p0, p1)
+
+
 def test_continuation_matches_oracle(glnk):
     """Natural continuation from psi = 1 at mu = 0 in steps of 0.05 on a 33 x 33
     grid of side 8: Newton steps per continuation step equal the oracle's, MINRES
