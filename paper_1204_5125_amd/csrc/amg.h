@@ -46,6 +46,8 @@ struct Level {
     DevBuf<int> perm, iperm;        // new -> old, old -> new (l >= 1)
     Csr Aa, Pa, Ra;                 // Aa (l >= 1); Pa, Ra: transfers to l + 1
     DevBuf<int> amap, pmap, rmap;   // value of entry q = value of entry map[q] of A, P, R
+    Csr Rb;                         // level 0: Ra without the red columns (the residual is zero there)
+    DevBuf<int> bmap;               // value of entry q of Rb = entry bmap[q] of R
     DevBuf<double> dg64;            // diagonal in the new order (l >= 1)
     DevBuf<float> dg32;
     // Aa once more, each colour as a padded row-major block (ELL): row r of

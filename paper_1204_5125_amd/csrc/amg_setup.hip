@@ -846,6 +846,41 @@ __global__ void k_perm_fill(int nrows, const int *rowperm, const int *rp, const 
     }
 }
 
+// Level-0 restriction without the red columns: the level-0 residual the
+// V-cycle restricts is zero on red nodes (their last pre-smoothing update
+// zeroes it), so those entries only ever multiply zeros.  Row r keeps the
+// entries of columns i with (c0 + c1 + c2) odd; map composes the copy's entry
+// with the value map of the source copy.
+__device__ __forceinline__ bool black_node(const GeomT<double> &g, int i)
+{
+    const int c0 = i % g.N[0], r = i / g.N[0];
+    const int c1 = r % g.N[1], c2 = r / g.N[1];
+    return ((c0 + c1 + c2) & 1) != 0;
+}
+
+__global__ void k_black_count(int nrows, GeomT<double> g, const int *rp, const int *ci, int *cnt)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    int c = 0;
+    for (int p = rp[r]; p < rp[r + 1]; ++p) c += black_node(g, ci[p]);
+    cnt[r] = c;
+}
+
+__global__ void k_black_fill(int nrows, GeomT<double> g, const int *rp, const int *ci, const int *srcmap,
+                             const int *nrp, int *nci, int *map)
+{
+    const int r = blockIdx.x * kBlock + threadIdx.x;
+    if (r >= nrows) return;
+    int q = nrp[r];
+    for (int p = rp[r]; p < rp[r + 1]; ++p)
+        if (black_node(g, ci[p])) {
+            nci[q] = ci[p];
+            map[q] = srcmap[p];
+            ++q;
+        }
+}
+
 __global__ void k_gather_c(int nnz, const int *map, const double2 *src, double2 *d64, float2 *d32)
 {
     const int q = blockIdx.x * kBlock + threadIdx.x;
@@ -1164,6 +1199,22 @@ static void build_apply_copies(gl_precond *pre, hipStream_t s)
             Level &Nx = pre->L[l + 1];
             permuted_copy(L.P, rowp, Nx.iperm.get(), L.Pa, L.pmap, s);
             permuted_copy(L.R, Nx.perm.get(), colp, L.Ra, L.rmap, s);
+            if (l == 0) {
+                const GeomT<double> g = geom_t<double>(pre->mesh->g);
+                Csr &B = L.Rb;
+                B.n = L.Ra.n;
+                B.m = L.Ra.m;
+                DevBuf<int> cnt(std::max(1, B.n));
+                k_black_count<<<blocks_for(B.n), kBlock, 0, s>>>(B.n, g, L.Ra.rp.get(), L.Ra.ci.get(), cnt.get());
+                GLK_CHECK_LAUNCH();
+                alloc_rowptr(B, cnt.get(), s);
+                L.bmap.alloc(std::max(1, B.nnz));
+                k_black_fill<<<blocks_for(B.n), kBlock, 0, s>>>(B.n, g, L.Ra.rp.get(), L.Ra.ci.get(), L.rmap.get(),
+                                                                B.rp.get(), B.ci.get(), L.bmap.get());
+                GLK_CHECK_LAUNCH();
+                B.v64.alloc(std::max(1, B.nnz));
+                B.v32.alloc(std::max(1, B.nnz));
+            }
         }
         if (l >= 1) {
             // padded colour blocks for the Gauss-Seidel sweeps
@@ -1293,6 +1344,9 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
                                                                L.Pa.v64.get(), L.Pa.v32.get());
             k_gather_c<<<blocks_for(L.Ra.nnz), kBlock, 0, s>>>(L.Ra.nnz, L.rmap.get(), L.R.v64.get(),
                                                                L.Ra.v64.get(), L.Ra.v32.get());
+            if (l == 0)
+                k_gather_c<<<blocks_for(L.Rb.nnz), kBlock, 0, s>>>(L.Rb.nnz, L.bmap.get(), L.R.v64.get(),
+                                                                   L.Rb.v64.get(), L.Rb.v32.get());
         }
         GLK_CHECK_LAUNCH();
     }

@@ -883,7 +883,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const double szc = sizeof(C<TC>);
     const double b_prol = (mc + 1 + 0.5 * L0.Pa.nnz) * 4.0 + 0.5 * L0.Pa.nnz * szc + L0.nc * szc + 2.0 * mc * sz;
     const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
-    const double b_restr = (L0.nc + 1 + L0.Ra.nnz) * 4.0 + L0.Ra.nnz * szc + nn * sz + L0.nc * szc;
+    const double b_restr = (L0.nc + 1 + L0.Rb.nnz) * 4.0 + L0.Rb.nnz * szc + (nn - mc) * sz + L0.nc * szc;
     // level 0 (one thread per red-black pair), down: red (from zero, folded) +
     // black, red, black residual, restriction
     const int nbp = blocks_for(g.npair);
@@ -897,7 +897,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
         L.run(nbp, L0Residual<DIM, T>{g, v, b0, x0, U, hd, vec_r<T>(L0), gate});
     });
     prof_launch(PROF_L0_TRANSFER, b_restr, L, [&] {
-        csr_spmv<TC, T>(L0.Ra, vec_r<T>(L0), vec_b<TC>(L1), false, 0, gate, L);
+        csr_spmv<TC, T>(L0.Rb, vec_r<T>(L0), vec_b<TC>(L1), false, 0, gate, L);
     });
     // multi-kernel coarse levels, down
     const int nb_first = pre->bottom;
