@@ -46,7 +46,10 @@ struct Level {
     DevBuf<int> perm, iperm;        // new -> old, old -> new (l >= 1)
     Csr Aa, Pa, Ra;                 // Aa (l >= 1); Pa, Ra: transfers to l + 1
     DevBuf<int> amap, pmap, rmap;   // value of entry q = value of entry map[q] of A, P, R
-    Csr Rb;                         // level 0: Ra without the red columns (the residual is zero there)
+    Csr Rb;                         // level 0: Ra without the red columns (the residual is zero there),
+                                    // columns numbered in the colour-split layout of the level-0 vectors
+    DevBuf<double> hs64;            // level 0: the diagonal in that layout
+    DevBuf<float> hs32;
     DevBuf<int> bmap;               // value of entry q of Rb = entry bmap[q] of R
     DevBuf<double> dg64;            // diagonal in the new order (l >= 1)
     DevBuf<float> dg32;
@@ -57,7 +60,8 @@ struct Level {
     DevBuf<int> eci, emap;          // emap: entry of Aa, or -1 for padding
     DevBuf<double2> ev64;
     DevBuf<float2> ev32;
-    // V-cycle vectors (new order on levels >= 1)
+    // V-cycle vectors (new order on levels >= 1; level 0: split by colour, the
+    // node of colour c in red-black pair t at c * npair + t, 2 npair entries)
     DevBuf<double2> b64, x64, r64;
     DevBuf<float2> b32, x32, r32;
 };

@@ -867,18 +867,38 @@ __global__ void k_black_count(int nrows, GeomT<double> g, const int *rp, const i
     cnt[r] = c;
 }
 
+// columns numbered as the V-cycle stores level-0 vectors: black node i of
+// red-black pair t at npair + t
 __global__ void k_black_fill(int nrows, GeomT<double> g, const int *rp, const int *ci, const int *srcmap,
                              const int *nrp, int *nci, int *map)
 {
     const int r = blockIdx.x * kBlock + threadIdx.x;
     if (r >= nrows) return;
     int q = nrp[r];
-    for (int p = rp[r]; p < rp[r + 1]; ++p)
-        if (black_node(g, ci[p])) {
-            nci[q] = ci[p];
+    for (int p = rp[r]; p < rp[r + 1]; ++p) {
+        const int i = ci[p];
+        if (black_node(g, i)) {
+            nci[q] = g.npair + (i / g.N[0]) * g.hr + (i % g.N[0]) / 2;
             map[q] = srcmap[p];
             ++q;
         }
+    }
+}
+
+// the level-0 diagonal in the colour-split layout (an absent odd node's slot
+// holds 1)
+__global__ void k_split_diag(GeomT<double> g, const double *d, double *s64, float *s32)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g.npair) return;
+    const int row = t / g.hr, c0 = 2 * (t - row * g.hr);
+    const int c1 = row % g.N[1], c2 = row / g.N[1];
+    const int ie = c0 + g.N[0] * row, ce = (c0 + c1 + c2) & 1;
+    const double de = d[ie], dodd = c0 + 1 < g.N[0] ? d[ie + 1] : 1.0;
+    s64[ce * g.npair + t] = de;
+    s32[ce * g.npair + t] = (float)de;
+    s64[(1 - ce) * g.npair + t] = dodd;
+    s32[(1 - ce) * g.npair + t] = (float)dodd;
 }
 
 __global__ void k_gather_c(int nnz, const int *map, const double2 *src, double2 *d64, float2 *d32)
@@ -1127,18 +1147,24 @@ static void transfer_patterns(gl_precond *pre, int l, hipStream_t s)
 
 static void alloc_values(gl_precond *pre)
 {
+    const int ns = 2 * geom_t<double>(pre->mesh->g).npair;  // level-0 split layout
     for (int l = 0; l < pre->nlev; ++l) {
         Level &L = pre->L[l];
+        const int nv = l == 0 ? std::max(L.n, ns) : L.n;
         L.A.v64.alloc(std::max(1, L.A.nnz));
         L.A.v32.alloc(std::max(1, L.A.nnz));
         L.diag64.alloc(L.n);
         L.diag32.alloc(L.n);
-        L.b64.alloc(L.n);
-        L.x64.alloc(L.n);
-        L.r64.alloc(L.n);
-        L.b32.alloc(L.n);
-        L.x32.alloc(L.n);
-        L.r32.alloc(L.n);
+        L.b64.alloc(nv);
+        L.x64.alloc(nv);
+        L.r64.alloc(nv);
+        L.b32.alloc(nv);
+        L.x32.alloc(nv);
+        L.r32.alloc(nv);
+        if (l == 0) {
+            L.hs64.alloc(ns);
+            L.hs32.alloc(ns);
+        }
         if (l < pre->nlev - 1) {
             L.P.v64.alloc(std::max(1, L.P.nnz));
             L.P.v32.alloc(std::max(1, L.P.nnz));
@@ -1203,7 +1229,7 @@ static void build_apply_copies(gl_precond *pre, hipStream_t s)
                 const GeomT<double> g = geom_t<double>(pre->mesh->g);
                 Csr &B = L.Rb;
                 B.n = L.Ra.n;
-                B.m = L.Ra.m;
+                B.m = 2 * g.npair;
                 DevBuf<int> cnt(std::max(1, B.n));
                 k_black_count<<<blocks_for(B.n), kBlock, 0, s>>>(B.n, g, L.Ra.rp.get(), L.Ra.ci.get(), cnt.get());
                 GLK_CHECK_LAUNCH();
@@ -1326,6 +1352,7 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
         k_diag<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Lc.A.rp.get(), Lc.A.ci.get(), Lc.A.v64.get(), Lc.diag64.get());
     // level 0 in single precision (its stencil diagonal; the CSR copy serves export only)
     k_to_f32r<<<blocks_for(n0), kBlock, 0, s>>>(n0, L0.diag64.get(), L0.diag32.get());
+    k_split_diag<<<blocks_for(g.npair), kBlock, 0, s>>>(g, L0.diag64.get(), L0.hs64.get(), L0.hs32.get());
     // colour-ordered copies for the V-cycle, FP64 and rounded to FP32
     for (int l = 0; l < pre->nlev; ++l) {
         Level &L = pre->L[l];

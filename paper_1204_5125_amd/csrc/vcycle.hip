@@ -31,12 +31,6 @@ namespace glk {
 // the flag is uniform, so every thread takes the same branch.
 #define GATE_LOAD() const bool gate_go = gate == nullptr || *gate != 0
 
-template <class T> __device__ __forceinline__ C<T> load_b(const double2 *v, const C<T> *b, int i)
-{
-    if constexpr (std::is_same<T, double>::value) return v[i];
-    else return b[i];
-}
-
 // Level-0 colour passes run one thread per red-black pair: thread t owns the
 // nodes c0 = 2k and 2k + 1 of x-row `row` (k = t mod hr, row = t / hr), one
 // of each colour, so every thread updates a node (a thread per node would
@@ -67,7 +61,42 @@ __device__ __forceinline__ bool pair_colour(const Pair &P, int col, int &s)
     return s == 0 || P.odd;
 }
 
-// pre-smoothing, black pass from zero; FP32 also stores b = round(v)
+// The V-cycle's level-0 vectors (b, x, r) and the diagonal it divides by are
+// stored split by colour: the node of colour col in pair t sits at
+// col * npair + t.  A colour pass then reads and writes one contiguous half,
+// and the neighbours of a node, all of the other colour, sit in the other
+// half at pairs t +- 1 (x), t +- hr (y) and t +- hr N1 (z).  The sum below
+// takes the terms in the order of khat_offdiag, so the results do not change.
+template <int DIM, class T>
+__device__ __forceinline__ C<T> khat_offdiag_rb(const GeomT<T> &g, const int c[3], int t,
+                                                const C<T> *__restrict__ xo, const LinkTab<T> &U)
+{
+    T s[3];
+    const T d = node_volume<DIM, T>(g, c, s);
+    C<T> acc = mk<T>(0, 0);
+    const int row0 = t - (c[0] >> 1);  // first pair of the node's x-row
+    int pstride = g.hr;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const T al = d * s[a] * g.inv_h2[a];
+        int tl, tu;
+        if (a == 0) {
+            tl = row0 + ((c[0] - 1) >> 1);
+            tu = row0 + ((c[0] + 1) >> 1);
+        } else {
+            tl = t - pstride;
+            tu = t + pstride;
+            pstride *= g.N[a];
+        }
+        if (c[a] > 0) acc = csub(acc, cscale(cmul(link_u<DIM, T>(U, a, c, c[a] - 1), xo[tl]), al));
+        if (c[a] < g.N[a] - 1) acc = csub(acc, cscale(cmulc(link_u<DIM, T>(U, a, c, c[a]), xo[tu]), al));
+    }
+    return acc;
+}
+
+// pre-smoothing: b = round(v) into the split layout, and the black pass from
+// zero (the red pass from zero, x_red = b / diag, folded in: it reads v and
+// the natural-order diagonal hd at the red neighbours)
 template <int DIM, class T>
 struct L0PreBlack {
     GeomT<T> g;
@@ -82,18 +111,18 @@ struct L0PreBlack {
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         if (t >= g.npair) return;
         const Pair P = pair_at<DIM, T>(g, t);
-        if constexpr (std::is_same<T, float>::value) {
-            const C<T> b0 = narrow<T>(v[P.ie]);
-            const C<T> b1 = P.odd ? narrow<T>(v[P.ie + 1]) : mk<T>(0, 0);
-            if (!gate_go) return;
-            b[P.ie] = b0;
-            if (P.odd) b[P.ie + 1] = b1;
+        const int np = g.npair, ce = (P.c[1] + P.c[2]) & 1;  // colour of the even node
+        const C<T> b0 = narrow<T>(v[P.ie]);
+        const C<T> b1 = P.odd ? narrow<T>(v[P.ie + 1]) : mk<T>(0, 0);
+        if (gate_go) {
+            b[ce * np + t] = b0;
+            if (P.odd) b[(1 - ce) * np + t] = b1;
         }
         int sb;
         if (!pair_colour(P, 1, sb)) return;
         const int i = P.ie + sb;
         const int c[3] = {P.c[0] + sb, P.c[1], P.c[2]};
-        const C<T> bi = narrow<T>(v[i]);
+        const C<T> bi = sb ? b1 : b0;
         T s[3];
         const T d = node_volume<DIM, T>(g, c, s);
         C<T> off = mk<T>(0, 0);
@@ -115,20 +144,20 @@ struct L0PreBlack {
         }
         const C<T> xi = cscale(csub(bi, off), (T)1 / hd[i]);
         if (!gate_go) return;
-        x[i] = xi;
+        x[np + t] = xi;
     }
 };
 
-// x_i = (b_i - sum_{j != i} H_ij x_j) / H_ii on one colour
+// x_i = (b_i - sum_{j != i} H_ij x_j) / H_ii on one colour (split layout; hs:
+// the diagonal in that layout)
 template <int DIM, class T>
 struct L0Sweep {
     GeomT<T> g;
     int colour;
-    const double2 *v;
     const C<T> *b;
     C<T> *x;
     LinkTab<T> U;
-    const T *hd;
+    const T *hs;
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
     {
@@ -138,25 +167,25 @@ struct L0Sweep {
         const Pair P = pair_at<DIM, T>(g, t);
         int sc;
         if (!pair_colour(P, colour, sc)) return;
-        const int i = P.ie + sc;
         const int c[3] = {P.c[0] + sc, P.c[1], P.c[2]};
-        const C<T> bi = load_b<T>(v, b, i);
-        const T di = hd[i];
-        const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+        const int q = colour * g.npair + t;
+        const C<T> bi = b[q];
+        const T di = hs[q];
+        const C<T> off = khat_offdiag_rb<DIM, T>(g, c, t, x + (1 - colour) * g.npair, U);
         const C<T> xi = cscale(csub(bi, off), (T)1 / di);
         if (!gate_go) return;
-        x[i] = xi;
+        x[q] = xi;
     }
 };
 
-// r = b - H x on black nodes, 0 on red nodes
+// r = b - H x on the black nodes (split layout); the red residual is zero and
+// is neither stored nor read (the restriction has no red columns)
 template <int DIM, class T>
 struct L0Residual {
     GeomT<T> g;
-    const double2 *v;
     const C<T> *b, *x;
     LinkTab<T> U;
-    const T *hd;
+    const T *hs;
     C<T> *r;
     const int *gate;
     __device__ void operator()(int bx, int nbx) const
@@ -165,21 +194,17 @@ struct L0Residual {
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         if (t >= g.npair) return;
         const Pair P = pair_at<DIM, T>(g, t);
-        int sb, sr;
-        const bool red = pair_colour(P, 0, sr), black = pair_colour(P, 1, sb);
-        C<T> ri = mk<T>(0, 0);
-        const int i = P.ie + sb;
-        if (black) {
-            const int c[3] = {P.c[0] + sb, P.c[1], P.c[2]};
-            const C<T> bi = load_b<T>(v, b, i);
-            const C<T> xi = x[i];
-            const T di = hd[i];
-            const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
-            ri = csub(csub(bi, cscale(xi, di)), off);
-        }
+        int sb;
+        if (!pair_colour(P, 1, sb)) return;
+        const int c[3] = {P.c[0] + sb, P.c[1], P.c[2]};
+        const int q = g.npair + t;
+        const C<T> bi = b[q];
+        const C<T> xi = x[q];
+        const T di = hs[q];
+        const C<T> off = khat_offdiag_rb<DIM, T>(g, c, t, x, U);
+        const C<T> ri = csub(csub(bi, cscale(xi, di)), off);
         if (!gate_go) return;
-        if (red) r[P.ie + sr] = mk<T>(0, 0);
-        if (black) r[i] = ri;
+        r[q] = ri;
     }
 };
 
@@ -215,7 +240,8 @@ __device__ __forceinline__ C<T> prolong_row(const int *__restrict__ prp, const i
 }
 
 // coarse correction of the black nodes: x_b += (P x_c)_b (the red nodes are
-// overwritten by the red pass that follows, which reads only black values)
+// overwritten by the red pass that follows, which reads only black values);
+// x in the split layout, P by natural row
 template <int DIM, class T, class TC = T>
 struct L0ProlongBlack {
     GeomT<T> g;
@@ -231,11 +257,11 @@ struct L0ProlongBlack {
         const Pair P = pair_at<DIM, T>(g, t);
         int sb;
         if (!pair_colour(P, 1, sb)) return;
-        const int i = P.ie + sb;
-        const C<T> xo = x[i];
-        const C<T> xi = cadd(xo, as_c<T>(prolong_row<TC>(prp, pci, pv, xc, i)));
+        const int q = g.npair + t;
+        const C<T> xo = x[q];
+        const C<T> xi = cadd(xo, as_c<T>(prolong_row<TC>(prp, pci, pv, xc, P.ie + sb)));
         if (!gate_go) return;
-        x[i] = xi;
+        x[q] = xi;
     }
 };
 
@@ -243,11 +269,10 @@ struct L0ProlongBlack {
 template <int DIM, class T, int ADD>
 struct L0Last {
     GeomT<T> g;
-    const double2 *v;
     const C<T> *b;
     C<T> *x;
     LinkTab<T> U;
-    const T *hd;
+    const T *hs;
     double2 *z;
     const double2 *vdot;
     RedSlot slot;
@@ -260,19 +285,21 @@ struct L0Last {
         const int t = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         const bool in = t < g.npair;
         const Pair P = pair_at<DIM, T>(g, in ? t : 0);
-        // the red node's update, then z on both nodes (even first); every
-        // load before the (uniform) gate check, every store after it
-        int sr;
+        // the red node's update, then z on both nodes (even first, natural
+        // order); every load before the (uniform) gate check, every store
+        // after it
+        int sr, sb;
         const bool red = in && pair_colour(P, 0, sr);
+        const bool black = in && pair_colour(P, 1, sb);
         C<T> xr = mk<T>(0, 0);
+        const C<T> xb = black ? x[g.npair + t] : mk<T>(0, 0);
         double2 zq[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
         double part = 0.0;
         if (red) {
-            const int i = P.ie + sr;
             const int c[3] = {P.c[0] + sr, P.c[1], P.c[2]};
-            const C<T> bi = load_b<T>(v, b, i);
-            const T di = hd[i];
-            const C<T> off = khat_offdiag<DIM, T>(g, i, c, x, U);
+            const C<T> bi = b[t];
+            const T di = hs[t];
+            const C<T> off = khat_offdiag_rb<DIM, T>(g, c, t, x + g.npair, U);
             xr = cscale(csub(bi, off), (T)1 / di);
         }
         if (in) {
@@ -280,7 +307,7 @@ struct L0Last {
             for (int q = 0; q < 2; ++q) {
                 if (q == 1 && !P.odd) break;
                 const int i = P.ie + q;
-                double2 zi = widen(red && q == sr ? xr : x[i]);
+                double2 zi = widen(red && q == sr ? xr : xb);
                 if (ADD) zi = cadd(z[i], zi);
                 zq[q] = zi;
                 if (want_dot) part += redot(vdot[i], zi);
@@ -288,7 +315,7 @@ struct L0Last {
         }
         if (!gate_go) return;
         if (in) {
-            if (red) x[P.ie + sr] = xr;
+            if (red) x[t] = xr;
             z[P.ie] = zq[0];
             if (P.odd) z[P.ie + 1] = zq[1];
         }
@@ -715,6 +742,10 @@ template <> const float2 *vals<float>(const Csr &M) { return M.v32.get(); }
 template <class T> static const T *diag(const Level &L);
 template <> const double *diag<double>(const Level &L) { return L.diag64.get(); }
 template <> const float *diag<float>(const Level &L) { return L.diag32.get(); }
+// level-0 diagonal in the colour-split layout of the V-cycle's level-0 vectors
+template <class T> static const T *hsplit(const Level &L);
+template <> const double *hsplit<double>(const Level &L) { return L.hs64.get(); }
+template <> const float *hsplit<float>(const Level &L) { return L.hs32.get(); }
 template <class T> static const T *dgn(const Level &L);
 template <> const double *dgn<double>(const Level &L) { return L.dg64.get(); }
 template <> const float *dgn<float>(const Level &L) { return L.dg32.get(); }
@@ -860,7 +891,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const int n0 = L0.n, nb0 = blocks_for(n0);
     const int nl = pre->nlev;
     const bool f32 = std::is_same<T, float>::value;
-    C<T> *b0 = f32 ? vec_b<T>(L0) : (C<T> *)v;
+    C<T> *b0 = vec_b<T>(L0);
     C<T> *x0 = vec_x<T>(L0);
     const int want = ks != nullptr;
     if (nl == 1) {
@@ -872,14 +903,14 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
         if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, L);
         return;
     }
-    const T *hd = diag<T>(L0);
+    const T *hd = diag<T>(L0), *hs = hsplit<T>(L0);
     Level &L1 = pre->L[1];
     // algorithmic bytes of the level-0 kernels (each array touched once)
     // (the link factor tables are a few KB and stay in cache)
     const double sz = sizeof(C<T>), szr = sizeof(T), nn = n0, mc = 0.5 * nn;
-    const double b_pre = nn * 16 + (f32 ? nn * sz : 0) + nn * szr + mc * sz;
-    const double b_sweep = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz;
-    const double b_resid = mc * ((f32 ? sz : 16) + szr + sz) + (nn - mc) * sz + nn * sz;
+    const double b_pre = nn * 16 + nn * sz + nn * szr + mc * sz;
+    const double b_sweep = mc * (sz + szr + sz) + (nn - mc) * sz;
+    const double b_resid = b_sweep + (nn - mc) * sz;
     const double szc = sizeof(C<TC>);
     const double b_prol = (mc + 1 + 0.5 * L0.Pa.nnz) * 4.0 + 0.5 * L0.Pa.nnz * szc + L0.nc * szc + 2.0 * mc * sz;
     const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
@@ -891,10 +922,10 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
         L.run(nbp, L0PreBlack<DIM, T>{g, v, vec_b<T>(L0), x0, U, hd, gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
-        L.run(nbp, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
+        L.run(nbp, L0Sweep<DIM, T>{g, 0, b0, x0, U, hs, gate});
     });
     prof_launch(PROF_L0_RESIDUAL, b_resid, L, [&] {
-        L.run(nbp, L0Residual<DIM, T>{g, v, b0, x0, U, hd, vec_r<T>(L0), gate});
+        L.run(nbp, L0Residual<DIM, T>{g, b0, x0, U, hs, vec_r<T>(L0), gate});
     });
     prof_launch(PROF_L0_TRANSFER, b_restr, L, [&] {
         csr_spmv<TC, T>(L0.Rb, vec_r<T>(L0), vec_b<TC>(L1), false, 0, gate, L);
@@ -932,14 +963,14 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
                                               vec_x<TC>(L1), gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
-        L.run(nbp, L0Sweep<DIM, T>{g, 0, v, b0, x0, U, hd, gate});
+        L.run(nbp, L0Sweep<DIM, T>{g, 0, b0, x0, U, hs, gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
-        L.run(nbp, L0Sweep<DIM, T>{g, 1, v, b0, x0, U, hd, gate});
+        L.run(nbp, L0Sweep<DIM, T>{g, 1, b0, x0, U, hs, gate});
     });
     prof_launch(PROF_L0_SWEEP, b_last, L, [&] {
-        if (add) L.run(nbp, L0Last<DIM, T, 1>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
-        else L.run(nbp, L0Last<DIM, T, 0>{g, v, b0, x0, U, hd, z, vdot, slot, want, gate});
+        if (add) L.run(nbp, L0Last<DIM, T, 1>{g, b0, x0, U, hs, z, vdot, slot, want, gate});
+        else L.run(nbp, L0Last<DIM, T, 0>{g, b0, x0, U, hs, z, vdot, slot, want, gate});
     });
     if (ks) launch_finalize(slot.partials, nbp, mode, ks, nullptr, gate, L);
 }
