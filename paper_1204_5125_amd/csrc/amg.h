@@ -48,6 +48,8 @@ struct Level {
     DevBuf<int> amap, pmap, rmap;   // value of entry q = value of entry map[q] of A, P, R
     Csr Rb;                         // level 0: Ra without the red columns (the residual is zero there),
                                     // columns numbered in the colour-split layout of the level-0 vectors
+    Csr Pb;                         // level 0: Pa rows of the black nodes, row t = pair t
+    DevBuf<int> pbmap;              // value of entry q of Pb = entry pbmap[q] of P
     DevBuf<double> hs64;            // level 0: the diagonal in that layout
     DevBuf<float> hs32;
     DevBuf<int> bmap;               // value of entry q of Rb = entry bmap[q] of R

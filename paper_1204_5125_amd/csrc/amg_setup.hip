@@ -885,6 +885,40 @@ __global__ void k_black_fill(int nrows, GeomT<double> g, const int *rp, const in
     }
 }
 
+// Level-0 prolongation rows of the black nodes only, row t = the black node
+// of red-black pair t (empty where the pair has none): the V-cycle corrects
+// only black nodes from the coarse level, and the copy keeps those rows
+// contiguous.  map composes with the value map of the source copy.
+__device__ __forceinline__ int pair_black(const GeomT<double> &g, int t)
+{
+    const int row = t / g.hr, c0 = 2 * (t - row * g.hr);
+    const int c1 = row % g.N[1], c2 = row / g.N[1];
+    const int s = (1 + c1 + c2) & 1;
+    return c0 + s < g.N[0] ? c0 + s + g.N[0] * row : -1;
+}
+
+__global__ void k_pblack_count(GeomT<double> g, const int *rp, int *cnt)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g.npair) return;
+    const int i = pair_black(g, t);
+    cnt[t] = i < 0 ? 0 : rp[i + 1] - rp[i];
+}
+
+__global__ void k_pblack_fill(GeomT<double> g, const int *rp, const int *ci, const int *srcmap, const int *nrp,
+                              int *nci, int *map)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= g.npair) return;
+    const int i = pair_black(g, t);
+    if (i < 0) return;
+    int q = nrp[t];
+    for (int p = rp[i]; p < rp[i + 1]; ++p, ++q) {
+        nci[q] = ci[p];
+        map[q] = srcmap[p];
+    }
+}
+
 // the level-0 diagonal in the colour-split layout (an absent odd node's slot
 // holds 1)
 __global__ void k_split_diag(GeomT<double> g, const double *d, double *s64, float *s32)
@@ -1240,6 +1274,19 @@ static void build_apply_copies(gl_precond *pre, hipStream_t s)
                 GLK_CHECK_LAUNCH();
                 B.v64.alloc(std::max(1, B.nnz));
                 B.v32.alloc(std::max(1, B.nnz));
+                Csr &Q = L.Pb;
+                Q.n = g.npair;
+                Q.m = L.Pa.m;
+                DevBuf<int> qcnt(std::max(1, Q.n));
+                k_pblack_count<<<blocks_for(Q.n), kBlock, 0, s>>>(g, L.Pa.rp.get(), qcnt.get());
+                GLK_CHECK_LAUNCH();
+                alloc_rowptr(Q, qcnt.get(), s);
+                L.pbmap.alloc(std::max(1, Q.nnz));
+                k_pblack_fill<<<blocks_for(Q.n), kBlock, 0, s>>>(g, L.Pa.rp.get(), L.Pa.ci.get(), L.pmap.get(),
+                                                                 Q.rp.get(), Q.ci.get(), L.pbmap.get());
+                GLK_CHECK_LAUNCH();
+                Q.v64.alloc(std::max(1, Q.nnz));
+                Q.v32.alloc(std::max(1, Q.nnz));
             }
         }
         if (l >= 1) {
@@ -1371,9 +1418,12 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
                                                                L.Pa.v64.get(), L.Pa.v32.get());
             k_gather_c<<<blocks_for(L.Ra.nnz), kBlock, 0, s>>>(L.Ra.nnz, L.rmap.get(), L.R.v64.get(),
                                                                L.Ra.v64.get(), L.Ra.v32.get());
-            if (l == 0)
+            if (l == 0) {
                 k_gather_c<<<blocks_for(L.Rb.nnz), kBlock, 0, s>>>(L.Rb.nnz, L.bmap.get(), L.R.v64.get(),
                                                                    L.Rb.v64.get(), L.Rb.v32.get());
+                k_gather_c<<<blocks_for(L.Pb.nnz), kBlock, 0, s>>>(L.Pb.nnz, L.pbmap.get(), L.P.v64.get(),
+                                                                   L.Pb.v64.get(), L.Pb.v32.get());
+            }
         }
         GLK_CHECK_LAUNCH();
     }

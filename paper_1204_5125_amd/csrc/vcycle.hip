@@ -241,7 +241,8 @@ __device__ __forceinline__ C<T> prolong_row(const int *__restrict__ prp, const i
 
 // coarse correction of the black nodes: x_b += (P x_c)_b (the red nodes are
 // overwritten by the red pass that follows, which reads only black values);
-// x in the split layout, P by natural row
+// x in the split layout, P's black rows by pair (row t: the black node of
+// pair t)
 template <int DIM, class T, class TC = T>
 struct L0ProlongBlack {
     GeomT<T> g;
@@ -259,7 +260,7 @@ struct L0ProlongBlack {
         if (!pair_colour(P, 1, sb)) return;
         const int q = g.npair + t;
         const C<T> xo = x[q];
-        const C<T> xi = cadd(xo, as_c<T>(prolong_row<TC>(prp, pci, pv, xc, P.ie + sb)));
+        const C<T> xi = cadd(xo, as_c<T>(prolong_row<TC>(prp, pci, pv, xc, t)));
         if (!gate_go) return;
         x[q] = xi;
     }
@@ -912,7 +913,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const double b_sweep = mc * (sz + szr + sz) + (nn - mc) * sz;
     const double b_resid = b_sweep + (nn - mc) * sz;
     const double szc = sizeof(C<TC>);
-    const double b_prol = (mc + 1 + 0.5 * L0.Pa.nnz) * 4.0 + 0.5 * L0.Pa.nnz * szc + L0.nc * szc + 2.0 * mc * sz;
+    const double b_prol = (g.npair + 1 + L0.Pb.nnz) * 4.0 + L0.Pb.nnz * szc + L0.nc * szc + 2.0 * mc * sz;
     const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
     const double b_restr = (L0.nc + 1 + L0.Rb.nnz) * 4.0 + L0.Rb.nnz * szc + (nn - mc) * sz + L0.nc * szc;
     // level 0 (one thread per red-black pair), down: red (from zero, folded) +
@@ -959,7 +960,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     // black coarse correction, then the red pass (fusing the two reads every
     // black correction four times and was measured slower)
     prof_launch(PROF_L0_TRANSFER, b_prol, L, [&] {
-        L.run(nbp, L0ProlongBlack<DIM, T, TC>{g, x0, L0.Pa.rp.get(), L0.Pa.ci.get(), vals<TC>(L0.Pa),
+        L.run(nbp, L0ProlongBlack<DIM, T, TC>{g, x0, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
                                               vec_x<TC>(L1), gate});
     });
     prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
