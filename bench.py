@@ -46,8 +46,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "f78f367160dd57b9e556636487b874e4e8fede4a4b7f9da443d6803a5e6c00bd",
-           8: 4962869.2, 2: 32239310.8}
+TRAFFIC = {"csrc_sha256": "3e9cf1cdaa1ec611bb0325ec55bcc47e76eb11b5018b829e105baa5bb2d340c1",
+           8: 4962807.4, 2: 20219317.2}
 
 
 def csrc_fingerprint():

@@ -288,7 +288,8 @@ struct L0Last {
         const Pair P = pair_at<DIM, T>(g, in ? t : 0);
         // the red node's update, then z on both nodes (even first, natural
         // order); every load before the (uniform) gate check, every store
-        // after it
+        // after it.  The red update goes to z only: the next cycle starts
+        // from zero and writes every node before it reads it.
         int sr, sb;
         const bool red = in && pair_colour(P, 0, sr);
         const bool black = in && pair_colour(P, 1, sb);
@@ -316,7 +317,6 @@ struct L0Last {
         }
         if (!gate_go) return;
         if (in) {
-            if (red) x[t] = xr;
             z[P.ie] = zq[0];
             if (P.odd) z[P.ie + 1] = zq[1];
         }
@@ -914,7 +914,7 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const double b_resid = b_sweep + (nn - mc) * sz;
     const double szc = sizeof(C<TC>);
     const double b_prol = (g.npair + 1 + L0.Pb.nnz) * 4.0 + L0.Pb.nnz * szc + L0.nc * szc + 2.0 * mc * sz;
-    const double b_last = b_sweep + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
+    const double b_last = b_sweep - mc * sz + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
     const double b_restr = (L0.nc + 1 + L0.Rb.nnz) * 4.0 + L0.Rb.nnz * szc + (nn - mc) * sz + L0.nc * szc;
     // level 0 (one thread per red-black pair), down: red (from zero, folded) +
     // black, red, black residual, restriction
