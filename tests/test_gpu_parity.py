@@ -21,8 +21,11 @@ CASES = [
     (2, (37, 23), (6.0, 4.0), 1.1, (0, 0, 1)),
     (3, (9, 9, 9), (5.0, 5.0, 5.0), 0.6, (1, 1, 1)),
     (3, (7, 5, 11), (3.0, 2.0, 4.0), 0.9, (0.3, -0.5, 1.0)),
+    # even x-widths: every red-black pair of the level-0 layout holds two nodes
+    (2, (24, 17), (5.0, 4.0), 0.9, (0, 0, 1)),
+    (3, (8, 6, 5), (4.0, 3.0, 2.5), 0.7, (0.2, 0.4, 1.0)),
 ]
-IDS = ["2d-33x33", "2d-37x23", "3d-9^3", "3d-7x5x11"]
+IDS = ["2d-33x33", "2d-37x23", "3d-9^3", "3d-7x5x11", "2d-24x17", "3d-8x6x5"]
 
 
 @pytest.fixture(scope="module")
