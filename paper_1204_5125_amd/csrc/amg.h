@@ -2,7 +2,8 @@
 // H = K-hat + 2 D |psi|^2 (Sec. 4.1, eq. prec2).  Level 0 is applied as a
 // stencil; its CSR copy exists for setup and export.  Coarser levels are CSR
 // with int32 indices, values stored in FP64 and FP32.  The smallest levels and
-// the dense coarsest solve run inside one work-group ("bottom" kernel).
+// the dense coarsest solve run inside one work-group ("bottom" kernel), or the
+// cycle below a chosen level is applied as an explicit dense matrix.
 #pragma once
 
 #include "common.h"

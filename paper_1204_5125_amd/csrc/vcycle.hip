@@ -14,7 +14,10 @@
 //   - after the coarse correction only the black values x_b + (P x_c)_b are
 //     read (by the first red update), so only black nodes are prolonged.
 // On the coarser levels the zero start and the first two colour passes of the
-// pre-smoothing sweep are one dispatch for the same reason.
+// pre-smoothing sweep are one dispatch for the same reason.  Below the first
+// level with at most dense_rows rows (a tile choice) the cycle is a fixed
+// linear map of that level's right-hand side; it is formed as a dense matrix
+// at setup and applied as one product, like the coarsest inverse.
 #include <cstring>
 #include <type_traits>
 
