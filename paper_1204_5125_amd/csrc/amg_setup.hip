@@ -636,19 +636,31 @@ __global__ void k_rap_fill(int nc, const int *rrp, const int *rci, const int *ar
     });
 }
 
-// cv[t] = sum of (R_p A_q) P_s over the products of entry t (0 for J < I)
+// cv[t] = sum of (R_p A_q) P_s over the products of entry t (0 for J < I).
+// kRapLanes lanes share an entry: lane j sums products j, j + kRapLanes, ...
+// of its list in order, then the lanes are added by a fixed butterfly, so a
+// setup is bit-reproducible; neighbouring lanes read neighbouring triples.
+constexpr int kRapLanes = 8;
+
 __global__ void k_rap_values(int nnz, const int *__restrict__ tp, const int *__restrict__ trip,
                              const double2 *__restrict__ rv, const double2 *__restrict__ av,
                              const double2 *__restrict__ pv, double2 *__restrict__ cv)
 {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= nnz) return;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int t = (int)(g / kRapLanes), lane = (int)(g % kRapLanes);
+    const bool act = t < nnz;
     double2 acc = make_double2(0.0, 0.0);
-    for (int k = tp[t]; k < tp[t + 1]; ++k) {
-        const double2 ra = cmul(rv[trip[3 * k]], av[trip[3 * k + 1]]);
-        acc = cadd(acc, cmul(ra, pv[trip[3 * k + 2]]));
+    if (act)
+        for (int k = tp[t] + lane; k < tp[t + 1]; k += kRapLanes) {
+            const double2 ra = cmul(rv[trip[3 * k]], av[trip[3 * k + 1]]);
+            acc = cadd(acc, cmul(ra, pv[trip[3 * k + 2]]));
+        }
+#pragma unroll
+    for (int o = kRapLanes / 2; o > 0; o >>= 1) {
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
     }
-    cv[t] = acc;
+    if (act && lane == 0) cv[t] = acc;
 }
 
 __global__ void k_rap_mirror(int nc, const int *crp, const int *cci, double2 *cv)
@@ -1387,9 +1399,9 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
                                          L.P.ci.get(), L.P.v64.get());
         k_r_values<<<blocks_for(L.R.nnz), kBlock, 0, s>>>(L.R.nnz, L.rsrc.get(), L.P.v64.get(), L.R.v64.get());
         const int nbc = blocks_for(L.nc);
-        k_rap_values<<<blocks_for(Nx.A.nnz), kBlock, 0, s>>>(Nx.A.nnz, L.rap_tp.get(), L.rap_trip.get(),
-                                                             L.R.v64.get(), L.A.v64.get(), L.P.v64.get(),
-                                                             Nx.A.v64.get());
+        k_rap_values<<<blocks_for((int64_t)Nx.A.nnz * kRapLanes), kBlock, 0, s>>>(
+            Nx.A.nnz, L.rap_tp.get(), L.rap_trip.get(), L.R.v64.get(), L.A.v64.get(), L.P.v64.get(),
+            Nx.A.v64.get());
         k_rap_mirror<<<nbc, kBlock, 0, s>>>(L.nc, Nx.A.rp.get(), Nx.A.ci.get(), Nx.A.v64.get());
         GLK_CHECK_LAUNCH();
     }
