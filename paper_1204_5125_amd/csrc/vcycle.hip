@@ -700,8 +700,10 @@ struct Bottom {
 
 // Columns col0 .. col0 + ncols - 1 of the explicit sub-cycle of level
 // D.first: work-group c runs bottom_cycle on the unit vector e_{col0 + c}
-// with vectors of its own (ws + c * ws_col: b, x, r of each level in turn)
-// and stores the result as that column of the row-major n x n matrix out.
+// with vectors of its own (ws + c * ws_col: b, x, r of each level in turn;
+// with lds set, the iterate of level D.first lives in LDS instead, so the
+// gathers of its passes stay on the compute unit) and stores the result as
+// that column of the row-major n x n matrix out.
 template <class T>
 struct TailColumns {
     const BottomDesc<T> *Dp;
@@ -709,13 +711,17 @@ struct TailColumns {
     size_t ws_col;
     int col0, ncols;
     C<T> *out;
+    int lds;
     __device__ void operator()(int bx, int) const
     {
         if (bx >= ncols) return;
+        extern __shared__ double2 glk_tail_lds[];
         const BottomDesc<T> &D = *Dp;
         const int n = D.L[D.first].n, j = col0 + bx;
         C<T> *base = ws + (size_t)bx * ws_col;
+        C<T> *xs = reinterpret_cast<C<T> *>(glk_tail_lds);
         auto vec = [&](int l, int k) -> C<T> * {
+            if (lds && l == D.first && k == 1) return xs;
             size_t off = 0;
             for (int q = D.first; q < l; ++q) off += 3 * (size_t)D.L[q].n;
             return base + off + (size_t)k * D.L[l].n;
@@ -1146,10 +1152,16 @@ void form_tail(gl_precond *pre, hipStream_t s)
     const int nt = pre->L[pre->tail].n;
     const auto *D = reinterpret_cast<const BottomDesc<double> *>(pre->tdesc64.get());
     const Launch L{s};
+    int dev = 0, lmax = 0;
+    GLK_HIP(hipGetDevice(&dev));
+    GLK_HIP(hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t lds = (size_t)nt * sizeof(double2);
+    const bool use_lds = lds + 1024 <= (size_t)lmax;
     for (int c0 = 0; c0 < nt; c0 += pre->tws_cols) {
         const int nc = std::min(pre->tws_cols, nt - c0);
         L.run<TailColumns<double>, kBottomThreads>(
-            nc, TailColumns<double>{D, pre->tws.get(), pre->tws_col, c0, nc, pre->tinv64.get()});
+            nc, TailColumns<double>{D, pre->tws.get(), pre->tws_col, c0, nc, pre->tinv64.get(), use_lds ? 1 : 0},
+            use_lds ? (int)lds : 0);
     }
     const int64_t nn = (int64_t)nt * nt;
     L.run(blocks_for(nn), Narrow<float>{(int)nn, pre->tinv64.get(), pre->tinv32.get(), nullptr});
