@@ -46,8 +46,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "3e9cf1cdaa1ec611bb0325ec55bcc47e76eb11b5018b829e105baa5bb2d340c1",
-           8: 4962807.4, 2: 20219317.2}
+TRAFFIC = {"csrc_sha256": "59fe29bed8bc29095609a085e233e8bfbd856ee8570f1c61264b9db9d5453709",
+           8: 4961731.7, 2: 20221855.0}
 
 
 def csrc_fingerprint():
