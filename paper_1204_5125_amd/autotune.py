@@ -53,11 +53,26 @@ def _key(mesh, precision, max_coarse):
     return f"{dev}|dim{mesh.dim}|{'x'.join(str(n) for n in mesh.shape)}|p{precision}|mc{max_coarse}"
 
 
+# Tile sets also change the numeric setup (an explicit sub-cycle is formed at
+# every setup), so a candidate is charged its setup time spread over this many
+# iterations, a typical Jacobian solve (170-400 MINRES iterations on the
+# 1025^2 grid from a random-phase start, about 100 on the 129^3 grid).
+SETUP_AMORTIZED_OVER = 100
+
+
 def time_tiles(mesh, psi, pre, tiles, iters=24, reps=3):
     """Seconds per MINRES iteration of J(psi) with preconditioner `pre` under
-    `tiles`, over a fixed iteration count (rtol = 0)."""
+    `tiles`, over a fixed iteration count (rtol = 0), plus the numeric setup
+    time over SETUP_AMORTIZED_OVER iterations."""
     import torch
     glnk.gl_precond_set_tiles(pre, *tiles)
+    setup = float("inf")
+    for r in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pre.update(psi)
+        torch.cuda.synchronize()
+        setup = min(setup, time.perf_counter() - t0)
     b = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
     x = torch.empty_like(b)
     best = float("inf")
@@ -69,7 +84,7 @@ def time_tiles(mesh, psi, pre, tiles, iters=24, reps=3):
         torch.cuda.synchronize()
         if r:  # the first run builds the graph
             best = min(best, (time.perf_counter() - t0) / iters)
-    return best
+    return best + setup / SETUP_AMORTIZED_OVER
 
 
 def tune(mesh, psi, precision=glnk.GL_FP32, max_coarse=64, cache=None, candidates=None,

@@ -41,6 +41,9 @@ def test_tile_split_rule():
     assert autotune.split(info, (0, 0, 200000)) == (0, 1, 1)
     many = dict(info, ncolors=[2, 4, 4, 70, 5])                  # too many colours for the bottom kernel
     assert autotune.split(many, (0, 8192, 4096)) == (0, 4, 4)
+    cube = {"sizes": [2146689, 255871, 5592, 66], "ncolors": [2, 16, 31, 23]}  # 129^3
+    assert autotune.split(cube, (1, 64, 4096)) == (1, 3, 3)
+    assert autotune.split(cube, (1, 64, 8192)) == (1, 2, 2)      # the rule itself has no upper bound
 
 
 def test_autotune_picks_fastest_and_caches(tmp_path, monkeypatch):
