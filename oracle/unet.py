@@ -3,9 +3,9 @@
 Used only by the tests, by smoke() and by the benchmark's CPU baseline; the
 GPU path never imports it.
 
-The predictor is a convolutional U-Net on the vertex grid (north-star
-extension of the continuation in Sec. 4; the paper itself predicts with
-pseudo-arclength).  This module states the network in plain numpy, in the
+The predictor is a convolutional U-Net on the vertex grid (an extension
+beyond the paper of the continuation in Sec. 4; the paper itself predicts
+with pseudo-arclength).  This module states the network in plain numpy, in the
 order the computation is defined, so that the GPU kernels can be checked
 value by value:
 

@@ -1,5 +1,5 @@
-"""Learned Newton start for the mu-continuation (spec extension of the
-continuation in Sec. 4): the library's U-Net corrects the secant start.
+"""Learned Newton start for the mu-continuation (an extension beyond the paper
+of the continuation in Sec. 4): the library's U-Net corrects the secant start.
 Training data come from a seeded continuation sweep; training runs the
 library's own kernels; at run time the corrected start is used unless the
 plain secant start has the smaller GL residual.
