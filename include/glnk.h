@@ -184,7 +184,7 @@ void gl_precond_destroy(gl_precond *pre);
  *     explicit matrix at every setup, in FP64 by the bottom kernel's
  *     arithmetic applied to the unit vectors, and applied as one dense
  *     product; the same operator up to rounding, one dispatch in place of a
- *     few dozen latency-bound ones.  0 = off (default), else 1 .. 4096; the
+ *     few dozen latency-bound ones.  0 = off (default), else 1 .. 8192; the
  *     matrix takes 24 n^2 bytes (FP64 and FP32 copies).
  * Chosen by the autotuner per grid shape; cached iteration graphs of the
  * handle are rebuilt on their next use. */

@@ -16,8 +16,8 @@ constexpr int kMaxDense = 2048;   // largest coarsest level handled by the dense
 constexpr int kMaxRow = 512;      // longest row handled by the setup kernels
 constexpr int kMaxColors = 64;    // colours per level handled by the bottom kernel
 constexpr int kBottomRows = 512;  // levels up to this size go to the bottom kernel
-constexpr int kMaxTail = 4096;    // largest level whose sub-cycle is formed as a dense matrix
-constexpr int kTailCols = 512;    // columns of that matrix formed per launch
+constexpr int kMaxTail = 8192;    // largest level whose sub-cycle is formed as a dense matrix
+constexpr size_t kTailWorkspace = size_t(1536) << 20;  // bytes of per-column vectors while forming it
 
 struct Csr {
     int n = 0, m = 0, nnz = 0;  // rows, columns, entries
@@ -220,14 +220,15 @@ struct gl_precond {
     glk::DevBuf<double> pwn;       // setup: norms of the spectral-radius estimate
     glk::DevBuf<char> bdesc64, bdesc32;  // BottomDesc<double>, BottomDesc<float>
     // explicit sub-cycle of level `tail` (when above the coarsest): row-major
-    // n_tail x n_tail in the V-cycle's row order, formed by k_tail_columns
-    // from a descriptor of levels tail .. coarsest, a column per work-group
+    // n_tail x n_tail in the V-cycle's row order, formed by TailColumns
+    // from a descriptor of levels tail .. coarsest, a block of columns per
+    // work-group
     glk::DevBuf<double2> tinv64;
     glk::DevBuf<float2> tinv32;
-    glk::DevBuf<double2> tws;      // per-column vectors of that formation
+    glk::DevBuf<double2> tws;      // per-block vectors of that formation
     glk::DevBuf<char> tdesc64;
-    size_t tws_col = 0;            // elements per column of tws
-    int tws_cols = 0;              // columns per launch
+    size_t tws_col = 0;            // elements per block of columns in tws
+    int tws_cols = 0;              // blocks of columns per launch
     int lds64 = 0, lds32 = 0;      // dynamic LDS bytes of the bottom kernel
 };
 

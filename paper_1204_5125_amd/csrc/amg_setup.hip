@@ -1567,7 +1567,7 @@ gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles)
         if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 || tiles->bottom_rows > 65536 ||
             tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail)
             fail(GL_ERR_INVALID_ARGUMENT,
-                 "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..4096");
+                 "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..8192");
         const int rows = tiles->bottom_rows ? tiles->bottom_rows : kBottomRows;
         if (rows == pre->bottom_rows && tiles->lane_shift == pre->lane_shift && tiles->dense_rows == pre->dense_rows)
             return;

@@ -1262,7 +1262,7 @@ gl_status gl_batch_set_tiles(gl_batch *batch, int index, const gl_tiles *tiles)
             } else if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 ||
                        tiles->bottom_rows > 65536 || tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail) {
                 fail(GL_ERR_INVALID_ARGUMENT,
-                     "gl_batch_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..4096");
+                     "gl_batch_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..8192");
             }
             batch->tiles[i] = *tiles;
         }

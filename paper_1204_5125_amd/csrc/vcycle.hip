@@ -698,40 +698,177 @@ struct Bottom {
     }
 };
 
-// Columns col0 .. col0 + ncols - 1 of the explicit sub-cycle of level
-// D.first: work-group c runs bottom_cycle on the unit vector e_{col0 + c}
-// with vectors of its own (ws + c * ws_col: b, x, r of each level in turn;
-// with lds set, the iterate of level D.first lives in LDS instead, so the
-// gathers of its passes stay on the compute unit) and stores the result as
-// that column of the row-major n x n matrix out.
+// Block forms of the bottom kernel's steps, for forming an explicit sub-cycle
+// kTailBlock columns at a time: vectors are [n][kTailBlock] blocks (the
+// columns of a row contiguous), thread t works on row t / kTailBlock and
+// column t % kTailBlock, and the kTailBlock threads of a row read the same
+// matrix entries, so a level's matrix is read once per block of columns
+// instead of once per column.  A thread takes its row's entries in groups of
+// kTailUnroll, every gather of a group issued before any is used, and sums
+// them in order.  A null right-hand side stands for columns bid .. bid +
+// kTailBlock - 1 of the identity.
+constexpr int kTailBlock = 16;
+constexpr int kTailRows = kBottomThreads / kTailBlock;  // rows per round
+constexpr int kTailUnroll = 8;
+
+template <class T>
+__device__ __forceinline__ C<T> blk_rhs(const C<T> *b, int bid, int i, int c)
+{
+    return b ? b[(size_t)i * kTailBlock + c] : mk<T>(i == bid + c ? 1 : 0, 0);
+}
+
+// sum over k in [k0, k1) of v[k] x[idx[k]][c], skipping idx[k] == skip
+template <class T>
+__device__ __forceinline__ C<T> blk_row_sum(const int *idx, const C<T> *v, int k0, int k1, const C<T> *x, int c,
+                                            int skip)
+{
+    C<T> acc = mk<T>(0, 0);
+    int k = k0;
+    for (; k + kTailUnroll <= k1; k += kTailUnroll) {
+        int j[kTailUnroll];
+        C<T> a[kTailUnroll], xv[kTailUnroll];
+#pragma unroll
+        for (int u = 0; u < kTailUnroll; ++u) {
+            j[u] = idx[k + u];
+            a[u] = v[k + u];
+        }
+#pragma unroll
+        for (int u = 0; u < kTailUnroll; ++u) xv[u] = x[(size_t)j[u] * kTailBlock + c];
+#pragma unroll
+        for (int u = 0; u < kTailUnroll; ++u)
+            if (j[u] != skip) acc = cadd(acc, cmul(a[u], xv[u]));
+    }
+    for (; k < k1; ++k) {
+        const int jj = idx[k];
+        if (jj != skip) acc = cadd(acc, cmul(v[k], x[(size_t)jj * kTailBlock + c]));
+    }
+    return acc;
+}
+
+// one colour of a level, from its ELL block
+template <class T>
+__device__ __forceinline__ void blk_sgs_colour(const BottomLevel<T> &L, int colour, const C<T> *b, int bid, C<T> *x)
+{
+    const int cnt = L.coff[colour + 1] - L.coff[colour];
+    const int row0 = L.coff[colour];
+    const int W = L.ewidth[colour];
+    const int *eci = L.eci + L.eoff[colour];
+    const C<T> *ev = L.ev + L.eoff[colour];
+    const int c = threadIdx.x % kTailBlock;
+    for (int r = threadIdx.x / kTailBlock; r < cnt; r += kTailRows) {
+        const int i = row0 + r;
+        const C<T> bi = blk_rhs<T>(b, bid, i, c);
+        const size_t e0 = (size_t)r * W;
+        const C<T> acc = blk_row_sum<T>(eci + e0, ev + e0, 0, W, x, c, i);
+        x[(size_t)i * kTailBlock + c] = cscale(csub(bi, acc), (T)1 / L.diag[i]);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void blk_sgs(const BottomLevel<T> &L, const C<T> *b, int bid, C<T> *x)
+{
+    for (int t = 0; t < 2 * L.ncolors - 1; ++t) {
+        blk_sgs_colour<T>(L, t < L.ncolors ? t : 2 * L.ncolors - 2 - t, b, bid, x);
+        __syncthreads();
+    }
+}
+
+// MODE 0: y = M x, 1: y += M x, 2: y = b - M x
+template <class T, int MODE>
+__device__ __forceinline__ void blk_spmv(int nrows, const int *rp, const int *ci, const C<T> *v, const C<T> *x,
+                                         const C<T> *b, int bid, C<T> *y)
+{
+    const int c = threadIdx.x % kTailBlock;
+    for (int i = threadIdx.x / kTailBlock; i < nrows; i += kTailRows) {
+        const C<T> acc = blk_row_sum<T>(ci, v, rp[i], rp[i + 1], x, c, -1);
+        C<T> &yi = y[(size_t)i * kTailBlock + c];
+        if (MODE == 0) yi = acc;
+        else if (MODE == 1) yi = cadd(yi, acc);
+        else yi = csub(blk_rhs<T>(b, bid, i, c), acc);
+    }
+}
+
+// y = M b for a dense row-major n x n matrix
+template <class T>
+__device__ __forceinline__ void blk_dense(int n, const C<T> *M, const C<T> *b, C<T> *y)
+{
+    const int c = threadIdx.x % kTailBlock;
+    for (int i = threadIdx.x / kTailBlock; i < n; i += kTailRows) {
+        const C<T> *row = M + (size_t)i * n;
+        C<T> acc = mk<T>(0, 0);
+        int j = 0;
+        for (; j + kTailUnroll <= n; j += kTailUnroll) {
+            C<T> a[kTailUnroll], xv[kTailUnroll];
+#pragma unroll
+            for (int u = 0; u < kTailUnroll; ++u) {
+                a[u] = row[j + u];
+                xv[u] = b[(size_t)(j + u) * kTailBlock + c];
+            }
+#pragma unroll
+            for (int u = 0; u < kTailUnroll; ++u) acc = cadd(acc, cmul(a[u], xv[u]));
+        }
+        for (; j < n; ++j) acc = cadd(acc, cmul(row[j], b[(size_t)j * kTailBlock + c]));
+        y[(size_t)i * kTailBlock + c] = acc;
+    }
+}
+
+// The V-cycle over levels D.first .. D.last on kTailBlock identity columns
+// (the steps of bottom_cycle); vec(l, k): level l's b (k = 0, unused on
+// D.first), x (1) or r (2) block.
+template <class T, class V>
+__device__ __forceinline__ void blk_cycle(const BottomDesc<T> &D, V vec, int bid)
+{
+    for (int l = D.first; l < D.last; ++l) {
+        const BottomLevel<T> &L = D.L[l];
+        const C<T> *b = l == D.first ? nullptr : vec(l, 0);
+        C<T> *x = vec(l, 1), *r = vec(l, 2);
+        for (int t = threadIdx.x; t < L.n * kTailBlock; t += kBottomThreads) x[t] = mk<T>(0, 0);
+        __syncthreads();
+        blk_sgs<T>(L, b, bid, x);
+        blk_spmv<T, 2>(L.n, L.rp, L.ci, L.v, x, b, bid, r);
+        __syncthreads();
+        blk_spmv<T, 0>(L.nc, L.rrp, L.rci, L.rv, r, nullptr, 0, vec(l + 1, 0));
+        __syncthreads();
+    }
+    blk_dense<T>(D.L[D.last].n, D.cinv, vec(D.last, 0), vec(D.last, 1));
+    __syncthreads();
+    for (int l = D.last - 1; l >= D.first; --l) {
+        const BottomLevel<T> &L = D.L[l];
+        C<T> *x = vec(l, 1);
+        blk_spmv<T, 1>(L.n, L.prp, L.pci, L.pv, vec(l + 1, 1), nullptr, 0, x);
+        __syncthreads();
+        blk_sgs<T>(L, l == D.first ? nullptr : vec(l, 0), bid, x);
+    }
+}
+
+// Columns of the explicit sub-cycle of level D.first: work-group g forms
+// columns col0 + g kTailBlock .. + kTailBlock - 1 (those below n) with
+// blocks of its own (ws + g * ws_blk: b, x, r of each level in turn) and
+// stores them into the row-major n x n matrix out.
 template <class T>
 struct TailColumns {
     const BottomDesc<T> *Dp;
     C<T> *ws;
-    size_t ws_col;
-    int col0, ncols;
+    size_t ws_blk;
+    int col0, nblk;
     C<T> *out;
-    int lds;
     __device__ void operator()(int bx, int) const
     {
-        if (bx >= ncols) return;
-        extern __shared__ double2 glk_tail_lds[];
+        if (bx >= nblk) return;
         const BottomDesc<T> &D = *Dp;
-        const int n = D.L[D.first].n, j = col0 + bx;
-        C<T> *base = ws + (size_t)bx * ws_col;
-        C<T> *xs = reinterpret_cast<C<T> *>(glk_tail_lds);
+        const int n = D.L[D.first].n, bid = col0 + bx * kTailBlock;
+        C<T> *base = ws + (size_t)bx * ws_blk;
         auto vec = [&](int l, int k) -> C<T> * {
-            if (lds && l == D.first && k == 1) return xs;
             size_t off = 0;
             for (int q = D.first; q < l; ++q) off += 3 * (size_t)D.L[q].n;
-            return base + off + (size_t)k * D.L[l].n;
+            return base + (off + (size_t)k * D.L[l].n) * kTailBlock;
         };
-        C<T> *b = vec(D.first, 0);
-        for (int i = threadIdx.x; i < n; i += kBottomThreads) b[i] = mk<T>(i == j ? 1 : 0, 0);
-        __syncthreads();
-        bottom_cycle<T>(D, vec);
+        blk_cycle<T>(D, vec, bid);
         const C<T> *x = vec(D.first, 1);
-        for (int i = threadIdx.x; i < n; i += kBottomThreads) out[(size_t)i * n + j] = x[i];
+        for (int t = threadIdx.x; t < n * kTailBlock; t += kBottomThreads) {
+            const int i = t / kTailBlock, col = bid + t % kTailBlock;
+            if (col < n) out[(size_t)i * n + col] = x[t];
+        }
     }
 };
 
@@ -1108,8 +1245,10 @@ void bottom_descriptors(gl_precond *pre, hipStream_t s)
         pre->tinv32.alloc((size_t)nt * nt);
         size_t col = 0;
         for (int l = tail; l <= last; ++l) col += 3 * (size_t)pre->L[l].n;
-        pre->tws_col = (col + 31) / 32 * 32;
-        pre->tws_cols = std::min(nt, kTailCols);
+        pre->tws_col = col * kTailBlock;  // elements per block of columns
+        const int nblk = (nt + kTailBlock - 1) / kTailBlock;
+        const size_t fit = kTailWorkspace / (pre->tws_col * sizeof(double2));
+        pre->tws_cols = (int)std::max<size_t>(1, std::min<size_t>(nblk, fit));  // blocks per launch
         pre->tws.alloc(pre->tws_col * pre->tws_cols);
         // formation: levels tail .. coarsest with the coarsest inverse
         BottomDesc<double> dt;
@@ -1145,23 +1284,19 @@ void bottom_descriptors(gl_precond *pre, hipStream_t s)
 }
 
 // The explicit sub-cycle of level `tail` from the current values: FP64
-// columns, kTailCols work-groups per launch, then the FP32 copy.
+// columns, kTailBlock per work-group and as many work-groups per launch as
+// the workspace holds, then the FP32 copy.
 void form_tail(gl_precond *pre, hipStream_t s)
 {
     if (!pre->has_values || pre->tail >= pre->nlev - 1) return;
     const int nt = pre->L[pre->tail].n;
     const auto *D = reinterpret_cast<const BottomDesc<double> *>(pre->tdesc64.get());
     const Launch L{s};
-    int dev = 0, lmax = 0;
-    GLK_HIP(hipGetDevice(&dev));
-    GLK_HIP(hipDeviceGetAttribute(&lmax, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t lds = (size_t)nt * sizeof(double2);
-    const bool use_lds = lds + 1024 <= (size_t)lmax;
-    for (int c0 = 0; c0 < nt; c0 += pre->tws_cols) {
-        const int nc = std::min(pre->tws_cols, nt - c0);
+    const int nblk = (nt + kTailBlock - 1) / kTailBlock;
+    for (int b0 = 0; b0 < nblk; b0 += pre->tws_cols) {
+        const int nb = std::min(pre->tws_cols, nblk - b0);
         L.run<TailColumns<double>, kBottomThreads>(
-            nc, TailColumns<double>{D, pre->tws.get(), pre->tws_col, c0, nc, pre->tinv64.get(), use_lds ? 1 : 0},
-            use_lds ? (int)lds : 0);
+            nb, TailColumns<double>{D, pre->tws.get(), pre->tws_col, b0 * kTailBlock, nb, pre->tinv64.get()});
     }
     const int64_t nn = (int64_t)nt * nt;
     L.run(blocks_for(nn), Narrow<float>{(int)nn, pre->tinv64.get(), pre->tinv32.get(), nullptr});

@@ -298,7 +298,7 @@ def test_vcycle_and_solve_deeper_hierarchy(glnk, max_coarse):
                 pre.apply(dev(r), z)
                 assert relerr(host(z), ref) < tol, (dense, rows, prec, sizes)
     with pytest.raises(glnk.GlnkError):
-        glnk.gl_precond_set_tiles(pre, 0, 0, 4097)
+        glnk.gl_precond_set_tiles(pre, 0, 0, 8193)
     # the explicit sub-cycle with the values of a later setup (graphs keep
     # its address), then MINRES through it against the oracle
     glnk.gl_precond_set_tiles(pre, 0, 0, 4096)
