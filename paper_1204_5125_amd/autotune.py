@@ -15,7 +15,7 @@ import time
 
 from . import glnk
 
-CANDIDATES = [(ls, br, dr) for ls in (-1, 0, 1) for br in (64, 512, 2048, 8192) for dr in (0, 4096)]
+CANDIDATES = [(ls, br, dr) for ls in (-1, 0, 1) for br in (64, 512, 2048, 8192) for dr in (0, 4096, 8192)]
 # A batch runs many instances per dispatch: the launches an explicit
 # sub-cycle saves are shared there, its matrix reads are not, so batches
 # choose among the tile sets without one.
