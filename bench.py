@@ -46,8 +46,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "59fe29bed8bc29095609a085e233e8bfbd856ee8570f1c61264b9db9d5453709",
-           8: 4961731.7, 2: 20221855.0}
+TRAFFIC = {"csrc_sha256": "741e6f4bc81d851096dc820ca8a05a7dba3d4aceae8767bb331d5fbb6684789f",
+           8: 4953586.1, 2: 20218820.3}
 
 
 def csrc_fingerprint():
