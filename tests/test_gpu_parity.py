@@ -156,6 +156,18 @@ def test_vcycle(glnk, case):
     pre.update(dev(psi), precision=glnk.GL_FP64, cycles=3)
     pre.apply(dev(r), z)
     assert relerr(host(z), amg.precond(mo, r, cycles=3)) < 1e-11
+    # the cycle below level 1 as an explicit matrix (where the hierarchy has
+    # a level between level 1 and the coarsest), FP64, FP32 and k = 3 cycles
+    glnk.gl_precond_set_tiles(pre, 0, 64, 8192)
+    pre.update(dev(psi), precision=glnk.GL_FP64, cycles=1)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-11
+    pre.update(dev(psi), precision=glnk.GL_FP32)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-5
+    pre.update(dev(psi), precision=glnk.GL_FP64, cycles=3)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), amg.precond(mo, r, cycles=3)) < 1e-11
 
 
 @pytest.mark.parametrize("case", CASES, ids=IDS)
