@@ -492,19 +492,38 @@ __global__ void k_pw_start(int n, double2 *x, RedSlot slot)
     block_reduce_store(part, slot, sm, blockIdx.x);
 }
 
-// y = D^-1 A x / ||x|| (||x||^2 in *xn2), partial sums of |y|^2
+// y = D^-1 A x / ||x|| (||x||^2 in *xn2), partial sums of |y|^2; kPwLanes
+// lanes share a row (lane j takes entries j, j + kPwLanes, ... in order, then
+// a fixed butterfly), so long coarse rows are not one serial chain of gathers.
+// The grid is at most the partial-sum slot's size: a block strides over the
+// rows by the grid (the same iterations for all its threads) and stores one
+// partial.
+constexpr int kPwLanes = 8;
+
 __global__ void k_pw_step(int n, const int *rp, const int *ci, const double2 *v, const double *diag,
                           const double2 *x, const double *xn2, double2 *y, RedSlot slot)
 {
     __shared__ double sm[kBlock / 64];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int64_t total = (int64_t)n * kPwLanes;
+    const double scale = 1.0 / sqrt(*xn2);
     double part = 0.0;
-    if (i < n) {
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < total; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t g = base + threadIdx.x;
+        const int i = (int)(g / kPwLanes), lane = (int)(g % kPwLanes);
+        const bool act = g < total;
         double2 acc = make_double2(0.0, 0.0);
-        for (int p = rp[i]; p < rp[i + 1]; ++p) acc = cadd(acc, cmul(v[p], x[ci[p]]));
-        const double2 yi = cscale(acc, 1.0 / (diag[i] * sqrt(*xn2)));
-        y[i] = yi;
-        part = cabs2(yi);
+        if (act)
+            for (int p = rp[i] + lane; p < rp[i + 1]; p += kPwLanes) acc = cadd(acc, cmul(v[p], x[ci[p]]));
+#pragma unroll
+        for (int o = kPwLanes / 2; o > 0; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if (act && lane == 0) {
+            const double2 yi = cscale(acc, scale / diag[i]);
+            y[i] = yi;
+            part += cabs2(yi);
+        }
     }
     block_reduce_store(part, slot, sm, blockIdx.x);
 }
@@ -547,6 +566,8 @@ static void rho_estimate(gl_precond *pre, Level &L, hipStream_t s)
     launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm, nullptr, s);
     const bool l0 = &L == &pre->L[0];
     const GeomT<double> g = geom_t<double>(m->g);
+    // CSR levels: kPwLanes threads per row, at most one partial per level-0 block
+    const int nbl = std::min(blocks_for((int64_t)n * kPwLanes), blocks_for(m->g.n));
     for (int k = 1; k <= kRhoSteps; ++k) {
         const double *xn2 = nrm + ((k - 1) & 1);
         if (l0 && m->g.dim == 2)
@@ -554,9 +575,9 @@ static void rho_estimate(gl_precond *pre, Level &L, hipStream_t s)
         else if (l0)
             k_pw_step_l0<3><<<nb, kBlock, 0, s>>>(g, link_tab<double>(m), L.diag64.get(), x, xn2, y, slot);
         else
-            k_pw_step<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(), x, xn2,
-                                            y, slot);
-        launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm + (k & 1), nullptr, s);
+            k_pw_step<<<nbl, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(), x, xn2,
+                                             y, slot);
+        launch_finalize(slot.partials, l0 ? nb : nbl, FIN_STORE, nullptr, nrm + (k & 1), nullptr, s);
         std::swap(x, y);
     }
     k_pw_rho<<<1, 64, 0, s>>>(nrm + (kRhoSteps & 1), L.rho.get());
