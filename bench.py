@@ -46,8 +46,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "741e6f4bc81d851096dc820ca8a05a7dba3d4aceae8767bb331d5fbb6684789f",
-           8: 4953586.1, 2: 20218820.3}
+TRAFFIC = {"csrc_sha256": "4e9cf03d60f736fda81122fb5eb31d7881f328a576c6ccdeac382570767d9aed",
+           8: 4953587.3, 2: 20221792.5}
 
 
 def csrc_fingerprint():
