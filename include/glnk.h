@@ -185,7 +185,9 @@ void gl_precond_destroy(gl_precond *pre);
  *     arithmetic applied to the unit vectors, and applied as one dense
  *     product; the same operator up to rounding, one dispatch in place of a
  *     few dozen latency-bound ones.  0 = off (default), else 1 .. 8192; the
- *     matrix takes 24 n^2 bytes (FP64 and FP32 copies).
+ *     matrix takes 24 n^2 bytes (FP64 and FP32 copies) and its formation a
+ *     workspace of at most 1.5 GB (per-column vectors of every level from
+ *     that one down), all held by the handle.
  * Chosen by the autotuner per grid shape; cached iteration graphs of the
  * handle are rebuilt on their next use. */
 typedef struct {
