@@ -46,8 +46,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "4e9cf03d60f736fda81122fb5eb31d7881f328a576c6ccdeac382570767d9aed",
-           8: 4953587.3, 2: 20221792.5}
+TRAFFIC = {"csrc_sha256": "21bd4b65f4ced2984e2ece3b2d204a7158fcda1abefa78973b30af76c1c0a7dd",
+           8: 4953581.8, 2: 20218336.9}
 
 
 def csrc_fingerprint():

@@ -22,6 +22,7 @@ CANDIDATES = [(ls, br, dr) for ls in (-1, 0, 1) for br in (64, 512, 2048, 8192) 
 BATCH_CANDIDATES = [c for c in CANDIDATES if c[2] == 0]
 MAX_COLOURS = 64   # colours per level the bottom kernel handles
 DEFAULT_BOTTOM = 512
+BOTTOM_DENSE_ROWS = 512  # largest explicit sub-cycle the bottom kernel applies
 
 
 def split(info, tiles):
@@ -40,10 +41,11 @@ def split(info, tiles):
                     tail = lev
                 break
     first = tail
-    for lev in range(tail - 1, 0, -1):
-        if sizes[lev] > (br or DEFAULT_BOTTOM) or colours[lev] > MAX_COLOURS:
-            break
-        first = lev
+    if tail == last or sizes[tail] <= BOTTOM_DENSE_ROWS:
+        for lev in range(tail - 1, 0, -1):
+            if sizes[lev] > (br or DEFAULT_BOTTOM) or colours[lev] > MAX_COLOURS:
+                break
+            first = lev
     return ls, first, tail
 
 

@@ -16,6 +16,7 @@ constexpr int kMaxDense = 2048;   // largest coarsest level handled by the dense
 constexpr int kMaxRow = 512;      // longest row handled by the setup kernels
 constexpr int kMaxColors = 64;    // colours per level handled by the bottom kernel
 constexpr int kBottomRows = 512;  // levels up to this size go to the bottom kernel
+constexpr int kBottomDenseRows = 512;  // largest explicit sub-cycle the bottom kernel applies
 constexpr int kMaxTail = 8192;    // largest level whose sub-cycle is formed as a dense matrix
 constexpr size_t kTailWorkspace = size_t(1536) << 20;  // bytes of per-column vectors while forming it
 

@@ -1231,13 +1231,16 @@ void bottom_descriptors(gl_precond *pre, hipStream_t s)
     pre->tail = tail;
     // first level of the bottom kernel: the smallest l >= 1 from which every
     // level above the tail fits (size and colour count); a single-level
-    // hierarchy is just the dense solve on level 0
+    // hierarchy is just the dense solve on level 0.  One work-group applies
+    // an explicit sub-cycle only up to kBottomDenseRows rows: a larger one is
+    // a product for many work-groups, so no level goes to the bottom kernel.
     int first = tail;
-    for (int l = tail - 1; l >= 1; --l) {
-        const Level &L = pre->L[l];
-        if (L.n > pre->bottom_rows || L.ncolors > kMaxColors) break;
-        first = l;
-    }
+    if (tail == last || pre->L[tail].n <= kBottomDenseRows)
+        for (int l = tail - 1; l >= 1; --l) {
+            const Level &L = pre->L[l];
+            if (L.n > pre->bottom_rows || L.ncolors > kMaxColors) break;
+            first = l;
+        }
     pre->bottom = first;
     if (tail < last) {
         const int nt = pre->L[tail].n;

@@ -36,7 +36,11 @@ def test_tile_split_rule():
     assert autotune.split(info, (1, 2048, 0)) == (1, 4, 4)
     assert autotune.split(info, (1, 2048, 4096)) == (1, 3, 3)
     assert autotune.split(info, (0, 8192, 0)) == (0, 3, 4)
-    assert autotune.split(info, (0, 65536, 4096)) == (0, 2, 3)
+    # a 2181-row sub-cycle is too large for the one-work-group bottom kernel
+    assert autotune.split(info, (0, 65536, 4096)) == (0, 3, 3)
+    small = {"sizes": [16641, 2827, 318, 40], "ncolors": [2, 4, 6, 7]}  # 129^2, max_coarse 64
+    assert autotune.split(small, (0, 65536, 512)) == (0, 1, 2)
+    assert autotune.split(small, (0, 65536, 4096)) == (0, 1, 1)
     assert autotune.split(info, (0, 0, 100)) == (0, 4, 4)      # no level above the coarsest small enough
     assert autotune.split(info, (0, 0, 200000)) == (0, 1, 1)
     many = dict(info, ncolors=[2, 4, 4, 70, 5])                  # too many colours for the bottom kernel
