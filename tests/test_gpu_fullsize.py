@@ -1,0 +1,122 @@
+"""Parity at the full size and in the launch configuration of the Jacobian-solve
+benchmark: the 1025 x 1025 grid (side 10, mu 1, psi0 = 0.9 e^{i theta} with
+seed 0), preconditioner with max_coarse 512 and the tiles the benchmark times
+(lane_shift 0, bottom_rows 64, dense_rows 4096, so the 2 181-row level runs as
+an explicit sub-cycle).  The oracle handles every check here in seconds:
+operators over all nodes, the hierarchy, one V-cycle and the first Newton
+step's solve (16 MINRES iterations).  Tolerances as in test_gpu_parity.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_5125_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N, SIDE, MU, MAX_COARSE, TILES = (1025, 1025), (10.0, 10.0), 1.0, 512, (0, 64, 4096)
+
+
+@pytest.fixture(scope="module")
+def glnk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_5125_amd import glnk as g
+    g.lib()
+    return g
+
+
+@pytest.fixture(scope="module")
+def setup(glnk):
+    mg = glnk.Mesh(2, N, SIDE, mu=MU)
+    mo = oracle.Mesh(2, N, SIDE, mu=MU)
+    psi = inputs.random_phase_state(mo.n, seed=0)
+    amg = oracle.Amg.for_state(mo, psi, max_coarse=MAX_COARSE)
+    return mg, mo, psi, amg
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def test_operators_full_size(glnk, setup):
+    mg, mo, psi, _ = setup
+    phi = inputs.random_complex(mo.n, seed=21)
+    out = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    nrm = glnk.gl_residual(mg, dev(psi), out)
+    ref = mo.gl(psi)
+    assert relerr(host(out), ref) < 1e-12
+    assert nrm == pytest.approx(mo.norm(ref), rel=1e-12)
+    glnk.gl_jacobian_apply(mg, dev(psi), dev(phi), out)
+    assert relerr(host(out), mo.jac(psi, phi)) < 1e-12
+
+
+def test_hierarchy_and_vcycle_full_size(glnk, setup):
+    """Every integer array of the hierarchy bit for bit and its values within
+    1e-12; then R_1 r in the benchmark's tiles, FP64 within 1e-11 and FP32
+    within 1e-5 of the oracle's recursive V-cycle."""
+    mg, mo, psi, amg = setup
+    pre = glnk.Precond(mg, dev(psi), max_coarse=MAX_COARSE)
+    info = pre.info()
+    assert info["sizes"] == [L["n"] for L in amg.levels]
+    for l, L in enumerate(amg.levels):
+        assert np.array_equal(pre.export(l, "color"), L["color"])
+        assert np.array_equal(pre.export(l, "A_rp"), L["A"].indptr)
+        assert np.array_equal(pre.export(l, "A_ci"), L["A"].indices)
+        assert relerr(pre.export(l, "A_v"), L["A"].data) < 1e-12
+        if l < amg.nlev - 1:
+            assert np.array_equal(pre.export(l, "agg"), L["agg"])
+            assert np.array_equal(pre.export(l, "root"), L["root"])
+            for M in ("P", "R"):
+                assert np.array_equal(pre.export(l, M + "_ci"), L[M].indices)
+                assert relerr(pre.export(l, M + "_v"), L[M].data) < 1e-12
+    glnk.gl_precond_set_tiles(pre, *TILES)
+    r = inputs.random_complex(mo.n, seed=22)
+    ref = amg.precond(mo, r)
+    z = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    pre.update(dev(psi), precision=glnk.GL_FP64)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-11
+    pre.update(dev(psi), precision=glnk.GL_FP32)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-5
+
+
+def test_first_newton_solve_full_size(glnk, setup):
+    """J(psi0) dx = -GL(psi0) to 1e-10 in the benchmark's tiles.  FP64 V-cycle:
+    the same MINRES iterates as the oracle's (iterations within 1, solution
+    within 1e-8 of the oracle's 1e-10 solve).  FP32 V-cycle under FP64
+    refinement, a different iteration: its true residual, checked with the
+    oracle's Jacobian, is below 1e-9, and its solution is within 1e-6 of the
+    oracle's 1e-12 solve.  That bound is the residual times the condition of
+    this system: the FP64 solve at 1e-10 is 1.1e-7 from the 1e-12 one."""
+    mg, mo, psi, amg = setup
+    b = -mo.gl(psi)
+    xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-10, max_iter=200)
+    xe, ie, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-12, max_iter=400)
+    assert io["converged"] and ie["converged"]
+    pre = glnk.Precond(mg, dev(psi), max_coarse=MAX_COARSE)
+    glnk.gl_precond_set_tiles(pre, *TILES)
+    pre.update(dev(psi), precision=glnk.GL_FP64)
+    x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=200)
+    assert rc == 0 and ig["converged"]
+    assert abs(ig["iterations"] - io["iterations"]) <= 1
+    assert relerr(host(x), xo) < 1e-8
+    pre.update(dev(psi), precision=glnk.GL_FP32)
+    rc, i32 = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=400)
+    assert rc == 0 and i32["converged"] and i32["res_true"] < 1e-9
+    xs = host(x)
+    assert mo.norm(mo.jac(psi, xs) - b) < 1e-9 * mo.norm(b)
+    assert relerr(xs, xe) < 1e-6
