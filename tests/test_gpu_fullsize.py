@@ -1,10 +1,12 @@
 """Parity at the full size and in the launch configuration of the Jacobian-solve
-benchmark: the 1025 x 1025 grid (side 10, mu 1, psi0 = 0.9 e^{i theta} with
+benchmarks: the 1025 x 1025 grid (side 10, mu 1, psi0 = 0.9 e^{i theta} with
 seed 0), preconditioner with max_coarse 512 and the tiles the benchmark times
 (lane_shift 0, bottom_rows 64, dense_rows 4096, so the 2 181-row level runs as
 an explicit sub-cycle).  The oracle handles every check here in seconds:
 operators over all nodes, the hierarchy, one V-cycle and the first Newton
-step's solve (16 MINRES iterations).  Tolerances as in test_gpu_parity.
+step's solve (16 MINRES iterations).  The same for the 129^3 cube, whose
+5 592-row level runs as an explicit sub-cycle.  Tolerances as in
+test_gpu_parity.
 """
 import numpy as np
 import pytest
@@ -120,3 +122,53 @@ def test_first_newton_solve_full_size(glnk, setup):
     xs = host(x)
     assert mo.norm(mo.jac(psi, xs) - b) < 1e-9 * mo.norm(b)
     assert relerr(xs, xe) < 1e-6
+
+
+# the 3D benchmark: 129^3 cube, side 5, mu 0.6 along (1, 1, 1)/sqrt 3, tiles
+# (0, 64, 8192) (its 5 592-row level as an explicit sub-cycle)
+CN, CSIDE, CMU, CTILES = (129, 129, 129), (5.0, 5.0, 5.0), 0.6, (0, 64, 8192)
+CB = tuple(np.ones(3) / np.sqrt(3))
+
+
+@pytest.fixture(scope="module")
+def cube(glnk):
+    mg = glnk.Mesh(3, CN, CSIDE, mu=CMU, b_dir=CB)
+    mo = oracle.Mesh(3, CN, CSIDE, mu=CMU, bdir=CB)
+    psi = inputs.random_phase_state(mo.n, seed=0)
+    amg = oracle.Amg.for_state(mo, psi, max_coarse=MAX_COARSE)
+    return mg, mo, psi, amg
+
+
+def test_cube_full_size(glnk, cube):
+    """129^3: the hierarchy bit-exact (values within 1e-12), R_1 r through the
+    explicit sub-cycle of the 5 592-row level within 1e-11 (FP64) and 1e-5
+    (FP32), and the first Newton step's FP64 solve with the oracle's MINRES
+    iterates (iterations within 1, solution within 1e-8)."""
+    mg, mo, psi, amg = cube
+    pre = glnk.Precond(mg, dev(psi), max_coarse=MAX_COARSE)
+    assert pre.info()["sizes"] == [L["n"] for L in amg.levels]
+    for l, L in enumerate(amg.levels):
+        assert np.array_equal(pre.export(l, "color"), L["color"])
+        assert np.array_equal(pre.export(l, "A_ci"), L["A"].indices)
+        assert relerr(pre.export(l, "A_v"), L["A"].data) < 1e-12
+        if l < amg.nlev - 1:
+            assert np.array_equal(pre.export(l, "agg"), L["agg"])
+    glnk.gl_precond_set_tiles(pre, *CTILES)
+    r = inputs.random_complex(mo.n, seed=23)
+    ref = amg.precond(mo, r)
+    z = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    pre.update(dev(psi), precision=glnk.GL_FP64)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-11
+    pre.update(dev(psi), precision=glnk.GL_FP32)
+    pre.apply(dev(r), z)
+    assert relerr(host(z), ref) < 1e-5
+    b = -mo.gl(psi)
+    xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-10, max_iter=200)
+    assert io["converged"]
+    pre.update(dev(psi), precision=glnk.GL_FP64)
+    x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=200)
+    assert rc == 0 and ig["converged"]
+    assert abs(ig["iterations"] - io["iterations"]) <= 1
+    assert relerr(host(x), xo) < 1e-8
