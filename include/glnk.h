@@ -114,6 +114,19 @@ void gl_mesh_destroy(gl_mesh *mesh);
 gl_status gl_residual(const gl_mesh *mesh, const void *psi, void *out, double *norm_D,
                       gl_stream stream);
 
+/* gl_residual without any device allocation or library-held reduction
+ * buffer, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, results and errors as gl_residual (bitwise the same
+ * output and norm).  Its block partial sums and its result live in one
+ * static device array per GPU (513 KiB, held until the process ends), so
+ * meshes of at most 2^24 = 16,777,216 nodes are accepted (INVALID_ARGUMENT
+ * beyond).  Calls that overlap on one GPU, on any streams or threads, share
+ * that array and race; serialise them.  Nothing in the array needs clearing
+ * between calls. */
+gl_status gl_residual_noalloc(const gl_mesh *mesh, const void *psi, void *out, double *norm_D,
+                              gl_stream stream);
+
 /* out = J(psi) phi (discrete Jacobian, Sec. 3).  out aliases neither input. */
 gl_status gl_jacobian_apply(const gl_mesh *mesh, const void *psi, const void *phi, void *out,
                             gl_stream stream);

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "amg.h"
 #include "stencil.h"
@@ -169,6 +170,37 @@ void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, dou
     });
     GLK_CHECK_LAUNCH();
     launch_finalize(red_slot(m, 0).partials, nb, FIN_STORE, nullptr, dresult, nullptr, s);
+}
+
+// ------------------------------------- GL residual without allocation ---
+// gl_residual_noalloc keeps its block partial sums and its result in this
+// file-scope device array instead of the mesh's reduction buffers.  Each GPU
+// the library runs on holds its own copy until the process ends.  In host
+// code `scratch` names a host-side stand-in, never the device memory: the
+// device address comes from hipGetSymbolAddress, once per device, and only
+// that address is passed to kernels.
+constexpr int kNoAllocParts = 1 << 16;  // block partials: n <= 2^16 * 256 nodes
+constexpr int kNoAllocSlots = kNoAllocParts + 64;
+static __device__ __align__(256) double scratch[kNoAllocSlots];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on first use).
+static double *scratch_on_current_device()
+{
+    int dev = -1;
+    GLK_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) fail(GL_ERR_UNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        GLK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(GL_ERR_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    return g_scratch_ptr[dev];
 }
 
 // ---------------------------------------------------- Jacobian apply ---
@@ -438,6 +470,40 @@ gl_status gl_residual(const gl_mesh *mesh, const void *psi, void *out, double *n
             GLK_HIP(hipMemcpyAsync(mesh->hscal, mesh->dscal.get(), sizeof(double), hipMemcpyDeviceToHost, s));
             GLK_HIP(hipStreamSynchronize(s));
             *norm_D = std::sqrt(mesh->hscal[0]);
+        }
+    });
+}
+
+gl_status gl_residual_noalloc(const gl_mesh *mesh, const void *psi, void *out, double *norm_D,
+                              gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !psi) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual_noalloc: NULL mesh or psi");
+        if (out == psi) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual_noalloc: out aliases psi");
+        const int nb = blocks_for(mesh->g.n);
+        if (nb > kNoAllocParts)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_residual_noalloc: more than " +
+                                              std::to_string((int64_t)kNoAllocParts * kBlock) + " nodes");
+        double *sc = scratch_on_current_device();
+        hipStream_t s = as_stream(stream);
+        // every partial is written by its block and the result by the
+        // finalisation, so nothing has to be cleared between calls
+        const GeomT<double> g = geom_t<double>(mesh->g);
+        const LinkTab<double> U = link_tab<double>(mesh);
+        const RedSlot slot{sc};
+        if (mesh->g.dim == 2)
+            k_gl_residual<2><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, U, (double2 *)out, slot);
+        else
+            k_gl_residual<3><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, U, (double2 *)out, slot);
+        GLK_CHECK_LAUNCH();
+        double *res = sc + kNoAllocParts;
+        launch_finalize(sc, nb, FIN_STORE, nullptr, res, nullptr, Launch{s});
+        GLK_CHECK_LAUNCH();
+        if (norm_D) {
+            double v = 0.0;
+            GLK_HIP(hipMemcpyAsync(&v, res, sizeof(double), hipMemcpyDeviceToHost, s));
+            GLK_HIP(hipStreamSynchronize(s));
+            *norm_D = std::sqrt(v);
         }
     });
 }

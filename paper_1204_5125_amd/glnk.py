@@ -25,7 +25,7 @@ EXPORT = {"agg": 0, "root": 1, "color": 2, "A_rp": 3, "A_ci": 4, "A_v": 5, "P_rp
 
 EXPORTED_SYMBOLS = [
     "gl_mesh_create_grid", "gl_mesh_set_field", "gl_mesh_num_nodes", "gl_mesh_export_links",
-    "gl_mesh_destroy", "gl_residual", "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
+    "gl_mesh_destroy", "gl_residual", "gl_residual_noalloc", "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
     "gl_precond_apply",
     "gl_precond_info", "gl_precond_export", "gl_precond_destroy", "gl_jacobian_solve",
     "gl_newton_solve", "gl_precond_set_tiles", "gl_precond_get_tiles", "gl_batch_create",
@@ -103,6 +103,7 @@ def lib():
     L.gl_mesh_destroy.argtypes = [vp]
     L.gl_mesh_destroy.restype = None
     L.gl_residual.argtypes = [vp, vp, vp, P(C.c_double), vp]
+    L.gl_residual_noalloc.argtypes = [vp, vp, vp, P(C.c_double), vp]
     L.gl_jacobian_apply.argtypes = [vp, vp, vp, vp, vp]
     L.gl_secant_predict.argtypes = [vp, vp, vp, C.c_double, vp, vp]
     L.gl_precond_setup.argtypes = [vp, vp, P(AmgOpts), P(vp), vp]
@@ -223,6 +224,16 @@ def gl_residual(mesh, psi, out=None, norm=True, stream=None):
     _check(lib().gl_residual(mesh.handle, _vec(psi, mesh.n, "psi"),
                              _vec(out, mesh.n, "out") if out is not None else None,
                              C.byref(nd) if norm else None, _stream(stream)), "gl_residual")
+    return nd.value if norm else None
+
+
+def gl_residual_noalloc(mesh, psi, out=None, norm=True, stream=None):
+    """gl_residual with its reduction scratch in the library's static device
+    array (no allocation); returns ||GL(psi)||_D when norm is True."""
+    nd = C.c_double()
+    _check(lib().gl_residual_noalloc(mesh.handle, _vec(psi, mesh.n, "psi"),
+                                     _vec(out, mesh.n, "out") if out is not None else None,
+                                     C.byref(nd) if norm else None, _stream(stream)), "gl_residual_noalloc")
     return nd.value if norm else None
 
 
