@@ -79,18 +79,29 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
+def _mix(Wt, x):
+    """sum_i Wt[o, i] x[i, h, w] (a channel mixing, as one matrix product)."""
+    ci, H, Wd = x.shape
+    return (Wt @ x.reshape(ci, H * Wd)).reshape(Wt.shape[0], H, Wd)
+
+
+def _corr(a, b):
+    """sum_{h,w} a[o, h, w] b[i, h, w] (as one matrix product)."""
+    return a.reshape(a.shape[0], -1) @ b.reshape(b.shape[0], -1).T
+
+
 def conv(x, W, b):
     """x (ci, H, W); W (co, k, k, ci); zero padding, same size."""
     co, k, _, ci = W.shape
     H, Wd = x.shape[1:]
     if k == 1:
-        return np.einsum("oi,ihw->ohw", W[:, 0, 0, :], x) + b[:, None, None]
+        return _mix(W[:, 0, 0, :], x) + b[:, None, None]
     xp = np.zeros((ci, H + 2, Wd + 2))
     xp[:, 1:-1, 1:-1] = x
     out = np.zeros((co, H, Wd)) + b[:, None, None]
     for ky in range(3):
         for kx in range(3):
-            out += np.einsum("oi,ihw->ohw", W[:, ky, kx, :], xp[:, ky:ky + H, kx:kx + Wd])
+            out += _mix(W[:, ky, kx, :], xp[:, ky:ky + H, kx:kx + Wd])
     return out
 
 
@@ -101,8 +112,8 @@ def conv_backward(x, W, dout):
     H, Wd = x.shape[1:]
     db = dout.sum(axis=(1, 2))
     if k == 1:
-        dW = np.einsum("ohw,ihw->oi", dout, x)[:, None, None, :]
-        dx = np.einsum("oi,ohw->ihw", W[:, 0, 0, :], dout)
+        dW = _corr(dout, x)[:, None, None, :]
+        dx = _mix(W[:, 0, 0, :].T, dout)
         return dx, dW, db
     xp = np.zeros((ci, H + 2, Wd + 2))
     xp[:, 1:-1, 1:-1] = x
@@ -110,8 +121,8 @@ def conv_backward(x, W, dout):
     dxp = np.zeros_like(xp)
     for ky in range(3):
         for kx in range(3):
-            dW[:, ky, kx, :] = np.einsum("ohw,ihw->oi", dout, xp[:, ky:ky + H, kx:kx + Wd])
-            dxp[:, ky:ky + H, kx:kx + Wd] += np.einsum("oi,ohw->ihw", W[:, ky, kx, :], dout)
+            dW[:, ky, kx, :] = _corr(dout, xp[:, ky:ky + H, kx:kx + Wd])
+            dxp[:, ky:ky + H, kx:kx + Wd] += _mix(W[:, ky, kx, :].T, dout)
     return dxp[:, 1:-1, 1:-1], dW, db
 
 

@@ -278,6 +278,52 @@ def test_vcycle_hermitian_positive_definite_contracting():
     assert rho < 0.5
 
 
+def dense_vcycle(amg, l):
+    """The V-cycle of level l as a dense matrix, restated from its definition
+    (Sec. 4.1: one pre- and one post-smoothing symmetric Gauss-Seidel sweep
+    around the coarse correction): with S = (D+U)^-1 D (D+L)^-1 in the colour
+    order (one sweep, x += S (b - A x)), x1 = S b, x2 = x1 + P B_{l+1} R (b - A x1),
+    x3 = x2 + S (b - A x2); the last level is A^-1.  Uses only the stored
+    operators, transfers and colours."""
+    L = amg.levels[l]
+    A = L["A"].toarray()
+    n = A.shape[0]
+    if l == amg.nlev - 1:
+        return np.linalg.inv(A)
+    perm = np.argsort(L["color"], kind="stable")
+    Ap = A[np.ix_(perm, perm)]
+    Dg = np.diag(np.diag(Ap))
+    Sp = np.linalg.solve(Dg + np.triu(Ap, 1), Dg @ np.linalg.inv(Dg + np.tril(Ap, -1)))
+    S = np.zeros_like(Sp)
+    S[np.ix_(perm, perm)] = Sp
+    P, R = L["P"].toarray(), L["R"].toarray()
+    Bc = dense_vcycle(amg, l + 1)
+    I = np.eye(n)
+    X1 = S
+    X2 = X1 + P @ Bc @ R @ (I - A @ X1)
+    return X2 + S @ (I - A @ X2)
+
+
+@pytest.mark.parametrize("grid,max_coarse", [((17, 17), 8), ((13, 11), 6), ((7, 6, 5), 6)])
+def test_deep_vcycle_operator(grid, max_coarse):
+    """A hierarchy of at least three levels: the oracle's recursive V-cycle
+    (columns from unit vectors) equals the dense restatement of the cycle,
+    and it is Hermitian and positive definite (it is the preconditioner of
+    MINRES, Sec. 4) with a contracting error propagator I - V H."""
+    dim = len(grid)
+    m = oracle.Mesh(dim, grid, (5.0,) * dim, mu=0.8, bdir=(0.3, 0.5, 1.0) if dim == 3 else (0, 0, 1))
+    psi = inputs.random_phase_state(m.n, seed=7)
+    amg = oracle.Amg.for_state(m, psi, max_coarse=max_coarse)
+    assert amg.nlev >= 3
+    V = vcycle_matrix(amg, m.n)
+    Vd = dense_vcycle(amg, 0)
+    assert np.abs(V - Vd).max() < 1e-12 * np.abs(Vd).max()
+    assert np.abs(V - V.conj().T).max() < 1e-12 * np.abs(V).max()
+    assert np.linalg.eigvalsh(0.5 * (V + V.conj().T)).min() > 0
+    H = m.hmat(psi).toarray()
+    assert np.abs(np.linalg.eigvals(np.eye(m.n) - V @ H)).max() < 1.0
+
+
 def test_single_level_is_exact_inverse():
     """A hierarchy with one level solves the coarse problem by Cholesky, i.e.
     applies H^-1 exactly."""
