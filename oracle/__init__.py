@@ -89,8 +89,9 @@ def lib():
                                  C.c_double, C.c_int, vp, C.POINTER(_KInfo)]
         L.orc_minres_generic.argtypes = [C.c_int64, vp, _OP, vp, _OP, vp, vp, vp, C.c_double,
                                          C.c_int, vp, C.POINTER(_KInfo)]
+        L.orc_minres_deflated.argtypes = L.orc_minres.argtypes
         L.orc_newton.argtypes = [C.POINTER(_Mesh), vp, C.c_double, C.c_int, C.c_int, C.c_double,
-                                 C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_NInfo)]
+                                 C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_NInfo)]
         _lib = L
     return _lib
 
@@ -269,15 +270,17 @@ def _kinfo(ki):
             "eta": ki.eta, "res_true": ki.res_true}
 
 
-def minres(mesh, psi, b, amg=None, cycles=1, rtol=1e-10, max_iter=1000):
+def minres(mesh, psi, b, amg=None, cycles=1, rtol=1e-10, max_iter=1000, deflate=False):
     """MINRES for J(psi) x = b in the D-weighted real product, preconditioned
-    by R_k = AMG_k(H, D .) when amg is given.  Returns (x, info, history)."""
+    by R_k = AMG_k(H, D .) when amg is given; with deflate, on the complement
+    of the gauge mode i psi (orc_minres_deflated).  Returns (x, info, history)."""
     psi, b = _c128(psi), _c128(b)
     x = np.empty_like(b)
     hist = np.zeros(max_iter + 1)
     ki = _KInfo()
-    rc = lib().orc_minres(mesh._p, _ptr(psi), amg._p if amg is not None else None, cycles,
-                          _ptr(b), _ptr(x), rtol, max_iter, _ptr(hist), C.byref(ki))
+    fn = lib().orc_minres_deflated if deflate else lib().orc_minres
+    rc = fn(mesh._p, _ptr(psi), amg._p if amg is not None else None, cycles,
+            _ptr(b), _ptr(x), rtol, max_iter, _ptr(hist), C.byref(ki))
     info = _kinfo(ki)
     info["status"] = rc
     return x, info, hist[:ki.iterations + 1].copy()
@@ -310,12 +313,13 @@ def minres_generic(w, A, b, minv=None, rtol=1e-10, max_iter=1000):
 
 
 def newton(mesh, psi0, tol=1e-10, max_steps=50, fixed_steps=0, krylov_rtol=1e-10,
-           krylov_max_iter=1000, use_amg=True, cycles=1, max_coarse=64):
-    """Newton for GL(psi) = 0 with MINRES + R_k inner solves (Sec. 2, Sec. 4)."""
+           krylov_max_iter=1000, use_amg=True, cycles=1, max_coarse=64, deflate=False):
+    """Newton for GL(psi) = 0 with MINRES + R_k inner solves (Sec. 2, Sec. 4);
+    with deflate, each step is solved on the complement of i psi."""
     psi = _c128(psi0).copy()
     ni = _NInfo()
     rc = lib().orc_newton(mesh._p, _ptr(psi), tol, max_steps, fixed_steps, krylov_rtol,
-                          krylov_max_iter, int(use_amg), cycles, max_coarse, C.byref(ni))
+                          krylov_max_iter, int(use_amg), cycles, max_coarse, int(deflate), C.byref(ni))
     info = {"status": rc, "steps": ni.steps, "converged": bool(ni.converged),
             "res": list(ni.res[:ni.steps + 1]), "krylov_iters": list(ni.krylov_iters[:ni.steps])}
     return psi, info

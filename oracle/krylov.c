@@ -126,10 +126,76 @@ int orc_minres(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycle
     return rc;
 }
 
+/* ------------------------------------ solve on the complement of i psi --- */
+/* Near a solution J(psi) is nearly singular along the gauge mode i psi
+ * (eq. jacobian nullspace: exactly singular at a solution); Sec. 3 names
+ * deflation among the remedies for such systems.  Reading: MINRES restricted
+ * to the <.,.>_R-orthogonal complement of u = i psi, i.e. applied to the
+ * self-adjoint operator Pi J Pi, the right-hand side Pi b and the
+ * preconditioner Pi R_k Pi, with Pi x = x - u <u, x>_R / <u, u>_R the
+ * orthogonal projector.  x0 = 0 lies in the complement and so does every
+ * iterate (each is a combination of preconditioner outputs). */
+typedef struct {
+    const orc_mesh *m;
+    const cplx *u;
+    double uu;
+    orc_op op;
+    void *ctx;
+    cplx *tmp;
+} defl_ctx;
+
+static void project(const orc_mesh *m, const cplx *u, double uu, cplx *x)
+{
+    if (!(uu > 0.0)) return;
+    const double s = orc_inner(m, u, x) / uu;
+    for (int64_t i = 0; i < m->n; ++i) x[i] -= s * u[i];
+}
+
+/* y = Pi op(Pi x) */
+static void projected_op(void *ctx, const cplx *x, cplx *y)
+{
+    defl_ctx *c = ctx;
+    memcpy(c->tmp, x, (size_t)c->m->n * sizeof(cplx));
+    project(c->m, c->u, c->uu, c->tmp);
+    c->op(c->ctx, c->tmp, y);
+    project(c->m, c->u, c->uu, y);
+}
+
+int orc_minres_deflated(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycles,
+                        const cplx *b, cplx *x, double rtol, int max_iter,
+                        double *hist, orc_krylov_info *info)
+{
+    const int64_t n = m->n;
+    const size_t bytes = (size_t)n * sizeof(cplx);
+    cplx *u = malloc(bytes), *pb = malloc(bytes), *r = malloc(bytes);
+    for (int64_t i = 0; i < n; ++i) u[i] = I * psi[i];
+    const double uu = orc_inner(m, u, u);
+    memcpy(pb, b, bytes);
+    project(m, u, uu, pb);
+    jac_ctx jc = {m, psi};
+    pre_ctx pc = {m, amg, cycles < 1 ? 1 : cycles, NULL};
+    if (amg) pc.tmp = malloc(bytes);
+    defl_ctx dj = {m, u, uu, jac_op, &jc, malloc(bytes)};
+    defl_ctx dm = {m, u, uu, pre_op, &pc, malloc(bytes)};
+    int rc = orc_minres_generic(n, m->vol, projected_op, &dj, amg ? projected_op : NULL, &dm, pb, x,
+                                rtol, max_iter, hist, info);
+    /* without a preconditioner the iterates are combinations of Pi-images
+     * already; project once more so that x is in the complement to rounding */
+    project(m, u, uu, x);
+    orc_jac(m, psi, x, r);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
+    project(m, u, uu, r);
+    double nb = sqrt(orc_inner(m, pb, pb));
+    info->res_true = nb > 0 ? sqrt(orc_inner(m, r, r)) / nb : 0.0;
+    free(pc.tmp); free(dj.tmp); free(dm.tmp);
+    free(u); free(pb); free(r);
+    return rc;
+}
+
 /* ----------------------------------------------------------- Newton --- */
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               int max_coarse, orc_newton_info *info)
+               int max_coarse, int deflate, orc_newton_info *info)
 {
     const int64_t n = m->n;
     cplx *r = malloc((size_t)n * sizeof(cplx)), *b = malloc((size_t)n * sizeof(cplx));
@@ -155,7 +221,8 @@ int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixe
         }
         for (int64_t i = 0; i < n; ++i) b[i] = -r[i];
         orc_krylov_info ki;
-        int krc = orc_minres(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, NULL, &ki);
+        int krc = deflate ? orc_minres_deflated(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, NULL, &ki)
+                          : orc_minres(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, NULL, &ki);
         orc_amg_free(amg);
         if (krc != ORC_OK && krc != ORC_ERR_NOT_CONVERGED) { rc = krc; break; }
         for (int64_t i = 0; i < n; ++i) psi[i] += dx[i];

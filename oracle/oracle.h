@@ -127,6 +127,15 @@ int orc_minres_generic(int64_t n, const double *w, orc_op A, void *actx, orc_op 
                        void *mctx, const cplx *b, cplx *x, double rtol, int max_iter,
                        double *hist, orc_krylov_info *info);
 
+/* Solve J(psi) x = b on the <.,.>_R-orthogonal complement of the gauge mode
+ * u = i psi: MINRES (as orc_minres) on Pi J Pi x = Pi b with the orthogonal
+ * projector Pi x = x - u <u, x>_R / <u, u>_R and the preconditioner
+ * Pi R_k Pi.  x is orthogonal to u.  res_true = ||Pi (b - J x)||_D /
+ * ||Pi b||_D.  psi = 0 (u = 0) is the plain solve. */
+int orc_minres_deflated(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycles,
+                        const cplx *b, cplx *x, double rtol, int max_iter,
+                        double *hist, orc_krylov_info *info);
+
 /* ------------------------------------------------------------- Newton --- */
 typedef struct {
     int steps;
@@ -135,8 +144,10 @@ typedef struct {
     int krylov_iters[64];
 } orc_newton_info;
 
+/* deflate != 0: every Newton step is solved on the complement of i psi
+ * (orc_minres_deflated). */
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               int max_coarse, orc_newton_info *info);
+               int max_coarse, int deflate, orc_newton_info *info);
 
 #endif
