@@ -2,8 +2,12 @@
 
 Sizes: several tiles of 256 nodes with ragged tails, 2D and 3D, plus the
 33 x 33 config-0 grid.  Tolerances: integer and index arrays bit-exact;
-FP64 outputs within 1e-12 (operators) / 1e-10 (solves) relative; FP32
-preconditioner outputs within 1e-5 relative to the FP64 oracle.
+FP64 operators within 1e-12 and V-cycles within 1e-11 relative; MINRES
+iterates after the same number of iterations within 1e-12 (a few) or 1e-10
+(a converged solve, compared with the oracle run to the GPU's count);
+Krylov counts within 1; Newton states within 1e-10 of max(|psi|, 1) after
+phase alignment;
+FP32 preconditioner outputs within 1e-5 relative to the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -173,8 +177,9 @@ def test_vcycle(glnk, case):
 @pytest.mark.parametrize("case", CASES, ids=IDS)
 @pytest.mark.parametrize("precond", [True, False], ids=["R1", "none"])
 def test_minres_iterates(glnk, case, precond):
-    """Fixed-k iterates equal the oracle's; to rtol 1e-10 the iteration count
-    agrees within 1 and the solution within 1e-8."""
+    """Fixed-k iterates equal the oracle's (1e-12); to rtol 1e-10 the
+    iteration count agrees within 1 and the solution equals the oracle's
+    iterate after the same number of iterations within 1e-10."""
     mg, mo = make_pair(glnk, case)
     psi = inputs.random_phase_state(mo.n, seed=6)
     b = inputs.random_complex(mo.n, seed=7)
@@ -185,13 +190,17 @@ def test_minres_iterates(glnk, case, precond):
         xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=0.0, max_iter=k)
         rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=0.0, max_iter=k, poll_every=2)
         assert ig["iterations"] == k == io["iterations"]
-        assert relerr(host(x), xo) < 1e-9
-        assert ig["res_est"] == pytest.approx(io["eta"] / io["eta0"], rel=1e-8)
+        e = relerr(host(x), xo)
+        assert e < 1e-12, (k, e)
+        assert ig["res_est"] == pytest.approx(io["eta"] / io["eta0"], rel=1e-10)
     xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-10, max_iter=2000)
     rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=2000)
     assert io["converged"] and ig["converged"]
     assert abs(ig["iterations"] - io["iterations"]) <= 1
-    assert relerr(host(x), xo) < 1e-8
+    # the same iterate: the oracle run to the GPU's count
+    xk, ik, _ = oracle.minres(mo, psi, b, amg=amg, rtol=0.0, max_iter=ig["iterations"])
+    e = relerr(host(x), xk)
+    assert e < 1e-10, e
     assert ig["res_true"] < 1e-9
 
 
@@ -232,7 +241,10 @@ def test_newton_config0(glnk):
         assert a == pytest.approx(b, rel=1e-6)
     ps = host(psi)
     chi = np.angle(np.vdot(ps, pso)) if np.abs(pso).max() > 1e-8 else 0.0
-    assert np.abs(ps * np.exp(1j * chi) - pso).max() < 1e-8
+    # in units of max(|psi|, 1): GL solutions have |psi| <= 1, and this start
+    # converges to the normal state psi = 0
+    e = np.abs(ps * np.exp(1j * chi) - pso).max() / max(np.abs(pso).max(), 1.0)
+    assert e < 1e-10, e
     # FP32 preconditioner reaches the same tolerance
     psi = dev(psi0)
     rc, i32 = glnk.gl_newton_solve(mg, psi, tol=1e-10, max_steps=50, precision=glnk.GL_FP32)
@@ -247,21 +259,30 @@ def test_fp32_preconditioned_solve_reaches_fp64_accuracy(glnk, case):
     psi = inputs.random_phase_state(mo.n, seed=10)
     b = inputs.random_complex(mo.n, seed=11)
     amg = oracle.Amg.for_state(mo, psi)
-    xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-12, max_iter=2000)
+    xo, io, _ = oracle.minres(mo, psi, b, amg=amg, rtol=1e-13, max_iter=2000)
     pre = glnk.Precond(mg, dev(psi), precision=glnk.GL_FP32)
     x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
-    rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=2000)
-    assert rc == 0 and info["converged"]
-    assert info["res_true"] < 1e-9
-    assert relerr(host(x), xo) < 1e-8
+
+    def check(info):
+        # the solution's residual in the oracle's Jacobian, and its distance
+        # from the oracle's 1e-13 solve
+        assert info["converged"]
+        xs = host(x)
+        rr = mo.norm(mo.jac(psi, xs) - b) / mo.norm(b)
+        assert rr < 1e-10 and info["res_true"] < 1e-10, (rr, info)
+        e = relerr(xs, xo)
+        assert e < 1e-9, e
+
+    rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-11, max_iter=2000)
+    assert rc == 0
+    check(info)
     # one recurrence: FP64 V-cycle down to 1e-3, the reduced precision after
     for prec in (glnk.GL_FP32, glnk.GL_MIXED):
         pre.update(dev(psi), precision=prec)
-        rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-10, max_iter=2000,
+        rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-11, max_iter=2000,
                                           relax_rtol=1e-3)
-        assert rc == 0 and info["converged"]
-        assert info["res_true"] < 1e-9
-        assert relerr(host(x), xo) < 1e-8
+        assert rc == 0
+        check(info)
 
 
 def test_repeated_solves_bitwise_identical(glnk):
@@ -313,20 +334,18 @@ def test_vcycle_and_solve_deeper_hierarchy(glnk, max_coarse):
         glnk.gl_precond_set_tiles(pre, 0, 0, 8193)
     # the explicit sub-cycle with the values of a later setup (graphs keep
     # its address), then MINRES through it against the oracle
-    glnk.gl_precond_set_tiles(pre, 0, 0, 4096)
-    pre.update(dev(psi), precision=glnk.GL_FP64)
     xo, io, _ = oracle.minres(mo, psi, r, amg=amg, rtol=1e-10, max_iter=3000)
-    rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(r), z, rtol=1e-10, max_iter=3000)
-    assert io["converged"] and ig["converged"]
-    assert abs(ig["iterations"] - io["iterations"]) <= 1
-    assert relerr(host(z), xo) < 1e-8
-    glnk.gl_precond_set_tiles(pre, 0, 0)
-    pre.update(dev(psi), precision=glnk.GL_FP64)
-    xo, io, _ = oracle.minres(mo, psi, r, amg=amg, rtol=1e-10, max_iter=3000)
-    rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(r), z, rtol=1e-10, max_iter=3000)
-    assert io["converged"] and ig["converged"]
-    assert abs(ig["iterations"] - io["iterations"]) <= 1
-    assert relerr(host(z), xo) < 1e-8
+    assert io["converged"]
+    for tiles in ((0, 0, 4096), (0, 0)):
+        glnk.gl_precond_set_tiles(pre, *tiles)
+        pre.update(dev(psi), precision=glnk.GL_FP64)
+        rc, ig = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(r), z, rtol=1e-10, max_iter=3000)
+        assert ig["converged"]
+        assert abs(ig["iterations"] - io["iterations"]) <= 1
+        xk = xo if ig["iterations"] == io["iterations"] else \
+            oracle.minres(mo, psi, r, amg=amg, rtol=0.0, max_iter=ig["iterations"])[0]
+        e = relerr(host(z), xk)
+        assert e < 1e-10, (tiles, e)
 
 
 def test_secant_predictor(glnk):
@@ -366,11 +385,12 @@ def test_continuation_falls_back_to_secant(glnk):
 def test_continuation_matches_oracle(glnk):
     """Natural continuation from psi = 1 at mu = 0 in steps of 0.05 on a 33 x 33
     grid of side 8: Newton steps per continuation step equal the oracle's, MINRES
-    counts of each Newton step but the last within max(2, 5 %) (the two
-    trajectories are rounded differently, which moves indefinite solves by a
-    few iterations; the last step's right-hand side GL(psi) is at the rounding
-    level of psi, so its count is set by rounding noise and is not compared),
-    final states equal up to a global phase."""
+    counts of each Newton step but the last within 1, final states equal up to
+    a global phase (1e-10).  The last Newton step of a continuation step is
+    not compared: its right-hand side GL(psi) is at the rounding level of psi,
+    and the oracle's own count there moves by up to 15 when its start is only
+    rotated by a global phase (test_oracle_continuation), while every earlier
+    count stays put."""
     from oracle import continuation as oc
     from paper_1204_5125_amd import continuation as gc
     N, side = (33, 33), (8.0, 8.0)
@@ -382,10 +402,11 @@ def test_continuation_matches_oracle(glnk):
         assert a["status"] == 0 and b["status"] == 0
         assert a["newton_steps"] == b["newton_steps"]
         for x, y in zip(a["krylov_iters"][:-1], b["krylov_iters"][:-1]):
-            assert abs(x - y) <= max(2, 0.05 * y)
+            assert abs(x - y) <= 1, (a, b)
     ps = host(psg)
     chi = np.angle(np.vdot(ps, pso))
-    assert np.abs(ps * np.exp(1j * chi) - pso).max() < 1e-8
+    e = np.abs(ps * np.exp(1j * chi) - pso).max() / max(np.abs(pso).max(), 1.0)
+    assert e < 1e-10, e
 
 
 def test_mesh_independent_iteration_counts(glnk):
