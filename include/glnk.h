@@ -231,6 +231,17 @@ typedef struct {
                           to rtol and stopped on the true residual (restarted
                           by refinement if that misses rtol); 0 = the reduced
                           precision from the first iteration */
+    int deflate;       /* 1: solve on the <.,.>_R-orthogonal complement of the
+                          gauge mode u = i psi, which spans the kernel of J at a
+                          solution (eq. jacobian nullspace) and makes J nearly
+                          singular near one (Sec. 3 names deflation for such
+                          systems): MINRES on Pi J Pi x = Pi b, preconditioner
+                          Pi R_k Pi, Pi x = x - u <u, x>_R / <u, u>_R.  x is
+                          orthogonal to u; for b = -GL(psi) (itself orthogonal
+                          to u) this is the Newton step under the phase
+                          condition <i psi, dpsi>_R = 0.  res_true is then
+                          ||Pi (b - J x)||_D / ||Pi b||_D.  psi = 0: plain solve.
+                          0: plain */
 } gl_krylov_opts;
 
 typedef struct {

@@ -100,18 +100,25 @@ struct BottomDesc {
 };
 
 // Krylov scalar state kept on the device (see krylov.hip).
+// Deflation of the gauge mode u = i psi (the solve restricted to the
+// <.,.>_R-orthogonal complement of u): defl_c = <u, u>_R, defl_sq the last
+// projection coefficient of a residual-space vector, defl_sy that of the
+// newest preconditioner output (0 when there is nothing to project), and
+// defl_pending set by the recurrence whenever it has produced a new one.
 struct KrylovScalars {
     double gamma, gamma_prev, c, c_prev, s, s_prev, eta, eta0, delta;
     double wx_inv_gamma, wx_a1, wx_a2, wx_a3, wx_coef;
     double rtol;
     double res_num, res_den;
+    double defl_c, defl_sq, defl_sy, res_u_num, res_u_den;
     int iter, max_iter, running, wx_valid, status, converged;
+    int defl_pending;
 };
 
 // What a reduction's finalize kernel does with the total.
 enum FinalizeMode {
     FIN_STORE = 0, FIN_MINRES_INIT = 1, FIN_MINRES_STEP = 2, FIN_DELTA = 3, FIN_RESNUM = 4,
-    FIN_RESDEN = 5
+    FIN_RESDEN = 5, FIN_DEFL_Y = 6
 };
 
 // Scalar part of preconditioned MINRES (Paige-Saunders Lanczos + Givens
@@ -124,6 +131,13 @@ __device__ __forceinline__ void minres_finalize(KrylovScalars *ks, int mode, dou
     if (mode == FIN_DELTA) { ks->delta = total; return; }
     if (mode == FIN_RESNUM) { ks->res_num = total; return; }
     if (mode == FIN_RESDEN) { ks->res_den = total; return; }
+    if (mode == FIN_DEFL_Y) {
+        // coefficient of the newest preconditioner output along u, or 0 when
+        // the recurrence has produced none since the last projection
+        ks->defl_sy = ks->defl_pending ? total : 0.0;
+        ks->defl_pending = 0;
+        return;
+    }
     if (mode == FIN_MINRES_INIT) {
         ks->iter = 0;
         ks->converged = 0;
@@ -143,6 +157,7 @@ __device__ __forceinline__ void minres_finalize(KrylovScalars *ks, int mode, dou
         ks->s = ks->s_prev = 0.0;
         ks->converged = (g == 0.0);
         ks->running = (g > 0.0) && (ks->max_iter > 0);
+        ks->defl_pending = 1;
         return;
     }
     // FIN_MINRES_STEP
@@ -179,6 +194,7 @@ __device__ __forceinline__ void minres_finalize(KrylovScalars *ks, int mode, dou
     ks->s = sn;
     ks->iter += 1;
     ks->wx_valid = 1;
+    ks->defl_pending = 1;
     if (fabs(ks->eta) <= ks->rtol * ks->eta0 || gnew == 0.0) {
         ks->converged = 1;
         ks->running = 0;

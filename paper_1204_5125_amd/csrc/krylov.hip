@@ -115,6 +115,8 @@ struct MinresJapply {
     double2 *wp, *x;
     const KrylovScalars *ks;
     RedSlot slot;
+    RedSlot slot_u;  // deflation: partials of <u, q>_E, u = i psi (unused otherwise)
+    int defl;
     __device__ void operator()(int bx, int nbx) const
     {
         // the scalars and the vectors are loaded together; the (uniform)
@@ -125,7 +127,7 @@ struct MinresJapply {
         const bool upd = ks->iter >= 1;
         const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         const bool in = i < g.n;
-        double part = 0.0;
+        double part = 0.0, part_u = 0.0;
         double2 wn = make_double2(0.0, 0.0), xn = wn, qi = wn;
         if (in) {
             if (upd) {
@@ -143,6 +145,8 @@ struct MinresJapply {
             const double2 react = cadd(cscale(zn, 2.0 * cabs2(p) - 1.0), cmul(cmul(p, p), cconj(zn)));
             qi = cadd(cscale(kz, ig), cscale(react, d));
             part = redot(qi, zn);
+            // Re(conj(i psi) q) = Im(conj(psi) q)
+            part_u = p.x * qi.y - p.y * qi.x;
         }
         if (running == 0) return;
         if (in) {
@@ -153,6 +157,7 @@ struct MinresJapply {
             q[i] = qi;
         }
         block_reduce_store(part, slot, sm, bx);
+        if (defl) block_reduce_store(part_u, slot_u, sm, bx);
     }
 };
 
@@ -170,6 +175,141 @@ struct MinresVupdate {
         const double2 qi = q[i], vi = v[i], vpi = vp[i];
         if (running == 0) return;
         vp[i] = csub(csub(qi, cscale(vi, a)), cscale(vpi, b));
+    }
+};
+
+// ---------------------------------------------- deflation of i psi ----
+// The solve restricted to the <.,.>_R-orthogonal complement of the gauge
+// mode u = i psi: at a solution J(psi) u = 0 (eq. jacobian nullspace), and
+// near one J is nearly singular along u; Sec. 3 names deflation among the
+// remedies.  In the D-scaled form the projector of solution-space vectors
+// (z, w, x) is Pi z = z - u <u, z>_R / c and that of residual-space vectors
+// (v, q = D J z) its transpose Pi' v = v - D u Re(sum conj(u) v) / c, with
+// c = <u, u>_R.  MINRES runs on Pi' (D J) Pi with the preconditioner
+// Pi AMG Pi': q is projected before the Lanczos update (its coefficient comes
+// with delta from MinresJapply) and every preconditioner output after it.
+// delta and gamma need no correction: <q, z> and <v, M^-1 v> are unchanged by
+// the projections when z and v already lie in the complements.
+
+// partials of c = <u, u>_R = sum d |psi|^2 and <u, b>_R = sum d Im(conj(psi) b)
+template <int DIM>
+struct DeflInit {
+    GeomT<double> g;
+    const double2 *psi, *b;
+    RedSlot sc, sb;
+    __device__ void operator()(int bx, int) const
+    {
+        __shared__ double sm[kBlock / 64];
+        const int i = bx * kBlock + threadIdx.x;
+        double pc = 0.0, pb = 0.0;
+        if (i < g.n) {
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            double sf[3];
+            const double d = node_volume<DIM, double>(g, c, sf);
+            const double2 p = psi[i], bi = b[i];
+            pc = d * cabs2(p);
+            pb = d * (p.x * bi.y - p.y * bi.x);
+        }
+        block_reduce_store(pc, sc, sm, bx);
+        block_reduce_store(pb, sb, sm, bx);
+    }
+};
+
+// v = D Pi b = D (b - u <u, b>_R / c), v_prev = w = w_prev = x = 0
+template <int DIM>
+struct MinresInitDefl {
+    GeomT<double> g;
+    const double2 *psi, *b;
+    double2 *v, *vp, *w, *wp, *x;
+    const KrylovScalars *ks;
+    __device__ void operator()(int bx, int) const
+    {
+        const double cu = ks->defl_c;
+        const double sb = cu > 0.0 ? ks->defl_sq / cu : 0.0;
+        const int i = bx * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        double sf[3];
+        const double d = node_volume<DIM, double>(g, c, sf);
+        const double2 p = psi[i], bi = b[i];
+        const double2 zero = make_double2(0.0, 0.0);
+        // u = i psi = (-Im psi, Re psi)
+        v[i] = cscale(make_double2(bi.x + sb * p.y, bi.y - sb * p.x), d);
+        vp[i] = zero;
+        w[i] = zero;
+        wp[i] = zero;
+        x[i] = zero;
+    }
+};
+
+// v_{j+1} = Pi'(q) - (delta / gamma) v_j - (gamma / gamma_prev) v_{j-1}
+template <int DIM>
+struct MinresVupdateDefl {
+    GeomT<double> g;
+    const double2 *psi, *q, *v;
+    double2 *vp;
+    const KrylovScalars *ks;
+    __device__ void operator()(int bx, int) const
+    {
+        const int running = ks->running;
+        const double a = ks->delta / ks->gamma, b = ks->gamma / ks->gamma_prev;
+        const double cu = ks->defl_c;
+        const double sq = cu > 0.0 ? ks->defl_sq / cu : 0.0;
+        const int i = bx * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        double sf[3];
+        const double d = node_volume<DIM, double>(g, c, sf);
+        const double2 qi = q[i], vi = v[i], vpi = vp[i], p = psi[i];
+        if (running == 0) return;
+        const double2 pq = make_double2(qi.x + sq * d * p.y, qi.y - sq * d * p.x);
+        vp[i] = csub(csub(pq, cscale(vi, a)), cscale(vpi, b));
+    }
+};
+
+// partials of <u, z>_R = sum d Im(conj(psi) z) for a new preconditioner output
+template <int DIM>
+struct DeflZ {
+    GeomT<double> g;
+    const double2 *psi, *z;
+    const KrylovScalars *ks;
+    RedSlot slot;
+    __device__ void operator()(int bx, int) const
+    {
+        if (!ks->defl_pending) return;  // the finalisation then stores 0
+        __shared__ double sm[kBlock / 64];
+        const int i = bx * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < g.n) {
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            double sf[3];
+            const double d = node_volume<DIM, double>(g, c, sf);
+            const double2 p = psi[i], zi = z[i];
+            part = d * (p.x * zi.y - p.y * zi.x);
+        }
+        block_reduce_store(part, slot, sm, bx);
+    }
+};
+
+// z = Pi z = z - u defl_sy / c
+struct DeflApply {
+    int n;
+    const double2 *psi;
+    double2 *z;
+    const KrylovScalars *ks;
+    __device__ void operator()(int bx, int) const
+    {
+        const double cu = ks->defl_c, sy = ks->defl_sy;
+        if (!(cu > 0.0) || sy == 0.0) return;
+        const double s = sy / cu;
+        const int i = bx * kBlock + threadIdx.x;
+        if (i >= n) return;
+        const double2 p = psi[i], zi = z[i];
+        z[i] = make_double2(zi.x + s * p.y, zi.y - s * p.x);
     }
 };
 
@@ -208,6 +348,58 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(GeomT<double> g, const
         const double2 bi = b[i];
         pr = d * cabs2(csub(bi, jx));
         pb = d * cabs2(bi);
+    }
+    block_reduce_store(pr, s1, sm, blockIdx.x);
+    block_reduce_store(pb, s2, sm, blockIdx.x);
+}
+
+// deflated solves: partials of <u, r>_R and <u, b>_R (u = i psi), with r the
+// residual vector b - J x already formed
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_defl_dots(GeomT<double> g, const double2 *__restrict__ psi,
+                                                      const double2 *__restrict__ r,
+                                                      const double2 *__restrict__ b, RedSlot s1, RedSlot s2)
+{
+    __shared__ double sm[kBlock / 64];
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double pr = 0.0, pb = 0.0;
+    if (i < g.n) {
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        double sf[3];
+        const double d = node_volume<DIM, double>(g, c, sf);
+        const double2 p = psi[i], ri = r[i], bi = b[i];
+        pr = d * (p.x * ri.y - p.y * ri.x);
+        pb = d * (p.x * bi.y - p.y * bi.x);
+    }
+    block_reduce_store(pr, s1, sm, blockIdx.x);
+    block_reduce_store(pb, s2, sm, blockIdx.x);
+}
+
+// partials of ||Pi r||_D^2 and ||Pi b||_D^2, Pi y = y - u <u, y>_R / c (the
+// projections formed explicitly: the residual carries the phase condition's
+// multiplier along u, which a difference of squares would cancel badly)
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_defl_norms(GeomT<double> g, const double2 *__restrict__ psi,
+                                                       const double2 *__restrict__ r,
+                                                       const double2 *__restrict__ b,
+                                                       const KrylovScalars *__restrict__ ks, RedSlot s1,
+                                                       RedSlot s2)
+{
+    __shared__ double sm[kBlock / 64];
+    const double cu = ks->defl_c;
+    const double sr = cu > 0.0 ? ks->res_u_num / cu : 0.0, sb = cu > 0.0 ? ks->res_u_den / cu : 0.0;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    double pr = 0.0, pb = 0.0;
+    if (i < g.n) {
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        double sf[3];
+        const double d = node_volume<DIM, double>(g, c, sf);
+        const double2 p = psi[i], ri = r[i], bi = b[i];
+        // y - s u with u = i psi = (-Im psi, Re psi)
+        pr = d * cabs2(make_double2(ri.x + sr * p.y, ri.y - sr * p.x));
+        pb = d * cabs2(make_double2(bi.x + sb * p.y, bi.y - sb * p.x));
     }
     block_reduce_store(pr, s1, sm, blockIdx.x);
     block_reduce_store(pb, s2, sm, blockIdx.x);
@@ -291,16 +483,29 @@ struct Ksolve {
     double2 *x;
     double2 *v, *vp, *z, *zn, *q, *w, *wp;
     gl_precision prec;  // of the V-cycle applications
+    bool defl;          // restricted to the complement of i psi
 };
 
 static Ksolve make_ksolve(const gl_mesh *m, const double2 *psi, const gl_precond *pre, const double2 *rhs,
-                          double2 *x)
+                          double2 *x, bool defl)
 {
     const size_t n = (size_t)m->g.n;
     double2 *W = m->work.get();
     return Ksolve{m,         psi,       pre,       rhs,       x,         W,
                   W + n,     W + 2 * n, W + 3 * n, W + 4 * n, W + 5 * n, W + 6 * n,
-                  pre ? pre->opts.precision : GL_FP64};
+                  pre ? pre->opts.precision : GL_FP64, defl};
+}
+
+// z = Pi z after a new preconditioner output (deflated solves)
+template <int DIM>
+static void defl_project_z(const Ksolve &k, double2 *z, const Launch &L)
+{
+    const gl_mesh *m = k.m;
+    const int n = m->g.n, nb = blocks_for(n);
+    KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
+    L.run(nb, DeflZ<DIM>{geom_t<double>(m->g), k.psi, z, ks, red_slot(m, 3)});
+    launch_finalize(red_slot(m, 3).partials, nb, FIN_DEFL_Y, ks, nullptr, nullptr, L);
+    L.run(nb, DeflApply{n, k.psi, z, ks});
 }
 
 // the roles of the rotating buffers after `iters` further iterations
@@ -323,13 +528,21 @@ static void ksolve_init(const Ksolve &k, double rtol, int max_iter, const Launch
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
     L.run<KsInit, 64>(1, KsInit{ks, rtol, max_iter});
-    L.run(nb, MinresInit<DIM>{g, k.rhs, k.v, k.vp, k.w, k.wp, k.x});
+    if (k.defl) {
+        L.run(nb, DeflInit<DIM>{g, k.psi, k.rhs, red_slot(m, 2), red_slot(m, 3)});
+        launch_finalize(red_slot(m, 2).partials, nb, FIN_STORE, nullptr, &ks->defl_c, nullptr, L);
+        launch_finalize(red_slot(m, 3).partials, nb, FIN_STORE, nullptr, &ks->defl_sq, nullptr, L);
+        L.run(nb, MinresInitDefl<DIM>{g, k.psi, k.rhs, k.v, k.vp, k.w, k.wp, k.x, ks});
+    } else {
+        L.run(nb, MinresInit<DIM>{g, k.rhs, k.v, k.vp, k.w, k.wp, k.x});
+    }
     if (k.pre) {
         vcycle_enqueue(k.pre, k.v, k.z, nullptr, ks, FIN_MINRES_INIT, L, k.prec);
     } else {
         L.run(nb, Unprec<DIM>{g, k.v, k.z, nullptr, red_slot(m, 1)});
         launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_INIT, ks, nullptr, nullptr, L);
     }
+    if (k.defl) defl_project_z<DIM>(k, k.z, L);
 }
 
 template <int DIM>
@@ -342,16 +555,23 @@ static void enqueue_iteration(Ksolve &k, const Launch &L)
     const int *gate = &ks->running;
     prof_launch(PROF_MINRES_JAPPLY, 48.0 * n + 96.0 * n, L, [&] {
         L.run(nb, MinresJapply<DIM>{g, k.psi, k.z, link_tab<double>(m), k.q, k.zn, k.w, k.wp, k.x, ks,
-                                    red_slot(m, 0)});
+                                    red_slot(m, 0), red_slot(m, 2), k.defl ? 1 : 0});
     });
     launch_finalize(red_slot(m, 0).partials, nb, FIN_DELTA, ks, nullptr, gate, L);
-    prof_launch(PROF_VUPDATE, 64.0 * n, L, [&] { L.run(nb, MinresVupdate{n, k.q, k.v, k.vp, ks}); });
+    if (k.defl) {
+        launch_finalize(red_slot(m, 2).partials, nb, FIN_STORE, nullptr, &ks->defl_sq, gate, L);
+        prof_launch(PROF_VUPDATE, 80.0 * n, L,
+                    [&] { L.run(nb, MinresVupdateDefl<DIM>{g, k.psi, k.q, k.v, k.vp, ks}); });
+    } else {
+        prof_launch(PROF_VUPDATE, 64.0 * n, L, [&] { L.run(nb, MinresVupdate{n, k.q, k.v, k.vp, ks}); });
+    }
     if (k.pre) {
         vcycle_enqueue(k.pre, k.vp, k.zn, gate, ks, FIN_MINRES_STEP, L, k.prec);
     } else {
         L.run(nb, Unprec<DIM>{g, k.vp, k.zn, gate, red_slot(m, 1)});
         launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_STEP, ks, nullptr, gate, L);
     }
+    if (k.defl) defl_project_z<DIM>(k, k.zn, L);
     std::swap(k.v, k.vp);
     std::swap(k.z, k.zn);
     std::swap(k.w, k.wp);
@@ -364,7 +584,7 @@ static hipGraphExec_t iteration_graph(Ksolve k, hipStream_t s)
     gl_mesh *m = const_cast<gl_mesh *>(k.m);
     const uint64_t key[6] = {(uint64_t)(uintptr_t)k.psi, (uint64_t)(uintptr_t)k.rhs, (uint64_t)(uintptr_t)k.x,
                              k.pre ? k.pre->uid : 0,
-                             k.pre ? (uint64_t)(k.prec * 4096 + k.pre->opts.cycles) : 0,
+                             (k.pre ? (uint64_t)(k.prec * 4096 + k.pre->opts.cycles) : 0) | ((uint64_t)k.defl << 40),
                              (uint64_t)(uintptr_t)k.v};
     for (auto &e : m->graphs)
         if (std::memcmp(e.key, key, sizeof(key)) == 0) return e.exec;
@@ -433,11 +653,26 @@ static void ksolve_iterate(Ksolve k, int max_iter, int poll, hipStream_t s, Kryl
 }
 
 template <int DIM>
-static void true_residual(const gl_mesh *m, const double2 *psi, const double2 *x, const double2 *b, hipStream_t s)
+static void true_residual(const gl_mesh *m, const double2 *psi, const double2 *x, const double2 *b, bool defl,
+                          hipStream_t s)
 {
     const int nb = blocks_for(m->g.n);
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
+    if (defl) {
+        // r = b - J x into the refinement's residual buffer (free once the solve has ended)
+        double2 *r = m->work.get() + 10 * (size_t)m->g.n;
+        k_residual_vec<DIM><<<nb, kBlock, 0, s>>>(g, psi, x, b, link_tab<double>(m), r);
+        k_defl_dots<DIM><<<nb, kBlock, 0, s>>>(g, psi, r, b, red_slot(m, 0), red_slot(m, 1));
+        GLK_CHECK_LAUNCH();
+        launch_finalize(red_slot(m, 0).partials, nb, FIN_STORE, nullptr, &ks->res_u_num, nullptr, s);
+        launch_finalize(red_slot(m, 1).partials, nb, FIN_STORE, nullptr, &ks->res_u_den, nullptr, s);
+        k_defl_norms<DIM><<<nb, kBlock, 0, s>>>(g, psi, r, b, ks, red_slot(m, 2), red_slot(m, 3));
+        GLK_CHECK_LAUNCH();
+        launch_finalize(red_slot(m, 2).partials, nb, FIN_RESNUM, ks, nullptr, nullptr, s);
+        launch_finalize(red_slot(m, 3).partials, nb, FIN_RESDEN, ks, nullptr, nullptr, s);
+        return;
+    }
     k_true_residual<DIM><<<nb, kBlock, 0, s>>>(g, psi, x, b, link_tab<double>(m), red_slot(m, 2), red_slot(m, 3));
     GLK_CHECK_LAUNCH();
     launch_finalize(red_slot(m, 2).partials, nb, FIN_RESNUM, ks, nullptr, nullptr, s);
@@ -459,8 +694,9 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
     bool converged = false;
     double eta0 = 0.0, res_est = 0.0;
     const bool fp64 = !pre || pre->opts.precision == GL_FP64;
+    const bool defl = o.deflate != 0;
     if (fp64 && o.inner_rtol <= 0.0) {
-        Ksolve k = make_ksolve(m, psi, pre, b, x);
+        Ksolve k = make_ksolve(m, psi, pre, b, x, defl);
         ksolve_init<DIM>(k, o.rtol, o.max_iter, Launch{s});
         ksolve_iterate<DIM>(k, o.max_iter, poll, s, h);
         iters = h.iter;
@@ -482,7 +718,7 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
         double2 *d = m->work.get() + 9 * (size_t)n, *r = m->work.get() + 10 * (size_t)n;
         k_copy<<<nb, kBlock, 0, s>>>(n, r, b);
         k_zero<<<nb, kBlock, 0, s>>>(n, x);
-        Ksolve k = make_ksolve(m, psi, pre, r, d);
+        Ksolve k = make_ksolve(m, psi, pre, r, d, defl);
         if (relax) k.prec = GL_FP64;
         double eta_first = 0.0;
         for (int outer = 0; outer < 64; ++outer) {
@@ -520,7 +756,7 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
         }
         eta0 = eta_first;
     }
-    true_residual<DIM>(m, psi, x, b, s);
+    true_residual<DIM>(m, psi, x, b, defl, s);
     read_scalars(m, &h, s);
     if (info) {
         info->iterations = iters;
@@ -552,7 +788,8 @@ static void check_krylov_opts(const gl_krylov_opts *o, const char *who)
 {
     if (!o) fail(GL_ERR_INVALID_ARGUMENT, std::string(who) + ": NULL options");
     if (!(o->rtol >= 0.0) || o->max_iter < 0 || o->max_iter > 100000000 || o->poll_every < 1 ||
-        !(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0) || !(o->relax_rtol >= 0.0 && o->relax_rtol < 1.0))
+        !(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0) || !(o->relax_rtol >= 0.0 && o->relax_rtol < 1.0) ||
+        (o->deflate != 0 && o->deflate != 1))
         fail(GL_ERR_INVALID_ARGUMENT, std::string(who) + ": invalid Krylov options");
 }
 
@@ -747,6 +984,7 @@ struct gl_batch {
     size_t staging_cap = 0;
     int64_t graph_launches = 0;
     double seconds[3] = {0.0, 0.0, 0.0};  // residuals, preconditioner setups, Krylov solves
+    int deflate = 0;                      // Krylov option of the running solve
     ~gl_batch();
 };
 
@@ -771,7 +1009,7 @@ static Ksolve batch_ksolve(gl_batch *B, double2 *const *psi, int i, bool refine,
     const size_t n = (size_t)m->g.n;
     double2 *W = m->work.get();
     return make_ksolve(m, psi[i], use_pre ? B->pre[i] : nullptr, refine ? W + 10 * n : W + 7 * n,
-                       refine ? W + 9 * n : W + 8 * n);
+                       refine ? W + 9 * n : W + 8 * n, B->deflate != 0);
 }
 
 // Group instances by the shape of a recorded sequence; rec(i, out) records one.
@@ -889,7 +1127,7 @@ static void batch_iterate(gl_batch *B, double2 *const *psi, bool refine, bool us
         B->groups.push_back(std::move(bg));
     }
     auto key_of = [&](const std::vector<int> &mem) {
-        std::vector<uint64_t> key{(uint64_t)refine, (uint64_t)use_pre};
+        std::vector<uint64_t> key{(uint64_t)refine, (uint64_t)use_pre, (uint64_t)B->deflate};
         for (int i : mem) {
             const gl_precond *p = use_pre ? B->pre[i] : nullptr;
             key.push_back((uint64_t)i);
@@ -1075,6 +1313,7 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
     std::vector<char> active(N, 1);
     std::vector<double> res(N, 0.0);
     std::vector<int> iters(N, 0);
+    B->deflate = o.krylov.deflate;
     for (int i = 0; i < N; ++i) k_ks_stop<<<1, 1, 0, B->s>>>(kscal_of(B->meshes[i]));
     GLK_CHECK_LAUNCH();
     auto residuals = [&]() {

@@ -57,7 +57,7 @@ class AmgOpts(C.Structure):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("poll_every", C.c_int),
-                ("inner_rtol", C.c_double), ("relax_rtol", C.c_double)]
+                ("inner_rtol", C.c_double), ("relax_rtol", C.c_double), ("deflate", C.c_int)]
 
 
 class KrylovInfo(C.Structure):
@@ -328,9 +328,10 @@ def gl_precond_apply(pre, r, z, stream=None):
 
 
 def gl_jacobian_solve(mesh, psi, pre, b, x, rtol=1e-10, max_iter=1000, poll_every=8, inner_rtol=0.0,
-                      relax_rtol=0.0, stream=None, raise_on_fail=True):
-    """Solve J(psi) x = b by preconditioned MINRES; returns (status, info dict)."""
-    o = KrylovOpts(rtol, max_iter, poll_every, inner_rtol, relax_rtol)
+                      relax_rtol=0.0, deflate=False, stream=None, raise_on_fail=True):
+    """Solve J(psi) x = b by preconditioned MINRES (with deflate: on the
+    complement of the gauge mode i psi); returns (status, info dict)."""
+    o = KrylovOpts(rtol, max_iter, poll_every, inner_rtol, relax_rtol, int(deflate))
     ki = KrylovInfo()
     rc = lib().gl_jacobian_solve(mesh.handle, _vec(psi, mesh.n, "psi"),
                                  pre.handle if pre is not None else None, _vec(b, mesh.n, "b"),
@@ -369,11 +370,12 @@ class PrecondHandle:
 def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
                     krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
                     relax_rtol=0.0, precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, precond=None,
-                    stream=None, raise_on_fail=True):
+                    deflate=False, stream=None, raise_on_fail=True):
     """Newton for GL(psi) = 0 in place; returns (status, info dict).  precond:
-    an optional PrecondHandle whose hierarchy is reused (and filled on first use)."""
+    an optional PrecondHandle whose hierarchy is reused (and filled on first use);
+    deflate: each step under the phase condition <i psi, dpsi>_R = 0."""
     o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
-                   KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, relax_rtol),
+                   KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, relax_rtol, int(deflate)),
                    AmgOpts(precision, cycles, max_coarse, max_levels))
     ni = NewtonInfo()
     rc = lib().gl_newton_solve(mesh.handle, _vec(psi, mesh.n, "psi"), C.byref(o),
@@ -421,7 +423,7 @@ class Batch:
 
     def newton_solve(self, psis, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
                      krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
-                     precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, stream=None,
+                     precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, deflate=False, stream=None,
                      raise_on_fail=True):
         """Newton on every instance in place (psis[i] on meshes[i]); returns
         (status, [info dict per instance])."""
@@ -429,7 +431,7 @@ class Batch:
             raise ValueError("one psi per mesh")
         ptrs = (C.c_void_p * len(psis))(*[_vec(p, m.n, "psi") for p, m in zip(psis, self.meshes)])
         o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
-                       KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol),
+                       KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, 0.0, int(deflate)),
                        AmgOpts(precision, cycles, max_coarse, max_levels))
         infos = (NewtonInfo * len(psis))()
         rc = lib().gl_batch_newton_solve(self._h, ptrs, C.byref(o), infos, _stream(stream))

@@ -82,33 +82,64 @@ def test_batch_equals_single_bitwise(glnk, precision):
 
 
 def test_batch_follows_oracle(glnk):
-    """Each instance against the oracle's Newton from the same start: the same
-    number of steps, the first solve's Krylov count within 1 (same system),
-    the totals without the last step within 5 % (later systems differ by the
-    rounding of the two trajectories, which moves indefinite solves by a few
-    iterations; the last step's right-hand side is at the rounding level of
-    psi), and the converged states equal up to a global phase."""
+    """Each instance against the oracle, system by system: the batch is
+    stepped one Newton round at a time and, at every Newton iterate psi_k it
+    produced (but the last, whose right-hand side GL(psi_k) is at the
+    rounding level of psi), the oracle solves the same system
+    J(psi_k) d = -GL(psi_k).  The batch's Krylov count equals the oracle's
+    within 1, or, where it stops earlier, the oracle's own residual estimate
+    at the batch's count is already within 5x of the tolerance, or, where it
+    stops later, it is within 1 of the most the oracle takes on the same
+    system rotated by global phases (rounded differently).  These
+    trajectories end in the normal state psi = 0, where J ~ K - 1 is nearly
+    singular and the estimate creeps along the tolerance: on the 9^3 grid's
+    fifth Newton system the oracle's last four estimates read 3.3e-10,
+    1.5e-10, 1.45e-10, 9.3e-11, and its count over phase rotations is 68, 68,
+    68 or 70, so rounding moves the crossing by several iterations.  The
+    oracle's own Newton from
+    the same start takes the same number of steps and ends, up to a global
+    phase, in the same state (1e-10 of max(|psi|, 1); GL solutions have
+    |psi| <= 1)."""
     ms = meshes(glnk)
     p0 = starts(ms)
     batch = glnk.Batch(ms)
     psis = [dev(p) for p in p0]
-    rc, infos = batch.newton_solve(psis, tol=1e-10, max_steps=30, krylov_max_iter=2000)
-    assert rc == 0
-    for (d, N, s, mu, b, _), p, info, psi in zip(INSTANCES, p0, infos, psis):
+    states = [[p.copy()] for p in p0]
+    counts = [[] for _ in ms]
+    for _ in range(30):
+        rc, infos = batch.newton_solve(psis, tol=1e-10, max_steps=1, krylov_max_iter=2000, raise_on_fail=False)
+        if all(i["steps"] == 0 for i in infos):
+            break
+        for i, info in enumerate(infos):
+            if info["steps"]:
+                counts[i].append(info["krylov_iters"][0])
+                states[i].append(host(psis[i]))
+    for (d, N, s, mu, b, _), p, ks, st in zip(INSTANCES, p0, counts, states):
         mo = oracle.Mesh(d, N, s, mu=mu, bdir=unit(b))
         pso, io = oracle.newton(mo, p, tol=1e-10, max_steps=30, krylov_rtol=1e-10)
-        assert io["converged"] and info["steps"] == io["steps"]
-        assert abs(info["krylov_iters"][0] - io["krylov_iters"][0]) <= 1
-        assert abs(sum(info["krylov_iters"][:-1]) - sum(io["krylov_iters"][:-1])) <= 0.05 * sum(io["krylov_iters"][:-1])
-        ps = host(psi)
+        assert io["converged"] and len(ks) == io["steps"]
+        assert mo.norm(mo.gl(st[-1])) < 1e-10
+        for k, psik in enumerate(st[:len(ks) - 1]):
+            rhs = -mo.gl(psik)
+            amg = oracle.Amg.for_state(mo, psik)  # H depends on |psi| only
+            _, io0, hist = oracle.minres(mo, psik, rhs, amg=amg, rtol=1e-10, max_iter=2000)
+            ko, kg = io0["iterations"], ks[k]
+            if kg < ko - 1:
+                assert hist[kg] <= 5e-10, (N, k, ks, ko, hist[kg])
+            elif kg > ko + 1:
+                rot = [oracle.minres(mo, psik * np.exp(1j * a), rhs * np.exp(1j * a), amg=amg, rtol=1e-10,
+                                     max_iter=2000)[1]["iterations"] for a in (0.3, 1.1, 2.5)]
+                assert kg <= max(rot) + 1, (N, k, ks, ko, rot)
+        ps = st[-1]
         chi = np.angle(np.vdot(ps, pso)) if np.abs(pso).max() > 1e-8 else 0.0
-        assert np.abs(ps * np.exp(1j * chi) - pso).max() < 1e-8
+        e = np.abs(ps * np.exp(1j * chi) - pso).max() / max(np.abs(pso).max(), 1.0)
+        assert e < 1e-10, e
 
 
 def test_batch_tiles_and_reuse(glnk):
-    """Other tile choices change only rounding: same Newton steps, first
-    Krylov count within 1 and totals within 5 % (as for the oracle), states
-    within 1e-8.  A second solve on the same batch
+    """Other tile choices change only rounding: same Newton steps, every
+    Krylov count but the last step's within 1 (as for the oracle), states
+    within 1e-10 of max(|psi|, 1).  A second solve on the same batch
     (warm preconditioners, cached graph) reproduces the first bitwise."""
     ms = meshes(glnk)
     p0 = starts(ms)
@@ -129,11 +160,12 @@ def test_batch_tiles_and_reuse(glnk):
     assert rc == 0
     for x, y, i1, i2 in zip(a, c, ia, ic):
         assert i1["steps"] == i2["steps"]
-        assert abs(i1["krylov_iters"][0] - i2["krylov_iters"][0]) <= 1
-        assert abs(sum(i1["krylov_iters"][:-1]) - sum(i2["krylov_iters"][:-1])) <= 0.05 * sum(i1["krylov_iters"][:-1])
+        for u, w in zip(i1["krylov_iters"][:-1], i2["krylov_iters"][:-1]):
+            assert abs(u - w) <= 1, (i1["krylov_iters"], i2["krylov_iters"])
         hx, hy = host(x), host(y)
         chi = np.angle(np.vdot(hy, hx))
-        assert np.abs(hy * np.exp(1j * chi) - hx).max() < 1e-8
+        e = np.abs(hy * np.exp(1j * chi) - hx).max() / max(np.abs(hx).max(), 1.0)
+        assert e < 1e-10, e
 
 
 def test_batch_errors(glnk):
@@ -146,3 +178,107 @@ def test_batch_errors(glnk):
         batch.newton_solve([p[0], p[0]])
     with pytest.raises(glnk.GlnkError):
         batch.set_tiles(lane_shift=3)
+
+
+# Three instances of the 64-instance continuation workload: the first of its
+# draw (seed 0) on each grid size whose field is not zero -- instance 3
+# (129^2, mu = 6/63), 1 (257^2, 2/63) and 9 (513^2, 18/63) -- side 10,
+# psi = 1 start, FP32 V-cycle under FP64 outer iterations, the workload's
+# coarsening bound (64 rows), default tiles, Newton to 1e-10.
+CFG3 = [(129, 2.0 * 3 / 63), (257, 2.0 * 1 / 63), (513, 2.0 * 9 / 63)]
+
+
+def _cfg3_run(glnk, batched, precision, deflate=False):
+    ms = [glnk.Mesh(2, (N, N), (10.0, 10.0), mu=mu) for N, mu in CFG3]
+    psis = [torch.ones(m.n, dtype=torch.complex128, device="cuda") for m in ms]
+    kw = dict(tol=1e-10, krylov_rtol=1e-10, krylov_max_iter=4000, max_coarse=64, precision=precision,
+              poll_every=16, deflate=deflate)
+    if batched:
+        b = glnk.Batch(ms)
+        solve = lambda ps: b.newton_solve(ps, max_steps=40, **kw)[1]  # noqa: E731
+    else:
+        def solve(ps):
+            out = []
+            for m, p in zip(ms, ps):
+                h = glnk.PrecondHandle(m)
+                rc, info = glnk.gl_newton_solve(m, p, max_steps=40, precond=h, **kw)
+                out.append(info)
+            return out
+    warm = solve(psis)
+    states = [host(p).copy() for p in psis]
+    # one continuation step of 0.02 from the converged states (the first
+    # step's constant predictor)
+    for m, (N, mu) in zip(ms, CFG3):
+        m.set_field(mu + 0.02)
+    step = solve(psis)
+    return warm, step, states, [host(p) for p in psis]
+
+
+@pytest.mark.parametrize("precision", [1, 0], ids=["fp32", "fp64"])
+def test_continuation_workload_subset(glnk, precision):
+    """Batched (one dispatch per step for each grid size) against the single
+    solves, bitwise: Newton records and states.  Against the oracle's FP64
+    Newton on the same two systems (warm start at mu_k, then mu_k + 0.02 from
+    the oracle's own converged state): both converge, to states within 1e-10
+    of max(|psi|, 1) after phase alignment, and the residual history agrees
+    within 1e-6 relative while it is above 1e-5.  Krylov counts and the
+    number of Newton steps are not compared here: the Jacobian is nearly
+    singular along the gauge mode i psi (J(psi)(i psi) = i GL(psi)), and the
+    oracle's own counts on the 513^2 step move under a mere global phase
+    rotation of its start (53 or 55 at the third Newton step, 62 or 59 at the
+    fifth; 9 or 8 Newton steps, its residual going 9e-6, 3e-9, 2e-10, 3e-9,
+    9e-12 in one rounding).  The deflated variant below removes that mode and
+    is compared count by count."""
+    wb, sb, s0b, s1b = _cfg3_run(glnk, True, precision)
+    ws, ss, s0s, s1s = _cfg3_run(glnk, False, precision)
+    assert wb == ws and sb == ss
+    assert all(np.array_equal(a, b) for a, b in zip(s0b + s1b, s0s + s1s))
+    for (N, mu), w, s, p0, p1 in zip(CFG3, wb, sb, s0b, s1b):
+        assert w["converged"] and s["converged"]
+        mo = oracle.Mesh(2, (N, N), (10.0, 10.0), mu=mu)
+        po0, io0 = oracle.newton(mo, np.ones(N * N, complex), tol=1e-10, max_steps=40, krylov_rtol=1e-10,
+                                 krylov_max_iter=4000)
+        mo1 = oracle.Mesh(2, (N, N), (10.0, 10.0), mu=mu + 0.02)
+        po1, io1 = oracle.newton(mo1, po0, tol=1e-10, max_steps=40, krylov_rtol=1e-10, krylov_max_iter=4000)
+        for g, o, pg, po in ((w, io0, p0, po0), (s, io1, p1, po1)):
+            assert o["converged"], (N, o)
+            k = 0
+            while k < min(len(g["res"]), len(o["res"])) and o["res"][k] > 1e-5:
+                assert g["res"][k] == pytest.approx(o["res"][k], rel=1e-6), (N, k, g["res"], o["res"])
+                k += 1
+            chi = np.angle(np.vdot(pg, po))
+            e = np.abs(pg * np.exp(1j * chi) - po).max() / max(np.abs(po).max(), 1.0)
+            assert e < 1e-10, (N, e)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_continuation_workload_subset_deflated(glnk, precision):
+    """The same three instances with every Newton step solved on the
+    complement of i psi (Krylov option deflate): batched equals single
+    bitwise, and against the oracle's deflated Newton the whole trajectory
+    agrees -- the same number of Newton steps, the residual history within
+    1e-6 relative while above 1e-9, with the FP64 V-cycle every Krylov count
+    within 1 (the last step's too), and the states within 1e-10."""
+    wb, sb, s0b, s1b = _cfg3_run(glnk, True, precision, deflate=True)
+    ws, ss, s0s, s1s = _cfg3_run(glnk, False, precision, deflate=True)
+    assert wb == ws and sb == ss
+    assert all(np.array_equal(a, b) for a, b in zip(s0b + s1b, s0s + s1s))
+    for (N, mu), w, s, p0, p1 in zip(CFG3, wb, sb, s0b, s1b):
+        mo = oracle.Mesh(2, (N, N), (10.0, 10.0), mu=mu)
+        po0, io0 = oracle.newton(mo, np.ones(N * N, complex), tol=1e-10, max_steps=40, krylov_rtol=1e-10,
+                                 krylov_max_iter=4000, deflate=True)
+        mo1 = oracle.Mesh(2, (N, N), (10.0, 10.0), mu=mu + 0.02)
+        po1, io1 = oracle.newton(mo1, po0, tol=1e-10, max_steps=40, krylov_rtol=1e-10, krylov_max_iter=4000,
+                                 deflate=True)
+        for g, o, pg, po in ((w, io0, p0, po0), (s, io1, p1, po1)):
+            assert g["converged"] and o["converged"]
+            assert g["steps"] == o["steps"], (N, g, o)
+            for a, b in zip(g["res"], o["res"]):
+                if b > 1e-9:
+                    assert a == pytest.approx(b, rel=1e-6), (N, g["res"], o["res"])
+            if precision == 0:
+                for a, b in zip(g["krylov_iters"], o["krylov_iters"]):
+                    assert abs(a - b) <= 1, (N, g["krylov_iters"], o["krylov_iters"])
+            chi = np.angle(np.vdot(pg, po))
+            e = np.abs(pg * np.exp(1j * chi) - po).max() / max(np.abs(po).max(), 1.0)
+            assert e < 1e-10, (N, e)
