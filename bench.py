@@ -296,13 +296,19 @@ def bench_continuation(args):
     log(f"[bench] U-Net forward: {fwd_ms:.2f} ms, {unet_roof['achieved']:.1f} TFLOP/s")
     mus = [0.02 * k for k in range(101)]
     runs = {}
-    for name, prec, learned in [("fp64_secant", glnk.GL_FP64, None), ("fp64_learned", glnk.GL_FP64, "residual"),
-                                ("fp64_learned_always", glnk.GL_FP64, "always")]:
+    variants = [("fp64_secant", glnk.GL_FP64, None, False),
+                ("fp64_learned", glnk.GL_FP64, "residual", False),
+                ("fp64_learned_always", glnk.GL_FP64, "always", False),
+                ("fp64_secant_deflated", glnk.GL_FP64, None, True),
+                ("fp32_secant_deflated", glnk.GL_FP32, None, True),
+                ("fp64_learned_always_deflated", glnk.GL_FP64, "always", True),
+                ("fp32_learned_always_deflated", glnk.GL_FP32, "always", True)]
+    for name, prec, learned, defl in variants:
         pred = predictor.LearnedPredictor(net, mesh, select=learned) if learned else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         recs, _, _ = continuation.continuation_path(mesh, ones, mus, precision=prec, predictor=pred,
-                                                    callback=progress(name), **common)
+                                                    callback=progress(name), deflate=defl, **common)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         runs[name] = {"seconds": dt, "steps": len(recs) - 1,
@@ -317,12 +323,23 @@ def bench_continuation(args):
             runs[name]["start_residual_ratio_median"] = float(np.median(ratio)) if ratio else None
         log(f"[bench] {name}: {runs[name]}")
     base_run = runs["fp64_secant"]
-    best = min((runs["fp64_learned"], runs["fp64_learned_always"]), key=lambda r: (r["failed"], r["seconds"]))
+    mixed = runs["fp32_learned_always_deflated"]
+    best_learned = min((runs["fp64_learned"], runs["fp64_learned_always"]), key=lambda r: (r["failed"], r["seconds"]))
+    best_name = min((k for k in runs if k != "fp64_secant" and runs[k]["failed"] == 0),
+                    key=lambda k: runs[k]["seconds"])
+    best = runs[best_name]
     out = {
-        "metric": "continuation speedup: learned start vs secant start",
+        "metric": "continuation speedup over the plain FP64 secant path (learned start, deflation, precision)",
         "value": base_run["seconds"] / best["seconds"], "unit": "x", "n_gpus": 1, "steps": 100, "warmup": 0,
+        "best_variant": best_name,
         "ms_per_step": 1e3 * best["seconds"] / max(1, best["steps"]), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (solver) / bf16 (U-Net, f32 accumulation)",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (outer) / f32 (V-cycle) / bf16 (U-Net, f32 accumulation)",
+        "speedups": {"learned_vs_secant_fp64": base_run["seconds"] / best_learned["seconds"],
+                     "deflated_vs_plain_fp64_secant": base_run["seconds"] / runs["fp64_secant_deflated"]["seconds"],
+                     "fp32_vs_fp64_deflated_secant": runs["fp64_secant_deflated"]["seconds"]
+                     / runs["fp32_secant_deflated"]["seconds"],
+                     "mixed_learned_deflated_vs_plain_fp64": base_run["seconds"] / mixed["seconds"]},
         "data": "synthetic: continuation of psi = 1 from mu = 0 on a uniform grid; training states from a seeded sweep",
         "config": {"workload": "2D 513x513 grid, side 8, mu 0 -> 2 in steps of 0.02 (Newton to 1e-10); U-Net 4 levels, "
                                "32 base channels, BF16 / FP32 accumulation",
@@ -330,6 +347,63 @@ def bench_continuation(args):
         "runs": runs, "roofline": unet_roof,
         "training": {"sweep_seconds": t_sweep, "train_seconds": t_train,
                                    "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_arclength(args):
+    """Pseudo-arclength continuation (Sec. 4) on the continuation grid: 2D
+    513^2, side 8, from psi = 1 at mu = 0, arclength steps of 0.05 in
+    <(u, a), (v, b)> = <u, v>_R / |Omega| + a b, deflated Jacobian solves,
+    FP64 and FP32 V-cycle; beside it natural continuation in steps of 0.02
+    over the same mu range, which cannot pass the branch's fold."""
+    import torch
+
+    from paper_1204_5125_amd import continuation, glnk
+    torch.cuda.set_device(0)
+    N, side, ds = 513, 8.0, 0.05
+    mesh = glnk.Mesh(2, (N, N), (side, side), mu=0.0)
+    ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
+    runs = {}
+    for name, prec in (("fp64", glnk.GL_FP64), ("fp32", glnk.GL_FP32)):
+        def cb(rec, _):
+            log(f"[bench] arclength {name}: mu {rec['mu']:.4f} ds {rec['ds']:.4f} newton {rec['newton_steps']} "
+                f"krylov {sum(a + b for a, b in rec['krylov_iters'])}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs, states = continuation.arclength_path(mesh, ones, 0.0, ds, args.arc_steps, precision=prec,
+                                                   max_coarse=64, poll_every=16, callback=cb)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mus = [r["mu"] for r in recs]
+        turns = sum(1 for a, b, c in zip(mus, mus[1:], mus[2:]) if (b - a) * (c - b) < 0)
+        runs[name] = {"seconds": dt, "points": len(recs) - 1, "converged": sum(r["converged"] for r in recs[1:]),
+                      "newton_steps": sum(r["newton_steps"] for r in recs[1:]),
+                      "krylov_iterations": sum(a + b for r in recs[1:] for a, b in r["krylov_iters"]),
+                      "mu_max": max(mus), "mu_final": mus[-1], "turning_points": turns}
+        log(f"[bench] arclength {name}: {runs[name]}")
+    mu_max = runs["fp64"]["mu_max"]
+    mus = [0.02 * k for k in range(int(mu_max / 0.02) + 4)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs, _, _ = continuation.continuation_path(mesh, ones, mus, precision=glnk.GL_FP64, max_coarse=64,
+                                                poll_every=16, deflate=True, krylov_max_iter=3000, max_newton=25)
+    dt = time.perf_counter() - t0
+    runs["natural_fp64"] = {"seconds": dt, "points": len(recs) - 1,
+                            "newton_steps": sum(r["newton_steps"] for r in recs[1:]),
+                            "newton_steps_per_point": [r["newton_steps"] for r in recs[1:]],
+                            "mu": [r["mu"] for r in recs[1:]], "failed": sum(r["status"] != 0 for r in recs)}
+    log(f"[bench] natural continuation to {mus[-1]:.2f}: {runs['natural_fp64']['newton_steps']} Newton steps")
+    r64 = runs["fp64"]
+    out = {
+        "metric": "pseudo-arclength continuation points/s",
+        "value": r64["points"] / r64["seconds"], "unit": "points/s", "n_gpus": 1, "steps": args.arc_steps,
+        "warmup": 0, "ms_per_step": 1e3 * r64["seconds"] / max(1, r64["points"]), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64 (solver)",
+        "data": "synthetic: continuation of psi = 1 from mu = 0 on a uniform grid",
+        "config": {"workload": "2D 513x513 grid, side 8, pseudo-arclength steps of 0.05 from psi = 1 at mu = 0, "
+                               "Newton to 1e-10, deflated MINRES to 1e-10 (two solves per Newton step)"},
+        "runs": runs,
     }
     print(json.dumps(out), flush=True)
 
@@ -466,12 +540,13 @@ def bench_cube(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["jacobian", "batch", "continuation", "cube", "meshind"],
+    ap.add_argument("--workload", choices=["jacobian", "batch", "continuation", "cube", "meshind", "arclength"],
                     default="jacobian",
                     help="jacobian: the 1M-node Jacobian solves (headline); batch: batched continuation; "
                          "continuation: learned vs secant predictor; cube: 3D 129^3 mixed precision; "
                          "meshind: R_1 iteration counts against grid size")
     ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--arc-steps", type=int, default=60)
     ap.add_argument("--batch-max-coarse", type=int, default=64)
     ap.add_argument("--tile-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "glnk_tiles.json"))
     ap.add_argument("--steps", type=int, default=3)
@@ -503,6 +578,9 @@ def main():
         return
     if args.workload == "meshind":
         bench_meshind(args)
+        return
+    if args.workload == "arclength":
+        bench_arclength(args)
         return
 
     import torch

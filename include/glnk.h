@@ -141,6 +141,22 @@ gl_status gl_jacobian_apply(const gl_mesh *mesh, const void *psi, const void *ph
 gl_status gl_secant_predict(const gl_mesh *mesh, const void *psi_m, const void *psi_prev, double ratio,
                             void *out, gl_stream stream);
 
+/* out = d GL(psi; mu) / d mu at the mesh's current mu (potential == 0,
+ * A = mu A_1): GL_mu = D^-1 (dK-hat/dmu) psi with dU_jk/dmu = -i phi_jk U_jk,
+ * phi_jk = (x_j - x_k) . A_1(edge midpoint).  The parameter derivative of the
+ * bordered Newton system of pseudo-arclength continuation (Sec. 4, numerical
+ * parameter continuation).  UNSUPPORTED for a matrix potential.  out does
+ * not alias psi.  Stream-ordered. */
+gl_status gl_residual_dmu(const gl_mesh *mesh, const void *psi, void *out, gl_stream stream);
+
+/* *out = <u, v>_R = Re sum_i |V_i| conj(u_i) v_i (eq. disc inner2).  Host
+ * scalar; the stream is synchronised. */
+gl_status gl_inner(const gl_mesh *mesh, const void *u, const void *v, double *out, gl_stream stream);
+
+/* out = a x + b y with real a, b (out may alias x or y).  Stream-ordered. */
+gl_status gl_axpby(const gl_mesh *mesh, double a, const void *x, double b, const void *y, void *out,
+                   gl_stream stream);
+
 /* --------------------------------------------------- preconditioner ---- */
 typedef struct {
     gl_precision precision; /* storage and arithmetic of the V-cycle */

@@ -285,6 +285,77 @@ void secant_enqueue(const gl_mesh *m, const double2 *psi, const double2 *prev, d
     GLK_CHECK_LAUNCH();
 }
 
+// ----------------------------------------- parameter derivative of GL ---
+// d GL(psi; mu) / d mu for A = mu A_1 (the continuation parameter of Sec. 4):
+// the diagonal of K-hat does not depend on mu, and the link variable of the
+// forward edge along axis a leaving node c is U = exp(-i mu phi1) with
+// phi1 = h_a A_1,a(edge midpoint), so dU/dmu = -i phi1 U.  With the stencil
+// of K-hat, (dK-hat/dmu x)_i = sum_a alpha_a [ i phi1(k) U_a[k] x_k
+// - i phi1(i) conj(U_a[i]) x_j ] (k = i - s_a, j = i + s_a), and
+// GL_mu = D^-1 (dK-hat/dmu) psi.
+struct FieldDeriv {
+    double m1[3][3];  // A_1 = m1 r
+    double lo[3];     // coordinate of node 0 along each axis
+};
+
+template <int DIM>
+__device__ __forceinline__ double edge_phase1(const GeomT<double> &g, const FieldDeriv &fd, int a, const int c[3],
+                                              int ca)
+{
+    double ph = 0.0;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+        const double mid = fd.lo[b] + (b == a ? ca : c[b]) * g.h[b] + (b == a ? 0.5 * g.h[a] : 0.0);
+        ph += fd.m1[a][b] * mid;
+    }
+    return g.h[a] * ph;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_gl_dmu(GeomT<double> g, const double2 *__restrict__ psi,
+                                                   const LinkTab<double> U, FieldDeriv fd,
+                                                   double2 *__restrict__ out)
+{
+    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    double s[3];
+    const double d = node_volume<DIM, double>(g, c, s);
+    double2 acc = make_double2(0.0, 0.0);
+    int stride = 1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        const double al = d * s[a] * g.inv_h2[a];
+        if (c[a] > 0) {
+            const double ph = edge_phase1<DIM>(g, fd, a, c, c[a] - 1);
+            const double2 w = cmul(link_u<DIM, double>(U, a, c, c[a] - 1), psi[i - stride]);
+            // + al i ph w
+            acc.x -= al * ph * w.y;
+            acc.y += al * ph * w.x;
+        }
+        if (c[a] < g.N[a] - 1) {
+            const double ph = edge_phase1<DIM>(g, fd, a, c, c[a]);
+            const double2 w = cmulc(link_u<DIM, double>(U, a, c, c[a]), psi[i + stride]);
+            // - al i ph w
+            acc.x += al * ph * w.y;
+            acc.y -= al * ph * w.x;
+        }
+        stride *= g.N[a];
+    }
+    out[i] = cscale(acc, 1.0 / d);
+}
+
+// out = a x + b y (out may alias x or y)
+__global__ void k_axpby(int n, double a, const double2 *x, double b, const double2 *y, double2 *out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) {
+        const double2 xi = x[i], yi = y[i];
+        out[i] = make_double2(a * xi.x + b * yi.x, a * xi.y + b * yi.y);
+    }
+}
+
 // y = D x
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_scale_volume(GeomT<double> g, const double2 *__restrict__ x,
@@ -517,6 +588,65 @@ gl_status gl_secant_predict(const gl_mesh *mesh, const void *psi_m, const void *
         if (!std::isfinite(ratio)) fail(GL_ERR_INVALID_ARGUMENT, "gl_secant_predict: ratio");
         secant_enqueue(mesh, (const double2 *)psi_m, (const double2 *)psi_prev, ratio, (double2 *)out,
                        as_stream(stream));
+    });
+}
+
+gl_status gl_residual_dmu(const gl_mesh *mesh, const void *psi, void *out, gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !psi || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual_dmu: NULL argument");
+        if (out == psi) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual_dmu: out aliases psi");
+        if (mesh->desc.potential != 0)
+            fail(GL_ERR_UNSUPPORTED, "gl_residual_dmu: the mesh has no field-strength parameter");
+        FieldDeriv fd;
+        double m1[9];
+        compute_amat(mesh->desc, 1.0, m1);
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) fd.m1[a][b] = m1[3 * a + b];
+            fd.lo[a] = -0.5 * mesh->g.h[a] * (mesh->g.N[a] - 1);
+        }
+        const int nb = blocks_for(mesh->g.n);
+        const GeomT<double> g = geom_t<double>(mesh->g);
+        hipStream_t s = as_stream(stream);
+        if (mesh->g.dim == 2)
+            k_gl_dmu<2><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, link_tab<double>(mesh), fd, (double2 *)out);
+        else
+            k_gl_dmu<3><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, link_tab<double>(mesh), fd, (double2 *)out);
+        GLK_CHECK_LAUNCH();
+    });
+}
+
+gl_status gl_inner(const gl_mesh *mesh, const void *u, const void *v, double *out, gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !u || !v || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_inner: NULL argument");
+        const int nb = blocks_for(mesh->g.n);
+        const GeomT<double> g = geom_t<double>(mesh->g);
+        hipStream_t s = as_stream(stream);
+        if (mesh->g.dim == 2)
+            k_cdot<2><<<nb, kBlock, 0, s>>>(g, (const double2 *)u, (const double2 *)v, red_slot(mesh, 2),
+                                            red_slot(mesh, 3));
+        else
+            k_cdot<3><<<nb, kBlock, 0, s>>>(g, (const double2 *)u, (const double2 *)v, red_slot(mesh, 2),
+                                            red_slot(mesh, 3));
+        GLK_CHECK_LAUNCH();
+        launch_finalize(red_slot(mesh, 2).partials, nb, FIN_STORE, nullptr, mesh->dscal.get() + 6, nullptr, s);
+        GLK_HIP(hipMemcpyAsync(mesh->hscal + 6, mesh->dscal.get() + 6, sizeof(double), hipMemcpyDeviceToHost, s));
+        GLK_HIP(hipStreamSynchronize(s));
+        *out = mesh->hscal[6];
+    });
+}
+
+gl_status gl_axpby(const gl_mesh *mesh, double a, const void *x, double b, const void *y, void *out,
+                   gl_stream stream)
+{
+    return guarded([&] {
+        if (!mesh || !x || !y || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_axpby: NULL argument");
+        if (!std::isfinite(a) || !std::isfinite(b)) fail(GL_ERR_INVALID_ARGUMENT, "gl_axpby: coefficient");
+        const int n = mesh->g.n;
+        k_axpby<<<blocks_for(n), kBlock, 0, as_stream(stream)>>>(n, a, (const double2 *)x, b, (const double2 *)y,
+                                                                 (double2 *)out);
+        GLK_CHECK_LAUNCH();
     });
 }
 

@@ -25,7 +25,8 @@ EXPORT = {"agg": 0, "root": 1, "color": 2, "A_rp": 3, "A_ci": 4, "A_v": 5, "P_rp
 
 EXPORTED_SYMBOLS = [
     "gl_mesh_create_grid", "gl_mesh_set_field", "gl_mesh_num_nodes", "gl_mesh_export_links",
-    "gl_mesh_destroy", "gl_residual", "gl_residual_noalloc", "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
+    "gl_mesh_destroy", "gl_residual", "gl_residual_noalloc", "gl_residual_dmu", "gl_inner", "gl_axpby",
+    "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
     "gl_precond_apply",
     "gl_precond_info", "gl_precond_export", "gl_precond_destroy", "gl_jacobian_solve",
     "gl_newton_solve", "gl_precond_set_tiles", "gl_precond_get_tiles", "gl_batch_create",
@@ -104,6 +105,9 @@ def lib():
     L.gl_mesh_destroy.restype = None
     L.gl_residual.argtypes = [vp, vp, vp, P(C.c_double), vp]
     L.gl_residual_noalloc.argtypes = [vp, vp, vp, P(C.c_double), vp]
+    L.gl_residual_dmu.argtypes = [vp, vp, vp, vp]
+    L.gl_inner.argtypes = [vp, vp, vp, P(C.c_double), vp]
+    L.gl_axpby.argtypes = [vp, C.c_double, vp, C.c_double, vp, vp, vp]
     L.gl_jacobian_apply.argtypes = [vp, vp, vp, vp, vp]
     L.gl_secant_predict.argtypes = [vp, vp, vp, C.c_double, vp, vp]
     L.gl_precond_setup.argtypes = [vp, vp, P(AmgOpts), P(vp), vp]
@@ -188,6 +192,7 @@ class Mesh:
         self._h = h
         self.dim = dim
         self.shape = tuple(int(v) for v in n_axis[:dim])
+        self.side = tuple(float(v) for v in side[:dim])
         nn = C.c_int64()
         _check(lib().gl_mesh_num_nodes(h, C.byref(nn)), "gl_mesh_num_nodes")
         self.n = nn.value
@@ -235,6 +240,26 @@ def gl_residual_noalloc(mesh, psi, out=None, norm=True, stream=None):
                                      _vec(out, mesh.n, "out") if out is not None else None,
                                      C.byref(nd) if norm else None, _stream(stream)), "gl_residual_noalloc")
     return nd.value if norm else None
+
+
+def gl_residual_dmu(mesh, psi, out, stream=None):
+    """out = d GL(psi; mu) / d mu at the mesh's current mu."""
+    _check(lib().gl_residual_dmu(mesh.handle, _vec(psi, mesh.n, "psi"), _vec(out, mesh.n, "out"),
+                                 _stream(stream)), "gl_residual_dmu")
+
+
+def gl_inner(mesh, u, v, stream=None):
+    """<u, v>_R = Re sum |V_i| conj(u_i) v_i."""
+    r = C.c_double()
+    _check(lib().gl_inner(mesh.handle, _vec(u, mesh.n, "u"), _vec(v, mesh.n, "v"), C.byref(r), _stream(stream)),
+           "gl_inner")
+    return r.value
+
+
+def gl_axpby(mesh, a, x, b, y, out, stream=None):
+    """out = a x + b y (real a, b; out may alias x or y)."""
+    _check(lib().gl_axpby(mesh.handle, float(a), _vec(x, mesh.n, "x"), float(b), _vec(y, mesh.n, "y"),
+                          _vec(out, mesh.n, "out"), _stream(stream)), "gl_axpby")
 
 
 def gl_jacobian_apply(mesh, psi, phi, out, stream=None):
