@@ -265,6 +265,24 @@ class Amg:
         return x
 
 
+def precond_exact(mesh, psi, r):
+    """R_inf(psi) r = H^-1 D r with H = K-hat + 2 D |psi|^2 (eq. prec1): the
+    preconditioner the V-cycles approximate, by a sparse direct solve."""
+    import scipy.sparse.linalg as spla
+    H = mesh.hmat(psi).tocsc()
+    return spla.spsolve(H, mesh.vol * _c128(r))
+
+
+def minres_exact_precond(mesh, psi, b, rtol=1e-10, max_iter=1000):
+    """MINRES for J(psi) x = b preconditioned by R_inf (one sparse LU of H,
+    reused for every application).  Returns (x, info, history)."""
+    import scipy.sparse.linalg as spla
+    psi = _c128(psi)
+    lu = spla.splu(mesh.hmat(psi).tocsc())
+    return minres_generic(mesh.vol, lambda x: mesh.jac(psi, x), b,
+                          minv=lambda r: lu.solve(mesh.vol * r), rtol=rtol, max_iter=max_iter)
+
+
 def _kinfo(ki):
     return {"iterations": ki.iterations, "converged": bool(ki.converged), "eta0": ki.eta0,
             "eta": ki.eta, "res_true": ki.res_true}

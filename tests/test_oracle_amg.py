@@ -356,3 +356,33 @@ def test_singular_preconditioner_detected():
     with pytest.raises(oracle.OracleError) as e:
         oracle.Amg.for_state(m, np.zeros(m.n))
     assert e.value.code == oracle.ORC_ERR_SINGULAR
+
+
+def test_exact_preconditioner_is_the_limit_of_the_cycles():
+    """R_inf = H^-1 D by a sparse direct solve (eq. prec1) equals the dense
+    inverse, and R_k reaches it to 1e-12 as k grows (the paper's R_10 stands
+    in for R_inf)."""
+    m = oracle.Mesh(2, (17, 17), (5.0, 5.0), mu=0.8)
+    psi = inputs.random_phase_state(m.n, seed=8)
+    r = inputs.random_complex(m.n, seed=9)
+    ex = oracle.precond_exact(m, psi, r)
+    H = m.hmat(psi).toarray()
+    np.testing.assert_allclose(ex, np.linalg.solve(H, m.vol * r), rtol=1e-12, atol=1e-13)
+    amg = oracle.Amg.for_state(m, psi, max_coarse=10)
+    errs = [np.abs(amg.precond(m, r, k) - ex).max() / np.abs(ex).max() for k in (1, 5, 40)]
+    assert errs[0] > errs[1] > errs[2] and errs[2] < 1e-12
+
+
+def test_minres_with_exact_preconditioner():
+    """MINRES with R_inf solves J x = b (dense check) and needs fewer
+    iterations than with R_1 (Fig. 1: R_inf is the ideal SPD preconditioner)."""
+    m = oracle.Mesh(2, (17, 17), (5.0, 5.0), mu=0.8)
+    psi = inputs.random_phase_state(m.n, seed=10)
+    b = inputs.random_complex(m.n, seed=11)
+    x, info, _ = oracle.minres_exact_precond(m, psi, b, rtol=1e-12, max_iter=500)
+    assert info["converged"]
+    r = b - m.jac(psi, x)
+    assert m.norm(r) < 1e-10 * m.norm(b)
+    amg = oracle.Amg.for_state(m, psi, max_coarse=10)
+    _, i1, _ = oracle.minres(m, psi, b, amg=amg, rtol=1e-12, max_iter=500)
+    assert info["iterations"] < i1["iterations"]
