@@ -408,6 +408,75 @@ def bench_arclength(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_fig1(args):
+    """Fig. 1 protocol: J(psi = 1) x = 1 from x = 0 on the square of side
+    5 sqrt 2 with 1001^2 nodes (about the paper's 1000^2 unknowns), A_z with
+    mu = 1; MINRES without preconditioner and with R_k, k = 1, 2, 5, 10, and
+    R_inf (conjugate gradients with the V-cycle, fixed steps); iterations to
+    1e-8, 1e-10, 1e-11, 1e-12, and the cost per iteration and per solve in
+    units of one Jacobian application, measured."""
+    import math
+
+    import torch
+
+    from paper_1204_5125_amd import glnk
+    torch.cuda.set_device(0)
+    N, side = 1001, 5.0 * math.sqrt(2.0)
+    mesh = glnk.Mesh(2, (N, N), (side, side), mu=1.0)
+    ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
+    x = torch.empty_like(ones)
+    out = torch.empty_like(ones)
+    for _ in range(3):
+        glnk.gl_jacobian_apply(mesh, ones, ones, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(50):
+        glnk.gl_jacobian_apply(mesh, ones, ones, out)
+    e1.record()
+    torch.cuda.synchronize()
+    t_mv = e0.elapsed_time(e1) / 50 * 1e-3
+    tols = (1e-8, 1e-10, 1e-11, 1e-12)
+    paper = {"0": None, "1": [20, 26, 28, 30], "2": [14, 21, 25, 27], "5": [7, 13, 15, 18], "10": [7, 9, 9, 10]}
+    rows = {}
+    for k in (0, 1, 2, 5, 10, "inf"):
+        pre = None
+        if k != 0:
+            pre = glnk.Precond(mesh, ones, cycles=0 if k == "inf" else k, max_coarse=64)
+        counts, secs = [], []
+        for tol in tols:
+            glnk.gl_jacobian_solve(mesh, ones, pre, ones, x, rtol=tol, max_iter=500 if k == 0 else 200,
+                                   poll_every=16, raise_on_fail=False)  # graph capture and warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, info = glnk.gl_jacobian_solve(mesh, ones, pre, ones, x, rtol=tol, max_iter=500 if k == 0 else 200,
+                                              poll_every=16, raise_on_fail=False)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t0)
+            counts.append(info["iterations"] if info["converged"] else None)
+        it10 = counts[1]
+        row = {"iterations": dict(zip(["1e-8", "1e-10", "1e-11", "1e-12"], counts)),
+               "vcycles_per_iteration": pre.inner_steps() if pre is not None else 0,
+               "seconds_to_1e-10": secs[1],
+               "matvec_equiv_per_iteration": (secs[1] / it10 / t_mv) if it10 else None,
+               "matvec_equiv_to_1e-10": secs[1] / t_mv,
+               "paper_iterations": paper.get(str(k))}
+        rows[str(k)] = row
+        log(f"[bench] fig1 k={k}: {row}")
+    best = min((r for r in rows.values() if r["iterations"]["1e-10"]), key=lambda r: r["seconds_to_1e-10"])
+    out = {
+        "metric": "Jacobian solve time to 1e-10 with the cheapest R_k (Fig. 1 protocol)",
+        "value": best["seconds_to_1e-10"] * 1e3, "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": best["seconds_to_1e-10"] * 1e3, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic: psi = 1, b = 1, x0 = 0",
+        "config": {"workload": "2D 1001x1001 grid (1,002,001 nodes), side 5 sqrt 2, A_z with mu = 1; MINRES "
+                               "with R_k, k = 0 (none), 1, 2, 5, 10, inf"},
+        "matvec_seconds": t_mv, "rows": rows,
+        "cheapest_k": [k for k, r in rows.items() if r is best][0],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_meshind(args):
     """Mesh independence of R_1 (Fig. 3 protocol): J(psi = 1) x = 1 from x = 0
     to rtol 1e-11 with one V-cycle per MINRES step, uniform field mu = 1 along
@@ -540,7 +609,8 @@ def bench_cube(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["jacobian", "batch", "continuation", "cube", "meshind", "arclength"],
+    ap.add_argument("--workload", choices=["jacobian", "batch", "continuation", "cube", "meshind", "arclength",
+                                           "fig1"],
                     default="jacobian",
                     help="jacobian: the 1M-node Jacobian solves (headline); batch: batched continuation; "
                          "continuation: learned vs secant predictor; cube: 3D 129^3 mixed precision; "
@@ -581,6 +651,9 @@ def main():
         return
     if args.workload == "arclength":
         bench_arclength(args)
+        return
+    if args.workload == "fig1":
+        bench_fig1(args)
         return
 
     import torch

@@ -160,7 +160,14 @@ gl_status gl_axpby(const gl_mesh *mesh, double a, const void *x, double b, const
 /* --------------------------------------------------- preconditioner ---- */
 typedef struct {
     gl_precision precision; /* storage and arithmetic of the V-cycle */
-    int cycles;             /* k in R_k (>= 1; 1 is the paper's choice) */
+    int cycles;             /* k in R_k (>= 1; 1 is the paper's choice);
+                               0: R_inf = H^-1 D (eq. prec1) to about 1e-12:
+                               conjugate gradients on H x = D r from 0 with one
+                               V-cycle per step as preconditioner, for a fixed
+                               number m of steps chosen at each setup as the
+                               steps that take a seeded right-hand side's
+                               residual below 1e-12, plus 2 (at most 64;
+                               gl_precond_inner_steps); GL_FP64 only */
     int max_coarse;         /* coarsening stops at <= max_coarse rows (default 64) */
     int max_levels;         /* <= 16 */
 } gl_amg_opts;
@@ -196,6 +203,10 @@ gl_status gl_precond_info(const gl_precond *pre, int *nlev, int64_t *sizes, int6
  * whatever the storage precision. */
 gl_status gl_precond_export(const gl_precond *pre, int level, int what, void *host_buf,
                             size_t *bytes);
+
+/* V-cycles per application of the preconditioner: k for R_k, m for R_inf
+ * (cycles == 0). */
+gl_status gl_precond_inner_steps(const gl_precond *pre, int *steps);
 
 void gl_precond_destroy(gl_precond *pre);
 

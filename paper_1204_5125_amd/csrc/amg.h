@@ -233,6 +233,11 @@ struct gl_precond {
     glk::DevBuf<int> status;       // device status word of the numeric setup
     glk::DevBuf<double> cdmax;     // largest diagonal entry of the coarsest operator
     glk::DevBuf<double2> cyc_r;    // k > 1 cycles: level-0 residual (and a setup scratch vector)
+    // R_inf (cycles == 0): conjugate gradients on H x = v with the V-cycle as
+    // preconditioner, a fixed number pcg_m of steps chosen at each setup
+    glk::DevBuf<double2> pcg;      // x, r, p, q, z (5 n)
+    glk::DevBuf<double> pcg_sc;    // <r_j, z_j> (j = 0 .. m) then <p_j, H p_j> (j = 0 .. m-1)
+    int pcg_m = 0;
     glk::DevBuf<double2> vin;      // gl_precond_apply: D r (and a setup scratch vector)
     glk::DevBuf<double> pwn;       // setup: norms of the spectral-radius estimate
     glk::DevBuf<char> bdesc64, bdesc32;  // BottomDesc<double>, BottomDesc<float>
@@ -264,6 +269,8 @@ void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, dou
 void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, double2 *out,
                       hipStream_t s);
 void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s);
+void pcg_calibrate(gl_precond *pre, hipStream_t s);  // R_inf: the CG step count of this setup
+constexpr int kPcgMaxSteps = 64;
 void scale_by_volume(const gl_mesh *m, const double2 *x, double2 *y, hipStream_t s);
 void bottom_descriptors(gl_precond *pre, hipStream_t s);
 void form_tail(gl_precond *pre, hipStream_t s);  // after a numeric setup

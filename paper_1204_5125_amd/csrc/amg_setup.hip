@@ -1473,6 +1473,7 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
     GLK_CHECK_LAUNCH();
     pre->has_values = true;
     form_tail(pre, s);
+    if (pre->opts.cycles == 0) pcg_calibrate(pre, s);
 }
 
 }  // namespace glk
@@ -1502,8 +1503,10 @@ gl_status gl_precond_setup(const gl_mesh *mesh, const void *psi, const gl_amg_op
         if (opts) {
             if (opts->precision != GL_FP64 && opts->precision != GL_FP32 && opts->precision != GL_MIXED)
                 fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: precision");
-            if (opts->cycles < 1 || opts->cycles > 1000)
-                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: cycles must be in 1..1000");
+            if (opts->cycles < 0 || opts->cycles > 1000)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: cycles must be in 0..1000");
+            if (opts->cycles == 0 && opts->precision != GL_FP64)
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: R_inf (cycles 0) needs the FP64 V-cycle");
             if (opts->max_coarse < 1 || opts->max_coarse > kMaxDense)
                 fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: max_coarse must be in 1..2048");
             if (opts->max_levels < 1 || opts->max_levels > kMaxLevels)
@@ -1531,6 +1534,14 @@ gl_status gl_precond_setup(const gl_mesh *mesh, const void *psi, const gl_amg_op
             }
             precond_numeric(pre, (const double2 *)psi, s);
         }
+    });
+}
+
+gl_status gl_precond_inner_steps(const gl_precond *pre, int *steps)
+{
+    return guarded([&] {
+        if (!pre || !steps) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_inner_steps: NULL argument");
+        *steps = pre->opts.cycles == 0 ? pre->pcg_m : pre->opts.cycles;
     });
 }
 

@@ -584,7 +584,8 @@ static hipGraphExec_t iteration_graph(Ksolve k, hipStream_t s)
     gl_mesh *m = const_cast<gl_mesh *>(k.m);
     const uint64_t key[6] = {(uint64_t)(uintptr_t)k.psi, (uint64_t)(uintptr_t)k.rhs, (uint64_t)(uintptr_t)k.x,
                              k.pre ? k.pre->uid : 0,
-                             (k.pre ? (uint64_t)(k.prec * 4096 + k.pre->opts.cycles) : 0) | ((uint64_t)k.defl << 40),
+                             (k.pre ? (uint64_t)(k.prec * 4096 + k.pre->opts.cycles) : 0) | ((uint64_t)k.defl << 40) |
+                                 (k.pre ? (uint64_t)k.pre->pcg_m << 48 : 0),
                              (uint64_t)(uintptr_t)k.v};
     for (auto &e : m->graphs)
         if (std::memcmp(e.key, key, sizeof(key)) == 0) return e.exec;
@@ -1134,6 +1135,7 @@ static void batch_iterate(gl_batch *B, double2 *const *psi, bool refine, bool us
             key.push_back((uint64_t)(uintptr_t)psi[i]);
             key.push_back(p ? p->uid : 0);
             key.push_back(p ? (uint64_t)(p->opts.precision * 4096 + p->opts.cycles) : 0);
+            key.push_back(p ? (uint64_t)p->pcg_m : 0);
         }
         return key;
     };

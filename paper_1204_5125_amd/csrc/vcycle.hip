@@ -34,6 +34,24 @@ namespace glk {
 // the flag is uniform, so every thread takes the same branch.
 #define GATE_LOAD() const bool gate_go = gate == nullptr || *gate != 0
 
+// a seeded right-hand side in [-1, 1]^2 per node (MurmurHash3 finaliser of
+// the node index), for calibrating R_inf
+__global__ void k_hash_rhs(int n, double2 *v)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    auto mix = [](uint32_t h) {
+        h ^= h >> 16;
+        h *= 0x85ebca6bu;
+        h ^= h >> 13;
+        h *= 0xc2b2ae35u;
+        h ^= h >> 16;
+        return h;
+    };
+    const uint32_t a = mix(2u * (uint32_t)i + 0x9e3779b9u), b = mix(2u * (uint32_t)i + 1u + 0x9e3779b9u);
+    v[i] = make_double2(a * (2.0 / 4294967295.0) - 1.0, b * (2.0 / 4294967295.0) - 1.0);
+}
+
 // Level-0 colour passes run one thread per red-black pair: thread t owns the
 // nodes c0 = 2k and 2k + 1 of x-row `row` (k = t mod hr, row = t / hr), one
 // of each colour, so every thread updates a node (a thread per node would
@@ -1027,7 +1045,8 @@ static void csr_residual(Level &Lv, int shift, const int *gate, const Launch &L)
 // coarsest solve (latency-bound: their precision costs no bandwidth)
 template <int DIM, class T, class TC>
 static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
-                        const int *gate, KrylovScalars *ks, int mode, int add, const Launch &L)
+                        const int *gate, KrylovScalars *ks, int mode, int add, const Launch &L,
+                        double *store = nullptr)
 {
     gl_precond *pre = const_cast<gl_precond *>(cpre);
     const gl_mesh *m = pre->mesh;
@@ -1040,14 +1059,16 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const bool f32 = std::is_same<T, float>::value;
     C<T> *b0 = vec_b<T>(L0);
     C<T> *x0 = vec_x<T>(L0);
-    const int want = ks != nullptr;
+    // Re<vdot, z> is reduced for the Krylov scalars (ks) or stored (store)
+    const int want = ks != nullptr || store != nullptr;
+    const int fmode = store ? (int)FIN_STORE : mode;
     if (nl == 1) {
         C<TC> *xc0 = vec_x<TC>(L0);
         L.run(nb0, Narrow<TC>{n0, v, vec_b<TC>(L0), gate});
         L.run(blocks_for((int64_t)n0 * 64), DenseApply<TC>{n0, cinv<TC>(pre), vec_b<TC>(L0), xc0, gate});
         if (add) L.run(nb0, Output<TC, 1>{n0, xc0, vdot, z, slot, want, gate});
         else L.run(nb0, Output<TC, 0>{n0, xc0, vdot, z, slot, want, gate});
-        if (ks) launch_finalize(slot.partials, nb0, mode, ks, nullptr, gate, L);
+        if (want) launch_finalize(slot.partials, nb0, fmode, ks, store, gate, L);
         return;
     }
     const T *hd = diag<T>(L0), *hs = hsplit<T>(L0);
@@ -1119,7 +1140,213 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
         if (add) L.run(nbp, L0Last<DIM, T, 1>{g, b0, x0, U, hs, z, vdot, slot, want, gate});
         else L.run(nbp, L0Last<DIM, T, 0>{g, b0, x0, U, hs, z, vdot, slot, want, gate});
     });
-    if (ks) launch_finalize(slot.partials, nbp, mode, ks, nullptr, gate, L);
+    if (want) launch_finalize(slot.partials, nbp, fmode, ks, store, gate, L);
+}
+
+// ------------------------------------------------------------- R_inf ---
+// R_inf = H^-1 (eq. prec1; the scaled form of H^-1 D): preconditioned
+// conjugate gradients on H x = v from x = 0 with one V-cycle per step, run
+// for a fixed number m of steps (chosen at each setup, pcg_calibrate), so
+// that the operator is a fixed linear map to the calibration's accuracy and
+// the steps can be captured in the MINRES iteration graph.  Scalars of step
+// j live at fixed places: rz[j] = <r_j, z_j>, pq[j] = <p_j, H p_j>.
+
+// q = H p (level 0 as the FP64 stencil with its diagonal), partials of Re<p, q>
+template <int DIM>
+struct PcgHp {
+    GeomT<double> g;
+    const double2 *p;
+    LinkTab<double> U;
+    const double *hd;
+    double2 *q;
+    RedSlot slot;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE();
+        __shared__ double sm[kBlock / 64];
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < g.n) {
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            const double2 pi = p[i];
+            const double2 qi = cadd(khat_offdiag<DIM, double>(g, i, c, p, U), cscale(pi, hd[i]));
+            q[i] = qi;
+            part = redot(pi, qi);
+        }
+        block_reduce_store(part, slot, sm, bx);
+    }
+};
+
+// x += alpha p (x = alpha p at the first step), r -= alpha q, alpha = rz / pq
+// (0 when pq is not positive: nothing left to reduce); partials of |r|^2
+// when asked (calibration)
+struct PcgStep {
+    int n;
+    const double2 *p, *q;
+    double2 *x, *r;
+    const double *rz, *pq;
+    int first;
+    RedSlot slot;
+    int want_rr;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        __shared__ double sm[kBlock / 64];
+        const double den = *pq;
+        const double alpha = den > 0.0 ? *rz / den : 0.0;
+        const int i = bx * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < n) {
+            const double2 pi = p[i], qi = q[i];
+            x[i] = first ? cscale(pi, alpha) : cadd(x[i], cscale(pi, alpha));
+            const double2 ri = csub(r[i], cscale(qi, alpha));
+            r[i] = ri;
+            part = cabs2(ri);
+        }
+        if (want_rr) block_reduce_store(part, slot, sm, bx);
+    }
+};
+
+// p = z + beta p, beta = rz_new / rz (0 when rz is not positive)
+struct PcgDir {
+    int n;
+    const double2 *z;
+    double2 *p;
+    const double *rz, *rz_new;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const double den = *rz;
+        const double beta = den > 0.0 ? *rz_new / den : 0.0;
+        const int i = bx * kBlock + threadIdx.x;
+        if (i < n) p[i] = cadd(z[i], cscale(p[i], beta));
+    }
+};
+
+// partials of |r|^2 (calibration)
+struct PcgNorm {
+    int n;
+    const double2 *r;
+    RedSlot slot;
+    __device__ void operator()(int bx, int) const
+    {
+        __shared__ double sm[kBlock / 64];
+        const int i = bx * kBlock + threadIdx.x;
+        block_reduce_store(i < n ? cabs2(r[i]) : 0.0, slot, sm, bx);
+    }
+};
+
+// r = v (the first residual, x = 0)
+struct PcgInit {
+    int n;
+    const double2 *v;
+    double2 *r;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const int i = bx * kBlock + threadIdx.x;
+        if (i < n) r[i] = v[i];
+    }
+};
+
+struct PcgBufs {
+    double2 *x, *r, *p, *q, *z;
+    double *rz, *pq;
+};
+
+static PcgBufs pcg_bufs(const gl_precond *pre)
+{
+    gl_precond *p = const_cast<gl_precond *>(pre);
+    const size_t n = (size_t)pre->L[0].n;
+    double2 *b = p->pcg.get();
+    double *sc = p->pcg_sc.get();
+    return PcgBufs{b, b + n, b + 2 * n, b + 3 * n, b + 4 * n, sc, sc + kPcgMaxSteps + 1};
+}
+
+// m steps of CG; z = x with the Krylov partials of Re<vdot, z> when ks is set
+template <int DIM, class T, class TC>
+static void vcycle_pcg(const gl_precond *pre, const double2 *v, double2 *z, const int *gate, KrylovScalars *ks,
+                       int mode, const Launch &L)
+{
+    const gl_mesh *m = pre->mesh;
+    const GeomT<double> g = geom_t<double>(m->g);
+    const int n = pre->L[0].n, nb = blocks_for(n);
+    const PcgBufs B = pcg_bufs(pre);
+    const int steps = std::max(1, pre->pcg_m);
+    const RedSlot hslot = red_slot(m, 0);
+    L.run(nb, PcgInit{n, v, B.r, gate});
+    // z_0 = V(r_0) straight into p_0
+    vcycle_once<DIM, T, TC>(pre, B.r, B.r, B.p, gate, nullptr, 0, 0, L, B.rz);
+    for (int j = 0; j < steps; ++j) {
+        L.run(nb, PcgHp<DIM>{g, B.p, link_tab<double>(m), pre->L[0].diag64.get(), B.q, hslot, gate});
+        launch_finalize(hslot.partials, nb, FIN_STORE, nullptr, B.pq + j, gate, L);
+        L.run(nb, PcgStep{n, B.p, B.q, B.x, B.r, B.rz + j, B.pq + j, j == 0, hslot, 0, gate});
+        if (j + 1 < steps) {
+            vcycle_once<DIM, T, TC>(pre, B.r, B.r, B.z, gate, nullptr, 0, 0, L, B.rz + j + 1);
+            L.run(nb, PcgDir{n, B.z, B.p, B.rz + j, B.rz + j + 1, gate});
+        }
+    }
+    const RedSlot slot = red_slot(m, 1);
+    L.run(nb, Output<double, 0>{n, B.x, v, z, slot, ks != nullptr, gate});
+    if (ks) launch_finalize(slot.partials, nb, mode, ks, nullptr, gate, L);
+}
+
+template <int DIM>
+static void pcg_calibrate_dim(gl_precond *pre, hipStream_t s)
+{
+    // CG from a seeded counter-hash right-hand side with the norm of the
+    // residual read after every step: m = the steps to 1e-12, plus 2
+    const gl_mesh *m = pre->mesh;
+    const GeomT<double> g = geom_t<double>(m->g);
+    const int n = pre->L[0].n, nb = blocks_for(n);
+    const PcgBufs B = pcg_bufs(pre);
+    const RedSlot hslot = red_slot(m, 0), rslot = red_slot(m, 2);
+    double2 *v = pre->vin.get();
+    k_hash_rhs<<<nb, kBlock, 0, s>>>(n, v);
+    GLK_CHECK_LAUNCH();
+    const Launch L{s};
+    double *rr = m->dscal.get() + 8;
+    auto host_rr = [&]() {
+        double h = 0.0;
+        GLK_HIP(hipMemcpyAsync(&h, rr, sizeof(double), hipMemcpyDeviceToHost, s));
+        GLK_HIP(hipStreamSynchronize(s));
+        return h;
+    };
+    L.run(nb, PcgInit{n, v, B.r, nullptr});
+    L.run(nb, PcgNorm{n, B.r, rslot});
+    launch_finalize(rslot.partials, nb, FIN_STORE, nullptr, rr, nullptr, L);
+    const double rr0 = host_rr();
+    vcycle_once<DIM, double, double>(pre, B.r, B.r, B.p, nullptr, nullptr, 0, 0, L, B.rz);
+    int steps = kPcgMaxSteps;
+    for (int j = 0; j < kPcgMaxSteps; ++j) {
+        L.run(nb, PcgHp<DIM>{g, B.p, link_tab<double>(m), pre->L[0].diag64.get(), B.q, hslot, nullptr});
+        launch_finalize(hslot.partials, nb, FIN_STORE, nullptr, B.pq + j, nullptr, L);
+        L.run(nb, PcgStep{n, B.p, B.q, B.x, B.r, B.rz + j, B.pq + j, j == 0, rslot, 1, nullptr});
+        launch_finalize(rslot.partials, nb, FIN_STORE, nullptr, rr, nullptr, L);
+        if (!(host_rr() > 1e-24 * rr0)) {
+            steps = std::min(kPcgMaxSteps, j + 1 + 2);
+            break;
+        }
+        if (j + 1 < kPcgMaxSteps) {
+            vcycle_once<DIM, double, double>(pre, B.r, B.r, B.z, nullptr, nullptr, 0, 0, L, B.rz + j + 1);
+            L.run(nb, PcgDir{n, B.z, B.p, B.rz + j, B.rz + j + 1, nullptr});
+        }
+    }
+    pre->pcg_m = steps;
+}
+
+void pcg_calibrate(gl_precond *pre, hipStream_t s)
+{
+    const size_t n = (size_t)pre->L[0].n;
+    if (pre->pcg.count < 5 * n) pre->pcg.alloc(5 * n);
+    if (pre->pcg_sc.count < 2 * kPcgMaxSteps + 2) pre->pcg_sc.alloc(2 * kPcgMaxSteps + 2);
+    if (pre->mesh->g.dim == 2) pcg_calibrate_dim<2>(pre, s);
+    else pcg_calibrate_dim<3>(pre, s);
 }
 
 template <int DIM, class T, class TC>
@@ -1127,6 +1354,10 @@ static void vcycle_k(const gl_precond *pre, const double2 *v, double2 *z, const 
                      KrylovScalars *ks, int mode, const Launch &L)
 {
     const int k = pre->opts.cycles;
+    if (k == 0) {
+        vcycle_pcg<DIM, T, TC>(pre, v, z, gate, ks, mode, L);
+        return;
+    }
     if (k <= 1) {
         vcycle_once<DIM, T, TC>(pre, v, v, z, gate, ks, mode, 0, L);
         return;

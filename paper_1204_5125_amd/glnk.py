@@ -27,7 +27,7 @@ EXPORTED_SYMBOLS = [
     "gl_mesh_create_grid", "gl_mesh_set_field", "gl_mesh_num_nodes", "gl_mesh_export_links",
     "gl_mesh_destroy", "gl_residual", "gl_residual_noalloc", "gl_residual_dmu", "gl_inner", "gl_axpby",
     "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
-    "gl_precond_apply",
+    "gl_precond_apply", "gl_precond_inner_steps",
     "gl_precond_info", "gl_precond_export", "gl_precond_destroy", "gl_jacobian_solve",
     "gl_newton_solve", "gl_precond_set_tiles", "gl_precond_get_tiles", "gl_batch_create",
     "gl_batch_newton_solve", "gl_batch_set_tiles", "gl_batch_stats", "gl_batch_destroy",
@@ -112,6 +112,7 @@ def lib():
     L.gl_secant_predict.argtypes = [vp, vp, vp, C.c_double, vp, vp]
     L.gl_precond_setup.argtypes = [vp, vp, P(AmgOpts), P(vp), vp]
     L.gl_precond_apply.argtypes = [vp, vp, vp, vp]
+    L.gl_precond_inner_steps.argtypes = [vp, P(C.c_int)]
     L.gl_precond_info.argtypes = [vp, P(C.c_int), P(C.c_int64), P(C.c_int64), P(C.c_int)]
     L.gl_precond_export.argtypes = [vp, C.c_int, C.c_int, vp, P(C.c_size_t)]
     L.gl_precond_destroy.argtypes = [vp]
@@ -304,6 +305,12 @@ class Precond:
     def apply(self, r, z, stream=None):
         _check(lib().gl_precond_apply(self._h, _vec(r, self.mesh.n, "r"), _vec(z, self.mesh.n, "z"),
                                       _stream(stream)), "gl_precond_apply")
+
+    def inner_steps(self):
+        """V-cycles per application: k for R_k, the CG steps m for R_inf (cycles 0)."""
+        k = C.c_int()
+        _check(lib().gl_precond_inner_steps(self._h, C.byref(k)), "gl_precond_inner_steps")
+        return k.value
 
     def info(self):
         nlev = C.c_int()
