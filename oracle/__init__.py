@@ -70,6 +70,7 @@ def lib():
         L = C.CDLL(path)
         vp = C.c_void_p
         L.orc_mesh_build.argtypes = [C.c_int, _i64, _d, _d, C.POINTER(C.POINTER(_Mesh))]
+        L.orc_mesh_build_dipole.argtypes = [C.c_int, _i64, _d, C.c_double, _d, _d, C.POINTER(C.POINTER(_Mesh))]
         L.orc_mesh_free.argtypes = [C.POINTER(_Mesh)]
         for f in ("orc_khat_apply",):
             getattr(L, f).argtypes = [C.POINTER(_Mesh), vp, vp]
@@ -125,16 +126,23 @@ class Mesh:
     """Tensor grid on [-L/2, L/2]^dim with Voronoi volumes, edge coefficients,
     link variables and K-hat (Sec. 3)."""
 
-    def __init__(self, dim, N, L, amat=None, mu=None, bdir=(0.0, 0.0, 1.0)):
+    def __init__(self, dim, N, L, amat=None, mu=None, bdir=(0.0, 0.0, 1.0), dipole=None):
+        """dipole = (m, x0): the potential mu A_d(x) = mu m x (x - x0) / |x - x0|^3
+        (Sec. 4.1) instead of a linear one."""
         if amat is None:
-            amat = field_matrix(0.0 if mu is None else mu, bdir)
+            amat = field_matrix(0.0 if mu is None else mu, bdir) if dipole is None else np.zeros((3, 3))
         N = list(N) + [1] * (3 - len(N))
         L = list(L) + [0.0] * (3 - len(L))
         Na = (C.c_int64 * 3)(*N)
         La = (C.c_double * 3)(*L)
         am = (C.c_double * 9)(*np.asarray(amat, dtype=np.float64).ravel())
         p = C.POINTER(_Mesh)()
-        rc = lib().orc_mesh_build(dim, Na, La, am, C.byref(p))
+        if dipole is not None:
+            dm = (C.c_double * 3)(*[float(v) for v in dipole[0]])
+            dx = (C.c_double * 3)(*[float(v) for v in dipole[1]])
+            rc = lib().orc_mesh_build_dipole(dim, Na, La, 1.0 if mu is None else float(mu), dm, dx, C.byref(p))
+        else:
+            rc = lib().orc_mesh_build(dim, Na, La, am, C.byref(p))
         if rc != ORC_OK:
             raise OracleError(rc, "orc_mesh_build")
         self._p = p

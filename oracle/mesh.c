@@ -10,7 +10,12 @@
  *    3D (cube grid, degenerate Delaunay): alpha = |dual Voronoi facet| / |e|.
  *  - Link variable U_jk = exp(-i int_{x_k}^{x_j} e_jk . A(w) dw), integral taken
  *    along the straight edge; evaluated here by 3-point Gauss-Legendre, which is
- *    exact for the linear potentials used.
+ *    exact for the linear potentials A = M r.  The dipole potential of the
+ *    experiments (Sec. 4.1), A_d(x) = m x (x - x0) / |x - x0|^3 scaled by mu,
+ *    has a closed-form edge integral: with a = x_k - x0 and e = x_j - x_k,
+ *    e . (m x (a + t e)) = m . (a x e) for every t, and
+ *    int_0^1 q(t)^(-3/2) dt, q = A t^2 + B t + C (A = |e|^2, B = 2 a.e,
+ *    C = |a|^2), is [(4 A t + 2 B) / ((4 A C - B^2) sqrt q)] from 0 to 1.
  *  - Discrete kinetic energy operator (edge form) and the Remark K = D^-1 K-hat:
  *    K-hat_jj = sum alpha, K-hat_jk = -alpha U_jk, K-hat_kj = -alpha conj(U_jk).
  */
@@ -56,6 +61,24 @@ static double edge_integral(const double *amat, const double *xk, const double *
     return s;
 }
 
+/* the same integral for mu A_d (dip = {mu, m[3], x0[3]}), closed form */
+static double edge_integral_dipole(const double *dip, const double *xk, const double *xj)
+{
+    const double mu = dip[0], *mm = dip + 1, *x0 = dip + 4;
+    double a[3], e[3];
+    for (int c = 0; c < 3; ++c) { a[c] = xk[c] - x0[c]; e[c] = xj[c] - xk[c]; }
+    const double axe[3] = {a[1] * e[2] - a[2] * e[1], a[2] * e[0] - a[0] * e[2], a[0] * e[1] - a[1] * e[0]};
+    const double num = mm[0] * axe[0] + mm[1] * axe[1] + mm[2] * axe[2];
+    const double A = e[0] * e[0] + e[1] * e[1] + e[2] * e[2];
+    const double B = 2.0 * (a[0] * e[0] + a[1] * e[1] + a[2] * e[2]);
+    const double C = a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+    const double disc = 4.0 * A * C - B * B;
+    if (!(disc > 0.0)) return 0.0;  /* the edge's line passes through x0: m . (a x e) = 0 */
+    const double F1 = (4.0 * A + 2.0 * B) / (disc * sqrt(A + B + C));
+    const double F0 = 2.0 * B / (disc * sqrt(C));
+    return mu * num * (F1 - F0);
+}
+
 /* 1/2 cot of the angle at vertex p between the edges p->q and p->r
  * (Remark: alpha = 1/2 t / sqrt(1 - t^2), t the cosine of the angle). */
 static double half_cot(const double *p, const double *q, const double *r)
@@ -91,8 +114,25 @@ static int64_t edge_slot(const orc_mesh *m, int64_t lo, int64_t hi)
     return off + r;
 }
 
+static int mesh_build(int dim, const int64_t *N, const double *L, const double *amat, const double *dip,
+                      orc_mesh **out);
+
 int orc_mesh_build(int dim, const int64_t *N, const double *L, const double *amat,
                    orc_mesh **out)
+{
+    return mesh_build(dim, N, L, amat, NULL, out);
+}
+
+int orc_mesh_build_dipole(int dim, const int64_t *N, const double *L, double mu, const double *m,
+                          const double *x0, orc_mesh **out)
+{
+    static const double zero[9] = {0};
+    double dip[7] = {mu, m[0], m[1], m[2], x0[0], x0[1], x0[2]};
+    return mesh_build(dim, N, L, zero, dip, out);
+}
+
+static int mesh_build(int dim, const int64_t *N, const double *L, const double *amat, const double *dip,
+                      orc_mesh **out)
 {
     if (dim != 2 && dim != 3) return ORC_ERR_ARG;
     orc_mesh *m = calloc(1, sizeof(*m));
@@ -200,7 +240,8 @@ int orc_mesh_build(int dim, const int64_t *N, const double *L, const double *ama
         m->ej[q] = E[q].j;
         m->ek[q] = E[q].k;
         m->alpha[q] = E[q].alpha;
-        double phi = edge_integral(amat, &m->x[3 * E[q].k], &m->x[3 * E[q].j]);
+        double phi = dip ? edge_integral_dipole(dip, &m->x[3 * E[q].k], &m->x[3 * E[q].j])
+                         : edge_integral(amat, &m->x[3 * E[q].k], &m->x[3 * E[q].j]);
         m->U[q] = cexp(-I * phi);
     }
     free(E);

@@ -46,6 +46,10 @@ typedef struct {
 
 int  orc_mesh_build(int dim, const int64_t *N, const double *L, const double *amat,
                     orc_mesh **out);
+/* the same grid in the dipole potential mu A_d(x) = mu m x (x - x0) / |x - x0|^3
+ * (Sec. 4.1; 2D points are (x, y, 0)), link integrals in closed form */
+int  orc_mesh_build_dipole(int dim, const int64_t *N, const double *L, double mu, const double *m,
+                           const double *x0, orc_mesh **out);
 void orc_mesh_free(orc_mesh *m);
 
 /* --------------------------------------------------------- operators --- */

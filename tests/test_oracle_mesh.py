@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_1204_5125_amd import inputs
 
 
 def grid_coords(mesh):
@@ -153,3 +154,49 @@ def test_rayleigh_quotient_of_constant(mu):
     lhs = m.inner(one, m.khat_apply(one) / m.vol) / m.inner(one, one)
     rhs = (m.alpha * np.abs(2 * np.sin(np.angle(m.U) / 2)) ** 2).sum() / 25.0
     assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
+DIPOLE_3D = ((0.0, 0.0, 1.0), (0.0, 0.0, 6.0))   # Sec. 4.1: m = e_z, x0 = (0, 0, 6) in 3D
+DIPOLE_2D = ((0.0, 0.0, 1.0), (0.0, 0.0, 1.0))   # x0 = (0, 0, 1) above the 2D domains
+
+
+def test_dipole_links_equal_the_edge_integral():
+    """The closed-form link phases of mu A_d against adaptive quadrature of
+    the line integral along every edge (3D cube of circumradius 5 and the
+    2D square), and |U| = 1."""
+    from scipy.integrate import quad
+    for dim, N, L, (mm, x0) in ((3, (5, 4, 6), (5.77, 5.77, 5.77), DIPOLE_3D),
+                                (2, (7, 6), (7.07, 7.07), DIPOLE_2D)):
+        mu = 0.8
+        m = oracle.Mesh(dim, N, L, mu=mu, dipole=(mm, x0))
+        mm, x0 = np.asarray(mm), np.asarray(x0)
+        phases = -np.angle(m.U)
+        for q in range(m.ne):
+            xk, xj = m.x[m.ek[q]], m.x[m.ej[q]]
+            e = xj - xk
+
+            def f(t):
+                r = xk + t * e - x0
+                return e @ np.cross(mm, r) / np.linalg.norm(r) ** 3
+            ref = mu * quad(f, 0.0, 1.0, epsabs=1e-17, epsrel=1e-13, limit=200)[0]
+            assert phases[q] == pytest.approx(ref, rel=1e-11, abs=1e-15)
+        np.testing.assert_allclose(np.abs(m.U), 1.0, rtol=1e-15)
+
+
+def test_dipole_khat_hermitian_and_jacobian_identities():
+    """K-hat in the dipole potential is Hermitian positive definite; J is the
+    derivative of GL (central differences), self-adjoint in <.,.>_R, and
+    J(psi)(i psi) = i GL(psi)."""
+    m = oracle.Mesh(3, (5, 5, 5), (5.77, 5.77, 5.77), mu=1.0, dipole=DIPOLE_3D)
+    K = m.khat.toarray()
+    assert np.abs(K - K.conj().T).max() == 0.0
+    assert np.linalg.eigvalsh(K).min() > 0
+    psi = inputs.random_complex(m.n, seed=91)
+    phi = inputs.random_complex(m.n, seed=92)
+    chi = inputs.random_complex(m.n, seed=93)
+    eps = 1e-6
+    fd = (m.gl(psi + eps * phi) - m.gl(psi - eps * phi)) / (2 * eps)
+    jp = m.jac(psi, phi)
+    assert np.abs(fd - jp).max() < 1e-8 * np.abs(jp).max()
+    assert m.inner(phi, m.jac(psi, chi)) == pytest.approx(m.inner(m.jac(psi, phi), chi), rel=1e-12)
+    assert np.abs(m.jac(psi, 1j * psi) - 1j * m.gl(psi)).max() < 1e-12 * np.abs(m.gl(psi)).max()
