@@ -86,33 +86,84 @@ def timed(glnk, torch, mesh, psi0, psi, handle, precision, steps, relax=0.0):
     return time.perf_counter() - t0, infos
 
 
-def cpu_baseline(mean_iters):
-    """The serial C oracle on a bounded sample of the same workload: the first
-    Newton step in full, then the preconditioner setup and 60 MINRES
-    iterations of the second step's system.  Scaled to solves/s for a solve of
-    `mean_iters` iterations (the mean of the GPU run): setup + mean_iters x
-    the time per iteration."""
+def host_stream_add():
+    """Host memory bandwidth on one thread: a = b + c over 2^25 doubles per
+    array (24 bytes moved per element), best of 5 (numpy)."""
+    import numpy as np
+    n = 1 << 25
+    b, c = np.ones(n), np.ones(n)
+    a = np.empty(n)
+    best = float("inf")
+    for _ in range(5):
+        t0 = time.perf_counter()
+        np.add(b, c, out=a)
+        best = min(best, time.perf_counter() - t0)
+    return 24.0 * n / best / 1e9
+
+
+def cpu_baseline():
+    """The serial C oracle on one full Jacobian solve of the same workload:
+    the second Newton step's system (the first step, untimed, reaches its
+    state from the same psi0), timed from the preconditioner setup to the
+    MINRES solution at rtol 1e-10."""
+    import platform
+
     import oracle
     from paper_1204_5125_amd import inputs
     m = oracle.Mesh(2, N_AXIS, SIDE, mu=MU)
     psi0 = inputs.random_phase_state(m.n, seed=0)
-    t0 = time.perf_counter()
     psi, info = oracle.newton(m, psi0, fixed_steps=1, krylov_rtol=RTOL, krylov_max_iter=4000,
                               max_coarse=MAX_COARSE)
-    t_first = time.perf_counter() - t0
     t0 = time.perf_counter()
     amg = oracle.Amg.for_state(m, psi, max_coarse=MAX_COARSE)
     t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    _, ki, _ = oracle.minres(m, psi, -m.gl(psi), amg=amg, rtol=RTOL, max_iter=60)
-    t_iter = (time.perf_counter() - t0) / max(1, ki["iterations"])
-    per_solve = t_setup + mean_iters * t_iter
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"first Newton step in full ({info['krylov_iters'][0]} MINRES iterations, {t_first:.1f} s), "
-                      f"then the setup ({t_setup:.2f} s) and {ki['iterations']} MINRES iterations "
-                      f"({t_iter * 1e3:.0f} ms each) of the second step's system, on the same 1025x1025 grid "
-                      f"from the same psi0; scaled to a solve of {mean_iters:.0f} iterations (the GPU run's "
-                      f"mean), serial C (one host core)"}
+    _, ki, _ = oracle.minres(m, psi, -m.gl(psi), amg=amg, rtol=RTOL, max_iter=4000)
+    t_solve = time.perf_counter() - t0
+    t_iter = (t_solve - t_setup) / max(1, ki["iterations"])
+    bw = host_stream_add()
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    # the survey's per-iteration byte model of the FP64 path (594 B per node)
+    model = 594.0 * m.n
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full solve of the workload's second Newton system (1025x1025, from the same psi0 "
+                      f"after one untimed oracle Newton step): preconditioner setup {t_setup:.2f} s + "
+                      f"{ki['iterations']} MINRES iterations to 1e-10 ({t_iter * 1e3:.0f} ms each), "
+                      f"{t_solve:.1f} s, serial C on one host core",
+            "seconds_per_solve": t_solve, "minres_iterations": ki["iterations"],
+            "converged": bool(ki["converged"]), "res_true": ki["res_true"],
+            "host_cpu": cpu, "host_threads": os.cpu_count(),
+            "host_stream_add_gbs_1thread": bw,
+            "roofline": {"bound": "host memory", "achieved": model / t_iter / 1e9, "peak": bw, "unit": "GB/s",
+                         "frac": model / t_iter / 1e9 / bw,
+                         "note": "594 B per node per MINRES iteration (FP64 byte model) over the oracle's "
+                                 "time per iteration, against one thread's measured a = b + c bandwidth"}}
+
+
+def iteration_bytes(glnk, pre, precision):
+    """Algorithmic bytes of the V-cycle kernels the profiler does not count,
+    per MINRES iteration, from the handle's hierarchy: per multi-kernel
+    level >= 1 the residual (operator, b, x, r) and the transfers
+    (P / R entries, both vectors), and the dense product of the explicit
+    sub-cycle or coarsest inverse."""
+    info = pre.info()
+    tiles = glnk.gl_precond_get_tiles(pre)
+    sz = 16.0 if precision == glnk.GL_FP64 else 8.0
+    sizes, nnz = info["sizes"], info["nnz"]
+    nlev = info["nlev"]
+    dense = next((l for l in range(1, nlev) if sizes[l] <= tiles["dense_rows"]), nlev - 1)
+    total = 0.0
+    for l in range(1, dense):
+        total += nnz[l] * (4 + sz) + (sizes[l] + 1) * 4 + 3 * sizes[l] * sz          # residual
+    for l in range(1, dense):
+        pn = int(pre.export(l, "P_rp")[-1])
+        total += 2 * (pn * (4 + sz) + (sizes[l] + sizes[l + 1] + 2) * 4) + 3 * (sizes[l] + sizes[l + 1]) * sz
+    total += sizes[dense] ** 2 * sz + 2 * sizes[dense] * sz                          # dense product
+    return total
 
 
 def one_pass():
@@ -504,6 +555,19 @@ def bench_meshind(args):
         row["levels"] = pre.info()["sizes"]
         log(f"[bench] meshind {row}")
         rows.append(row)
+    # Fig. 3, cube in the dipole potential A_d (m = e_z at (0, 0, 6)), the
+    # paper's grids N = 5 ... 40 and two finer ones; the paper's R_1 counts
+    # for this panel are 6, 22, 29, 31, 31, 32, 32, 31
+    dip_rows = []
+    for n in (5, 10, 15, 20, 25, 30, 35, 40, 65, 129):
+        mesh = glnk.Mesh(3, (n,) * 3, (10.0 / 3 ** 0.5,) * 3, mu=1.0, dipole=((0, 0, 1), (0, 0, 6)))
+        ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
+        x = torch.empty_like(ones)
+        pre = glnk.Precond(mesh, ones, max_coarse=64)
+        rc, info = glnk.gl_jacobian_solve(mesh, ones, pre, ones, x, rtol=1e-11, max_iter=4000, poll_every=8,
+                                          raise_on_fail=False)
+        dip_rows.append({"N": n, "nodes": mesh.n, "iterations": info["iterations"], "status": rc})
+        log(f"[bench] meshind cube A_d {dip_rows[-1]}")
     it2 = [r["fp64"]["iterations"] for r in rows if r["dim"] == 2]
     it3 = [r["fp64"]["iterations"] for r in rows if r["dim"] == 3]
     out = {
@@ -515,6 +579,8 @@ def bench_meshind(args):
         "config": {"workload": "2D N = 33..1025 (side 10), 3D N = 9..129 (side 10/sqrt 3), mu 1 along z, "
                                "x0 = 0, rtol 1e-11, one V-cycle per step, max_coarse 512"},
         "iterations_2d_fp64": it2, "iterations_3d_fp64": it3, "grids": rows,
+        "cube_dipole_fig3": {"iterations": [r["iterations"] for r in dip_rows], "N": [r["N"] for r in dip_rows],
+                             "paper_R1": [6, 22, 29, 31, 31, 32, 32, 31]},
     }
     print(json.dumps(out), flush=True)
 
@@ -716,6 +782,24 @@ def main():
                 "kernel_ms_per_step": ms}
     roof = profile(args.profile_kernel)
     roof_l0 = profile(2) if args.profile_kernel != 2 else roof
+    # whole iteration: the algorithmic bytes of every profiled kernel class in
+    # one pass of the workload, plus the coarse residuals, transfers and the
+    # dense product from the hierarchy, per MINRES iteration, over the timed
+    # run's time per iteration
+    by_class = {}
+    for kid in sorted(KERNEL_NAMES):
+        glnk.gl_profile_start(kid)
+        infos = run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, 1)
+        _, nbytes, _ = glnk.gl_profile_stop()
+        by_class[KERNEL_NAMES[kid]] = nbytes / max(1, sum(infos[-1]["krylov_iters"]))
+    rest = iteration_bytes(glnk, h32, glnk.GL_FP32)
+    bytes_iter = sum(by_class.values()) + rest
+    t_iter32 = t32 / args.steps / sum(info32[-1]["krylov_iters"])
+    roof_iter = {"bound": "hbm", "kernel": "one MINRES iteration (all kernels)", "achieved": bytes_iter / t_iter32 / 1e9,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": bytes_iter / t_iter32 / 1e9 / HBM_PEAK_GBS,
+                 "bytes_per_iteration": bytes_iter, "us_per_iteration": t_iter32 * 1e6,
+                 "bytes_by_kernel_class": by_class, "bytes_coarse_residual_transfer_dense": rest,
+                 "traffic": None}
     # the peak measured two ways: vendor 8 TB/s, and a plain copy of the size
     # of one level-0 FP64 vector set (256 MiB in, 256 MiB out)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -766,10 +850,11 @@ def main():
                                  "final_gl_residual": infor[-1]["res"][-1]},
         "roofline": roof,
         "roofline_level0": roof_l0,
+        "roofline_iteration": roof_iter,
     }
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle, bounded sample of the workload)")
-        out["cpu_baseline"] = cpu_baseline(sum(iters64) / len(iters64))
+        log("[bench] cpu baseline (oracle, one full solve of the workload's second Newton system)")
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

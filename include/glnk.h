@@ -76,15 +76,25 @@ typedef void *gl_stream;
  *   potential == 0:  A(r) = mu/2 (b_dir x r)        (uniform field mu b_dir)
  *   potential == 1:  A(r) = a_matrix r               (3x3 row-major)
  * and U_jk = exp(-i (x_j - x_k) . A((x_j + x_k)/2)), the link variable of
- * Sec. 3 (exact for linear A).  In 2D, r = (x, y, 0). */
+ * Sec. 3 (exact for linear A), or
+ *   potential == 2:  A(r) = mu m x (r - x0) / |r - x0|^3
+ *                    (the dipole potential A_d of Sec. 4.1, moment
+ *                    dipole_m at dipole_x0; the paper's experiments use
+ *                    m = e_z and x0 = (0,0,6) in 3D, (0,0,1) in 2D)
+ * with U_jk = exp(-i int e . A) along the straight edge in closed form; its
+ * links are stored per edge (dim complex numbers per node, FP64 and FP32).
+ * In 2D, r = (x, y, 0). */
 typedef struct {
     int dim;            /* 2 or 3 */
     int64_t n_axis[3];  /* nodes per axis, >= 2 each (n_axis[2] ignored in 2D) */
     double side[3];     /* side lengths, > 0 */
-    int potential;      /* 0 or 1, see above */
-    double mu;          /* field strength (potential == 0) */
+    int potential;      /* 0, 1 or 2, see above */
+    double mu;          /* field strength (potential 0 and 2) */
     double b_dir[3];    /* field direction (potential == 0), need not be unit */
     double a_matrix[9]; /* potential == 1 */
+    double dipole_m[3]; /* potential == 2: dipole moment (nonzero) */
+    double dipole_x0[3];/* potential == 2: dipole position, off every grid edge's line
+                           segment */
 } gl_grid_desc;
 
 /* Build the grid and its link variables on the device.  Errors:
@@ -92,7 +102,7 @@ typedef struct {
  * OUT_OF_MEMORY, HIP. */
 gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mesh **out);
 
-/* Replace mu (potential == 0) and recompute the link variables: the
+/* Replace mu (potential 0 or 2) and recompute the link variables: the
  * continuation parameter of Sec. 4 (numerical parameter continuation). */
 gl_status gl_mesh_set_field(gl_mesh *mesh, double mu, gl_stream stream);
 
@@ -420,6 +430,24 @@ void gl_unet_destroy(gl_unet *unet);
  * benchmarking only (the events add a small gap between kernels). */
 gl_status gl_profile_start(int kernel_id);
 gl_status gl_profile_stop(double *ms_total, double *bytes_total, int64_t *launches);
+
+/* ---------------------------------------------------------- allocator -- */
+/* Device memory for the handles' workspaces (meshes, preconditioners,
+ * batches, U-Nets) from the caller's allocator, e.g. PyTorch's caching
+ * allocator: alloc(bytes, stream, ctx) returns device memory of the current
+ * device, aligned to 256 bytes, or NULL (the creating call then returns
+ * OUT_OF_MEMORY); release(ptr, stream, ctx) takes it back.  stream is NULL
+ * (the memory is used on the library's streams, and the device is
+ * synchronised before a buffer is released).  The allocator applies to
+ * buffers allocated after the call; each buffer is released through the
+ * allocator that gave it its memory, so release and ctx must stay valid
+ * until every handle created meanwhile is destroyed.  alloc == NULL and
+ * release == NULL restore hipMalloc / hipFree; setting only one of them is
+ * INVALID_ARGUMENT.  Not thread-safe: set it before creating handles.  Host
+ * (pinned) staging memory is not affected. */
+typedef void *(*gl_alloc_fn)(size_t bytes, gl_stream stream, void *ctx);
+typedef void (*gl_free_fn)(void *ptr, gl_stream stream, void *ctx);
+gl_status gl_set_allocator(gl_alloc_fn alloc, gl_free_fn release, void *ctx);
 
 /* ------------------------------------------------------------- errors -- */
 const char *gl_status_string(gl_status s);

@@ -55,32 +55,80 @@ gl_status guarded(F &&body)
 }
 
 // ---------------------------------------------------- device buffers ----
+// Device memory of every handle comes from here: the caller's allocator when
+// one is set (gl_set_allocator), hipMalloc otherwise.  A buffer remembers the
+// release function of the allocator that gave it its memory.
+struct Allocator {
+    gl_alloc_fn alloc = nullptr;
+    gl_free_fn release = nullptr;
+    void *ctx = nullptr;
+};
+Allocator &allocator();
+
 template <class T>
 struct DevBuf {
     T *p = nullptr;
     size_t count = 0;
+    gl_free_fn rel = nullptr;  // null: hipFree
+    void *rctx = nullptr;
     DevBuf() = default;
     explicit DevBuf(size_t c) { alloc(c); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), count(o.count) { o.p = nullptr; o.count = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), count(o.count), rel(o.rel), rctx(o.rctx)
+    {
+        o.p = nullptr;
+        o.count = 0;
+        o.rel = nullptr;
+        o.rctx = nullptr;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept
     {
-        if (this != &o) { release(); p = o.p; count = o.count; o.p = nullptr; o.count = 0; }
+        if (this != &o) {
+            release();
+            p = o.p;
+            count = o.count;
+            rel = o.rel;
+            rctx = o.rctx;
+            o.p = nullptr;
+            o.count = 0;
+            o.rel = nullptr;
+            o.rctx = nullptr;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t c)
     {
         release();
+        if (!c) return;
+        const Allocator &A = allocator();
+        if (A.alloc) {
+            p = static_cast<T *>(A.alloc(c * sizeof(T), nullptr, A.ctx));
+            if (!p) fail(GL_ERR_OUT_OF_MEMORY, "the caller's allocator returned no memory");
+            rel = A.release;
+            rctx = A.ctx;
+        } else {
+            GLK_HIP(hipMalloc(&p, c * sizeof(T)));
+        }
         count = c;
-        if (c) GLK_HIP(hipMalloc(&p, c * sizeof(T)));
     }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (rel) {
+                // the memory goes back to an allocator that may hand it out
+                // at once: nothing may still be using it
+                (void)hipDeviceSynchronize();
+                rel(p, nullptr, rctx);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         count = 0;
+        rel = nullptr;
+        rctx = nullptr;
     }
     T *get() const { return p; }
 };
@@ -244,10 +292,16 @@ template <class T> inline GeomT<T> geom_t(const Geom &g)
 // components the field direction lacks, zeros of a given matrix), whose
 // factor is 1.  The offsets depend on the grid and that pattern only, so a
 // field change rewrites the values in place.
+// Potentials that are not linear (the dipole) have no factor tables: then
+// n_edge > 0 and f holds one link per node and axis, the forward edge along
+// axis a leaving node i at f[a n_edge + i] (N0, N1: the grid's first two
+// extents, to index the node).
 template <class T>
 struct LinkTab {
     const C<T> *__restrict__ f;
     int off[3][3];
+    int n_edge;
+    int N0, N1;
 };
 
 }  // namespace glk
@@ -267,6 +321,7 @@ struct gl_mesh {
     glk::DevBuf<double2> F64;  // link factor tables (glk::LinkTab), FP64 and rounded to FP32
     glk::DevBuf<float2> F32;
     int foff[3][3] = {};
+    bool per_edge = false;           // links stored per edge (non-linear potential)
     // reductions
     glk::DevBuf<double> partials;
     glk::DevBuf<double> dscal;       // device scalar results
@@ -287,6 +342,9 @@ template <> inline LinkTab<double> link_tab<double>(const gl_mesh *m)
     LinkTab<double> t;
     t.f = m->F64.get();
     std::memcpy(t.off, m->foff, sizeof(t.off));
+    t.n_edge = m->per_edge ? m->g.n : 0;
+    t.N0 = m->g.N[0];
+    t.N1 = m->g.N[1];
     return t;
 }
 template <> inline LinkTab<float> link_tab<float>(const gl_mesh *m)
@@ -294,6 +352,9 @@ template <> inline LinkTab<float> link_tab<float>(const gl_mesh *m)
     LinkTab<float> t;
     t.f = m->F32.get();
     std::memcpy(t.off, m->foff, sizeof(t.off));
+    t.n_edge = m->per_edge ? m->g.n : 0;
+    t.N0 = m->g.N[0];
+    t.N1 = m->g.N[1];
     return t;
 }
 }  // namespace glk

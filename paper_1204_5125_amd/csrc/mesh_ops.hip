@@ -26,6 +26,12 @@ Profiler &profiler()
     return p;
 }
 
+Allocator &allocator()
+{
+    static Allocator a;
+    return a;
+}
+
 RedSlot red_slot(const gl_mesh *m, int k)
 {
     const size_t per = m->partials.count / kMaxSlots;
@@ -91,6 +97,65 @@ __global__ __launch_bounds__(kBlock) void k_link_tables(Geom g, Potential pot, T
     F32[t.off[a][b] + j] = make_float2((float)u.x, (float)u.y);
 }
 
+// Links of the dipole potential mu A_d, A_d(r) = m x (r - x0) / |r - x0|^3, one
+// per node and axis (the forward edge; 0 on the axis's upper face).  Along
+// the edge from node k (a = x_k - x0) in unit direction t of length h, the
+// integrand e . A_d = m . (a x e) / |a + s t|^3 has a constant numerator;
+// with d the distance of x0 from the edge's line and s the coordinate along
+// it (s0 = a . t at node k, s1 = s0 + h),
+//   int e . A_d = m . (a x t) [s / (d^2 sqrt(d^2 + s^2))]_{s0}^{s1},
+// evaluated without the division by d^2 when s0 and s1 have the same sign
+// (the two terms then nearly cancel far from x0):
+//   m . (a x t) (s1 - s0)(s1 + s0) / (r0 r1 (s1 r0 + s0 r1)), r = sqrt(d^2 + s^2).
+struct Dipole {
+    double mu;
+    double m[3], x0[3];
+    double lo[3];  // coordinate of node 0 along each axis
+};
+
+__device__ __forceinline__ double dipole_phase(const Dipole &D, const double xk[3], int axis, double h)
+{
+    double a[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c] = xk[c] - D.x0[c];
+    // a x t with t the unit vector of `axis`
+    double axt[3] = {0.0, 0.0, 0.0};
+    if (axis == 0) { axt[1] = a[2]; axt[2] = -a[1]; }
+    else if (axis == 1) { axt[0] = -a[2]; axt[2] = a[0]; }
+    else { axt[0] = a[1]; axt[1] = -a[0]; }
+    const double num = D.m[0] * axt[0] + D.m[1] * axt[1] + D.m[2] * axt[2];
+    const double d2 = axt[0] * axt[0] + axt[1] * axt[1] + axt[2] * axt[2];
+    if (!(d2 > 0.0)) return 0.0;  // the line passes through x0: no transverse part, num = 0
+    const double s0 = a[axis], s1 = s0 + h;
+    const double r0 = sqrt(d2 + s0 * s0), r1 = sqrt(d2 + s1 * s1);
+    if (s0 * s1 > 0.0) return num * (s1 - s0) * (s1 + s0) / (r0 * r1 * (s1 * r0 + s0 * r1));
+    return num / d2 * (s1 / r1 - s0 / r0);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_link_dipole(Geom g, Dipole D, double2 *__restrict__ F64,
+                                                        float2 *__restrict__ F32)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int c[3];
+    node_coords<DIM>(g.N, i, c);
+    double xk[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) xk[a] = D.lo[a] + c[a] * g.h[a];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double2 u = make_double2(0.0, 0.0);
+        if (c[a] < g.N[a] - 1) {
+            double sn, cs;
+            sincos(D.mu * dipole_phase(D, xk, a, g.h[a]), &sn, &cs);
+            u = make_double2(cs, -sn);
+        }
+        F64[(int64_t)a * g.n + i] = u;
+        F32[(int64_t)a * g.n + i] = make_float2((float)u.x, (float)u.y);
+    }
+}
+
 // the forward-edge links of one axis per node (0 on the axis's upper face)
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_link_export(Geom g, LinkTab<double> U, int a, double2 *out)
@@ -108,6 +173,10 @@ static void compute_amat(const gl_grid_desc &d, double mu, double out[9])
         std::memcpy(out, d.a_matrix, sizeof(double) * 9);
         return;
     }
+    if (d.potential == 2) {  // not linear: links per edge
+        for (int k = 0; k < 9; ++k) out[k] = 0.0;
+        return;
+    }
     double b[3] = {d.b_dir[0], d.b_dir[1], d.b_dir[2]};
     double nb = std::sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
     for (double &v : b) v /= nb;
@@ -118,6 +187,20 @@ static void compute_amat(const gl_grid_desc &d, double mu, double out[9])
 
 static void launch_links(gl_mesh *m, hipStream_t s)
 {
+    if (m->per_edge) {
+        Dipole D;
+        D.mu = m->desc.mu;
+        for (int a = 0; a < 3; ++a) {
+            D.m[a] = m->desc.dipole_m[a];
+            D.x0[a] = m->desc.dipole_x0[a];
+            D.lo[a] = a < m->g.dim ? -0.5 * m->desc.side[a] : 0.0;
+        }
+        const int nb = blocks_for(m->g.n);
+        if (m->g.dim == 2) k_link_dipole<2><<<nb, kBlock, 0, s>>>(m->g, D, m->F64.get(), m->F32.get());
+        else k_link_dipole<3><<<nb, kBlock, 0, s>>>(m->g, D, m->F64.get(), m->F32.get());
+        GLK_CHECK_LAUNCH();
+        return;
+    }
     Potential pot;
     std::memcpy(pot.m, m->amat, sizeof(pot.m));
     for (int a = 0; a < 3; ++a) pot.L[a] = m->desc.side[a];
@@ -418,8 +501,14 @@ gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mes
         *out = nullptr;
         if (desc->dim != 2 && desc->dim != 3)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: dim must be 2 or 3");
-        if (desc->potential != 0 && desc->potential != 1)
-            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: potential must be 0 or 1");
+        if (desc->potential < 0 || desc->potential > 2)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: potential must be 0, 1 or 2");
+        if (desc->potential == 2) {
+            const double *mm = desc->dipole_m, *x0 = desc->dipole_x0;
+            if (!(mm[0] * mm[0] + mm[1] * mm[1] + mm[2] * mm[2] > 0.0) || !std::isfinite(desc->mu) ||
+                !std::isfinite(x0[0] + x0[1] + x0[2]) || !std::isfinite(mm[0] + mm[1] + mm[2]))
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_grid: dipole moment, position or mu");
+        }
         int64_t n = 1;
         for (int a = 0; a < desc->dim; ++a) {
             if (desc->n_axis[a] < 2 || desc->n_axis[a] > (int64_t)1 << 30)
@@ -466,8 +555,14 @@ gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mes
                         tot += m->g.N[b];
                     }
                 }
-            m->F64.alloc(std::max(tot, 1));
-            m->F32.alloc(std::max(tot, 1));
+            if (desc->potential == 2) {
+                m->per_edge = true;
+                m->F64.alloc((size_t)desc->dim * n);
+                m->F32.alloc((size_t)desc->dim * n);
+            } else {
+                m->F64.alloc(std::max(tot, 1));
+                m->F32.alloc(std::max(tot, 1));
+            }
             const size_t per = (size_t)blocks_for(n) + 64;
             m->partials.alloc(per * kMaxSlots);
             m->dscal.alloc(64);
@@ -493,7 +588,7 @@ gl_status gl_mesh_set_field(gl_mesh *mesh, double mu, gl_stream stream)
 {
     return guarded([&] {
         if (!mesh) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_set_field: NULL mesh");
-        if (mesh->desc.potential != 0)
+        if (mesh->desc.potential == 1)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_set_field: mesh has a matrix potential");
         if (!std::isfinite(mu)) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_set_field: mu");
         mesh->desc.mu = mu;
@@ -588,6 +683,18 @@ gl_status gl_secant_predict(const gl_mesh *mesh, const void *psi_m, const void *
         if (!std::isfinite(ratio)) fail(GL_ERR_INVALID_ARGUMENT, "gl_secant_predict: ratio");
         secant_enqueue(mesh, (const double2 *)psi_m, (const double2 *)psi_prev, ratio, (double2 *)out,
                        as_stream(stream));
+    });
+}
+
+gl_status gl_set_allocator(gl_alloc_fn alloc, gl_free_fn release, void *ctx)
+{
+    return guarded([&] {
+        if ((alloc == nullptr) != (release == nullptr))
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_set_allocator: set both functions or neither");
+        Allocator &a = allocator();
+        a.alloc = alloc;
+        a.release = release;
+        a.ctx = alloc ? ctx : nullptr;
     });
 }
 

@@ -16,6 +16,11 @@ namespace glk {
 template <int DIM, class T>
 __device__ __forceinline__ C<T> link_u(const LinkTab<T> &L, int a, const int c[3], int ca)
 {
+    if (L.n_edge > 0) {
+        const int i0 = a == 0 ? ca : c[0], i1 = a == 1 ? ca : c[1];
+        const int i2 = DIM == 3 ? (a == 2 ? ca : c[2]) : 0;
+        return L.f[(int64_t)a * L.n_edge + i0 + L.N0 * (i1 + L.N1 * i2)];
+    }
     C<T> u = mk<T>(1, 0);
     bool first = true;
 #pragma unroll

@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = [
     "gl_batch_newton_solve", "gl_batch_set_tiles", "gl_batch_stats", "gl_batch_destroy",
     "gl_unet_create", "gl_unet_num_params", "gl_unet_set_params", "gl_unet_get_params", "gl_unet_predict",
     "gl_unet_loss_grad", "gl_unet_train_step", "gl_unet_destroy",
-    "gl_profile_start", "gl_profile_stop", "gl_status_string", "gl_last_error",
+    "gl_profile_start", "gl_profile_stop", "gl_set_allocator", "gl_status_string", "gl_last_error",
 ]
 _VOID = ("gl_mesh_destroy", "gl_precond_destroy", "gl_batch_destroy", "gl_unet_destroy", "gl_status_string",
          "gl_last_error")
@@ -48,7 +48,7 @@ class GlnkError(RuntimeError):
 class GridDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_axis", C.c_int64 * 3), ("side", C.c_double * 3),
                 ("potential", C.c_int), ("mu", C.c_double), ("b_dir", C.c_double * 3),
-                ("a_matrix", C.c_double * 9)]
+                ("a_matrix", C.c_double * 9), ("dipole_m", C.c_double * 3), ("dipole_x0", C.c_double * 3)]
 
 
 class AmgOpts(C.Structure):
@@ -85,6 +85,9 @@ class NewtonInfo(C.Structure):
 
 
 _lib = None
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+_allocator_refs = []   # callbacks handed to the library stay alive for its lifetime
 
 
 def lib():
@@ -137,6 +140,7 @@ def lib():
                                      P(AdamOpts), P(C.c_double), vp]
     L.gl_unet_destroy.argtypes = [vp]
     L.gl_unet_destroy.restype = None
+    L.gl_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, vp]
     L.gl_profile_start.argtypes = [C.c_int]
     L.gl_profile_stop.argtypes = [P(C.c_double), P(C.c_double), P(C.c_int64)]
     L.gl_status_string.argtypes = [st]
@@ -175,7 +179,9 @@ def _vec(t, n, name):
 class Mesh:
     """gl_mesh handle: a tensor grid with its link variables on the GPU."""
 
-    def __init__(self, dim, n_axis, side, mu=0.0, b_dir=(0.0, 0.0, 1.0), a_matrix=None, stream=None):
+    def __init__(self, dim, n_axis, side, mu=0.0, b_dir=(0.0, 0.0, 1.0), a_matrix=None, dipole=None,
+                 stream=None):
+        """dipole = (m, x0): the potential mu A_d(r) = mu m x (r - x0) / |r - x0|^3."""
         d = GridDesc()
         d.dim = dim
         for a in range(3):
@@ -188,6 +194,11 @@ class Mesh:
             d.potential = 1
             for k, v in enumerate(np.asarray(a_matrix, dtype=np.float64).ravel()):
                 d.a_matrix[k] = v
+        if dipole is not None:
+            d.potential = 2
+            for a in range(3):
+                d.dipole_m[a] = float(dipole[0][a])
+                d.dipole_x0[a] = float(dipole[1][a])
         h = C.c_void_p()
         _check(lib().gl_mesh_create_grid(C.byref(d), _stream(stream), C.byref(h)), "gl_mesh_create_grid")
         self._h = h
@@ -340,6 +351,26 @@ class Precond:
         self.close()
 
 
+def gl_set_allocator(alloc=None, release=None):
+    """Device workspaces of handles created from now on come from
+    alloc(nbytes) -> int pointer and go back through release(ptr); None for
+    both restores hipMalloc / hipFree."""
+    if alloc is None and release is None:
+        _check(lib().gl_set_allocator(_ALLOC_FN(), _FREE_FN(), None), "gl_set_allocator")
+        return
+    fa = _ALLOC_FN(lambda nbytes, stream, ctx: alloc(nbytes) or None)
+    fr = _FREE_FN(lambda ptr, stream, ctx: release(ptr))
+    _allocator_refs.append((fa, fr))
+    _check(lib().gl_set_allocator(fa, fr, None), "gl_set_allocator")
+
+
+def use_torch_allocator():
+    """Route the handles' device workspaces through PyTorch's caching allocator."""
+    import torch
+    gl_set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                     lambda p: torch.cuda.caching_allocator_delete(p))
+
+
 def gl_profile_start(kernel_id):
     _check(lib().gl_profile_start(kernel_id), "gl_profile_start")
 
@@ -386,6 +417,11 @@ class PrecondHandle:
         if self._h is None:
             self._h = C.c_void_p()
         return self._h
+
+    # the handle's hierarchy (once a Newton solve has built it)
+    info = Precond.info
+    export = Precond.export
+    inner_steps = Precond.inner_steps
 
     def close(self):
         if self._h and _lib is not None:
