@@ -204,8 +204,8 @@ def newton_rounds(batch, psis, max_rounds, tag, **kw):
         sec = batch.stats()["seconds"]
         log(f"[bench] {tag} round {r + 1}: {n} solves, {iters} iterations so far; "
             f"setup {sec['setup']:.2f} s, solve {sec['solve']:.2f} s")
-    conv = sum(1 for i in infos if i["res"][-1] < kw["tol"])
-    return solves, iters, conv
+    bad = [k for k, i in enumerate(infos) if not i["res"][-1] < kw["tol"]]
+    return solves, iters, len(infos) - len(bad), bad
 
 
 def bench_batch(args):
@@ -225,13 +225,14 @@ def bench_batch(args):
     mus = [2.0 * k / (count - 1) for k in range(count)]
     meshes = [glnk.Mesh(2, (int(N), int(N)), (side, side), mu=mu) for N, mu in zip(sizes, mus)]
     psis = [torch.ones(m.n, dtype=torch.complex128, device="cuda") for m in meshes]
-    kw = dict(tol=1e-10, krylov_rtol=1e-10, poll_every=16, precision=glnk.GL_FP32,
-              max_coarse=args.batch_max_coarse)
+    prec = glnk.GL_FP64 if args.batch_fp64 else glnk.GL_FP32
+    kw = dict(tol=1e-10, krylov_rtol=1e-10, poll_every=16, precision=prec,
+              max_coarse=args.batch_max_coarse, deflate=not args.batch_plain)
     batch = glnk.Batch(meshes)
     tiles = {}
     for N in sorted(set(int(v) for v in sizes)):
         i = int(np.nonzero(sizes == N)[0][0])
-        tiles[N] = autotune.tune(meshes[i], psis[i], precision=glnk.GL_FP32, max_coarse=args.batch_max_coarse,
+        tiles[N] = autotune.tune(meshes[i], psis[i], precision=prec, max_coarse=args.batch_max_coarse,
                                  cache=args.tile_cache, log=log, batch=True)
         log(f"[bench] tiles for {N}^2: lane_shift {tiles[N][0]}, bottom_rows {tiles[N][1]}")
     for i, N in enumerate(sizes):
@@ -239,12 +240,13 @@ def bench_batch(args):
     log(f"[bench] warm start of {count} instances, sizes "
         f"{ {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))} }")
     t0 = time.perf_counter()
-    ws, wi, wc = newton_rounds(batch, psis, 40, "warm start", krylov_max_iter=4000, **kw)
+    ws, wi, wc, _ = newton_rounds(batch, psis, 40, "warm start", krylov_max_iter=4000, **kw)
     log(f"[bench] warm start: {time.perf_counter() - t0:.2f} s, {ws} solves, converged {wc}/{count}")
     prev = [p.clone() for p in psis]
     pred = [torch.empty_like(p) for p in psis]
     mu_now = list(mus)
     solves = iters = conv = 0
+    unconverged = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(args.steps):
@@ -254,10 +256,11 @@ def bench_batch(args):
                 pred[i].copy_(psis[i])
             else:
                 glnk.gl_secant_predict(m, psis[i], prev[i], 1.0, pred[i])
-        s_, i_, c_ = newton_rounds(batch, pred, 15, f"step {step + 1}", krylov_max_iter=1000, **kw)
+        s_, i_, c_, bad = newton_rounds(batch, pred, 15, f"step {step + 1}", krylov_max_iter=1000, **kw)
         solves += s_
         iters += i_
         conv += c_
+        unconverged += [{"step": step + 1, "instance": i, "N": int(sizes[i]), "mu": mu_now[i] + dmu} for i in bad]
         for i in range(count):
             prev[i].copy_(psis[i])
             psis[i].copy_(pred[i])
@@ -269,17 +272,21 @@ def bench_batch(args):
         "metric": "batched Jacobian solves/s (continuation, 64 instances)",
         "value": solves / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64 (outer) / f32 (V-cycle)",
+        "vs_baseline": None, "dtype": "f64 (outer) / " + ("f64" if args.batch_fp64 else "f32") + " (V-cycle)",
         "data": "synthetic: 64 continuation instances, grid sizes drawn with seed 0",
         "config": {"workload": "64 instances, 2D grids of 129^2 / 257^2 / 513^2 nodes (seed 0), side 10, "
                                "mu_k = 2k/63, continuation steps of 0.02 with the secant predictor, "
-                               "Newton to 1e-10, MINRES to 1e-10, FP32 V-cycle",
+                               "Newton to 1e-10, MINRES to 1e-10 (deflated unless --batch-plain), FP32 V-cycle "
+                               "(FP64 with --batch-fp64)",
                    "sizes": {str(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))},
                    "tiles": {str(k): list(v) for k, v in tiles.items()},
                    "amg_max_coarse": args.batch_max_coarse},
         "jacobian_solves": solves, "minres_iterations": iters,
         "dispatches_per_graph": st["dispatches_per_graph"], "groups": st["groups"],
-        "converged_fraction": conv / (count * args.steps),
+        "graph_launches": st["graph_launches"], "host_seconds": st["seconds"],
+        "deflate": not args.batch_plain,
+        "converged_fraction": conv / (count * args.steps), "unconverged": unconverged,
+        "graph_launches_per_step": st["graph_launches"] / args.steps,
         "warm_start": {"solves": ws, "iterations": wi, "converged": wc},
     }
     print(json.dumps(out), flush=True)
@@ -684,6 +691,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--arc-steps", type=int, default=60)
     ap.add_argument("--batch-max-coarse", type=int, default=64)
+    ap.add_argument("--batch-plain", action="store_true",
+                    help="batch: Newton without deflation of the gauge mode")
+    ap.add_argument("--batch-fp64", action="store_true", help="batch: FP64 V-cycle")
     ap.add_argument("--tile-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "glnk_tiles.json"))
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
