@@ -244,6 +244,12 @@ typedef struct {
     int lane_shift;
     int bottom_rows;
     int dense_rows;
+    int l0_tiled;       /* 2D grids: 1 runs level 0's passes of a V-cycle as
+                           two LDS-tiled kernels (down: the three sweep passes
+                           and the residual; up: the coarse correction, the
+                           three passes and the output), 0 (default) one
+                           dispatch per pass; the same operator up to rounding.
+                           3D grids always use one dispatch per pass */
 } gl_tiles;
 
 gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles);

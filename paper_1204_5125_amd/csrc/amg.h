@@ -225,6 +225,7 @@ struct gl_precond {
     int bottom_rows = glk::kBottomRows;  // tile choices (gl_precond_set_tiles)
     int lane_shift = 0;
     int dense_rows = 0;
+    int l0_tiled = 0;              // 1: 2D level-0 passes in two LDS-tiled kernels
     bool has_values = false;       // a numeric setup has run
     glk::Level L[glk::kMaxLevels];
     glk::DevBuf<double2> cfac;     // Cholesky factor of the coarsest operator

@@ -1597,15 +1597,17 @@ gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles)
     return guarded([&] {
         if (!pre || !tiles) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: NULL argument");
         if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 || tiles->bottom_rows > 65536 ||
-            tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail)
-            fail(GL_ERR_INVALID_ARGUMENT,
-                 "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..8192");
+            tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail || tiles->l0_tiled < 0 || tiles->l0_tiled > 1)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, "
+                                          "dense_rows in 0..8192, l0_tiled 0 or 1");
         const int rows = tiles->bottom_rows ? tiles->bottom_rows : kBottomRows;
-        if (rows == pre->bottom_rows && tiles->lane_shift == pre->lane_shift && tiles->dense_rows == pre->dense_rows)
+        if (rows == pre->bottom_rows && tiles->lane_shift == pre->lane_shift && tiles->dense_rows == pre->dense_rows &&
+            tiles->l0_tiled == pre->l0_tiled)
             return;
         pre->bottom_rows = rows;
         pre->lane_shift = tiles->lane_shift;
         pre->dense_rows = tiles->dense_rows;
+        pre->l0_tiled = tiles->l0_tiled;
         pre->uid = new_precond_uid();  // captured graphs of the old shape are stale
         hipStream_t s = pre->mesh->ws;
         GLK_HIP(hipStreamSynchronize(s));  // no pending use of the buffers re-made here
@@ -1622,6 +1624,7 @@ gl_status gl_precond_get_tiles(const gl_precond *pre, gl_tiles *tiles)
         tiles->lane_shift = pre->lane_shift;
         tiles->bottom_rows = pre->bottom_rows;
         tiles->dense_rows = pre->dense_rows;
+        tiles->l0_tiled = pre->l0_tiled;
     });
 }
 

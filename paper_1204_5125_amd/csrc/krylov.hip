@@ -1434,7 +1434,7 @@ gl_status gl_batch_create(int count, gl_mesh *const *meshes, gl_batch **out)
         try {
             B->meshes.assign(meshes, meshes + count);
             B->pre.assign(count, nullptr);
-            B->tiles.assign(count, gl_tiles{0, 0, 0});
+            B->tiles.assign(count, gl_tiles{0, 0, 0, 0});
             GLK_HIP(hipStreamCreateWithFlags(&B->s, hipStreamNonBlocking));
             GLK_HIP(hipEventCreateWithFlags(&B->ev_in, hipEventDisableTiming));
             GLK_HIP(hipEventCreateWithFlags(&B->ev_out, hipEventDisableTiming));
@@ -1501,9 +1501,11 @@ gl_status gl_batch_set_tiles(gl_batch *batch, int index, const gl_tiles *tiles)
                 gl_status r = gl_precond_set_tiles(batch->pre[i], tiles);
                 if (r != GL_OK) fail(r, gl_last_error());
             } else if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 ||
-                       tiles->bottom_rows > 65536 || tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail) {
+                       tiles->bottom_rows > 65536 || tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail ||
+                       tiles->l0_tiled < 0 || tiles->l0_tiled > 1) {
                 fail(GL_ERR_INVALID_ARGUMENT,
-                     "gl_batch_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..8192");
+                     "gl_batch_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..8192, "
+                     "l0_tiled 0 or 1");
             }
             batch->tiles[i] = *tiles;
         }

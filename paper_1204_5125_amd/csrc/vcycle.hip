@@ -345,6 +345,218 @@ struct L0Last {
     }
 };
 
+// ------------------------------------------- level 0 in LDS tiles (2D) ---
+// The level-0 passes of a V-cycle fused into two kernels, each over a tile
+// of kL0TX x kL0TY nodes held in LDS with a halo of three nodes: the three
+// colour passes of a sweep need neighbours' values of the previous pass, so
+// a pass is exact one node further inside than the one before, and three
+// passes (or two and the residual) are exact on the tile itself.  Every node
+// value is the same expression, in the same order, as in the
+// one-pass-per-dispatch kernels above (red from zero folded, khat_offdiag
+// order), so the cycle's output agrees with theirs to rounding (the compiler
+// may contract multiply-adds differently in the two); the partial sums of
+// Re<vdot, z> are grouped by tile.
+constexpr int kL0TX = 32, kL0TY = 32, kL0H = 3;
+constexpr int kL0LX = kL0TX + 2 * kL0H, kL0LY = kL0TY + 2 * kL0H, kL0LN = kL0LX * kL0LY;
+constexpr int kL0Threads = 1024;  // about 1.4 LDS nodes per thread and pass
+
+// the forward links of node (gx, gy) along x and y (0 past the grid's edge),
+// loaded once per tile so that the passes read only LDS
+template <class T>
+__device__ __forceinline__ void l0_links(const GeomT<T> &g, const LinkTab<T> &U, int gx, int gy, C<T> &ux, C<T> &uy)
+{
+    const int c[3] = {gx, gy, 0};
+    ux = gx < g.N[0] - 1 ? link_u<2, T>(U, 0, c, gx) : mk<T>(0, 0);
+    uy = gy < g.N[1] - 1 ? link_u<2, T>(U, 1, c, gy) : mk<T>(0, 0);
+}
+
+// (sum_{j != i} H_ij x_j) of node (gx, gy) at LDS position q (2D); the link
+// of the edge towards the lower neighbour is that neighbour's forward link
+template <class T>
+__device__ __forceinline__ C<T> l0_offdiag_lds(const GeomT<T> &g, int gx, int gy, int q, const C<T> *sx,
+                                               const C<T> *ux, const C<T> *uy)
+{
+    const int c[3] = {gx, gy, 0};
+    T s[3];
+    const T d = node_volume<2, T>(g, c, s);
+    C<T> acc = mk<T>(0, 0);
+    const T a0 = d * s[0] * g.inv_h2[0];
+    if (gx > 0) acc = csub(acc, cscale(cmul(ux[q - 1], sx[q - 1]), a0));
+    if (gx < g.N[0] - 1) acc = csub(acc, cscale(cmulc(ux[q], sx[q + 1]), a0));
+    const T a1 = d * s[1] * g.inv_h2[1];
+    if (gy > 0) acc = csub(acc, cscale(cmul(uy[q - kL0LX], sx[q - kL0LX]), a1));
+    if (gy < g.N[1] - 1) acc = csub(acc, cscale(cmulc(uy[q], sx[q + kL0LX]), a1));
+    return acc;
+}
+
+struct L0TileAt {
+    int x0, y0;  // grid coordinates of LDS position 0
+};
+
+__device__ __forceinline__ L0TileAt l0_tile(int tile, int ntx)
+{
+    return L0TileAt{(tile % ntx) * kL0TX - kL0H, (tile / ntx) * kL0TY - kL0H};
+}
+
+// LDS position q: grid coordinates, in the grid, and its ring (distance from
+// the LDS border: 0 on the outermost ring, kL0H inside the tile)
+__device__ __forceinline__ void l0_pos(const L0TileAt &T0, int q, const int *N, int &gx, int &gy, bool &in,
+                                       int &ring)
+{
+    const int lx = q % kL0LX, ly = q / kL0LX;
+    gx = T0.x0 + lx;
+    gy = T0.y0 + ly;
+    in = gx >= 0 && gx < N[0] && gy >= 0 && gy < N[1];
+    ring = min(min(lx, kL0LX - 1 - lx), min(ly, kL0LY - 1 - ly));
+}
+
+// Down: b = round(v), red from zero, black, red, black residual (L0PreBlack,
+// L0Sweep(0), L0Residual); writes b and x of the tile's nodes and r of its
+// black nodes in the split layout.
+template <class T>
+struct L0PreTile {
+    GeomT<T> g;
+    const double2 *v;
+    const T *hd;
+    LinkTab<T> U;
+    C<T> *b, *x, *r;
+    int ntx;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE_LOAD();
+        __shared__ C<T> sb[kL0LN], sx[kL0LN], ux[kL0LN], uy[kL0LN];
+        __shared__ T sd[kL0LN];
+        const L0TileAt T0 = l0_tile(xcd_tile(bx, nbx), ntx);
+        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+            int gx, gy, ring;
+            bool in;
+            l0_pos(T0, q, g.N, gx, gy, in, ring);
+            const int i = gx + g.N[0] * gy;
+            const C<T> bi = in ? narrow<T>(v[i]) : mk<T>(0, 0);
+            const T di = in ? hd[i] : (T)1;
+            C<T> lx = mk<T>(0, 0), ly = lx;
+            if (in) l0_links<T>(g, U, gx, gy, lx, ly);
+            sb[q] = bi;
+            sd[q] = di;
+            ux[q] = lx;
+            uy[q] = ly;
+            // red from zero: x = b / d
+            sx[q] = in && ((gx + gy) & 1) == 0 ? cscale(bi, (T)1 / di) : mk<T>(0, 0);
+        }
+        __syncthreads();
+        // black (exact one ring in), then red (two rings in)
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const int col = pass == 0 ? 1 : 0;
+            for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+                int gx, gy, ring;
+                bool in;
+                l0_pos(T0, q, g.N, gx, gy, in, ring);
+                if (!in || ring < pass + 1 || ((gx + gy) & 1) != col) continue;
+                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+            }
+            __syncthreads();
+        }
+        // the tile's nodes: b, x, and the black residual
+        const int np = g.npair;
+        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+            int gx, gy, ring;
+            bool in;
+            l0_pos(T0, q, g.N, gx, gy, in, ring);
+            if (!in || ring < kL0H) continue;
+            const int col = (gx + gy) & 1;
+            const int t = (gx >> 1) + g.hr * gy;
+            C<T> ri = mk<T>(0, 0);
+            if (col == 1) ri = csub(csub(sb[q], cscale(sx[q], sd[q])), l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy));
+            if (!gate_go) continue;
+            b[col * np + t] = sb[q];
+            x[col * np + t] = sx[q];
+            if (col == 1) r[np + t] = ri;
+        }
+    }
+};
+
+// Up: black += (P x_c)_b, red, black, last red; z = x on the tile's nodes (ADD:
+// z += x) and partial sums of Re<vdot, z> (L0ProlongBlack, L0Sweep(0),
+// L0Sweep(1), L0Last).
+template <class T, class TC, int ADD>
+struct L0PostTile {
+    GeomT<T> g;
+    const C<T> *b, *x;
+    const T *hd;
+    LinkTab<T> U;
+    const int *prp, *pci;
+    const C<TC> *pv, *xc;
+    double2 *z;
+    const double2 *vdot;
+    RedSlot slot;
+    int want_dot;
+    int ntx;
+    const int *gate;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        GATE_LOAD();
+        __shared__ C<T> sb[kL0LN], sx[kL0LN], ux[kL0LN], uy[kL0LN];
+        __shared__ T sd[kL0LN];
+        __shared__ double sm[kL0Threads / 64];
+        const L0TileAt T0 = l0_tile(xcd_tile(bx, nbx), ntx);
+        const int np = g.npair;
+        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+            int gx, gy, ring;
+            bool in;
+            l0_pos(T0, q, g.N, gx, gy, in, ring);
+            C<T> bi = mk<T>(0, 0), xi = mk<T>(0, 0), lx = xi, ly = xi;
+            T di = (T)1;
+            if (in) {
+                const int col = (gx + gy) & 1;
+                const int t = (gx >> 1) + g.hr * gy;
+                bi = b[col * np + t];
+                di = hd[gx + g.N[0] * gy];
+                l0_links<T>(g, U, gx, gy, lx, ly);
+                // red values are recomputed from the black ones before any use
+                if (col == 1) xi = cadd(x[np + t], as_c<T>(prolong_row<TC>(prp, pci, pv, xc, t)));
+            }
+            sb[q] = bi;
+            sx[q] = xi;
+            sd[q] = di;
+            ux[q] = lx;
+            uy[q] = ly;
+        }
+        __syncthreads();
+        // red (one ring in), black (two rings in)
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass) {
+            const int col = pass;
+            for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+                int gx, gy, ring;
+                bool in;
+                l0_pos(T0, q, g.N, gx, gy, in, ring);
+                if (!in || ring < pass + 1 || ((gx + gy) & 1) != col) continue;
+                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+            }
+            __syncthreads();
+        }
+        // last red on the tile, into z only; z on every node of the tile
+        double part = 0.0;
+        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+            int gx, gy, ring;
+            bool in;
+            l0_pos(T0, q, g.N, gx, gy, in, ring);
+            if (!in || ring < kL0H) continue;
+            C<T> xi = sx[q];
+            if (((gx + gy) & 1) == 0)
+                xi = cscale(csub(sb[q], l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+            const int i = gx + g.N[0] * gy;
+            double2 zi = widen(xi);
+            if (ADD) zi = cadd(z[i], zi);
+            if (want_dot) part += redot(vdot[i], zi);
+            if (gate_go) z[i] = zi;
+        }
+        if (want_dot && gate_go) block_reduce_store(part, slot, sm, bx);
+    }
+};
+
 // --------------------------------------------------------------- CSR ---
 // LPR lanes of one wave share a row; partial sums are combined by shuffles.
 template <class T, int LPR>
@@ -1084,17 +1296,28 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     const double b_last = b_sweep - mc * sz + (nn - mc) * sz + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
     const double b_restr = (L0.nc + 1 + L0.Rb.nnz) * 4.0 + L0.Rb.nnz * szc + (nn - mc) * sz + L0.nc * szc;
     // level 0 (one thread per red-black pair), down: red (from zero, folded) +
-    // black, red, black residual, restriction
+    // black, red, black residual, restriction; in 2D by default the three
+    // passes in one LDS-tiled kernel (L0PreTile)
     const int nbp = blocks_for(g.npair);
-    prof_launch(PROF_L0_SWEEP, b_pre, L, [&] {
-        L.run(nbp, L0PreBlack<DIM, T>{g, v, vec_b<T>(L0), x0, U, hd, gate});
-    });
-    prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
-        L.run(nbp, L0Sweep<DIM, T>{g, 0, b0, x0, U, hs, gate});
-    });
-    prof_launch(PROF_L0_RESIDUAL, b_resid, L, [&] {
-        L.run(nbp, L0Residual<DIM, T>{g, b0, x0, U, hs, vec_r<T>(L0), gate});
-    });
+    const bool tiled = DIM == 2 && pre->l0_tiled;
+    const int ntx = (g.N[0] + kL0TX - 1) / kL0TX, nbt = ntx * ((g.N[1] + kL0TY - 1) / kL0TY);
+    if (tiled) {
+        // each array once (the halo's re-reads come from cache)
+        const double b_tile = nn * 16 + nn * szr + 2 * nn * sz + mc * sz;
+        prof_launch(PROF_L0_SWEEP, b_tile, L, [&] {
+            L.run<L0PreTile<T>, kL0Threads>(nbt, L0PreTile<T>{g, v, hd, U, vec_b<T>(L0), x0, vec_r<T>(L0), ntx, gate});
+        });
+    } else {
+        prof_launch(PROF_L0_SWEEP, b_pre, L, [&] {
+            L.run(nbp, L0PreBlack<DIM, T>{g, v, vec_b<T>(L0), x0, U, hd, gate});
+        });
+        prof_launch(PROF_L0_SWEEP, b_sweep, L, [&] {
+            L.run(nbp, L0Sweep<DIM, T>{g, 0, b0, x0, U, hs, gate});
+        });
+        prof_launch(PROF_L0_RESIDUAL, b_resid, L, [&] {
+            L.run(nbp, L0Residual<DIM, T>{g, b0, x0, U, hs, vec_r<T>(L0), gate});
+        });
+    }
     prof_launch(PROF_L0_TRANSFER, b_restr, L, [&] {
         csr_spmv<TC, T>(L0.Rb, vec_r<T>(L0), vec_b<TC>(L1), false, 0, gate, L);
     });
@@ -1125,7 +1348,25 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     }
     // level 0, up: red with the coarse correction, black, red + output
     // black coarse correction, then the red pass (fusing the two reads every
-    // black correction four times and was measured slower)
+    // black correction four times and was measured slower); in 2D by default
+    // all four in one LDS-tiled kernel (L0PostTile), each tile correcting the
+    // black nodes of its halo once
+    if (tiled) {
+        const double b_tile = (g.npair + 1 + L0.Pb.nnz) * 4.0 + L0.Pb.nnz * szc + L0.nc * szc + mc * sz +
+                              nn * sz + nn * szr + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
+        prof_launch(PROF_L0_SWEEP, b_tile, L, [&] {
+            if (add)
+                L.run<L0PostTile<T, TC, 1>, kL0Threads>(
+                    nbt, L0PostTile<T, TC, 1>{g, b0, x0, hd, U, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
+                                              vec_x<TC>(L1), z, vdot, slot, want, ntx, gate});
+            else
+                L.run<L0PostTile<T, TC, 0>, kL0Threads>(
+                    nbt, L0PostTile<T, TC, 0>{g, b0, x0, hd, U, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
+                                              vec_x<TC>(L1), z, vdot, slot, want, ntx, gate});
+        });
+        if (want) launch_finalize(slot.partials, nbt, fmode, ks, store, gate, L);
+        return;
+    }
     prof_launch(PROF_L0_TRANSFER, b_prol, L, [&] {
         L.run(nbp, L0ProlongBlack<DIM, T, TC>{g, x0, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
                                               vec_x<TC>(L1), gate});

@@ -72,7 +72,8 @@ class NewtonOpts(C.Structure):
 
 
 class Tiles(C.Structure):
-    _fields_ = [("lane_shift", C.c_int), ("bottom_rows", C.c_int), ("dense_rows", C.c_int)]
+    _fields_ = [("lane_shift", C.c_int), ("bottom_rows", C.c_int), ("dense_rows", C.c_int),
+                ("l0_tiled", C.c_int)]
 
 
 class AdamOpts(C.Structure):
@@ -460,15 +461,16 @@ def _newton_info(ni):
             "krylov_iters": list(ni.krylov_iters[:ni.steps])}
 
 
-def gl_precond_set_tiles(pre, lane_shift=0, bottom_rows=0, dense_rows=0):
-    _check(lib().gl_precond_set_tiles(pre.handle, C.byref(Tiles(lane_shift, bottom_rows, dense_rows))),
+def gl_precond_set_tiles(pre, lane_shift=0, bottom_rows=0, dense_rows=0, l0_tiled=0):
+    _check(lib().gl_precond_set_tiles(pre.handle, C.byref(Tiles(lane_shift, bottom_rows, dense_rows, l0_tiled))),
            "gl_precond_set_tiles")
 
 
 def gl_precond_get_tiles(pre):
     t = Tiles()
     _check(lib().gl_precond_get_tiles(pre.handle, C.byref(t)), "gl_precond_get_tiles")
-    return {"lane_shift": t.lane_shift, "bottom_rows": t.bottom_rows, "dense_rows": t.dense_rows}
+    return {"lane_shift": t.lane_shift, "bottom_rows": t.bottom_rows, "dense_rows": t.dense_rows,
+            "l0_tiled": t.l0_tiled}
 
 
 class Batch:
@@ -485,8 +487,9 @@ class Batch:
     def handle(self):
         return self._h
 
-    def set_tiles(self, lane_shift=0, bottom_rows=0, dense_rows=0, index=-1):
-        _check(lib().gl_batch_set_tiles(self._h, index, C.byref(Tiles(lane_shift, bottom_rows, dense_rows))),
+    def set_tiles(self, lane_shift=0, bottom_rows=0, dense_rows=0, l0_tiled=0, index=-1):
+        _check(lib().gl_batch_set_tiles(self._h, index,
+                                        C.byref(Tiles(lane_shift, bottom_rows, dense_rows, l0_tiled))),
                "gl_batch_set_tiles")
 
     def newton_solve(self, psis, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,

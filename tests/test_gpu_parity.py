@@ -325,7 +325,8 @@ def test_vcycle_and_solve_deeper_hierarchy(glnk, max_coarse):
     for dense in (0, 512, 4096):
         for rows in (512, 4096, 65536):
             glnk.gl_precond_set_tiles(pre, 0, rows, dense)
-            assert glnk.gl_precond_get_tiles(pre) == {"lane_shift": 0, "bottom_rows": rows, "dense_rows": dense}
+            assert glnk.gl_precond_get_tiles(pre) == {"lane_shift": 0, "bottom_rows": rows, "dense_rows": dense,
+                                                      "l0_tiled": 0}
             for prec, tol in ((glnk.GL_FP64, 1e-11), (glnk.GL_FP32, 1e-5), (glnk.GL_MIXED, 1e-5)):
                 pre.update(dev(psi), precision=prec)
                 pre.apply(dev(r), z)
@@ -429,3 +430,42 @@ def test_mesh_independent_iteration_counts(glnk):
             _, io, _ = oracle.minres(mo, o1, o1, amg=amg, rtol=1e-11, max_iter=500)
             assert abs(io["iterations"] - info["iterations"]) <= 1
     assert max(counts) <= 1.25 * min(counts), counts
+
+
+@pytest.mark.parametrize("grid", [((33, 33), (5.0, 5.0), 0.8), ((37, 23), (6.0, 4.0), 1.1),
+                                  ((24, 17), (5.0, 4.0), 0.9), ((129, 129), (10.0, 10.0), 1.0),
+                                  ((70, 45), (7.0, 4.5), 0.6), ((5, 3), (2.0, 1.0), 0.9)],
+                         ids=["33x33", "37x23", "24x17", "129x129", "70x45", "5x3"])
+def test_level0_tiles_bitwise(glnk, grid):
+    """2D level 0 in two LDS-tiled kernels against one dispatch per pass (the
+    default): the V-cycle's output agrees to rounding (every node value is the
+    same expression in the same order; the compiler may contract its
+    multiply-adds differently in the two kernels), FP64 within 1e-13, FP32
+    and mixed within 1e-6; k = 3 cycles (the accumulating output); tiles with
+    ragged edges."""
+    N, side, mu = grid
+    mg = glnk.Mesh(2, N, side, mu=mu)
+    n = N[0] * N[1]
+    psi = dev(inputs.random_phase_state(n, seed=17))
+    r = dev(inputs.random_complex(n, seed=18))
+    pre = glnk.Precond(mg, psi, max_coarse=16)
+    z1 = torch.empty_like(r)
+    z2 = torch.empty_like(r)
+    for prec, cycles in ((glnk.GL_FP64, 1), (glnk.GL_FP32, 1), (glnk.GL_MIXED, 1), (glnk.GL_FP64, 3)):
+        pre.update(psi, precision=prec, cycles=cycles)
+        glnk.gl_precond_set_tiles(pre, 0, 0, 0, 1)
+        pre.apply(r, z1)
+        glnk.gl_precond_set_tiles(pre, 0, 0, 0, 0)
+        pre.apply(r, z2)
+        e = relerr(host(z1), host(z2))
+        assert e < (1e-13 if prec == glnk.GL_FP64 else 1e-6), (prec, cycles, e)
+    # and MINRES through the tiled level 0 against the oracle (fixed count)
+    mo = oracle.Mesh(2, N, side, mu=mu)
+    hp = host(psi)
+    amg = oracle.Amg.for_state(mo, hp, max_coarse=16)
+    b = inputs.random_complex(n, seed=19)
+    pre.update(psi, precision=glnk.GL_FP64, cycles=1)
+    glnk.gl_precond_set_tiles(pre, 0, 0, 0, 1)
+    xo, io, _ = oracle.minres(mo, hp, b, amg=amg, rtol=0.0, max_iter=5)
+    rc, ig = glnk.gl_jacobian_solve(mg, psi, pre, dev(b), z1, rtol=0.0, max_iter=5, poll_every=2)
+    assert relerr(host(z1), xo) < 1e-12
