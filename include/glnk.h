@@ -244,12 +244,14 @@ typedef struct {
     int lane_shift;
     int bottom_rows;
     int dense_rows;
-    int l0_tiled;       /* 2D grids: 1 runs level 0's passes of a V-cycle as
-                           two LDS-tiled kernels (down: the three sweep passes
-                           and the residual; up: the coarse correction, the
-                           three passes and the output), 0 (default) one
-                           dispatch per pass; the same operator up to rounding.
-                           3D grids always use one dispatch per pass */
+    int l0_tiled;       /* 2D grids: 1, 2, 3 run level 0's passes of a
+                           V-cycle as two LDS-tiled kernels (down: the three
+                           sweep passes and the residual; up: the coarse
+                           correction, the three passes and the output) on
+                           tiles of 32 x 32 (1024 threads), 32 x 16 (512) or
+                           16 x 16 nodes (256); 0 (default) one dispatch per
+                           pass; the same operator up to rounding.  3D grids
+                           always use one dispatch per pass */
 } gl_tiles;
 
 gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles);

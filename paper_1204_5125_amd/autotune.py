@@ -5,10 +5,10 @@ of preconditioned MINRES iterations (graph-replayed, as in the solvers) for
 every candidate tile set, keeps the fastest, and caches the choice in a JSON
 file keyed by device name, grid shape, precision and coarse-size limit.  The
 candidates change only the order of rounding (lanes per row; a sub-cycle
-applied as an explicit matrix; level 0 of a 2D grid in two LDS-tiled kernels)
-and which levels run inside the one-work-group bottom kernel; candidates that
-give the same split of the hierarchy are timed once.  The level-0 form is
-timed on the best coarse-level choice only.
+applied as an explicit matrix; level 0 of a 2D grid in two LDS-tiled kernels,
+on one of L0_SHAPES) and which levels run inside the one-work-group bottom
+kernel; candidates that give the same split of the hierarchy are timed once.
+The level-0 forms are timed on the best coarse-level choice only.
 """
 import json
 import os
@@ -23,6 +23,7 @@ CANDIDATES = [(ls, br, dr) for ls in (-1, 0, 1) for br in (64, 512, 2048, 8192) 
 BATCH_CANDIDATES = [c for c in CANDIDATES if c[2] == 0]
 MAX_COLOURS = 64   # colours per level the bottom kernel handles
 DEFAULT_BOTTOM = 512
+L0_SHAPES = (1, 2, 3)  # gl_tiles.l0_tiled: 32 x 32, 32 x 16, 16 x 16 node tiles
 BOTTOM_DENSE_ROWS = 512  # largest explicit sub-cycle the bottom kernel applies
 
 
@@ -121,13 +122,16 @@ def tune(mesh, psi, precision=glnk.GL_FP32, max_coarse=64, cache=None, candidate
     times = {t + (0,): v for t, v in times.items()}
     best = best + (0,)
     if mesh.dim == 2 and not batch:
-        tiled = best[:3] + (1,)
-        times[tiled] = time_tiles(mesh, psi, pre, tiled)
-        if log:
-            log(f"[autotune] {key} tiles {tiled}: {times[tiled] * 1e6:.1f} us/iteration")
-        # re-time the one-dispatch form beside it, so both see the same state
+        forms = [best]
+        for shape in L0_SHAPES:
+            tiled = best[:3] + (shape,)
+            times[tiled] = time_tiles(mesh, psi, pre, tiled)
+            forms.append(tiled)
+            if log:
+                log(f"[autotune] {key} tiles {tiled}: {times[tiled] * 1e6:.1f} us/iteration")
+        # re-time the one-dispatch form beside them, so all see the same state
         times[best] = min(times[best], time_tiles(mesh, psi, pre, best))
-        best = min((best, tiled), key=times.get)
+        best = min(forms, key=times.get)
     if cache:
         table[key] = {"tiles": list(best), "us_per_iteration": times[best] * 1e6,
                       "default_us_per_iteration": times.get((0, 512, 0, 0), float("nan")) * 1e6}

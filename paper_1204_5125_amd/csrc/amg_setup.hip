@@ -1597,9 +1597,9 @@ gl_status gl_precond_set_tiles(gl_precond *pre, const gl_tiles *tiles)
     return guarded([&] {
         if (!pre || !tiles) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: NULL argument");
         if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 || tiles->bottom_rows > 65536 ||
-            tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail || tiles->l0_tiled < 0 || tiles->l0_tiled > 1)
+            tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail || tiles->l0_tiled < 0 || tiles->l0_tiled > 3)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, "
-                                          "dense_rows in 0..8192, l0_tiled 0 or 1");
+                                          "dense_rows in 0..8192, l0_tiled 0..3");
         const int rows = tiles->bottom_rows ? tiles->bottom_rows : kBottomRows;
         if (rows == pre->bottom_rows && tiles->lane_shift == pre->lane_shift && tiles->dense_rows == pre->dense_rows &&
             tiles->l0_tiled == pre->l0_tiled)

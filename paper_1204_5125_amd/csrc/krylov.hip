@@ -1502,10 +1502,10 @@ gl_status gl_batch_set_tiles(gl_batch *batch, int index, const gl_tiles *tiles)
                 if (r != GL_OK) fail(r, gl_last_error());
             } else if (tiles->lane_shift < -2 || tiles->lane_shift > 2 || tiles->bottom_rows < 0 ||
                        tiles->bottom_rows > 65536 || tiles->dense_rows < 0 || tiles->dense_rows > kMaxTail ||
-                       tiles->l0_tiled < 0 || tiles->l0_tiled > 1) {
+                       tiles->l0_tiled < 0 || tiles->l0_tiled > 3) {
                 fail(GL_ERR_INVALID_ARGUMENT,
                      "gl_batch_set_tiles: lane_shift in -2..2, bottom_rows in 0..65536, dense_rows in 0..8192, "
-                     "l0_tiled 0 or 1");
+                     "l0_tiled 0..3");
             }
             batch->tiles[i] = *tiles;
         }

@@ -563,7 +563,12 @@ gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mes
                 m->F64.alloc(std::max(tot, 1));
                 m->F32.alloc(std::max(tot, 1));
             }
-            const size_t per = (size_t)blocks_for(n) + 64;
+            // one partial per block, or per level-0 tile of the smallest
+            // tiled shape (16 x 16 nodes) on a 2D grid
+            size_t per = (size_t)blocks_for(n);
+            if (desc->dim == 2)
+                per = std::max(per, (size_t)((desc->n_axis[0] + 15) / 16) * (size_t)((desc->n_axis[1] + 15) / 16));
+            per += 64;
             m->partials.alloc(per * kMaxSlots);
             m->dscal.alloc(64);
             m->work.alloc((size_t)kWorkVecs * n);

@@ -347,7 +347,7 @@ struct L0Last {
 
 // ------------------------------------------- level 0 in LDS tiles (2D) ---
 // The level-0 passes of a V-cycle fused into two kernels, each over a tile
-// of kL0TX x kL0TY nodes held in LDS with a halo of three nodes: the three
+// of S::TX x S::TY nodes held in LDS with a halo of three nodes: the three
 // colour passes of a sweep need neighbours' values of the previous pass, so
 // a pass is exact one node further inside than the one before, and three
 // passes (or two and the residual) are exact on the tile itself.  Every node
@@ -356,9 +356,15 @@ struct L0Last {
 // order), so the cycle's output agrees with theirs to rounding (the compiler
 // may contract multiply-adds differently in the two); the partial sums of
 // Re<vdot, z> are grouped by tile.
-constexpr int kL0TX = 32, kL0TY = 32, kL0H = 3;
-constexpr int kL0LX = kL0TX + 2 * kL0H, kL0LY = kL0TY + 2 * kL0H, kL0LN = kL0LX * kL0LY;
-constexpr int kL0Threads = 1024;  // about 1.4 LDS nodes per thread and pass
+// Tile shapes (gl_tiles.l0_tiled 1, 2, 3): fewer threads and smaller tiles
+// keep more tiles resident per CU at the price of a larger halo share.
+template <int X, int Y, int NT>
+struct L0Shape {
+    static constexpr int TX = X, TY = Y, H = 3, LX = X + 2 * H, LY = Y + 2 * H, LN = LX * LY, threads = NT;
+};
+using L0Shape1 = L0Shape<32, 32, 1024>;  // about 1.4 LDS nodes per thread and pass
+using L0Shape2 = L0Shape<32, 16, 512>;
+using L0Shape3 = L0Shape<16, 16, 256>;
 
 // the forward links of node (gx, gy) along x and y (0 past the grid's edge),
 // loaded once per tile so that the passes read only LDS
@@ -372,7 +378,7 @@ __device__ __forceinline__ void l0_links(const GeomT<T> &g, const LinkTab<T> &U,
 
 // (sum_{j != i} H_ij x_j) of node (gx, gy) at LDS position q (2D); the link
 // of the edge towards the lower neighbour is that neighbour's forward link
-template <class T>
+template <class T, int LX>
 __device__ __forceinline__ C<T> l0_offdiag_lds(const GeomT<T> &g, int gx, int gy, int q, const C<T> *sx,
                                                const C<T> *ux, const C<T> *uy)
 {
@@ -384,8 +390,8 @@ __device__ __forceinline__ C<T> l0_offdiag_lds(const GeomT<T> &g, int gx, int gy
     if (gx > 0) acc = csub(acc, cscale(cmul(ux[q - 1], sx[q - 1]), a0));
     if (gx < g.N[0] - 1) acc = csub(acc, cscale(cmulc(ux[q], sx[q + 1]), a0));
     const T a1 = d * s[1] * g.inv_h2[1];
-    if (gy > 0) acc = csub(acc, cscale(cmul(uy[q - kL0LX], sx[q - kL0LX]), a1));
-    if (gy < g.N[1] - 1) acc = csub(acc, cscale(cmulc(uy[q], sx[q + kL0LX]), a1));
+    if (gy > 0) acc = csub(acc, cscale(cmul(uy[q - LX], sx[q - LX]), a1));
+    if (gy < g.N[1] - 1) acc = csub(acc, cscale(cmulc(uy[q], sx[q + LX]), a1));
     return acc;
 }
 
@@ -393,27 +399,29 @@ struct L0TileAt {
     int x0, y0;  // grid coordinates of LDS position 0
 };
 
+template <class S>
 __device__ __forceinline__ L0TileAt l0_tile(int tile, int ntx)
 {
-    return L0TileAt{(tile % ntx) * kL0TX - kL0H, (tile / ntx) * kL0TY - kL0H};
+    return L0TileAt{(tile % ntx) * S::TX - S::H, (tile / ntx) * S::TY - S::H};
 }
 
 // LDS position q: grid coordinates, in the grid, and its ring (distance from
-// the LDS border: 0 on the outermost ring, kL0H inside the tile)
+// the LDS border: 0 on the outermost ring, S::H inside the tile)
+template <class S>
 __device__ __forceinline__ void l0_pos(const L0TileAt &T0, int q, const int *N, int &gx, int &gy, bool &in,
                                        int &ring)
 {
-    const int lx = q % kL0LX, ly = q / kL0LX;
+    const int lx = q % S::LX, ly = q / S::LX;
     gx = T0.x0 + lx;
     gy = T0.y0 + ly;
     in = gx >= 0 && gx < N[0] && gy >= 0 && gy < N[1];
-    ring = min(min(lx, kL0LX - 1 - lx), min(ly, kL0LY - 1 - ly));
+    ring = min(min(lx, S::LX - 1 - lx), min(ly, S::LY - 1 - ly));
 }
 
 // Down: b = round(v), red from zero, black, red, black residual (L0PreBlack,
 // L0Sweep(0), L0Residual); writes b and x of the tile's nodes and r of its
 // black nodes in the split layout.
-template <class T>
+template <class T, class S>
 struct L0PreTile {
     GeomT<T> g;
     const double2 *v;
@@ -425,13 +433,13 @@ struct L0PreTile {
     __device__ void operator()(int bx, int nbx) const
     {
         GATE_LOAD();
-        __shared__ C<T> sb[kL0LN], sx[kL0LN], ux[kL0LN], uy[kL0LN];
-        __shared__ T sd[kL0LN];
-        const L0TileAt T0 = l0_tile(xcd_tile(bx, nbx), ntx);
-        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+        __shared__ C<T> sb[S::LN], sx[S::LN], ux[S::LN], uy[S::LN];
+        __shared__ T sd[S::LN];
+        const L0TileAt T0 = l0_tile<S>(xcd_tile(bx, nbx), ntx);
+        for (int q = threadIdx.x; q < S::LN; q += S::threads) {
             int gx, gy, ring;
             bool in;
-            l0_pos(T0, q, g.N, gx, gy, in, ring);
+            l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
             const int i = gx + g.N[0] * gy;
             const C<T> bi = in ? narrow<T>(v[i]) : mk<T>(0, 0);
             const T di = in ? hd[i] : (T)1;
@@ -449,26 +457,26 @@ struct L0PreTile {
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             const int col = pass == 0 ? 1 : 0;
-            for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+            for (int q = threadIdx.x; q < S::LN; q += S::threads) {
                 int gx, gy, ring;
                 bool in;
-                l0_pos(T0, q, g.N, gx, gy, in, ring);
+                l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
                 if (!in || ring < pass + 1 || ((gx + gy) & 1) != col) continue;
-                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
             }
             __syncthreads();
         }
         // the tile's nodes: b, x, and the black residual
         const int np = g.npair;
-        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+        for (int q = threadIdx.x; q < S::LN; q += S::threads) {
             int gx, gy, ring;
             bool in;
-            l0_pos(T0, q, g.N, gx, gy, in, ring);
-            if (!in || ring < kL0H) continue;
+            l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
+            if (!in || ring < S::H) continue;
             const int col = (gx + gy) & 1;
             const int t = (gx >> 1) + g.hr * gy;
             C<T> ri = mk<T>(0, 0);
-            if (col == 1) ri = csub(csub(sb[q], cscale(sx[q], sd[q])), l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy));
+            if (col == 1) ri = csub(csub(sb[q], cscale(sx[q], sd[q])), l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy));
             if (!gate_go) continue;
             b[col * np + t] = sb[q];
             x[col * np + t] = sx[q];
@@ -480,7 +488,7 @@ struct L0PreTile {
 // Up: black += (P x_c)_b, red, black, last red; z = x on the tile's nodes (ADD:
 // z += x) and partial sums of Re<vdot, z> (L0ProlongBlack, L0Sweep(0),
 // L0Sweep(1), L0Last).
-template <class T, class TC, int ADD>
+template <class T, class TC, int ADD, class S>
 struct L0PostTile {
     GeomT<T> g;
     const C<T> *b, *x;
@@ -497,15 +505,15 @@ struct L0PostTile {
     __device__ void operator()(int bx, int nbx) const
     {
         GATE_LOAD();
-        __shared__ C<T> sb[kL0LN], sx[kL0LN], ux[kL0LN], uy[kL0LN];
-        __shared__ T sd[kL0LN];
-        __shared__ double sm[kL0Threads / 64];
-        const L0TileAt T0 = l0_tile(xcd_tile(bx, nbx), ntx);
+        __shared__ C<T> sb[S::LN], sx[S::LN], ux[S::LN], uy[S::LN];
+        __shared__ T sd[S::LN];
+        __shared__ double sm[S::threads / 64];
+        const L0TileAt T0 = l0_tile<S>(xcd_tile(bx, nbx), ntx);
         const int np = g.npair;
-        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+        for (int q = threadIdx.x; q < S::LN; q += S::threads) {
             int gx, gy, ring;
             bool in;
-            l0_pos(T0, q, g.N, gx, gy, in, ring);
+            l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
             C<T> bi = mk<T>(0, 0), xi = mk<T>(0, 0), lx = xi, ly = xi;
             T di = (T)1;
             if (in) {
@@ -528,25 +536,25 @@ struct L0PostTile {
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             const int col = pass;
-            for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+            for (int q = threadIdx.x; q < S::LN; q += S::threads) {
                 int gx, gy, ring;
                 bool in;
-                l0_pos(T0, q, g.N, gx, gy, in, ring);
+                l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
                 if (!in || ring < pass + 1 || ((gx + gy) & 1) != col) continue;
-                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
             }
             __syncthreads();
         }
         // last red on the tile, into z only; z on every node of the tile
         double part = 0.0;
-        for (int q = threadIdx.x; q < kL0LN; q += kL0Threads) {
+        for (int q = threadIdx.x; q < S::LN; q += S::threads) {
             int gx, gy, ring;
             bool in;
-            l0_pos(T0, q, g.N, gx, gy, in, ring);
-            if (!in || ring < kL0H) continue;
+            l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
+            if (!in || ring < S::H) continue;
             C<T> xi = sx[q];
             if (((gx + gy) & 1) == 0)
-                xi = cscale(csub(sb[q], l0_offdiag_lds<T>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+                xi = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
             const int i = gx + g.N[0] * gy;
             double2 zi = widen(xi);
             if (ADD) zi = cadd(z[i], zi);
@@ -1253,6 +1261,15 @@ static void csr_residual(Level &Lv, int shift, const int *gate, const Launch &L)
     });
 }
 
+// calls f with the tile shape of gl_tiles.l0_tiled (1, 2 or 3)
+template <class F>
+static void l0_tiled_shape(int which, F &&f)
+{
+    if (which == 1) f(L0Shape1{});
+    else if (which == 2) f(L0Shape2{});
+    else f(L0Shape3{});
+}
+
 // T: level 0 (stencil sweeps, where the bytes are); TC: levels >= 1 and the
 // coarsest solve (latency-bound: their precision costs no bandwidth)
 template <int DIM, class T, class TC>
@@ -1299,13 +1316,17 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     // black, red, black residual, restriction; in 2D by default the three
     // passes in one LDS-tiled kernel (L0PreTile)
     const int nbp = blocks_for(g.npair);
-    const bool tiled = DIM == 2 && pre->l0_tiled;
-    const int ntx = (g.N[0] + kL0TX - 1) / kL0TX, nbt = ntx * ((g.N[1] + kL0TY - 1) / kL0TY);
+    const int tiled = DIM == 2 ? pre->l0_tiled : 0;
     if (tiled) {
         // each array once (the halo's re-reads come from cache)
         const double b_tile = nn * 16 + nn * szr + 2 * nn * sz + mc * sz;
         prof_launch(PROF_L0_SWEEP, b_tile, L, [&] {
-            L.run<L0PreTile<T>, kL0Threads>(nbt, L0PreTile<T>{g, v, hd, U, vec_b<T>(L0), x0, vec_r<T>(L0), ntx, gate});
+            l0_tiled_shape(tiled, [&](auto sh) {
+                using S = decltype(sh);
+                const int ntx = (g.N[0] + S::TX - 1) / S::TX, nbt = ntx * ((g.N[1] + S::TY - 1) / S::TY);
+                L.run<L0PreTile<T, S>, S::threads>(nbt,
+                                                   L0PreTile<T, S>{g, v, hd, U, vec_b<T>(L0), x0, vec_r<T>(L0), ntx, gate});
+            });
         });
     } else {
         prof_launch(PROF_L0_SWEEP, b_pre, L, [&] {
@@ -1354,15 +1375,21 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     if (tiled) {
         const double b_tile = (g.npair + 1 + L0.Pb.nnz) * 4.0 + L0.Pb.nnz * szc + L0.nc * szc + mc * sz +
                               nn * sz + nn * szr + nn * 16 * (want ? 2 : 1) + (add ? nn * 16 : 0);
+        int nbt = 0;
         prof_launch(PROF_L0_SWEEP, b_tile, L, [&] {
-            if (add)
-                L.run<L0PostTile<T, TC, 1>, kL0Threads>(
-                    nbt, L0PostTile<T, TC, 1>{g, b0, x0, hd, U, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
-                                              vec_x<TC>(L1), z, vdot, slot, want, ntx, gate});
-            else
-                L.run<L0PostTile<T, TC, 0>, kL0Threads>(
-                    nbt, L0PostTile<T, TC, 0>{g, b0, x0, hd, U, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
-                                              vec_x<TC>(L1), z, vdot, slot, want, ntx, gate});
+            l0_tiled_shape(tiled, [&](auto sh) {
+                using S = decltype(sh);
+                const int ntx = (g.N[0] + S::TX - 1) / S::TX;
+                nbt = ntx * ((g.N[1] + S::TY - 1) / S::TY);
+                if (add)
+                    L.run<L0PostTile<T, TC, 1, S>, S::threads>(
+                        nbt, L0PostTile<T, TC, 1, S>{g, b0, x0, hd, U, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
+                                                     vec_x<TC>(L1), z, vdot, slot, want, ntx, gate});
+                else
+                    L.run<L0PostTile<T, TC, 0, S>, S::threads>(
+                        nbt, L0PostTile<T, TC, 0, S>{g, b0, x0, hd, U, L0.Pb.rp.get(), L0.Pb.ci.get(), vals<TC>(L0.Pb),
+                                                     vec_x<TC>(L1), z, vdot, slot, want, ntx, gate});
+            });
         });
         if (want) launch_finalize(slot.partials, nbt, fmode, ks, store, gate, L);
         return;

@@ -437,8 +437,8 @@ def test_mesh_independent_iteration_counts(glnk):
                                   ((70, 45), (7.0, 4.5), 0.6), ((5, 3), (2.0, 1.0), 0.9)],
                          ids=["33x33", "37x23", "24x17", "129x129", "70x45", "5x3"])
 def test_level0_tiles_bitwise(glnk, grid):
-    """2D level 0 in two LDS-tiled kernels against one dispatch per pass (the
-    default): the V-cycle's output agrees to rounding (every node value is the
+    """2D level 0 in two LDS-tiled kernels, each tile shape, against one
+    dispatch per pass (the default): the V-cycle's output agrees to rounding (every node value is the
     same expression in the same order; the compiler may contract its
     multiply-adds differently in the two kernels), FP64 within 1e-13, FP32
     and mixed within 1e-6; k = 3 cycles (the accumulating output); tiles with
@@ -453,12 +453,13 @@ def test_level0_tiles_bitwise(glnk, grid):
     z2 = torch.empty_like(r)
     for prec, cycles in ((glnk.GL_FP64, 1), (glnk.GL_FP32, 1), (glnk.GL_MIXED, 1), (glnk.GL_FP64, 3)):
         pre.update(psi, precision=prec, cycles=cycles)
-        glnk.gl_precond_set_tiles(pre, 0, 0, 0, 1)
-        pre.apply(r, z1)
         glnk.gl_precond_set_tiles(pre, 0, 0, 0, 0)
         pre.apply(r, z2)
-        e = relerr(host(z1), host(z2))
-        assert e < (1e-13 if prec == glnk.GL_FP64 else 1e-6), (prec, cycles, e)
+        for shape in (1, 2, 3):
+            glnk.gl_precond_set_tiles(pre, 0, 0, 0, shape)
+            pre.apply(r, z1)
+            e = relerr(host(z1), host(z2))
+            assert e < (1e-13 if prec == glnk.GL_FP64 else 1e-6), (prec, cycles, shape, e)
     # and MINRES through the tiled level 0 against the oracle (fixed count)
     mo = oracle.Mesh(2, N, side, mu=mu)
     hp = host(psi)
@@ -469,3 +470,27 @@ def test_level0_tiles_bitwise(glnk, grid):
     xo, io, _ = oracle.minres(mo, hp, b, amg=amg, rtol=0.0, max_iter=5)
     rc, ig = glnk.gl_jacobian_solve(mg, psi, pre, dev(b), z1, rtol=0.0, max_iter=5, poll_every=2)
     assert relerr(host(z1), xo) < 1e-12
+
+
+def test_level0_tiles_full_size(glnk):
+    """The benchmark's 1025 x 1025 grid (4225 tiles of 16 x 16 nodes, a
+    one-node ragged row and column of tiles for every shape): each tiled form
+    against one dispatch per pass, FP64 within 1e-13 and FP32 within 1e-6."""
+    N = (1025, 1025)
+    mg = glnk.Mesh(2, N, (10.0, 10.0), mu=1.0)
+    n = N[0] * N[1]
+    psi = dev(inputs.random_phase_state(n, seed=21))
+    r = dev(inputs.random_complex(n, seed=22))
+    pre = glnk.Precond(mg, psi, max_coarse=512)
+    z1 = torch.empty_like(r)
+    z2 = torch.empty_like(r)
+    for prec in (glnk.GL_FP64, glnk.GL_FP32):
+        pre.update(psi, precision=prec)
+        glnk.gl_precond_set_tiles(pre, 0, 64, 4096, 0)
+        pre.apply(r, z2)
+        ref = host(z2)
+        for shape in (1, 2, 3):
+            glnk.gl_precond_set_tiles(pre, 0, 64, 4096, shape)
+            pre.apply(r, z1)
+            e = relerr(host(z1), ref)
+            assert e < (1e-13 if prec == glnk.GL_FP64 else 1e-6), (prec, shape, e)

@@ -55,7 +55,7 @@ def test_autotune_picks_fastest_and_caches(tmp_path, monkeypatch):
     best = (1, 2048, 0)
     times[best] = 0.5
     calls = []
-    l0 = {0: 0.5, 1: 0.4}  # seconds per iteration of the chosen set by level-0 form
+    l0 = {0: 0.5, 1: 0.45, 2: 0.4, 3: 0.42}  # seconds per iteration of the chosen set by level-0 form
 
     def fake_time(mesh, psi, pre, tiles, iters=24, reps=3):
         calls.append(tiles)
@@ -65,23 +65,23 @@ def test_autotune_picks_fastest_and_caches(tmp_path, monkeypatch):
     monkeypatch.setattr(autotune, "_key", lambda mesh, p, mc: f"dev|{mesh.shape}|{p}|{mc}")
     monkeypatch.setattr(glnk, "Precond", FakePrecond)
     cache = str(tmp_path / "tiles.json")
-    assert autotune.tune(FakeMesh(), None, cache=cache) == best + (1,)
-    # each distinct split timed once, by its first candidate; then both
-    # level-0 forms of the fastest
+    assert autotune.tune(FakeMesh(), None, cache=cache) == best + (2,)
+    # each distinct split timed once, by its first candidate; then every
+    # level-0 form of the fastest
     coarse = [t for t in calls if len(t) == 3]
-    assert sorted(t for t in calls if len(t) == 4) == [best + (0,), best + (1,)]
+    assert sorted(t for t in calls if len(t) == 4) == [best + (k,) for k in range(4)]
     splits = [autotune.split(FakePrecond.INFO, t) for t in coarse]
     assert len(set(splits)) == len(splits)
     assert set(splits) == {autotune.split(FakePrecond.INFO, t) for t in autotune.CANDIDATES}
     assert len(coarse) < len(autotune.CANDIDATES)
     table = json.load(open(cache))
     (entry,) = table.values()
-    assert tuple(entry["tiles"]) == best + (1,)
+    assert tuple(entry["tiles"]) == best + (2,)
     calls.clear()
-    assert autotune.tune(FakeMesh(), None, cache=cache) == best + (1,)  # from the cache
+    assert autotune.tune(FakeMesh(), None, cache=cache) == best + (2,)  # from the cache
     assert calls == []
     # the one-dispatch form when it is the faster; none tried in a batch
-    l0[1] = 0.6
+    l0.update({1: 0.6, 2: 0.6, 3: 0.6})
     assert autotune.tune(FakeMesh(), None) == best + (0,)
     calls.clear()
     assert autotune.tune(FakeMesh(), None, batch=True)[3] == 0
