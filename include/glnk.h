@@ -317,6 +317,14 @@ typedef struct {
     int use_precond;  /* 0: unpreconditioned MINRES */
     gl_krylov_opts krylov;
     gl_amg_opts amg;
+    int linesearch;   /* 0: the full Newton step (the method as stated in
+                         Sec. 4); k in 1..30: backtracking, the step length
+                         alpha = 1, 1/2, ... (at most k halvings) until
+                         ||GL(psi + alpha dpsi)||_D <= (1 - 1e-4 alpha)
+                         ||GL(psi)||_D, else the last one tried.  A
+                         globalisation this library adds: plain Newton from
+                         a poor start (past a fold of the tracked branch) can
+                         cycle or diverge */
 } gl_newton_opts;
 
 typedef struct {
@@ -324,10 +332,12 @@ typedef struct {
     int converged;
     double res[64];         /* ||GL(psi_k)||_D, k = 0 .. steps */
     int krylov_iters[64];   /* MINRES iterations of step k */
+    double alpha[64];       /* step length taken at step k (1 without linesearch) */
 } gl_newton_info;
 
 /* Newton for GL(psi) = 0 starting from psi_inout (eq. Newton system):
- * per step, set up R_k(psi), solve J(psi) dpsi = -GL(psi), psi += dpsi.
+ * per step, set up R_k(psi), solve J(psi) dpsi = -GL(psi), psi += alpha
+ * dpsi (alpha = 1 unless opts->linesearch > 0).
  * psi_inout is overwritten with the last iterate.  pre_inout (nullable):
  * a preconditioner handle of this mesh to reuse (only its values are
  * recomputed), or a pointer to NULL that receives the handle built on the

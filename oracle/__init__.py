@@ -57,7 +57,7 @@ class _KInfo(C.Structure):
 
 class _NInfo(C.Structure):
     _fields_ = [("steps", C.c_int), ("converged", C.c_int), ("res", C.c_double * 64),
-                ("krylov_iters", C.c_int * 64)]
+                ("krylov_iters", C.c_int * 64), ("alpha", C.c_double * 64)]
 
 
 _OP = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -92,7 +92,7 @@ def lib():
                                          C.c_int, vp, C.POINTER(_KInfo)]
         L.orc_minres_deflated.argtypes = L.orc_minres.argtypes
         L.orc_newton.argtypes = [C.POINTER(_Mesh), vp, C.c_double, C.c_int, C.c_int, C.c_double,
-                                 C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_NInfo)]
+                                 C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_NInfo)]
         _lib = L
     return _lib
 
@@ -339,13 +339,17 @@ def minres_generic(w, A, b, minv=None, rtol=1e-10, max_iter=1000):
 
 
 def newton(mesh, psi0, tol=1e-10, max_steps=50, fixed_steps=0, krylov_rtol=1e-10,
-           krylov_max_iter=1000, use_amg=True, cycles=1, max_coarse=64, deflate=False):
+           krylov_max_iter=1000, use_amg=True, cycles=1, max_coarse=64, deflate=False, linesearch=0):
     """Newton for GL(psi) = 0 with MINRES + R_k inner solves (Sec. 2, Sec. 4);
-    with deflate, each step is solved on the complement of i psi."""
+    with deflate, each step is solved on the complement of i psi; with
+    linesearch > 0, backtracking on ||GL||_D (at most that many halvings of
+    the step, a globalisation the paper does not use)."""
     psi = _c128(psi0).copy()
     ni = _NInfo()
     rc = lib().orc_newton(mesh._p, _ptr(psi), tol, max_steps, fixed_steps, krylov_rtol,
-                          krylov_max_iter, int(use_amg), cycles, max_coarse, int(deflate), C.byref(ni))
+                          krylov_max_iter, int(use_amg), cycles, max_coarse, int(deflate), int(linesearch),
+                          C.byref(ni))
     info = {"status": rc, "steps": ni.steps, "converged": bool(ni.converged),
-            "res": list(ni.res[:ni.steps + 1]), "krylov_iters": list(ni.krylov_iters[:ni.steps])}
+            "res": list(ni.res[:ni.steps + 1]), "krylov_iters": list(ni.krylov_iters[:ni.steps]),
+            "alpha": list(ni.alpha[:ni.steps])}
     return psi, info

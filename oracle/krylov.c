@@ -195,11 +195,11 @@ int orc_minres_deflated(const orc_mesh *m, const cplx *psi, const orc_amg *amg, 
 /* ----------------------------------------------------------- Newton --- */
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               int max_coarse, int deflate, orc_newton_info *info)
+               int max_coarse, int deflate, int linesearch, orc_newton_info *info)
 {
     const int64_t n = m->n;
     cplx *r = malloc((size_t)n * sizeof(cplx)), *b = malloc((size_t)n * sizeof(cplx));
-    cplx *dx = malloc((size_t)n * sizeof(cplx));
+    cplx *dx = malloc((size_t)n * sizeof(cplx)), *psik = malloc((size_t)n * sizeof(cplx));
     cplx *hv = malloc((size_t)m->rp[n] * sizeof(cplx));
     int rc = ORC_OK;
     memset(info, 0, sizeof(*info));
@@ -225,10 +225,21 @@ int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixe
                           : orc_minres(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, NULL, &ki);
         orc_amg_free(amg);
         if (krc != ORC_OK && krc != ORC_ERR_NOT_CONVERGED) { rc = krc; break; }
-        for (int64_t i = 0; i < n; ++i) psi[i] += dx[i];
-        orc_gl(m, psi, r);
-        res = sqrt(orc_inner(m, r, r));
+        /* psi_{k+1} = psi_k + alpha dx: alpha = 1, halved while the residual
+         * norm does not fall by the factor 1 - 1e-4 alpha (at most linesearch
+         * times) */
+        memcpy(psik, psi, (size_t)n * sizeof(cplx));
+        double alpha = 1.0, res_new;
+        for (int h = 0;; ++h) {
+            for (int64_t i = 0; i < n; ++i) psi[i] = psik[i] + alpha * dx[i];
+            orc_gl(m, psi, r);
+            res_new = sqrt(orc_inner(m, r, r));
+            if (h == linesearch || res_new <= (1.0 - 1e-4 * alpha) * res) break;
+            alpha *= 0.5;
+        }
+        res = res_new;
         info->krylov_iters[k] = ki.iterations;
+        info->alpha[k] = alpha;
         ++k;
         info->res[k] = res;
         if (!isfinite(res)) { rc = ORC_ERR_NOT_CONVERGED; break; }
@@ -236,6 +247,6 @@ int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixe
     info->steps = k;
     info->converged = res < tol;
     if (rc == ORC_OK && fixed_steps <= 0 && !info->converged) rc = ORC_ERR_NOT_CONVERGED;
-    free(r); free(b); free(dx); free(hv);
+    free(r); free(b); free(dx); free(psik); free(hv);
     return rc;
 }

@@ -146,12 +146,16 @@ typedef struct {
     int converged;
     double res[64];       /* ||GL(psi_k)||_D, k = 0..steps */
     int krylov_iters[64];
+    double alpha[64];     /* step length of step k */
 } orc_newton_info;
 
 /* deflate != 0: every Newton step is solved on the complement of i psi
- * (orc_minres_deflated). */
+ * (orc_minres_deflated).  linesearch > 0 (not part of the paper's method, a
+ * standard globalisation of Newton): the step psi_k + alpha dpsi takes the
+ * first alpha in 1, 1/2, ..., 2^-linesearch with ||GL||_D <= (1 - 1e-4 alpha)
+ * ||GL(psi_k)||_D, else the last one. */
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               int max_coarse, int deflate, orc_newton_info *info);
+               int max_coarse, int deflate, int linesearch, orc_newton_info *info);
 
 #endif

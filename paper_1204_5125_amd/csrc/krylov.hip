@@ -419,6 +419,21 @@ __global__ void k_add(int n, double2 *x, const double2 *d)
     if (i < n) x[i] = cadd(x[i], d[i]);
 }
 
+// x += c d (a backtracking step of the Newton line search)
+__global__ void k_axpy(int n, double c, double2 *x, const double2 *d)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] = cadd(x[i], cscale(d[i], c));
+}
+
+// Sufficient decrease of the Newton line search: a step of length alpha is
+// kept when the residual norm falls by the factor 1 - 1e-4 alpha (false for
+// NaN).
+static bool newton_accepts(double res_new, double res_old, double alpha)
+{
+    return res_new <= (1.0 - 1e-4 * alpha) * res_old;
+}
+
 // r = b - J(psi) x
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_residual_vec(GeomT<double> g, const double2 *__restrict__ psi,
@@ -827,6 +842,8 @@ gl_status gl_newton_solve(const gl_mesh *mesh, void *psi_inout, const gl_newton_
         check_krylov_opts(&opts->krylov, "gl_newton_solve");
         if (opts->max_steps < 0 || opts->max_steps > 63 || opts->fixed_steps < 0 || opts->fixed_steps > 63)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_newton_solve: steps must be in 0..63");
+        if (opts->linesearch < 0 || opts->linesearch > 30)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_newton_solve: linesearch must be in 0..30");
         hipStream_t s = as_stream(stream);
         const int n = mesh->g.n;
         double2 *psi = (double2 *)psi_inout;
@@ -858,8 +875,17 @@ gl_status gl_newton_solve(const gl_mesh *mesh, void *psi_inout, const gl_newton_
             k_sub<<<blocks_for(n), kBlock, 0, s>>>(n, psi, dx);
             GLK_CHECK_LAUNCH();
             ni.krylov_iters[k] = ki.iterations;
+            double res_new = residual(), alpha = 1.0;
+            // backtracking: psi = psi_k - alpha dpsi_k with alpha halved
+            for (int h = 0; h < opts->linesearch && !newton_accepts(res_new, res, alpha); ++h) {
+                k_axpy<<<blocks_for(n), kBlock, 0, s>>>(n, 0.5 * alpha, psi, dx);
+                GLK_CHECK_LAUNCH();
+                alpha *= 0.5;
+                res_new = residual();
+            }
+            ni.alpha[k] = alpha;
             ++k;
-            res = residual();
+            res = res_new;
             ni.res[k] = res;
         }
         ni.steps = k;
@@ -1318,15 +1344,20 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
     B->deflate = o.krylov.deflate;
     for (int i = 0; i < N; ++i) k_ks_stop<<<1, 1, 0, B->s>>>(kscal_of(B->meshes[i]));
     GLK_CHECK_LAUNCH();
-    auto residuals = [&]() {
-        for (int i = 0; i < N; ++i) {
-            if (!active[i]) continue;
+    // residual norms of the instances in `which` into out[i]
+    auto residuals_of = [&](const std::vector<int> &which, std::vector<double> &out) {
+        for (int i : which) {
             gl_mesh *m = B->meshes[i];
             gl_residual_enqueue(m, psi[i], m->work.get() + 7 * (size_t)m->g.n, m->dscal.get(), B->s);
         }
         batch_gather(B);
+        for (int i : which) out[i] = std::sqrt(B->host_sc[i].res2);
+    };
+    auto residuals = [&]() {
+        std::vector<int> all;
         for (int i = 0; i < N; ++i)
-            if (active[i]) res[i] = std::sqrt(B->host_sc[i].res2);
+            if (active[i]) all.push_back(i);
+        residuals_of(all, res);
     };
     using clk = std::chrono::steady_clock;
     auto since = [](clk::time_point t) { return std::chrono::duration<double>(clk::now() - t).count(); };
@@ -1381,10 +1412,33 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
         }
         B->seconds[2] += since(t0);
         t0 = clk::now();
-        residuals();
-        B->seconds[0] += since(t0);
+        std::vector<int> upd;
         for (int i : act)
-            if (active[i]) ni[i].res[k + 1] = res[i];
+            if (active[i]) upd.push_back(i);
+        std::vector<double> res_new(N, 0.0), alpha(N, 1.0);
+        residuals_of(upd, res_new);
+        // backtracking, the instances whose step does not reduce the residual
+        // enough halve theirs together (as in gl_newton_solve)
+        for (int h = 0; h < o.linesearch; ++h) {
+            std::vector<int> back;
+            for (int i : upd)
+                if (!newton_accepts(res_new[i], res[i], alpha[i])) back.push_back(i);
+            if (back.empty()) break;
+            for (int i : back) {
+                gl_mesh *m = B->meshes[i];
+                const int n = m->g.n;
+                k_axpy<<<blocks_for(n), kBlock, 0, B->s>>>(n, 0.5 * alpha[i], psi[i], m->work.get() + 8 * (size_t)n);
+                alpha[i] *= 0.5;
+            }
+            GLK_CHECK_LAUNCH();
+            residuals_of(back, res_new);
+        }
+        B->seconds[0] += since(t0);
+        for (int i : upd) {
+            res[i] = res_new[i];
+            ni[i].res[k + 1] = res[i];
+            ni[i].alpha[k] = alpha[i];
+        }
     }
     gl_status rc = GL_OK;
     for (int i = 0; i < N; ++i) {
@@ -1473,6 +1527,8 @@ gl_status gl_batch_newton_solve(gl_batch *batch, void *const *psi_inout, const g
         check_krylov_opts(&opts->krylov, "gl_batch_newton_solve");
         if (opts->max_steps < 0 || opts->max_steps > 63 || opts->fixed_steps < 0 || opts->fixed_steps > 63)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: steps must be in 0..63");
+        if (opts->linesearch < 0 || opts->linesearch > 30)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: linesearch must be in 0..30");
         if (profiler().kernel != 0) fail(GL_ERR_UNSUPPORTED, "gl_batch_newton_solve: not under gl_profile_start");
         hipStream_t s = as_stream(stream);
         batch->graph_launches = 0;

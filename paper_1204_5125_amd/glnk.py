@@ -68,7 +68,7 @@ class KrylovInfo(C.Structure):
 
 class NewtonOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_steps", C.c_int), ("fixed_steps", C.c_int),
-                ("use_precond", C.c_int), ("krylov", KrylovOpts), ("amg", AmgOpts)]
+                ("use_precond", C.c_int), ("krylov", KrylovOpts), ("amg", AmgOpts), ("linesearch", C.c_int)]
 
 
 class Tiles(C.Structure):
@@ -82,7 +82,7 @@ class AdamOpts(C.Structure):
 
 class NewtonInfo(C.Structure):
     _fields_ = [("steps", C.c_int), ("converged", C.c_int), ("res", C.c_double * 64),
-                ("krylov_iters", C.c_int * 64)]
+                ("krylov_iters", C.c_int * 64), ("alpha", C.c_double * 64)]
 
 
 _lib = None
@@ -439,26 +439,27 @@ class PrecondHandle:
 def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
                     krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
                     relax_rtol=0.0, precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, precond=None,
-                    deflate=False, stream=None, raise_on_fail=True):
+                    deflate=False, linesearch=0, stream=None, raise_on_fail=True):
     """Newton for GL(psi) = 0 in place; returns (status, info dict).  precond:
     an optional PrecondHandle whose hierarchy is reused (and filled on first use);
-    deflate: each step under the phase condition <i psi, dpsi>_R = 0."""
+    deflate: each step under the phase condition <i psi, dpsi>_R = 0;
+    linesearch: at most this many halvings of a step that does not reduce
+    ||GL||_D enough (0: full steps)."""
     o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
                    KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, relax_rtol, int(deflate)),
-                   AmgOpts(precision, cycles, max_coarse, max_levels))
+                   AmgOpts(precision, cycles, max_coarse, max_levels), int(linesearch))
     ni = NewtonInfo()
     rc = lib().gl_newton_solve(mesh.handle, _vec(psi, mesh.n, "psi"), C.byref(o),
                                C.byref(precond.handle) if precond is not None else None, C.byref(ni),
                                _stream(stream))
     if raise_on_fail:
         _check(rc, "gl_newton_solve", allow=(4,))
-    return rc, {"steps": ni.steps, "converged": bool(ni.converged), "res": list(ni.res[:ni.steps + 1]),
-                "krylov_iters": list(ni.krylov_iters[:ni.steps])}
+    return rc, _newton_info(ni)
 
 
 def _newton_info(ni):
     return {"steps": ni.steps, "converged": bool(ni.converged), "res": list(ni.res[:ni.steps + 1]),
-            "krylov_iters": list(ni.krylov_iters[:ni.steps])}
+            "krylov_iters": list(ni.krylov_iters[:ni.steps]), "alpha": list(ni.alpha[:ni.steps])}
 
 
 def gl_precond_set_tiles(pre, lane_shift=0, bottom_rows=0, dense_rows=0, l0_tiled=0):
@@ -494,8 +495,8 @@ class Batch:
 
     def newton_solve(self, psis, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
                      krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
-                     precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, deflate=False, stream=None,
-                     raise_on_fail=True):
+                     precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, deflate=False, linesearch=0,
+                     stream=None, raise_on_fail=True):
         """Newton on every instance in place (psis[i] on meshes[i]); returns
         (status, [info dict per instance])."""
         if len(psis) != len(self.meshes):
@@ -503,7 +504,7 @@ class Batch:
         ptrs = (C.c_void_p * len(psis))(*[_vec(p, m.n, "psi") for p, m in zip(psis, self.meshes)])
         o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
                        KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, 0.0, int(deflate)),
-                       AmgOpts(precision, cycles, max_coarse, max_levels))
+                       AmgOpts(precision, cycles, max_coarse, max_levels), int(linesearch))
         infos = (NewtonInfo * len(psis))()
         rc = lib().gl_batch_newton_solve(self._h, ptrs, C.byref(o), infos, _stream(stream))
         if raise_on_fail:

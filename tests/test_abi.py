@@ -55,3 +55,38 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(glnk, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         glnk.lib()
+
+
+# ctypes mirror of each C struct of the header
+STRUCTS = {"gl_grid_desc": "GridDesc", "gl_amg_opts": "AmgOpts", "gl_krylov_opts": "KrylovOpts",
+           "gl_krylov_info": "KrylovInfo", "gl_newton_opts": "NewtonOpts", "gl_tiles": "Tiles",
+           "gl_adam_opts": "AdamOpts", "gl_newton_info": "NewtonInfo"}
+
+
+def test_binding_struct_layouts_match_header(tmp_path):
+    """Size and every field offset of the binding's ctypes structures equal
+    what the C compiler lays out from include/glnk.h."""
+    import shutil
+    import subprocess
+
+    from paper_1204_5125_amd import glnk
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "glnk.h"', "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(glnk, pyname)
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in cls._fields_:
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(glnk, pyname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f in cls._fields_:
+            assert got[(cname, f[0])] == getattr(cls, f[0]).offset, (cname, f[0])
