@@ -40,6 +40,7 @@ def log(msg):
 
 
 MAX_COARSE = 512
+BATCH_HALVINGS = 3   # batched continuation: halvings of a step whose Newton fails
 # tiles of the single counter pass (--one-pass): the autotuner's choice for
 # this grid on MI355X, FP32 and FP64 alike (lane_shift, bottom_rows, dense_rows)
 ONE_PASS_TILES = (0, 64, 4096)
@@ -189,23 +190,35 @@ def one_pass():
     torch.cuda.synchronize()
 
 
-def newton_rounds(batch, psis, max_rounds, tag, **kw):
+def newton_rounds(batch, psis, max_rounds, tag, totals=None, **kw):
     """Batched Newton one lock-step round per call (the same work as one call
-    with max_steps = max_rounds, with a progress line per round)."""
+    with max_steps = max_rounds, with a progress line per round); the
+    library's per-call statistics are added up in `totals`."""
     solves = iters = 0
     infos = None
+    hist = [[] for _ in psis]  # per instance: (GL residual, MINRES iterations) of each Newton step
     for r in range(max_rounds):
         rc, infos = batch.newton_solve(psis, max_steps=1, raise_on_fail=False, **kw)
+        st = batch.stats()
+        if totals is not None:
+            totals["graph_launches"] += st["graph_launches"]
+            totals["dispatches_per_graph"] = max(totals["dispatches_per_graph"], st["dispatches_per_graph"])
+            totals["groups"] = max(totals["groups"], st["groups"])
+            for k, v in st["seconds"].items():
+                totals["seconds"][k] += v
         n = sum(i["steps"] for i in infos)
         if n == 0:
             break
         solves += n
         iters += sum(sum(i["krylov_iters"]) for i in infos)
-        sec = batch.stats()["seconds"]
+        for k, i in enumerate(infos):
+            if i["steps"]:
+                hist[k].append((i["res"][-1], i["krylov_iters"][-1]))
+        sec = st["seconds"]
         log(f"[bench] {tag} round {r + 1}: {n} solves, {iters} iterations so far; "
             f"setup {sec['setup']:.2f} s, solve {sec['solve']:.2f} s")
     bad = [k for k, i in enumerate(infos) if not i["res"][-1] < kw["tol"]]
-    return solves, iters, len(infos) - len(bad), bad
+    return solves, iters, len(infos) - len(bad), {k: hist[k] for k in bad}
 
 
 def bench_batch(args):
@@ -214,7 +227,10 @@ def bench_batch(args):
     outer iterations.  Untimed: autotuning of the tiles per grid size and the
     warm start (Newton from psi = 1 at mu_k).  Timed: `steps` continuation
     steps of dmu = 0.02 (secant predictor after the first), each one batched
-    Newton solve of all instances."""
+    Newton solve of all instances; an instance whose Newton does not converge
+    within 15 steps retries from its last solution with the step halved (at
+    most 3 times: the tracked branch can end at a fold), in a batched solve
+    of the retrying instances."""
     import numpy as np
     import torch
 
@@ -245,29 +261,56 @@ def bench_batch(args):
     prev = [p.clone() for p in psis]
     pred = [torch.empty_like(p) for p in psis]
     mu_now = list(mus)
-    solves = iters = conv = 0
-    unconverged = []
+    hlast = [None] * count   # each instance's last continuation step (none before the first)
+    solves = iters = conv = first = 0
+    unconverged, halved, folds = [], [], []
+    totals = {"graph_launches": 0, "dispatches_per_graph": 0, "groups": 0,
+              "seconds": {"residual": 0.0, "setup": 0.0, "solve": 0.0}}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for step in range(args.steps):
-        for i, m in enumerate(meshes):
-            m.set_field(mu_now[i] + dmu)
-            if step == 0:
-                pred[i].copy_(psis[i])
+        # every instance tries the full step; one that does not converge
+        # within 15 Newton steps retries from its last solution with the step
+        # halved (at most BATCH_HALVINGS times), as natural continuation does
+        h = [dmu] * count
+        todo = list(range(count))
+        for attempt in range(BATCH_HALVINGS + 1):
+            for i in todo:
+                meshes[i].set_field(mu_now[i] + h[i])
+                if hlast[i] is None:
+                    pred[i].copy_(psis[i])
+                else:
+                    glnk.gl_secant_predict(meshes[i], psis[i], prev[i], h[i] / hlast[i], pred[i])
+            tag = f"step {step + 1}" + (f" retry {attempt}" if attempt else "")
+            s_, i_, c_, bad = newton_rounds(batch, pred, 15, tag, totals, krylov_max_iter=1000, **kw)
+            solves += s_
+            iters += i_
+            if attempt == 0:
+                first += c_
+                unconverged += [{"step": step + 1, "instance": i, "N": int(sizes[i]), "mu": mu_now[i] + dmu,
+                                 "gl_residual_and_minres_iterations": hh} for i, hh in bad.items()]
             else:
-                glnk.gl_secant_predict(m, psis[i], prev[i], 1.0, pred[i])
-        s_, i_, c_, bad = newton_rounds(batch, pred, 15, f"step {step + 1}", krylov_max_iter=1000, **kw)
-        solves += s_
-        iters += i_
-        conv += c_
-        unconverged += [{"step": step + 1, "instance": i, "N": int(sizes[i]), "mu": mu_now[i] + dmu} for i in bad]
+                halved += [{"step": step + 1, "instance": i, "N": int(sizes[i]), "mu": mu_now[i] + h[i],
+                            "dmu": h[i]} for i in todo if i not in bad]
+            todo = [i for i in todo if i in bad]
+            if not todo:
+                break
+            for i in todo:
+                h[i] *= 0.5
+        for i in todo:  # no step size worked: the instance stays where it is
+            folds.append({"step": step + 1, "instance": i, "N": int(sizes[i]), "mu": mu_now[i]})
+            meshes[i].set_field(mu_now[i])
+        conv += count - len(todo)
         for i in range(count):
+            if i in todo:
+                continue
             prev[i].copy_(psis[i])
             psis[i].copy_(pred[i])
-            mu_now[i] += dmu
+            mu_now[i] += h[i]
+            hlast[i] = h[i]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    st = batch.stats()
+    st = totals
     out = {
         "metric": "batched Jacobian solves/s (continuation, 64 instances)",
         "value": solves / dt, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -275,9 +318,10 @@ def bench_batch(args):
         "vs_baseline": None, "dtype": "f64 (outer) / " + ("f64" if args.batch_fp64 else "f32") + " (V-cycle)",
         "data": "synthetic: 64 continuation instances, grid sizes drawn with seed 0",
         "config": {"workload": "64 instances, 2D grids of 129^2 / 257^2 / 513^2 nodes (seed 0), side 10, "
-                               "mu_k = 2k/63, continuation steps of 0.02 with the secant predictor, "
-                               "Newton to 1e-10, MINRES to 1e-10 (deflated unless --batch-plain), FP32 V-cycle "
-                               "(FP64 with --batch-fp64)",
+                               "mu_k = 2k/63, continuation steps of 0.02 with the secant predictor (an "
+                               "instance that fails retries with the step halved, up to 3 times), "
+                               "Newton to 1e-10 within 15 steps, MINRES to 1e-10 (deflated unless --batch-plain), "
+                               "FP32 V-cycle (FP64 with --batch-fp64)",
                    "sizes": {str(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))},
                    "tiles": {str(k): list(v) for k, v in tiles.items()},
                    "amg_max_coarse": args.batch_max_coarse},
@@ -285,7 +329,9 @@ def bench_batch(args):
         "dispatches_per_graph": st["dispatches_per_graph"], "groups": st["groups"],
         "graph_launches": st["graph_launches"], "host_seconds": st["seconds"],
         "deflate": not args.batch_plain,
-        "converged_fraction": conv / (count * args.steps), "unconverged": unconverged,
+        "converged_fraction": conv / (count * args.steps),
+        "converged_first_try_fraction": first / (count * args.steps), "unconverged_first_try": unconverged,
+        "halved_steps": halved, "folds": folds,
         "graph_launches_per_step": st["graph_launches"] / args.steps,
         "warm_start": {"solves": ws, "iterations": wi, "converged": wc},
     }
