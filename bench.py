@@ -47,8 +47,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "21bd4b65f4ced2984e2ece3b2d204a7158fcda1abefa78973b30af76c1c0a7dd",
-           8: 4953581.8, 2: 20218336.9}
+TRAFFIC = {"csrc_sha256": "01aa18ae38c64e34173cfbfe4792ef7d5f245266bf17cc3af22bba797f171935",
+           8: 4980976.1, 2: 21189177.1}
 
 
 def csrc_fingerprint():
@@ -167,9 +167,10 @@ def iteration_bytes(glnk, pre, precision):
     return total
 
 
-def one_pass():
-    """One Newton step of the headline workload (FP32 V-cycle) and a plain
-    copy of known size, for rocprofv3 counter passes."""
+def one_pass(l0_tiled=0):
+    """One Newton step of the headline workload (FP32 V-cycle; level 0 in
+    LDS tiles of the given shape when l0_tiled > 0) and a plain copy of known
+    size, for rocprofv3 counter passes."""
     import torch
 
     from paper_1204_5125_amd import glnk, inputs
@@ -181,7 +182,7 @@ def one_pass():
     glnk.gl_newton_solve(mesh, psi.clone(), fixed_steps=1, krylov_rtol=RTOL, krylov_max_iter=2,
                          poll_every=2, precision=glnk.GL_FP32, max_coarse=MAX_COARSE, precond=h,
                          raise_on_fail=False)
-    glnk.gl_precond_set_tiles(h, *ONE_PASS_TILES)
+    glnk.gl_precond_set_tiles(h, *ONE_PASS_TILES, l0_tiled)
     glnk.gl_newton_solve(mesh, psi, fixed_steps=1, krylov_rtol=RTOL, krylov_max_iter=8000,
                          poll_every=16, precision=glnk.GL_FP32, max_coarse=MAX_COARSE, precond=h)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -750,6 +751,8 @@ def main():
                     help="for hardware-counter runs: one Newton step of the headline workload with the "
                          "FP32 V-cycle (tiles lane_shift 0, bottom_rows 64, dense_rows 4096), then a 256 MiB elementwise "
                          "copy whose bytes calibrate the counters; prints nothing")
+    ap.add_argument("--one-pass-l0-tiled", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="with --one-pass: level 0 in LDS tiles of this shape (gl_tiles.l0_tiled)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -757,7 +760,7 @@ def main():
         sys.exit(2)
 
     if args.one_pass:
-        one_pass()
+        one_pass(args.one_pass_l0_tiled)
         return
     if args.workload == "batch":
         bench_batch(args)
