@@ -35,7 +35,7 @@ class _Mesh(C.Structure):
     _fields_ = [("dim", C.c_int), ("N", C.c_int64 * 3), ("L", C.c_double * 3),
                 ("h", C.c_double * 3), ("amat", C.c_double * 9), ("n", C.c_int64),
                 ("x", _d), ("vol", _d), ("ne", C.c_int64), ("ej", _i64), ("ek", _i64),
-                ("alpha", _d), ("U", _d), ("rp", _i64), ("ci", _i64), ("kv", _d)]
+                ("alpha", _d), ("U", _d), ("rp", _i64), ("ci", _i64), ("kv", _d), ("grid", C.c_int)]
 
 
 class _Level(C.Structure):
@@ -71,6 +71,9 @@ def lib():
         vp = C.c_void_p
         L.orc_mesh_build.argtypes = [C.c_int, _i64, _d, _d, C.POINTER(C.POINTER(_Mesh))]
         L.orc_mesh_build_dipole.argtypes = [C.c_int, _i64, _d, C.c_double, _d, _d, C.POINTER(C.POINTER(_Mesh))]
+        L.orc_mesh_build_tri.argtypes = [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, _d, C.POINTER(C.POINTER(_Mesh))]
+        L.orc_mesh_build_tri_dipole.argtypes = [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_double, _d, _d,
+                                                C.POINTER(C.POINTER(_Mesh))]
         L.orc_mesh_free.argtypes = [C.POINTER(_Mesh)]
         for f in ("orc_khat_apply",):
             getattr(L, f).argtypes = [C.POINTER(_Mesh), vp, vp]
@@ -145,12 +148,42 @@ class Mesh:
             rc = lib().orc_mesh_build(dim, Na, La, am, C.byref(p))
         if rc != ORC_OK:
             raise OracleError(rc, "orc_mesh_build")
+        self._adopt(p, amat)
+
+    @classmethod
+    def triangles(cls, xy, tri, amat=None, mu=None, bdir=(0.0, 0.0, 1.0), dipole=None):
+        """2D simplicial mesh: nodes xy (n x 2), triangles tri (m x 3); edge
+        coefficients by the Corollary's system per triangle, control volumes
+        as the nodes' shares of their triangles (oracle/oracle.h)."""
+        if amat is None:
+            amat = field_matrix(0.0 if mu is None else mu, bdir) if dipole is None else np.zeros((3, 3))
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int64)
+        p = C.POINTER(_Mesh)()
+        if dipole is not None:
+            dm = (C.c_double * 3)(*[float(v) for v in dipole[0]])
+            dx = (C.c_double * 3)(*[float(v) for v in dipole[1]])
+            rc = lib().orc_mesh_build_tri_dipole(len(xy), _ptr(xy), len(tri), _ptr(tri),
+                                                 1.0 if mu is None else float(mu), dm, dx, C.byref(p))
+        else:
+            am = (C.c_double * 9)(*np.asarray(amat, dtype=np.float64).ravel())
+            rc = lib().orc_mesh_build_tri(len(xy), _ptr(xy), len(tri), _ptr(tri), am, C.byref(p))
+        if rc != ORC_OK:
+            raise OracleError(rc, "orc_mesh_build_tri")
+        self = cls.__new__(cls)
+        self._adopt(p, amat)
+        self.tri = tri.copy()
+        return self
+
+    def _adopt(self, p, amat):
         self._p = p
         m = p.contents
+        dim = m.dim
+        self.grid = bool(m.grid)
         self.dim, self.n, self.ne = dim, m.n, m.ne
-        self.N = tuple(m.N[:dim])
-        self.h = tuple(m.h[:dim])
-        self.Lside = tuple(m.L[:dim])
+        self.N = tuple(m.N[:dim]) if self.grid else None
+        self.h = tuple(m.h[:dim]) if self.grid else None
+        self.Lside = tuple(m.L[:dim]) if self.grid else None
         self.amat = np.array(amat, dtype=np.float64).reshape(3, 3)
         self.x = _arr(m.x, 3 * m.n, np.float64).reshape(m.n, 3)
         self.vol = _arr(m.vol, m.n, np.float64)
@@ -248,7 +281,7 @@ class Amg:
     @classmethod
     def for_state(cls, mesh, psi, **kw):
         """Hierarchy of H = K-hat + 2 D |psi|^2 on a grid mesh (red-black level 0)."""
-        return cls(mesh.hmat(psi), grid_N=mesh.N, **kw)
+        return cls(mesh.hmat(psi), grid_N=mesh.N if mesh.grid else None, **kw)
 
     def __del__(self):
         if getattr(self, "_p", None) is not None and _lib is not None:

@@ -215,8 +215,8 @@ int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixe
         orc_amg *amg = NULL;
         if (use_amg) {
             orc_hmat_values(m, psi, hv);
-            int grid_N_dim = m->dim;
-            rc = orc_amg_build(n, m->rp, m->ci, hv, grid_N_dim, m->N, max_coarse, 16, &amg);
+            /* level 0 of a tensor grid is coloured red-black, of a simplicial mesh greedily */
+            rc = orc_amg_build(n, m->rp, m->ci, hv, m->grid ? m->dim : 0, m->N, max_coarse, 16, &amg);
             if (rc != ORC_OK) break;
         }
         for (int64_t i = 0; i < n; ++i) b[i] = -r[i];

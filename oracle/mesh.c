@@ -6,7 +6,12 @@
  *  - Sec. 3, Voronoi regions V_j and mass lumping F_2 ~ sum |V_j| (...): vol.
  *  - Corollary on simplex edge coefficients and the Remark giving
  *    alpha = 1/2 cot(theta) for triangles; alpha_jk is summed over all
- *    simplices adjacent to the edge.  2D: computed triangle by triangle.
+ *    simplices adjacent to the edge.  2D grids: the Remark's cotangent,
+ *    triangle by triangle; simplicial meshes: the Corollary's system
+ *    M alpha = b per triangle (a second route to the same numbers), and the
+ *    control volume of a node as the sum of its shares
+ *    1/4 alpha_e |e|^2 over the triangle's two edges at it (the Voronoi
+ *    region's part of a triangle that holds its circumcentre).
  *    3D (cube grid, degenerate Delaunay): alpha = |dual Voronoi facet| / |e|.
  *  - Link variable U_jk = exp(-i int_{x_k}^{x_j} e_jk . A(w) dw), integral taken
  *    along the straight edge; evaluated here by 3-point Gauss-Legendre, which is
@@ -117,6 +122,72 @@ static int64_t edge_slot(const orc_mesh *m, int64_t lo, int64_t hi)
 static int mesh_build(int dim, const int64_t *N, const double *L, const double *amat, const double *dip,
                       orc_mesh **out);
 
+/* edge list -> edge arrays, link variables and K-hat in CSR (shared by the
+   grid and simplicial builders; the caller frees E) */
+static void finish_mesh(orc_mesh *m, const edge_rec *E, int64_t ne, const double *amat, const double *dip)
+{
+    const int64_t n = m->n;
+    m->ne = ne;
+    m->ej = malloc((size_t)ne * sizeof(int64_t));
+    m->ek = malloc((size_t)ne * sizeof(int64_t));
+    m->alpha = malloc((size_t)ne * sizeof(double));
+    m->U = malloc((size_t)ne * sizeof(cplx));
+    for (int64_t q = 0; q < ne; ++q) {
+        m->ej[q] = E[q].j;
+        m->ek[q] = E[q].k;
+        m->alpha[q] = E[q].alpha;
+        double phi = dip ? edge_integral_dipole(dip, &m->x[3 * E[q].k], &m->x[3 * E[q].j])
+                         : edge_integral(amat, &m->x[3 * E[q].k], &m->x[3 * E[q].j]);
+        m->U[q] = cexp(-I * phi);
+    }
+
+    /* K-hat in CSR.  Row i: diagonal sum of alpha over incident edges; for the
+       edge (j,k): K(j,k) = -alpha U_jk, K(k,j) = -alpha conj(U_jk). */
+    int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t q = 0; q < ne; ++q) { cnt[m->ej[q]]++; cnt[m->ek[q]]++; }
+    m->rp = malloc((size_t)(n + 1) * sizeof(int64_t));
+    m->rp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) m->rp[i + 1] = m->rp[i] + cnt[i] + 1;
+    int64_t nnz = m->rp[n];
+    m->ci = malloc((size_t)nnz * sizeof(int64_t));
+    m->kv = malloc((size_t)nnz * sizeof(cplx));
+    int64_t *fill = calloc((size_t)n, sizeof(int64_t));
+    double *diag = calloc((size_t)n, sizeof(double));
+    /* write (column, value) pairs, then sort each row by column */
+    typedef struct { int64_t c; cplx v; } ent;
+    ent *tmp = malloc((size_t)nnz * sizeof(ent));
+    for (int64_t q = 0; q < ne; ++q) {
+        int64_t j = m->ej[q], k = m->ek[q];
+        double al = m->alpha[q];
+        tmp[m->rp[j] + fill[j]].c = k;
+        tmp[m->rp[j] + fill[j]].v = -al * m->U[q];
+        fill[j]++;
+        tmp[m->rp[k] + fill[k]].c = j;
+        tmp[m->rp[k] + fill[k]].v = -al * conj(m->U[q]);
+        fill[k]++;
+        diag[j] += al;
+        diag[k] += al;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        tmp[m->rp[i] + fill[i]].c = i;
+        tmp[m->rp[i] + fill[i]].v = diag[i];
+        /* insertion sort on column */
+        for (int64_t p = m->rp[i] + 1; p < m->rp[i + 1]; ++p) {
+            ent e = tmp[p];
+            int64_t q = p - 1;
+            while (q >= m->rp[i] && tmp[q].c > e.c) { tmp[q + 1] = tmp[q]; --q; }
+            tmp[q + 1] = e;
+        }
+    }
+    for (int64_t p = 0; p < nnz; ++p) { m->ci[p] = tmp[p].c; m->kv[p] = tmp[p].v; }
+    free(tmp);
+    free(fill);
+    free(diag);
+    free(cnt);
+}
+
+
+
 int orc_mesh_build(int dim, const int64_t *N, const double *L, const double *amat,
                    orc_mesh **out)
 {
@@ -137,6 +208,7 @@ static int mesh_build(int dim, const int64_t *N, const double *L, const double *
     if (dim != 2 && dim != 3) return ORC_ERR_ARG;
     orc_mesh *m = calloc(1, sizeof(*m));
     m->dim = dim;
+    m->grid = 1;
     m->n = 1;
     for (int a = 0; a < 3; ++a) { m->N[a] = 1; m->L[a] = 0; m->h[a] = 0; }
     for (int a = 0; a < dim; ++a) {
@@ -231,66 +303,135 @@ static int mesh_build(int dim, const int64_t *N, const double *L, const double *
         }
     }
 
-    m->ne = ne;
-    m->ej = malloc((size_t)ne * sizeof(int64_t));
-    m->ek = malloc((size_t)ne * sizeof(int64_t));
-    m->alpha = malloc((size_t)ne * sizeof(double));
-    m->U = malloc((size_t)ne * sizeof(cplx));
-    for (int64_t q = 0; q < ne; ++q) {
-        m->ej[q] = E[q].j;
-        m->ek[q] = E[q].k;
-        m->alpha[q] = E[q].alpha;
-        double phi = dip ? edge_integral_dipole(dip, &m->x[3 * E[q].k], &m->x[3 * E[q].j])
-                         : edge_integral(amat, &m->x[3 * E[q].k], &m->x[3 * E[q].j]);
-        m->U[q] = cexp(-I * phi);
-    }
+    finish_mesh(m, E, ne, amat, dip);
     free(E);
-
-    /* K-hat in CSR.  Row i: diagonal sum of alpha over incident edges; for the
-       edge (j,k): K(j,k) = -alpha U_jk, K(k,j) = -alpha conj(U_jk). */
-    int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
-    for (int64_t q = 0; q < ne; ++q) { cnt[m->ej[q]]++; cnt[m->ek[q]]++; }
-    m->rp = malloc((size_t)(n + 1) * sizeof(int64_t));
-    m->rp[0] = 0;
-    for (int64_t i = 0; i < n; ++i) m->rp[i + 1] = m->rp[i] + cnt[i] + 1;
-    int64_t nnz = m->rp[n];
-    m->ci = malloc((size_t)nnz * sizeof(int64_t));
-    m->kv = malloc((size_t)nnz * sizeof(cplx));
-    int64_t *fill = calloc((size_t)n, sizeof(int64_t));
-    double *diag = calloc((size_t)n, sizeof(double));
-    /* write (column, value) pairs, then sort each row by column */
-    typedef struct { int64_t c; cplx v; } ent;
-    ent *tmp = malloc((size_t)nnz * sizeof(ent));
-    for (int64_t q = 0; q < ne; ++q) {
-        int64_t j = m->ej[q], k = m->ek[q];
-        double al = m->alpha[q];
-        tmp[m->rp[j] + fill[j]].c = k;
-        tmp[m->rp[j] + fill[j]].v = -al * m->U[q];
-        fill[j]++;
-        tmp[m->rp[k] + fill[k]].c = j;
-        tmp[m->rp[k] + fill[k]].v = -al * conj(m->U[q]);
-        fill[k]++;
-        diag[j] += al;
-        diag[k] += al;
-    }
-    for (int64_t i = 0; i < n; ++i) {
-        tmp[m->rp[i] + fill[i]].c = i;
-        tmp[m->rp[i] + fill[i]].v = diag[i];
-        /* insertion sort on column */
-        for (int64_t p = m->rp[i] + 1; p < m->rp[i + 1]; ++p) {
-            ent e = tmp[p];
-            int64_t q = p - 1;
-            while (q >= m->rp[i] && tmp[q].c > e.c) { tmp[q + 1] = tmp[q]; --q; }
-            tmp[q + 1] = e;
-        }
-    }
-    for (int64_t p = 0; p < nnz; ++p) { m->ci[p] = tmp[p].c; m->kv[p] = tmp[p].v; }
-    free(tmp);
-    free(fill);
-    free(diag);
-    free(cnt);
     *out = m;
     return ORC_OK;
+}
+
+/* ---------------------------------------------------------- simplicial --- */
+/* M a = b for 3 x 3, Gaussian elimination with partial pivoting; 0 if singular */
+static int solve3(double M[3][3], double b[3], double a[3])
+{
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
+        if (!(fabs(M[piv][c]) > 0.0)) return 0;
+        for (int k = 0; k < 3; ++k) { double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t; }
+        double t = b[c]; b[c] = b[piv]; b[piv] = t;
+        for (int r = c + 1; r < 3; ++r) {
+            double f = M[r][c] / M[c][c];
+            for (int k = c; k < 3; ++k) M[r][k] -= f * M[c][k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int c = 2; c >= 0; --c) {
+        double s = b[c];
+        for (int k = c + 1; k < 3; ++k) s -= M[c][k] * a[k];
+        a[c] = s / M[c][c];
+    }
+    return 1;
+}
+
+static int cmp_edge(const void *x, const void *y)
+{
+    const edge_rec *a = x, *b = y;
+    if (a->j != b->j) return a->j < b->j ? -1 : 1;
+    if (a->k != b->k) return a->k < b->k ? -1 : 1;
+    return 0;
+}
+
+/* index of the edge (hi, lo) in the sorted list */
+static int64_t find_edge(const edge_rec *E, int64_t ne, int64_t hi, int64_t lo)
+{
+    int64_t a = 0, b = ne - 1;
+    while (a <= b) {
+        int64_t c = (a + b) / 2;
+        if (E[c].j == hi && E[c].k == lo) return c;
+        if (E[c].j < hi || (E[c].j == hi && E[c].k < lo)) a = c + 1;
+        else b = c - 1;
+    }
+    return -1;
+}
+
+static int tri_build(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, const double *amat,
+                     const double *dip, orc_mesh **out)
+{
+    if (n < 3 || ntri < 1) return ORC_ERR_ARG;
+    for (int64_t t = 0; t < 3 * ntri; ++t)
+        if (tri[t] < 0 || tri[t] >= n) return ORC_ERR_ARG;
+    orc_mesh *m = calloc(1, sizeof(*m));
+    m->dim = 2;
+    m->grid = 0;
+    m->n = n;
+    m->N[0] = n;
+    m->N[1] = m->N[2] = 1;
+    for (int a = 0; a < 9; ++a) m->amat[a] = amat[a];
+    m->x = calloc((size_t)n * 3, sizeof(double));
+    for (int64_t i = 0; i < n; ++i) { m->x[3 * i] = xy[2 * i]; m->x[3 * i + 1] = xy[2 * i + 1]; }
+    m->vol = calloc((size_t)n, sizeof(double));
+    /* the distinct edges, (j, k) with j > k, in ascending order */
+    edge_rec *E = malloc((size_t)(3 * ntri) * sizeof(edge_rec));
+    for (int64_t t = 0; t < ntri; ++t)
+        for (int e = 0; e < 3; ++e) {
+            int64_t a = tri[3 * t + e], b = tri[3 * t + (e + 1) % 3];
+            E[3 * t + e].j = a > b ? a : b;
+            E[3 * t + e].k = a > b ? b : a;
+            E[3 * t + e].alpha = 0.0;
+        }
+    qsort(E, (size_t)(3 * ntri), sizeof(edge_rec), cmp_edge);
+    int64_t ne = 0;
+    for (int64_t q = 0; q < 3 * ntri; ++q)
+        if (ne == 0 || cmp_edge(&E[ne - 1], &E[q]) != 0) E[ne++] = E[q];
+    /* per triangle: the Corollary's system for its three edge coefficients,
+       then each vertex's share of the triangle */
+    for (int64_t t = 0; t < ntri; ++t) {
+        const int64_t *p = &tri[3 * t];
+        double e[3][2];
+        for (int i = 0; i < 3; ++i) {
+            const double *u = &m->x[3 * p[i]], *v = &m->x[3 * p[(i + 1) % 3]];
+            e[i][0] = v[0] - u[0];
+            e[i][1] = v[1] - u[1];
+        }
+        const double area = 0.5 * fabs(e[0][0] * (-e[2][1]) - e[0][1] * (-e[2][0]));
+        if (!(area > 0.0)) { free(E); orc_mesh_free(m); return ORC_ERR_ARG; }
+        double M[3][3], b[3], al[3], l2[3];
+        for (int i = 0; i < 3; ++i) {
+            l2[i] = e[i][0] * e[i][0] + e[i][1] * e[i][1];
+            b[i] = area * l2[i];
+            for (int j = 0; j < 3; ++j) {
+                double d = e[i][0] * e[j][0] + e[i][1] * e[j][1];
+                M[i][j] = d * d;
+            }
+        }
+        if (!solve3(M, b, al)) { free(E); orc_mesh_free(m); return ORC_ERR_ARG; }
+        for (int i = 0; i < 3; ++i) {
+            int64_t a = p[i], c = p[(i + 1) % 3];
+            int64_t q = find_edge(E, ne, a > c ? a : c, a > c ? c : a);
+            E[q].alpha += al[i];
+            m->vol[a] += 0.25 * al[i] * l2[i];
+            m->vol[c] += 0.25 * al[i] * l2[i];
+        }
+    }
+    finish_mesh(m, E, ne, amat, dip);
+    free(E);
+    *out = m;
+    return ORC_OK;
+}
+
+int orc_mesh_build_tri(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, const double *amat,
+                       orc_mesh **out)
+{
+    return tri_build(n, xy, ntri, tri, amat, NULL, out);
+}
+
+int orc_mesh_build_tri_dipole(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, double mu,
+                              const double *mm, const double *x0, orc_mesh **out)
+{
+    static const double zero[9] = {0};
+    double dip[7] = {mu, mm[0], mm[1], mm[2], x0[0], x0[1], x0[2]};
+    return tri_build(n, xy, ntri, tri, zero, dip, out);
 }
 
 void orc_mesh_free(orc_mesh *m)

@@ -42,6 +42,7 @@ typedef struct {
        rows ascending, columns ascending, diagonal included. */
     int64_t *rp, *ci;
     cplx *kv;
+    int grid;         /* 1: tensor grid (dim, N, L, h describe it); 0: simplicial mesh */
 } orc_mesh;
 
 int  orc_mesh_build(int dim, const int64_t *N, const double *L, const double *amat,
@@ -50,6 +51,17 @@ int  orc_mesh_build(int dim, const int64_t *N, const double *L, const double *am
  * (Sec. 4.1; 2D points are (x, y, 0)), link integrals in closed form */
 int  orc_mesh_build_dipole(int dim, const int64_t *N, const double *L, double mu, const double *m,
                            const double *x0, orc_mesh **out);
+/* 2D simplicial mesh: nodes xy (n x 2), triangles tri (ntri x 3, node
+ * indices).  Edge coefficients by the Corollary's system M alpha = b per
+ * triangle (M_ij = <e_i, e_j>^2, b_i = |T| |e_i|^2), summed over the
+ * triangles at each edge; |V_j| = sum over triangles T at j of
+ * 1/4 sum_{edges e of T at j} alpha_e^T |e|^2, the area of V_j within T when
+ * the triangle holds its circumcentre, and sum_j |V_j| = sum_T |T| for any
+ * triangulation.  Potential: A = amat r, or mu A_d with dip = (m, x0). */
+int  orc_mesh_build_tri(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, const double *amat,
+                        orc_mesh **out);
+int  orc_mesh_build_tri_dipole(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, double mu,
+                               const double *m, const double *x0, orc_mesh **out);
 void orc_mesh_free(orc_mesh *m);
 
 /* --------------------------------------------------------- operators --- */

@@ -1,0 +1,81 @@
+"""Simplicial meshes of the paper's two-dimensional test domains (Sec. 4.1):
+the triangle and the disc of circumradius 5 centred at the origin.
+
+Input generation only: node coordinates and triangles (node index triples),
+shared by the oracle and the GPU path; none of the method's arithmetic (edge
+coefficients, control volumes, link variables) is computed here.  Both
+meshes are built explicitly, without a Delaunay search, so they are exactly
+reproducible: the triangle as its regular subdivision into equilateral
+triangles, the disc as rings of nodes stitched in angle order.
+"""
+import numpy as np
+
+RADIUS = 5.0
+SQ3 = np.sqrt(3.0)
+
+
+def triangle(k):
+    """Omega_tri, the triangle with vertices (0, 5), (-5 sqrt3 / 2, -5 / 2),
+    (5 sqrt3 / 2, -5 / 2), split into k^2 equilateral triangles of side
+    5 sqrt3 / k.  Nodes (k + 1)(k + 2) / 2, row by row from the bottom side
+    (node (i, j) = B + i/k (C - B) + j/k (A - B)).  Returns (xy, tri)."""
+    if k < 1:
+        raise ValueError("k >= 1")
+    A = np.array([0.0, RADIUS])
+    B = np.array([-RADIUS * SQ3 / 2, -RADIUS / 2])
+    Cv = np.array([RADIUS * SQ3 / 2, -RADIUS / 2])
+    index = {}
+    pts = []
+    for j in range(k + 1):
+        for i in range(k + 1 - j):
+            index[(i, j)] = len(pts)
+            pts.append(B + (i / k) * (Cv - B) + (j / k) * (A - B))
+    tris = []
+    for j in range(k):
+        for i in range(k - j):
+            tris.append((index[(i, j)], index[(i + 1, j)], index[(i, j + 1)]))
+            if i + j <= k - 2:
+                tris.append((index[(i + 1, j)], index[(i + 1, j + 1)], index[(i, j + 1)]))
+    return np.array(pts, dtype=np.float64), np.array(tris, dtype=np.int64)
+
+
+def disc(k):
+    """Omega_circ, the disc of radius 5: the centre and k rings, ring r of 6r
+    nodes at radius 5 r / k equally spaced in angle from angle 0; ring 1 is
+    joined to the centre by six triangles, and each further ring to the one
+    inside it by a merge of the two rings in angle order (at equal angles the
+    inner ring advances first: every angle then stays below 90 degrees, so
+    the mesh is Delaunay with every circumcentre inside its triangle).
+    Nodes 1 + 3k(k + 1), triangles 6k^2.  Returns (xy, tri)."""
+    if k < 1:
+        raise ValueError("k >= 1")
+    pts = [(0.0, 0.0)]
+    start = [0]
+    for r in range(1, k + 1):
+        start.append(len(pts))
+        for t in range(6 * r):
+            th = 2.0 * np.pi * t / (6 * r)
+            pts.append((RADIUS * r / k * np.cos(th), RADIUS * r / k * np.sin(th)))
+    tris = [(0, start[1] + t, start[1] + (t + 1) % 6) for t in range(6)]
+    for r in range(2, k + 1):
+        ni, no = 6 * (r - 1), 6 * r
+        a = b = 0  # steps taken along the inner / outer ring
+        while a < ni or b < no:
+            inner, outer = start[r - 1] + a % ni, start[r] + b % no
+            # compare the angles of the next node on each ring: (a+1)/ni vs (b+1)/no
+            if b < no and (a >= ni or (b + 1) * ni < (a + 1) * no):
+                tris.append((inner, outer, start[r] + (b + 1) % no))
+                b += 1
+            else:
+                tris.append((inner, outer, start[r - 1] + (a + 1) % ni))
+                a += 1
+    return np.array(pts, dtype=np.float64), np.array(tris, dtype=np.int64)
+
+
+def domain(name, k):
+    """(xy, tri) of "tri" or "circ" at refinement k."""
+    if name == "tri":
+        return triangle(k)
+    if name == "circ":
+        return disc(k)
+    raise ValueError(f"unknown domain {name!r}")
