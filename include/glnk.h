@@ -102,6 +102,41 @@ typedef struct {
  * OUT_OF_MEMORY, HIP. */
 gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mesh **out);
 
+/* 2D simplicial mesh given by its nodes and triangles (Sec. 3: a Delaunay
+ * triangulation dual to the Voronoi tessellation of the nodes; the paper's
+ * test domains of Sec. 4.1 beyond the square, e.g. the triangle and the
+ * disc).  On the device: alpha_jk = sum over the triangles at edge jk of
+ * 1/2 cot of the opposite angle (the Remark on the Corollary's simplex
+ * coefficients); |V_j| = sum over the triangles T at j of
+ * 1/4 sum_{edges e of T at j} alpha_e^T |e|^2, the part of the Voronoi
+ * region V_j inside T when T holds its circumcentre (the shares of a
+ * triangle add up to its area for any triangulation); link variables of
+ * every edge from the exact line integral (linear potentials: the midpoint
+ * value; the dipole: closed form).  The fields potential, mu, b_dir,
+ * a_matrix, dipole_m and dipole_x0 mean what they mean in gl_grid_desc
+ * (2D points r = (x, y, 0)).  xy and triangles are host arrays read during
+ * the call and not kept.  Every node must lie in a triangle.  Meshes of this
+ * kind support the residual, the Jacobian, gl_precond_* (level 0 coloured
+ * like the coarse levels), gl_jacobian_solve, gl_newton_solve, batches and
+ * the continuation calls; not gl_mesh_export_links, the LDS-tiled level 0,
+ * or the U-Net.  Errors: INVALID_ARGUMENT (n_nodes < 3 or above 2^31 - 2,
+ * an index out of range, a degenerate triangle, an edge in more than two
+ * triangles, a node in no triangle), OUT_OF_MEMORY, HIP. */
+typedef struct {
+    int64_t n_nodes;
+    const double *xy;          /* host, n_nodes x 2 (x, y), row-major */
+    int64_t n_triangles;
+    const int64_t *triangles;  /* host, n_triangles x 3 node indices */
+    int potential;             /* 0, 1 or 2, as in gl_grid_desc */
+    double mu;
+    double b_dir[3];
+    double a_matrix[9];
+    double dipole_m[3];
+    double dipole_x0[3];       /* off every edge's line segment */
+} gl_simplicial_desc;
+
+gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream stream, gl_mesh **out);
+
 /* Replace mu (potential 0 or 2) and recompute the link variables: the
  * continuation parameter of Sec. 4 (numerical parameter continuation). */
 gl_status gl_mesh_set_field(gl_mesh *mesh, double mu, gl_stream stream);

@@ -193,6 +193,42 @@ __global__ void k_l0_values(GeomT<double> g, const int *rp, const LinkTab<double
     diag[i] = dg;
 }
 
+// Level 0 of a simplicial mesh: its adjacency with the diagonal inserted
+// (columns ascending), H_jj = K-hat_jj + 2 |V_j| |psi_j|^2, H_jk = -kw_jk
+__global__ void k_l0s_count(int n, const int *arp, int *cnt)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) cnt[i] = arp[i + 1] - arp[i] + 1;
+}
+
+__global__ void k_l0s_cols(int n, const int *arp, const int *aci, const int *rp, int *ci)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    int p = rp[i];
+    bool diag = false;
+    for (int q = arp[i]; q < arp[i + 1]; ++q) {
+        if (!diag && aci[q] > i) {
+            ci[p++] = i;
+            diag = true;
+        }
+        ci[p++] = aci[q];
+    }
+    if (!diag) ci[p] = i;
+}
+
+__global__ void k_l0s_values(GeomT<double> g, const int *rp, const int *ci, const double2 *__restrict__ psi,
+                             double2 *v, double *diag)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= g.n) return;
+    int q = g.rp[i];
+    const double dg = g.ks[i] + 2.0 * g.vol[i] * cabs2(psi[i]);
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        v[p] = ci[p] == i ? make_double2(dg, 0.0) : cscale(g.kw[q++], -1.0);
+    diag[i] = dg;
+}
+
 // --------------------------------------------------------- MIS-2 -----
 __global__ void k_fill_int(int *a, int n, int val)
 {
@@ -564,7 +600,9 @@ static void rho_estimate(gl_precond *pre, Level &L, hipStream_t s)
     double *nrm = pre->pwn.get();
     k_pw_start<<<nb, kBlock, 0, s>>>(n, x, slot);
     launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm, nullptr, s);
-    const bool l0 = &L == &pre->L[0];
+    // level 0 of a grid as the stencil, every other level (and level 0 of a
+    // simplicial mesh) through its CSR matrix
+    const bool l0 = &L == &pre->L[0] && !m->g.simplicial;
     const GeomT<double> g = geom_t<double>(m->g);
     // CSR levels: kPwLanes threads per row, at most one partial per level-0 block
     const int nbl = std::min(blocks_for((int64_t)n * kPwLanes), blocks_for(m->g.n));
@@ -1045,7 +1083,7 @@ static void colour_level(gl_precond *pre, int l, hipStream_t s)
     const int n = L.n, nb = blocks_for(n);
     L.color.alloc(n);
     const gl_mesh *m = pre->mesh;
-    if (l == 0) {
+    if (l == 0 && !m->g.simplicial) {
         if (m->g.dim == 2) k_parity_colour<2><<<nb, kBlock, 0, s>>>(m->g, L.color.get());
         else k_parity_colour<3><<<nb, kBlock, 0, s>>>(m->g, L.color.get());
         GLK_CHECK_LAUNCH();
@@ -1214,7 +1252,8 @@ static void transfer_patterns(gl_precond *pre, int l, hipStream_t s)
 
 static void alloc_values(gl_precond *pre)
 {
-    const int ns = 2 * geom_t<double>(pre->mesh->g).npair;  // level-0 split layout
+    const bool simp = pre->mesh->g.simplicial;
+    const int ns = simp ? 0 : 2 * geom_t<double>(pre->mesh->g).npair;  // level-0 split layout of a grid
     for (int l = 0; l < pre->nlev; ++l) {
         Level &L = pre->L[l];
         const int nv = l == 0 ? std::max(L.n, ns) : L.n;
@@ -1228,7 +1267,7 @@ static void alloc_values(gl_precond *pre)
         L.b32.alloc(nv);
         L.x32.alloc(nv);
         L.r32.alloc(nv);
-        if (l == 0) {
+        if (l == 0 && !simp) {
             L.hs64.alloc(ns);
             L.hs32.alloc(ns);
         }
@@ -1273,7 +1312,11 @@ static void permuted_copy(const Csr &M, const int *rowperm, const int *colmap, C
 // the colour-ordered copies the V-cycle works on
 static void build_apply_copies(gl_precond *pre, hipStream_t s)
 {
-    for (int l = 1; l < pre->nlev; ++l) {
+    // level 0 of a simplicial mesh is a CSR level like the coarse ones (when
+    // it is not the coarsest, which is applied as a dense inverse in node order)
+    const bool simp = pre->mesh->g.simplicial && pre->nlev > 1;
+    const int lfirst = simp ? 0 : 1;
+    for (int l = lfirst; l < pre->nlev; ++l) {
         Level &L = pre->L[l];
         L.perm.alloc(L.n);
         GLK_HIP(hipMemcpyAsync(L.perm.get(), L.cperm.get(), sizeof(int) * L.n, hipMemcpyDeviceToDevice, s));
@@ -1285,14 +1328,15 @@ static void build_apply_copies(gl_precond *pre, hipStream_t s)
     }
     for (int l = 0; l < pre->nlev; ++l) {
         Level &L = pre->L[l];
-        const int *rowp = l >= 1 ? L.perm.get() : nullptr;
-        const int *colp = l >= 1 ? L.iperm.get() : nullptr;
-        if (l >= 1) permuted_copy(L.A, rowp, colp, L.Aa, L.amap, s);
+        const bool generic = l >= lfirst;
+        const int *rowp = generic ? L.perm.get() : nullptr;
+        const int *colp = generic ? L.iperm.get() : nullptr;
+        if (generic) permuted_copy(L.A, rowp, colp, L.Aa, L.amap, s);
         if (l + 1 < pre->nlev) {
             Level &Nx = pre->L[l + 1];
             permuted_copy(L.P, rowp, Nx.iperm.get(), L.Pa, L.pmap, s);
             permuted_copy(L.R, Nx.perm.get(), colp, L.Ra, L.rmap, s);
-            if (l == 0) {
+            if (l == 0 && !generic) {
                 const GeomT<double> g = geom_t<double>(pre->mesh->g);
                 Csr &B = L.Rb;
                 B.n = L.Ra.n;
@@ -1322,7 +1366,7 @@ static void build_apply_copies(gl_precond *pre, hipStream_t s)
                 Q.v32.alloc(std::max(1, Q.nnz));
             }
         }
-        if (l >= 1) {
+        if (generic) {
             // padded colour blocks for the Gauss-Seidel sweeps
             std::vector<int> rp = to_host(L.Aa.rp.get(), (size_t)L.n + 1, s);
             L.ewidth.assign(L.ncolors, 0);
@@ -1360,11 +1404,14 @@ void precond_symbolic(gl_precond *pre, hipStream_t s)
     L0.A.n = L0.A.m = n0;
     {
         DevBuf<int> cnt(n0);
-        if (m->g.dim == 2) k_l0_count<2><<<nb0, kBlock, 0, s>>>(m->g, cnt.get());
+        if (m->g.simplicial) k_l0s_count<<<nb0, kBlock, 0, s>>>(n0, m->g.rp, cnt.get());
+        else if (m->g.dim == 2) k_l0_count<2><<<nb0, kBlock, 0, s>>>(m->g, cnt.get());
         else k_l0_count<3><<<nb0, kBlock, 0, s>>>(m->g, cnt.get());
         GLK_CHECK_LAUNCH();
         alloc_rowptr(L0.A, cnt.get(), s);
-        if (m->g.dim == 2) k_l0_cols<2><<<nb0, kBlock, 0, s>>>(m->g, L0.A.rp.get(), L0.A.ci.get());
+        if (m->g.simplicial)
+            k_l0s_cols<<<nb0, kBlock, 0, s>>>(n0, m->g.rp, m->g.ci, L0.A.rp.get(), L0.A.ci.get());
+        else if (m->g.dim == 2) k_l0_cols<2><<<nb0, kBlock, 0, s>>>(m->g, L0.A.rp.get(), L0.A.ci.get());
         else k_l0_cols<3><<<nb0, kBlock, 0, s>>>(m->g, L0.A.rp.get(), L0.A.ci.get());
         GLK_CHECK_LAUNCH();
     }
@@ -1400,7 +1447,11 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
     Level &L0 = pre->L[0];
     const int n0 = L0.n;
     const GeomT<double> g = geom_t<double>(m->g);
-    if (m->g.dim == 2)
+    const bool simp = m->g.simplicial;
+    if (simp)
+        k_l0s_values<<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), L0.A.ci.get(), psi, L0.A.v64.get(),
+                                                       L0.diag64.get());
+    else if (m->g.dim == 2)
         k_l0_values<2><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), link_tab<double>(m), psi, L0.A.v64.get(),
                                                          L0.diag64.get());
     else
@@ -1432,11 +1483,12 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
         k_diag<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Lc.A.rp.get(), Lc.A.ci.get(), Lc.A.v64.get(), Lc.diag64.get());
     // level 0 in single precision (its stencil diagonal; the CSR copy serves export only)
     k_to_f32r<<<blocks_for(n0), kBlock, 0, s>>>(n0, L0.diag64.get(), L0.diag32.get());
-    k_split_diag<<<blocks_for(g.npair), kBlock, 0, s>>>(g, L0.diag64.get(), L0.hs64.get(), L0.hs32.get());
+    if (!simp)
+        k_split_diag<<<blocks_for(g.npair), kBlock, 0, s>>>(g, L0.diag64.get(), L0.hs64.get(), L0.hs32.get());
     // colour-ordered copies for the V-cycle, FP64 and rounded to FP32
     for (int l = 0; l < pre->nlev; ++l) {
         Level &L = pre->L[l];
-        if (l >= 1) {
+        if (l >= 1 || (simp && last > 0)) {
             k_gather_c<<<blocks_for(L.Aa.nnz), kBlock, 0, s>>>(L.Aa.nnz, L.amap.get(), L.A.v64.get(),
                                                                L.Aa.v64.get(), L.Aa.v32.get());
             k_gather_r<<<blocks_for(L.n), kBlock, 0, s>>>(L.n, L.perm.get(), L.diag64.get(), L.dg64.get(),
@@ -1451,7 +1503,7 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
                                                                L.Pa.v64.get(), L.Pa.v32.get());
             k_gather_c<<<blocks_for(L.Ra.nnz), kBlock, 0, s>>>(L.Ra.nnz, L.rmap.get(), L.R.v64.get(),
                                                                L.Ra.v64.get(), L.Ra.v32.get());
-            if (l == 0) {
+            if (l == 0 && !simp) {
                 k_gather_c<<<blocks_for(L.Rb.nnz), kBlock, 0, s>>>(L.Rb.nnz, L.bmap.get(), L.R.v64.get(),
                                                                    L.Rb.v64.get(), L.Rb.v32.get());
                 k_gather_c<<<blocks_for(L.Pb.nnz), kBlock, 0, s>>>(L.Pb.nnz, L.pbmap.get(), L.P.v64.get(),

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -251,12 +252,24 @@ __device__ __forceinline__ void block_reduce_store(double part, RedSlot slot, do
 // e_a = h_a (interior) or h_a / 2 (boundary); the edge coefficient along axis
 // a at node i is alpha_a = |V_i| s_a / h_a^2, s_a = 2 on a boundary of axis a
 // (so alpha_a = prod_{b != a} e_b / h_a, the dual-facet area over the edge length).
+// A 2D simplicial mesh (simplicial = true) keeps its operator per edge
+// instead: the node adjacency in CSR (rp, ci: the other end of each edge at
+// a node, ascending), kw = alpha_jk U_jk for the entry (row j, column k), so
+// that K-hat_jk = -kw, the diagonal ks_j = K-hat_jj = sum of alpha at j, the
+// volumes |V_j|, and phi_jk, the link phase at mu = 1 (U_jk = exp(-i mu phi)).
+// Kernels templated on DIM take it as DIM == 0.
 struct Geom {
     int dim;
     int N[3];
     int n;
     double h[3];
     double inv_h2[3];
+    bool simplicial = false;
+    const int *rp = nullptr, *ci = nullptr;
+    const double2 *kw64 = nullptr;
+    const float2 *kw32 = nullptr;
+    const double *ks64 = nullptr, *vol64 = nullptr, *phi = nullptr;
+    const float *ks32 = nullptr, *vol32 = nullptr;
 };
 
 template <class T>
@@ -266,6 +279,11 @@ struct GeomT {
     int hr, npair;  // red-black pairs: ceil(N0 / 2) per x-row, hr * n / N0 in all
     T h[3];
     T inv_h2[3];
+    // simplicial meshes (DIM == 0)
+    const int *rp, *ci;
+    const C<T> *kw;
+    const T *ks, *vol;
+    const double *phi;
 };
 
 template <class T> inline GeomT<T> geom_t(const Geom &g)
@@ -279,7 +297,29 @@ template <class T> inline GeomT<T> geom_t(const Geom &g)
     r.n = g.n;
     r.hr = (g.N[0] + 1) / 2;
     r.npair = r.hr * (g.n / g.N[0]);
+    r.rp = g.rp;
+    r.ci = g.ci;
+    r.phi = g.phi;
+    if constexpr (std::is_same<T, double>::value) {
+        r.kw = g.kw64;
+        r.ks = g.ks64;
+        r.vol = g.vol64;
+    } else {
+        r.kw = g.kw32;
+        r.ks = g.ks32;
+        r.vol = g.vol32;
+    }
     return r;
+}
+
+// Calls f(std::integral_constant<int, K>) with the mesh kind: 0 for a
+// simplicial mesh, else its dimension (2 or 3).
+template <class F>
+inline void with_dim(const Geom &g, F &&f)
+{
+    if (g.simplicial) f(std::integral_constant<int, 0>{});
+    else if (g.dim == 2) f(std::integral_constant<int, 2>{});
+    else f(std::integral_constant<int, 3>{});
 }
 
 // Link variables of the linear potential A(r) = M r as factor tables.  The
@@ -322,6 +362,15 @@ struct gl_mesh {
     glk::DevBuf<float2> F32;
     int foff[3][3] = {};
     bool per_edge = false;           // links stored per edge (non-linear potential)
+    // simplicial meshes: topology (device), per-entry and per-node arrays
+    glk::DevBuf<int> s_rp, s_ci;     // node adjacency (CSR without the diagonal)
+    glk::DevBuf<int> s_opp;          // per entry: third vertices of the (up to 2) triangles at the edge, -1 if none
+    glk::DevBuf<int> s_trp, s_tv;    // per node: (other vertex a, other vertex b) of each triangle at the node
+    glk::DevBuf<double2> s_xy;       // node coordinates
+    glk::DevBuf<double> s_alpha, s_phi, s_ks64, s_vol64;
+    glk::DevBuf<float> s_ks32, s_vol32;
+    glk::DevBuf<double2> s_kw64;
+    glk::DevBuf<float2> s_kw32;
     // reductions
     glk::DevBuf<double> partials;
     glk::DevBuf<double> dscal;       // device scalar results

@@ -793,8 +793,8 @@ gl_status minres_solve(const gl_mesh *m, const double2 *psi, const gl_precond *p
 {
     GLK_HIP(hipEventRecord(m->ev_in, s));
     GLK_HIP(hipStreamWaitEvent(m->ws, m->ev_in, 0));
-    gl_status st = m->g.dim == 2 ? minres_run<2>(m, psi, pre, b, x, o, info, m->ws)
-                                 : minres_run<3>(m, psi, pre, b, x, o, info, m->ws);
+    gl_status st = GL_OK;
+    with_dim(m->g, [&](auto D) { st = minres_run<decltype(D)::value>(m, psi, pre, b, x, o, info, m->ws); });
     GLK_HIP(hipEventRecord(m->ev_out, m->ws));
     GLK_HIP(hipStreamWaitEvent(s, m->ev_out, 0));
     return st;
@@ -1090,13 +1090,10 @@ static void record_iterations(gl_batch *B, double2 *const *psi, int i, bool refi
 {
     Launch L{nullptr, &out};
     Ksolve k = batch_ksolve(B, psi, i, refine, use_pre);
-    if (B->meshes[i]->g.dim == 2) {
-        enqueue_iteration<2>(k, L);
-        enqueue_iteration<2>(k, L);
-    } else {
-        enqueue_iteration<3>(k, L);
-        enqueue_iteration<3>(k, L);
-    }
+    with_dim(B->meshes[i]->g, [&](auto D) {
+        enqueue_iteration<decltype(D)::value>(k, L);
+        enqueue_iteration<decltype(D)::value>(k, L);
+    });
 }
 
 static GroupGraph build_group_graph(gl_batch *B, BatchGroup &G, const std::vector<int> &members,
@@ -1248,8 +1245,7 @@ static void batch_init(gl_batch *B, double2 *const *psi, const std::vector<int> 
     batch_run_direct(B, members, [&](int i, std::vector<Step> &r) {
         Launch L{nullptr, &r};
         Ksolve k = batch_ksolve(B, psi, i, refine, use_pre);
-        if (B->meshes[i]->g.dim == 2) ksolve_init<2>(k, rtol, max_iter, L);
-        else ksolve_init<3>(k, rtol, max_iter, L);
+        with_dim(B->meshes[i]->g, [&](auto D) { ksolve_init<decltype(D)::value>(k, rtol, max_iter, L); });
     });
 }
 
@@ -1315,14 +1311,10 @@ static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int>
             double2 *W = m->work.get();
             k_add<<<blocks_for(n), kBlock, 0, B->s>>>(n, W + 8 * (size_t)n, W + 9 * (size_t)n);
             const GeomT<double> g = geom_t<double>(m->g);
-            if (m->g.dim == 2)
-                k_residual_vec<2><<<blocks_for(n), kBlock, 0, B->s>>>(g, psi[i], W + 8 * (size_t)n,
-                                                                       W + 7 * (size_t)n, link_tab<double>(m),
-                                                                       W + 10 * (size_t)n);
-            else
-                k_residual_vec<3><<<blocks_for(n), kBlock, 0, B->s>>>(g, psi[i], W + 8 * (size_t)n,
-                                                                       W + 7 * (size_t)n, link_tab<double>(m),
-                                                                       W + 10 * (size_t)n);
+            with_dim(m->g, [&](auto D) {
+                k_residual_vec<decltype(D)::value><<<blocks_for(n), kBlock, 0, B->s>>>(
+                    g, psi[i], W + 8 * (size_t)n, W + 7 * (size_t)n, link_tab<double>(m), W + 10 * (size_t)n);
+            });
             GLK_CHECK_LAUNCH();
         }
         std::vector<int> keep;

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 
+#include <algorithm>
 #include "amg.h"
 #include "stencil.h"
 
@@ -132,6 +133,119 @@ __device__ __forceinline__ double dipole_phase(const Dipole &D, const double xk[
     return num / d2 * (s1 / r1 - s0 / r0);
 }
 
+// The same integral along the edge from xk to xj in any direction (unit t,
+// length L): m . (a x t) [s / (d^2 sqrt(d^2 + s^2))] between s0 = a . t and
+// s0 + L, d^2 = |a x t|^2, with the cancellation-free form when s0 and s1
+// have the same sign.  D.mu is not applied.
+__device__ __forceinline__ double dipole_phase_edge(const Dipole &D, const double xk[3], const double xj[3])
+{
+    double a[3], t[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a[c] = xk[c] - D.x0[c];
+        t[c] = xj[c] - xk[c];
+    }
+    const double L = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) t[c] /= L;
+    const double axt[3] = {a[1] * t[2] - a[2] * t[1], a[2] * t[0] - a[0] * t[2], a[0] * t[1] - a[1] * t[0]};
+    const double num = D.m[0] * axt[0] + D.m[1] * axt[1] + D.m[2] * axt[2];
+    const double d2 = axt[0] * axt[0] + axt[1] * axt[1] + axt[2] * axt[2];
+    if (!(d2 > 0.0)) return 0.0;
+    const double s0 = a[0] * t[0] + a[1] * t[1] + a[2] * t[2], s1 = s0 + L;
+    const double r0 = sqrt(d2 + s0 * s0), r1 = sqrt(d2 + s1 * s1);
+    if (s0 * s1 > 0.0) return num * (s1 - s0) * (s1 + s0) / (r0 * r1 * (s1 * r0 + s0 * r1));
+    return num / d2 * (s1 / r1 - s0 / r0);
+}
+
+// ------------------------------------------------- simplicial meshes ---
+// 1/2 cot of the angle at o between the edges o -> p and o -> q
+__device__ __forceinline__ double half_cot_at(double2 o, double2 p, double2 q)
+{
+    const double ux = p.x - o.x, uy = p.y - o.y, vx = q.x - o.x, vy = q.y - o.y;
+    return 0.5 * (ux * vx + uy * vy) / fabs(ux * vy - uy * vx);
+}
+
+// Per adjacency entry (row j, column k): alpha_jk, the sum over the (one or
+// two) triangles at the edge of 1/2 cot of the opposite angle (the Remark's
+// form of the Corollary), and phi_jk = int_{x_k}^{x_j} A_1 . dl, the link
+// phase at unit field strength (linear A_1 = M r: exact at the midpoint;
+// the dipole: dipole_phase_edge).
+__global__ __launch_bounds__(kBlock) void k_simp_edges(int n, const int *__restrict__ rp,
+                                                       const int *__restrict__ ci, const int *__restrict__ opp,
+                                                       const double2 *__restrict__ xy, int dipole, Potential pot,
+                                                       Dipole D, double *__restrict__ alpha,
+                                                       double *__restrict__ phi)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const double2 xj = xy[j];
+    for (int p = rp[j]; p < rp[j + 1]; ++p) {
+        const int k = ci[p];
+        const double2 xk = xy[k];
+        double al = 0.0;
+        for (int t = 0; t < 2; ++t) {
+            const int o = opp[2 * p + t];
+            if (o >= 0) al += half_cot_at(xy[o], xj, xk);
+        }
+        alpha[p] = al;
+        double ph;
+        if (dipole) {
+            const double a3[3] = {xk.x, xk.y, 0.0}, b3[3] = {xj.x, xj.y, 0.0};
+            ph = dipole_phase_edge(D, a3, b3);
+        } else {
+            const double mid[3] = {0.5 * (xj.x + xk.x), 0.5 * (xj.y + xk.y), 0.0};
+            const double e[3] = {xj.x - xk.x, xj.y - xk.y, 0.0};
+            ph = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                ph += e[a] * (pot.m[3 * a] * mid[0] + pot.m[3 * a + 1] * mid[1] + pot.m[3 * a + 2] * mid[2]);
+        }
+        phi[p] = ph;
+    }
+}
+
+// Per node: K-hat_jj = sum of alpha over its edges, and |V_j| = sum over its
+// triangles (other vertices a, b) of 1/4 (alpha_ja^T |x_j - x_a|^2 +
+// alpha_jb^T |x_j - x_b|^2), alpha^T the triangle's own 1/2 cot terms.
+__global__ __launch_bounds__(kBlock) void k_simp_nodes(int n, const int *__restrict__ rp,
+                                                       const double *__restrict__ alpha, const int *__restrict__ trp,
+                                                       const int *__restrict__ tv, const double2 *__restrict__ xy,
+                                                       double *ks64, float *ks32, double *vol64, float *vol32)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    double ks = 0.0;
+    for (int p = rp[j]; p < rp[j + 1]; ++p) ks += alpha[p];
+    const double2 xj = xy[j];
+    double v = 0.0;
+    for (int q = trp[j]; q < trp[j + 1]; ++q) {
+        const double2 xa = xy[tv[2 * q]], xb = xy[tv[2 * q + 1]];
+        const double la = (xj.x - xa.x) * (xj.x - xa.x) + (xj.y - xa.y) * (xj.y - xa.y);
+        const double lb = (xj.x - xb.x) * (xj.x - xb.x) + (xj.y - xb.y) * (xj.y - xb.y);
+        v += 0.25 * (half_cot_at(xb, xj, xa) * la + half_cot_at(xa, xj, xb) * lb);
+    }
+    ks64[j] = ks;
+    ks32[j] = (float)ks;
+    vol64[j] = v;
+    vol32[j] = (float)v;
+}
+
+// kw_jk = alpha_jk U_jk, U_jk = exp(-i mu phi_jk)
+__global__ __launch_bounds__(kBlock) void k_simp_links(int nnz, double mu, const double *__restrict__ alpha,
+                                                       const double *__restrict__ phi, double2 *__restrict__ kw64,
+                                                       float2 *__restrict__ kw32)
+{
+    const int p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= nnz) return;
+    double sn, cs;
+    sincos(mu * phi[p], &sn, &cs);
+    const double a = alpha[p];
+    const double2 w = make_double2(a * cs, -a * sn);
+    kw64[p] = w;
+    kw32[p] = make_float2((float)w.x, (float)w.y);
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_link_dipole(Geom g, Dipole D, double2 *__restrict__ F64,
                                                         float2 *__restrict__ F32)
@@ -187,6 +301,15 @@ static void compute_amat(const gl_grid_desc &d, double mu, double out[9])
 
 static void launch_links(gl_mesh *m, hipStream_t s)
 {
+    if (m->g.simplicial) {
+        // the matrix potential carries its strength in phi
+        const double mu = m->desc.potential == 1 ? 1.0 : m->desc.mu;
+        const int nnz = m->g.rp ? (int)m->s_ci.count : 0;
+        k_simp_links<<<blocks_for(nnz), kBlock, 0, s>>>(nnz, mu, m->s_alpha.get(), m->s_phi.get(), m->s_kw64.get(),
+                                                       m->s_kw32.get());
+        GLK_CHECK_LAUNCH();
+        return;
+    }
     if (m->per_edge) {
         Dipole D;
         D.mu = m->desc.mu;
@@ -246,10 +369,9 @@ void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, dou
     const double bytes = 16.0 * m->g.n * (out ? 2 : 1);
     const LinkTab<double> U = link_tab<double>(m);
     prof_launch(PROF_GL, bytes, s, [&] {
-        if (m->g.dim == 2)
-            k_gl_residual<2><<<nb, kBlock, 0, s>>>(g, psi, U, out, red_slot(m, 0));
-        else
-            k_gl_residual<3><<<nb, kBlock, 0, s>>>(g, psi, U, out, red_slot(m, 0));
+        with_dim(m->g, [&](auto D) {
+            k_gl_residual<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, psi, U, out, red_slot(m, 0));
+        });
     });
     GLK_CHECK_LAUNCH();
     launch_finalize(red_slot(m, 0).partials, nb, FIN_STORE, nullptr, dresult, nullptr, s);
@@ -312,10 +434,9 @@ void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, 
 {
     const int nb = blocks_for(m->g.n);
     const GeomT<double> g = geom_t<double>(m->g);
-    if (m->g.dim == 2)
-        k_jacobian<2><<<nb, kBlock, 0, s>>>(g, psi, phi, link_tab<double>(m), out);
-    else
-        k_jacobian<3><<<nb, kBlock, 0, s>>>(g, psi, phi, link_tab<double>(m), out);
+    with_dim(m->g, [&](auto D) {
+        k_jacobian<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, psi, phi, link_tab<double>(m), out);
+    });
     GLK_CHECK_LAUNCH();
 }
 
@@ -358,8 +479,9 @@ void secant_enqueue(const gl_mesh *m, const double2 *psi, const double2 *prev, d
 {
     const int nb = blocks_for(m->g.n);
     const GeomT<double> g = geom_t<double>(m->g);
-    if (m->g.dim == 2) k_cdot<2><<<nb, kBlock, 0, s>>>(g, prev, psi, red_slot(m, 2), red_slot(m, 3));
-    else k_cdot<3><<<nb, kBlock, 0, s>>>(g, prev, psi, red_slot(m, 2), red_slot(m, 3));
+    with_dim(m->g, [&](auto D) {
+        k_cdot<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, prev, psi, red_slot(m, 2), red_slot(m, 3));
+    });
     GLK_CHECK_LAUNCH();
     double *ip = m->dscal.get() + 2;
     launch_finalize(red_slot(m, 2).partials, nb, FIN_STORE, nullptr, ip, nullptr, s);
@@ -401,6 +523,18 @@ __global__ __launch_bounds__(kBlock) void k_gl_dmu(GeomT<double> g, const double
 {
     const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (i >= g.n) return;
+    if constexpr (DIM == 0) {
+        // dK-hat_jk / dmu = -alpha dU_jk/dmu = i phi_jk kw_jk (the diagonal does not depend on mu)
+        double2 acc = make_double2(0.0, 0.0);
+        for (int p = g.rp[i]; p < g.rp[i + 1]; ++p) {
+            const double2 w = cmul(g.kw[p], psi[g.ci[p]]);
+            const double ph = g.phi[p];
+            acc.x -= ph * w.y;
+            acc.y += ph * w.x;
+        }
+        out[i] = cscale(acc, 1.0 / g.vol[i]);
+        return;
+    }
     int c[3];
     node_coords<DIM>(g.N, i, c);
     double s[3];
@@ -455,8 +589,9 @@ __global__ __launch_bounds__(kBlock) void k_scale_volume(GeomT<double> g, const 
 void scale_by_volume(const gl_mesh *m, const double2 *x, double2 *y, hipStream_t s)
 {
     const GeomT<double> g = geom_t<double>(m->g);
-    if (m->g.dim == 2) k_scale_volume<2><<<blocks_for(m->g.n), kBlock, 0, s>>>(g, x, y);
-    else k_scale_volume<3><<<blocks_for(m->g.n), kBlock, 0, s>>>(g, x, y);
+    with_dim(m->g, [&](auto D) {
+        k_scale_volume<decltype(D)::value><<<blocks_for(m->g.n), kBlock, 0, s>>>(g, x, y);
+    });
     GLK_CHECK_LAUNCH();
 }
 
@@ -589,6 +724,184 @@ gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mes
     });
 }
 
+gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream stream, gl_mesh **out)
+{
+    return guarded([&] {
+        if (!desc || !out || !desc->xy || !desc->triangles)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: NULL argument");
+        *out = nullptr;
+        const int64_t n = desc->n_nodes, nt = desc->n_triangles;
+        if (n < 3 || n > ((int64_t)1 << 31) - 2 || nt < 1 || nt > ((int64_t)1 << 29))
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: node or triangle count out of range");
+        if (desc->potential < 0 || desc->potential > 2)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: potential must be 0, 1 or 2");
+        if (!std::isfinite(desc->mu)) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: mu");
+        if (desc->potential == 0) {
+            const double *b = desc->b_dir;
+            if (!(b[0] * b[0] + b[1] * b[1] + b[2] * b[2] > 0.0))
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: b_dir is zero");
+        }
+        if (desc->potential == 2) {
+            const double *mm = desc->dipole_m, *x0 = desc->dipole_x0;
+            if (!(mm[0] * mm[0] + mm[1] * mm[1] + mm[2] * mm[2] > 0.0) || !std::isfinite(x0[0] + x0[1] + x0[2]) ||
+                !std::isfinite(mm[0] + mm[1] + mm[2]))
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: dipole moment or position");
+        }
+        const double *xy = desc->xy;
+        const int64_t *tri = desc->triangles;
+        for (int64_t i = 0; i < 2 * n; ++i)
+            if (!std::isfinite(xy[i])) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: coordinates");
+        // topology on the host: directed edge entries (row, column, third vertex)
+        struct Ent {
+            int r, c, o;
+        };
+        std::vector<Ent> ents;
+        ents.reserve((size_t)6 * nt);
+        std::vector<int> tdeg((size_t)n, 0);
+        for (int64_t t = 0; t < nt; ++t) {
+            int v[3];
+            for (int e = 0; e < 3; ++e) {
+                const int64_t x = tri[3 * t + e];
+                if (x < 0 || x >= n) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: node index out of range");
+                v[e] = (int)x;
+            }
+            const double ux = xy[2 * v[1]] - xy[2 * v[0]], uy = xy[2 * v[1] + 1] - xy[2 * v[0] + 1];
+            const double wx = xy[2 * v[2]] - xy[2 * v[0]], wy = xy[2 * v[2] + 1] - xy[2 * v[0] + 1];
+            if (!(std::fabs(ux * wy - uy * wx) > 0.0))
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: degenerate triangle");
+            for (int e = 0; e < 3; ++e) {
+                const int a = v[e], b = v[(e + 1) % 3], o = v[(e + 2) % 3];
+                ents.push_back({a, b, o});
+                ents.push_back({b, a, o});
+                ++tdeg[(size_t)v[e]];
+            }
+        }
+        std::sort(ents.begin(), ents.end(), [](const Ent &x, const Ent &y) {
+            return x.r != y.r ? x.r < y.r : (x.c != y.c ? x.c < y.c : x.o < y.o);
+        });
+        std::vector<int> rp((size_t)n + 1, 0), ci, opp;
+        for (size_t q = 0; q < ents.size();) {
+            size_t e = q;
+            while (e < ents.size() && ents[e].r == ents[q].r && ents[e].c == ents[q].c) ++e;
+            if (e - q > 2) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: an edge in more than two triangles");
+            ci.push_back(ents[q].c);
+            opp.push_back(ents[q].o);
+            opp.push_back(e - q == 2 ? ents[q + 1].o : -1);
+            ++rp[(size_t)ents[q].r + 1];
+            q = e;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (tdeg[(size_t)i] == 0) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: a node in no triangle");
+            rp[(size_t)i + 1] += rp[(size_t)i];
+        }
+        // per node: the other two vertices of each of its triangles, in triangle order
+        std::vector<int> trp((size_t)n + 1, 0), tv((size_t)6 * nt), fill((size_t)n, 0);
+        for (int64_t i = 0; i < n; ++i) trp[(size_t)i + 1] = trp[(size_t)i] + tdeg[(size_t)i];
+        for (int64_t t = 0; t < nt; ++t)
+            for (int e = 0; e < 3; ++e) {
+                const int j = (int)tri[3 * t + e];
+                const size_t q = (size_t)trp[j] + fill[j]++;
+                tv[2 * q] = (int)tri[3 * t + (e + 1) % 3];
+                tv[2 * q + 1] = (int)tri[3 * t + (e + 2) % 3];
+            }
+        const int nnz = (int)ci.size();
+        hipStream_t s = as_stream(stream);
+        gl_mesh *m = new gl_mesh();
+        try {
+            gl_grid_desc &d = m->desc;
+            std::memset(&d, 0, sizeof(d));
+            d.dim = 2;
+            d.n_axis[0] = n;
+            d.n_axis[1] = d.n_axis[2] = 1;
+            d.potential = desc->potential;
+            d.mu = desc->mu;
+            for (int a = 0; a < 3; ++a) {
+                d.b_dir[a] = desc->b_dir[a];
+                d.dipole_m[a] = desc->dipole_m[a];
+                d.dipole_x0[a] = desc->dipole_x0[a];
+            }
+            std::memcpy(d.a_matrix, desc->a_matrix, sizeof(d.a_matrix));
+            m->g.dim = 2;
+            m->g.n = (int)n;
+            m->g.N[0] = (int)n;
+            m->g.N[1] = m->g.N[2] = 1;
+            for (int a = 0; a < 3; ++a) m->g.h[a] = m->g.inv_h2[a] = 1.0;
+            compute_amat(d, d.mu, m->amat);
+            m->F64.alloc(1);
+            m->F32.alloc(1);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) m->foff[a][b] = -1;
+            auto upload = [&](auto &buf, const auto &v) {
+                buf.alloc(std::max<size_t>(1, v.size()));
+                if (!v.empty())
+                    GLK_HIP(hipMemcpyAsync(buf.get(), v.data(), sizeof(v[0]) * v.size(), hipMemcpyHostToDevice, s));
+            };
+            upload(m->s_rp, rp);
+            upload(m->s_ci, ci);
+            upload(m->s_opp, opp);
+            upload(m->s_trp, trp);
+            upload(m->s_tv, tv);
+            std::vector<double2> pts((size_t)n);
+            for (int64_t i = 0; i < n; ++i) pts[(size_t)i] = make_double2(xy[2 * i], xy[2 * i + 1]);
+            upload(m->s_xy, pts);
+            m->s_alpha.alloc(std::max(1, nnz));
+            m->s_phi.alloc(std::max(1, nnz));
+            m->s_kw64.alloc(std::max(1, nnz));
+            m->s_kw32.alloc(std::max(1, nnz));
+            m->s_ks64.alloc(n);
+            m->s_ks32.alloc(n);
+            m->s_vol64.alloc(n);
+            m->s_vol32.alloc(n);
+            Geom &g = m->g;
+            g.simplicial = true;
+            g.rp = m->s_rp.get();
+            g.ci = m->s_ci.get();
+            g.kw64 = m->s_kw64.get();
+            g.kw32 = m->s_kw32.get();
+            g.ks64 = m->s_ks64.get();
+            g.ks32 = m->s_ks32.get();
+            g.vol64 = m->s_vol64.get();
+            g.vol32 = m->s_vol32.get();
+            g.phi = m->s_phi.get();
+            m->partials.alloc(((size_t)blocks_for(n) + 64) * kMaxSlots);
+            m->dscal.alloc(64);
+            m->work.alloc((size_t)kWorkVecs * n);
+            m->kscal.alloc(4096);
+            GLK_HIP(hipHostMalloc(&m->hscal, 64 * sizeof(double), hipHostMallocDefault));
+            GLK_HIP(hipStreamCreateWithFlags(&m->ws, hipStreamNonBlocking));
+            GLK_HIP(hipEventCreateWithFlags(&m->ev_in, hipEventDisableTiming));
+            GLK_HIP(hipEventCreateWithFlags(&m->ev_out, hipEventDisableTiming));
+            GLK_HIP(hipMemsetAsync(m->dscal.get(), 0, 64 * sizeof(double), s));
+            GLK_HIP(hipMemsetAsync(m->kscal.get(), 0, 4096, s));
+            // the edge phases at unit strength: the field direction's matrix, the
+            // given matrix, or the dipole
+            Potential pot;
+            compute_amat(d, 1.0, pot.m);
+            for (int a = 0; a < 3; ++a) pot.L[a] = 0.0;
+            Dipole D;
+            D.mu = 1.0;
+            for (int a = 0; a < 3; ++a) {
+                D.m[a] = d.dipole_m[a];
+                D.x0[a] = d.dipole_x0[a];
+                D.lo[a] = 0.0;
+            }
+            const int nb = blocks_for(n);
+            k_simp_edges<<<nb, kBlock, 0, s>>>((int)n, m->s_rp.get(), m->s_ci.get(), m->s_opp.get(), m->s_xy.get(),
+                                               d.potential == 2, pot, D, m->s_alpha.get(), m->s_phi.get());
+            k_simp_nodes<<<nb, kBlock, 0, s>>>((int)n, m->s_rp.get(), m->s_alpha.get(), m->s_trp.get(),
+                                               m->s_tv.get(), m->s_xy.get(), m->s_ks64.get(), m->s_ks32.get(),
+                                               m->s_vol64.get(), m->s_vol32.get());
+            GLK_CHECK_LAUNCH();
+            launch_links(m, s);
+            GLK_HIP(hipStreamSynchronize(s));
+        } catch (...) {
+            delete m;
+            throw;
+        }
+        *out = m;
+    });
+}
+
 gl_status gl_mesh_set_field(gl_mesh *mesh, double mu, gl_stream stream)
 {
     return guarded([&] {
@@ -614,6 +927,7 @@ gl_status gl_mesh_export_links(const gl_mesh *mesh, int axis, void *host_out)
 {
     return guarded([&] {
         if (!mesh || !host_out) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_export_links: NULL argument");
+        if (mesh->g.simplicial) fail(GL_ERR_UNSUPPORTED, "gl_mesh_export_links: a simplicial mesh has no axes");
         if (axis < 0 || axis >= mesh->g.dim) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_export_links: axis");
         GLK_HIP(hipDeviceSynchronize());
         // staged in the first Krylov vector (no solve is in flight after the synchronisation)
@@ -662,10 +976,9 @@ gl_status gl_residual_noalloc(const gl_mesh *mesh, const void *psi, void *out, d
         const GeomT<double> g = geom_t<double>(mesh->g);
         const LinkTab<double> U = link_tab<double>(mesh);
         const RedSlot slot{sc};
-        if (mesh->g.dim == 2)
-            k_gl_residual<2><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, U, (double2 *)out, slot);
-        else
-            k_gl_residual<3><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, U, (double2 *)out, slot);
+        with_dim(mesh->g, [&](auto D) {
+            k_gl_residual<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, U, (double2 *)out, slot);
+        });
         GLK_CHECK_LAUNCH();
         double *res = sc + kNoAllocParts;
         launch_finalize(sc, nb, FIN_STORE, nullptr, res, nullptr, Launch{s});
@@ -708,8 +1021,10 @@ gl_status gl_residual_dmu(const gl_mesh *mesh, const void *psi, void *out, gl_st
     return guarded([&] {
         if (!mesh || !psi || !out) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual_dmu: NULL argument");
         if (out == psi) fail(GL_ERR_INVALID_ARGUMENT, "gl_residual_dmu: out aliases psi");
-        if (mesh->desc.potential != 0)
+        if (mesh->desc.potential == 1)
             fail(GL_ERR_UNSUPPORTED, "gl_residual_dmu: the mesh has no field-strength parameter");
+        if (mesh->desc.potential == 2 && !mesh->g.simplicial)
+            fail(GL_ERR_UNSUPPORTED, "gl_residual_dmu: the dipole potential on a grid");
         FieldDeriv fd;
         double m1[9];
         compute_amat(mesh->desc, 1.0, m1);
@@ -720,10 +1035,10 @@ gl_status gl_residual_dmu(const gl_mesh *mesh, const void *psi, void *out, gl_st
         const int nb = blocks_for(mesh->g.n);
         const GeomT<double> g = geom_t<double>(mesh->g);
         hipStream_t s = as_stream(stream);
-        if (mesh->g.dim == 2)
-            k_gl_dmu<2><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, link_tab<double>(mesh), fd, (double2 *)out);
-        else
-            k_gl_dmu<3><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, link_tab<double>(mesh), fd, (double2 *)out);
+        with_dim(mesh->g, [&](auto D) {
+            k_gl_dmu<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, link_tab<double>(mesh), fd,
+                                                               (double2 *)out);
+        });
         GLK_CHECK_LAUNCH();
     });
 }
@@ -735,12 +1050,10 @@ gl_status gl_inner(const gl_mesh *mesh, const void *u, const void *v, double *ou
         const int nb = blocks_for(mesh->g.n);
         const GeomT<double> g = geom_t<double>(mesh->g);
         hipStream_t s = as_stream(stream);
-        if (mesh->g.dim == 2)
-            k_cdot<2><<<nb, kBlock, 0, s>>>(g, (const double2 *)u, (const double2 *)v, red_slot(mesh, 2),
-                                            red_slot(mesh, 3));
-        else
-            k_cdot<3><<<nb, kBlock, 0, s>>>(g, (const double2 *)u, (const double2 *)v, red_slot(mesh, 2),
-                                            red_slot(mesh, 3));
+        with_dim(mesh->g, [&](auto D) {
+            k_cdot<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, (const double2 *)u, (const double2 *)v,
+                                                             red_slot(mesh, 2), red_slot(mesh, 3));
+        });
         GLK_CHECK_LAUNCH();
         launch_finalize(red_slot(mesh, 2).partials, nb, FIN_STORE, nullptr, mesh->dscal.get() + 6, nullptr, s);
         GLK_HIP(hipMemcpyAsync(mesh->hscal + 6, mesh->dscal.get() + 6, sizeof(double), hipMemcpyDeviceToHost, s));

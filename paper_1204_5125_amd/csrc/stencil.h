@@ -5,6 +5,8 @@
 // where U_a[k] is the link variable of the forward edge leaving node k along
 // axis a, a product of factor-table entries (LinkTab).  |V_i| and alpha_a are
 // computed from the node's position, so the operator streams only x.
+// On a simplicial mesh (DIM == 0) the same quantities come from its edge
+// arrays: (K-hat x)_j = ks_j x_j - sum_k kw_jk x_k over the node's adjacency.
 #pragma once
 
 #include "common.h"
@@ -38,6 +40,11 @@ __device__ __forceinline__ C<T> link_u(const LinkTab<T> &L, int a, const int c[3
 template <int DIM>
 __device__ __forceinline__ void node_coords(const int *N, int i, int c[3])
 {
+    if constexpr (DIM == 0) {  // a simplicial mesh: the node index itself
+        c[0] = i;
+        c[1] = c[2] = 0;
+        return;
+    }
     c[0] = i % N[0];
     int t = i / N[0];
     if (DIM == 3) {
@@ -53,6 +60,10 @@ __device__ __forceinline__ void node_coords(const int *N, int i, int c[3])
 template <int DIM, class T>
 __device__ __forceinline__ T node_volume(const GeomT<T> &g, const int c[3], T s[3])
 {
+    if constexpr (DIM == 0) {
+        s[0] = s[1] = s[2] = (T)1;
+        return g.vol[c[0]];
+    }
     T d = (T)1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -70,6 +81,13 @@ __device__ __forceinline__ C<T> khat_node(const GeomT<T> &g, int i, const int c[
                                           const C<T> *__restrict__ x,
                                           const LinkTab<T> &U, C<T> xi, T &d, T &asum)
 {
+    if constexpr (DIM == 0) {
+        d = g.vol[i];
+        asum = g.ks[i];
+        C<T> acc = mk<T>(0, 0);
+        for (int p = g.rp[i]; p < g.rp[i + 1]; ++p) acc = csub(acc, cmul(g.kw[p], x[g.ci[p]]));
+        return cadd(acc, cscale(xi, asum));
+    }
     T s[3];
     d = node_volume<DIM, T>(g, c, s);
     C<T> acc = mk<T>(0, 0);
@@ -101,6 +119,11 @@ __device__ __forceinline__ C<T> khat_offdiag(const GeomT<T> &g, int i, const int
                                              const C<T> *__restrict__ x,
                                              const LinkTab<T> &U)
 {
+    if constexpr (DIM == 0) {
+        C<T> acc = mk<T>(0, 0);
+        for (int p = g.rp[i]; p < g.rp[i + 1]; ++p) acc = csub(acc, cmul(g.kw[p], x[g.ci[p]]));
+        return acc;
+    }
     T s[3];
     const T d = node_volume<DIM, T>(g, c, s);
     C<T> acc = mk<T>(0, 0);

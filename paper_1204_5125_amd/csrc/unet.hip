@@ -703,7 +703,7 @@ static double read_double(const double *d, hipStream_t s)
 
 static void check_grid(const gl_unet *u, const gl_mesh *m)
 {
-    if (m->g.dim != 2 || m->g.N[0] != m->g.N[1])
+    if (m->g.simplicial || m->g.dim != 2 || m->g.N[0] != m->g.N[1])
         fail(GL_ERR_UNSUPPORTED, "gl_unet: the predictor needs a square 2D grid");
     const int N = m->g.N[0], q = 1 << (u->levels - 1);
     if ((N - 1) % q != 0 || (N - 1) / q < 1)

@@ -757,6 +757,51 @@ struct Output {
     }
 };
 
+// b[r] = round(v[perm[r]]): level 0 of a simplicial mesh, whose V-cycle
+// vectors are in colour order (row r is node perm[r])
+template <class T>
+struct NarrowPerm {
+    int n;
+    const double2 *v;
+    const int *perm;
+    C<T> *b;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        const int r = bx * kBlock + threadIdx.x;
+        if (r < n) b[r] = narrow<T>(v[perm[r]]);
+    }
+};
+
+// z[perm[r]] = x[r] (ADD: +=), partial sums of Re<vdot, z> in row order
+template <class T, int ADD>
+struct OutputPerm {
+    int n;
+    const C<T> *x;
+    const int *perm;
+    const double2 *vdot;
+    double2 *z;
+    RedSlot slot;
+    int want_dot;
+    const int *gate;
+    __device__ void operator()(int bx, int) const
+    {
+        GATE();
+        __shared__ double sm[kBlock / 64];
+        const int r = bx * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (r < n) {
+            const int i = perm[r];
+            double2 zi = widen(x[r]);
+            if (ADD) zi = cadd(z[i], zi);
+            z[i] = zi;
+            if (want_dot) part = redot(vdot[i], zi);
+        }
+        if (want_dot) block_reduce_store(part, slot, sm, bx);
+    }
+};
+
 // x = M b for a dense row-major operator (the coarsest inverse or an explicit
 // sub-cycle), a wave per row.  Each lane issues kDenseUnroll loads before it
 // uses any (a row of a few thousand entries is otherwise one memory round
@@ -1272,8 +1317,39 @@ static void l0_tiled_shape(int which, F &&f)
 
 // T: level 0 (stencil sweeps, where the bytes are); TC: levels >= 1 and the
 // coarsest solve (latency-bound: their precision costs no bandwidth)
+// The V-cycle below level 0, from b of level 1 to x of level 1: the
+// multi-kernel levels down (sweep from zero, residual, restriction), the
+// small levels and the dense operator of level `tail` (the coarsest inverse
+// or the explicit sub-cycle) in one work-group, or that dense product alone
+// over many work-groups, then the multi-kernel levels up (prolongation,
+// sweep).
+template <class TC>
+static void coarse_levels(gl_precond *pre, const int *gate, const Launch &L)
+{
+    const int nb_first = pre->bottom;
+    const int sh = pre->lane_shift;
+    for (int l = 1; l < nb_first; ++l) {
+        Level &Lv = pre->L[l];
+        csr_sgs<TC>(Lv, sh, true, gate, L);
+        csr_residual<TC>(Lv, sh, gate, L);
+        csr_spmv<TC>(Lv.Ra, vec_r<TC>(Lv), vec_b<TC>(pre->L[l + 1]), false, sh, gate, L);
+    }
+    if (pre->bottom < pre->tail) {
+        L.run<Bottom<TC>, kBottomThreads>(1, Bottom<TC>{bdesc<TC>(pre), gate}, bottom_lds<TC>(pre));
+    } else {
+        Level &Lc = pre->L[pre->tail];
+        L.run(blocks_for((int64_t)Lc.n * 64),
+              DenseApply<TC>{Lc.n, cinv<TC>(pre), vec_b<TC>(Lc), vec_x<TC>(Lc), gate});
+    }
+    for (int l = nb_first - 1; l >= 1; --l) {
+        Level &Lv = pre->L[l];
+        csr_spmv<TC>(Lv.Pa, vec_x<TC>(pre->L[l + 1]), vec_x<TC>(Lv), true, sh, gate, L);
+        csr_sgs<TC>(Lv, sh, false, gate, L);
+    }
+}
+
 template <int DIM, class T, class TC>
-static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
+static void vcycle_once_grid(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
                         const int *gate, KrylovScalars *ks, int mode, int add, const Launch &L,
                         double *store = nullptr)
 {
@@ -1342,31 +1418,8 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
     prof_launch(PROF_L0_TRANSFER, b_restr, L, [&] {
         csr_spmv<TC, T>(L0.Rb, vec_r<T>(L0), vec_b<TC>(L1), false, 0, gate, L);
     });
-    // multi-kernel coarse levels, down
-    const int nb_first = pre->bottom;
-    const int sh = pre->lane_shift;
-    for (int l = 1; l < nb_first; ++l) {
-        Level &Lv = pre->L[l];
-        csr_sgs<TC>(Lv, sh, true, gate, L);
-        csr_residual<TC>(Lv, sh, gate, L);
-        csr_spmv<TC>(Lv.Ra, vec_r<TC>(Lv), vec_b<TC>(pre->L[l + 1]), false, sh, gate, L);
-    }
-    // small levels and the dense operator of level `tail` (the coarsest
-    // inverse or the explicit sub-cycle) in one work-group, or that dense
-    // product alone over many work-groups
-    if (pre->bottom < pre->tail) {
-        L.run<Bottom<TC>, kBottomThreads>(1, Bottom<TC>{bdesc<TC>(pre), gate}, bottom_lds<TC>(pre));
-    } else {
-        Level &Lc = pre->L[pre->tail];
-        L.run(blocks_for((int64_t)Lc.n * 64),
-              DenseApply<TC>{Lc.n, cinv<TC>(pre), vec_b<TC>(Lc), vec_x<TC>(Lc), gate});
-    }
-    // multi-kernel coarse levels, up
-    for (int l = nb_first - 1; l >= 1; --l) {
-        Level &Lv = pre->L[l];
-        csr_spmv<TC>(Lv.Pa, vec_x<TC>(pre->L[l + 1]), vec_x<TC>(Lv), true, sh, gate, L);
-        csr_sgs<TC>(Lv, sh, false, gate, L);
-    }
+    // levels >= 1: b of level 1 in, x of level 1 out
+    coarse_levels<TC>(pre, gate, L);
     // level 0, up: red with the coarse correction, black, red + output
     // black coarse correction, then the red pass (fusing the two reads every
     // black correction four times and was measured slower); in 2D by default
@@ -1409,6 +1462,56 @@ static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 
         else L.run(nbp, L0Last<DIM, T, 0>{g, b0, x0, U, hs, z, vdot, slot, want, gate});
     });
     if (want) launch_finalize(slot.partials, nbp, fmode, ks, store, gate, L);
+}
+
+// Level 0 of a simplicial mesh is a CSR level like the coarse ones: its
+// rows in colour order (perm), padded colour blocks for the sweeps, the full
+// restriction and prolongation.
+template <class T, class TC>
+static void vcycle_once_simplicial(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
+                                   const int *gate, KrylovScalars *ks, int mode, int add, const Launch &L,
+                                   double *store)
+{
+    gl_precond *pre = const_cast<gl_precond *>(cpre);
+    const gl_mesh *m = pre->mesh;
+    const RedSlot slot = red_slot(m, 1);
+    Level &L0 = pre->L[0];
+    const int n0 = L0.n, nb0 = blocks_for(n0);
+    const int want = ks != nullptr || store != nullptr;
+    const int fmode = store ? (int)FIN_STORE : mode;
+    if (pre->nlev == 1) {  // the coarsest inverse in node order
+        C<TC> *xc0 = vec_x<TC>(L0);
+        L.run(nb0, Narrow<TC>{n0, v, vec_b<TC>(L0), gate});
+        L.run(blocks_for((int64_t)n0 * 64), DenseApply<TC>{n0, cinv<TC>(pre), vec_b<TC>(L0), xc0, gate});
+        if (add) L.run(nb0, Output<TC, 1>{n0, xc0, vdot, z, slot, want, gate});
+        else L.run(nb0, Output<TC, 0>{n0, xc0, vdot, z, slot, want, gate});
+        if (want) launch_finalize(slot.partials, nb0, fmode, ks, store, gate, L);
+        return;
+    }
+    Level &L1 = pre->L[1];
+    const int sh = pre->lane_shift;
+    const int *perm = L0.perm.get();
+    C<T> *x0 = vec_x<T>(L0);
+    L.run(nb0, NarrowPerm<T>{n0, v, perm, vec_b<T>(L0), gate});
+    csr_sgs<T>(L0, sh, true, gate, L);
+    csr_residual<T>(L0, sh, gate, L);
+    csr_spmv<TC, T>(L0.Ra, vec_r<T>(L0), vec_b<TC>(L1), false, sh, gate, L);
+    coarse_levels<TC>(pre, gate, L);
+    csr_spmv<T, TC>(L0.Pa, vec_x<TC>(L1), x0, true, sh, gate, L);
+    csr_sgs<T>(L0, sh, false, gate, L);
+    if (add) L.run(nb0, OutputPerm<T, 1>{n0, x0, perm, vdot, z, slot, want, gate});
+    else L.run(nb0, OutputPerm<T, 0>{n0, x0, perm, vdot, z, slot, want, gate});
+    if (want) launch_finalize(slot.partials, nb0, fmode, ks, store, gate, L);
+}
+
+// One V-cycle on H x = D v from x = 0 (DIM 0: a simplicial mesh)
+template <int DIM, class T, class TC>
+static void vcycle_once(const gl_precond *cpre, const double2 *v, const double2 *vdot, double2 *z,
+                        const int *gate, KrylovScalars *ks, int mode, int add, const Launch &L,
+                        double *store = nullptr)
+{
+    if constexpr (DIM == 0) vcycle_once_simplicial<T, TC>(cpre, v, vdot, z, gate, ks, mode, add, L, store);
+    else vcycle_once_grid<DIM, T, TC>(cpre, v, vdot, z, gate, ks, mode, add, L, store);
 }
 
 // ------------------------------------------------------------- R_inf ---
@@ -1613,8 +1716,7 @@ void pcg_calibrate(gl_precond *pre, hipStream_t s)
     const size_t n = (size_t)pre->L[0].n;
     if (pre->pcg.count < 5 * n) pre->pcg.alloc(5 * n);
     if (pre->pcg_sc.count < 2 * kPcgMaxSteps + 2) pre->pcg_sc.alloc(2 * kPcgMaxSteps + 2);
-    if (pre->mesh->g.dim == 2) pcg_calibrate_dim<2>(pre, s);
-    else pcg_calibrate_dim<3>(pre, s);
+    with_dim(pre->mesh->g, [&](auto D) { pcg_calibrate_dim<decltype(D)::value>(pre, s); });
 }
 
 template <int DIM, class T, class TC>
@@ -1646,15 +1748,12 @@ static void vcycle_k(const gl_precond *pre, const double2 *v, double2 *z, const 
 void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,
                     KrylovScalars *ks, int mode, const Launch &L, gl_precision p)
 {
-    if (pre->mesh->g.dim == 2) {
-        if (p == GL_FP32) vcycle_k<2, float, float>(pre, v, z, gate, ks, mode, L);
-        else if (p == GL_MIXED) vcycle_k<2, float, double>(pre, v, z, gate, ks, mode, L);
-        else vcycle_k<2, double, double>(pre, v, z, gate, ks, mode, L);
-    } else {
-        if (p == GL_FP32) vcycle_k<3, float, float>(pre, v, z, gate, ks, mode, L);
-        else if (p == GL_MIXED) vcycle_k<3, float, double>(pre, v, z, gate, ks, mode, L);
-        else vcycle_k<3, double, double>(pre, v, z, gate, ks, mode, L);
-    }
+    with_dim(pre->mesh->g, [&](auto D) {
+        constexpr int K = decltype(D)::value;
+        if (p == GL_FP32) vcycle_k<K, float, float>(pre, v, z, gate, ks, mode, L);
+        else if (p == GL_MIXED) vcycle_k<K, float, double>(pre, v, z, gate, ks, mode, L);
+        else vcycle_k<K, double, double>(pre, v, z, gate, ks, mode, L);
+    });
 }
 
 void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const int *gate,

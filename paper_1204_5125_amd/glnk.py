@@ -24,7 +24,7 @@ EXPORT = {"agg": 0, "root": 1, "color": 2, "A_rp": 3, "A_ci": 4, "A_v": 5, "P_rp
           "P_v": 8, "R_rp": 9, "R_ci": 10, "R_v": 11}
 
 EXPORTED_SYMBOLS = [
-    "gl_mesh_create_grid", "gl_mesh_set_field", "gl_mesh_num_nodes", "gl_mesh_export_links",
+    "gl_mesh_create_grid", "gl_mesh_create_simplicial", "gl_mesh_set_field", "gl_mesh_num_nodes", "gl_mesh_export_links",
     "gl_mesh_destroy", "gl_residual", "gl_residual_noalloc", "gl_residual_dmu", "gl_inner", "gl_axpby",
     "gl_jacobian_apply", "gl_secant_predict", "gl_precond_setup",
     "gl_precond_apply", "gl_precond_inner_steps",
@@ -49,6 +49,13 @@ class GridDesc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_axis", C.c_int64 * 3), ("side", C.c_double * 3),
                 ("potential", C.c_int), ("mu", C.c_double), ("b_dir", C.c_double * 3),
                 ("a_matrix", C.c_double * 9), ("dipole_m", C.c_double * 3), ("dipole_x0", C.c_double * 3)]
+
+
+class SimplicialDesc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xy", C.c_void_p), ("n_triangles", C.c_int64),
+                ("triangles", C.c_void_p), ("potential", C.c_int), ("mu", C.c_double),
+                ("b_dir", C.c_double * 3), ("a_matrix", C.c_double * 9), ("dipole_m", C.c_double * 3),
+                ("dipole_x0", C.c_double * 3)]
 
 
 class AmgOpts(C.Structure):
@@ -102,6 +109,7 @@ def lib():
     vp, st = C.c_void_p, C.c_int
     P = C.POINTER
     L.gl_mesh_create_grid.argtypes = [P(GridDesc), vp, P(vp)]
+    L.gl_mesh_create_simplicial.argtypes = [P(SimplicialDesc), vp, P(vp)]
     L.gl_mesh_set_field.argtypes = [vp, C.c_double, vp]
     L.gl_mesh_num_nodes.argtypes = [vp, P(C.c_int64)]
     L.gl_mesh_export_links.argtypes = [vp, C.c_int, vp]
@@ -210,6 +218,40 @@ class Mesh:
         _check(lib().gl_mesh_num_nodes(h, C.byref(nn)), "gl_mesh_num_nodes")
         self.n = nn.value
 
+    @classmethod
+    def simplicial(cls, xy, triangles, mu=0.0, b_dir=(0.0, 0.0, 1.0), a_matrix=None, dipole=None, stream=None):
+        """gl_mesh_create_simplicial: a 2D mesh of nodes xy (n x 2) and
+        triangles (m x 3 node indices); the potential as for the grid."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        tri = np.ascontiguousarray(triangles, dtype=np.int64)
+        if xy.ndim != 2 or xy.shape[1] != 2 or tri.ndim != 2 or tri.shape[1] != 3:
+            raise ValueError("xy must be n x 2 and triangles m x 3")
+        d = SimplicialDesc()
+        d.n_nodes, d.n_triangles = len(xy), len(tri)
+        d.xy, d.triangles = xy.ctypes.data, tri.ctypes.data
+        d.mu = mu
+        for a in range(3):
+            d.b_dir[a] = b_dir[a]
+        if a_matrix is not None:
+            d.potential = 1
+            for k, v in enumerate(np.asarray(a_matrix, dtype=np.float64).ravel()):
+                d.a_matrix[k] = v
+        if dipole is not None:
+            d.potential = 2
+            for a in range(3):
+                d.dipole_m[a] = float(dipole[0][a])
+                d.dipole_x0[a] = float(dipole[1][a])
+        h = C.c_void_p()
+        _check(lib().gl_mesh_create_simplicial(C.byref(d), _stream(stream), C.byref(h)),
+               "gl_mesh_create_simplicial")
+        self = cls.__new__(cls)
+        self._h = h
+        self.dim = 2
+        self.shape = None
+        self.side = None
+        self.n = len(xy)
+        return self
+
     @property
     def handle(self):
         return self._h
@@ -234,6 +276,10 @@ class Mesh:
 
 def gl_mesh_create_grid(dim, n_axis, side, **kw):
     return Mesh(dim, n_axis, side, **kw)
+
+
+def gl_mesh_create_simplicial(xy, triangles, **kw):
+    return Mesh.simplicial(xy, triangles, **kw)
 
 
 def gl_residual(mesh, psi, out=None, norm=True, stream=None):

@@ -60,7 +60,7 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 # ctypes mirror of each C struct of the header
 STRUCTS = {"gl_grid_desc": "GridDesc", "gl_amg_opts": "AmgOpts", "gl_krylov_opts": "KrylovOpts",
            "gl_krylov_info": "KrylovInfo", "gl_newton_opts": "NewtonOpts", "gl_tiles": "Tiles",
-           "gl_adam_opts": "AdamOpts", "gl_newton_info": "NewtonInfo"}
+           "gl_adam_opts": "AdamOpts", "gl_newton_info": "NewtonInfo", "gl_simplicial_desc": "SimplicialDesc"}
 
 
 def test_binding_struct_layouts_match_header(tmp_path):
