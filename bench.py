@@ -587,7 +587,10 @@ def bench_meshind(args):
     to rtol 1e-11 with one V-cycle per MINRES step, uniform field mu = 1 along
     z; 2D squares of side 10 with N = 33 ... 1025 nodes per axis, 3D cubes of
     side 10/sqrt(3) (circumradius 5) with N = 9 ... 129.  Reports the MINRES
-    iterations per grid with the FP64 and the FP32 V-cycle."""
+    iterations per grid with the FP64 and the FP32 V-cycle; the cube in the
+    dipole potential; and the triangle and disc of circumradius 5 as
+    simplicial meshes (153 to 1.05 M nodes) in both potentials with R_1,
+    R_inf and, up to 3000 nodes, no preconditioner."""
     import torch
 
     from paper_1204_5125_amd import glnk
@@ -622,6 +625,35 @@ def bench_meshind(args):
                                           raise_on_fail=False)
         dip_rows.append({"N": n, "nodes": mesh.n, "iterations": info["iterations"], "status": rc})
         log(f"[bench] meshind cube A_d {dip_rows[-1]}")
+    # Fig. 3 protocol on the paper's other 2D domains, the triangle and the
+    # disc of circumradius 5 as simplicial meshes, A_z and A_d (m = e_z at
+    # (0, 0, 1)), mu = 1: R_1, R_inf and (small meshes) no preconditioner
+    from paper_1204_5125_amd import meshes
+    simp_rows = []
+    sizes = {"tri": (16, 32, 64, 128, 256, 512, 1024, 1448), "circ": (8, 16, 32, 64, 128, 256, 512)}
+    for dom, ks in sizes.items():
+        for k in ks:
+            xy, tri = meshes.domain(dom, k)
+            for pot, kw in (("Az", {}), ("Ad", {"dipole": ((0, 0, 1), (0, 0, 1))})):
+                mesh = glnk.Mesh.simplicial(xy, tri, mu=1.0, **kw)
+                ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
+                x = torch.empty_like(ones)
+                row = {"domain": dom, "potential": pot, "k": k, "nodes": mesh.n}
+                for name, cyc in (("R1", 1), ("Rinf", 0)):
+                    if cyc == 0 and mesh.n > 300000:
+                        continue
+                    pre = glnk.Precond(mesh, ones, cycles=cyc, max_coarse=64)
+                    rc, info = glnk.gl_jacobian_solve(mesh, ones, pre, ones, x, rtol=1e-11, max_iter=4000,
+                                                      poll_every=8, raise_on_fail=False)
+                    row[name] = info["iterations"] if rc == 0 else None
+                    if cyc == 1:
+                        row["levels"] = pre.info()["sizes"]
+                if mesh.n <= 3000:
+                    rc, info = glnk.gl_jacobian_solve(mesh, ones, None, ones, x, rtol=1e-11, max_iter=3000,
+                                                      poll_every=8, raise_on_fail=False)
+                    row["unpreconditioned"] = info["iterations"] if rc == 0 else None
+                log(f"[bench] meshind simplicial {row}")
+                simp_rows.append(row)
     it2 = [r["fp64"]["iterations"] for r in rows if r["dim"] == 2]
     it3 = [r["fp64"]["iterations"] for r in rows if r["dim"] == 3]
     out = {
@@ -635,6 +667,7 @@ def bench_meshind(args):
         "iterations_2d_fp64": it2, "iterations_3d_fp64": it3, "grids": rows,
         "cube_dipole_fig3": {"iterations": [r["iterations"] for r in dip_rows], "N": [r["N"] for r in dip_rows],
                              "paper_R1": [6, 22, 29, 31, 31, 32, 32, 31]},
+        "simplicial_2d": simp_rows,
     }
     print(json.dumps(out), flush=True)
 
