@@ -74,6 +74,8 @@ def lib():
         L.orc_mesh_build_tri.argtypes = [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, _d, C.POINTER(C.POINTER(_Mesh))]
         L.orc_mesh_build_tri_dipole.argtypes = [C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_double, _d, _d,
                                                 C.POINTER(C.POINTER(_Mesh))]
+        L.orc_mesh_build_tet.argtypes = L.orc_mesh_build_tri.argtypes
+        L.orc_mesh_build_tet_dipole.argtypes = L.orc_mesh_build_tri_dipole.argtypes
         L.orc_mesh_free.argtypes = [C.POINTER(_Mesh)]
         for f in ("orc_khat_apply",):
             getattr(L, f).argtypes = [C.POINTER(_Mesh), vp, vp]
@@ -151,29 +153,36 @@ class Mesh:
         self._adopt(p, amat)
 
     @classmethod
-    def triangles(cls, xy, tri, amat=None, mu=None, bdir=(0.0, 0.0, 1.0), dipole=None):
-        """2D simplicial mesh: nodes xy (n x 2), triangles tri (m x 3); edge
-        coefficients by the Corollary's system per triangle, control volumes
-        as the nodes' shares of their triangles (oracle/oracle.h)."""
+    def simplices(cls, x, cells, amat=None, mu=None, bdir=(0.0, 0.0, 1.0), dipole=None):
+        """Simplicial mesh: nodes x (n x 2 or n x 3), cells (m x 3 triangles
+        or m x 4 tetrahedra); edge coefficients by the Corollary's system per
+        simplex, control volumes as the nodes' shares of their simplices
+        (oracle/oracle.h)."""
         if amat is None:
             amat = field_matrix(0.0 if mu is None else mu, bdir) if dipole is None else np.zeros((3, 3))
-        xy = np.ascontiguousarray(xy, dtype=np.float64)
-        tri = np.ascontiguousarray(tri, dtype=np.int64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        dim = x.shape[1]
+        if dim not in (2, 3) or cells.ndim != 2 or cells.shape[1] != dim + 1:
+            raise ValueError("x must be n x 2 with triangles or n x 3 with tetrahedra")
+        name = "orc_mesh_build_tri" if dim == 2 else "orc_mesh_build_tet"
         p = C.POINTER(_Mesh)()
         if dipole is not None:
             dm = (C.c_double * 3)(*[float(v) for v in dipole[0]])
             dx = (C.c_double * 3)(*[float(v) for v in dipole[1]])
-            rc = lib().orc_mesh_build_tri_dipole(len(xy), _ptr(xy), len(tri), _ptr(tri),
-                                                 1.0 if mu is None else float(mu), dm, dx, C.byref(p))
+            rc = getattr(lib(), name + "_dipole")(len(x), _ptr(x), len(cells), _ptr(cells),
+                                                  1.0 if mu is None else float(mu), dm, dx, C.byref(p))
         else:
             am = (C.c_double * 9)(*np.asarray(amat, dtype=np.float64).ravel())
-            rc = lib().orc_mesh_build_tri(len(xy), _ptr(xy), len(tri), _ptr(tri), am, C.byref(p))
+            rc = getattr(lib(), name)(len(x), _ptr(x), len(cells), _ptr(cells), am, C.byref(p))
         if rc != ORC_OK:
-            raise OracleError(rc, "orc_mesh_build_tri")
+            raise OracleError(rc, name)
         self = cls.__new__(cls)
         self._adopt(p, amat)
-        self.tri = tri.copy()
+        self.cells = cells.copy()
         return self
+
+    triangles = simplices
 
     def _adopt(self, p, amat):
         self._p = p

@@ -7,11 +7,12 @@
  *  - Corollary on simplex edge coefficients and the Remark giving
  *    alpha = 1/2 cot(theta) for triangles; alpha_jk is summed over all
  *    simplices adjacent to the edge.  2D grids: the Remark's cotangent,
- *    triangle by triangle; simplicial meshes: the Corollary's system
- *    M alpha = b per triangle (a second route to the same numbers), and the
- *    control volume of a node as the sum of its shares
- *    1/4 alpha_e |e|^2 over the triangle's two edges at it (the Voronoi
- *    region's part of a triangle that holds its circumcentre).
+ *    triangle by triangle; simplicial meshes (triangles and tetrahedra):
+ *    the Corollary's system M alpha = b per simplex (for triangles a second
+ *    route to the Remark's numbers), and the control volume of a node as
+ *    the sum of its shares 1/(2 dim) alpha_e |e|^2 over each simplex's edges
+ *    at it (the Voronoi region's part of a simplex that holds its
+ *    circumcentre).
  *    3D (cube grid, degenerate Delaunay): alpha = |dual Voronoi facet| / |e|.
  *  - Link variable U_jk = exp(-i int_{x_k}^{x_j} e_jk . A(w) dw), integral taken
  *    along the straight edge; evaluated here by 3-point Gauss-Legendre, which is
@@ -310,25 +311,26 @@ static int mesh_build(int dim, const int64_t *N, const double *L, const double *
 }
 
 /* ---------------------------------------------------------- simplicial --- */
-/* M a = b for 3 x 3, Gaussian elimination with partial pivoting; 0 if singular */
-static int solve3(double M[3][3], double b[3], double a[3])
+/* M a = b for m x m (m <= 6), Gaussian elimination with partial pivoting;
+   M and b are overwritten; 0 if singular */
+static int solve_small(int m, double M[6][6], double b[6], double a[6])
 {
-    for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < m; ++c) {
         int piv = c;
-        for (int r = c + 1; r < 3; ++r)
+        for (int r = c + 1; r < m; ++r)
             if (fabs(M[r][c]) > fabs(M[piv][c])) piv = r;
         if (!(fabs(M[piv][c]) > 0.0)) return 0;
-        for (int k = 0; k < 3; ++k) { double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t; }
+        for (int k = 0; k < m; ++k) { double t = M[c][k]; M[c][k] = M[piv][k]; M[piv][k] = t; }
         double t = b[c]; b[c] = b[piv]; b[piv] = t;
-        for (int r = c + 1; r < 3; ++r) {
+        for (int r = c + 1; r < m; ++r) {
             double f = M[r][c] / M[c][c];
-            for (int k = c; k < 3; ++k) M[r][k] -= f * M[c][k];
+            for (int k = c; k < m; ++k) M[r][k] -= f * M[c][k];
             b[r] -= f * b[c];
         }
     }
-    for (int c = 2; c >= 0; --c) {
+    for (int c = m - 1; c >= 0; --c) {
         double s = b[c];
-        for (int k = c + 1; k < 3; ++k) s -= M[c][k] * a[k];
+        for (int k = c + 1; k < m; ++k) s -= M[c][k] * a[k];
         a[c] = s / M[c][c];
     }
     return 1;
@@ -355,63 +357,80 @@ static int64_t find_edge(const edge_rec *E, int64_t ne, int64_t hi, int64_t lo)
     return -1;
 }
 
-static int tri_build(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, const double *amat,
-                     const double *dip, orc_mesh **out)
+/* |S| of the simplex with vertex coordinates P[0..dim] (rows of 3) */
+static double simplex_volume(int dim, const double P[4][3])
 {
-    if (n < 3 || ntri < 1) return ORC_ERR_ARG;
-    for (int64_t t = 0; t < 3 * ntri; ++t)
-        if (tri[t] < 0 || tri[t] >= n) return ORC_ERR_ARG;
+    double u[3], v[3], w[3];
+    for (int c = 0; c < 3; ++c) { u[c] = P[1][c] - P[0][c]; v[c] = P[2][c] - P[0][c]; }
+    if (dim == 2) return 0.5 * fabs(u[0] * v[1] - u[1] * v[0]);
+    for (int c = 0; c < 3; ++c) w[c] = P[3][c] - P[0][c];
+    return fabs(u[0] * (v[1] * w[2] - v[2] * w[1]) - u[1] * (v[0] * w[2] - v[2] * w[0]) +
+                u[2] * (v[0] * w[1] - v[1] * w[0])) / 6.0;
+}
+
+static int simplex_build(int dim, int64_t n, const double *x, int64_t ncell, const int64_t *cells,
+                         const double *amat, const double *dip, orc_mesh **out)
+{
+    const int nv = dim + 1, ned = dim * (dim + 1) / 2;
+    if ((dim != 2 && dim != 3) || n < dim + 1 || ncell < 1) return ORC_ERR_ARG;
+    for (int64_t t = 0; t < nv * ncell; ++t)
+        if (cells[t] < 0 || cells[t] >= n) return ORC_ERR_ARG;
     orc_mesh *m = calloc(1, sizeof(*m));
-    m->dim = 2;
+    m->dim = dim;
     m->grid = 0;
     m->n = n;
     m->N[0] = n;
     m->N[1] = m->N[2] = 1;
     for (int a = 0; a < 9; ++a) m->amat[a] = amat[a];
     m->x = calloc((size_t)n * 3, sizeof(double));
-    for (int64_t i = 0; i < n; ++i) { m->x[3 * i] = xy[2 * i]; m->x[3 * i + 1] = xy[2 * i + 1]; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < dim; ++c) m->x[3 * i + c] = x[dim * i + c];
     m->vol = calloc((size_t)n, sizeof(double));
+    /* the local edges of a simplex: vertex pairs (a, b), a < b */
+    int ea[6], eb[6], q = 0;
+    for (int a = 0; a < nv; ++a)
+        for (int b = a + 1; b < nv; ++b) { ea[q] = a; eb[q] = b; ++q; }
     /* the distinct edges, (j, k) with j > k, in ascending order */
-    edge_rec *E = malloc((size_t)(3 * ntri) * sizeof(edge_rec));
-    for (int64_t t = 0; t < ntri; ++t)
-        for (int e = 0; e < 3; ++e) {
-            int64_t a = tri[3 * t + e], b = tri[3 * t + (e + 1) % 3];
-            E[3 * t + e].j = a > b ? a : b;
-            E[3 * t + e].k = a > b ? b : a;
-            E[3 * t + e].alpha = 0.0;
+    edge_rec *E = malloc((size_t)(ned * ncell) * sizeof(edge_rec));
+    for (int64_t t = 0; t < ncell; ++t)
+        for (int e = 0; e < ned; ++e) {
+            int64_t a = cells[nv * t + ea[e]], b = cells[nv * t + eb[e]];
+            E[ned * t + e].j = a > b ? a : b;
+            E[ned * t + e].k = a > b ? b : a;
+            E[ned * t + e].alpha = 0.0;
         }
-    qsort(E, (size_t)(3 * ntri), sizeof(edge_rec), cmp_edge);
+    qsort(E, (size_t)(ned * ncell), sizeof(edge_rec), cmp_edge);
     int64_t ne = 0;
-    for (int64_t q = 0; q < 3 * ntri; ++q)
-        if (ne == 0 || cmp_edge(&E[ne - 1], &E[q]) != 0) E[ne++] = E[q];
-    /* per triangle: the Corollary's system for its three edge coefficients,
-       then each vertex's share of the triangle */
-    for (int64_t t = 0; t < ntri; ++t) {
-        const int64_t *p = &tri[3 * t];
-        double e[3][2];
-        for (int i = 0; i < 3; ++i) {
-            const double *u = &m->x[3 * p[i]], *v = &m->x[3 * p[(i + 1) % 3]];
-            e[i][0] = v[0] - u[0];
-            e[i][1] = v[1] - u[1];
+    for (int64_t r = 0; r < ned * ncell; ++r)
+        if (ne == 0 || cmp_edge(&E[ne - 1], &E[r]) != 0) E[ne++] = E[r];
+    /* per simplex: the Corollary's system M alpha = b for its edge
+       coefficients, M_ij = <e_i, e_j>^2, b_i = |S| |e_i|^2; then each
+       vertex's share 1/(2 dim) alpha_e |e|^2 of each of its edges */
+    for (int64_t t = 0; t < ncell; ++t) {
+        const int64_t *p = &cells[nv * t];
+        double P[4][3] = {{0}};
+        for (int a = 0; a < nv; ++a)
+            for (int c = 0; c < 3; ++c) P[a][c] = m->x[3 * p[a] + c];
+        const double vol = simplex_volume(dim, P);
+        if (!(vol > 0.0)) { free(E); orc_mesh_free(m); return ORC_ERR_ARG; }
+        double e[6][3], M[6][6], bb[6], al[6], l2[6];
+        for (int i = 0; i < ned; ++i) {
+            for (int c = 0; c < 3; ++c) e[i][c] = P[eb[i]][c] - P[ea[i]][c];
+            l2[i] = e[i][0] * e[i][0] + e[i][1] * e[i][1] + e[i][2] * e[i][2];
+            bb[i] = vol * l2[i];
         }
-        const double area = 0.5 * fabs(e[0][0] * (-e[2][1]) - e[0][1] * (-e[2][0]));
-        if (!(area > 0.0)) { free(E); orc_mesh_free(m); return ORC_ERR_ARG; }
-        double M[3][3], b[3], al[3], l2[3];
-        for (int i = 0; i < 3; ++i) {
-            l2[i] = e[i][0] * e[i][0] + e[i][1] * e[i][1];
-            b[i] = area * l2[i];
-            for (int j = 0; j < 3; ++j) {
-                double d = e[i][0] * e[j][0] + e[i][1] * e[j][1];
+        for (int i = 0; i < ned; ++i)
+            for (int j = 0; j < ned; ++j) {
+                double d = e[i][0] * e[j][0] + e[i][1] * e[j][1] + e[i][2] * e[j][2];
                 M[i][j] = d * d;
             }
-        }
-        if (!solve3(M, b, al)) { free(E); orc_mesh_free(m); return ORC_ERR_ARG; }
-        for (int i = 0; i < 3; ++i) {
-            int64_t a = p[i], c = p[(i + 1) % 3];
-            int64_t q = find_edge(E, ne, a > c ? a : c, a > c ? c : a);
-            E[q].alpha += al[i];
-            m->vol[a] += 0.25 * al[i] * l2[i];
-            m->vol[c] += 0.25 * al[i] * l2[i];
+        if (!solve_small(ned, M, bb, al)) { free(E); orc_mesh_free(m); return ORC_ERR_ARG; }
+        for (int i = 0; i < ned; ++i) {
+            int64_t a = p[ea[i]], c = p[eb[i]];
+            int64_t r = find_edge(E, ne, a > c ? a : c, a > c ? c : a);
+            E[r].alpha += al[i];
+            m->vol[a] += al[i] * l2[i] / (2.0 * dim);
+            m->vol[c] += al[i] * l2[i] / (2.0 * dim);
         }
     }
     finish_mesh(m, E, ne, amat, dip);
@@ -423,7 +442,7 @@ static int tri_build(int64_t n, const double *xy, int64_t ntri, const int64_t *t
 int orc_mesh_build_tri(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, const double *amat,
                        orc_mesh **out)
 {
-    return tri_build(n, xy, ntri, tri, amat, NULL, out);
+    return simplex_build(2, n, xy, ntri, tri, amat, NULL, out);
 }
 
 int orc_mesh_build_tri_dipole(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, double mu,
@@ -431,7 +450,21 @@ int orc_mesh_build_tri_dipole(int64_t n, const double *xy, int64_t ntri, const i
 {
     static const double zero[9] = {0};
     double dip[7] = {mu, mm[0], mm[1], mm[2], x0[0], x0[1], x0[2]};
-    return tri_build(n, xy, ntri, tri, zero, dip, out);
+    return simplex_build(2, n, xy, ntri, tri, zero, dip, out);
+}
+
+int orc_mesh_build_tet(int64_t n, const double *xyz, int64_t ntet, const int64_t *tet, const double *amat,
+                       orc_mesh **out)
+{
+    return simplex_build(3, n, xyz, ntet, tet, amat, NULL, out);
+}
+
+int orc_mesh_build_tet_dipole(int64_t n, const double *xyz, int64_t ntet, const int64_t *tet, double mu,
+                              const double *mm, const double *x0, orc_mesh **out)
+{
+    static const double zero[9] = {0};
+    double dip[7] = {mu, mm[0], mm[1], mm[2], x0[0], x0[1], x0[2]};
+    return simplex_build(3, n, xyz, ntet, tet, zero, dip, out);
 }
 
 void orc_mesh_free(orc_mesh *m)

@@ -62,6 +62,12 @@ int  orc_mesh_build_tri(int64_t n, const double *xy, int64_t ntri, const int64_t
                         orc_mesh **out);
 int  orc_mesh_build_tri_dipole(int64_t n, const double *xy, int64_t ntri, const int64_t *tri, double mu,
                                const double *m, const double *x0, orc_mesh **out);
+/* 3D: nodes xyz (n x 3), tetrahedra (ntet x 4); the same rules with six
+ * edges per simplex and shares 1/6 alpha_e |e|^2. */
+int  orc_mesh_build_tet(int64_t n, const double *xyz, int64_t ntet, const int64_t *tet, const double *amat,
+                        orc_mesh **out);
+int  orc_mesh_build_tet_dipole(int64_t n, const double *xyz, int64_t ntet, const int64_t *tet, double mu,
+                               const double *m, const double *x0, orc_mesh **out);
 void orc_mesh_free(orc_mesh *m);
 
 /* --------------------------------------------------------- operators --- */

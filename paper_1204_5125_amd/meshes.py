@@ -1,12 +1,14 @@
-"""Simplicial meshes of the paper's two-dimensional test domains (Sec. 4.1):
-the triangle and the disc of circumradius 5 centred at the origin.
+"""Simplicial meshes of the paper's test domains (Sec. 4.1): the triangle,
+the disc and the tetrahedron of circumradius 5 centred at the origin.
 
-Input generation only: node coordinates and triangles (node index triples),
-shared by the oracle and the GPU path; none of the method's arithmetic (edge
-coefficients, control volumes, link variables) is computed here.  Both
-meshes are built explicitly, without a Delaunay search, so they are exactly
+Input generation only: node coordinates and cells (node index triples or
+quadruples), shared by the oracle and the GPU path; none of the method's
+arithmetic (edge coefficients, control volumes, link variables) is computed
+here.  The meshes are built explicitly, without a Delaunay search, so they are exactly
 reproducible: the triangle as its regular subdivision into equilateral
-triangles, the disc as rings of nodes stitched in angle order.
+triangles, the disc as rings of nodes stitched in angle order, the
+tetrahedron as its regular lattice of tetrahedra and octahedra, each
+octahedron split at its centre.
 """
 import numpy as np
 
@@ -72,10 +74,67 @@ def disc(k):
     return np.array(pts, dtype=np.float64), np.array(tris, dtype=np.int64)
 
 
+# Omega_tet: the regular tetrahedron of circumradius 5 (Sec. 4.1)
+TET_VERTICES = RADIUS * np.array([[0.0, 0.0, 1.0], [2 * np.sqrt(2) / 3, 0.0, -1 / 3],
+                                  [-np.sqrt(2) / 3, np.sqrt(2 / 3), -1 / 3], [-np.sqrt(2) / 3, -np.sqrt(2 / 3), -1 / 3]])
+
+
+def tetrahedron(k):
+    """Omega_tet, the regular tetrahedron of circumradius 5, by its lattice of
+    edge 1/k: nodes (i, j, l) = V0 + i/k (V1 - V0) + j/k (V2 - V0) + l/k
+    (V3 - V0), i + j + l <= k, ordered by l, then j, then i; cells: the
+    upward tetrahedra, the downward ones and the octahedra between them, each
+    octahedron split into the eight tetrahedra that join its centre to its
+    faces.  The centres are appended after the lattice nodes, in the order of
+    their octahedra.  Nodes (k + 1)(k + 2)(k + 3) / 6 + (k - 1) k (k + 1) / 6,
+    cells k (k + 1)(k + 2) / 6 + (k - 2)(k - 1) k / 6 + 8 (k - 1) k (k + 1) / 6.
+
+    The split around a centre gives every edge a coefficient alpha >= 0 (the
+    centre's edges see the octahedron's faces at acute angles, and its
+    faces' edges see the centre at right angles); the split of an octahedron
+    into four tetrahedra around one of its diagonals would give that
+    diagonal a negative one (the opposite dihedral angle is the
+    octahedron's, above 90 degrees), which can leave K-hat indefinite in a
+    magnetic field.  Returns (xyz, tets)."""
+    if k < 1:
+        raise ValueError("k >= 1")
+    V = TET_VERTICES
+    index = {}
+    pts = []
+    for l in range(k + 1):
+        for j in range(k + 1 - l):
+            for i in range(k + 1 - l - j):
+                index[(i, j, l)] = len(pts)
+                pts.append(V[0] + (i / k) * (V[1] - V[0]) + (j / k) * (V[2] - V[0]) + (l / k) * (V[3] - V[0]))
+    cells = []
+    centres = []
+    for l in range(k):
+        for j in range(k - l):
+            for i in range(k - l - j):
+                def at(di, dj, dl):
+                    return index[(i + di, j + dj, l + dl)]
+                cells.append((at(0, 0, 0), at(1, 0, 0), at(0, 1, 0), at(0, 0, 1)))
+                if i + j + l <= k - 2:
+                    # the octahedron's three antipodal vertex pairs; each face
+                    # takes one vertex of every pair
+                    pairs = ((at(1, 0, 0), at(0, 1, 1)), (at(0, 1, 0), at(1, 0, 1)), (at(0, 0, 1), at(1, 1, 0)))
+                    c = len(pts) + len(centres)
+                    centres.append(np.mean([pts[v] for pr in pairs for v in pr], axis=0))
+                    for a in range(2):
+                        for b in range(2):
+                            for d in range(2):
+                                cells.append((c, pairs[0][a], pairs[1][b], pairs[2][d]))
+                if i + j + l <= k - 3:
+                    cells.append((at(1, 1, 0), at(1, 0, 1), at(0, 1, 1), at(1, 1, 1)))
+    return np.array(pts + centres, dtype=np.float64).reshape(-1, 3), np.array(cells, dtype=np.int64)
+
+
 def domain(name, k):
-    """(xy, tri) of "tri" or "circ" at refinement k."""
+    """(coordinates, cells) of "tri", "circ" or "tet" at refinement k."""
     if name == "tri":
         return triangle(k)
     if name == "circ":
         return disc(k)
+    if name == "tet":
+        return tetrahedron(k)
     raise ValueError(f"unknown domain {name!r}")

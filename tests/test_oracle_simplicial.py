@@ -1,11 +1,12 @@
-"""Pins of the oracle on simplicial meshes of the paper's 2D test domains
-(Sec. 3, Sec. 4.1): the triangle and the disc of circumradius 5
-(paper_1204_5125_amd/meshes.py).
+"""Pins of the oracle on simplicial meshes of the paper's test domains
+(Sec. 3, Sec. 4.1): the triangle, the disc and the tetrahedron of
+circumradius 5 (paper_1204_5125_amd/meshes.py).
 
 The oracle takes the edge coefficients from the Corollary's system
 M alpha = b per triangle and the control volumes from the nodes' shares
-1/4 alpha_e |e|^2 of their triangles' edges.  Pinned against: the Remark's
-cotangent formula (a second route), the Corollary's identity
+1/4 alpha_e |e|^2 of their triangles' edges; in 3D the same system per
+tetrahedron, with shares 1/6 alpha_e |e|^2.  Pinned against: the Remark's cotangent formula (a second
+route; in 3D the dihedral-angle cotangents), the Corollary's identity
 sum alpha e e^T = |Omega| I for the whole mesh, the equilateral lattice's
 closed forms, the circumcentric (Voronoi) kite areas computed geometrically,
 quadrature of the dipole's link integral, finite differences of GL, the
@@ -191,3 +192,151 @@ def test_newton_converges_and_gauge_kernel():
     # the hierarchy colours level 0 greedily (no red-black parity on triangles)
     amg = oracle.Amg.for_state(m, psi, max_coarse=16)
     assert amg.levels[0]["ncolors"] >= 3
+
+
+# ---------------------------------------------------------------- tetrahedra
+DIPOLE_3D = ((0.0, 0.0, 1.0), (0.0, 0.0, 6.0))   # Sec. 4.1: x0 = (0, 0, 6) for the 3D domains
+TET_VOLUME = 5 ** 3 * 8 / (9 * np.sqrt(3))       # regular tetrahedron of circumradius 5
+
+
+def tet_volumes(x, t):
+    P = x[t]
+    return np.abs(np.einsum("ij,ij->i", P[:, 1] - P[:, 0], np.cross(P[:, 2] - P[:, 0], P[:, 3] - P[:, 0]))) / 6
+
+
+def jittered_tet(k, seed):
+    """The tetrahedron mesh with interior lattice nodes moved by up to 8 % of
+    the lattice edge (still a valid mesh; coefficients of either sign)."""
+    x, t = meshes.tetrahedron(k)
+    rng = np.random.default_rng(seed)
+    x = x.copy()
+    # interior: strictly inside all four faces (barycentric coordinates > 0)
+    B = np.linalg.solve(np.vstack([meshes.TET_VERTICES.T, np.ones(4)]), np.vstack([x.T, np.ones(len(x))]))
+    inner = np.all(B > 1e-9, axis=0)
+    x[inner] += rng.uniform(-1, 1, (inner.sum(), 3)) * 0.08 * 5 * np.sqrt(8 / 3) / k
+    return x, t
+
+
+TETS = [("tet", *meshes.tetrahedron(4)), ("tet-jitter", *jittered_tet(5, 7))]
+TET_IDS = [m[0] for m in TETS]
+
+
+def test_tet_mesh_covers_the_domain():
+    for k in (1, 2, 5):
+        x, t = meshes.tetrahedron(k)
+        assert len(x) == (k + 1) * (k + 2) * (k + 3) // 6 + (k - 1) * k * (k + 1) // 6
+        v = tet_volumes(x, t)
+        assert v.min() > 0 and v.sum() == pytest.approx(TET_VOLUME, rel=1e-13)
+        faces = {}
+        for c in t:
+            for f in range(4):
+                key = tuple(sorted(np.delete(c, f)))
+                faces[key] = faces.get(key, 0) + 1
+        assert max(faces.values()) <= 2
+        # the faces in one cell tile the surface: four equilateral triangles of side s
+        once = np.array([f for f, c in faces.items() if c == 1])
+        area = 0.5 * np.linalg.norm(np.cross(x[once[:, 1]] - x[once[:, 0]], x[once[:, 2]] - x[once[:, 0]]), axis=1)
+        assert area.sum() == pytest.approx(4 * np.sqrt(3) / 4 * (5 * np.sqrt(8 / 3)) ** 2, rel=1e-13)
+
+
+@pytest.mark.parametrize("mesh", TETS, ids=TET_IDS)
+def test_tet_coefficients_follow_the_dihedral_cotangents(mesh):
+    """In 3D the Corollary's alpha of an edge is the sum over its tetrahedra
+    of |e'| cot(theta') / 6, e' the opposite edge and theta' the dihedral
+    angle there (the linear finite-element stiffness), computed here from
+    face normals; the sum alpha e e^T is |Omega| I; the volumes add up to
+    |Omega|."""
+    _, x, t = mesh
+    m = oracle.Mesh.simplices(x, t, mu=0.7)
+    want = {}
+    for c in t:
+        for a in range(4):
+            for b in range(a + 1, 4):
+                o = [v for v in range(4) if v not in (a, b)]
+                p, q = x[c[o[0]]], x[c[o[1]]]
+                eo = q - p
+                na, nb = np.cross(eo, x[c[a]] - p), np.cross(eo, x[c[b]] - p)
+                cos = na @ nb / (np.linalg.norm(na) * np.linalg.norm(nb))
+                key = (max(c[a], c[b]), min(c[a], c[b]))
+                want[key] = want.get(key, 0.0) + np.linalg.norm(eo) * cos / np.sqrt(1 - cos * cos) / 6
+    got = {(int(j), int(kk)): a for j, kk, a in zip(m.ej, m.ek, m.alpha)}
+    assert set(got) == set(want)
+    for key, a in got.items():
+        assert a == pytest.approx(want[key], rel=1e-11, abs=1e-13)
+    S = np.zeros((3, 3))
+    for j, kk, a in zip(m.ej, m.ek, m.alpha):
+        e = x[j] - x[kk]
+        S += a * np.outer(e, e)
+    np.testing.assert_allclose(S, TET_VOLUME * np.eye(3), atol=1e-11 * TET_VOLUME)
+    assert m.vol.sum() == pytest.approx(TET_VOLUME, rel=1e-13)
+
+
+def test_tet_regular_cell_closed_forms():
+    """k = 1: one regular tetrahedron of edge s = 5 sqrt(8/3); every dihedral
+    angle is arccos(1/3), so every edge has alpha = s / (6 sqrt 8) and every
+    vertex |V| = 3 shares of alpha s^2 / 6 = |T| / 4."""
+    x, t = meshes.tetrahedron(1)
+    m = oracle.Mesh.simplices(x, t, mu=0.0)
+    s = 5 * np.sqrt(8 / 3)
+    np.testing.assert_allclose(m.alpha, s / (6 * np.sqrt(8)), rtol=1e-13)
+    np.testing.assert_allclose(m.vol, TET_VOLUME / 4, rtol=1e-13)
+
+
+def test_tet_dipole_links():
+    """The closed-form link phases of mu A_d (x0 = (0, 0, 6), m = e_z) on a
+    tetrahedron mesh against adaptive quadrature of the line integral."""
+    from scipy.integrate import quad
+    x, t = meshes.tetrahedron(3)
+    mu = 0.9
+    m = oracle.Mesh.simplices(x, t, mu=mu, dipole=DIPOLE_3D)
+    mm, x0 = np.asarray(DIPOLE_3D[0]), np.asarray(DIPOLE_3D[1])
+    phases = -np.angle(m.U)
+    for q in range(m.ne):
+        xk, xj = m.x[m.ek[q]], m.x[m.ej[q]]
+        e = xj - xk
+
+        def f(s_):
+            r = xk + s_ * e - x0
+            return e @ np.cross(mm, r) / np.linalg.norm(r) ** 3
+        ref = mu * quad(f, 0.0, 1.0, epsabs=1e-17, epsrel=1e-13, limit=200)[0]
+        assert phases[q] == pytest.approx(ref, rel=1e-11, abs=1e-15)
+
+
+@pytest.mark.parametrize("pot", ["Az", "Ad"])
+@pytest.mark.parametrize("mesh", TETS, ids=TET_IDS)
+def test_tet_operators(mesh, pot):
+    """As on triangles: K-hat Hermitian, positive definite in a field and
+    with constants in its kernel at A = 0; J the derivative of GL, self-adjoint
+    in <.,.>_R, with J(psi)(i psi) = i GL(psi); gauge covariance."""
+    _, x, t = mesh
+    kw = dict(mu=0.8, dipole=DIPOLE_3D) if pot == "Ad" else dict(mu=0.8)
+    m = oracle.Mesh.simplices(x, t, **kw)
+    K = m.khat.toarray()
+    assert np.abs(K - K.conj().T).max() == 0.0
+    assert np.linalg.eigvalsh(K).min() > 0
+    m0 = oracle.Mesh.simplices(x, t, mu=0.0)
+    np.testing.assert_allclose(m0.khat @ np.ones(m0.n), 0.0, atol=1e-12)
+    psi = inputs.random_complex(m.n, seed=51)
+    phi = inputs.random_complex(m.n, seed=52)
+    chi = inputs.random_complex(m.n, seed=53)
+    eps = 1e-6
+    fd = (m.gl(psi + eps * phi) - m.gl(psi - eps * phi)) / (2 * eps)
+    J = m.jac(psi, phi)
+    assert np.abs(fd - J).max() < 1e-7 * np.abs(J).max()
+    assert m.inner(chi, m.jac(psi, phi)) == pytest.approx(m.inner(m.jac(psi, chi), phi), rel=1e-12, abs=1e-12)
+    np.testing.assert_allclose(m.jac(psi, 1j * psi), 1j * m.gl(psi), atol=1e-12 * np.abs(m.gl(psi)).max())
+    if pot == "Az":
+        S = np.array([[0.3, -0.2, 0.1], [-0.2, 0.5, 0.0], [0.1, 0.0, -0.4]])
+        amat = oracle.field_matrix(0.8, (0.0, 0.0, 1.0))
+        mg = oracle.Mesh.simplices(x, t, amat=amat + S)
+        g = np.exp(-0.5j * np.einsum("ij,jk,ik->i", m.x, S, m.x))
+        Kp = (g[:, None] * m.khat.toarray()) * g.conj()[None, :]
+        assert np.abs(mg.khat.toarray() - Kp).max() < 1e-12 * np.abs(Kp).max()
+
+
+def test_tet_newton_converges():
+    x, t = meshes.tetrahedron(8)
+    m = oracle.Mesh.simplices(x, t, mu=0.5)
+    psi, info = oracle.newton(m, np.ones(m.n, complex), max_steps=30, max_coarse=16)
+    assert info["converged"] and info["res"][-1] < 1e-10
+    assert m.norm(m.jac(psi, 1j * psi)) < 1e-9 * m.norm(psi)
