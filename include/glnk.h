@@ -102,31 +102,37 @@ typedef struct {
  * OUT_OF_MEMORY, HIP. */
 gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mesh **out);
 
-/* 2D simplicial mesh given by its nodes and triangles (Sec. 3: a Delaunay
- * triangulation dual to the Voronoi tessellation of the nodes; the paper's
- * test domains of Sec. 4.1 beyond the square, e.g. the triangle and the
- * disc).  On the device: alpha_jk = sum over the triangles at edge jk of
- * 1/2 cot of the opposite angle (the Remark on the Corollary's simplex
- * coefficients); |V_j| = sum over the triangles T at j of
- * 1/4 sum_{edges e of T at j} alpha_e^T |e|^2, the part of the Voronoi
- * region V_j inside T when T holds its circumcentre (the shares of a
- * triangle add up to its area for any triangulation); link variables of
+/* Simplicial mesh given by its nodes and cells: triangles in the plane or
+ * tetrahedra in space (Sec. 3: a Delaunay triangulation dual to the Voronoi
+ * tessellation of the nodes; the paper's test domains of Sec. 4.1 beyond the
+ * square and the cube, e.g. the triangle, the disc and the tetrahedron).  On
+ * the device: alpha_jk = sum over the cells at edge jk of the cell's
+ * coefficient of that edge, 1/2 cot of the opposite angle of a triangle (the
+ * Remark on the Corollary's simplex coefficients) or |e'| cot(theta') / 6 for
+ * a tetrahedron (e' the opposite edge, theta' the dihedral angle there: the
+ * solution of the Corollary's system for that cell); |V_j| = sum over the
+ * cells T at j of 1/(2 dim) sum_{edges e of T at j} alpha_e^T |e|^2, the part
+ * of the Voronoi region V_j inside T when T holds its circumcentre (the
+ * shares of a cell add up to its volume for any mesh); link variables of
  * every edge from the exact line integral (linear potentials: the midpoint
- * value; the dipole: closed form).  The fields potential, mu, b_dir,
- * a_matrix, dipole_m and dipole_x0 mean what they mean in gl_grid_desc
- * (2D points r = (x, y, 0)).  xy and triangles are host arrays read during
- * the call and not kept.  Every node must lie in a triangle.  Meshes of this
- * kind support the residual, the Jacobian, gl_precond_* (level 0 coloured
- * like the coarse levels), gl_jacobian_solve, gl_newton_solve, batches and
- * the continuation calls; not gl_mesh_export_links, the LDS-tiled level 0,
- * or the U-Net.  Errors: INVALID_ARGUMENT (n_nodes < 3 or above 2^31 - 2,
- * an index out of range, a degenerate triangle, an edge in more than two
- * triangles, a node in no triangle), OUT_OF_MEMORY, HIP. */
+ * value; the dipole: closed form).  alpha_jk = alpha_kj and
+ * U_kj = conj(U_jk) hold exactly.  The fields potential, mu, b_dir,
+ * a_matrix, dipole_m and dipole_x0 mean what they mean in gl_grid_desc (2D
+ * points r = (x, y, 0)).  x and cells are host arrays read during the call
+ * and not kept.  Every node must lie in a cell.  Meshes of this kind support
+ * the residual, the Jacobian, gl_precond_* (level 0 coloured like the coarse
+ * levels), gl_jacobian_solve, gl_newton_solve, batches and the continuation
+ * calls; not gl_mesh_export_links, the LDS-tiled level 0, or the U-Net.
+ * Errors: INVALID_ARGUMENT (dim not 2 or 3, fewer than dim + 1 nodes or
+ * more than 2^31 - 2, more than (2^31 - 1) / (dim (dim + 1)) cells, an index
+ * out of range, a degenerate cell, a face (triangles: an edge) in more than
+ * two cells, a node in no cell), OUT_OF_MEMORY, HIP. */
 typedef struct {
+    int dim;                   /* 2: triangles, 3: tetrahedra */
     int64_t n_nodes;
-    const double *xy;          /* host, n_nodes x 2 (x, y), row-major */
-    int64_t n_triangles;
-    const int64_t *triangles;  /* host, n_triangles x 3 node indices */
+    const double *x;           /* host, n_nodes x dim coordinates, row-major */
+    int64_t n_cells;
+    const int64_t *cells;      /* host, n_cells x (dim + 1) node indices */
     int potential;             /* 0, 1 or 2, as in gl_grid_desc */
     double mu;
     double b_dir[3];

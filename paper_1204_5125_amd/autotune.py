@@ -54,7 +54,8 @@ def split(info, tiles):
 def _key(mesh, precision, max_coarse):
     import torch
     dev = torch.cuda.get_device_name(0).replace(" ", "_")
-    return f"{dev}|dim{mesh.dim}|{'x'.join(str(n) for n in mesh.shape)}|p{precision}|mc{max_coarse}"
+    shape = 'x'.join(str(n) for n in mesh.shape) if mesh.shape else f"simplicial{mesh.n}"
+    return f"{dev}|dim{mesh.dim}|{shape}|p{precision}|mc{max_coarse}"
 
 
 # Tile sets also change the numeric setup (an explicit sub-cycle is formed at
@@ -121,7 +122,7 @@ def tune(mesh, psi, precision=glnk.GL_FP32, max_coarse=64, cache=None, candidate
     best = min(times, key=times.get)
     times = {t + (0,): v for t, v in times.items()}
     best = best + (0,)
-    if mesh.dim == 2 and not batch:
+    if mesh.dim == 2 and mesh.shape and not batch:  # the LDS-tiled level 0 is for grids
         forms = [best]
         for shape in L0_SHAPES:
             tiled = best[:3] + (shape,)

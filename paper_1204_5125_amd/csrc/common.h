@@ -364,9 +364,9 @@ struct gl_mesh {
     bool per_edge = false;           // links stored per edge (non-linear potential)
     // simplicial meshes: topology (device), per-entry and per-node arrays
     glk::DevBuf<int> s_rp, s_ci;     // node adjacency (CSR without the diagonal)
-    glk::DevBuf<int> s_opp;          // per entry: third vertices of the (up to 2) triangles at the edge, -1 if none
-    glk::DevBuf<int> s_trp, s_tv;    // per node: (other vertex a, other vertex b) of each triangle at the node
-    glk::DevBuf<double2> s_xy;       // node coordinates
+    glk::DevBuf<int> s_erp, s_eo;    // per entry: its cells' other vertices (2D: one and -1; 3D: the opposite edge)
+    glk::DevBuf<int> s_trp, s_tv;    // per node: the dim other vertices of each cell at the node
+    glk::DevBuf<double> s_x;         // node coordinates (x, y, z), z = 0 in 2D
     glk::DevBuf<double> s_alpha, s_phi, s_ks64, s_vol64;
     glk::DevBuf<float> s_ks32, s_vol32;
     glk::DevBuf<double2> s_kw64;

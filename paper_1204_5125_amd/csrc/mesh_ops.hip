@@ -8,6 +8,7 @@
 #include <mutex>
 
 #include <algorithm>
+#include <array>
 #include "amg.h"
 #include "stencil.h"
 
@@ -159,71 +160,109 @@ __device__ __forceinline__ double dipole_phase_edge(const Dipole &D, const doubl
 }
 
 // ------------------------------------------------- simplicial meshes ---
-// 1/2 cot of the angle at o between the edges o -> p and o -> q
-__device__ __forceinline__ double half_cot_at(double2 o, double2 p, double2 q)
+struct P3 {
+    double x, y, z;
+};
+
+__device__ __forceinline__ P3 node_at(const double *__restrict__ x, int i)
 {
-    const double ux = p.x - o.x, uy = p.y - o.y, vx = q.x - o.x, vy = q.y - o.y;
-    return 0.5 * (ux * vx + uy * vy) / fabs(ux * vy - uy * vx);
+    return P3{x[3 * i], x[3 * i + 1], x[3 * i + 2]};
 }
 
-// Per adjacency entry (row j, column k): alpha_jk, the sum over the (one or
-// two) triangles at the edge of 1/2 cot of the opposite angle (the Remark's
-// form of the Corollary), and phi_jk = int_{x_k}^{x_j} A_1 . dl, the link
-// phase at unit field strength (linear A_1 = M r: exact at the midpoint;
-// the dipole: dipole_phase_edge).
-__global__ __launch_bounds__(kBlock) void k_simp_edges(int n, const int *__restrict__ rp,
-                                                       const int *__restrict__ ci, const int *__restrict__ opp,
-                                                       const double2 *__restrict__ xy, int dipole, Potential pot,
-                                                       Dipole D, double *__restrict__ alpha,
-                                                       double *__restrict__ phi)
+__device__ __forceinline__ P3 sub(P3 a, P3 b) { return P3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double dot(P3 a, P3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ P3 cross(P3 a, P3 b)
+{
+    return P3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// Triangle: 1/2 cot of the angle at o between the edges o -> p and o -> q
+// (the Remark's edge coefficient of the edge pq in that triangle).
+__device__ __forceinline__ double half_cot_at(P3 o, P3 p, P3 q)
+{
+    const P3 u = sub(p, o), v = sub(q, o);
+    return 0.5 * dot(u, v) / fabs(u.x * v.y - u.y * v.x);
+}
+
+// Tetrahedron (p, q, u, v): the coefficient of the edge uv in it,
+// |pq| cot(theta_pq) / 6 with theta_pq the dihedral angle at the opposite
+// edge pq.  With n_u = (q - p) x (u - p) and n_v = (q - p) x (v - p),
+// cot theta = n_u . n_v / |n_u x n_v| and |n_u x n_v| = |pq| |det(q - p,
+// u - p, v - p)|, so the coefficient is n_u . n_v / (6 |det|).
+__device__ __forceinline__ double dihedral_coef(P3 p, P3 q, P3 u, P3 v)
+{
+    const P3 e = sub(q, p), a = sub(u, p), b = sub(v, p);
+    return dot(cross(e, a), cross(e, b)) / (6.0 * fabs(dot(e, cross(a, b))));
+}
+
+// Per adjacency entry (row j, column k): alpha_jk, the sum over the cells at
+// the edge of its coefficient there (triangles: 1/2 cot of the opposite
+// angle; tetrahedra: the dihedral form above; both the Corollary's
+// coefficients), and phi_jk = int_{x_k}^{x_j} A_1 . dl, the link phase at
+// unit field strength (linear A_1 = M r: exact at the midpoint; the dipole:
+// dipole_phase_edge).  Both entries of an edge evaluate the same expressions
+// with the lower-numbered node first, so alpha_jk = alpha_kj and
+// phi_jk = -phi_kj hold exactly (K-hat stays exactly Hermitian whatever the
+// rounding of the contracted products).
+__global__ __launch_bounds__(kBlock) void k_simp_edges(int n, int dim, const int *__restrict__ rp,
+                                                       const int *__restrict__ ci, const int *__restrict__ erp,
+                                                       const int *__restrict__ eo, const double *__restrict__ x,
+                                                       int dipole, Potential pot, Dipole D,
+                                                       double *__restrict__ alpha, double *__restrict__ phi)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
-    const double2 xj = xy[j];
     for (int p = rp[j]; p < rp[j + 1]; ++p) {
         const int k = ci[p];
-        const double2 xk = xy[k];
+        const P3 lo = node_at(x, min(j, k)), hi = node_at(x, max(j, k));
         double al = 0.0;
-        for (int t = 0; t < 2; ++t) {
-            const int o = opp[2 * p + t];
-            if (o >= 0) al += half_cot_at(xy[o], xj, xk);
-        }
+        for (int t = erp[p]; t < erp[p + 1]; ++t)
+            al += dim == 2 ? half_cot_at(node_at(x, eo[2 * t]), lo, hi)
+                           : dihedral_coef(node_at(x, eo[2 * t]), node_at(x, eo[2 * t + 1]), lo, hi);
         alpha[p] = al;
-        double ph;
+        // the phase from lo to hi
+        const double a3[3] = {lo.x, lo.y, lo.z}, b3[3] = {hi.x, hi.y, hi.z};
+        double ph = 0.0;
         if (dipole) {
-            const double a3[3] = {xk.x, xk.y, 0.0}, b3[3] = {xj.x, xj.y, 0.0};
             ph = dipole_phase_edge(D, a3, b3);
         } else {
-            const double mid[3] = {0.5 * (xj.x + xk.x), 0.5 * (xj.y + xk.y), 0.0};
-            const double e[3] = {xj.x - xk.x, xj.y - xk.y, 0.0};
-            ph = 0.0;
+            const double mid[3] = {0.5 * (a3[0] + b3[0]), 0.5 * (a3[1] + b3[1]), 0.5 * (a3[2] + b3[2])};
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                ph += e[a] * (pot.m[3 * a] * mid[0] + pot.m[3 * a + 1] * mid[1] + pot.m[3 * a + 2] * mid[2]);
+                ph += (b3[a] - a3[a]) * (pot.m[3 * a] * mid[0] + pot.m[3 * a + 1] * mid[1] + pot.m[3 * a + 2] * mid[2]);
         }
-        phi[p] = ph;
+        phi[p] = j > k ? ph : -ph;
     }
 }
 
 // Per node: K-hat_jj = sum of alpha over its edges, and |V_j| = sum over its
-// triangles (other vertices a, b) of 1/4 (alpha_ja^T |x_j - x_a|^2 +
-// alpha_jb^T |x_j - x_b|^2), alpha^T the triangle's own 1/2 cot terms.
-__global__ __launch_bounds__(kBlock) void k_simp_nodes(int n, const int *__restrict__ rp,
+// cells T and the edges e of T at j of 1/(2 dim) alpha_e^T |e|^2, alpha_e^T
+// the cell's own coefficient of e (triangle: others a, b; tetrahedron:
+// others a, b, c, the edge ja opposite bc and so on).
+__global__ __launch_bounds__(kBlock) void k_simp_nodes(int n, int dim, const int *__restrict__ rp,
                                                        const double *__restrict__ alpha, const int *__restrict__ trp,
-                                                       const int *__restrict__ tv, const double2 *__restrict__ xy,
+                                                       const int *__restrict__ tv, const double *__restrict__ x,
                                                        double *ks64, float *ks32, double *vol64, float *vol32)
 {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= n) return;
     double ks = 0.0;
     for (int p = rp[j]; p < rp[j + 1]; ++p) ks += alpha[p];
-    const double2 xj = xy[j];
+    const P3 xj = node_at(x, j);
     double v = 0.0;
     for (int q = trp[j]; q < trp[j + 1]; ++q) {
-        const double2 xa = xy[tv[2 * q]], xb = xy[tv[2 * q + 1]];
-        const double la = (xj.x - xa.x) * (xj.x - xa.x) + (xj.y - xa.y) * (xj.y - xa.y);
-        const double lb = (xj.x - xb.x) * (xj.x - xb.x) + (xj.y - xb.y) * (xj.y - xb.y);
-        v += 0.25 * (half_cot_at(xb, xj, xa) * la + half_cot_at(xa, xj, xb) * lb);
+        if (dim == 2) {
+            const P3 xa = node_at(x, tv[2 * q]), xb = node_at(x, tv[2 * q + 1]);
+            const P3 da = sub(xj, xa), db = sub(xj, xb);
+            v += 0.25 * (half_cot_at(xb, xj, xa) * dot(da, da) + half_cot_at(xa, xj, xb) * dot(db, db));
+        } else {
+            const P3 o[3] = {node_at(x, tv[3 * q]), node_at(x, tv[3 * q + 1]), node_at(x, tv[3 * q + 2])};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const P3 d = sub(xj, o[a]);
+                v += dihedral_coef(o[(a + 1) % 3], o[(a + 2) % 3], xj, o[a]) * dot(d, d) / 6.0;
+            }
+        }
     }
     ks64[j] = ks;
     ks32[j] = (float)ks;
@@ -231,19 +270,25 @@ __global__ __launch_bounds__(kBlock) void k_simp_nodes(int n, const int *__restr
     vol32[j] = (float)v;
 }
 
-// kw_jk = alpha_jk U_jk, U_jk = exp(-i mu phi_jk)
-__global__ __launch_bounds__(kBlock) void k_simp_links(int nnz, double mu, const double *__restrict__ alpha,
+// kw_jk = alpha_jk U_jk, U_jk = exp(-i mu phi_jk), per row j; the sine and
+// cosine are taken of the edge's phase from its lower-numbered node, so
+// U_kj = conj(U_jk) exactly.
+__global__ __launch_bounds__(kBlock) void k_simp_links(int n, const int *__restrict__ rp, const int *__restrict__ ci,
+                                                       double mu, const double *__restrict__ alpha,
                                                        const double *__restrict__ phi, double2 *__restrict__ kw64,
                                                        float2 *__restrict__ kw32)
 {
-    const int p = blockIdx.x * kBlock + threadIdx.x;
-    if (p >= nnz) return;
-    double sn, cs;
-    sincos(mu * phi[p], &sn, &cs);
-    const double a = alpha[p];
-    const double2 w = make_double2(a * cs, -a * sn);
-    kw64[p] = w;
-    kw32[p] = make_float2((float)w.x, (float)w.y);
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    for (int p = rp[j]; p < rp[j + 1]; ++p) {
+        const bool up = j > ci[p];
+        double sn, cs;
+        sincos(mu * (up ? phi[p] : -phi[p]), &sn, &cs);
+        const double a = alpha[p];
+        const double2 w = make_double2(a * cs, up ? -(a * sn) : a * sn);
+        kw64[p] = w;
+        kw32[p] = make_float2((float)w.x, (float)w.y);
+    }
 }
 
 template <int DIM>
@@ -304,9 +349,9 @@ static void launch_links(gl_mesh *m, hipStream_t s)
     if (m->g.simplicial) {
         // the matrix potential carries its strength in phi
         const double mu = m->desc.potential == 1 ? 1.0 : m->desc.mu;
-        const int nnz = m->g.rp ? (int)m->s_ci.count : 0;
-        k_simp_links<<<blocks_for(nnz), kBlock, 0, s>>>(nnz, mu, m->s_alpha.get(), m->s_phi.get(), m->s_kw64.get(),
-                                                       m->s_kw32.get());
+        const int n = m->g.n;
+        k_simp_links<<<blocks_for(n), kBlock, 0, s>>>(n, m->s_rp.get(), m->s_ci.get(), mu, m->s_alpha.get(),
+                                                     m->s_phi.get(), m->s_kw64.get(), m->s_kw32.get());
         GLK_CHECK_LAUNCH();
         return;
     }
@@ -727,12 +772,15 @@ gl_status gl_mesh_create_grid(const gl_grid_desc *desc, gl_stream stream, gl_mes
 gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream stream, gl_mesh **out)
 {
     return guarded([&] {
-        if (!desc || !out || !desc->xy || !desc->triangles)
+        if (!desc || !out || !desc->x || !desc->cells)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: NULL argument");
         *out = nullptr;
-        const int64_t n = desc->n_nodes, nt = desc->n_triangles;
-        if (n < 3 || n > ((int64_t)1 << 31) - 2 || nt < 1 || nt > ((int64_t)1 << 29))
-            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: node or triangle count out of range");
+        const int dim = desc->dim, nv = dim + 1;
+        if (dim != 2 && dim != 3) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: dim must be 2 or 3");
+        const int64_t n = desc->n_nodes, nc = desc->n_cells;
+        // every (cell, ordered vertex pair) is an int-indexed incidence
+        if (n < nv || n > ((int64_t)1 << 31) - 2 || nc < 1 || nc > ((int64_t)1 << 31) || nc * nv * dim > ((int64_t)1 << 31) - 1)
+            fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: node or cell count out of range");
         if (desc->potential < 0 || desc->potential > 2)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: potential must be 0, 1 or 2");
         if (!std::isfinite(desc->mu)) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: mu");
@@ -747,62 +795,94 @@ gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream st
                 !std::isfinite(mm[0] + mm[1] + mm[2]))
                 fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: dipole moment or position");
         }
-        const double *xy = desc->xy;
-        const int64_t *tri = desc->triangles;
-        for (int64_t i = 0; i < 2 * n; ++i)
-            if (!std::isfinite(xy[i])) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: coordinates");
-        // topology on the host: directed edge entries (row, column, third vertex)
+        const int64_t *cell = desc->cells;
+        std::vector<double> pts((size_t)3 * n, 0.0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int c = 0; c < dim; ++c) {
+                const double v = desc->x[dim * i + c];
+                if (!std::isfinite(v)) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: coordinates");
+                pts[(size_t)(3 * i + c)] = v;
+            }
+        // topology on the host: directed edge entries (row, column, the
+        // cell's other vertices: the third one of a triangle, the opposite
+        // edge of a tetrahedron), and the faces to check that no face lies in
+        // more than two cells
         struct Ent {
-            int r, c, o;
+            int r, c, o1, o2;
         };
         std::vector<Ent> ents;
-        ents.reserve((size_t)6 * nt);
+        ents.reserve((size_t)(nc * nv * dim));
+        std::vector<std::array<int, 3>> faces;
+        faces.reserve((size_t)(nc * nv));
         std::vector<int> tdeg((size_t)n, 0);
-        for (int64_t t = 0; t < nt; ++t) {
-            int v[3];
-            for (int e = 0; e < 3; ++e) {
-                const int64_t x = tri[3 * t + e];
+        for (int64_t t = 0; t < nc; ++t) {
+            int v[4];
+            for (int e = 0; e < nv; ++e) {
+                const int64_t x = cell[nv * t + e];
                 if (x < 0 || x >= n) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: node index out of range");
                 v[e] = (int)x;
             }
-            const double ux = xy[2 * v[1]] - xy[2 * v[0]], uy = xy[2 * v[1] + 1] - xy[2 * v[0] + 1];
-            const double wx = xy[2 * v[2]] - xy[2 * v[0]], wy = xy[2 * v[2] + 1] - xy[2 * v[0] + 1];
-            if (!(std::fabs(ux * wy - uy * wx) > 0.0))
-                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: degenerate triangle");
-            for (int e = 0; e < 3; ++e) {
-                const int a = v[e], b = v[(e + 1) % 3], o = v[(e + 2) % 3];
-                ents.push_back({a, b, o});
-                ents.push_back({b, a, o});
-                ++tdeg[(size_t)v[e]];
+            double u[3][3];
+            for (int e = 0; e < dim; ++e)
+                for (int c = 0; c < 3; ++c) u[e][c] = pts[(size_t)(3 * v[e + 1] + c)] - pts[(size_t)(3 * v[0] + c)];
+            const double det = dim == 2 ? u[0][0] * u[1][1] - u[0][1] * u[1][0]
+                                        : u[0][0] * (u[1][1] * u[2][2] - u[1][2] * u[2][1]) -
+                                              u[0][1] * (u[1][0] * u[2][2] - u[1][2] * u[2][0]) +
+                                              u[0][2] * (u[1][0] * u[2][1] - u[1][1] * u[2][0]);
+            if (!(std::fabs(det) > 0.0)) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: degenerate cell");
+            for (int a = 0; a < nv; ++a) {
+                ++tdeg[(size_t)v[a]];
+                std::array<int, 3> f{-1, -1, -1};
+                for (int b = 0, q = 0; b < nv; ++b)
+                    if (b != a) f[(size_t)q++] = v[b];
+                std::sort(f.begin(), f.begin() + dim);
+                faces.push_back(f);
+                for (int b = 0; b < nv; ++b) {
+                    if (b == a) continue;
+                    int o[2] = {-1, -1};
+                    for (int c = 0, q = 0; c < nv; ++c)
+                        if (c != a && c != b) o[q++] = v[c];
+                    ents.push_back({v[a], v[b], o[0], o[1]});
+                }
             }
         }
+        std::sort(faces.begin(), faces.end());
+        for (size_t q = 0; q + 2 < faces.size(); ++q)
+            if (faces[q] == faces[q + 2])
+                fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: a face in more than two cells");
+        faces = {};
         std::sort(ents.begin(), ents.end(), [](const Ent &x, const Ent &y) {
-            return x.r != y.r ? x.r < y.r : (x.c != y.c ? x.c < y.c : x.o < y.o);
+            if (x.r != y.r) return x.r < y.r;
+            if (x.c != y.c) return x.c < y.c;
+            return x.o1 != y.o1 ? x.o1 < y.o1 : x.o2 < y.o2;
         });
-        std::vector<int> rp((size_t)n + 1, 0), ci, opp;
+        std::vector<int> rp((size_t)n + 1, 0), ci, erp(1, 0), eo;
+        eo.reserve((size_t)2 * ents.size());
         for (size_t q = 0; q < ents.size();) {
             size_t e = q;
-            while (e < ents.size() && ents[e].r == ents[q].r && ents[e].c == ents[q].c) ++e;
-            if (e - q > 2) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: an edge in more than two triangles");
+            while (e < ents.size() && ents[e].r == ents[q].r && ents[e].c == ents[q].c) {
+                eo.push_back(ents[e].o1);
+                eo.push_back(ents[e].o2);
+                ++e;
+            }
             ci.push_back(ents[q].c);
-            opp.push_back(ents[q].o);
-            opp.push_back(e - q == 2 ? ents[q + 1].o : -1);
+            erp.push_back((int)(eo.size() / 2));
             ++rp[(size_t)ents[q].r + 1];
             q = e;
         }
+        ents = {};
         for (int64_t i = 0; i < n; ++i) {
-            if (tdeg[(size_t)i] == 0) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: a node in no triangle");
+            if (tdeg[(size_t)i] == 0) fail(GL_ERR_INVALID_ARGUMENT, "gl_mesh_create_simplicial: a node in no cell");
             rp[(size_t)i + 1] += rp[(size_t)i];
         }
-        // per node: the other two vertices of each of its triangles, in triangle order
-        std::vector<int> trp((size_t)n + 1, 0), tv((size_t)6 * nt), fill((size_t)n, 0);
+        // per node: the other dim vertices of each of its cells, in cell order
+        std::vector<int> trp((size_t)n + 1, 0), tv((size_t)(nc * nv * dim)), fill((size_t)n, 0);
         for (int64_t i = 0; i < n; ++i) trp[(size_t)i + 1] = trp[(size_t)i] + tdeg[(size_t)i];
-        for (int64_t t = 0; t < nt; ++t)
-            for (int e = 0; e < 3; ++e) {
-                const int j = (int)tri[3 * t + e];
+        for (int64_t t = 0; t < nc; ++t)
+            for (int e = 0; e < nv; ++e) {
+                const int j = (int)cell[nv * t + e];
                 const size_t q = (size_t)trp[j] + fill[j]++;
-                tv[2 * q] = (int)tri[3 * t + (e + 1) % 3];
-                tv[2 * q + 1] = (int)tri[3 * t + (e + 2) % 3];
+                for (int b = 1; b < nv; ++b) tv[(size_t)dim * q + b - 1] = (int)cell[nv * t + (e + b) % nv];
             }
         const int nnz = (int)ci.size();
         hipStream_t s = as_stream(stream);
@@ -810,7 +890,7 @@ gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream st
         try {
             gl_grid_desc &d = m->desc;
             std::memset(&d, 0, sizeof(d));
-            d.dim = 2;
+            d.dim = dim;
             d.n_axis[0] = n;
             d.n_axis[1] = d.n_axis[2] = 1;
             d.potential = desc->potential;
@@ -821,7 +901,7 @@ gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream st
                 d.dipole_x0[a] = desc->dipole_x0[a];
             }
             std::memcpy(d.a_matrix, desc->a_matrix, sizeof(d.a_matrix));
-            m->g.dim = 2;
+            m->g.dim = dim;
             m->g.n = (int)n;
             m->g.N[0] = (int)n;
             m->g.N[1] = m->g.N[2] = 1;
@@ -838,12 +918,11 @@ gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream st
             };
             upload(m->s_rp, rp);
             upload(m->s_ci, ci);
-            upload(m->s_opp, opp);
+            upload(m->s_erp, erp);
+            upload(m->s_eo, eo);
             upload(m->s_trp, trp);
             upload(m->s_tv, tv);
-            std::vector<double2> pts((size_t)n);
-            for (int64_t i = 0; i < n; ++i) pts[(size_t)i] = make_double2(xy[2 * i], xy[2 * i + 1]);
-            upload(m->s_xy, pts);
+            upload(m->s_x, pts);
             m->s_alpha.alloc(std::max(1, nnz));
             m->s_phi.alloc(std::max(1, nnz));
             m->s_kw64.alloc(std::max(1, nnz));
@@ -886,10 +965,11 @@ gl_status gl_mesh_create_simplicial(const gl_simplicial_desc *desc, gl_stream st
                 D.lo[a] = 0.0;
             }
             const int nb = blocks_for(n);
-            k_simp_edges<<<nb, kBlock, 0, s>>>((int)n, m->s_rp.get(), m->s_ci.get(), m->s_opp.get(), m->s_xy.get(),
-                                               d.potential == 2, pot, D, m->s_alpha.get(), m->s_phi.get());
-            k_simp_nodes<<<nb, kBlock, 0, s>>>((int)n, m->s_rp.get(), m->s_alpha.get(), m->s_trp.get(),
-                                               m->s_tv.get(), m->s_xy.get(), m->s_ks64.get(), m->s_ks32.get(),
+            k_simp_edges<<<nb, kBlock, 0, s>>>((int)n, dim, m->s_rp.get(), m->s_ci.get(), m->s_erp.get(),
+                                               m->s_eo.get(), m->s_x.get(), d.potential == 2, pot, D,
+                                               m->s_alpha.get(), m->s_phi.get());
+            k_simp_nodes<<<nb, kBlock, 0, s>>>((int)n, dim, m->s_rp.get(), m->s_alpha.get(), m->s_trp.get(),
+                                               m->s_tv.get(), m->s_x.get(), m->s_ks64.get(), m->s_ks32.get(),
                                                m->s_vol64.get(), m->s_vol32.get());
             GLK_CHECK_LAUNCH();
             launch_links(m, s);

@@ -52,8 +52,8 @@ class GridDesc(C.Structure):
 
 
 class SimplicialDesc(C.Structure):
-    _fields_ = [("n_nodes", C.c_int64), ("xy", C.c_void_p), ("n_triangles", C.c_int64),
-                ("triangles", C.c_void_p), ("potential", C.c_int), ("mu", C.c_double),
+    _fields_ = [("dim", C.c_int), ("n_nodes", C.c_int64), ("x", C.c_void_p), ("n_cells", C.c_int64),
+                ("cells", C.c_void_p), ("potential", C.c_int), ("mu", C.c_double),
                 ("b_dir", C.c_double * 3), ("a_matrix", C.c_double * 9), ("dipole_m", C.c_double * 3),
                 ("dipole_x0", C.c_double * 3)]
 
@@ -219,16 +219,18 @@ class Mesh:
         self.n = nn.value
 
     @classmethod
-    def simplicial(cls, xy, triangles, mu=0.0, b_dir=(0.0, 0.0, 1.0), a_matrix=None, dipole=None, stream=None):
-        """gl_mesh_create_simplicial: a 2D mesh of nodes xy (n x 2) and
-        triangles (m x 3 node indices); the potential as for the grid."""
-        xy = np.ascontiguousarray(xy, dtype=np.float64)
-        tri = np.ascontiguousarray(triangles, dtype=np.int64)
-        if xy.ndim != 2 or xy.shape[1] != 2 or tri.ndim != 2 or tri.shape[1] != 3:
-            raise ValueError("xy must be n x 2 and triangles m x 3")
+    def simplicial(cls, x, cells, mu=0.0, b_dir=(0.0, 0.0, 1.0), a_matrix=None, dipole=None, stream=None):
+        """gl_mesh_create_simplicial: nodes x (n x 2 or n x 3) and cells
+        (m x 3 triangles or m x 4 tetrahedra, node indices); the potential as
+        for the grid."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        if x.ndim != 2 or x.shape[1] not in (2, 3) or cells.ndim != 2 or cells.shape[1] != x.shape[1] + 1:
+            raise ValueError("x must be n x 2 with triangles m x 3, or n x 3 with tetrahedra m x 4")
         d = SimplicialDesc()
-        d.n_nodes, d.n_triangles = len(xy), len(tri)
-        d.xy, d.triangles = xy.ctypes.data, tri.ctypes.data
+        d.dim = x.shape[1]
+        d.n_nodes, d.n_cells = len(x), len(cells)
+        d.x, d.cells = x.ctypes.data, cells.ctypes.data
         d.mu = mu
         for a in range(3):
             d.b_dir[a] = b_dir[a]
@@ -246,10 +248,10 @@ class Mesh:
                "gl_mesh_create_simplicial")
         self = cls.__new__(cls)
         self._h = h
-        self.dim = 2
+        self.dim = x.shape[1]
         self.shape = None
         self.side = None
-        self.n = len(xy)
+        self.n = len(x)
         return self
 
     @property

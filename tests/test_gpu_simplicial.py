@@ -1,15 +1,17 @@
-"""The GPU path on simplicial meshes of the paper's 2D test domains (Sec. 4.1:
-the triangle and the disc of circumradius 5; paper_1204_5125_amd/meshes.py)
-against the oracle, through the C-ABI: the operators (FP64 within 1e-12),
+"""The GPU path on simplicial meshes of the paper's test domains (Sec. 4.1:
+the triangle, the disc and the tetrahedron of circumradius 5;
+paper_1204_5125_amd/meshes.py) against the oracle, through the C-ABI: the operators (FP64 within 1e-12),
 the hierarchy (integer arrays bit-exact, values within 1e-12; level 0
 coloured like the coarse levels), the V-cycle (FP64 1e-11, FP32 and mixed
 1e-5, k = 3, R_inf), MINRES iterates (1e-12) and counts (within 1), Newton
 (states within 1e-10 after phase alignment), the deflated solve, the
 parameter derivative, batches bitwise equal to single solves, and the
 errors the call reports.  Meshes span several 256-node tiles with ragged
-tails; uniform field A_z and the dipole A_d (m = e_z, x0 = (0, 0, 1))."""
+tails; uniform field A_z and the dipole A_d (m = e_z, x0 = (0, 0, 1) in 2D,
+(0, 0, 6) in 3D).  Level 0 is checked to be exactly Hermitian."""
 import numpy as np
 import pytest
+import scipy.sparse as sp
 
 import oracle
 from oracle import arclength as oal
@@ -20,6 +22,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 DIPOLE_2D = ((0.0, 0.0, 1.0), (0.0, 0.0, 1.0))
+DIPOLE_3D = ((0.0, 0.0, 1.0), (0.0, 0.0, 6.0))
 
 
 def jittered_disc(k, seed):
@@ -32,7 +35,18 @@ def jittered_disc(k, seed):
     return xy, tri
 
 
-MESHES = {"tri-24": meshes.triangle(24), "circ-14": meshes.disc(14), "circ-jitter-9": jittered_disc(9, 5)}
+def jittered_tet(k, seed):
+    x, t = meshes.tetrahedron(k)
+    rng = np.random.default_rng(seed)
+    B = np.linalg.solve(np.vstack([meshes.TET_VERTICES.T, np.ones(4)]), np.vstack([x.T, np.ones(len(x))]))
+    inner = np.all(B > 1e-9, axis=0)
+    x = x.copy()
+    x[inner] += rng.uniform(-1, 1, (inner.sum(), 3)) * 0.08 * 5 * np.sqrt(8 / 3) / k
+    return x, t
+
+
+MESHES = {"tri-24": meshes.triangle(24), "circ-14": meshes.disc(14), "circ-jitter-9": jittered_disc(9, 5),
+          "tet-12": meshes.tetrahedron(12), "tet-jitter-9": jittered_tet(9, 6)}
 CASES = [(name, pot) for name in MESHES for pot in ("Az", "Ad")]
 IDS = [f"{n}-{p}" for n, p in CASES]
 
@@ -48,9 +62,15 @@ def glnk():
 
 def make_pair(glnk, case, mu=0.8):
     name, pot = case
-    xy, tri = MESHES[name]
-    kw = dict(dipole=DIPOLE_2D) if pot == "Ad" else {}
-    return glnk.Mesh.simplicial(xy, tri, mu=mu, **kw), oracle.Mesh.triangles(xy, tri, mu=mu, **kw)
+    x, cells = MESHES[name]
+    kw = dipole_kw(x, pot)
+    return glnk.Mesh.simplicial(x, cells, mu=mu, **kw), oracle.Mesh.simplices(x, cells, mu=mu, **kw)
+
+
+def dipole_kw(x, pot):
+    if pot != "Ad":
+        return {}
+    return dict(dipole=DIPOLE_2D if x.shape[1] == 2 else DIPOLE_3D)
 
 
 def dev(x):
@@ -81,8 +101,8 @@ def test_operators(glnk, case):
     assert relerr(host(out), mo.jac(psi, phi)) < 1e-12
     # the field can be changed in place
     mg.set_field(1.3)
-    kw = dict(dipole=DIPOLE_2D) if case[1] == "Ad" else {}
-    m2 = oracle.Mesh.triangles(*MESHES[case[0]], mu=1.3, **kw)
+    kw = dipole_kw(MESHES[case[0]][0], case[1])
+    m2 = oracle.Mesh.simplices(*MESHES[case[0]], mu=1.3, **kw)
     glnk.gl_residual(mg, dev(psi), out)
     assert relerr(host(out), m2.gl(psi)) < 1e-12
 
@@ -95,7 +115,10 @@ def test_hierarchy_bit_exact(glnk, case):
     amg = oracle.Amg.for_state(mo, psi, max_coarse=16)
     info = pre.info()
     assert info["nlev"] == amg.nlev >= 2
-    assert info["ncolors"][0] >= 3  # no red-black parity on triangles
+    assert info["ncolors"][0] >= 3  # no red-black parity on triangles or tetrahedra
+    # level 0 exactly Hermitian: both entries of an edge computed alike
+    Ag = sp.csr_matrix((pre.export(0, "A_v"), pre.export(0, "A_ci"), pre.export(0, "A_rp")), shape=(mo.n, mo.n))
+    assert (Ag - Ag.conj().T).count_nonzero() == 0
     for l, L in enumerate(amg.levels):
         assert info["sizes"][l] == L["n"]
         assert np.array_equal(pre.export(l, "color"), L["color"])
@@ -185,28 +208,30 @@ def test_newton_from_psi_one(glnk, case):
     assert all(abs(a - b) <= 1 for a, b in zip(ig["krylov_iters"], idf["krylov_iters"]))
 
 
-def test_parameter_derivative(glnk):
+@pytest.mark.parametrize("name", ["circ-jitter-9", "tet-jitter-9"])
+def test_parameter_derivative(glnk, name):
     """gl_residual_dmu against the oracle's GL_mu (uniform field) and central
     differences in mu (both potentials)."""
-    xy, tri = MESHES["circ-jitter-9"]
+    xy, tri = MESHES[name]
     psi = inputs.random_phase_state(len(xy), seed=8)
     out = torch.empty(len(xy), dtype=torch.complex128, device="cuda")
     mg = glnk.Mesh.simplicial(xy, tri, mu=0.7)
-    mo = oracle.Mesh.triangles(xy, tri, mu=0.7)
+    mo = oracle.Mesh.simplices(xy, tri, mu=0.7)
     glnk.gl_residual_dmu(mg, dev(psi), out)
     assert relerr(host(out), oal.gl_dmu(mo, psi, (0.0, 0.0, 1.0))) < 1e-12
-    for kw in ({}, {"dipole": DIPOLE_2D}):
+    for pot in ("Az", "Ad"):
+        kw = dipole_kw(xy, pot)
         mg = glnk.Mesh.simplicial(xy, tri, mu=0.7, **kw)
         glnk.gl_residual_dmu(mg, dev(psi), out)
         h = 1e-5
-        fd = (oracle.Mesh.triangles(xy, tri, mu=0.7 + h, **kw).gl(psi)
-              - oracle.Mesh.triangles(xy, tri, mu=0.7 - h, **kw).gl(psi)) / (2 * h)
+        fd = (oracle.Mesh.simplices(xy, tri, mu=0.7 + h, **kw).gl(psi)
+              - oracle.Mesh.simplices(xy, tri, mu=0.7 - h, **kw).gl(psi)) / (2 * h)
         assert relerr(host(out), fd) < 1e-8
 
 
 def test_batch_equals_single(glnk):
     ms, p0 = [], []
-    for name, pot in CASES[:4]:
+    for name, pot in CASES[:4] + CASES[-2:]:
         m, _ = make_pair(glnk, (name, pot), mu=0.5)
         ms.append(m)
         p0.append(inputs.random_phase_state(m.n, seed=9))
@@ -245,5 +270,16 @@ def test_errors(glnk):
     with pytest.raises(RuntimeError, match="more than two"):
         glnk.Mesh.simplicial(xy, np.concatenate([tri, tri[:1]]))
     xy2 = np.concatenate([xy, [[9.0, 9.0]]])
-    with pytest.raises(RuntimeError, match="no triangle"):
+    with pytest.raises(RuntimeError, match="no cell"):
         glnk.Mesh.simplicial(xy2, tri)
+    # tetrahedra: a flat cell, a face in three cells
+    x3, t3 = meshes.tetrahedron(3)
+    glnk.Mesh.simplicial(x3, t3, mu=0.5)
+    flat = t3.copy()
+    flat[0, 3] = flat[0, 2]
+    with pytest.raises(RuntimeError, match="degenerate"):
+        glnk.Mesh.simplicial(x3, flat)
+    with pytest.raises(RuntimeError, match="more than two"):
+        glnk.Mesh.simplicial(x3, np.concatenate([t3, t3[:1]]))
+    with pytest.raises(ValueError):
+        glnk.Mesh.simplicial(x3, tri)
