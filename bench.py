@@ -588,8 +588,8 @@ def bench_meshind(args):
     z; 2D squares of side 10 with N = 33 ... 1025 nodes per axis, 3D cubes of
     side 10/sqrt(3) (circumradius 5) with N = 9 ... 129.  Reports the MINRES
     iterations per grid with the FP64 and the FP32 V-cycle; the cube in the
-    dipole potential; and the triangle and disc of circumradius 5 as
-    simplicial meshes (153 to 1.05 M nodes) in both potentials with R_1,
+    dipole potential; and the triangle, disc and tetrahedron of circumradius
+    5 as simplicial meshes (153 to 1.05 M nodes) in both potentials with R_1,
     R_inf and, up to 3000 nodes, no preconditioner."""
     import torch
 
@@ -625,16 +625,20 @@ def bench_meshind(args):
                                           raise_on_fail=False)
         dip_rows.append({"N": n, "nodes": mesh.n, "iterations": info["iterations"], "status": rc})
         log(f"[bench] meshind cube A_d {dip_rows[-1]}")
-    # Fig. 3 protocol on the paper's other 2D domains, the triangle and the
-    # disc of circumradius 5 as simplicial meshes, A_z and A_d (m = e_z at
-    # (0, 0, 1)), mu = 1: R_1, R_inf and (small meshes) no preconditioner
+    # Fig. 3 protocol on the paper's other domains as simplicial meshes: the
+    # triangle and the disc of circumradius 5 (A_d: m = e_z at (0, 0, 1)) and
+    # the tetrahedron (A_d at (0, 0, 6); k = 7 ... 55 give about the paper's
+    # 2n = 406 ... 112580), A_z and A_d, mu = 1: R_1, R_inf and (small
+    # meshes) no preconditioner
     from paper_1204_5125_amd import meshes
     simp_rows = []
-    sizes = {"tri": (16, 32, 64, 128, 256, 512, 1024, 1448), "circ": (8, 16, 32, 64, 128, 256, 512)}
+    sizes = {"tri": (16, 32, 64, 128, 256, 512, 1024, 1448), "circ": (8, 16, 32, 64, 128, 256, 512),
+             "tet": (7, 15, 23, 31, 39, 47, 55, 80, 128)}
     for dom, ks in sizes.items():
+        x0 = (0, 0, 6) if dom == "tet" else (0, 0, 1)
         for k in ks:
             xy, tri = meshes.domain(dom, k)
-            for pot, kw in (("Az", {}), ("Ad", {"dipole": ((0, 0, 1), (0, 0, 1))})):
+            for pot, kw in (("Az", {}), ("Ad", {"dipole": ((0, 0, 1), x0)})):
                 mesh = glnk.Mesh.simplicial(xy, tri, mu=1.0, **kw)
                 ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
                 x = torch.empty_like(ones)
@@ -667,7 +671,11 @@ def bench_meshind(args):
         "iterations_2d_fp64": it2, "iterations_3d_fp64": it3, "grids": rows,
         "cube_dipole_fig3": {"iterations": [r["iterations"] for r in dip_rows], "N": [r["N"] for r in dip_rows],
                              "paper_R1": [6, 22, 29, 31, 31, 32, 32, 31]},
-        "simplicial_2d": simp_rows,
+        "simplicial": simp_rows,
+        "tet_fig3_paper": {"2n": [406, 3018, 9676, 22270, 42748, 71832, 112580],
+                           "Az_R1": [20, 22, 22, 22, 22, 22, 22], "Az_Rinf": [20, 19, 19, 18, 18, 18, 18],
+                           "Ad_R1": [26, 29, 27, 29, 27, 28, 28], "Ad_Rinf": [26, 25, 23, 23, 22, 22, 22],
+                           "unpreconditioned_406": {"Az": 75, "Ad": 91}},
     }
     print(json.dumps(out), flush=True)
 
