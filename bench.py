@@ -588,9 +588,9 @@ def bench_meshind(args):
     z; 2D squares of side 10 with N = 33 ... 1025 nodes per axis, 3D cubes of
     side 10/sqrt(3) (circumradius 5) with N = 9 ... 129.  Reports the MINRES
     iterations per grid with the FP64 and the FP32 V-cycle; the cube in the
-    dipole potential; and the triangle, disc and tetrahedron of circumradius
-    5 as simplicial meshes (153 to 1.05 M nodes) in both potentials with R_1,
-    R_inf and, up to 3000 nodes, no preconditioner."""
+    dipole potential; and the triangle, disc, tetrahedron and ball of
+    circumradius 5 as simplicial meshes (137 to 1.05 M nodes) in both
+    potentials with R_1, R_inf and, up to 3000 nodes, no preconditioner."""
     import torch
 
     from paper_1204_5125_amd import glnk
@@ -626,16 +626,17 @@ def bench_meshind(args):
         dip_rows.append({"N": n, "nodes": mesh.n, "iterations": info["iterations"], "status": rc})
         log(f"[bench] meshind cube A_d {dip_rows[-1]}")
     # Fig. 3 protocol on the paper's other domains as simplicial meshes: the
-    # triangle and the disc of circumradius 5 (A_d: m = e_z at (0, 0, 1)) and
-    # the tetrahedron (A_d at (0, 0, 6); k = 7 ... 55 give about the paper's
-    # 2n = 406 ... 112580), A_z and A_d, mu = 1: R_1, R_inf and (small
-    # meshes) no preconditioner
+    # triangle and the disc of circumradius 5 (A_d: m = e_z at (0, 0, 1)),
+    # the tetrahedron and the ball (A_d at (0, 0, 6); tetrahedron k = 7 ... 55
+    # and ball m = 4 ... 49 give about the paper's 2n = 406 ... 112580 and
+    # 250 ... 273598), A_z and A_d, mu = 1: R_1, R_inf and (small meshes) no
+    # preconditioner
     from paper_1204_5125_amd import meshes
     simp_rows = []
     sizes = {"tri": (16, 32, 64, 128, 256, 512, 1024, 1448), "circ": (8, 16, 32, 64, 128, 256, 512),
-             "tet": (7, 15, 23, 31, 39, 47, 55, 80, 128)}
+             "tet": (7, 15, 23, 31, 39, 47, 55, 80, 128), "ball": (4, 7, 15, 22, 29, 36, 43, 49, 64, 80)}
     for dom, ks in sizes.items():
-        x0 = (0, 0, 6) if dom == "tet" else (0, 0, 1)
+        x0 = (0, 0, 6) if dom in ("tet", "ball") else (0, 0, 1)
         for k in ks:
             xy, tri = meshes.domain(dom, k)
             for pot, kw in (("Az", {}), ("Ad", {"dipole": ((0, 0, 1), x0)})):
@@ -676,6 +677,10 @@ def bench_meshind(args):
                            "Az_R1": [20, 22, 22, 22, 22, 22, 22], "Az_Rinf": [20, 19, 19, 18, 18, 18, 18],
                            "Ad_R1": [26, 29, 27, 29, 27, 28, 28], "Ad_Rinf": [26, 25, 23, 23, 22, 22, 22],
                            "unpreconditioned_406": {"Az": 75, "Ad": 91}},
+        "ball_fig3_paper": {"2n": [250, 1222, 8024, 24248, 54920, 104160, 176708, 273598],
+                            "Az_R1": [3, 20, 19, 19, 19, 18, 18, 18], "Az_Rinf": [3, 18, 17, 16, 15, 14, 14, 14],
+                            "Ad_R1": [6, 37, 34, 34, 32, 34, 32, 32], "Ad_Rinf": [6, 33, 29, 27, 27, 27, 27, 26],
+                            "unpreconditioned": {"Az": [14, 70], "Ad": [15, 122]}},
     }
     print(json.dumps(out), flush=True)
 

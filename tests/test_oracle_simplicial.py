@@ -1,5 +1,5 @@
 """Pins of the oracle on simplicial meshes of the paper's test domains
-(Sec. 3, Sec. 4.1): the triangle, the disc and the tetrahedron of
+(Sec. 3, Sec. 4.1): the triangle, the disc, the tetrahedron and the ball of
 circumradius 5 (paper_1204_5125_amd/meshes.py).
 
 The oracle takes the edge coefficients from the Corollary's system
@@ -217,7 +217,7 @@ def jittered_tet(k, seed):
     return x, t
 
 
-TETS = [("tet", *meshes.tetrahedron(4)), ("tet-jitter", *jittered_tet(5, 7))]
+TETS = [("tet", *meshes.tetrahedron(4)), ("tet-jitter", *jittered_tet(5, 7)), ("ball", *meshes.ball(6))]
 TET_IDS = [m[0] for m in TETS]
 
 
@@ -267,8 +267,9 @@ def test_tet_coefficients_follow_the_dihedral_cotangents(mesh):
     for j, kk, a in zip(m.ej, m.ek, m.alpha):
         e = x[j] - x[kk]
         S += a * np.outer(e, e)
-    np.testing.assert_allclose(S, TET_VOLUME * np.eye(3), atol=1e-11 * TET_VOLUME)
-    assert m.vol.sum() == pytest.approx(TET_VOLUME, rel=1e-13)
+    omega = tet_volumes(x, t).sum()
+    np.testing.assert_allclose(S, omega * np.eye(3), atol=1e-11 * omega)
+    assert m.vol.sum() == pytest.approx(omega, rel=1e-13)
 
 
 def test_tet_regular_cell_closed_forms():
@@ -336,6 +337,55 @@ def test_tet_operators(mesh, pot):
 
 def test_tet_newton_converges():
     x, t = meshes.tetrahedron(8)
+    m = oracle.Mesh.simplices(x, t, mu=0.5)
+    psi, info = oracle.newton(m, np.ones(m.n, complex), max_steps=30, max_coarse=16)
+    assert info["converged"] and info["res"][-1] < 1e-10
+    assert m.norm(m.jac(psi, 1j * psi)) < 1e-9 * m.norm(psi)
+
+
+def test_ball_mesh_and_closed_forms():
+    """The body-centred cubic ball: every cell the same tetrahedron (volume
+    h^3 / 12), no face in more than two cells, the volume within 0.3 % of
+    the ball's from m = 16 on.  In the Corollary's coefficients the lattice's
+    long edges (length h, dihedral angle 90 degrees opposite) get 0 and a
+    short edge (length h sqrt3 / 2) with all six cells around it gets
+    6 (h sqrt3 / 2) cot(60 deg) / 6 = h / 2; a node with all 24 of its cells
+    present has |V| = h^3 / 2, the lattice's Voronoi cell (a truncated
+    octahedron)."""
+    for m in (4, 7, 16):
+        x, t = meshes.ball(m)
+        h = 10.0 / m
+        v = tet_volumes(x, t)
+        np.testing.assert_allclose(v, h ** 3 / 12, rtol=1e-12)
+        faces = {}
+        for c in t:
+            for f in range(4):
+                key = tuple(sorted(np.delete(c, f)))
+                faces[key] = faces.get(key, 0) + 1
+        assert max(faces.values()) <= 2
+        ball = 4 / 3 * np.pi * 125
+        assert abs(v.sum() - ball) < (0.003 if m >= 16 else 0.05) * ball
+        if m == 16:
+            continue
+        mo = oracle.Mesh.simplices(x, t, mu=0.0)
+        L = np.linalg.norm(x[mo.ej] - x[mo.ek], axis=1)
+        long = np.abs(L - h) < 1e-9 * h
+        assert np.all(np.abs(L[~long] - h * np.sqrt(3) / 2) < 1e-9 * h)
+        assert np.all(np.abs(mo.alpha[long]) < 1e-12 * h)
+        assert mo.alpha.min() > -1e-12 * h
+        full = np.bincount(t.ravel(), minlength=len(x)) == 24
+        assert full.sum() > 0
+        np.testing.assert_allclose(mo.vol[full], h ** 3 / 2, rtol=1e-12)
+        inner = ~long & full[mo.ej] & full[mo.ek]
+        assert inner.sum() > 0
+        np.testing.assert_allclose(mo.alpha[inner], h / 2, rtol=1e-12)
+
+
+def test_ball_newton_converges():
+    x, t = meshes.ball(8)
+    m = oracle.Mesh.simplices(x, t, mu=0.5, dipole=DIPOLE_3D)
+    psi, info = oracle.newton(m, np.ones(m.n, complex), max_steps=30, max_coarse=16)
+    assert info["converged"] and info["res"][-1] < 1e-10
     m = oracle.Mesh.simplices(x, t, mu=0.5)
     psi, info = oracle.newton(m, np.ones(m.n, complex), max_steps=30, max_coarse=16)
     assert info["converged"] and info["res"][-1] < 1e-10
