@@ -92,12 +92,15 @@ def lib():
         L.orc_amg_solve.argtypes = [C.POINTER(_Amg), vp, vp, C.c_int]
         L.orc_sgs.argtypes = [C.POINTER(_Level), vp, vp]
         L.orc_minres.argtypes = [C.POINTER(_Mesh), vp, C.POINTER(_Amg), C.c_int, vp, vp,
-                                 C.c_double, C.c_int, vp, C.POINTER(_KInfo)]
+                                 C.c_double, C.c_int, C.c_int, vp, C.POINTER(_KInfo)]
         L.orc_minres_generic.argtypes = [C.c_int64, vp, _OP, vp, _OP, vp, vp, vp, C.c_double,
                                          C.c_int, vp, C.POINTER(_KInfo)]
+        L.orc_minres_reorth_generic.argtypes = [C.c_int64, vp, _OP, vp, _OP, vp, vp, vp, C.c_double,
+                                                C.c_int, C.c_int, vp, C.POINTER(_KInfo)]
         L.orc_minres_deflated.argtypes = L.orc_minres.argtypes
         L.orc_newton.argtypes = [C.POINTER(_Mesh), vp, C.c_double, C.c_int, C.c_int, C.c_double,
-                                 C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_NInfo)]
+                                 C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                 C.POINTER(_NInfo)]
         _lib = L
     return _lib
 
@@ -338,25 +341,27 @@ def _kinfo(ki):
             "eta": ki.eta, "res_true": ki.res_true}
 
 
-def minres(mesh, psi, b, amg=None, cycles=1, rtol=1e-10, max_iter=1000, deflate=False):
+def minres(mesh, psi, b, amg=None, cycles=1, rtol=1e-10, max_iter=1000, deflate=False, reorth=0):
     """MINRES for J(psi) x = b in the D-weighted real product, preconditioned
     by R_k = AMG_k(H, D .) when amg is given; with deflate, on the complement
-    of the gauge mode i psi (orc_minres_deflated).  Returns (x, info, history)."""
+    of the gauge mode i psi (orc_minres_deflated); with reorth > 0, the
+    Krylov basis (at most reorth vectors) stored and reorthogonalised in
+    every step.  Returns (x, info, history)."""
     psi, b = _c128(psi), _c128(b)
     x = np.empty_like(b)
     hist = np.zeros(max_iter + 1)
     ki = _KInfo()
     fn = lib().orc_minres_deflated if deflate else lib().orc_minres
     rc = fn(mesh._p, _ptr(psi), amg._p if amg is not None else None, cycles,
-            _ptr(b), _ptr(x), rtol, max_iter, _ptr(hist), C.byref(ki))
+            _ptr(b), _ptr(x), rtol, max_iter, int(reorth), _ptr(hist), C.byref(ki))
     info = _kinfo(ki)
     info["status"] = rc
     return x, info, hist[:ki.iterations + 1].copy()
 
 
-def minres_generic(w, A, b, minv=None, rtol=1e-10, max_iter=1000):
+def minres_generic(w, A, b, minv=None, rtol=1e-10, max_iter=1000, reorth=0):
     """MINRES for a callable A (self-adjoint in Re sum w conj(u) v) with an
-    optional SPD callable preconditioner minv."""
+    optional SPD callable preconditioner minv; reorth > 0 as in minres."""
     w = np.ascontiguousarray(w, dtype=np.float64)
     b = _c128(b)
     n = b.size
@@ -373,24 +378,29 @@ def minres_generic(w, A, b, minv=None, rtol=1e-10, max_iter=1000):
     x = np.empty_like(b)
     hist = np.zeros(max_iter + 1)
     ki = _KInfo()
-    rc = lib().orc_minres_generic(n, _ptr(w), Acb, None, Mcb, None, _ptr(b), _ptr(x), rtol,
-                                  max_iter, _ptr(hist), C.byref(ki))
+    if reorth > 0:
+        rc = lib().orc_minres_reorth_generic(n, _ptr(w), Acb, None, Mcb, None, _ptr(b), _ptr(x), rtol,
+                                             max_iter, int(reorth), _ptr(hist), C.byref(ki))
+    else:
+        rc = lib().orc_minres_generic(n, _ptr(w), Acb, None, Mcb, None, _ptr(b), _ptr(x), rtol,
+                                      max_iter, _ptr(hist), C.byref(ki))
     info = _kinfo(ki)
     info["status"] = rc
     return x, info, hist[:ki.iterations + 1].copy()
 
 
 def newton(mesh, psi0, tol=1e-10, max_steps=50, fixed_steps=0, krylov_rtol=1e-10,
-           krylov_max_iter=1000, use_amg=True, cycles=1, max_coarse=64, deflate=False, linesearch=0):
+           krylov_max_iter=1000, use_amg=True, cycles=1, max_coarse=64, deflate=False, linesearch=0, reorth=0):
     """Newton for GL(psi) = 0 with MINRES + R_k inner solves (Sec. 2, Sec. 4);
     with deflate, each step is solved on the complement of i psi; with
     linesearch > 0, backtracking on ||GL||_D (at most that many halvings of
-    the step, a globalisation the paper does not use)."""
+    the step, a globalisation the paper does not use); reorth > 0: the
+    solves store and reorthogonalise their Krylov basis."""
     psi = _c128(psi0).copy()
     ni = _NInfo()
     rc = lib().orc_newton(mesh._p, _ptr(psi), tol, max_steps, fixed_steps, krylov_rtol,
                           krylov_max_iter, int(use_amg), cycles, max_coarse, int(deflate), int(linesearch),
-                          C.byref(ni))
+                          int(reorth), C.byref(ni))
     info = {"status": rc, "steps": ni.steps, "converged": bool(ni.converged),
             "res": list(ni.res[:ni.steps + 1]), "krylov_iters": list(ni.krylov_iters[:ni.steps]),
             "alpha": list(ni.alpha[:ni.steps])}

@@ -9,7 +9,8 @@
  *
  * MINRES is the preconditioned Lanczos + Givens recurrence of Paige and
  * Saunders (1975) in the form of Elman, Silvester and Wathen, with x0 = 0 and
- * no reorthogonalisation.  |eta_j| equals the preconditioned residual norm
+ * no reorthogonalisation; orc_minres_reorth_generic stores the basis and
+ * reorthogonalises it (the paper's remedy for the loss of orthogonality).  |eta_j| equals the preconditioned residual norm
  * ||b - A x_j||_{M^-1}; the iteration stops when |eta_j| <= rtol |eta_0|.
  */
 #include "oracle.h"
@@ -88,6 +89,122 @@ done:
     return rc;
 }
 
+/* ------------------------------------ MINRES with reorthogonalisation --- */
+/* Sec. 4 (remark on the iteration peaks of the continuation runs): they come
+ * from the loss of orthogonality of the MINRES Krylov basis, which storing
+ * the basis and fully reorthogonalising it in every step, as GMRES does,
+ * alleviates.  Reading: each step is the MINRES (preconditioned Lanczos)
+ * step -- q = A z_j minus its components alpha v_j and gamma_j v_{j-1} --
+ * followed by one classical Gram-Schmidt pass of q against every stored
+ * v_i in the preconditioned product, h_i = <z_i, q>; the coefficients join
+ * the column of the projected matrix (GMRES form), whose least-squares
+ * problem min || eta_0 e_1 - H y || is solved by Givens rotations, and
+ * x = x_0 + Z y with the stored preconditioned vectors z_i.  With an exactly
+ * self-adjoint preconditioner the h_i vanish in exact arithmetic and the
+ * iterates are those of MINRES.  When `basis` vectors are stored without
+ * convergence the solve restarts from the true residual.  |g_j| is the
+ * preconditioned residual norm; the iteration stops when |g_j| <= rtol eta_0,
+ * eta_0 the norm of b. */
+int orc_minres_reorth_generic(int64_t n, const double *w, orc_op A, void *actx, orc_op minv,
+                              void *mctx, const cplx *b, cplx *x, double rtol, int max_iter,
+                              int basis, double *hist, orc_krylov_info *info)
+{
+    if (basis < 2) basis = 2;
+    const size_t bytes = (size_t)n * sizeof(cplx);
+    cplx *V = malloc(bytes * (size_t)(basis + 1)), *Z = malloc(bytes * (size_t)(basis + 1));
+    cplx *q = malloc(bytes), *r = malloc(bytes), *t = malloc(bytes);
+    double *H = calloc((size_t)(basis + 1) * basis, sizeof(double));   /* column-major, basis+1 rows */
+    double *cs = malloc((size_t)basis * sizeof(double)), *sn = malloc((size_t)basis * sizeof(double));
+    double *g = malloc((size_t)(basis + 1) * sizeof(double)), *y = malloc((size_t)basis * sizeof(double));
+    double *h = malloc((size_t)(basis + 1) * sizeof(double));
+    int rc = ORC_OK, total = 0;
+    double eta0 = 0.0, eta = 0.0;
+    memset(info, 0, sizeof(*info));
+    for (int64_t i = 0; i < n; ++i) x[i] = 0;
+    memcpy(r, b, bytes);
+    if (hist) hist[0] = 1.0;
+    for (int start = 0;; ++start) {
+        /* v_0 = r / beta, z_0 = M r / beta */
+        memcpy(V, r, bytes);
+        if (minv) minv(mctx, V, Z); else memcpy(Z, V, bytes);
+        double b2 = wip(n, w, V, Z);
+        if (!(b2 >= 0.0)) { rc = ORC_ERR_BREAKDOWN; break; }
+        const double beta = sqrt(b2);
+        if (start == 0) { eta0 = beta; info->eta0 = eta0; }
+        eta = beta;
+        if (beta <= rtol * eta0 || beta == 0.0) { info->converged = 1; break; }
+        if (total >= max_iter) break;
+        for (int64_t i = 0; i < n; ++i) { V[i] /= beta; Z[i] /= beta; }
+        g[0] = beta;
+        int k = 0, done = 0;
+        for (int j = 0; j < basis && total < max_iter; ++j) {
+            cplx *vj = V + (size_t)j * n, *zj = Z + (size_t)j * n;
+            double *col = H + (size_t)j * (basis + 1);
+            A(actx, zj, q);
+            /* the MINRES (Lanczos) step */
+            const double alpha = wip(n, w, zj, q);
+            const double gam = j > 0 ? H[(size_t)(j - 1) * (basis + 1) + j] : 0.0;
+            for (int64_t i = 0; i < n; ++i) q[i] -= alpha * vj[i];
+            if (j > 0)
+                for (int64_t i = 0; i < n; ++i) q[i] -= gam * V[(size_t)(j - 1) * n + i];
+            /* full reorthogonalisation: every h_i from the same q */
+            for (int i = 0; i <= j; ++i) h[i] = wip(n, w, Z + (size_t)i * n, q);
+            for (int i = 0; i <= j; ++i) {
+                const cplx *vi = V + (size_t)i * n;
+                for (int64_t e = 0; e < n; ++e) q[e] -= h[i] * vi[e];
+            }
+            for (int i = 0; i <= j; ++i) col[i] = h[i];
+            col[j] += alpha;
+            if (j > 0) col[j - 1] += gam;
+            cplx *zn = Z + (size_t)(j + 1) * n;
+            if (minv) minv(mctx, q, zn); else memcpy(zn, q, bytes);
+            double g2 = wip(n, w, q, zn);
+            if (!(g2 >= 0.0)) { rc = ORC_ERR_BREAKDOWN; done = 1; break; }
+            const double gnew = sqrt(g2);
+            col[j + 1] = gnew;
+            /* the rotations of the previous columns, then this column's own */
+            for (int i = 0; i < j; ++i) {
+                const double a0 = col[i], a1 = col[i + 1];
+                col[i] = cs[i] * a0 + sn[i] * a1;
+                col[i + 1] = -sn[i] * a0 + cs[i] * a1;
+            }
+            const double rr = hypot(col[j], col[j + 1]);
+            if (!(rr > 0.0)) { rc = ORC_ERR_BREAKDOWN; done = 1; break; }
+            cs[j] = col[j] / rr;
+            sn[j] = col[j + 1] / rr;
+            col[j] = rr;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            ++total;
+            eta = fabs(g[j + 1]);
+            if (hist) hist[total] = eta / eta0;
+            if (eta <= rtol * eta0 || gnew == 0.0) { info->converged = 1; done = 1; break; }
+            cplx *vn = V + (size_t)(j + 1) * n;
+            for (int64_t i = 0; i < n; ++i) { vn[i] = q[i] / gnew; zn[i] /= gnew; }
+        }
+        /* x += Z y, R y = g (R: the rotated columns) */
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int c = i + 1; c < k; ++c) s -= H[(size_t)c * (basis + 1) + i] * y[c];
+            y[i] = s / H[(size_t)i * (basis + 1) + i];
+        }
+        for (int i = 0; i < k; ++i) {
+            const cplx *zi = Z + (size_t)i * n;
+            for (int64_t e = 0; e < n; ++e) x[e] += y[i] * zi[e];
+        }
+        if (done || total >= max_iter) break;
+        /* restart from the true residual */
+        A(actx, x, t);
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i] - t[i];
+    }
+    info->iterations = total;
+    info->eta = eta;
+    if (rc == ORC_OK && !info->converged) rc = ORC_ERR_NOT_CONVERGED;
+    free(V); free(Z); free(q); free(r); free(t); free(H); free(cs); free(sn); free(g); free(y); free(h);
+    return rc;
+}
+
 /* ------------------------------------------------- Jacobian solve --- */
 typedef struct { const orc_mesh *m; const cplx *psi; } jac_ctx;
 typedef struct { const orc_mesh *m; const orc_amg *amg; int cycles; cplx *tmp; } pre_ctx;
@@ -107,14 +224,17 @@ static void pre_op(void *ctx, const cplx *r, cplx *z)
 }
 
 int orc_minres(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycles,
-               const cplx *b, cplx *x, double rtol, int max_iter,
+               const cplx *b, cplx *x, double rtol, int max_iter, int reorth,
                double *hist, orc_krylov_info *info)
 {
     jac_ctx jc = {m, psi};
     pre_ctx pc = {m, amg, cycles < 1 ? 1 : cycles, NULL};
     if (amg) pc.tmp = malloc((size_t)m->n * sizeof(cplx));
-    int rc = orc_minres_generic(m->n, m->vol, jac_op, &jc, amg ? pre_op : NULL, &pc, b, x,
-                                rtol, max_iter, hist, info);
+    int rc = reorth > 0
+        ? orc_minres_reorth_generic(m->n, m->vol, jac_op, &jc, amg ? pre_op : NULL, &pc, b, x, rtol, max_iter,
+                                    reorth, hist, info)
+        : orc_minres_generic(m->n, m->vol, jac_op, &jc, amg ? pre_op : NULL, &pc, b, x, rtol, max_iter, hist,
+                             info);
     free(pc.tmp);
     /* true residual in the D-norm */
     cplx *r = malloc((size_t)m->n * sizeof(cplx));
@@ -162,7 +282,7 @@ static void projected_op(void *ctx, const cplx *x, cplx *y)
 }
 
 int orc_minres_deflated(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycles,
-                        const cplx *b, cplx *x, double rtol, int max_iter,
+                        const cplx *b, cplx *x, double rtol, int max_iter, int reorth,
                         double *hist, orc_krylov_info *info)
 {
     const int64_t n = m->n;
@@ -177,8 +297,11 @@ int orc_minres_deflated(const orc_mesh *m, const cplx *psi, const orc_amg *amg, 
     if (amg) pc.tmp = malloc(bytes);
     defl_ctx dj = {m, u, uu, jac_op, &jc, malloc(bytes)};
     defl_ctx dm = {m, u, uu, pre_op, &pc, malloc(bytes)};
-    int rc = orc_minres_generic(n, m->vol, projected_op, &dj, amg ? projected_op : NULL, &dm, pb, x,
-                                rtol, max_iter, hist, info);
+    int rc = reorth > 0
+        ? orc_minres_reorth_generic(n, m->vol, projected_op, &dj, amg ? projected_op : NULL, &dm, pb, x, rtol,
+                                    max_iter, reorth, hist, info)
+        : orc_minres_generic(n, m->vol, projected_op, &dj, amg ? projected_op : NULL, &dm, pb, x, rtol,
+                             max_iter, hist, info);
     /* without a preconditioner the iterates are combinations of Pi-images
      * already; project once more so that x is in the complement to rounding */
     project(m, u, uu, x);
@@ -195,7 +318,7 @@ int orc_minres_deflated(const orc_mesh *m, const cplx *psi, const orc_amg *amg, 
 /* ----------------------------------------------------------- Newton --- */
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               int max_coarse, int deflate, int linesearch, orc_newton_info *info)
+               int max_coarse, int deflate, int linesearch, int reorth, orc_newton_info *info)
 {
     const int64_t n = m->n;
     cplx *r = malloc((size_t)n * sizeof(cplx)), *b = malloc((size_t)n * sizeof(cplx));
@@ -221,8 +344,9 @@ int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixe
         }
         for (int64_t i = 0; i < n; ++i) b[i] = -r[i];
         orc_krylov_info ki;
-        int krc = deflate ? orc_minres_deflated(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, NULL, &ki)
-                          : orc_minres(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, NULL, &ki);
+        int krc = deflate ? orc_minres_deflated(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, reorth,
+                                                NULL, &ki)
+                          : orc_minres(m, psi, amg, cycles, b, dx, krylov_rtol, krylov_max_iter, reorth, NULL, &ki);
         orc_amg_free(amg);
         if (krc != ORC_OK && krc != ORC_ERR_NOT_CONVERGED) { rc = krc; break; }
         /* psi_{k+1} = psi_k + alpha dx: alpha = 1, halved while the residual

@@ -137,9 +137,11 @@ typedef struct {
 
 /* Solve J(psi) x = b by MINRES in the D-weighted real inner product with
  * preconditioner R_k = AMG_k(H, D .) (amg == NULL: none).  x0 = 0.
+ * reorth > 0: the Krylov basis (at most reorth vectors, then a restart) is
+ * stored and reorthogonalised in every step (orc_minres_reorth_generic).
  * hist (may be NULL) receives |eta_j|/eta0 for j = 0..iterations. */
 int orc_minres(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycles,
-               const cplx *b, cplx *x, double rtol, int max_iter,
+               const cplx *b, cplx *x, double rtol, int max_iter, int reorth,
                double *hist, orc_krylov_info *info);
 
 /* Generic preconditioned MINRES on an operator that is self-adjoint in
@@ -149,13 +151,23 @@ int orc_minres_generic(int64_t n, const double *w, orc_op A, void *actx, orc_op 
                        void *mctx, const cplx *b, cplx *x, double rtol, int max_iter,
                        double *hist, orc_krylov_info *info);
 
+/* The same system with the Krylov basis stored: each MINRES step is followed
+ * by one classical Gram-Schmidt pass against every stored vector in the
+ * preconditioned product, the coefficients join the projected matrix (GMRES
+ * form), and x = Z y from the stored preconditioned vectors (Sec. 4, the
+ * remedy for the loss of orthogonality).  At most `basis` vectors, then a
+ * restart from the true residual. */
+int orc_minres_reorth_generic(int64_t n, const double *w, orc_op A, void *actx, orc_op minv,
+                              void *mctx, const cplx *b, cplx *x, double rtol, int max_iter,
+                              int basis, double *hist, orc_krylov_info *info);
+
 /* Solve J(psi) x = b on the <.,.>_R-orthogonal complement of the gauge mode
  * u = i psi: MINRES (as orc_minres) on Pi J Pi x = Pi b with the orthogonal
  * projector Pi x = x - u <u, x>_R / <u, u>_R and the preconditioner
  * Pi R_k Pi.  x is orthogonal to u.  res_true = ||Pi (b - J x)||_D /
  * ||Pi b||_D.  psi = 0 (u = 0) is the plain solve. */
 int orc_minres_deflated(const orc_mesh *m, const cplx *psi, const orc_amg *amg, int cycles,
-                        const cplx *b, cplx *x, double rtol, int max_iter,
+                        const cplx *b, cplx *x, double rtol, int max_iter, int reorth,
                         double *hist, orc_krylov_info *info);
 
 /* ------------------------------------------------------------- Newton --- */
@@ -171,9 +183,10 @@ typedef struct {
  * (orc_minres_deflated).  linesearch > 0 (not part of the paper's method, a
  * standard globalisation of Newton): the step psi_k + alpha dpsi takes the
  * first alpha in 1, 1/2, ..., 2^-linesearch with ||GL||_D <= (1 - 1e-4 alpha)
- * ||GL(psi_k)||_D, else the last one. */
+ * ||GL(psi_k)||_D, else the last one.  reorth > 0: the solves store and
+ * reorthogonalise their Krylov basis (orc_minres). */
 int orc_newton(const orc_mesh *m, cplx *psi, double tol, int max_steps, int fixed_steps,
                double krylov_rtol, int krylov_max_iter, int use_amg, int cycles,
-               int max_coarse, int deflate, int linesearch, orc_newton_info *info);
+               int max_coarse, int deflate, int linesearch, int reorth, orc_newton_info *info);
 
 #endif
