@@ -328,6 +328,28 @@ typedef struct {
                           condition <i psi, dpsi>_R = 0.  res_true is then
                           ||Pi (b - J x)||_D / ||Pi b||_D.  psi = 0: plain solve.
                           0: plain */
+    int reorth;        /* > 0: store the Krylov basis (at most reorth vectors)
+                          and fully reorthogonalise every new vector against
+                          it (Sec. 4: the iteration peaks of the continuation
+                          runs come from the loss of orthogonality of the
+                          MINRES basis, which this alleviates, as in GMRES).
+                          Each MINRES step is followed by one classical
+                          Gram-Schmidt pass against every stored vector in
+                          the preconditioned product; the coefficients join
+                          the projected matrix, whose least-squares problem
+                          is solved by Givens rotations (the GMRES form: with
+                          an FP32 V-cycle, which is self-adjoint only up to
+                          rounding, the basis stays orthogonal and the
+                          iteration count stays that of the FP64 one); x =
+                          Z y from the stored preconditioned vectors.  A
+                          full basis restarts from the true residual (a
+                          restart slows these indefinite solves down: size
+                          reorth to the expected iteration count).  The
+                          mesh keeps the basis, 2 (reorth + 1) n complex
+                          doubles, allocated by the first such solve and
+                          grown when a larger one comes.  Not with
+                          inner_rtol or relax_rtol > 0 (INVALID_ARGUMENT),
+                          nor in batches (UNSUPPORTED).  0: plain MINRES */
 } gl_krylov_opts;
 
 typedef struct {

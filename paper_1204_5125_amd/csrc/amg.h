@@ -111,6 +111,7 @@ struct KrylovScalars {
     double rtol;
     double res_num, res_den;
     double defl_c, defl_sq, defl_sy, res_u_num, res_u_den;
+    double rg2;  // reorthogonalised solves: <v, M^-1 v> of the newest vector
     int iter, max_iter, running, wx_valid, status, converged;
     int defl_pending;
 };
@@ -118,7 +119,7 @@ struct KrylovScalars {
 // What a reduction's finalize kernel does with the total.
 enum FinalizeMode {
     FIN_STORE = 0, FIN_MINRES_INIT = 1, FIN_MINRES_STEP = 2, FIN_DELTA = 3, FIN_RESNUM = 4,
-    FIN_RESDEN = 5, FIN_DEFL_Y = 6
+    FIN_RESDEN = 5, FIN_DEFL_Y = 6, FIN_REORTH = 7
 };
 
 // Scalar part of preconditioned MINRES (Paige-Saunders Lanczos + Givens
@@ -131,6 +132,12 @@ __device__ __forceinline__ void minres_finalize(KrylovScalars *ks, int mode, dou
     if (mode == FIN_DELTA) { ks->delta = total; return; }
     if (mode == FIN_RESNUM) { ks->res_num = total; return; }
     if (mode == FIN_RESDEN) { ks->res_den = total; return; }
+    if (mode == FIN_REORTH) {
+        // the rest of the step is the column of the projected matrix
+        ks->rg2 = total;
+        ks->defl_pending = 1;
+        return;
+    }
     if (mode == FIN_DEFL_Y) {
         // coefficient of the newest preconditioner output along u, or 0 when
         // the recurrence has produced none since the last projection

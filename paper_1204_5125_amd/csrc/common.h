@@ -349,7 +349,7 @@ struct LinkTab {
 // --------------------------------------------------- public handles ----
 namespace glk {
 struct GraphEntry {
-    uint64_t key[6];
+    uint64_t key[8];
     hipGraphExec_t exec;
 };
 }  // namespace glk
@@ -377,6 +377,15 @@ struct gl_mesh {
     double *hscal = nullptr;         // pinned host mirror
     // Krylov workspace (allocated with the mesh so that solves allocate nothing)
     glk::DevBuf<double2> work;       // kWorkVecs * n
+    // reorthogonalised solves (rcap vectors): Z in FP64 (x = Z y) then, for
+    // FP64 V-cycles, V in FP64; for reduced-precision V-cycles the basis
+    // the reorthogonalisation reads, Z then V, in FP32; the projected
+    // matrix's state (R, rotations, g, coefficients, partials)
+    glk::DevBuf<double2> rbasis;
+    glk::DevBuf<float2> rbasis32;
+    glk::DevBuf<double> rstate;
+    int rcap = 0;
+    bool rcap_v64 = false, rcap_32 = false;
     glk::DevBuf<char> kscal;         // Krylov scalar state
     hipStream_t ws = nullptr;        // Krylov work stream (graph capture)
     hipEvent_t ev_in = nullptr, ev_out = nullptr;

@@ -27,6 +27,10 @@
 
 namespace glk {
 
+// stride of the stored Krylov basis of reorthogonalised solves: n rounded up
+// to a multiple of 4 (aligned wide loads)
+__host__ __device__ inline size_t reorth_ld(int n) { return ((size_t)n + 3) & ~(size_t)3; }
+
 __global__ void k_ks_init_running(KrylovScalars *ks)
 {
     ks->running = (ks->eta0 > 0.0) && (ks->max_iter > 0) && (ks->status == 0);
@@ -117,6 +121,9 @@ struct MinresJapply {
     RedSlot slot;
     RedSlot slot_u;  // deflation: partials of <u, q>_E, u = i psi (unused otherwise)
     int defl;
+    double2 *zb = nullptr;  // reorthogonalised solves: the basis Z (z_j / gamma_j stored
+                            // at slot j); no w / x update then
+    float2 *zb32 = nullptr; // and its FP32 copy (reduced-precision V-cycles)
     __device__ void operator()(int bx, int nbx) const
     {
         // the scalars and the vectors are loaded together; the (uniform)
@@ -124,7 +131,8 @@ struct MinresJapply {
         __shared__ double sm[kBlock / 64];
         const int running = ks->running;
         const double ig = 1.0 / ks->gamma;
-        const bool upd = ks->iter >= 1;
+        const int jt = ks->iter;
+        const bool upd = zb == nullptr && jt >= 1;
         const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
         const bool in = i < g.n;
         double part = 0.0, part_u = 0.0;
@@ -154,6 +162,12 @@ struct MinresJapply {
                 wp[i] = wn;
                 x[i] = xn;
             }
+            if (zb) {
+                const double2 zs = cscale(z[i], ig);
+                const size_t at = (size_t)jt * reorth_ld(g.n) + i;
+                zb[at] = zs;
+                if (zb32) zb32[at] = make_float2((float)zs.x, (float)zs.y);
+            }
             q[i] = qi;
         }
         block_reduce_store(part, slot, sm, bx);
@@ -161,22 +175,254 @@ struct MinresJapply {
     }
 };
 
+// a basis vector entry in FP64 or FP32 (whichever buffer is given)
+__device__ __forceinline__ void store_basis(double2 *b64, float2 *b32, size_t at, double2 v)
+{
+    if (b64) b64[at] = v;
+    if (b32) b32[at] = make_float2((float)v.x, (float)v.y);
+}
+
 struct MinresVupdate {
     int n;
     const double2 *q, *v;
     double2 *vp;
     const KrylovScalars *ks;
+    double2 *vb = nullptr;  // reorthogonalised solves: the basis V (v_j / gamma_j at slot j)
+    float2 *vb32 = nullptr; // or its FP32 form (reduced-precision V-cycles)
     __device__ void operator()(int bx, int) const
     {
         const int running = ks->running;
         const double a = ks->delta / ks->gamma, b = ks->gamma / ks->gamma_prev;
+        const int jt = ks->iter;
         const int i = bx * kBlock + threadIdx.x;
         if (i >= n) return;
         const double2 qi = q[i], vi = v[i], vpi = vp[i];
         if (running == 0) return;
         vp[i] = csub(csub(qi, cscale(vi, a)), cscale(vpi, b));
+        store_basis(vb, vb32, (size_t)jt * reorth_ld(n) + i, cscale(vi, 1.0 / ks->gamma));
     }
 };
+
+// ------------------------------ MINRES with the basis reorthogonalised ----
+// Sec. 4 traces the iteration peaks of the continuation runs to the loss of
+// orthogonality of the MINRES basis and names the remedy: store the basis
+// and fully reorthogonalise it in every step, as GMRES does.  Iteration j
+// keeps the MINRES step (the Japply, delta and the Lanczos update above, which
+// store V_j = v_j / gamma_j and Z_j = z_j / gamma_j in the basis) and then
+//   h_i = <Z_i, v_{j+1}>_E for every i <= j          (ReorthDots, ReorthSum)
+//   v_{j+1} -= sum_i h_i V_i                          (ReorthUpdate)
+//   z_{j+1} = M^-1 v_{j+1}, gamma_{j+1}^2 = <v_{j+1}, z_{j+1}>
+//   column j of the projected matrix: h_i, plus delta on the diagonal and
+//   gamma_j above it, gamma_{j+1} below; the previous Givens rotations, a new
+//   one, and |g_{j+1}| (the preconditioned residual norm) tested against
+//   rtol eta_0                                        (ReorthColumn)
+// classical Gram-Schmidt: every h_i from the same vector.  After the loop the
+// host solves R y = g and x += Z y (k_basis_combine).  Every kernel reads j
+// from the device scalars, so the graph of two iterations replays.
+
+constexpr int kReorthGroup = 8;  // basis vectors per block reduction
+
+// Basis vectors are stored with the padded stride ld = n rounded up to a
+// multiple of 4, four nodes per thread: the FP32 entries of a thread are two
+// aligned 16-byte loads.  Entries past n are never used (selected away).
+constexpr int kReorthNodes = 4;
+
+template <class T>
+__device__ __forceinline__ void load4(const C<T> *p, double2 out[4])
+{
+    if constexpr (sizeof(T) == 4) {
+        const float4 a = reinterpret_cast<const float4 *>(p)[0], b = reinterpret_cast<const float4 *>(p)[1];
+        out[0] = make_double2(a.x, a.y);
+        out[1] = make_double2(a.z, a.w);
+        out[2] = make_double2(b.x, b.y);
+        out[3] = make_double2(b.z, b.w);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[e] = p[e];
+    }
+}
+
+// partials of h_i = <Z_i, q>_E, i = 0 .. j, one per wave: part[i * nparts +
+// wave].  The basis is read in FP64 with an FP64 V-cycle and in FP32 with a
+// reduced-precision one (the coefficients are of the size of the loss of
+// orthogonality, and every one subtracted is also the one recorded in the
+// projected matrix, so the relation J Z = V H holds to FP64 rounding either
+// way).  No barrier: each wave keeps kReorthGroup sums in flight.
+template <class T>
+struct ReorthDots {
+    int n, nparts;
+    const C<T> *zb;
+    const double2 *q;
+    double *part;
+    const KrylovScalars *ks;
+    __device__ void operator()(int bx, int) const
+    {
+        if (ks->running == 0) return;  // uniform
+        const int j = ks->iter;
+        const size_t ld = reorth_ld(n);
+        const int t = bx * kBlock + threadIdx.x, base = t * kReorthNodes;
+        const int wave = t >> 6, lane = threadIdx.x & 63;
+        const bool any = base < n;
+        double2 qv[kReorthNodes];
+        bool ok[kReorthNodes];
+#pragma unroll
+        for (int e = 0; e < kReorthNodes; ++e) {
+            ok[e] = base + e < n;
+            qv[e] = ok[e] ? q[base + e] : make_double2(0.0, 0.0);
+        }
+        for (int k0 = 0; k0 <= j; k0 += kReorthGroup) {
+            double sv[kReorthGroup];
+#pragma unroll
+            for (int g = 0; g < kReorthGroup; ++g) {
+                double acc = 0.0;
+                if (any && k0 + g <= j) {
+                    double2 zv[kReorthNodes];
+                    load4<T>(zb + (size_t)(k0 + g) * ld + base, zv);
+#pragma unroll
+                    for (int e = 0; e < kReorthNodes; ++e) acc += ok[e] ? redot(zv[e], qv[e]) : 0.0;
+                }
+                sv[g] = acc;
+            }
+#pragma unroll
+            for (int g = 0; g < kReorthGroup; ++g) sv[g] = wave_sum(sv[g]);
+            if (lane == 0) {
+#pragma unroll
+                for (int g = 0; g < kReorthGroup; ++g)
+                    if (k0 + g <= j) part[(size_t)(k0 + g) * nparts + wave] = sv[g];
+            }
+        }
+    }
+};
+
+// h_i = sum of the nparts partials of coefficient i (block i, fixed order)
+struct ReorthSum {
+    int nparts;
+    const double *part;
+    double *h;
+    const KrylovScalars *ks;
+    __device__ void operator()(int bx, int) const
+    {
+        __shared__ double sm[kBlock / 64];
+        if (ks->running == 0 || bx > ks->iter) return;  // uniform per block
+        double sv = 0.0;
+        for (int k = threadIdx.x; k < nparts; k += kBlock) sv += part[(size_t)bx * nparts + k];
+        sv = block_sum(sv, sm);
+        if (threadIdx.x == 0) h[bx] = sv;
+    }
+};
+
+// q -= sum_{i <= j} h_i V_i (V in FP64 or FP32 as in ReorthDots)
+template <class T>
+struct ReorthUpdate {
+    int n;
+    const C<T> *vb;
+    const double *h;
+    double2 *q;
+    const KrylovScalars *ks;
+    __device__ void operator()(int bx, int) const
+    {
+        if (ks->running == 0) return;
+        const int j = ks->iter;
+        const size_t ld = reorth_ld(n);
+        const int base = (bx * kBlock + threadIdx.x) * kReorthNodes;
+        if (base >= n) return;
+        double2 acc[kReorthNodes];
+#pragma unroll
+        for (int e = 0; e < kReorthNodes; ++e) acc[e] = base + e < n ? q[base + e] : make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int k = 0; k <= j; ++k) {
+            double2 vv[kReorthNodes];
+            load4<T>(vb + (size_t)k * ld + base, vv);
+            const double hk = h[k];
+#pragma unroll
+            for (int e = 0; e < kReorthNodes; ++e) acc[e] = csub(acc[e], cscale(vv[e], hk));
+        }
+#pragma unroll
+        for (int e = 0; e < kReorthNodes; ++e)
+            if (base + e < n) q[base + e] = acc[e];
+    }
+};
+
+// Column j of the projected matrix, its rotations and the convergence test.
+// The rotations are a chain on thread 0; the block stages their
+// coefficients and the column's entries in LDS, 64 at a time.  R is
+// column-major with kmax + 1 rows.
+struct ReorthColumn {
+    int kmax;
+    double *R, *cs, *sn, *gv;
+    const double *h;
+    KrylovScalars *ks;
+    __device__ void operator()(int, int) const
+    {
+        __shared__ double scs[64], ssn[64], sh[64];
+        const int running = ks->running, j = ks->iter;
+        const double delta = ks->delta, gam = ks->gamma;
+        __syncthreads();  // every thread has read the scalars before thread 0 writes them
+        if (running == 0) return;  // uniform
+        auto entry = [&](int i) { return h[i] + (i == j ? delta : 0.0) + (i == j - 1 ? gam : 0.0); };
+        double *col = R + (size_t)j * (kmax + 1);
+        double carry = threadIdx.x == 0 ? entry(0) : 0.0;
+        for (int i0 = 0; i0 < j; i0 += 64) {
+            const int cnt = min(64, j - i0);
+            if ((int)threadIdx.x < cnt) {
+                scs[threadIdx.x] = cs[i0 + threadIdx.x];
+                ssn[threadIdx.x] = sn[i0 + threadIdx.x];
+                sh[threadIdx.x] = entry(i0 + threadIdx.x + 1);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                for (int t = 0; t < cnt; ++t) {
+                    const double a1 = sh[t];
+                    col[i0 + t] = scs[t] * carry + ssn[t] * a1;
+                    carry = -ssn[t] * carry + scs[t] * a1;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x != 0) return;
+        const double g2 = ks->rg2;
+        if (!(g2 >= 0.0)) {
+            ks->status = GL_ERR_BREAKDOWN;
+            ks->running = 0;
+            return;
+        }
+        const double gnew = sqrt(g2);
+        if (j == 0) gv[0] = ks->eta0;
+        const double rr = sqrt(carry * carry + gnew * gnew);
+        if (!(rr > 0.0)) {
+            ks->status = GL_ERR_BREAKDOWN;
+            ks->running = 0;
+            return;
+        }
+        cs[j] = carry / rr;
+        sn[j] = gnew / rr;
+        col[j] = rr;
+        gv[j + 1] = -sn[j] * gv[j];
+        gv[j] = cs[j] * gv[j];
+        ks->eta = gv[j + 1];
+        ks->iter = j + 1;
+        ks->gamma_prev = gam;
+        ks->gamma = gnew;
+        if (fabs(gv[j + 1]) <= ks->rtol * ks->eta0 || gnew == 0.0) {
+            ks->converged = 1;
+            ks->running = 0;
+        } else if (j + 1 >= kmax || j + 1 >= ks->max_iter) {
+            ks->running = 0;
+        }
+    }
+};
+
+// x += sum_{k < cols} y_k Z_k
+__global__ __launch_bounds__(kBlock) void k_basis_combine(int n, int cols, const double2 *__restrict__ zb,
+                                                          const double *__restrict__ y, double2 *__restrict__ x)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const size_t ld = reorth_ld(n);
+    double2 acc = x[i];
+    for (int k = 0; k < cols; ++k) acc = cadd(acc, cscale(zb[(size_t)k * ld + i], y[k]));
+    x[i] = acc;
+}
 
 // ---------------------------------------------- deflation of i psi ----
 // The solve restricted to the <.,.>_R-orthogonal complement of the gauge
@@ -251,10 +497,13 @@ struct MinresVupdateDefl {
     const double2 *psi, *q, *v;
     double2 *vp;
     const KrylovScalars *ks;
+    double2 *vb = nullptr;  // as in MinresVupdate
+    float2 *vb32 = nullptr;
     __device__ void operator()(int bx, int) const
     {
         const int running = ks->running;
         const double a = ks->delta / ks->gamma, b = ks->gamma / ks->gamma_prev;
+        const int jt = ks->iter;
         const double cu = ks->defl_c;
         const double sq = cu > 0.0 ? ks->defl_sq / cu : 0.0;
         const int i = bx * kBlock + threadIdx.x;
@@ -267,6 +516,7 @@ struct MinresVupdateDefl {
         if (running == 0) return;
         const double2 pq = make_double2(qi.x + sq * d * p.y, qi.y - sq * d * p.x);
         vp[i] = csub(csub(pq, cscale(vi, a)), cscale(vpi, b));
+        store_basis(vb, vb32, (size_t)jt * reorth_ld(g.n) + i, cscale(vi, 1.0 / ks->gamma));
     }
 };
 
@@ -499,7 +749,58 @@ struct Ksolve {
     double2 *v, *vp, *z, *zn, *q, *w, *wp;
     gl_precision prec;  // of the V-cycle applications
     bool defl;          // restricted to the complement of i psi
+    // reorthogonalised solves: the basis (V then Z, kmax vectors each) and
+    // the projected matrix's state; rb == nullptr: plain MINRES
+    double2 *rb = nullptr;
+    float2 *rb32 = nullptr;  // non-null: the reorthogonalisation reads the FP32 basis
+    double *rs = nullptr;
+    int kmax = 0;
 };
+
+// blocks of the reorthogonalisation kernels and their partials (one per wave)
+static int reorth_blocks(int n) { return (n + kBlock * kReorthNodes - 1) / (kBlock * kReorthNodes); }
+static int reorth_parts(int n) { return reorth_blocks(n) * (kBlock / 64); }
+
+// Layout of gl_mesh::rstate for a basis of kmax vectors and nbd dot partials
+struct ReorthLayout {
+    double *R, *cs, *sn, *gv, *h, *part;
+};
+
+static ReorthLayout reorth_layout(double *rs, int kmax)
+{
+    ReorthLayout L;
+    L.R = rs;
+    L.cs = L.R + (size_t)(kmax + 1) * kmax;
+    L.sn = L.cs + kmax;
+    L.gv = L.sn + kmax;
+    L.h = L.gv + kmax + 1;
+    L.part = L.h + kmax + 1;
+    return L;
+}
+
+// The mesh's basis and state for kmax vectors (grown, never shrunk).  The
+// cached iteration graphs are dropped when the buffers move (a graph holds
+// their addresses; the stream is idle between solves).
+static void ensure_reorth(gl_mesh *m, int kmax, bool fp32)
+{
+    if (m->rcap >= kmax && (fp32 ? m->rcap_32 : m->rcap_v64)) return;
+    const bool v64 = m->rcap_v64 || !fp32, b32 = m->rcap_32 || fp32;
+    kmax = std::max(kmax, m->rcap);
+    const size_t n = reorth_ld(m->g.n), nbd = (size_t)reorth_parts(m->g.n);
+    for (auto &e : m->graphs) (void)hipGraphExecDestroy(e.exec);
+    m->graphs.clear();
+    m->rbasis.release();
+    m->rbasis32.release();
+    m->rstate.release();
+    m->rcap = 0;
+    m->rcap_v64 = m->rcap_32 = false;
+    m->rbasis.alloc((v64 ? 2 : 1) * (size_t)kmax * n);
+    if (b32) m->rbasis32.alloc(2 * (size_t)kmax * n);
+    m->rstate.alloc((size_t)(kmax + 1) * kmax + 2 * (size_t)kmax + 2 * (size_t)(kmax + 1) + nbd * kmax);
+    m->rcap = kmax;
+    m->rcap_v64 = v64;
+    m->rcap_32 = b32;
+}
 
 static Ksolve make_ksolve(const gl_mesh *m, const double2 *psi, const gl_precond *pre, const double2 *rhs,
                           double2 *x, bool defl)
@@ -568,25 +869,47 @@ static void enqueue_iteration(Ksolve &k, const Launch &L)
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
     const int *gate = &ks->running;
+    // the basis: Z (FP64) and V (FP64), or Z (FP64) plus Z and V in FP32
+    const size_t kn = (size_t)k.kmax * reorth_ld(n);
+    const int nbr = reorth_blocks(n), npr = reorth_parts(n);
+    double2 *zb = k.rb;
+    double2 *vb = k.rb && !k.rb32 ? k.rb + kn : nullptr;
+    float2 *zb32 = k.rb32, *vb32 = k.rb32 ? k.rb32 + kn : nullptr;
     prof_launch(PROF_MINRES_JAPPLY, 48.0 * n + 96.0 * n, L, [&] {
         L.run(nb, MinresJapply<DIM>{g, k.psi, k.z, link_tab<double>(m), k.q, k.zn, k.w, k.wp, k.x, ks,
-                                    red_slot(m, 0), red_slot(m, 2), k.defl ? 1 : 0});
+                                    red_slot(m, 0), red_slot(m, 2), k.defl ? 1 : 0, zb, zb32});
     });
     launch_finalize(red_slot(m, 0).partials, nb, FIN_DELTA, ks, nullptr, gate, L);
     if (k.defl) {
         launch_finalize(red_slot(m, 2).partials, nb, FIN_STORE, nullptr, &ks->defl_sq, gate, L);
         prof_launch(PROF_VUPDATE, 80.0 * n, L,
-                    [&] { L.run(nb, MinresVupdateDefl<DIM>{g, k.psi, k.q, k.v, k.vp, ks}); });
+                    [&] { L.run(nb, MinresVupdateDefl<DIM>{g, k.psi, k.q, k.v, k.vp, ks, vb, vb32}); });
     } else {
-        prof_launch(PROF_VUPDATE, 64.0 * n, L, [&] { L.run(nb, MinresVupdate{n, k.q, k.v, k.vp, ks}); });
+        prof_launch(PROF_VUPDATE, 64.0 * n, L,
+                    [&] { L.run(nb, MinresVupdate{n, k.q, k.v, k.vp, ks, vb, vb32}); });
+    }
+    const int fin = k.rb ? FIN_REORTH : FIN_MINRES_STEP;
+    ReorthLayout R{};
+    if (k.rb) {
+        R = reorth_layout(k.rs, k.kmax);
+        if (k.rb32) {
+            L.run(nbr, ReorthDots<float>{n, npr, zb32, k.vp, R.part, ks});
+            L.run(k.kmax, ReorthSum{npr, R.part, R.h, ks});
+            L.run(nbr, ReorthUpdate<float>{n, vb32, R.h, k.vp, ks});
+        } else {
+            L.run(nbr, ReorthDots<double>{n, npr, zb, k.vp, R.part, ks});
+            L.run(k.kmax, ReorthSum{npr, R.part, R.h, ks});
+            L.run(nbr, ReorthUpdate<double>{n, vb, R.h, k.vp, ks});
+        }
     }
     if (k.pre) {
-        vcycle_enqueue(k.pre, k.vp, k.zn, gate, ks, FIN_MINRES_STEP, L, k.prec);
+        vcycle_enqueue(k.pre, k.vp, k.zn, gate, ks, fin, L, k.prec);
     } else {
         L.run(nb, Unprec<DIM>{g, k.vp, k.zn, gate, red_slot(m, 1)});
-        launch_finalize(red_slot(m, 1).partials, nb, FIN_MINRES_STEP, ks, nullptr, gate, L);
+        launch_finalize(red_slot(m, 1).partials, nb, fin, ks, nullptr, gate, L);
     }
     if (k.defl) defl_project_z<DIM>(k, k.zn, L);
+    if (k.rb) L.run<ReorthColumn, 64>(1, ReorthColumn{k.kmax, R.R, R.cs, R.sn, R.gv, R.h, ks});
     std::swap(k.v, k.vp);
     std::swap(k.z, k.zn);
     std::swap(k.w, k.wp);
@@ -597,11 +920,12 @@ template <int DIM>
 static hipGraphExec_t iteration_graph(Ksolve k, hipStream_t s)
 {
     gl_mesh *m = const_cast<gl_mesh *>(k.m);
-    const uint64_t key[6] = {(uint64_t)(uintptr_t)k.psi, (uint64_t)(uintptr_t)k.rhs, (uint64_t)(uintptr_t)k.x,
+    const uint64_t key[8] = {(uint64_t)(uintptr_t)k.psi, (uint64_t)(uintptr_t)k.rhs, (uint64_t)(uintptr_t)k.x,
                              k.pre ? k.pre->uid : 0,
                              (k.pre ? (uint64_t)(k.prec * 4096 + k.pre->opts.cycles) : 0) | ((uint64_t)k.defl << 40) |
                                  (k.pre ? (uint64_t)k.pre->pcg_m << 48 : 0),
-                             (uint64_t)(uintptr_t)k.v};
+                             (uint64_t)(uintptr_t)k.v, (uint64_t)(uintptr_t)k.rb ^ (uint64_t)(uintptr_t)k.rb32,
+                             (uint64_t)k.kmax | ((uint64_t)(k.rb32 != nullptr) << 40)};
     for (auto &e : m->graphs)
         if (std::memcmp(e.key, key, sizeof(key)) == 0) return e.exec;
     hipGraph_t graph = nullptr;
@@ -711,7 +1035,70 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
     double eta0 = 0.0, res_est = 0.0;
     const bool fp64 = !pre || pre->opts.precision == GL_FP64;
     const bool defl = o.deflate != 0;
-    if (fp64 && o.inner_rtol <= 0.0) {
+    if (o.reorth > 0) {
+        // the basis of at most kmax vectors; each start measures the true
+        // residual r = b - J x: the solve ends when its preconditioned norm
+        // meets rtol, and restarts otherwise (a full basis, or rounding)
+        const int kmax = o.reorth;
+        gl_mesh *mm = const_cast<gl_mesh *>(m);
+        ensure_reorth(mm, kmax, !fp64);
+        // the recurrence's own x (zeroed by every start, never updated with a
+        // basis) is scratch; the solution accumulates x += Z y in x
+        double2 *r = m->work.get() + 10 * (size_t)n, *scratch = m->work.get() + 9 * (size_t)n;
+        k_copy<<<nb, kBlock, 0, s>>>(n, r, b);
+        k_zero<<<nb, kBlock, 0, s>>>(n, x);
+        GLK_CHECK_LAUNCH();
+        Ksolve k = make_ksolve(m, psi, pre, r, scratch, defl);
+        k.rb = mm->rbasis.get();
+        k.rb32 = fp64 ? nullptr : mm->rbasis32.get();
+        k.rs = mm->rstate.get();
+        k.kmax = kmax;
+        const ReorthLayout RL = reorth_layout(k.rs, kmax);
+        const double2 *zb = k.rb;
+        std::vector<double> Rh, gh, y;
+        double eta_first = 0.0;
+        for (;;) {
+            ksolve_init<DIM>(k, 0.0, 0, Launch{s});
+            read_scalars(m, &h, s);
+            if (h.status) { st = (gl_status)h.status; break; }
+            if (eta_first == 0.0) eta_first = h.eta0;
+            res_est = eta_first > 0 ? h.eta0 / eta_first : 0.0;
+            if (h.eta0 <= o.rtol * eta_first || h.eta0 == 0.0) { converged = true; break; }
+            if (iters >= o.max_iter) break;
+            const int budget = o.max_iter - iters;
+            k_ks_set<<<1, 1, 0, s>>>(ks, o.rtol * eta_first / h.eta0, budget);
+            k_ks_init_running<<<1, 1, 0, s>>>(ks);
+            ksolve_iterate<DIM>(k, budget, poll, s, h, false);
+            const int cols = h.iter;
+            iters += cols;
+            if (cols > 0) {
+                // R y = g on the host (cols x cols, upper triangular), x += Z y
+                Rh.resize((size_t)cols * (kmax + 1));
+                gh.resize((size_t)cols);
+                y.assign((size_t)cols, 0.0);
+                GLK_HIP(hipMemcpyAsync(Rh.data(), RL.R, sizeof(double) * Rh.size(), hipMemcpyDeviceToHost, s));
+                GLK_HIP(hipMemcpyAsync(gh.data(), RL.gv, sizeof(double) * gh.size(), hipMemcpyDeviceToHost, s));
+                GLK_HIP(hipStreamSynchronize(s));
+                for (int i = cols - 1; i >= 0; --i) {
+                    double acc = gh[(size_t)i];
+                    for (int c = i + 1; c < cols; ++c) acc -= Rh[(size_t)c * (kmax + 1) + i] * y[(size_t)c];
+                    y[(size_t)i] = acc / Rh[(size_t)i * (kmax + 1) + i];
+                }
+                GLK_HIP(hipMemcpyAsync(RL.h, y.data(), sizeof(double) * cols, hipMemcpyHostToDevice, s));
+                k_basis_combine<<<nb, kBlock, 0, s>>>(n, cols, zb, RL.h, x);
+                GLK_CHECK_LAUNCH();
+                GLK_HIP(hipStreamSynchronize(s));
+            }
+            res_est = eta_first > 0 ? std::fabs(h.eta) / eta_first : 0.0;
+            if (h.status) { st = (gl_status)h.status; break; }
+            // also after convergence of the estimate: the next start measures
+            // the true residual's norm and ends the solve, or restarts
+            if (cols == 0) break;
+            k_residual_vec<DIM><<<nb, kBlock, 0, s>>>(g, psi, x, b, link_tab<double>(m), r);
+            GLK_CHECK_LAUNCH();
+        }
+        eta0 = eta_first;
+    } else if (fp64 && o.inner_rtol <= 0.0) {
         Ksolve k = make_ksolve(m, psi, pre, b, x, defl);
         ksolve_init<DIM>(k, o.rtol, o.max_iter, Launch{s});
         ksolve_iterate<DIM>(k, o.max_iter, poll, s, h);
@@ -805,7 +1192,8 @@ static void check_krylov_opts(const gl_krylov_opts *o, const char *who)
     if (!o) fail(GL_ERR_INVALID_ARGUMENT, std::string(who) + ": NULL options");
     if (!(o->rtol >= 0.0) || o->max_iter < 0 || o->max_iter > 100000000 || o->poll_every < 1 ||
         !(o->inner_rtol >= 0.0 && o->inner_rtol < 1.0) || !(o->relax_rtol >= 0.0 && o->relax_rtol < 1.0) ||
-        (o->deflate != 0 && o->deflate != 1))
+        (o->deflate != 0 && o->deflate != 1) || o->reorth < 0 || o->reorth > 100000 ||
+        (o->reorth > 0 && (o->inner_rtol > 0.0 || o->relax_rtol > 0.0)))
         fail(GL_ERR_INVALID_ARGUMENT, std::string(who) + ": invalid Krylov options");
 }
 
@@ -1517,6 +1905,8 @@ gl_status gl_batch_newton_solve(gl_batch *batch, void *const *psi_inout, const g
                 if (psi_inout[j] == psi_inout[i]) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: repeated psi");
         }
         check_krylov_opts(&opts->krylov, "gl_batch_newton_solve");
+        if (opts->krylov.reorth > 0)
+            fail(GL_ERR_UNSUPPORTED, "gl_batch_newton_solve: reorthogonalised solves are not batched");
         if (opts->max_steps < 0 || opts->max_steps > 63 || opts->fixed_steps < 0 || opts->fixed_steps > 63)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: steps must be in 0..63");
         if (opts->linesearch < 0 || opts->linesearch > 30)

@@ -65,7 +65,8 @@ class AmgOpts(C.Structure):
 
 class KrylovOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_iter", C.c_int), ("poll_every", C.c_int),
-                ("inner_rtol", C.c_double), ("relax_rtol", C.c_double), ("deflate", C.c_int)]
+                ("inner_rtol", C.c_double), ("relax_rtol", C.c_double), ("deflate", C.c_int),
+                ("reorth", C.c_int)]
 
 
 class KrylovInfo(C.Structure):
@@ -440,10 +441,12 @@ def gl_precond_apply(pre, r, z, stream=None):
 
 
 def gl_jacobian_solve(mesh, psi, pre, b, x, rtol=1e-10, max_iter=1000, poll_every=8, inner_rtol=0.0,
-                      relax_rtol=0.0, deflate=False, stream=None, raise_on_fail=True):
+                      relax_rtol=0.0, deflate=False, reorth=0, stream=None, raise_on_fail=True):
     """Solve J(psi) x = b by preconditioned MINRES (with deflate: on the
-    complement of the gauge mode i psi); returns (status, info dict)."""
-    o = KrylovOpts(rtol, max_iter, poll_every, inner_rtol, relax_rtol, int(deflate))
+    complement of the gauge mode i psi; with reorth > 0: the Krylov basis of
+    at most reorth vectors stored and reorthogonalised); returns (status,
+    info dict)."""
+    o = KrylovOpts(rtol, max_iter, poll_every, inner_rtol, relax_rtol, int(deflate), int(reorth))
     ki = KrylovInfo()
     rc = lib().gl_jacobian_solve(mesh.handle, _vec(psi, mesh.n, "psi"),
                                  pre.handle if pre is not None else None, _vec(b, mesh.n, "b"),
@@ -487,14 +490,16 @@ class PrecondHandle:
 def gl_newton_solve(mesh, psi, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
                     krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
                     relax_rtol=0.0, precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, precond=None,
-                    deflate=False, linesearch=0, stream=None, raise_on_fail=True):
+                    deflate=False, linesearch=0, reorth=0, stream=None, raise_on_fail=True):
     """Newton for GL(psi) = 0 in place; returns (status, info dict).  precond:
     an optional PrecondHandle whose hierarchy is reused (and filled on first use);
     deflate: each step under the phase condition <i psi, dpsi>_R = 0;
     linesearch: at most this many halvings of a step that does not reduce
-    ||GL||_D enough (0: full steps)."""
+    ||GL||_D enough (0: full steps); reorth: the solves' Krylov basis size
+    (0: plain MINRES)."""
     o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
-                   KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, relax_rtol, int(deflate)),
+                   KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, relax_rtol, int(deflate),
+                              int(reorth)),
                    AmgOpts(precision, cycles, max_coarse, max_levels), int(linesearch))
     ni = NewtonInfo()
     rc = lib().gl_newton_solve(mesh.handle, _vec(psi, mesh.n, "psi"), C.byref(o),
