@@ -476,21 +476,27 @@ def bench_arclength(args):
     mesh = glnk.Mesh(2, (N, N), (side, side), mu=0.0)
     ones = torch.ones(mesh.n, dtype=torch.complex128, device="cuda")
     runs = {}
-    for name, prec in (("fp64", glnk.GL_FP64), ("fp32", glnk.GL_FP32)):
+    # plain MINRES, and MINRES with the basis reorthogonalised (the paper's
+    # remedy for the iteration peaks of its continuation runs, Sec. 4)
+    for name, prec, reorth in (("fp64", glnk.GL_FP64, 0), ("fp32", glnk.GL_FP32, 0),
+                               ("fp64_reorth", glnk.GL_FP64, REORTH), ("fp32_reorth", glnk.GL_FP32, REORTH)):
         def cb(rec, _):
             log(f"[bench] arclength {name}: mu {rec['mu']:.4f} ds {rec['ds']:.4f} newton {rec['newton_steps']} "
                 f"krylov {sum(a + b for a, b in rec['krylov_iters'])}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         recs, states = continuation.arclength_path(mesh, ones, 0.0, ds, args.arc_steps, precision=prec,
-                                                   max_coarse=64, poll_every=16, callback=cb)
+                                                   max_coarse=64, poll_every=16, callback=cb, reorth=reorth)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         mus = [r["mu"] for r in recs]
         turns = sum(1 for a, b, c in zip(mus, mus[1:], mus[2:]) if (b - a) * (c - b) < 0)
+        per_solve = [k for r in recs[1:] for pair in r["krylov_iters"] for k in pair]
         runs[name] = {"seconds": dt, "points": len(recs) - 1, "converged": sum(r["converged"] for r in recs[1:]),
                       "newton_steps": sum(r["newton_steps"] for r in recs[1:]),
                       "krylov_iterations": sum(a + b for r in recs[1:] for a, b in r["krylov_iters"]),
+                      "krylov_max_per_solve": max(per_solve) if per_solve else 0,
+                      "krylov_per_point": [sum(a + b for a, b in r["krylov_iters"]) for r in recs[1:]],
                       "mu_max": max(mus), "mu_final": mus[-1], "turning_points": turns}
         log(f"[bench] arclength {name}: {runs[name]}")
     mu_max = runs["fp64"]["mu_max"]

@@ -99,7 +99,7 @@ def continuation(mesh, psi0, mu0, dmu, steps, **kw):
 
 def arclength_path(mesh, psi0, mu0, ds, steps, tol=1e-10, krylov_rtol=1e-10, krylov_max_iter=4000,
                    max_newton=20, precision=glnk.GL_FP64, max_coarse=64, max_halvings=3, poll_every=8,
-                   callback=None):
+                   callback=None, reorth=0):
     """Pseudo-arclength continuation from psi0 (corrected by Newton at mu0)
     for `steps` steps of arclength ds, in the product
     <(u, a), (v, b)> = <u, v>_R / |Omega| + a b.
@@ -112,20 +112,22 @@ def arclength_path(mesh, psi0, mu0, ds, steps, tol=1e-10, krylov_rtol=1e-10, kry
     complement of i psi (deflate): dmu = -(N + <t_psi, z1>/|Omega|) /
     (<t_psi, z2>/|Omega| + t_mu), dpsi = z1 + dmu z2.  A corrector that does
     not converge within max_newton steps is retried with h halved (at most
-    max_halvings times).  Returns (records, states) with states the (mu,
-    tensor) of every point."""
+    max_halvings times).  reorth > 0: the Jacobian solves store and
+    reorthogonalise their Krylov basis (at most reorth vectors).  Returns
+    (records, states) with states the (mu, tensor) of every point."""
     import torch
     area = 1.0
     for v in mesh.side:
         area *= v
     kw = dict(rtol=krylov_rtol, max_iter=krylov_max_iter, poll_every=poll_every, deflate=True,
-              raise_on_fail=False)
+              raise_on_fail=False, reorth=reorth)
     psi = psi0.clone()
     mesh.set_field(mu0)
     handle = glnk.PrecondHandle(mesh)
     rc, info = glnk.gl_newton_solve(mesh, psi, tol=tol, max_steps=max_newton, krylov_rtol=krylov_rtol,
                                     krylov_max_iter=krylov_max_iter, precision=precision, max_coarse=max_coarse,
-                                    precond=handle, poll_every=poll_every, deflate=True, raise_on_fail=False)
+                                    precond=handle, poll_every=poll_every, deflate=True, raise_on_fail=False,
+                                    reorth=reorth)
     handle.close()
     mu = mu0
     records = [{"mu": mu, "newton_steps": info["steps"], "res": info["res"][-1], "converged": rc == 0,
