@@ -51,8 +51,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "01aa18ae38c64e34173cfbfe4792ef7d5f245266bf17cc3af22bba797f171935",
-           8: 4980976.1, 2: 21189177.1}
+TRAFFIC = {"csrc_sha256": "3c9fa06f4e1d704479cc63ad313335b58fb8420fb8554899d6277fa33b9b4efa",
+           8: 4980756.4, 2: 21188671.3}
 
 
 def csrc_fingerprint():
@@ -173,10 +173,12 @@ def iteration_bytes(glnk, pre, precision):
     return total
 
 
-def one_pass(l0_tiled=0):
-    """One Newton step of the headline workload (FP32 V-cycle; level 0 in
-    LDS tiles of the given shape when l0_tiled > 0) and a plain copy of known
-    size, for rocprofv3 counter passes."""
+def one_pass(l0_tiled=0, reorth=0):
+    """One Newton step of the headline workload (FP32 V-cycle, plain MINRES;
+    level 0 in LDS tiles of the given shape when l0_tiled > 0) and a plain
+    copy of known size, for rocprofv3 counter passes.  reorth > 0: two Newton
+    steps with the basis reorthogonalised instead (the second solve is the
+    long one)."""
     import torch
 
     from paper_1204_5125_amd import glnk, inputs
@@ -189,8 +191,8 @@ def one_pass(l0_tiled=0):
                          poll_every=2, precision=glnk.GL_FP32, max_coarse=MAX_COARSE, precond=h,
                          raise_on_fail=False)
     glnk.gl_precond_set_tiles(h, *ONE_PASS_TILES, l0_tiled)
-    glnk.gl_newton_solve(mesh, psi, fixed_steps=1, krylov_rtol=RTOL, krylov_max_iter=8000,
-                         poll_every=16, precision=glnk.GL_FP32, max_coarse=MAX_COARSE, precond=h)
+    glnk.gl_newton_solve(mesh, psi, fixed_steps=2 if reorth else 1, krylov_rtol=RTOL, krylov_max_iter=8000,
+                         poll_every=16, precision=glnk.GL_FP32, max_coarse=MAX_COARSE, precond=h, reorth=reorth)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     torch.add(a, 0.0, out=b)
@@ -811,6 +813,8 @@ def main():
                          "copy whose bytes calibrate the counters; prints nothing")
     ap.add_argument("--one-pass-l0-tiled", type=int, default=0, choices=[0, 1, 2, 3],
                     help="with --one-pass: level 0 in LDS tiles of this shape (gl_tiles.l0_tiled)")
+    ap.add_argument("--one-pass-reorth", action="store_true",
+                    help="with --one-pass: two Newton steps with the Krylov basis reorthogonalised")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -818,7 +822,7 @@ def main():
         sys.exit(2)
 
     if args.one_pass:
-        one_pass(args.one_pass_l0_tiled)
+        one_pass(args.one_pass_l0_tiled, REORTH if args.one_pass_reorth else 0)
         return
     if args.workload == "batch":
         bench_batch(args)
