@@ -730,17 +730,20 @@ def bench_cube(args):
     first = {}
     from paper_1204_5125_amd import autotune
     tiles = {}
-    for name, prec in [("fp32", glnk.GL_FP32), ("fp64", glnk.GL_FP64)]:
-        tiles[name] = autotune.tune(mesh, psi0, precision=prec, max_coarse=MAX_COARSE, cache=args.tile_cache,
-                                    log=log)
+    for name, prec, reorth in [("fp32", glnk.GL_FP32, 0), ("fp64", glnk.GL_FP64, 0),
+                               ("fp32_reorth", glnk.GL_FP32, REORTH), ("fp64_reorth", glnk.GL_FP64, REORTH)]:
+        tname = name.split("_")[0]
+        if tname not in tiles:
+            tiles[tname] = autotune.tune(mesh, psi0, precision=prec, max_coarse=MAX_COARSE, cache=args.tile_cache,
+                                         log=log)
         h = glnk.PrecondHandle(mesh)
-        inner = RTOL if prec == glnk.GL_FP64 else 0.0
+        inner = RTOL if prec == glnk.GL_FP64 and reorth == 0 else 0.0
         kw = dict(krylov_rtol=RTOL, krylov_max_iter=8000, poll_every=16, precision=prec, inner_rtol=inner,
-                  max_coarse=MAX_COARSE, precond=h)
+                  max_coarse=MAX_COARSE, precond=h, reorth=reorth)
         psi.copy_(psi0)
         glnk.gl_newton_solve(mesh, psi, fixed_steps=1, **kw)  # warm-up: hierarchy + graphs
         first[name] = psi.clone()
-        glnk.gl_precond_set_tiles(h, *tiles[name])
+        glnk.gl_precond_set_tiles(h, *tiles[tname])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -757,15 +760,17 @@ def bench_cube(args):
     upd_err = float(torch.linalg.norm(d32 - d64) / torch.linalg.norm(d64))
     res = {
         "metric": "Jacobian solves/s at 2.1M nodes (3D), FP32 V-cycle vs FP64",
-        "value": out["fp32"]["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
-        "ms_per_step": out["fp32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "value": out["fp32_reorth"]["value"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": out["fp32_reorth"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 (outer) / f32 (V-cycle)",
         "data": "synthetic: seeded random-phase psi0 on a uniform cube grid",
         "config": {"workload": "3D 129^3 grid (2,146,689 nodes), side 5, mu 0.6 along (1,1,1)/sqrt3; 4 Newton "
-                               "steps from psi0 = 0.9 exp(i theta), seed 0, MINRES + R_1 to rtol 1e-10",
+                               "steps from psi0 = 0.9 exp(i theta), seed 0, MINRES + R_1 to rtol 1e-10; value: "
+                               f"FP32 V-cycle, Krylov basis reorthogonalised (at most {REORTH})",
                    "nodes": mesh.n, "amg_max_coarse": MAX_COARSE,
                    "tiles": {k: list(v) for k, v in tiles.items()}},
-        "fp32": out["fp32"], "fp64_precond": out["fp64"],
+        "fp32_precond_plain": out["fp32"], "fp64_precond": out["fp64"],
+        "fp32_precond_reorth": out["fp32_reorth"], "fp64_precond_reorth": out["fp64_reorth"],
         "fp32_vcycle_output_rel_error": prec_err,
         "first_newton_update_fp32_vs_fp64_rel_error": upd_err,
     }
