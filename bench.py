@@ -66,6 +66,7 @@ def csrc_fingerprint():
     return h.hexdigest()
 RELAX = 1e-4   # relaxed variant: FP64 V-cycle until the MINRES estimate falls below this
 REORTH = 400   # Krylov basis of the reorthogonalised solves (above every solve's count here)
+BATCH_REORTH = 300  # per instance in the batch (64 bases: 32 B per node and vector)
 
 
 def run_steps(glnk, torch, mesh, psi0, psi, handle, precision, steps, relax=0.0, reorth=0):
@@ -252,7 +253,8 @@ def bench_batch(args):
     psis = [torch.ones(m.n, dtype=torch.complex128, device="cuda") for m in meshes]
     prec = glnk.GL_FP64 if args.batch_fp64 else glnk.GL_FP32
     kw = dict(tol=1e-10, krylov_rtol=1e-10, poll_every=16, precision=prec,
-              max_coarse=args.batch_max_coarse, deflate=not args.batch_plain)
+              max_coarse=args.batch_max_coarse, deflate=not args.batch_plain,
+              reorth=BATCH_REORTH if args.batch_reorth else 0)
     batch = glnk.Batch(meshes)
     tiles = {}
     for N in sorted(set(int(v) for v in sizes)):
@@ -338,6 +340,7 @@ def bench_batch(args):
         "dispatches_per_graph": st["dispatches_per_graph"], "groups": st["groups"],
         "graph_launches": st["graph_launches"], "host_seconds": st["seconds"],
         "deflate": not args.batch_plain,
+        "reorth": BATCH_REORTH if args.batch_reorth else 0,
         "converged_fraction": conv / (count * args.steps),
         "converged_first_try_fraction": first / (count * args.steps), "unconverged_first_try": unconverged,
         "halved_steps": halved, "folds": folds,
@@ -806,6 +809,8 @@ def main():
     ap.add_argument("--batch-plain", action="store_true",
                     help="batch: Newton without deflation of the gauge mode")
     ap.add_argument("--batch-fp64", action="store_true", help="batch: FP64 V-cycle")
+    ap.add_argument("--batch-reorth", action="store_true",
+                    help="batch: MINRES with the Krylov basis stored and reorthogonalised")
     ap.add_argument("--tile-cache", default=os.path.join(os.path.expanduser("~"), ".cache", "glnk_tiles.json"))
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)

@@ -348,8 +348,9 @@ typedef struct {
                           mesh keeps the basis, 2 (reorth + 1) n complex
                           doubles, allocated by the first such solve and
                           grown when a larger one comes.  Not with
-                          inner_rtol or relax_rtol > 0 (INVALID_ARGUMENT),
-                          nor in batches (UNSUPPORTED).  0: plain MINRES */
+                          inner_rtol or relax_rtol > 0 (INVALID_ARGUMENT).
+                          Batches keep each mesh's basis the same way.
+                          0: plain MINRES */
 } gl_krylov_opts;
 
 typedef struct {

@@ -778,6 +778,28 @@ static ReorthLayout reorth_layout(double *rs, int kmax)
     return L;
 }
 
+// After a reorthogonalised run of `cols` columns: R y = g on the host (cols
+// x cols, upper triangular) and x += Z y on the device.  Synchronises s.
+static void reorth_combine(const gl_mesh *m, double *rs, int kmax, int cols, double2 *x, hipStream_t s)
+{
+    if (cols <= 0) return;
+    const int n = m->g.n;
+    const ReorthLayout RL = reorth_layout(rs, kmax);
+    std::vector<double> Rh((size_t)cols * (kmax + 1)), gh((size_t)cols), y((size_t)cols, 0.0);
+    GLK_HIP(hipMemcpyAsync(Rh.data(), RL.R, sizeof(double) * Rh.size(), hipMemcpyDeviceToHost, s));
+    GLK_HIP(hipMemcpyAsync(gh.data(), RL.gv, sizeof(double) * gh.size(), hipMemcpyDeviceToHost, s));
+    GLK_HIP(hipStreamSynchronize(s));
+    for (int i = cols - 1; i >= 0; --i) {
+        double acc = gh[(size_t)i];
+        for (int c = i + 1; c < cols; ++c) acc -= Rh[(size_t)c * (kmax + 1) + i] * y[(size_t)c];
+        y[(size_t)i] = acc / Rh[(size_t)i * (kmax + 1) + i];
+    }
+    GLK_HIP(hipMemcpyAsync(RL.h, y.data(), sizeof(double) * cols, hipMemcpyHostToDevice, s));
+    k_basis_combine<<<blocks_for(n), kBlock, 0, s>>>(n, cols, m->rbasis.get(), RL.h, x);
+    GLK_CHECK_LAUNCH();
+    GLK_HIP(hipStreamSynchronize(s));
+}
+
 // The mesh's basis and state for kmax vectors (grown, never shrunk).  The
 // cached iteration graphs are dropped when the buffers move (a graph holds
 // their addresses; the stream is idle between solves).
@@ -1053,9 +1075,6 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
         k.rb32 = fp64 ? nullptr : mm->rbasis32.get();
         k.rs = mm->rstate.get();
         k.kmax = kmax;
-        const ReorthLayout RL = reorth_layout(k.rs, kmax);
-        const double2 *zb = k.rb;
-        std::vector<double> Rh, gh, y;
         double eta_first = 0.0;
         for (;;) {
             ksolve_init<DIM>(k, 0.0, 0, Launch{s});
@@ -1071,24 +1090,7 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
             ksolve_iterate<DIM>(k, budget, poll, s, h, false);
             const int cols = h.iter;
             iters += cols;
-            if (cols > 0) {
-                // R y = g on the host (cols x cols, upper triangular), x += Z y
-                Rh.resize((size_t)cols * (kmax + 1));
-                gh.resize((size_t)cols);
-                y.assign((size_t)cols, 0.0);
-                GLK_HIP(hipMemcpyAsync(Rh.data(), RL.R, sizeof(double) * Rh.size(), hipMemcpyDeviceToHost, s));
-                GLK_HIP(hipMemcpyAsync(gh.data(), RL.gv, sizeof(double) * gh.size(), hipMemcpyDeviceToHost, s));
-                GLK_HIP(hipStreamSynchronize(s));
-                for (int i = cols - 1; i >= 0; --i) {
-                    double acc = gh[(size_t)i];
-                    for (int c = i + 1; c < cols; ++c) acc -= Rh[(size_t)c * (kmax + 1) + i] * y[(size_t)c];
-                    y[(size_t)i] = acc / Rh[(size_t)i * (kmax + 1) + i];
-                }
-                GLK_HIP(hipMemcpyAsync(RL.h, y.data(), sizeof(double) * cols, hipMemcpyHostToDevice, s));
-                k_basis_combine<<<nb, kBlock, 0, s>>>(n, cols, zb, RL.h, x);
-                GLK_CHECK_LAUNCH();
-                GLK_HIP(hipStreamSynchronize(s));
-            }
+            reorth_combine(m, k.rs, kmax, cols, x, s);
             res_est = eta_first > 0 ? std::fabs(h.eta) / eta_first : 0.0;
             if (h.status) { st = (gl_status)h.status; break; }
             // also after convergence of the estimate: the next start measures
@@ -1399,7 +1401,8 @@ struct gl_batch {
     size_t staging_cap = 0;
     int64_t graph_launches = 0;
     double seconds[3] = {0.0, 0.0, 0.0};  // residuals, preconditioner setups, Krylov solves
-    int deflate = 0;                      // Krylov option of the running solve
+    int deflate = 0;                      // Krylov options of the running solve
+    int reorth = 0;
     ~gl_batch();
 };
 
@@ -1420,11 +1423,20 @@ static void batch_gather(gl_batch *B)
 // r_ref (W10) in refinement; otherwise rhs = GL (W7).
 static Ksolve batch_ksolve(gl_batch *B, double2 *const *psi, int i, bool refine, bool use_pre)
 {
-    const gl_mesh *m = B->meshes[i];
+    gl_mesh *m = B->meshes[i];
     const size_t n = (size_t)m->g.n;
     double2 *W = m->work.get();
-    return make_ksolve(m, psi[i], use_pre ? B->pre[i] : nullptr, refine ? W + 10 * n : W + 7 * n,
-                       refine ? W + 9 * n : W + 8 * n, B->deflate != 0);
+    Ksolve k = make_ksolve(m, psi[i], use_pre ? B->pre[i] : nullptr, refine ? W + 10 * n : W + 7 * n,
+                           refine ? W + 9 * n : W + 8 * n, B->deflate != 0);
+    if (B->reorth > 0) {
+        // the basis of the mesh (ensure_reorth before the solve); the
+        // recurrence's x is the scratch vector, the solution W + 8 n
+        k.rb = m->rbasis.get();
+        k.rb32 = k.prec == GL_FP64 ? nullptr : m->rbasis32.get();
+        k.rs = m->rstate.get();
+        k.kmax = B->reorth;
+    }
+    return k;
 }
 
 // Group instances by the shape of a recorded sequence; rec(i, out) records one.
@@ -1547,6 +1559,13 @@ static void batch_iterate(gl_batch *B, double2 *const *psi, bool refine, bool us
             key.push_back(p ? p->uid : 0);
             key.push_back(p ? (uint64_t)(p->opts.precision * 4096 + p->opts.cycles) : 0);
             key.push_back(p ? (uint64_t)p->pcg_m : 0);
+            if (B->reorth > 0) {
+                const gl_mesh *m = B->meshes[i];
+                key.push_back((uint64_t)B->reorth);
+                key.push_back((uint64_t)(uintptr_t)m->rbasis.get());
+                key.push_back((uint64_t)(uintptr_t)m->rbasis32.get());
+                key.push_back((uint64_t)(uintptr_t)m->rstate.get());
+            }
         }
         return key;
     };
@@ -1647,6 +1666,62 @@ static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int>
     const bool refine = fp32 || ko.inner_rtol > 0.0;
     const int poll = std::max(1, ko.poll_every);
     for (int i : act) iters[i] = 0;
+    if (B->reorth > 0) {
+        // as a single reorthogonalised solve, instance by instance between
+        // the batched runs: every start measures the true residual, every
+        // run ends with x += Z y and r = b - J x
+        for (int i : act) {
+            gl_mesh *m = B->meshes[i];
+            ensure_reorth(m, B->reorth, use_pre && B->pre[i]->opts.precision != GL_FP64);
+            const int n = m->g.n;
+            double2 *W = m->work.get();
+            k_copy<<<blocks_for(n), kBlock, 0, B->s>>>(n, W + 10 * (size_t)n, W + 7 * (size_t)n);
+            k_zero<<<blocks_for(n), kBlock, 0, B->s>>>(n, W + 8 * (size_t)n);
+            GLK_CHECK_LAUNCH();
+        }
+        std::vector<double> eta_first(B->meshes.size(), 0.0);
+        std::vector<int> solving = act;
+        for (int outer = 0; outer < 1000 && !solving.empty(); ++outer) {
+            batch_init(B, psi, solving, true, use_pre, 0.0, 0);
+            batch_gather(B);
+            std::vector<int> next;
+            for (int i : solving) {
+                const KrylovScalars &h = B->host_sc[i].ks;
+                if (h.status) { st[i] = (gl_status)h.status; continue; }
+                if (outer == 0) eta_first[i] = h.eta0;
+                if (h.eta0 <= ko.rtol * eta_first[i] || h.eta0 == 0.0) continue;  // converged
+                if (iters[i] >= ko.max_iter) continue;
+                KrylovScalars *ks = kscal_of(B->meshes[i]);
+                k_ks_set<<<1, 1, 0, B->s>>>(ks, ko.rtol * eta_first[i] / h.eta0, ko.max_iter - iters[i]);
+                k_ks_init_running<<<1, 1, 0, B->s>>>(ks);
+                GLK_CHECK_LAUNCH();
+                next.push_back(i);
+            }
+            solving.swap(next);
+            if (solving.empty()) break;
+            batch_iterate(B, psi, true, use_pre, ko.max_iter, poll);
+            std::vector<int> keep;
+            for (int i : solving) {
+                const KrylovScalars &h = B->host_sc[i].ks;
+                if (h.status) { st[i] = (gl_status)h.status; continue; }
+                const gl_mesh *m = B->meshes[i];
+                const int n = m->g.n;
+                double2 *W = m->work.get();
+                iters[i] += h.iter;
+                reorth_combine(m, m->rstate.get(), B->reorth, h.iter, W + 8 * (size_t)n, B->s);
+                if (h.iter == 0) continue;
+                const GeomT<double> g = geom_t<double>(m->g);
+                with_dim(m->g, [&](auto D) {
+                    k_residual_vec<decltype(D)::value><<<blocks_for(n), kBlock, 0, B->s>>>(
+                        g, psi[i], W + 8 * (size_t)n, W + 7 * (size_t)n, link_tab<double>(m), W + 10 * (size_t)n);
+                });
+                GLK_CHECK_LAUNCH();
+                keep.push_back(i);
+            }
+            solving.swap(keep);
+        }
+        return;
+    }
     if (!refine) {
         batch_init(B, psi, act, false, use_pre, ko.rtol, ko.max_iter);
         batch_iterate(B, psi, false, use_pre, ko.max_iter, poll);
@@ -1722,6 +1797,7 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
     std::vector<double> res(N, 0.0);
     std::vector<int> iters(N, 0);
     B->deflate = o.krylov.deflate;
+    B->reorth = o.krylov.reorth;
     for (int i = 0; i < N; ++i) k_ks_stop<<<1, 1, 0, B->s>>>(kscal_of(B->meshes[i]));
     GLK_CHECK_LAUNCH();
     // residual norms of the instances in `which` into out[i]
@@ -1905,8 +1981,6 @@ gl_status gl_batch_newton_solve(gl_batch *batch, void *const *psi_inout, const g
                 if (psi_inout[j] == psi_inout[i]) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: repeated psi");
         }
         check_krylov_opts(&opts->krylov, "gl_batch_newton_solve");
-        if (opts->krylov.reorth > 0)
-            fail(GL_ERR_UNSUPPORTED, "gl_batch_newton_solve: reorthogonalised solves are not batched");
         if (opts->max_steps < 0 || opts->max_steps > 63 || opts->fixed_steps < 0 || opts->fixed_steps > 63)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: steps must be in 0..63");
         if (opts->linesearch < 0 || opts->linesearch > 30)

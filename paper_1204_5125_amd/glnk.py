@@ -549,14 +549,16 @@ class Batch:
     def newton_solve(self, psis, tol=1e-10, max_steps=50, fixed_steps=0, use_precond=True,
                      krylov_rtol=1e-10, krylov_max_iter=1000, poll_every=8, inner_rtol=0.0,
                      precision=GL_FP64, cycles=1, max_coarse=64, max_levels=16, deflate=False, linesearch=0,
-                     stream=None, raise_on_fail=True):
+                     reorth=0, stream=None, raise_on_fail=True):
         """Newton on every instance in place (psis[i] on meshes[i]); returns
-        (status, [info dict per instance])."""
+        (status, [info dict per instance]).  reorth: the solves' Krylov basis
+        size (0: plain MINRES)."""
         if len(psis) != len(self.meshes):
             raise ValueError("one psi per mesh")
         ptrs = (C.c_void_p * len(psis))(*[_vec(p, m.n, "psi") for p, m in zip(psis, self.meshes)])
         o = NewtonOpts(tol, max_steps, fixed_steps, int(use_precond),
-                       KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, 0.0, int(deflate)),
+                       KrylovOpts(krylov_rtol, krylov_max_iter, poll_every, inner_rtol, 0.0, int(deflate),
+                                  int(reorth)),
                        AmgOpts(precision, cycles, max_coarse, max_levels), int(linesearch))
         infos = (NewtonInfo * len(psis))()
         rc = lib().gl_batch_newton_solve(self._h, ptrs, C.byref(o), infos, _stream(stream))

@@ -7,7 +7,8 @@ solution within 1e-10 of the oracle's iterate after the same count; a small
 basis that restarts; Newton; the FP32 V-cycle (with an FP32 copy of the
 basis for the reorthogonalisation: iterates within 1e-5), whose count stays
 that of the FP64 one (where plain MINRES needs about twice as many); the graph replay
-(poll interval) bitwise neutral; and the option errors."""
+(poll interval) bitwise neutral; batches bitwise equal to single solves; and
+the option errors."""
 import numpy as np
 import pytest
 
@@ -191,14 +192,30 @@ def test_reorth_errors(glnk):
         glnk.gl_jacobian_solve(mg, psi, pre, psi, x, relax_rtol=1e-4, reorth=50)
     with pytest.raises(RuntimeError, match="invalid Krylov options"):
         glnk.gl_jacobian_solve(mg, psi, pre, psi, x, reorth=-1)
-    # batches take no reorthogonalised solves (the options straight through the C-ABI)
-    import ctypes as C
-    batch = glnk.Batch([mg])
-    o = glnk.NewtonOpts(1e-10, 2, 0, 1, glnk.KrylovOpts(1e-10, 100, 8, 0.0, 0.0, 0, 50),
-                        glnk.AmgOpts(glnk.GL_FP64, 1, 64, 16), 0)
-    infos = (glnk.NewtonInfo * 1)()
-    ptrs = (C.c_void_p * 1)(psi.data_ptr())
-    rc = glnk.lib().gl_batch_newton_solve(batch.handle, ptrs, C.byref(o), infos, None)
-    assert rc == 8  # GL_ERR_UNSUPPORTED
-    with pytest.raises(RuntimeError, match="not batched"):
-        glnk._check(rc, "gl_batch_newton_solve")
+
+
+@pytest.mark.parametrize("deflate", [False, True], ids=["plain", "deflated"])
+@pytest.mark.parametrize("fp32", [False, True], ids=["fp64", "fp32"])
+def test_batch_equals_single(glnk, fp32, deflate):
+    """Reorthogonalised Newton in a batch of three shapes (2D grid, 3D grid,
+    disc) bitwise equal to the single solves."""
+    prec = glnk.GL_FP32 if fp32 else glnk.GL_FP64
+    ms, p0 = [], []
+    for name in ("2d-33x33", "3d-9^3", "disc-9"):
+        mg, mo, psi, b = pair(glnk, name)
+        ms.append(mg)
+        p0.append(inputs.random_phase_state(mo.n, seed=9))
+    kw = dict(fixed_steps=3, krylov_rtol=1e-10, krylov_max_iter=2000, max_coarse=16, precision=prec,
+              deflate=deflate, reorth=300)
+    singles = []
+    for m, p in zip(ms, p0):
+        psi = dev(p)
+        rc, info = glnk.gl_newton_solve(m, psi, raise_on_fail=False, **kw)
+        singles.append((info, host(psi)))
+    batch = glnk.Batch(ms)
+    psis = [dev(p) for p in p0]
+    rc, infos = batch.newton_solve(psis, raise_on_fail=False, **kw)
+    for (i1, ps1), i2, psi in zip(singles, infos, psis):
+        assert i1["res"] == i2["res"] and i1["krylov_iters"] == i2["krylov_iters"]
+        assert np.array_equal(ps1, host(psi))
+    assert sum(infos[0]["krylov_iters"]) > 0
