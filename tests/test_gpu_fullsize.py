@@ -6,7 +6,8 @@ an explicit sub-cycle).  The oracle handles every check here in seconds:
 operators over all nodes, the hierarchy, one V-cycle and the first Newton
 step's solve (16 MINRES iterations), and the second Newton step's strongly
 indefinite system (the 200-700-iteration solves), whose first 60 MINRES
-iterates are compared.  The same for the 129^3 cube, whose 5 592-row level
+iterates are compared, in plain MINRES and with the Krylov basis
+reorthogonalised.  The same for the 129^3 cube, whose 5 592-row level
 runs as an explicit sub-cycle.  Tolerances as in test_gpu_parity: FP64
 iterates after the same number of iterations within 1e-10, FP32
 preconditioner outputs within 1e-5.
@@ -161,6 +162,28 @@ def test_second_newton_system_full_size(glnk, setup):
     pre.apply(dev(r), z)
     e32 = relerr(host(z), ref)
     assert e32 < 1e-5, e32
+
+
+def test_second_newton_system_reorth_full_size(glnk, setup):
+    """The same system solved with the Krylov basis reorthogonalised, in the
+    headline's configuration: the first 60 iterates with the FP64 V-cycle
+    equal the oracle's reorthogonalised MINRES within 1e-10, with the FP32
+    V-cycle (FP32 copy of the basis) within 1e-5."""
+    mg, mo, psi0, _ = setup
+    psi1, _ = oracle.newton(mo, psi0, fixed_steps=1, krylov_rtol=1e-10, krylov_max_iter=400,
+                            max_coarse=MAX_COARSE)
+    amg = oracle.Amg.for_state(mo, psi1, max_coarse=MAX_COARSE)
+    b = -mo.gl(psi1)
+    xo, io, _ = oracle.minres(mo, psi1, b, amg=amg, rtol=0.0, max_iter=60, reorth=400)
+    x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    for prec, tol in ((glnk.GL_FP64, 1e-10), (glnk.GL_FP32, 1e-5)):
+        pre = glnk.Precond(mg, dev(psi1), precision=prec, max_coarse=MAX_COARSE)
+        glnk.gl_precond_set_tiles(pre, *TILES)
+        rc, ig = glnk.gl_jacobian_solve(mg, dev(psi1), pre, dev(b), x, rtol=0.0, max_iter=60, poll_every=16,
+                                        reorth=400, raise_on_fail=False)
+        assert ig["iterations"] == 60 == io["iterations"]
+        e = relerr(host(x), xo)
+        assert e < tol, (prec, e)
 
 
 # the 3D benchmark: 129^3 cube, side 5, mu 0.6 along (1, 1, 1)/sqrt 3, tiles
