@@ -412,19 +412,23 @@ def bench_continuation(args):
     log(f"[bench] U-Net forward: {fwd_ms:.2f} ms, {unet_roof['achieved']:.1f} TFLOP/s")
     mus = [0.02 * k for k in range(101)]
     runs = {}
-    variants = [("fp64_secant", glnk.GL_FP64, None, False),
-                ("fp64_learned", glnk.GL_FP64, "residual", False),
-                ("fp64_learned_always", glnk.GL_FP64, "always", False),
-                ("fp64_secant_deflated", glnk.GL_FP64, None, True),
-                ("fp32_secant_deflated", glnk.GL_FP32, None, True),
-                ("fp64_learned_always_deflated", glnk.GL_FP64, "always", True),
-                ("fp32_learned_always_deflated", glnk.GL_FP32, "always", True)]
-    for name, prec, learned, defl in variants:
+    variants = [("fp64_secant", glnk.GL_FP64, None, False, 0),
+                ("fp64_learned", glnk.GL_FP64, "residual", False, 0),
+                ("fp64_learned_always", glnk.GL_FP64, "always", False, 0),
+                ("fp64_secant_deflated", glnk.GL_FP64, None, True, 0),
+                ("fp32_secant_deflated", glnk.GL_FP32, None, True, 0),
+                ("fp64_learned_always_deflated", glnk.GL_FP64, "always", True, 0),
+                ("fp32_learned_always_deflated", glnk.GL_FP32, "always", True, 0),
+                # MINRES with the Krylov basis reorthogonalised (Sec. 4's
+                # remedy), where the FP32 V-cycle keeps the FP64 count
+                ("fp32_secant_deflated_reorth", glnk.GL_FP32, None, True, REORTH),
+                ("fp32_learned_always_deflated_reorth", glnk.GL_FP32, "always", True, REORTH)]
+    for name, prec, learned, defl, reorth in variants:
         pred = predictor.LearnedPredictor(net, mesh, select=learned) if learned else None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         recs, _, _ = continuation.continuation_path(mesh, ones, mus, precision=prec, predictor=pred,
-                                                    callback=progress(name), deflate=defl, **common)
+                                                    callback=progress(name), deflate=defl, reorth=reorth, **common)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         runs[name] = {"seconds": dt, "steps": len(recs) - 1,
@@ -455,7 +459,9 @@ def bench_continuation(args):
                      "deflated_vs_plain_fp64_secant": base_run["seconds"] / runs["fp64_secant_deflated"]["seconds"],
                      "fp32_vs_fp64_deflated_secant": runs["fp64_secant_deflated"]["seconds"]
                      / runs["fp32_secant_deflated"]["seconds"],
-                     "mixed_learned_deflated_vs_plain_fp64": base_run["seconds"] / mixed["seconds"]},
+                     "mixed_learned_deflated_vs_plain_fp64": base_run["seconds"] / mixed["seconds"],
+                     "mixed_learned_deflated_reorth_vs_plain_fp64":
+                         base_run["seconds"] / runs["fp32_learned_always_deflated_reorth"]["seconds"]},
         "data": "synthetic: continuation of psi = 1 from mu = 0 on a uniform grid; training states from a seeded sweep",
         "config": {"workload": "2D 513x513 grid, side 8, mu 0 -> 2 in steps of 0.02 (Newton to 1e-10); U-Net 4 levels, "
                                "32 base channels, BF16 / FP32 accumulation",

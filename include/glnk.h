@@ -344,7 +344,11 @@ typedef struct {
                           Z y from the stored preconditioned vectors.  A
                           full basis restarts from the true residual (a
                           restart slows these indefinite solves down: size
-                          reorth to the expected iteration count).  The
+                          reorth to the expected iteration count); each
+                          start measures the true residual, and the solve
+                          ends unconverged when a restart has not halved it
+                          (the attainable accuracy is above rtol) or after
+                          64 starts.  The
                           mesh keeps the basis, 2 (reorth + 1) n complex
                           doubles, allocated by the first such solve and
                           grown when a larger one comes.  Not with

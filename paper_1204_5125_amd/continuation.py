@@ -13,7 +13,7 @@ from . import glnk
 
 def continuation_path(mesh, psi0, mus, tol=1e-10, krylov_rtol=1e-10, krylov_max_iter=4000, max_newton=30,
                       precision=glnk.GL_FP64, max_coarse=64, max_halvings=3, predictor=None, keep=False,
-                      callback=None, poll_every=8, deflate=False):
+                      callback=None, poll_every=8, deflate=False, reorth=0):
     """Continue from psi0 (corrected by Newton at mus[0]) through the field
     values mus.  Each step predicts psi at the next mu -- secant
     psi_m + r (psi_m - e^{i chi} psi_{m-1}) with r the ratio of the steps, or
@@ -27,12 +27,13 @@ def continuation_path(mesh, psi0, mus, tol=1e-10, krylov_rtol=1e-10, krylov_max_
     Returns (records, psi, states): states lists (mu, tensor) of every
     converged point when keep is set.  deflate: every Newton step under the
     phase condition <i psi, dpsi>_R = 0 (Jacobian solves on the complement
-    of the gauge mode)."""
+    of the gauge mode); reorth > 0: the Jacobian solves store and
+    reorthogonalise their Krylov basis (at most reorth vectors)."""
     import torch
     handle = glnk.PrecondHandle(mesh)
     opts = dict(tol=tol, max_steps=max_newton, krylov_rtol=krylov_rtol, krylov_max_iter=krylov_max_iter,
                 precision=precision, max_coarse=max_coarse, precond=handle, raise_on_fail=False,
-                poll_every=poll_every, deflate=deflate)
+                poll_every=poll_every, deflate=deflate, reorth=reorth)
     psi = psi0.clone()
     mesh.set_field(mus[0])
     rc, info = glnk.gl_newton_solve(mesh, psi, **opts)

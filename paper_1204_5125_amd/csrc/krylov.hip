@@ -800,6 +800,10 @@ static void reorth_combine(const gl_mesh *m, double *rs, int kmax, int cols, dou
     GLK_HIP(hipStreamSynchronize(s));
 }
 
+// starts of a reorthogonalised solve at most (as the refinement's outer
+// rounds); each one measures the true residual
+constexpr int kMaxStarts = 64;
+
 // The mesh's basis and state for kmax vectors (grown, never shrunk).  The
 // cached iteration graphs are dropped when the buffers move (a graph holds
 // their addresses; the stream is idle between solves).
@@ -1075,8 +1079,8 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
         k.rb32 = fp64 ? nullptr : mm->rbasis32.get();
         k.rs = mm->rstate.get();
         k.kmax = kmax;
-        double eta_first = 0.0;
-        for (;;) {
+        double eta_first = 0.0, eta_prev = 0.0;
+        for (int start = 0; start < kMaxStarts; ++start) {
             ksolve_init<DIM>(k, 0.0, 0, Launch{s});
             read_scalars(m, &h, s);
             if (h.status) { st = (gl_status)h.status; break; }
@@ -1084,6 +1088,10 @@ static gl_status minres_run(const gl_mesh *m, const double2 *psi, const gl_preco
             res_est = eta_first > 0 ? h.eta0 / eta_first : 0.0;
             if (h.eta0 <= o.rtol * eta_first || h.eta0 == 0.0) { converged = true; break; }
             if (iters >= o.max_iter) break;
+            // a restart that has not halved the true residual: the system's
+            // attainable accuracy is above rtol (near a singular J); stop
+            if (start > 0 && h.eta0 > 0.5 * eta_prev) break;
+            eta_prev = h.eta0;
             const int budget = o.max_iter - iters;
             k_ks_set<<<1, 1, 0, s>>>(ks, o.rtol * eta_first / h.eta0, budget);
             k_ks_init_running<<<1, 1, 0, s>>>(ks);
@@ -1679,9 +1687,9 @@ static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int>
             k_zero<<<blocks_for(n), kBlock, 0, B->s>>>(n, W + 8 * (size_t)n);
             GLK_CHECK_LAUNCH();
         }
-        std::vector<double> eta_first(B->meshes.size(), 0.0);
+        std::vector<double> eta_first(B->meshes.size(), 0.0), eta_prev(B->meshes.size(), 0.0);
         std::vector<int> solving = act;
-        for (int outer = 0; outer < 1000 && !solving.empty(); ++outer) {
+        for (int outer = 0; outer < kMaxStarts && !solving.empty(); ++outer) {
             batch_init(B, psi, solving, true, use_pre, 0.0, 0);
             batch_gather(B);
             std::vector<int> next;
@@ -1691,6 +1699,8 @@ static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int>
                 if (outer == 0) eta_first[i] = h.eta0;
                 if (h.eta0 <= ko.rtol * eta_first[i] || h.eta0 == 0.0) continue;  // converged
                 if (iters[i] >= ko.max_iter) continue;
+                if (outer > 0 && h.eta0 > 0.5 * eta_prev[i]) continue;  // stagnated, as a single solve
+                eta_prev[i] = h.eta0;
                 KrylovScalars *ks = kscal_of(B->meshes[i]);
                 k_ks_set<<<1, 1, 0, B->s>>>(ks, ko.rtol * eta_first[i] / h.eta0, ko.max_iter - iters[i]);
                 k_ks_init_running<<<1, 1, 0, B->s>>>(ks);

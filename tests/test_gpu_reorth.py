@@ -219,3 +219,18 @@ def test_batch_equals_single(glnk, fp32, deflate):
         assert i1["res"] == i2["res"] and i1["krylov_iters"] == i2["krylov_iters"]
         assert np.array_equal(ps1, host(psi))
     assert sum(infos[0]["krylov_iters"]) > 0
+
+
+def test_unattainable_tolerance_stops(glnk):
+    """Asked for a tolerance below the attainable accuracy, the
+    reorthogonalised solve stops once a restart no longer halves the true
+    residual (NOT_CONVERGED), far below its iteration limit, with the
+    accuracy the system allows."""
+    mg, mo, psi, b = pair(glnk, "2d-33x33")
+    pre = glnk.Precond(mg, dev(psi), max_coarse=16)
+    x = torch.empty(mo.n, dtype=torch.complex128, device="cuda")
+    rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=1e-17, max_iter=5000, reorth=500,
+                                      raise_on_fail=False)
+    assert rc == 4 and not info["converged"]
+    assert info["iterations"] < 1000
+    assert info["res_true"] < 1e-12
