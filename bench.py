@@ -51,8 +51,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "3c9fa06f4e1d704479cc63ad313335b58fb8420fb8554899d6277fa33b9b4efa",
-           8: 4980756.4, 2: 21188671.3}
+TRAFFIC = {"csrc_sha256": "ef0fd6a2b8825b464481184794672dd44e3996f202de189edbb5d228b1ed1c5e",
+           8: 4980747.2, 2: 21189678.1}
 
 
 def csrc_fingerprint():
