@@ -348,9 +348,14 @@ typedef struct {
                           start measures the true residual, and the solve
                           ends unconverged when a restart has not halved it
                           (the attainable accuracy is above rtol) or after
-                          64 starts.  The
-                          mesh keeps the basis, 2 (reorth + 1) n complex
-                          doubles, allocated by the first such solve and
+                          64 starts.  With a reduced-precision V-cycle the
+                          passes read a BF16 copy of Z for the coefficients
+                          and an FP32 copy of V for the update (the Lanczos
+                          coefficients and x stay FP64).  The mesh keeps
+                          the basis, with an FP64 V-cycle Z and V in FP64
+                          (32 (reorth + 1) n bytes), with a reduced-precision
+                          one Z in FP64 plus the two copies (28 (reorth + 1)
+                          n bytes), allocated by the first such solve and
                           grown when a larger one comes.  Not with
                           inner_rtol or relax_rtol > 0 (INVALID_ARGUMENT).
                           Batches keep each mesh's basis the same way.

@@ -379,7 +379,7 @@ struct gl_mesh {
     glk::DevBuf<double2> work;       // kWorkVecs * n
     // reorthogonalised solves (rcap vectors): Z in FP64 (x = Z y) then, for
     // FP64 V-cycles, V in FP64; for reduced-precision V-cycles the basis
-    // the reorthogonalisation reads, Z then V, in FP32; the projected
+    // the reorthogonalisation reads, Z in BF16 then V in FP32; the projected
     // matrix's state (R, rotations, g, coefficients, partials)
     glk::DevBuf<double2> rbasis;
     glk::DevBuf<float2> rbasis32;

@@ -31,6 +31,24 @@ namespace glk {
 // to a multiple of 4 (aligned wide loads)
 __host__ __device__ inline size_t reorth_ld(int n) { return ((size_t)n + 3) & ~(size_t)3; }
 
+// A complex number as two BF16 halves of one 32-bit word (real part low),
+// rounded to nearest even from FP32: the reorthogonalisation's copy of Z
+// with a reduced-precision V-cycle (it only steers the coefficients h_i,
+// whose rounding moves the basis' orthogonality, not the recorded relation)
+__device__ __forceinline__ uint32_t bf16_bits(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ uint32_t pack_bf16(double2 v)
+{
+    return bf16_bits((float)v.x) | (bf16_bits((float)v.y) << 16);
+}
+__device__ __forceinline__ double2 unpack_bf16(uint32_t w)
+{
+    return make_double2(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u));
+}
+
 __global__ void k_ks_init_running(KrylovScalars *ks)
 {
     ks->running = (ks->eta0 > 0.0) && (ks->max_iter > 0) && (ks->status == 0);
@@ -123,7 +141,7 @@ struct MinresJapply {
     int defl;
     double2 *zb = nullptr;  // reorthogonalised solves: the basis Z (z_j / gamma_j stored
                             // at slot j); no w / x update then
-    float2 *zb32 = nullptr; // and its FP32 copy (reduced-precision V-cycles)
+    uint32_t *zbh = nullptr; // and its BF16 copy (reduced-precision V-cycles)
     __device__ void operator()(int bx, int nbx) const
     {
         // the scalars and the vectors are loaded together; the (uniform)
@@ -166,7 +184,7 @@ struct MinresJapply {
                 const double2 zs = cscale(z[i], ig);
                 const size_t at = (size_t)jt * reorth_ld(g.n) + i;
                 zb[at] = zs;
-                if (zb32) zb32[at] = make_float2((float)zs.x, (float)zs.y);
+                if (zbh) zbh[at] = pack_bf16(zs);
             }
             q[i] = qi;
         }
@@ -220,12 +238,27 @@ struct MinresVupdate {
 // host solves R y = g and x += Z y (k_basis_combine).  Every kernel reads j
 // from the device scalars, so the graph of two iterations replays.
 
-constexpr int kReorthGroup = 8;  // basis vectors per block reduction
+// The multiply-adds of the passes are written as fma, so their rounding does
+// not depend on the compiler's contraction choices.
 
 // Basis vectors are stored with the padded stride ld = n rounded up to a
 // multiple of 4, four nodes per thread: the FP32 entries of a thread are two
-// aligned 16-byte loads.  Entries past n are never used (selected away).
+// aligned 16-byte loads, the BF16 ones one.  Entries past n are never used
+// (selected away).
 constexpr int kReorthNodes = 4;
+
+__device__ __forceinline__ void load4(const uint32_t *p, double2 out[4])
+{
+    const uint4 w = reinterpret_cast<const uint4 *>(p)[0];
+    out[0] = unpack_bf16(w.x);
+    out[1] = unpack_bf16(w.y);
+    out[2] = unpack_bf16(w.z);
+    out[3] = unpack_bf16(w.w);
+}
+
+template <class T>
+__device__ __forceinline__ void load4(const C<T> *p, double2 out[4]);
+__device__ __forceinline__ void load4(const double2 *p, double2 out[4]) { load4<double>(p, out); }
 
 template <class T>
 __device__ __forceinline__ void load4(const C<T> *p, double2 out[4])
@@ -243,15 +276,18 @@ __device__ __forceinline__ void load4(const C<T> *p, double2 out[4])
 }
 
 // partials of h_i = <Z_i, q>_E, i = 0 .. j, one per wave: part[i * nparts +
-// wave].  The basis is read in FP64 with an FP64 V-cycle and in FP32 with a
+// wave].  The basis is read in FP64 with an FP64 V-cycle and as BF16 with a
 // reduced-precision one (the coefficients are of the size of the loss of
 // orthogonality, and every one subtracted is also the one recorded in the
 // projected matrix, so the relation J Z = V H holds to FP64 rounding either
-// way).  No barrier: each wave keeps kReorthGroup sums in flight.
-template <class T>
+// way; their rounding only sets how orthogonal the basis stays).  No
+// barrier: each wave keeps G rows of the basis in flight.
+template <class S>
 struct ReorthDots {
+    // rows in flight per thread: 4 (16 bytes each in BF16, 64 in FP64)
+    static constexpr int G = 4;
     int n, nparts;
-    const C<T> *zb;
+    const S *zb;  // double2 (FP64) or uint32_t (BF16 pairs)
     const double2 *q;
     double *part;
     const KrylovScalars *ks;
@@ -262,7 +298,9 @@ struct ReorthDots {
         const size_t ld = reorth_ld(n);
         const int t = bx * kBlock + threadIdx.x, base = t * kReorthNodes;
         const int wave = t >> 6, lane = threadIdx.x & 63;
-        const bool any = base < n;
+        // a thread past n reads the first nodes (always present) and selects
+        // its terms away
+        const int cb = base < n ? base : 0;
         double2 qv[kReorthNodes];
         bool ok[kReorthNodes];
 #pragma unroll
@@ -270,24 +308,24 @@ struct ReorthDots {
             ok[e] = base + e < n;
             qv[e] = ok[e] ? q[base + e] : make_double2(0.0, 0.0);
         }
-        for (int k0 = 0; k0 <= j; k0 += kReorthGroup) {
-            double sv[kReorthGroup];
+        for (int k0 = 0; k0 <= j; k0 += G) {
+            // every load of the group first, with no branch between them, so
+            // that all are in flight together (rows past j re-read row j)
+            double2 zv[G][kReorthNodes];
 #pragma unroll
-            for (int g = 0; g < kReorthGroup; ++g) {
+            for (int g = 0; g < G; ++g) load4(zb + (size_t)min(k0 + g, j) * ld + cb, zv[g]);
+            double sv[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
                 double acc = 0.0;
-                if (any && k0 + g <= j) {
-                    double2 zv[kReorthNodes];
-                    load4<T>(zb + (size_t)(k0 + g) * ld + base, zv);
 #pragma unroll
-                    for (int e = 0; e < kReorthNodes; ++e) acc += ok[e] ? redot(zv[e], qv[e]) : 0.0;
-                }
-                sv[g] = acc;
+                for (int e = 0; e < kReorthNodes; ++e)
+                    acc = ok[e] ? fma(zv[g][e].y, qv[e].y, fma(zv[g][e].x, qv[e].x, acc)) : acc;
+                sv[g] = wave_sum(acc);
             }
-#pragma unroll
-            for (int g = 0; g < kReorthGroup; ++g) sv[g] = wave_sum(sv[g]);
             if (lane == 0) {
 #pragma unroll
-                for (int g = 0; g < kReorthGroup; ++g)
+                for (int g = 0; g < G; ++g)
                     if (k0 + g <= j) part[(size_t)(k0 + g) * nparts + wave] = sv[g];
             }
         }
@@ -335,7 +373,8 @@ struct ReorthUpdate {
             load4<T>(vb + (size_t)k * ld + base, vv);
             const double hk = h[k];
 #pragma unroll
-            for (int e = 0; e < kReorthNodes; ++e) acc[e] = csub(acc[e], cscale(vv[e], hk));
+            for (int e = 0; e < kReorthNodes; ++e)
+                acc[e] = make_double2(fma(-vv[e].x, hk, acc[e].x), fma(-vv[e].y, hk, acc[e].y));
         }
 #pragma unroll
         for (int e = 0; e < kReorthNodes; ++e)
@@ -752,7 +791,7 @@ struct Ksolve {
     // reorthogonalised solves: the basis (V then Z, kmax vectors each) and
     // the projected matrix's state; rb == nullptr: plain MINRES
     double2 *rb = nullptr;
-    float2 *rb32 = nullptr;  // non-null: the reorthogonalisation reads the FP32 basis
+    float2 *rb32 = nullptr;  // non-null: the reorthogonalisation reads the BF16 Z and FP32 V copies
     double *rs = nullptr;
     int kmax = 0;
 };
@@ -821,7 +860,7 @@ static void ensure_reorth(gl_mesh *m, int kmax, bool fp32)
     m->rcap = 0;
     m->rcap_v64 = m->rcap_32 = false;
     m->rbasis.alloc((v64 ? 2 : 1) * (size_t)kmax * n);
-    if (b32) m->rbasis32.alloc(2 * (size_t)kmax * n);
+    if (b32) m->rbasis32.alloc(3 * (size_t)kmax * n / 2);  // BF16 Z (half a float2 each), FP32 V
     m->rstate.alloc((size_t)(kmax + 1) * kmax + 2 * (size_t)kmax + 2 * (size_t)(kmax + 1) + nbd * kmax);
     m->rcap = kmax;
     m->rcap_v64 = v64;
@@ -895,15 +934,17 @@ static void enqueue_iteration(Ksolve &k, const Launch &L)
     const GeomT<double> g = geom_t<double>(m->g);
     KrylovScalars *ks = reinterpret_cast<KrylovScalars *>(m->kscal.get());
     const int *gate = &ks->running;
-    // the basis: Z (FP64) and V (FP64), or Z (FP64) plus Z and V in FP32
+    // the basis: Z (FP64) and V (FP64), or Z (FP64) plus Z in BF16 and V in
+    // FP32 (kn is even: ld is a multiple of 4, so V starts 16-byte aligned)
     const size_t kn = (size_t)k.kmax * reorth_ld(n);
     const int nbr = reorth_blocks(n), npr = reorth_parts(n);
     double2 *zb = k.rb;
     double2 *vb = k.rb && !k.rb32 ? k.rb + kn : nullptr;
-    float2 *zb32 = k.rb32, *vb32 = k.rb32 ? k.rb32 + kn : nullptr;
+    uint32_t *zbh = k.rb32 ? reinterpret_cast<uint32_t *>(k.rb32) : nullptr;  // BF16 Z, then FP32 V
+    float2 *vb32 = k.rb32 ? k.rb32 + kn / 2 : nullptr;
     prof_launch(PROF_MINRES_JAPPLY, 48.0 * n + 96.0 * n, L, [&] {
         L.run(nb, MinresJapply<DIM>{g, k.psi, k.z, link_tab<double>(m), k.q, k.zn, k.w, k.wp, k.x, ks,
-                                    red_slot(m, 0), red_slot(m, 2), k.defl ? 1 : 0, zb, zb32});
+                                    red_slot(m, 0), red_slot(m, 2), k.defl ? 1 : 0, zb, zbh});
     });
     launch_finalize(red_slot(m, 0).partials, nb, FIN_DELTA, ks, nullptr, gate, L);
     if (k.defl) {
@@ -919,11 +960,11 @@ static void enqueue_iteration(Ksolve &k, const Launch &L)
     if (k.rb) {
         R = reorth_layout(k.rs, k.kmax);
         if (k.rb32) {
-            L.run(nbr, ReorthDots<float>{n, npr, zb32, k.vp, R.part, ks});
+            L.run(nbr, ReorthDots<uint32_t>{n, npr, zbh, k.vp, R.part, ks});
             L.run(k.kmax, ReorthSum{npr, R.part, R.h, ks});
             L.run(nbr, ReorthUpdate<float>{n, vb32, R.h, k.vp, ks});
         } else {
-            L.run(nbr, ReorthDots<double>{n, npr, zb, k.vp, R.part, ks});
+            L.run(nbr, ReorthDots<double2>{n, npr, zb, k.vp, R.part, ks});
             L.run(k.kmax, ReorthSum{npr, R.part, R.h, ks});
             L.run(nbr, ReorthUpdate<double>{n, vb, R.h, k.vp, ks});
         }

@@ -18,16 +18,20 @@
 
 namespace glk {
 
+// Both kernels inline the step body.  Left to itself the compiler inlines
+// it into k_one but may call it out of line from k_many, with more
+// registers and, where it contracts multiply-adds differently in the two
+// copies, other rounding: a batch would then not equal the single solves.
 template <class A, int BS>
 __global__ __launch_bounds__(BS) void k_one(A a)
 {
-    a(blockIdx.x, gridDim.x);
+    [[clang::always_inline]] a(blockIdx.x, gridDim.x);
 }
 
 template <class A, int BS>
 __global__ __launch_bounds__(BS) void k_many(const A *__restrict__ a)
 {
-    a[blockIdx.y](blockIdx.x, gridDim.x);
+    [[clang::always_inline]] a[blockIdx.y](blockIdx.x, gridDim.x);
 }
 
 // one recorded dispatch

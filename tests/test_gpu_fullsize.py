@@ -168,7 +168,9 @@ def test_second_newton_system_reorth_full_size(glnk, setup):
     """The same system solved with the Krylov basis reorthogonalised, in the
     headline's configuration: the first 60 iterates with the FP64 V-cycle
     equal the oracle's reorthogonalised MINRES within 1e-10, with the FP32
-    V-cycle (FP32 copy of the basis) within 1e-5."""
+    V-cycle (BF16 copy of Z and FP32 copy of V for the passes) within 1e-5
+    (the BF16 rounding errors of the coefficients' n-term sums partly
+    cancel at a million nodes)."""
     mg, mo, psi0, _ = setup
     psi1, _ = oracle.newton(mo, psi0, fixed_steps=1, krylov_rtol=1e-10, krylov_max_iter=400,
                             max_coarse=MAX_COARSE)

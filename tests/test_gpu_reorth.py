@@ -4,8 +4,9 @@ against the oracle's, through the C-ABI: fixed-k iterates within 1e-12 on
 grids (2D, 3D, ragged) and a simplicial mesh, plain and deflated, with and
 without a preconditioner; converged counts within 1 of the oracle's and the
 solution within 1e-10 of the oracle's iterate after the same count; a small
-basis that restarts; Newton; the FP32 V-cycle (with an FP32 copy of the
-basis for the reorthogonalisation: iterates within 1e-5), whose count stays
+basis that restarts; Newton; the FP32 V-cycle (with a BF16 copy of Z and
+an FP32 copy of V for the reorthogonalisation: iterates within 1e-4, the
+minimised residual norm within 1e-6), whose count stays
 that of the FP64 one (where plain MINRES needs about twice as many); the graph replay
 (poll interval) bitwise neutral; batches bitwise equal to single solves; and
 the option errors."""
@@ -157,16 +158,30 @@ def test_fp32_vcycle_keeps_the_fp64_count(glnk):
             counts[prec, reorth] = info["iterations"]
     assert abs(counts[glnk.GL_FP32, 500] - counts[glnk.GL_FP64, 500]) <= 2
     assert counts[glnk.GL_FP64, 500] < counts[glnk.GL_FP64, 0]
-    # the FP32 mode (FP32 V-cycle, FP32 copy of the basis for the
-    # reorthogonalisation) against the oracle's FP64 iterates, to the FP32
-    # V-cycle's own bound
+    # the FP32 mode (FP32 V-cycle; the reorthogonalisation's coefficients
+    # from a BF16 copy of Z, its update from an FP32 copy of V) against the
+    # oracle's FP64 iterates.  The BF16 rounding (unit roundoff 2^-9) falls
+    # on the correction coefficients only, which are of the size of the loss
+    # of orthogonality (the Lanczos coefficients are FP64), so the basis
+    # stays orthogonal to about 2^-9 of that: the iterate moves within the
+    # Krylov space by about 1e-5 relative (bound 1e-4).  The minimised norm
+    # moves only to second order, since the minimiser's residual is
+    # M-orthogonal to J K_k: ||r||_M^2 = ||r*||_M^2 + ||J e||_M^2 for an
+    # iterate x* + e; bound 1e-6 relative (the FP32 V-cycle's own rounding
+    # moves it by about 1e-9).
     amg = oracle.Amg.for_state(mo, psi, max_coarse=16)
     pre = glnk.Precond(mg, dev(psi), precision=glnk.GL_FP32, max_coarse=16)
+
+    def res_m(xv):
+        r = b - mo.jac(psi, xv)
+        return np.sqrt(mo.inner(r, amg.precond(mo, r)))
+
     for k in (5, 20, 60):
         xo, _, _ = oracle.minres(mo, psi, b, amg=amg, rtol=0.0, max_iter=k, reorth=500)
         rc, info = glnk.gl_jacobian_solve(mg, dev(psi), pre, dev(b), x, rtol=0.0, max_iter=k, reorth=500,
                                           raise_on_fail=False)
-        assert relerr(host(x), xo) < 1e-5, k
+        assert relerr(host(x), xo) < 1e-4, k
+        assert abs(res_m(host(x)) / res_m(xo) - 1.0) < 1e-6, k
 
 
 def test_poll_interval_is_bitwise_neutral(glnk):
