@@ -51,8 +51,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "ef0fd6a2b8825b464481184794672dd44e3996f202de189edbb5d228b1ed1c5e",
-           8: 4980747.2, 2: 21189678.1}
+TRAFFIC = {"csrc_sha256": "929c8d9e845bf5fa065b3a5d6e2b32c3ef94503869f1c1870711bf62529fce68",
+           8: 4980731.5, 2: 21188651.9}
 
 
 def csrc_fingerprint():
@@ -66,7 +66,7 @@ def csrc_fingerprint():
     return h.hexdigest()
 RELAX = 1e-4   # relaxed variant: FP64 V-cycle until the MINRES estimate falls below this
 REORTH = 400   # Krylov basis of the reorthogonalised solves (above every solve's count here)
-BATCH_REORTH = 300  # per instance in the batch (64 bases: 32 B per node and vector)
+BATCH_REORTH = 300  # per instance in the batch (64 bases: 32 B per node and vector in FP64, 28 in FP32)
 
 
 def run_steps(glnk, torch, mesh, psi0, psi, handle, precision, steps, relax=0.0, reorth=0):
@@ -950,12 +950,12 @@ def main():
                  "bytes_by_kernel_class": by_class, "bytes_coarse_residual_transfer_dense": rest,
                  "traffic": None}
     # the headline leg: the same kernels per iteration plus the basis traffic
-    # of the reorthogonalisation, per node 8 (j + 1) bytes read by the dots
-    # (FP32 Z) and 8 (j + 1) by the update (FP32 V) in iteration j, 32 bytes
-    # written (Z in FP64 and FP32, V in FP32), and 16 read per stored vector
+    # of the reorthogonalisation, per node 4 (j + 1) bytes read by the dots
+    # (BF16 Z) and 8 (j + 1) by the update (FP32 V) in iteration j, 28 bytes
+    # written (Z in FP64 and BF16, V in FP32), and 16 read per stored vector
     # by x = Z y at the end of each solve
     its = info_head[-1]["krylov_iters"]
-    basis = sum(sum(16.0 * (j + 1) + 32.0 for j in range(k)) + 16.0 * k for k in its) * mesh.n
+    basis = sum(sum(12.0 * (j + 1) + 28.0 for j in range(k)) + 16.0 * k for k in its) * mesh.n
     bytes_iter_r = bytes_iter + basis / sum(its)
     t_iter_r = t_head / args.steps / sum(its)
     roof_iter_r = {"bound": "hbm", "kernel": "one reorthogonalised MINRES iteration, FP32 V-cycle (all kernels)",
