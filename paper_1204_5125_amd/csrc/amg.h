@@ -274,9 +274,20 @@ void vcycle_enqueue(const gl_precond *pre, const double2 *v, double2 *z, const i
                     KrylovScalars *ks, int mode, const Launch &L);  // in the handle's precision
 void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
                          hipStream_t s);
+// the same two dispatches (residual with block partials, fixed-order sum),
+// launched or recorded; no profiling brackets
+void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
+                         const Launch &L);
 void jacobian_enqueue(const gl_mesh *m, const double2 *psi, const double2 *phi, double2 *out,
                       hipStream_t s);
 void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s);
+// A numeric setup in two halves, so that many instances can be recorded and
+// run as batched dispatches: every kernel (launched or recorded; the coarsest
+// factor's failure flag is left in pre->status), then, with that flag read,
+// the error check, the explicit sub-cycle and R_inf's step count.
+void precond_numeric_enqueue(gl_precond *pre, const double2 *psi, const Launch &L);
+void precond_numeric_finish(gl_precond *pre, bool singular, hipStream_t s);
+void check_amg_opts(const gl_amg_opts *opts, const char *who);
 void pcg_calibrate(gl_precond *pre, hipStream_t s);  // R_inf: the CG step count of this setup
 constexpr int kPcgMaxSteps = 64;
 void scale_by_volume(const gl_mesh *m, const double2 *x, double2 *y, hipStream_t s);

@@ -166,32 +166,39 @@ __global__ void k_l0_cols(Geom g, const int *rp, int *ci)
 
 // H = K-hat + 2 D |psi|^2 in the same entry order
 template <int DIM>
-__global__ void k_l0_values(GeomT<double> g, const int *rp, const LinkTab<double> U,
-                            const double2 *__restrict__ psi, double2 *v, double *diag)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int c[3];
-    node_coords<DIM>(g.N, i, c);
-    double s[3];
-    const double d = node_volume<DIM, double>(g, c, s);
-    int p = rp[i];
-    double asum = 0.0;
-    for (int a = DIM - 1; a >= 0; --a)
-        if (c[a] > 0) {
+struct L0Values {
+    GeomT<double> g;
+    const int *rp;
+    LinkTab<double> U;
+    const double2 *__restrict__ psi;
+    double2 *v;
+    double *diag;
+    __device__ void operator()(int, int) const
+    {
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int c[3];
+        node_coords<DIM>(g.N, i, c);
+        double s[3];
+        const double d = node_volume<DIM, double>(g, c, s);
+        int p = rp[i];
+        double asum = 0.0;
+        for (int a = DIM - 1; a >= 0; --a)
+            if (c[a] > 0) {
+                const double al = d * s[a] * g.inv_h2[a];
+                v[p++] = cscale(link_u<DIM, double>(U, a, c, c[a] - 1), -al);
+            }
+        const int pd = p++;
+        for (int a = 0; a < DIM; ++a) {
             const double al = d * s[a] * g.inv_h2[a];
-            v[p++] = cscale(link_u<DIM, double>(U, a, c, c[a] - 1), -al);
+            if (c[a] < g.N[a] - 1) v[p++] = cscale(cconj(link_u<DIM, double>(U, a, c, c[a])), -al);
+            asum += al * ((c[a] > 0) + (c[a] < g.N[a] - 1));
         }
-    const int pd = p++;
-    for (int a = 0; a < DIM; ++a) {
-        const double al = d * s[a] * g.inv_h2[a];
-        if (c[a] < g.N[a] - 1) v[p++] = cscale(cconj(link_u<DIM, double>(U, a, c, c[a])), -al);
-        asum += al * ((c[a] > 0) + (c[a] < g.N[a] - 1));
+        const double dg = asum + 2.0 * d * cabs2(psi[i]);
+        v[pd] = make_double2(dg, 0.0);
+        diag[i] = dg;
     }
-    const double dg = asum + 2.0 * d * cabs2(psi[i]);
-    v[pd] = make_double2(dg, 0.0);
-    diag[i] = dg;
-}
+};
 
 // Level 0 of a simplicial mesh: its adjacency with the diagonal inserted
 // (columns ascending), H_jj = K-hat_jj + 2 |V_j| |psi_j|^2, H_jk = -kw_jk
@@ -217,17 +224,23 @@ __global__ void k_l0s_cols(int n, const int *arp, const int *aci, const int *rp,
     if (!diag) ci[p] = i;
 }
 
-__global__ void k_l0s_values(GeomT<double> g, const int *rp, const int *ci, const double2 *__restrict__ psi,
-                             double2 *v, double *diag)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= g.n) return;
-    int q = g.rp[i];
-    const double dg = g.ks[i] + 2.0 * g.vol[i] * cabs2(psi[i]);
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-        v[p] = ci[p] == i ? make_double2(dg, 0.0) : cscale(g.kw[q++], -1.0);
-    diag[i] = dg;
-}
+struct L0sValues {
+    GeomT<double> g;
+    const int *rp, *ci;
+    const double2 *__restrict__ psi;
+    double2 *v;
+    double *diag;
+    __device__ void operator()(int, int) const
+    {
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        if (i >= g.n) return;
+        int q = g.rp[i];
+        const double dg = g.ks[i] + 2.0 * g.vol[i] * cabs2(psi[i]);
+        for (int p = rp[i]; p < rp[i + 1]; ++p)
+            v[p] = ci[p] == i ? make_double2(dg, 0.0) : cscale(g.kw[q++], -1.0);
+        diag[i] = dg;
+    }
+};
 
 // --------------------------------------------------------- MIS-2 -----
 __global__ void k_fill_int(int *a, int n, int val)
@@ -501,32 +514,43 @@ __global__ void k_scatter_colour(int n, const int *col, int c, const int *pos, i
 }
 
 // --------------------------------------------------------- numeric ----
-__global__ void k_diag(int n, const int *rp, const int *ci, const double2 *v, double *diag)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int p = find_col(ci, rp[i], rp[i + 1], i);
-    diag[i] = (p < rp[i + 1] && ci[p] == i) ? v[p].x : 0.0;
-}
+struct Diag {
+    int n;
+    const int *rp, *ci;
+    const double2 *v;
+    double *diag;
+    __device__ void operator()(int, int) const
+    {
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        if (i >= n) return;
+        const int p = find_col(ci, rp[i], rp[i + 1], i);
+        diag[i] = (p < rp[i + 1] && ci[p] == i) ? v[p].x : 0.0;
+    }
+};
 
 // Spectral radius of D^-1 A by power iteration from the counter-hash start
 // s_i = (h1_i - 1/2) + i (h2_i - 1/2), h = fmix32(i ^ salt) / 2^32; the
 // normalisation of each iterate is folded into the next step.
 constexpr int kRhoSteps = 20;
 
-__global__ void k_pw_start(int n, double2 *x, RedSlot slot)
-{
-    __shared__ double sm[kBlock / 64];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double part = 0.0;
-    if (i < n) {
-        const double a = (double)fmix32((uint32_t)i ^ 0x2545F491u) / 4294967296.0 - 0.5;
-        const double b = (double)fmix32((uint32_t)i ^ 0x6C8E9CF5u) / 4294967296.0 - 0.5;
-        x[i] = make_double2(a, b);
-        part = a * a + b * b;
+struct PwStart {
+    int n;
+    double2 *x;
+    RedSlot slot;
+    __device__ void operator()(int, int) const
+    {
+        __shared__ double sm[kBlock / 64];
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < n) {
+            const double a = (double)fmix32((uint32_t)i ^ 0x2545F491u) / 4294967296.0 - 0.5;
+            const double b = (double)fmix32((uint32_t)i ^ 0x6C8E9CF5u) / 4294967296.0 - 0.5;
+            x[i] = make_double2(a, b);
+            part = a * a + b * b;
+        }
+        block_reduce_store(part, slot, sm, blockIdx.x);
     }
-    block_reduce_store(part, slot, sm, blockIdx.x);
-}
+};
 
 // y = D^-1 A x / ||x|| (||x||^2 in *xn2), partial sums of |y|^2; kPwLanes
 // lanes share a row (lane j takes entries j, j + kPwLanes, ... in order, then
@@ -536,118 +560,151 @@ __global__ void k_pw_start(int n, double2 *x, RedSlot slot)
 // partial.
 constexpr int kPwLanes = 8;
 
-__global__ void k_pw_step(int n, const int *rp, const int *ci, const double2 *v, const double *diag,
-                          const double2 *x, const double *xn2, double2 *y, RedSlot slot)
-{
-    __shared__ double sm[kBlock / 64];
-    const int64_t total = (int64_t)n * kPwLanes;
-    const double scale = 1.0 / sqrt(*xn2);
-    double part = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < total; base += (int64_t)gridDim.x * kBlock) {
-        const int64_t g = base + threadIdx.x;
-        const int i = (int)(g / kPwLanes), lane = (int)(g % kPwLanes);
-        const bool act = g < total;
-        double2 acc = make_double2(0.0, 0.0);
-        if (act)
-            for (int p = rp[i] + lane; p < rp[i + 1]; p += kPwLanes) acc = cadd(acc, cmul(v[p], x[ci[p]]));
-#pragma unroll
-        for (int o = kPwLanes / 2; o > 0; o >>= 1) {
-            acc.x += __shfl_xor(acc.x, o, 64);
-            acc.y += __shfl_xor(acc.y, o, 64);
+struct PwStep {
+    int n;
+    const int *rp, *ci;
+    const double2 *v;
+    const double *diag;
+    const double2 *x;
+    const double *xn2;
+    double2 *y;
+    RedSlot slot;
+    __device__ void operator()(int, int) const
+    {
+        __shared__ double sm[kBlock / 64];
+        const int64_t total = (int64_t)n * kPwLanes;
+        const double scale = 1.0 / sqrt(*xn2);
+        double part = 0.0;
+        for (int64_t base = (int64_t)blockIdx.x * kBlock; base < total; base += (int64_t)gridDim.x * kBlock) {
+            const int64_t g = base + threadIdx.x;
+            const int i = (int)(g / kPwLanes), lane = (int)(g % kPwLanes);
+            const bool act = g < total;
+            double2 acc = make_double2(0.0, 0.0);
+            if (act)
+                for (int p = rp[i] + lane; p < rp[i + 1]; p += kPwLanes) acc = cadd(acc, cmul(v[p], x[ci[p]]));
+    #pragma unroll
+            for (int o = kPwLanes / 2; o > 0; o >>= 1) {
+                acc.x += __shfl_xor(acc.x, o, 64);
+                acc.y += __shfl_xor(acc.y, o, 64);
+            }
+            if (act && lane == 0) {
+                const double2 yi = cscale(acc, scale / diag[i]);
+                y[i] = yi;
+                part += cabs2(yi);
+            }
         }
-        if (act && lane == 0) {
-            const double2 yi = cscale(acc, scale / diag[i]);
-            y[i] = yi;
-            part += cabs2(yi);
-        }
+        block_reduce_store(part, slot, sm, blockIdx.x);
     }
-    block_reduce_store(part, slot, sm, blockIdx.x);
-}
+};
 
 // Level 0: the same step with H applied as the stencil (link factor tables
 // and the diagonal; its CSR copy holds the same entries), so a step streams x
 // and the diagonal instead of the CSR arrays.
 template <int DIM>
-__global__ void k_pw_step_l0(GeomT<double> g, LinkTab<double> U, const double *diag, const double2 *x,
-                             const double *xn2, double2 *y, RedSlot slot)
-{
-    __shared__ double sm[kBlock / 64];
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    double part = 0.0;
-    if (i < g.n) {
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
-        const double di = diag[i];
-        const double2 acc = cadd(cscale(x[i], di), khat_offdiag<DIM, double>(g, i, c, x, U));
-        const double2 yi = cscale(acc, 1.0 / (di * sqrt(*xn2)));
-        y[i] = yi;
-        part = cabs2(yi);
+struct PwStepL0 {
+    GeomT<double> g;
+    LinkTab<double> U;
+    const double *diag;
+    const double2 *x;
+    const double *xn2;
+    double2 *y;
+    RedSlot slot;
+    __device__ void operator()(int, int) const
+    {
+        __shared__ double sm[kBlock / 64];
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < g.n) {
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            const double di = diag[i];
+            const double2 acc = cadd(cscale(x[i], di), khat_offdiag<DIM, double>(g, i, c, x, U));
+            const double2 yi = cscale(acc, 1.0 / (di * sqrt(*xn2)));
+            y[i] = yi;
+            part = cabs2(yi);
+        }
+        block_reduce_store(part, slot, sm, blockIdx.x);
     }
-    block_reduce_store(part, slot, sm, blockIdx.x);
-}
+};
 
-__global__ void k_pw_rho(const double *yn2, double *rho)
-{
-    if (threadIdx.x == 0) *rho = sqrt(*yn2);
-}
+struct PwRho {
+    const double *yn2;
+    double *rho;
+    __device__ void operator()(int, int) const
+    {
+        if (threadIdx.x == 0) *rho = sqrt(*yn2);
+    }
+};
 
-static void rho_estimate(gl_precond *pre, Level &L, hipStream_t s)
+static void rho_estimate(gl_precond *pre, Level &lev, const Launch &L)
 {
     const gl_mesh *m = pre->mesh;
-    const int n = L.n, nb = blocks_for(n);
+    const int n = lev.n, nb = blocks_for(n);
     const RedSlot slot = red_slot(m, 0);
     double2 *x = pre->vin.get(), *y = pre->cyc_r.get();
     double *nrm = pre->pwn.get();
-    k_pw_start<<<nb, kBlock, 0, s>>>(n, x, slot);
-    launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm, nullptr, s);
+    L.run(nb, PwStart{n, x, slot});
+    launch_finalize(slot.partials, nb, FIN_STORE, nullptr, nrm, nullptr, L);
     // level 0 of a grid as the stencil, every other level (and level 0 of a
     // simplicial mesh) through its CSR matrix
-    const bool l0 = &L == &pre->L[0] && !m->g.simplicial;
+    const bool l0 = &lev == &pre->L[0] && !m->g.simplicial;
     const GeomT<double> g = geom_t<double>(m->g);
     // CSR levels: kPwLanes threads per row, at most one partial per level-0 block
     const int nbl = std::min(blocks_for((int64_t)n * kPwLanes), blocks_for(m->g.n));
     for (int k = 1; k <= kRhoSteps; ++k) {
         const double *xn2 = nrm + ((k - 1) & 1);
         if (l0 && m->g.dim == 2)
-            k_pw_step_l0<2><<<nb, kBlock, 0, s>>>(g, link_tab<double>(m), L.diag64.get(), x, xn2, y, slot);
+            L.run(nb, PwStepL0<2>{g, link_tab<double>(m), lev.diag64.get(), x, xn2, y, slot});
         else if (l0)
-            k_pw_step_l0<3><<<nb, kBlock, 0, s>>>(g, link_tab<double>(m), L.diag64.get(), x, xn2, y, slot);
+            L.run(nb, PwStepL0<3>{g, link_tab<double>(m), lev.diag64.get(), x, xn2, y, slot});
         else
-            k_pw_step<<<nbl, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(), x, xn2,
-                                             y, slot);
-        launch_finalize(slot.partials, l0 ? nb : nbl, FIN_STORE, nullptr, nrm + (k & 1), nullptr, s);
+            L.run(nbl, PwStep{n, lev.A.rp.get(), lev.A.ci.get(), lev.A.v64.get(), lev.diag64.get(), x, xn2, y, slot});
+        launch_finalize(slot.partials, l0 ? nb : nbl, FIN_STORE, nullptr, nrm + (k & 1), nullptr, L);
         std::swap(x, y);
     }
-    k_pw_rho<<<1, 64, 0, s>>>(nrm + (kRhoSteps & 1), L.rho.get());
-    GLK_CHECK_LAUNCH();
+    L.run<PwRho, 64>(1, PwRho{nrm + (kRhoSteps & 1), lev.rho.get()});
 }
 
-__global__ void k_p_values(int n, const int *arp, const int *aci, const double2 *av, const double *diag,
-                           const int *agg, const int *aggsize, const double *rho, const int *prp,
-                           const int *pci, double2 *pv)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const double omega = (4.0 / 3.0) / *rho;
-    const double dii = diag[i];
-    const int ai = agg[i];
-    for (int p = prp[i]; p < prp[i + 1]; ++p) {
-        const int a = pci[p];
-        const double ta = 1.0 / sqrt((double)aggsize[a]);
-        double2 at = make_double2(0.0, 0.0);
-        for (int q = arp[i]; q < arp[i + 1]; ++q)
-            if (agg[aci[q]] == a) at = cadd(at, cscale(av[q], ta));
-        const double t0 = (ai == a) ? ta : 0.0;
-        const double f = omega / dii;
-        pv[p] = make_double2(t0 - f * at.x, -f * at.y);
+struct PValues {
+    int n;
+    const int *arp, *aci;
+    const double2 *av;
+    const double *diag;
+    const int *agg, *aggsize;
+    const double *rho;
+    const int *prp, *pci;
+    double2 *pv;
+    __device__ void operator()(int, int) const
+    {
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        if (i >= n) return;
+        const double omega = (4.0 / 3.0) / *rho;
+        const double dii = diag[i];
+        const int ai = agg[i];
+        for (int p = prp[i]; p < prp[i + 1]; ++p) {
+            const int a = pci[p];
+            const double ta = 1.0 / sqrt((double)aggsize[a]);
+            double2 at = make_double2(0.0, 0.0);
+            for (int q = arp[i]; q < arp[i + 1]; ++q)
+                if (agg[aci[q]] == a) at = cadd(at, cscale(av[q], ta));
+            const double t0 = (ai == a) ? ta : 0.0;
+            const double f = omega / dii;
+            pv[p] = make_double2(t0 - f * at.x, -f * at.y);
+        }
     }
-}
+};
 
-__global__ void k_r_values(int nnz, const int *rsrc, const double2 *pv, double2 *rv)
-{
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q < nnz) rv[q] = cconj(pv[rsrc[q]]);
-}
+struct RValues {
+    int nnz;
+    const int *rsrc;
+    const double2 *pv;
+    double2 *rv;
+    __device__ void operator()(int, int) const
+    {
+        const int q = blockIdx.x * kBlock + threadIdx.x;
+        if (q < nnz) rv[q] = cconj(pv[rsrc[q]]);
+    }
+};
 
 // Upper triangle (J >= I) of R A P.  The products of each stored entry are
 // listed once per hierarchy (symbolic), in the order of the row traversal
@@ -701,59 +758,84 @@ __global__ void k_rap_fill(int nc, const int *rrp, const int *rci, const int *ar
 // setup is bit-reproducible; neighbouring lanes read neighbouring triples.
 constexpr int kRapLanes = 8;
 
-__global__ void k_rap_values(int nnz, const int *__restrict__ tp, const int *__restrict__ trip,
-                             const double2 *__restrict__ rv, const double2 *__restrict__ av,
-                             const double2 *__restrict__ pv, double2 *__restrict__ cv)
-{
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int t = (int)(g / kRapLanes), lane = (int)(g % kRapLanes);
-    const bool act = t < nnz;
-    double2 acc = make_double2(0.0, 0.0);
-    if (act)
-        for (int k = tp[t] + lane; k < tp[t + 1]; k += kRapLanes) {
-            const double2 ra = cmul(rv[trip[3 * k]], av[trip[3 * k + 1]]);
-            acc = cadd(acc, cmul(ra, pv[trip[3 * k + 2]]));
+struct RapValues {
+    int nnz;
+    const int *__restrict__ tp, *__restrict__ trip;
+    const double2 *__restrict__ rv, *__restrict__ av, *__restrict__ pv;
+    double2 *__restrict__ cv;
+    __device__ void operator()(int, int) const
+    {
+        const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        const int t = (int)(g / kRapLanes), lane = (int)(g % kRapLanes);
+        const bool act = t < nnz;
+        double2 acc = make_double2(0.0, 0.0);
+        if (act)
+            for (int k = tp[t] + lane; k < tp[t + 1]; k += kRapLanes) {
+                const double2 ra = cmul(rv[trip[3 * k]], av[trip[3 * k + 1]]);
+                acc = cadd(acc, cmul(ra, pv[trip[3 * k + 2]]));
+            }
+    #pragma unroll
+        for (int o = kRapLanes / 2; o > 0; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
         }
-#pragma unroll
-    for (int o = kRapLanes / 2; o > 0; o >>= 1) {
-        acc.x += __shfl_xor(acc.x, o, 64);
-        acc.y += __shfl_xor(acc.y, o, 64);
+        if (act && lane == 0) cv[t] = acc;
     }
-    if (act && lane == 0) cv[t] = acc;
-}
+};
 
-__global__ void k_rap_mirror(int nc, const int *crp, const int *cci, double2 *cv)
-{
-    const int I = blockIdx.x * kBlock + threadIdx.x;
-    if (I >= nc) return;
-    for (int t = crp[I]; t < crp[I + 1]; ++t) {
-        const int J = cci[t];
-        if (J > I) break;
-        if (J == I) { cv[t].y = 0.0; break; }
-        const int u = find_col(cci, crp[J], crp[J + 1], I);
-        cv[t] = (u < crp[J + 1] && cci[u] == I) ? cconj(cv[u]) : make_double2(0.0, 0.0);
+struct RapMirror {
+    int nc;
+    const int *crp, *cci;
+    double2 *cv;
+    __device__ void operator()(int, int) const
+    {
+        const int I = blockIdx.x * kBlock + threadIdx.x;
+        if (I >= nc) return;
+        for (int t = crp[I]; t < crp[I + 1]; ++t) {
+            const int J = cci[t];
+            if (J > I) break;
+            if (J == I) { cv[t].y = 0.0; break; }
+            const int u = find_col(cci, crp[J], crp[J + 1], I);
+            cv[t] = (u < crp[J + 1] && cci[u] == I) ? cconj(cv[u]) : make_double2(0.0, 0.0);
+        }
     }
-}
+};
 
-__global__ void k_to_f32c(int n, const double2 *a, float2 *b)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
-}
+struct ToF32c {
+    int n;
+    const double2 *a;
+    float2 *b;
+    __device__ void operator()(int, int) const
+    {
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+    }
+};
 
-__global__ void k_to_f32r(int n, const double *a, float *b)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) b[i] = (float)a[i];
-}
+struct ToF32r {
+    int n;
+    const double *a;
+    float *b;
+    __device__ void operator()(int, int) const
+    {
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        if (i < n) b[i] = (float)a[i];
+    }
+};
 
-__global__ void k_dense_from_csr(int n, const int *rp, const int *ci, const double2 *v, double2 *M)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    for (int j = 0; j < n; ++j) M[(size_t)i * n + j] = make_double2(0.0, 0.0);
-    for (int p = rp[i]; p < rp[i + 1]; ++p) M[(size_t)i * n + ci[p]] = v[p];
-}
+struct DenseFromCsr {
+    int n;
+    const int *rp, *ci;
+    const double2 *v;
+    double2 *M;
+    __device__ void operator()(int, int) const
+    {
+        const int i = blockIdx.x * kBlock + threadIdx.x;
+        if (i >= n) return;
+        for (int j = 0; j < n; ++j) M[(size_t)i * n + j] = make_double2(0.0, 0.0);
+        for (int p = rp[i]; p < rp[i + 1]; ++p) M[(size_t)i * n + ci[p]] = v[p];
+    }
+};
 
 // Cholesky factor M = L L^H of the Hermitian coarsest operator, in place
 // (row-major, lower triangle; the upper part zeroed at the end), blocked
@@ -766,126 +848,156 @@ constexpr int kCholLds = (65536 - 1024) / sizeof(double2);  // panel entries hel
 
 int chol_panel_width(int n) { return std::max(1, std::min(32, kCholLds / std::max(n, 1))); }
 
-__global__ __launch_bounds__(1024) void k_chol_init(int n, const double2 *M, double *dmax, int *status)
-{
-    __shared__ double sm[1024 / 64];
-    double m = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(M[(size_t)i * n + i].x));
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
-    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double r = 0.0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sm[w]);
-        *dmax = r;
-        *status = 0;
+struct CholInit {
+    int n;
+    const double2 *M;
+    double *dmax;
+    int *status;
+    __device__ void operator()(int, int) const
+    {
+        __shared__ double sm[1024 / 64];
+        double m = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, fabs(M[(size_t)i * n + i].x));
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_down(m, o, 64));
+        if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = 0.0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, sm[w]);
+            *dmax = r;
+            *status = 0;
+        }
     }
-}
+};
 
 // columns p0 .. p0 + pw - 1, rows p0 .. n - 1 (already updated by the
 // earlier panels): P[r * pw + c] = M[p0 + r][p0 + c]
-__global__ __launch_bounds__(1024) void k_chol_panel(int n, int p0, int pw, double2 *M, const double *dmaxp,
-                                                     int *status)
-{
-    __shared__ double2 P[kCholLds];
-    __shared__ double piv;
-    __shared__ int bad;
-    if (*status) return;
-    const int rows = n - p0;
-    const double dmax = *dmaxp;
-    for (int t = threadIdx.x; t < rows * pw; t += blockDim.x)
-        P[t] = M[(size_t)(p0 + t / pw) * n + p0 + t % pw];
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    for (int c = 0; c < pw; ++c) {
-        if (threadIdx.x == 0) {
-            const double d = P[c * pw + c].x;
-            if (!(d > 1e-12 * dmax)) bad = 1;
-            else {
-                piv = sqrt(d);
-                P[c * pw + c] = make_double2(piv, 0.0);
+struct CholPanel {
+    int n, p0, pw;
+    double2 *M;
+    const double *dmaxp;
+    int *status;
+    __device__ void operator()(int, int) const
+    {
+        __shared__ double2 P[kCholLds];
+        __shared__ double piv;
+        __shared__ int bad;
+        if (*status) return;
+        const int rows = n - p0;
+        const double dmax = *dmaxp;
+        for (int t = threadIdx.x; t < rows * pw; t += blockDim.x)
+            P[t] = M[(size_t)(p0 + t / pw) * n + p0 + t % pw];
+        if (threadIdx.x == 0) bad = 0;
+        __syncthreads();
+        for (int c = 0; c < pw; ++c) {
+            if (threadIdx.x == 0) {
+                const double d = P[c * pw + c].x;
+                if (!(d > 1e-12 * dmax)) bad = 1;
+                else {
+                    piv = sqrt(d);
+                    P[c * pw + c] = make_double2(piv, 0.0);
+                }
             }
+            __syncthreads();
+            if (bad) break;
+            const double inv = 1.0 / piv;
+            for (int r = c + 1 + threadIdx.x; r < rows; r += blockDim.x) P[r * pw + c] = cscale(P[r * pw + c], inv);
+            __syncthreads();
+            // the panel's remaining columns c' > c, rows r >= c'
+            const int w = pw - c - 1;
+            for (int t = threadIdx.x; t < (rows - c - 1) * w; t += blockDim.x) {
+                const int r = c + 1 + t / w, q = c + 1 + t % w;
+                if (r >= q) P[r * pw + q] = csub(P[r * pw + q], cmul(P[r * pw + c], cconj(P[q * pw + c])));
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (bad) break;
-        const double inv = 1.0 / piv;
-        for (int r = c + 1 + threadIdx.x; r < rows; r += blockDim.x) P[r * pw + c] = cscale(P[r * pw + c], inv);
-        __syncthreads();
-        // the panel's remaining columns c' > c, rows r >= c'
-        const int w = pw - c - 1;
-        for (int t = threadIdx.x; t < (rows - c - 1) * w; t += blockDim.x) {
-            const int r = c + 1 + t / w, q = c + 1 + t % w;
-            if (r >= q) P[r * pw + q] = csub(P[r * pw + q], cmul(P[r * pw + c], cconj(P[q * pw + c])));
+        if (bad) {
+            if (threadIdx.x == 0) *status = 1;
+            return;
         }
-        __syncthreads();
+        for (int t = threadIdx.x; t < rows * pw; t += blockDim.x) {
+            const int r = t / pw, c = t % pw;
+            if (r >= c) M[(size_t)(p0 + r) * n + p0 + c] = P[t];
+        }
     }
-    if (bad) {
-        if (threadIdx.x == 0) *status = 1;
-        return;
-    }
-    for (int t = threadIdx.x; t < rows * pw; t += blockDim.x) {
-        const int r = t / pw, c = t % pw;
-        if (r >= c) M[(size_t)(p0 + r) * n + p0 + c] = P[t];
-    }
-}
+};
 
 // M[i][k] -= sum_c L[i][p0 + c] conj(L[k][p0 + c]) for p0 + pw <= k <= i < n
-__global__ void k_chol_update(int n, int p0, int pw, double2 *M, const int *status)
-{
-    if (*status) return;
-    const int b = p0 + pw;
-    const int i = b + blockIdx.y * 16 + threadIdx.y, k = b + blockIdx.x * 16 + threadIdx.x;
-    if (i >= n || k > i) return;
-    const double2 *li = M + (size_t)i * n + p0, *lk = M + (size_t)k * n + p0;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int c = 0; c < pw; ++c) acc = cadd(acc, cmul(li[c], cconj(lk[c])));
-    M[(size_t)i * n + k] = csub(M[(size_t)i * n + k], acc);
-}
+// One 16 x 16 tile of the trailing matrix per work-group of 256 threads:
+// tile bx = (tile row) * tiles + (tile column), tiles = ceil((n - p0 - pw) / 16).
+struct CholUpdate {
+    int n, p0, pw, tiles;
+    double2 *M;
+    const int *status;
+    __device__ void operator()(int bx, int) const
+    {
+        if (*status) return;
+        const int b = p0 + pw;
+        const int i = b + (bx / tiles) * 16 + (int)(threadIdx.x >> 4);
+        const int k = b + (bx % tiles) * 16 + (int)(threadIdx.x & 15);
+        if (i >= n || k > i) return;
+        const double2 *li = M + (size_t)i * n + p0, *lk = M + (size_t)k * n + p0;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int c = 0; c < pw; ++c) acc = cadd(acc, cmul(li[c], cconj(lk[c])));
+        M[(size_t)i * n + k] = csub(M[(size_t)i * n + k], acc);
+    }
+};
 
-__global__ void k_chol_zero_upper(int n, double2 *M)
-{
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= (int64_t)n * n) return;
-    if (t % n > t / n) M[t] = make_double2(0.0, 0.0);
-}
+struct CholZeroUpper {
+    int n;
+    double2 *M;
+    __device__ void operator()(int, int) const
+    {
+        const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        if (t >= (int64_t)n * n) return;
+        if (t % n > t / n) M[t] = make_double2(0.0, 0.0);
+    }
+};
 
-void cholesky(int n, double2 *M, double *dmax, int *status, hipStream_t s)
+static void cholesky(int n, double2 *M, double *dmax, int *status, const Launch &L)
 {
-    k_chol_init<<<1, 1024, 0, s>>>(n, M, dmax, status);
+    L.run<CholInit, 1024>(1, CholInit{n, M, dmax, status});
     const int pb = chol_panel_width(n);
     for (int p0 = 0; p0 < n; p0 += pb) {
         const int pw = std::min(pb, n - p0);
-        k_chol_panel<<<1, 1024, 0, s>>>(n, p0, pw, M, dmax, status);
+        L.run<CholPanel, 1024>(1, CholPanel{n, p0, pw, M, dmax, status});
         const int m = n - p0 - pw;
-        if (m > 0) k_chol_update<<<dim3((m + 15) / 16, (m + 15) / 16), dim3(16, 16), 0, s>>>(n, p0, pw, M, status);
+        const int tiles = (m + 15) / 16;
+        if (m > 0) L.run(tiles * tiles, CholUpdate{n, p0, pw, tiles, M, status});
     }
-    k_chol_zero_upper<<<blocks_for((int64_t)n * n), kBlock, 0, s>>>(n, M);
-    GLK_CHECK_LAUNCH();
+    L.run(blocks_for((int64_t)n * n), CholZeroUpper{n, M});
 }
 
 // Column j of (L L^H)^-1 (one work-group per column), stored row-major.
-__global__ __launch_bounds__(kBlock) void k_chol_inverse(int n, const double2 *__restrict__ Lf, double2 *inv)
-{
-    __shared__ double2 y[kMaxDense];
-    const int j = blockIdx.x;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    __syncthreads();
-    for (int k = j; k < n; ++k) {  // L y = e_j
-        const double2 yk = cscale(y[k], 1.0 / Lf[(size_t)k * n + k].x);
+struct CholInverse {
+    int n;
+    const double2 *__restrict__ Lf;
+    double2 *inv;
+    const int *status;  // nonzero: the factorisation failed, nothing to invert
+    __device__ void operator()(int, int) const
+    {
+        if (*status) return;
+        __shared__ double2 y[kMaxDense];
+        const int j = blockIdx.x;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = make_double2(i == j ? 1.0 : 0.0, 0.0);
         __syncthreads();
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] = csub(y[i], cmul(Lf[(size_t)i * n + k], yk));
-        if (threadIdx.x == 0) y[k] = yk;
-        __syncthreads();
+        for (int k = j; k < n; ++k) {  // L y = e_j
+            const double2 yk = cscale(y[k], 1.0 / Lf[(size_t)k * n + k].x);
+            __syncthreads();
+            for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] = csub(y[i], cmul(Lf[(size_t)i * n + k], yk));
+            if (threadIdx.x == 0) y[k] = yk;
+            __syncthreads();
+        }
+        for (int k = n - 1; k >= 0; --k) {  // L^H x = y
+            const double2 yk = cscale(y[k], 1.0 / Lf[(size_t)k * n + k].x);
+            __syncthreads();
+            for (int i = threadIdx.x; i < k; i += blockDim.x) y[i] = csub(y[i], cmulc(Lf[(size_t)k * n + i], yk));
+            if (threadIdx.x == 0) y[k] = yk;
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < n; i += blockDim.x) inv[(size_t)i * n + j] = y[i];
     }
-    for (int k = n - 1; k >= 0; --k) {  // L^H x = y
-        const double2 yk = cscale(y[k], 1.0 / Lf[(size_t)k * n + k].x);
-        __syncthreads();
-        for (int i = threadIdx.x; i < k; i += blockDim.x) y[i] = csub(y[i], cmulc(Lf[(size_t)k * n + i], yk));
-        if (threadIdx.x == 0) y[k] = yk;
-        __syncthreads();
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) inv[(size_t)i * n + j] = y[i];
-}
+};
 
 // ------------------------------------------------- colour renumbering --
 __global__ void k_iperm(int n, const int *perm, int *iperm)
@@ -992,28 +1104,41 @@ __global__ void k_pblack_fill(GeomT<double> g, const int *rp, const int *ci, con
 
 // the level-0 diagonal in the colour-split layout (an absent odd node's slot
 // holds 1)
-__global__ void k_split_diag(GeomT<double> g, const double *d, double *s64, float *s32)
-{
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= g.npair) return;
-    const int row = t / g.hr, c0 = 2 * (t - row * g.hr);
-    const int c1 = row % g.N[1], c2 = row / g.N[1];
-    const int ie = c0 + g.N[0] * row, ce = (c0 + c1 + c2) & 1;
-    const double de = d[ie], dodd = c0 + 1 < g.N[0] ? d[ie + 1] : 1.0;
-    s64[ce * g.npair + t] = de;
-    s32[ce * g.npair + t] = (float)de;
-    s64[(1 - ce) * g.npair + t] = dodd;
-    s32[(1 - ce) * g.npair + t] = (float)dodd;
-}
+struct SplitDiag {
+    GeomT<double> g;
+    const double *d;
+    double *s64;
+    float *s32;
+    __device__ void operator()(int, int) const
+    {
+        const int t = blockIdx.x * kBlock + threadIdx.x;
+        if (t >= g.npair) return;
+        const int row = t / g.hr, c0 = 2 * (t - row * g.hr);
+        const int c1 = row % g.N[1], c2 = row / g.N[1];
+        const int ie = c0 + g.N[0] * row, ce = (c0 + c1 + c2) & 1;
+        const double de = d[ie], dodd = c0 + 1 < g.N[0] ? d[ie + 1] : 1.0;
+        s64[ce * g.npair + t] = de;
+        s32[ce * g.npair + t] = (float)de;
+        s64[(1 - ce) * g.npair + t] = dodd;
+        s32[(1 - ce) * g.npair + t] = (float)dodd;
+    }
+};
 
-__global__ void k_gather_c(int nnz, const int *map, const double2 *src, double2 *d64, float2 *d32)
-{
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= nnz) return;
-    const double2 v = src[map[q]];
-    d64[q] = v;
-    d32[q] = make_float2((float)v.x, (float)v.y);
-}
+struct GatherC {
+    int nnz;
+    const int *map;
+    const double2 *src;
+    double2 *d64;
+    float2 *d32;
+    __device__ void operator()(int, int) const
+    {
+        const int q = blockIdx.x * kBlock + threadIdx.x;
+        if (q >= nnz) return;
+        const double2 v = src[map[q]];
+        d64[q] = v;
+        d32[q] = make_float2((float)v.x, (float)v.y);
+    }
+};
 
 // padded block of one colour (rows row0 .. row0 + count - 1 of Aa), row-major:
 // entry k of row r at r W + k
@@ -1029,24 +1154,38 @@ __global__ void k_ell_fill(int row0, int count, int W, const int *rp, const int 
     }
 }
 
-__global__ void k_ell_values(int n, const int *emap, const double2 *src, double2 *d64, float2 *d32)
-{
-    const int q = blockIdx.x * kBlock + threadIdx.x;
-    if (q >= n) return;
-    const int p = emap[q];
-    const double2 v = p >= 0 ? src[p] : make_double2(0.0, 0.0);
-    d64[q] = v;
-    d32[q] = make_float2((float)v.x, (float)v.y);
-}
+struct EllValues {
+    int n;
+    const int *emap;
+    const double2 *src;
+    double2 *d64;
+    float2 *d32;
+    __device__ void operator()(int, int) const
+    {
+        const int q = blockIdx.x * kBlock + threadIdx.x;
+        if (q >= n) return;
+        const int p = emap[q];
+        const double2 v = p >= 0 ? src[p] : make_double2(0.0, 0.0);
+        d64[q] = v;
+        d32[q] = make_float2((float)v.x, (float)v.y);
+    }
+};
 
-__global__ void k_gather_r(int n, const int *perm, const double *src, double *d64, float *d32)
-{
-    const int r = blockIdx.x * kBlock + threadIdx.x;
-    if (r >= n) return;
-    const double v = src[perm[r]];
-    d64[r] = v;
-    d32[r] = (float)v;
-}
+struct GatherR {
+    int n;
+    const int *perm;
+    const double *src;
+    double *d64;
+    float *d32;
+    __device__ void operator()(int, int) const
+    {
+        const int r = blockIdx.x * kBlock + threadIdx.x;
+        if (r >= n) return;
+        const double v = src[perm[r]];
+        d64[r] = v;
+        d32[r] = (float)v;
+    }
+};
 
 // ------------------------------------------------------------- host ---
 static int read_int(const int *d, hipStream_t s)
@@ -1441,7 +1580,7 @@ void precond_symbolic(gl_precond *pre, hipStream_t s)
     GLK_HIP(hipStreamSynchronize(s));
 }
 
-void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
+void precond_numeric_enqueue(gl_precond *pre, const double2 *psi, const Launch &L)
 {
     const gl_mesh *m = pre->mesh;
     Level &L0 = pre->L[0];
@@ -1449,83 +1588,72 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
     const GeomT<double> g = geom_t<double>(m->g);
     const bool simp = m->g.simplicial;
     if (simp)
-        k_l0s_values<<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), L0.A.ci.get(), psi, L0.A.v64.get(),
-                                                       L0.diag64.get());
+        L.run(blocks_for(n0), L0sValues{g, L0.A.rp.get(), L0.A.ci.get(), psi, L0.A.v64.get(), L0.diag64.get()});
     else if (m->g.dim == 2)
-        k_l0_values<2><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), link_tab<double>(m), psi, L0.A.v64.get(),
-                                                         L0.diag64.get());
+        L.run(blocks_for(n0), L0Values<2>{g, L0.A.rp.get(), link_tab<double>(m), psi, L0.A.v64.get(), L0.diag64.get()});
     else
-        k_l0_values<3><<<blocks_for(n0), kBlock, 0, s>>>(g, L0.A.rp.get(), link_tab<double>(m), psi, L0.A.v64.get(),
-                                                         L0.diag64.get());
-    GLK_CHECK_LAUNCH();
+        L.run(blocks_for(n0), L0Values<3>{g, L0.A.rp.get(), link_tab<double>(m), psi, L0.A.v64.get(), L0.diag64.get()});
     for (int l = 0; l + 1 < pre->nlev; ++l) {
-        Level &L = pre->L[l];
+        Level &lv = pre->L[l];
         Level &Nx = pre->L[l + 1];
-        const int n = L.n, nb = blocks_for(n);
-        if (l > 0) {
-            k_diag<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get());
-        }
-        rho_estimate(pre, L, s);
-        k_p_values<<<nb, kBlock, 0, s>>>(n, L.A.rp.get(), L.A.ci.get(), L.A.v64.get(), L.diag64.get(),
-                                         L.agg.get(), L.aggsize.get(), L.rho.get(), L.P.rp.get(),
-                                         L.P.ci.get(), L.P.v64.get());
-        k_r_values<<<blocks_for(L.R.nnz), kBlock, 0, s>>>(L.R.nnz, L.rsrc.get(), L.P.v64.get(), L.R.v64.get());
-        const int nbc = blocks_for(L.nc);
-        k_rap_values<<<blocks_for((int64_t)Nx.A.nnz * kRapLanes), kBlock, 0, s>>>(
-            Nx.A.nnz, L.rap_tp.get(), L.rap_trip.get(), L.R.v64.get(), L.A.v64.get(), L.P.v64.get(),
-            Nx.A.v64.get());
-        k_rap_mirror<<<nbc, kBlock, 0, s>>>(L.nc, Nx.A.rp.get(), Nx.A.ci.get(), Nx.A.v64.get());
-        GLK_CHECK_LAUNCH();
+        const int n = lv.n, nb = blocks_for(n);
+        if (l > 0) L.run(nb, Diag{n, lv.A.rp.get(), lv.A.ci.get(), lv.A.v64.get(), lv.diag64.get()});
+        rho_estimate(pre, lv, L);
+        L.run(nb, PValues{n, lv.A.rp.get(), lv.A.ci.get(), lv.A.v64.get(), lv.diag64.get(), lv.agg.get(),
+                          lv.aggsize.get(), lv.rho.get(), lv.P.rp.get(), lv.P.ci.get(), lv.P.v64.get()});
+        L.run(blocks_for(lv.R.nnz), RValues{lv.R.nnz, lv.rsrc.get(), lv.P.v64.get(), lv.R.v64.get()});
+        L.run(blocks_for((int64_t)Nx.A.nnz * kRapLanes),
+              RapValues{Nx.A.nnz, lv.rap_tp.get(), lv.rap_trip.get(), lv.R.v64.get(), lv.A.v64.get(), lv.P.v64.get(),
+                        Nx.A.v64.get()});
+        L.run(blocks_for(lv.nc), RapMirror{lv.nc, Nx.A.rp.get(), Nx.A.ci.get(), Nx.A.v64.get()});
     }
     const int last = pre->nlev - 1;
     Level &Lc = pre->L[last];
-    if (last > 0)
-        k_diag<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Lc.A.rp.get(), Lc.A.ci.get(), Lc.A.v64.get(), Lc.diag64.get());
+    if (last > 0) L.run(blocks_for(Lc.n), Diag{Lc.n, Lc.A.rp.get(), Lc.A.ci.get(), Lc.A.v64.get(), Lc.diag64.get()});
     // level 0 in single precision (its stencil diagonal; the CSR copy serves export only)
-    k_to_f32r<<<blocks_for(n0), kBlock, 0, s>>>(n0, L0.diag64.get(), L0.diag32.get());
-    if (!simp)
-        k_split_diag<<<blocks_for(g.npair), kBlock, 0, s>>>(g, L0.diag64.get(), L0.hs64.get(), L0.hs32.get());
+    L.run(blocks_for(n0), ToF32r{n0, L0.diag64.get(), L0.diag32.get()});
+    if (!simp) L.run(blocks_for(g.npair), SplitDiag{g, L0.diag64.get(), L0.hs64.get(), L0.hs32.get()});
     // colour-ordered copies for the V-cycle, FP64 and rounded to FP32
     for (int l = 0; l < pre->nlev; ++l) {
-        Level &L = pre->L[l];
+        Level &lv = pre->L[l];
         if (l >= 1 || (simp && last > 0)) {
-            k_gather_c<<<blocks_for(L.Aa.nnz), kBlock, 0, s>>>(L.Aa.nnz, L.amap.get(), L.A.v64.get(),
-                                                               L.Aa.v64.get(), L.Aa.v32.get());
-            k_gather_r<<<blocks_for(L.n), kBlock, 0, s>>>(L.n, L.perm.get(), L.diag64.get(), L.dg64.get(),
-                                                          L.dg32.get());
-            const int ne = L.eoff.empty() ? 0 : L.eoff.back();
-            if (ne > 0)
-                k_ell_values<<<blocks_for(ne), kBlock, 0, s>>>(ne, L.emap.get(), L.Aa.v64.get(), L.ev64.get(),
-                                                               L.ev32.get());
+            L.run(blocks_for(lv.Aa.nnz), GatherC{lv.Aa.nnz, lv.amap.get(), lv.A.v64.get(), lv.Aa.v64.get(), lv.Aa.v32.get()});
+            L.run(blocks_for(lv.n), GatherR{lv.n, lv.perm.get(), lv.diag64.get(), lv.dg64.get(), lv.dg32.get()});
+            const int ne = lv.eoff.empty() ? 0 : lv.eoff.back();
+            if (ne > 0) L.run(blocks_for(ne), EllValues{ne, lv.emap.get(), lv.Aa.v64.get(), lv.ev64.get(), lv.ev32.get()});
         }
         if (l < last) {
-            k_gather_c<<<blocks_for(L.Pa.nnz), kBlock, 0, s>>>(L.Pa.nnz, L.pmap.get(), L.P.v64.get(),
-                                                               L.Pa.v64.get(), L.Pa.v32.get());
-            k_gather_c<<<blocks_for(L.Ra.nnz), kBlock, 0, s>>>(L.Ra.nnz, L.rmap.get(), L.R.v64.get(),
-                                                               L.Ra.v64.get(), L.Ra.v32.get());
+            L.run(blocks_for(lv.Pa.nnz), GatherC{lv.Pa.nnz, lv.pmap.get(), lv.P.v64.get(), lv.Pa.v64.get(), lv.Pa.v32.get()});
+            L.run(blocks_for(lv.Ra.nnz), GatherC{lv.Ra.nnz, lv.rmap.get(), lv.R.v64.get(), lv.Ra.v64.get(), lv.Ra.v32.get()});
             if (l == 0 && !simp) {
-                k_gather_c<<<blocks_for(L.Rb.nnz), kBlock, 0, s>>>(L.Rb.nnz, L.bmap.get(), L.R.v64.get(),
-                                                                   L.Rb.v64.get(), L.Rb.v32.get());
-                k_gather_c<<<blocks_for(L.Pb.nnz), kBlock, 0, s>>>(L.Pb.nnz, L.pbmap.get(), L.P.v64.get(),
-                                                                   L.Pb.v64.get(), L.Pb.v32.get());
+                L.run(blocks_for(lv.Rb.nnz),
+                      GatherC{lv.Rb.nnz, lv.bmap.get(), lv.R.v64.get(), lv.Rb.v64.get(), lv.Rb.v32.get()});
+                L.run(blocks_for(lv.Pb.nnz),
+                      GatherC{lv.Pb.nnz, lv.pbmap.get(), lv.P.v64.get(), lv.Pb.v64.get(), lv.Pb.v32.get()});
             }
         }
-        GLK_CHECK_LAUNCH();
     }
     // coarsest: Cholesky in FP64 (positive definiteness check), then the inverse
     // in the V-cycle's row order, applied as a dense product
     const Csr &Mc = last > 0 ? Lc.Aa : Lc.A;
-    k_dense_from_csr<<<blocks_for(Lc.n), kBlock, 0, s>>>(Lc.n, Mc.rp.get(), Mc.ci.get(), Mc.v64.get(),
-                                                         pre->cfac.get());
-    cholesky(Lc.n, pre->cfac.get(), pre->cdmax.get(), pre->status.get(), s);
-    if (read_int(pre->status.get(), s))
-        fail(GL_ERR_SINGULAR, "gl_precond_setup: coarsest operator is not positive definite");
-    k_chol_inverse<<<Lc.n, kBlock, 0, s>>>(Lc.n, pre->cfac.get(), pre->cinv64.get());
-    k_to_f32c<<<blocks_for((int64_t)Lc.n * Lc.n), kBlock, 0, s>>>(Lc.n * Lc.n, pre->cinv64.get(), pre->cinv32.get());
-    GLK_CHECK_LAUNCH();
+    L.run(blocks_for(Lc.n), DenseFromCsr{Lc.n, Mc.rp.get(), Mc.ci.get(), Mc.v64.get(), pre->cfac.get()});
+    cholesky(Lc.n, pre->cfac.get(), pre->cdmax.get(), pre->status.get(), L);
+    L.run(Lc.n, CholInverse{Lc.n, pre->cfac.get(), pre->cinv64.get(), pre->status.get()});
+    L.run(blocks_for((int64_t)Lc.n * Lc.n), ToF32c{Lc.n * Lc.n, pre->cinv64.get(), pre->cinv32.get()});
+}
+
+void precond_numeric_finish(gl_precond *pre, bool singular, hipStream_t s)
+{
+    if (singular) fail(GL_ERR_SINGULAR, "gl_precond_setup: coarsest operator is not positive definite");
     pre->has_values = true;
     form_tail(pre, s);
     if (pre->opts.cycles == 0) pcg_calibrate(pre, s);
+}
+
+void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
+{
+    precond_numeric_enqueue(pre, psi, Launch{s});
+    precond_numeric_finish(pre, read_int(pre->status.get(), s) != 0, s);
 }
 
 }  // namespace glk
@@ -1533,6 +1661,20 @@ void precond_numeric(gl_precond *pre, const double2 *psi, hipStream_t s)
 using namespace glk;
 
 namespace glk {
+void check_amg_opts(const gl_amg_opts *opts, const char *who)
+{
+    const std::string w(who);
+    if (opts->precision != GL_FP64 && opts->precision != GL_FP32 && opts->precision != GL_MIXED)
+        fail(GL_ERR_INVALID_ARGUMENT, w + ": precision");
+    if (opts->cycles < 0 || opts->cycles > 1000) fail(GL_ERR_INVALID_ARGUMENT, w + ": cycles must be in 0..1000");
+    if (opts->cycles == 0 && opts->precision != GL_FP64)
+        fail(GL_ERR_INVALID_ARGUMENT, w + ": R_inf (cycles 0) needs the FP64 V-cycle");
+    if (opts->max_coarse < 1 || opts->max_coarse > kMaxDense)
+        fail(GL_ERR_INVALID_ARGUMENT, w + ": max_coarse must be in 1..2048");
+    if (opts->max_levels < 1 || opts->max_levels > kMaxLevels)
+        fail(GL_ERR_INVALID_ARGUMENT, w + ": max_levels must be in 1..16");
+}
+
 uint64_t new_precond_uid()
 {
     static std::atomic<uint64_t> next{1};
@@ -1552,18 +1694,7 @@ gl_status gl_precond_setup(const gl_mesh *mesh, const void *psi, const gl_amg_op
         if (pre && pre->mesh != mesh)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: handle belongs to another mesh");
         if (!pre && !opts) fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: opts required for a new handle");
-        if (opts) {
-            if (opts->precision != GL_FP64 && opts->precision != GL_FP32 && opts->precision != GL_MIXED)
-                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: precision");
-            if (opts->cycles < 0 || opts->cycles > 1000)
-                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: cycles must be in 0..1000");
-            if (opts->cycles == 0 && opts->precision != GL_FP64)
-                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: R_inf (cycles 0) needs the FP64 V-cycle");
-            if (opts->max_coarse < 1 || opts->max_coarse > kMaxDense)
-                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: max_coarse must be in 1..2048");
-            if (opts->max_levels < 1 || opts->max_levels > kMaxLevels)
-                fail(GL_ERR_INVALID_ARGUMENT, "gl_precond_setup: max_levels must be in 1..16");
-        }
+        if (opts) check_amg_opts(opts, "gl_precond_setup");
         if (!pre) {
             pre = new gl_precond();
             try {

@@ -694,12 +694,17 @@ __global__ __launch_bounds__(kBlock) void k_defl_norms(GeomT<double> g, const do
     block_reduce_store(pb, s2, sm, blockIdx.x);
 }
 
-// psi -= dx
-__global__ void k_sub(int n, double2 *psi, const double2 *dx)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) psi[i] = csub(psi[i], dx[i]);
-}
+// psi -= dx (the Newton update)
+struct NewtonSub {
+    int n;
+    double2 *psi;
+    const double2 *dx;
+    __device__ void operator()(int bx, int) const
+    {
+        const int i = bx * kBlock + threadIdx.x;
+        if (i < n) psi[i] = csub(psi[i], dx[i]);
+    }
+};
 
 // x += d
 __global__ void k_add(int n, double2 *x, const double2 *d)
@@ -709,11 +714,17 @@ __global__ void k_add(int n, double2 *x, const double2 *d)
 }
 
 // x += c d (a backtracking step of the Newton line search)
-__global__ void k_axpy(int n, double c, double2 *x, const double2 *d)
-{
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] = cadd(x[i], cscale(d[i], c));
-}
+struct NewtonAxpy {
+    int n;
+    double c;
+    double2 *x;
+    const double2 *d;
+    __device__ void operator()(int bx, int) const
+    {
+        const int i = bx * kBlock + threadIdx.x;
+        if (i < n) x[i] = cadd(x[i], cscale(d[i], c));
+    }
+};
 
 // Sufficient decrease of the Newton line search: a step of length alpha is
 // kept when the residual norm falls by the factor 1 - 1e-4 alpha (false for
@@ -1311,13 +1322,13 @@ gl_status gl_newton_solve(const gl_mesh *mesh, void *psi_inout, const gl_newton_
             gl_krylov_info ki;
             gl_status ks = minres_solve(mesh, psi, opts->use_precond ? pre : nullptr, r, dx, opts->krylov, &ki, s);
             if (ks != GL_OK && ks != GL_ERR_NOT_CONVERGED) { rc = ks; break; }
-            k_sub<<<blocks_for(n), kBlock, 0, s>>>(n, psi, dx);
+            Launch{s}.run(blocks_for(n), NewtonSub{n, psi, dx});
             GLK_CHECK_LAUNCH();
             ni.krylov_iters[k] = ki.iterations;
             double res_new = residual(), alpha = 1.0;
             // backtracking: psi = psi_k - alpha dpsi_k with alpha halved
             for (int h = 0; h < opts->linesearch && !newton_accepts(res_new, res, alpha); ++h) {
-                k_axpy<<<blocks_for(n), kBlock, 0, s>>>(n, 0.5 * alpha, psi, dx);
+                Launch{s}.run(blocks_for(n), NewtonAxpy{n, 0.5 * alpha, psi, dx});
                 GLK_CHECK_LAUNCH();
                 alpha *= 0.5;
                 res_new = residual();
@@ -1445,6 +1456,7 @@ struct gl_batch {
     glk::DevBuf<const double *> ds_ptr;
     glk::DevBuf<glk::BatchScalars> gathered;
     glk::BatchScalars *host_sc = nullptr;
+    int *host_status = nullptr;  // per instance: the coarsest factor's failure flag of the last setup
     glk::DevBuf<unsigned char> init_args;
     unsigned char *staging = nullptr;
     size_t staging_cap = 0;
@@ -1838,6 +1850,42 @@ static void batch_solve(gl_batch *B, double2 *const *psi, const std::vector<int>
     }
 }
 
+// Numeric setups of the instances in `which`, whose handles exist: every
+// kernel of every setup recorded and run as one batched dispatch per step and
+// shape group, one synchronisation, then each instance's failure flag (as
+// gl_precond_setup on an existing handle, instance by instance).
+static void batch_setups(gl_batch *B, double2 *const *psi, const std::vector<int> &which, const gl_amg_opts &amg,
+                         std::vector<gl_status> &st, std::vector<char> &active)
+{
+    std::vector<int> run;
+    for (int i : which) {
+        gl_precond *p = B->pre[i];
+        if (amg.max_coarse != p->opts.max_coarse || amg.max_levels != p->opts.max_levels) {
+            set_last_error("gl_batch_newton_solve: hierarchy limits differ from the handle's");
+            st[i] = GL_ERR_INVALID_ARGUMENT;
+            active[i] = 0;
+            continue;
+        }
+        p->opts.precision = amg.precision;
+        p->opts.cycles = amg.cycles;
+        run.push_back(i);
+    }
+    if (run.empty()) return;
+    batch_run_direct(B, run, [&](int i, std::vector<Step> &r) {
+        precond_numeric_enqueue(B->pre[i], psi[i], Launch{nullptr, &r});
+    });
+    for (int i : run)
+        GLK_HIP(hipMemcpyAsync(B->host_status + i, B->pre[i]->status.get(), sizeof(int), hipMemcpyDeviceToHost, B->s));
+    GLK_HIP(hipStreamSynchronize(B->s));
+    for (int i : run) {
+        const gl_status r = guarded([&] { precond_numeric_finish(B->pre[i], B->host_status[i] != 0, B->s); });
+        if (r != GL_OK) {
+            st[i] = r;
+            active[i] = 0;
+        }
+    }
+}
+
 static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_opts &o, gl_newton_info *infos)
 {
     const int N = (int)B->meshes.size();
@@ -1851,12 +1899,16 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
     B->reorth = o.krylov.reorth;
     for (int i = 0; i < N; ++i) k_ks_stop<<<1, 1, 0, B->s>>>(kscal_of(B->meshes[i]));
     GLK_CHECK_LAUNCH();
-    // residual norms of the instances in `which` into out[i]
-    auto residuals_of = [&](const std::vector<int> &which, std::vector<double> &out) {
-        for (int i : which) {
+    // Residual norms of the instances in `which` into out[i], batched: per
+    // instance first the update `before` records (the Newton step or a
+    // backtracking step; nothing for the start), then the residual.
+    auto residuals_of = [&](const std::vector<int> &which, std::vector<double> &out, auto &&before) {
+        batch_run_direct(B, which, [&](int i, std::vector<Step> &r) {
+            const Launch L{nullptr, &r};
             gl_mesh *m = B->meshes[i];
-            gl_residual_enqueue(m, psi[i], m->work.get() + 7 * (size_t)m->g.n, m->dscal.get(), B->s);
-        }
+            before(i, L);
+            gl_residual_enqueue(m, psi[i], m->work.get() + 7 * (size_t)m->g.n, m->dscal.get(), L);
+        });
         batch_gather(B);
         for (int i : which) out[i] = std::sqrt(B->host_sc[i].res2);
     };
@@ -1864,8 +1916,9 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
         std::vector<int> all;
         for (int i = 0; i < N; ++i)
             if (active[i]) all.push_back(i);
-        residuals_of(all, res);
+        residuals_of(all, res, [](int, const Launch &) {});
     };
+    auto dpsi = [&](int i) { return B->meshes[i]->work.get() + 8 * (size_t)B->meshes[i]->g.n; };
     using clk = std::chrono::steady_clock;
     auto since = [](clk::time_point t) { return std::chrono::duration<double>(clk::now() - t).count(); };
     auto t0 = clk::now();
@@ -1886,15 +1939,22 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
         if (act.empty()) break;
         t0 = clk::now();
         if (o.use_precond) {
+            // a new handle is built (and its tiles set) instance by instance;
+            // the numeric setups of existing handles run batched
+            std::vector<int> built;
             for (int i : act) {
-                const bool fresh = B->pre[i] == nullptr;
+                if (B->pre[i]) {
+                    built.push_back(i);
+                    continue;
+                }
                 gl_status ps = gl_precond_setup(B->meshes[i], psi[i], &o.amg, &B->pre[i], B->s);
-                if (ps == GL_OK && fresh) ps = gl_precond_set_tiles(B->pre[i], &B->tiles[i]);
+                if (ps == GL_OK) ps = gl_precond_set_tiles(B->pre[i], &B->tiles[i]);
                 if (ps != GL_OK) {
                     st[i] = ps;
                     active[i] = 0;
                 }
             }
+            batch_setups(B, psi, built, o.amg, st, active);
             std::vector<int> keep;
             for (int i : act)
                 if (active[i]) keep.push_back(i);
@@ -1904,26 +1964,25 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
         B->seconds[1] += since(t0);
         t0 = clk::now();
         batch_solve(B, psi, act, o, iters, st);
+        std::vector<int> upd;
         for (int i : act) {
             if (st[i] != GL_OK && st[i] != GL_ERR_NOT_CONVERGED) {
                 active[i] = 0;
                 continue;
             }
             st[i] = GL_OK;
-            gl_mesh *m = B->meshes[i];
-            const int n = m->g.n;
-            k_sub<<<blocks_for(n), kBlock, 0, B->s>>>(n, psi[i], m->work.get() + 8 * (size_t)n);
-            GLK_CHECK_LAUNCH();
             ni[i].krylov_iters[k] = iters[i];
             ni[i].steps = k + 1;
+            upd.push_back(i);
         }
         B->seconds[2] += since(t0);
         t0 = clk::now();
-        std::vector<int> upd;
-        for (int i : act)
-            if (active[i]) upd.push_back(i);
         std::vector<double> res_new(N, 0.0), alpha(N, 1.0);
-        residuals_of(upd, res_new);
+        // psi -= dpsi and the new residuals
+        residuals_of(upd, res_new, [&](int i, const Launch &L) {
+            const int n = B->meshes[i]->g.n;
+            L.run(blocks_for(n), NewtonSub{n, psi[i], dpsi(i)});
+        });
         // backtracking, the instances whose step does not reduce the residual
         // enough halve theirs together (as in gl_newton_solve)
         for (int h = 0; h < o.linesearch; ++h) {
@@ -1931,14 +1990,11 @@ static gl_status batch_newton(gl_batch *B, double2 *const *psi, const gl_newton_
             for (int i : upd)
                 if (!newton_accepts(res_new[i], res[i], alpha[i])) back.push_back(i);
             if (back.empty()) break;
-            for (int i : back) {
-                gl_mesh *m = B->meshes[i];
-                const int n = m->g.n;
-                k_axpy<<<blocks_for(n), kBlock, 0, B->s>>>(n, 0.5 * alpha[i], psi[i], m->work.get() + 8 * (size_t)n);
-                alpha[i] *= 0.5;
-            }
-            GLK_CHECK_LAUNCH();
-            residuals_of(back, res_new);
+            residuals_of(back, res_new, [&](int i, const Launch &L) {
+                const int n = B->meshes[i]->g.n;
+                L.run(blocks_for(n), NewtonAxpy{n, 0.5 * alpha[i], psi[i], dpsi(i)});
+            });
+            for (int i : back) alpha[i] *= 0.5;
         }
         B->seconds[0] += since(t0);
         for (int i : upd) {
@@ -1976,6 +2032,7 @@ gl_batch::~gl_batch()
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (s) (void)hipStreamDestroy(s);
     if (host_sc) (void)hipHostFree(host_sc);
+    if (host_status) (void)hipHostFree(host_status);
     if (staging) (void)hipHostFree(staging);
 }
 
@@ -2011,6 +2068,7 @@ gl_status gl_batch_create(int count, gl_mesh *const *meshes, gl_batch **out)
             GLK_HIP(hipMemcpy(B->ks_ptr.get(), kp.data(), sizeof(void *) * count, hipMemcpyHostToDevice));
             GLK_HIP(hipMemcpy(B->ds_ptr.get(), dp.data(), sizeof(void *) * count, hipMemcpyHostToDevice));
             GLK_HIP(hipHostMalloc(&B->host_sc, sizeof(BatchScalars) * count, hipHostMallocDefault));
+            GLK_HIP(hipHostMalloc(&B->host_status, sizeof(int) * count, hipHostMallocDefault));
         } catch (...) {
             delete B;
             throw;
@@ -2032,6 +2090,7 @@ gl_status gl_batch_newton_solve(gl_batch *batch, void *const *psi_inout, const g
                 if (psi_inout[j] == psi_inout[i]) fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: repeated psi");
         }
         check_krylov_opts(&opts->krylov, "gl_batch_newton_solve");
+        if (opts->use_precond) check_amg_opts(&opts->amg, "gl_batch_newton_solve");
         if (opts->max_steps < 0 || opts->max_steps > 63 || opts->fixed_steps < 0 || opts->fixed_steps > 63)
             fail(GL_ERR_INVALID_ARGUMENT, "gl_batch_newton_solve: steps must be in 0..63");
         if (opts->linesearch < 0 || opts->linesearch > 30)

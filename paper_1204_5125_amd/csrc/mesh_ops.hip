@@ -385,41 +385,59 @@ static void launch_links(gl_mesh *m, hipStream_t s)
 
 // ------------------------------------------------------- GL residual ---
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_gl_residual(GeomT<double> g, const double2 *__restrict__ psi,
-                                                        const LinkTab<double> U,
-                                                        double2 *__restrict__ out, RedSlot slot)
-{
-    __shared__ double sm[kBlock / 64];
-    const int i = xcd_tile(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-    double part = 0.0;
-    if (i < g.n) {
-        int c[3];
-        node_coords<DIM>(g.N, i, c);
-        const double2 p = psi[i];
-        double d, asum;
-        const double2 kp = khat_node<DIM, double>(g, i, c, psi, U, p, d, asum);
-        const double a2 = cabs2(p);
-        const double2 r = csub(cscale(kp, 1.0 / d), cscale(p, 1.0 - a2));
-        if (out) out[i] = r;
-        part = d * cabs2(r);
+struct GlResidual {
+    GeomT<double> g;
+    const double2 *__restrict__ psi;
+    LinkTab<double> U;
+    double2 *__restrict__ out;
+    RedSlot slot;
+    __device__ void operator()(int bx, int nbx) const
+    {
+        __shared__ double sm[kBlock / 64];
+        const int i = xcd_tile(bx, nbx) * kBlock + threadIdx.x;
+        double part = 0.0;
+        if (i < g.n) {
+            int c[3];
+            node_coords<DIM>(g.N, i, c);
+            const double2 p = psi[i];
+            double d, asum;
+            const double2 kp = khat_node<DIM, double>(g, i, c, psi, U, p, d, asum);
+            const double a2 = cabs2(p);
+            const double2 r = csub(cscale(kp, 1.0 / d), cscale(p, 1.0 - a2));
+            if (out) out[i] = r;
+            part = d * cabs2(r);
+        }
+        block_reduce_store(part, slot, sm, bx);
     }
-    block_reduce_store(part, slot, sm, blockIdx.x);
+};
+
+// residual into out (nullable) and its block partials in `slot`, then their
+// fixed-order sum into dresult
+static void residual_steps(const gl_mesh *m, const double2 *psi, double2 *out, RedSlot slot, double *dresult,
+                           const Launch &L, bool profiled)
+{
+    const int nb = blocks_for(m->g.n);
+    const GeomT<double> g = geom_t<double>(m->g);
+    const LinkTab<double> U = link_tab<double>(m);
+    const double bytes = 16.0 * m->g.n * (out ? 2 : 1);
+    auto run = [&] {
+        with_dim(m->g, [&](auto D) { L.run(nb, GlResidual<decltype(D)::value>{g, psi, U, out, slot}); });
+    };
+    if (profiled) prof_launch(PROF_GL, bytes, L, run);
+    else run();
+    launch_finalize(slot.partials, nb, FIN_STORE, nullptr, dresult, nullptr, L);
 }
 
 void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
                          hipStream_t s)
 {
-    const int nb = blocks_for(m->g.n);
-    const GeomT<double> g = geom_t<double>(m->g);
-    const double bytes = 16.0 * m->g.n * (out ? 2 : 1);
-    const LinkTab<double> U = link_tab<double>(m);
-    prof_launch(PROF_GL, bytes, s, [&] {
-        with_dim(m->g, [&](auto D) {
-            k_gl_residual<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, psi, U, out, red_slot(m, 0));
-        });
-    });
-    GLK_CHECK_LAUNCH();
-    launch_finalize(red_slot(m, 0).partials, nb, FIN_STORE, nullptr, dresult, nullptr, s);
+    residual_steps(m, psi, out, red_slot(m, 0), dresult, Launch{s}, true);
+}
+
+void gl_residual_enqueue(const gl_mesh *m, const double2 *psi, double2 *out, double *dresult,
+                         const Launch &L)
+{
+    residual_steps(m, psi, out, red_slot(m, 0), dresult, L, false);
 }
 
 // ------------------------------------- GL residual without allocation ---
@@ -1053,16 +1071,8 @@ gl_status gl_residual_noalloc(const gl_mesh *mesh, const void *psi, void *out, d
         hipStream_t s = as_stream(stream);
         // every partial is written by its block and the result by the
         // finalisation, so nothing has to be cleared between calls
-        const GeomT<double> g = geom_t<double>(mesh->g);
-        const LinkTab<double> U = link_tab<double>(mesh);
-        const RedSlot slot{sc};
-        with_dim(mesh->g, [&](auto D) {
-            k_gl_residual<decltype(D)::value><<<nb, kBlock, 0, s>>>(g, (const double2 *)psi, U, (double2 *)out, slot);
-        });
-        GLK_CHECK_LAUNCH();
         double *res = sc + kNoAllocParts;
-        launch_finalize(sc, nb, FIN_STORE, nullptr, res, nullptr, Launch{s});
-        GLK_CHECK_LAUNCH();
+        residual_steps(mesh, (const double2 *)psi, (double2 *)out, RedSlot{sc}, res, Launch{s}, false);
         if (norm_D) {
             double v = 0.0;
             GLK_HIP(hipMemcpyAsync(&v, res, sizeof(double), hipMemcpyDeviceToHost, s));
