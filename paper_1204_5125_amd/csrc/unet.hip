@@ -20,7 +20,9 @@
 //
 // Convolutions are implicit GEMMs: rows = pixels, columns = output channels,
 // reduction = 9 taps x input channels in slices of 32.  A wave owns a 32 x 32
-// output tile (2 x 2 MFMA tiles), a work-group four waves along the pixels.
+// or 32 x 64 output tile (2 x 2 or 2 x 4 MFMA tiles), a work-group four waves
+// along the pixels, or, in the deep layers, four waves that split the
+// reduction of one tile.
 // The weight gradient is a GEMM over pixels (split over work-groups, partial
 // sums reduced in a fixed order), staged through LDS.
 #include <algorithm>
@@ -36,9 +38,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 
 namespace glk {
 
-constexpr int kCi = 32;       // input channels per reduction slice
-constexpr int kConvPix = 128; // pixels per work-group
-constexpr int kConvCo = 32;   // output channels per work-group
+constexpr int kCi = 32;  // input channels per reduction slice
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_d(float z)
@@ -65,7 +65,15 @@ enum ConvMode { CONV_FWD = 0, CONV_DGRAD = 1, CONV_DGRAD_SILU = 2 };
 //   FWD:        z = acc + bias -> out0 (z), out1 (SiLU(z))
 //   DGRAD:      acc -> out0
 //   DGRAD_SILU: acc * SiLU'(zs[p][co]) -> out0
-template <int MODE>
+// Work-group of four waves; a wave owns 32 pixels x 16 WCO output channels
+// (2 x WCO MFMA tiles).  KS = 1: the waves take consecutive 32-pixel tiles
+// (128 pixels per work-group), each the whole reduction.  KS = 4: the four
+// waves share one 32-pixel tile and take every fourth reduction step; their
+// sums are added in LDS in wave order (the deep layers, whose few pixels
+// would otherwise leave most compute units without a wave).  The reduction
+// runs over steps (tap, 32-channel slice); each step's operand fragments are
+// loaded two steps ahead of its products.
+template <int MODE, int WCO, int KS>
 __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, int ldi, int cin, int H, int W,
                                                  const __bf16 *__restrict__ w, int cout,
                                                  const float *__restrict__ bias, __bf16 *out0, int ld0, int off0,
@@ -74,8 +82,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, 
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int P = H * W;
-    const int px0 = blockIdx.x * kConvPix + wave * 32;
-    const int co0 = blockIdx.y * kConvCo;
+    const int px0 = KS == 1 ? blockIdx.x * 128 + wave * 32 : blockIdx.x * 32;
+    const int co0 = blockIdx.y * (16 * WCO);
     const int kk = 8 * (lane >> 4), m = lane & 15;
     int py[2], pxx[2];
     bool pv[2];
@@ -86,60 +94,109 @@ __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, 
         py[r] = p / W;
         pxx[r] = p - py[r] * W;
     }
-    f4 acc[2][2];
+    f4 acc[2][WCO];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[r][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    const __bf16 *wrow[2];
+        for (int c = 0; c < WCO; ++c) acc[r][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    const __bf16 *wrow[WCO];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) wrow[c] = w + (size_t)(co0 + 16 * c + m) * 9 * cin + kk;
-    for (int tap = 0; tap < 9; ++tap) {
+    for (int c = 0; c < WCO; ++c) wrow[c] = w + (size_t)(co0 + 16 * c + m) * 9 * cin + kk;
+    const int nci = cin / kCi, S = 9 * nci;
+    auto load = [&](int st, bf16x8 (&a)[2], bf16x8 (&b)[WCO]) {
+        const int tap = st / nci, ci0 = (st - tap * nci) * kCi;
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const __bf16 *src[2];
-        bool ok[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int yy = py[r] + dy, xx = pxx[r] + dx;
-            ok[r] = pv[r] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            src[r] = in + (size_t)(ok[r] ? yy * W + xx : 0) * ldi + kk;
+            const bool ok = pv[r] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            a[r] = ok ? load8(in + (size_t)(yy * W + xx) * ldi + kk + ci0) : zero8();
         }
-        for (int ci0 = 0; ci0 < cin; ci0 += kCi) {
-            bf16x8 a[2], b[2];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) a[r] = ok[r] ? load8(src[r] + ci0) : zero8();
+        for (int c = 0; c < WCO; ++c) b[c] = load8(wrow[c] + tap * cin + ci0);
+    };
+    // fragments of this step (a, b) and the next two (a1, b1; a2, b2)
+    bf16x8 a[2], b[WCO], a1[2], b1[WCO];
+    int st = KS == 1 ? 0 : wave;
+    if (st < S) load(st, a, b);
+    if (st + KS < S) load(st + KS, a1, b1);
+    for (; st < S; st += KS) {
+        bf16x8 a2[2], b2[WCO];
+        if (st + 2 * KS < S) load(st + 2 * KS, a2, b2);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) b[c] = load8(wrow[c] + tap * cin + ci0);
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < WCO; ++c)
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            a[r] = a1[r];
+            a1[r] = a2[r];
+        }
+#pragma unroll
+        for (int c = 0; c < WCO; ++c) {
+            b[c] = b1[c];
+            b1[c] = b2[c];
+        }
+    }
+    if constexpr (KS > 1) {
+        __shared__ f4 red[KS - 1][2][WCO][64];
+        if (wave > 0)
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
-        }
+                for (int c = 0; c < WCO; ++c) red[wave - 1][r][c][lane] = acc[r][c];
+        __syncthreads();
+        if (wave > 0) return;
+        for (int v = 0; v < KS - 1; ++v)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int c = 0; c < WCO; ++c) acc[r][c] += red[v][r][c][lane];
     }
-    // D layout: row (pixel) 4 (lane / 16) + i, column (channel) lane % 16
+    // D layout: row (pixel) 4 (lane / 16) + i, column (channel) lane % 16.
+    // Each output tile goes through the wave's LDS slice so that a lane
+    // stores eight channels of one pixel (16 bytes) at a time.
+    __shared__ __bf16 stile[4][32][16 * WCO + 8];
+    auto emit = [&](auto value, __bf16 *out, int ld, int off) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int co = co0 + 16 * c + m;
+            for (int c = 0; c < WCO; ++c)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int p = px0 + 16 * r + 4 * (lane >> 4) + i;
-                if (p >= P) continue;
-                const float v = acc[r][c][i];
-                if (MODE == CONV_FWD) {
-                    const float z = v + bias[co];
-                    out0[(size_t)p * ld0 + off0 + co] = (__bf16)z;
-                    out1[(size_t)p * ld1 + off1 + co] = (__bf16)silu_f(z);
-                } else if (MODE == CONV_DGRAD) {
-                    out0[(size_t)p * ld0 + off0 + co] = (__bf16)v;
-                } else {
-                    const float z = (float)zs[(size_t)p * ldzs + co];
-                    out0[(size_t)p * ld0 + off0 + co] = (__bf16)(v * silu_d(z));
-                }
-            }
+                for (int i = 0; i < 4; ++i) stile[wave][16 * r + 4 * (lane >> 4) + i][16 * c + m] = value(r, c, i);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int q = lane; q < 64 * WCO; q += 64) {
+            const int row = q / (2 * WCO), ch = (q % (2 * WCO)) * 8;
+            const int p = px0 + row;
+            if (p < P)
+                *reinterpret_cast<bf16x8 *>(out + (size_t)p * ld + off + co0 + ch) =
+                    *reinterpret_cast<const bf16x8 *>(&stile[wave][row][ch]);
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    if constexpr (MODE == CONV_FWD) {
+        float bs[WCO];
+#pragma unroll
+        for (int c = 0; c < WCO; ++c) bs[c] = bias[co0 + 16 * c + m];
+        emit([&](int r, int c, int i) { return (__bf16)(acc[r][c][i] + bs[c]); }, out0, ld0, off0);
+        emit([&](int r, int c, int i) { return (__bf16)silu_f(acc[r][c][i] + bs[c]); }, out1, ld1, off1);
+    } else if constexpr (MODE == CONV_DGRAD) {
+        emit([&](int r, int c, int i) { return (__bf16)acc[r][c][i]; }, out0, ld0, off0);
+    } else {
+        emit(
+            [&](int r, int c, int i) {
+                const int p = px0 + 16 * r + 4 * (lane >> 4) + i;
+                const float z = p < P ? (float)zs[(size_t)p * ldzs + co0 + 16 * c + m] : 0.0f;
+                return (__bf16)(acc[r][c][i] * silu_d(z));
+            },
+            out0, ld0, off0);
+    }
 }
 
 // Weight gradient partials: part[s][co][tap][ci] = sum over the pixels of
@@ -209,15 +266,24 @@ __global__ void k_wgrad_reduce(const float *__restrict__ part, int splits, int c
 }
 
 // bias gradient partials: part[s][co] = sum over split s of dz[p][co]
-__global__ void k_bias_partial(const __bf16 *__restrict__ dz, int ldz, int cout, int P, int pix_per_split,
-                               float *__restrict__ part)
+// (256 threads; cout divides 256: thread t sums channel t mod cout over every
+// (256 / cout)-th pixel of the split, and the lanes of a channel are added in
+// lane order)
+__global__ __launch_bounds__(256) void k_bias_partial(const __bf16 *__restrict__ dz, int ldz, int cout, int P,
+                                                      int pix_per_split, float *__restrict__ part)
 {
+    __shared__ float sm[256];
     const int s = blockIdx.x;
     const int pbeg = s * pix_per_split, pend = min(P, pbeg + pix_per_split);
-    for (int co = threadIdx.x; co < cout; co += blockDim.x) {
-        float acc = 0.0f;
-        for (int p = pbeg; p < pend; ++p) acc += (float)dz[(size_t)p * ldz + co];
-        part[(size_t)s * cout + co] = acc;
+    const int lanes = 256 / cout, co = threadIdx.x % cout, l = threadIdx.x / cout;
+    float acc = 0.0f;
+    for (int p = pbeg + l; p < pend; p += lanes) acc += (float)dz[(size_t)p * ldz + co];
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < cout) {
+        float t = 0.0f;
+        for (int k = 0; k < lanes; ++k) t += sm[k * cout + threadIdx.x];
+        part[(size_t)s * cout + threadIdx.x] = t;
     }
 }
 
@@ -259,16 +325,20 @@ __global__ void k_down(int Nc, int C, const __bf16 *__restrict__ in, int ldi, in
 }
 
 // linear vertex interpolation to the finer grid, into channels [off, off + C) of out
+// (eight channels per thread: C, ldo and off are multiples of 8)
 __global__ void k_up(int Nc, int C, const __bf16 *__restrict__ in, __bf16 *__restrict__ out, int ldo, int off)
 {
-    const int Nf = 2 * Nc - 1;
+    const int Nf = 2 * Nc - 1, C8 = C / 8;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= Nf * Nf * C) return;
-    const int c = idx % C, q = idx / C, y = q / Nf, x = q % Nf;
+    if (idx >= Nf * Nf * C8) return;
+    const int c = (idx % C8) * 8, q = idx / C8, y = q / Nf, x = q % Nf;
     const int i0 = y >> 1, j0 = x >> 1, i1 = i0 + (y & 1), j1 = j0 + (x & 1);
-    const float v = 0.25f * ((float)in[(size_t)(i0 * Nc + j0) * C + c] + (float)in[(size_t)(i1 * Nc + j0) * C + c] +
-                             (float)in[(size_t)(i0 * Nc + j1) * C + c] + (float)in[(size_t)(i1 * Nc + j1) * C + c]);
-    out[(size_t)q * ldo + off + c] = (__bf16)v;
+    const bf16x8 a = load8(in + (size_t)(i0 * Nc + j0) * C + c), b = load8(in + (size_t)(i1 * Nc + j0) * C + c);
+    const bf16x8 d = load8(in + (size_t)(i0 * Nc + j1) * C + c), e = load8(in + (size_t)(i1 * Nc + j1) * C + c);
+    bf16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = (__bf16)(0.25f * ((float)a[j] + (float)b[j] + (float)d[j] + (float)e[j]));
+    *reinterpret_cast<bf16x8 *>(out + (size_t)q * ldo + off + c) = v;
 }
 
 // transpose of k_up: coarse node (i, j) gathers its fine neighbours
@@ -546,13 +616,39 @@ static void unet_alloc(gl_unet *u, int N)
     u->part.alloc(u->part_cap);
 }
 
+// A 3 x 3 convolution on an H x H grid: 64 output channels per wave where
+// cout allows, else 32; the reduction split over a work-group's waves when
+// 128-pixel work-groups would number fewer than eight per compute unit.
+template <int MODE>
+static void launch_conv(const __bf16 *in, int ldi, int cin, int H, const __bf16 *w, int cout, const float *bias,
+                        __bf16 *out0, int ld0, int off0, __bf16 *out1, int ld1, int off1, const __bf16 *zs, int ldzs,
+                        hipStream_t s)
+{
+    if (cin % kCi != 0 || cout % 32 != 0) fail(GL_ERR_INVALID_ARGUMENT, "conv3x3: channels must be multiples of 32");
+    const int64_t P = (int64_t)H * H;
+    const int wco = cout % 64 == 0 ? 4 : 2;
+    const int cot = cout / (16 * wco);
+    const bool split = (int64_t)blocks_for(P, 128) * cot < 2048;
+    const dim3 grid(split ? blocks_for(P, 32) : blocks_for(P, 128), cot);
+    auto go = [&](auto kern) {
+        kern<<<grid, 256, 0, s>>>(in, ldi, cin, H, H, w, cout, bias, out0, ld0, off0, out1, ld1, off1, zs, ldzs);
+    };
+    if (wco == 4) {
+        if (split) go(k_conv3x3<MODE, 4, 4>);
+        else go(k_conv3x3<MODE, 4, 1>);
+    } else {
+        if (split) go(k_conv3x3<MODE, 2, 4>);
+        else go(k_conv3x3<MODE, 2, 1>);
+    }
+    GLK_CHECK_LAUNCH();
+}
+
 static void conv_fwd(gl_unet *u, int li, const __bf16 *in, int ldi, int H, __bf16 *z, __bf16 *h, int ldh, int offh,
                      hipStream_t s)
 {
     const int cin = li == 0 ? 32 : u->cin[li], co = u->cout[li];
-    dim3 grid(blocks_for((int64_t)H * H, kConvPix), co / kConvCo);
-    k_conv3x3<CONV_FWD><<<grid, 256, 0, s>>>(in, ldi, cin, H, H, u->wf[li].get(), co,
-                                             u->theta.get() + u->boff[li], z, co, 0, h, ldh, offh, nullptr, 0);
+    launch_conv<CONV_FWD>(in, ldi, cin, H, u->wf[li].get(), co, u->theta.get() + u->boff[li], z, co, 0, h, ldh, offh,
+                          nullptr, 0, s);
 }
 
 // input gradient of layer li: out = W^T dz (* SiLU'(zs) when zs != NULL)
@@ -560,13 +656,10 @@ static void conv_dgrad(gl_unet *u, int li, const __bf16 *dz, int H, __bf16 *out,
                        hipStream_t s)
 {
     const int ci = u->cin[li], co = u->cout[li];
-    dim3 grid(blocks_for((int64_t)H * H, kConvPix), ci / kConvCo);
     if (zs)
-        k_conv3x3<CONV_DGRAD_SILU><<<grid, 256, 0, s>>>(dz, co, co, H, H, u->wt[li].get(), ci, nullptr, out, ldo, 0,
-                                                        nullptr, 0, 0, zs, ci);
+        launch_conv<CONV_DGRAD_SILU>(dz, co, co, H, u->wt[li].get(), ci, nullptr, out, ldo, 0, nullptr, 0, 0, zs, ci, s);
     else
-        k_conv3x3<CONV_DGRAD><<<grid, 256, 0, s>>>(dz, co, co, H, H, u->wt[li].get(), ci, nullptr, out, ldo, 0,
-                                                   nullptr, 0, 0, nullptr, 0);
+        launch_conv<CONV_DGRAD>(dz, co, co, H, u->wt[li].get(), ci, nullptr, out, ldo, 0, nullptr, 0, 0, nullptr, 0, s);
 }
 
 static void conv_wgrad(gl_unet *u, int li, const __bf16 *dz, const __bf16 *in, int ldi, int H, hipStream_t s)
@@ -583,6 +676,7 @@ static void conv_wgrad(gl_unet *u, int li, const __bf16 *dz, const __bf16 *in, i
     const int n = co * 9 * cin;
     k_wgrad_reduce<<<blocks_for(n), kBlock, 0, s>>>(u->part.get(), splits, co, cin_pad, cin,
                                                     u->grad.get() + u->woff[li]);
+    if (co > 256 || 256 % co != 0) fail(GL_ERR_INVALID_ARGUMENT, "bias gradient: c_out must divide 256");
     const int bs = std::min(256, std::max(1, P / 1024));
     const int bpps = (P + bs - 1) / bs;
     k_bias_partial<<<bs, 256, 0, s>>>(dz, co, co, P, bpps, u->part.get());
@@ -628,7 +722,7 @@ static void unet_forward(gl_unet *u, const gl_mesh *m, const double2 *psi, const
     for (int l = L - 2; l >= 0; --l) {
         const int H = u->Nl[l], Hc = u->Nl[l + 1], Cl = u->base << l, Cu = u->base << (l + 1);
         const int cc = Cu + Cl;
-        k_up<<<blocks_for((int64_t)H * H * Cu), kBlock, 0, s>>>(Hc, Cu, hc, u->cat[l].get(), cc, 0);
+        k_up<<<blocks_for((int64_t)H * H * Cu / 8), kBlock, 0, s>>>(Hc, Cu, hc, u->cat[l].get(), cc, 0);
         conv_fwd(u, dec_layer(u, l, 0), u->cat[l].get(), cc, H, u->dz0[l].get(), u->dh1[l].get(), Cl, 0, s);
         conv_fwd(u, dec_layer(u, l, 1), u->dh1[l].get(), Cl, H, u->dz1[l].get(), u->dh[l].get(), Cl, 0, s);
         hc = u->dh[l].get();
