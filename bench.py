@@ -809,7 +809,8 @@ def main():
                     help="jacobian: the 1M-node Jacobian solves (headline); batch: batched continuation; "
                          "continuation: learned vs secant predictor; cube: 3D 129^3 mixed precision; "
                          "meshind: R_1 iteration counts against grid size")
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=12,
+                    help="continuation: training epochs of the U-Net (12 take about 34 s at 513^2)")
     ap.add_argument("--arc-steps", type=int, default=60)
     ap.add_argument("--batch-max-coarse", type=int, default=64)
     ap.add_argument("--batch-plain", action="store_true",

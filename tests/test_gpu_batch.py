@@ -178,6 +178,15 @@ def test_batch_errors(glnk):
         batch.newton_solve([p[0], p[0]])
     with pytest.raises(glnk.GlnkError):
         batch.set_tiles(lane_shift=3)
+    with pytest.raises(glnk.GlnkError):
+        batch.newton_solve(p, precision=7)
+    # the batched numeric setups of existing handles keep each handle's
+    # hierarchy limits, as gl_precond_setup does
+    rc, _ = batch.newton_solve(p, fixed_steps=1)
+    assert rc == 0
+    with pytest.raises(glnk.GlnkError) as e:
+        batch.newton_solve(p, fixed_steps=1, max_coarse=32)
+    assert e.value.code == 1
 
 
 # Three instances of the 64-instance continuation workload: the first of its
