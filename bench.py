@@ -51,8 +51,8 @@ ONE_PASS_TILES = (0, 64, 4096)
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "929c8d9e845bf5fa065b3a5d6e2b32c3ef94503869f1c1870711bf62529fce68",
-           8: 4980731.5, 2: 21188651.9}
+TRAFFIC = {"csrc_sha256": "d6a740b895201aa07a10c5f09762290bc54b334710ee1ecb71f32712ce41aa5c",
+           8: 4980990.0, 2: 21189629.7}
 
 
 def csrc_fingerprint():
@@ -822,6 +822,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fixed-tiles", action="store_true",
+                    help="jacobian: skip the autotuner and use the tiles it picks on MI355X for this grid "
+                         "(lane_shift 0, bottom_rows 64, dense_rows 4096, level 0 one dispatch per pass), "
+                         "so that a profiled run times the configuration of an unprofiled one")
     ap.add_argument("--profile-kernel", type=int, default=8,
                     help="internal kernel id for the roofline (see gl_profile_start)")
     ap.add_argument("--one-pass", action="store_true",
@@ -873,8 +877,11 @@ def main():
     from paper_1204_5125_amd import autotune
     tiles = {}
     for name, prec in (("fp32", glnk.GL_FP32), ("fp64", glnk.GL_FP64)):
-        tiles[name] = autotune.tune(mesh, psi0, precision=prec, max_coarse=MAX_COARSE, cache=args.tile_cache,
-                                    log=log)
+        if args.fixed_tiles:
+            tiles[name] = ONE_PASS_TILES + (0,)
+        else:
+            tiles[name] = autotune.tune(mesh, psi0, precision=prec, max_coarse=MAX_COARSE, cache=args.tile_cache,
+                                        log=log)
         log(f"[bench] tiles {name}: lane_shift {tiles[name][0]}, bottom_rows {tiles[name][1]}, "
             f"dense_rows {tiles[name][2]}")
     log(f"[bench] grid {N_AXIS} n={mesh.n}; warm-up {args.warmup} step(s)")

@@ -3,8 +3,8 @@ FP64 oracle: forward output, loss, parameter gradient, Adam update, and a
 short training run.  Two architectures: 3 levels on a 17 x 17 grid, and the
 continuation benchmark's 4 levels / 32 base channels (32-256 channels, the
 384-channel decoder input) on 65 x 65, whose 256- and 384-channel layers
-take the weight gradient's capped pixel split; one forward pass at the
-benchmark's 513 x 513.  Tolerances follow BF16 storage (8 significant bits):
+take the weight gradient's capped pixel split; one forward pass and one
+gradient at the benchmark's 513 x 513.  Tolerances follow BF16 storage (8 significant bits):
 outputs and gradients within a few per cent in the L2 norm."""
 import numpy as np
 import pytest
@@ -98,7 +98,10 @@ def test_forward_full_size(glnk):
     assert e < 3e-2, e
 
 
-@pytest.mark.parametrize("arch", ARCHS, ids=ARCH_IDS)
+# the gradient also at the benchmark's 513 x 513, where the first level's
+# convolutions run with 128-pixel work-groups and the deeper ones split their
+# reduction over a work-group's waves (at 17 and 65 every layer splits)
+@pytest.mark.parametrize("arch", ARCHS + [(4, 32, 513, 8.0)], ids=ARCH_IDS + ["4lev-513"])
 def test_loss_and_gradient_match_oracle(glnk, arch):
     LEVELS, BASE, N, SIDE = arch
     mo, psi, psb, tgt = pair(2, N=N, SIDE=SIDE)
