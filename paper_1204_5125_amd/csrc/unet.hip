@@ -19,10 +19,10 @@
 // then b[2].
 //
 // Convolutions are implicit GEMMs: rows = pixels, columns = output channels,
-// reduction = 9 taps x input channels in slices of 32.  A wave owns a 32 x 32
-// or 32 x 64 output tile (2 x 2 or 2 x 4 MFMA tiles), a work-group four waves
-// along the pixels, or, in the deep layers, four waves that split the
-// reduction of one tile.
+// reduction = 9 taps x input channels in slices of 32.  A work-group owns an
+// 8 x 16-pixel block and 32 or 64 output channels (a wave two block rows:
+// 2 x 2 or 2 x 4 MFMA tiles), with each slice's input block (and halo) and
+// weights staged in LDS.
 // The weight gradient is a GEMM over pixels (split over work-groups, partial
 // sums reduced in a fixed order), staged through LDS.
 #include <algorithm>
@@ -65,116 +65,131 @@ enum ConvMode { CONV_FWD = 0, CONV_DGRAD = 1, CONV_DGRAD_SILU = 2 };
 //   FWD:        z = acc + bias -> out0 (z), out1 (SiLU(z))
 //   DGRAD:      acc -> out0
 //   DGRAD_SILU: acc * SiLU'(zs[p][co]) -> out0
-// Work-group of four waves; a wave owns 32 pixels x 16 WCO output channels
-// (2 x WCO MFMA tiles).  KS = 1: the waves take consecutive 32-pixel tiles
-// (128 pixels per work-group), each the whole reduction.  KS = 4: the four
-// waves share one 32-pixel tile and take every fourth reduction step; their
-// sums are added in LDS in wave order (the deep layers, whose few pixels
-// would otherwise leave most compute units without a wave).  The reduction
-// runs over steps (tap, 32-channel slice); each step's operand fragments are
-// loaded two steps ahead of its products.
-template <int MODE, int WCO, int KS>
+// A work-group computes an 8 x 16-pixel block of the image for 16 WCO output
+// channels; wave w owns the block's rows 2w and 2w + 1 (one 16-pixel MFMA
+// row tile each).  The reduction runs over 32-channel input slices: per
+// slice, the block's input with a one-pixel halo (10 x 18 pixels, zero
+// outside the image) and the slice's weights of all nine taps are staged in
+// LDS, so an input value is read from memory once per slice and channel tile
+// instead of once per tap, and a weight once per work-group instead of once
+// per wave.  The next slice's global loads are issued before the current
+// slice's products.
+constexpr int kBH = 8, kBW = 16;              // pixel block
+constexpr int kHH = kBH + 2, kHW = kBW + 2;   // with its halo
+constexpr int kSP = kCi + 8;                  // LDS row pitch (bf16): 80 bytes
+
+template <int WCO>
+struct ConvLds {
+    static constexpr int a_rows = kHH * kHW;        // halo pixels
+    static constexpr int b_rows = 9 * 16 * WCO;     // (tap, output channel)
+    static constexpr int na = a_rows * (kCi / 8);   // 16-byte pieces per slice
+    static constexpr int nb = b_rows * (kCi / 8);
+    static constexpr int ca = (na + 255) / 256;     // pieces per thread
+    static constexpr int cb = (nb + 255) / 256;
+    static constexpr int tile = 16 * WCO + 8;       // epilogue row pitch (bf16)
+    static constexpr int elems = (a_rows + b_rows) * kSP;
+    static_assert(4 * 32 * tile <= b_rows * kSP, "the epilogue tiles reuse the weight slice's LDS");
+};
+
+template <int MODE, int WCO>
 __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, int ldi, int cin, int H, int W,
                                                  const __bf16 *__restrict__ w, int cout,
                                                  const float *__restrict__ bias, __bf16 *out0, int ld0, int off0,
                                                  __bf16 *out1, int ld1, int off1, const __bf16 *__restrict__ zs,
-                                                 int ldzs)
+                                                 int ldzs, int bxs)
 {
+    using G = ConvLds<WCO>;
+    __shared__ __attribute__((aligned(16))) __bf16 lds[G::elems];
+    __bf16 *sA = lds, *sB = lds + G::a_rows * kSP;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int P = H * W;
-    const int px0 = KS == 1 ? blockIdx.x * 128 + wave * 32 : blockIdx.x * 32;
+    const int x0 = (blockIdx.x % bxs) * kBW, y0 = (blockIdx.x / bxs) * kBH;
     const int co0 = blockIdx.y * (16 * WCO);
     const int kk = 8 * (lane >> 4), m = lane & 15;
-    int py[2], pxx[2];
-    bool pv[2];
+    const int nci = cin / kCi;
+    bf16x8 ra[G::ca], rb[G::cb];
+    // global loads of slice s into registers (zero outside the image)
+    auto fetch = [&](int s) {
+        const int ci0 = s * kCi;
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int p = px0 + 16 * r + m;
-        pv[r] = p < P;
-        py[r] = p / W;
-        pxx[r] = p - py[r] * W;
-    }
+        for (int j = 0; j < G::ca; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            bf16x8 v = zero8();
+            if (q < G::na) {
+                const int h = q >> 2, part = (q & 3) * 8;
+                const int y = y0 - 1 + h / kHW, x = x0 - 1 + h % kHW;
+                if (y >= 0 && y < H && x >= 0 && x < W) v = load8(in + (size_t)(y * W + x) * ldi + ci0 + part);
+            }
+            ra[j] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < G::cb; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q < G::nb) {
+                const int row = q >> 2, part = (q & 3) * 8;
+                const int tap = row / (16 * WCO), col = row % (16 * WCO);
+                rb[j] = load8(w + (size_t)(co0 + col) * 9 * cin + tap * cin + ci0 + part);
+            }
+        }
+    };
     f4 acc[2][WCO];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < WCO; ++c) acc[r][c] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    const __bf16 *wrow[WCO];
+    fetch(0);
+    for (int s = 0; s < nci; ++s) {
+        __syncthreads();  // the previous slice's products are done with the LDS
 #pragma unroll
-    for (int c = 0; c < WCO; ++c) wrow[c] = w + (size_t)(co0 + 16 * c + m) * 9 * cin + kk;
-    const int nci = cin / kCi, S = 9 * nci;
-    auto load = [&](int st, bf16x8 (&a)[2], bf16x8 (&b)[WCO]) {
-        const int tap = st / nci, ci0 = (st - tap * nci) * kCi;
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int yy = py[r] + dy, xx = pxx[r] + dx;
-            const bool ok = pv[r] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            a[r] = ok ? load8(in + (size_t)(yy * W + xx) * ldi + kk + ci0) : zero8();
+        for (int j = 0; j < G::ca; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q < G::na) *reinterpret_cast<bf16x8 *>(sA + (q >> 2) * kSP + (q & 3) * 8) = ra[j];
         }
 #pragma unroll
-        for (int c = 0; c < WCO; ++c) b[c] = load8(wrow[c] + tap * cin + ci0);
-    };
-    // fragments of this step (a, b) and the next two (a1, b1; a2, b2)
-    bf16x8 a[2], b[WCO], a1[2], b1[WCO];
-    int st = KS == 1 ? 0 : wave;
-    if (st < S) load(st, a, b);
-    if (st + KS < S) load(st + KS, a1, b1);
-    for (; st < S; st += KS) {
-        bf16x8 a2[2], b2[WCO];
-        if (st + 2 * KS < S) load(st + 2 * KS, a2, b2);
+        for (int j = 0; j < G::cb; ++j) {
+            const int q = threadIdx.x + 256 * j;
+            if (q < G::nb) *reinterpret_cast<bf16x8 *>(sB + (q >> 2) * kSP + (q & 3) * 8) = rb[j];
+        }
+        __syncthreads();
+        if (s + 1 < nci) fetch(s + 1);
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            bf16x8 a[2], b[WCO];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                a[r] = *reinterpret_cast<const bf16x8 *>(sA + ((2 * wave + r + 1 + dy) * kHW + m + 1 + dx) * kSP + kk);
 #pragma unroll
             for (int c = 0; c < WCO; ++c)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            a[r] = a1[r];
-            a1[r] = a2[r];
-        }
-#pragma unroll
-        for (int c = 0; c < WCO; ++c) {
-            b[c] = b1[c];
-            b1[c] = b2[c];
-        }
-    }
-    if constexpr (KS > 1) {
-        __shared__ f4 red[KS - 1][2][WCO][64];
-        if (wave > 0)
+                b[c] = *reinterpret_cast<const bf16x8 *>(sB + (tap * 16 * WCO + 16 * c + m) * kSP + kk);
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
-                for (int c = 0; c < WCO; ++c) red[wave - 1][r][c][lane] = acc[r][c];
-        __syncthreads();
-        if (wave > 0) return;
-        for (int v = 0; v < KS - 1; ++v)
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int c = 0; c < WCO; ++c) acc[r][c] += red[v][r][c][lane];
+                for (int c = 0; c < WCO; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+        }
     }
-    // D layout: row (pixel) 4 (lane / 16) + i, column (channel) lane % 16.
-    // Each output tile goes through the wave's LDS slice so that a lane
-    // stores eight channels of one pixel (16 bytes) at a time.
-    __shared__ __bf16 stile[4][32][16 * WCO + 8];
+    __syncthreads();  // every wave is done with the weight slice: its LDS holds the epilogue tiles
+    // D layout: row (pixel) 4 (lane / 16) + i of the row tile, column (channel)
+    // lane % 16.  Each output tile goes through the wave's LDS tile so that a
+    // lane stores eight channels of one pixel (16 bytes) at a time.
+    __bf16 *stile = sB + wave * 32 * G::tile;
     auto emit = [&](auto value, __bf16 *out, int ld, int off) {
 #pragma unroll
         for (int r = 0; r < 2; ++r)
 #pragma unroll
             for (int c = 0; c < WCO; ++c)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) stile[wave][16 * r + 4 * (lane >> 4) + i][16 * c + m] = value(r, c, i);
+                for (int i = 0; i < 4; ++i) stile[(16 * r + 4 * (lane >> 4) + i) * G::tile + 16 * c + m] = value(r, c, i);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
         for (int q = lane; q < 64 * WCO; q += 64) {
             const int row = q / (2 * WCO), ch = (q % (2 * WCO)) * 8;
-            const int p = px0 + row;
-            if (p < P)
-                *reinterpret_cast<bf16x8 *>(out + (size_t)p * ld + off + co0 + ch) =
-                    *reinterpret_cast<const bf16x8 *>(&stile[wave][row][ch]);
+            const int y = y0 + 2 * wave + row / 16, x = x0 + row % 16;
+            if (y < H && x < W)
+                *reinterpret_cast<bf16x8 *>(out + (size_t)(y * W + x) * ld + off + co0 + ch) =
+                    *reinterpret_cast<const bf16x8 *>(stile + row * G::tile + ch);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -191,8 +206,8 @@ __global__ __launch_bounds__(256) void k_conv3x3(const __bf16 *__restrict__ in, 
     } else {
         emit(
             [&](int r, int c, int i) {
-                const int p = px0 + 16 * r + 4 * (lane >> 4) + i;
-                const float z = p < P ? (float)zs[(size_t)p * ldzs + co0 + 16 * c + m] : 0.0f;
+                const int y = y0 + 2 * wave + r, x = x0 + 4 * (lane >> 4) + i;
+                const float z = (y < H && x < W) ? (float)zs[(size_t)(y * W + x) * ldzs + co0 + 16 * c + m] : 0.0f;
                 return (__bf16)(acc[r][c][i] * silu_d(z));
             },
             out0, ld0, off0);
@@ -616,30 +631,26 @@ static void unet_alloc(gl_unet *u, int N)
     u->part.alloc(u->part_cap);
 }
 
-// A 3 x 3 convolution on an H x H grid: 64 output channels per wave where
-// cout allows, else 32; the reduction split over a work-group's waves when
-// 128-pixel work-groups would number fewer than eight per compute unit.
+// A 3 x 3 convolution on an H x H grid: 64 output channels per work-group
+// where cout allows and the grid still gets at least two work-groups per
+// compute unit, else 32.
 template <int MODE>
 static void launch_conv(const __bf16 *in, int ldi, int cin, int H, const __bf16 *w, int cout, const float *bias,
                         __bf16 *out0, int ld0, int off0, __bf16 *out1, int ld1, int off1, const __bf16 *zs, int ldzs,
                         hipStream_t s)
 {
-    if (cin % kCi != 0 || cout % 32 != 0) fail(GL_ERR_INVALID_ARGUMENT, "conv3x3: channels must be multiples of 32");
-    const int64_t P = (int64_t)H * H;
-    const int wco = cout % 64 == 0 ? 4 : 2;
-    const int cot = cout / (16 * wco);
-    const bool split = (int64_t)blocks_for(P, 128) * cot < 2048;
-    const dim3 grid(split ? blocks_for(P, 32) : blocks_for(P, 128), cot);
+    if (cin % kCi != 0 || cout % 32 != 0 || ldi < cin || ldi % 8 != 0)
+        fail(GL_ERR_INVALID_ARGUMENT, "conv3x3: channels must be multiples of 32");
+    const int bxs = (H + kBW - 1) / kBW, bys = (H + kBH - 1) / kBH;
+    const int64_t blocks = (int64_t)bxs * bys;
+    const int wco = (cout % 64 == 0 && blocks * (cout / 64) >= 512) ? 4 : 2;
+    const dim3 grid((unsigned)blocks, cout / (16 * wco));
     auto go = [&](auto kern) {
-        kern<<<grid, 256, 0, s>>>(in, ldi, cin, H, H, w, cout, bias, out0, ld0, off0, out1, ld1, off1, zs, ldzs);
+        kern<<<grid, 256, 0, s>>>(in, ldi, cin, H, H, w, cout, bias, out0, ld0, off0, out1, ld1, off1, zs, ldzs,
+                                  bxs);
     };
-    if (wco == 4) {
-        if (split) go(k_conv3x3<MODE, 4, 4>);
-        else go(k_conv3x3<MODE, 4, 1>);
-    } else {
-        if (split) go(k_conv3x3<MODE, 2, 4>);
-        else go(k_conv3x3<MODE, 2, 1>);
-    }
+    if (wco == 4) go(k_conv3x3<MODE, 4>);
+    else go(k_conv3x3<MODE, 2>);
     GLK_CHECK_LAUNCH();
 }
 
