@@ -36,7 +36,7 @@ NEWTON_STEPS = 4
 RTOL = 1e-10
 KERNEL_NAMES = {1: "MinresJapply", 2: "L0 Gauss-Seidel sweeps (L0PreBlack, L0Sweep, L0Last)",
                 3: "L0Residual", 4: "level-0 transfers (CsrSpmv restriction, L0ProlongBlack)", 5: "MinresVupdate", 6: "k_minres_wx",
-                7: "k_gl_residual", 8: "EllSgs (Gauss-Seidel colour sweep, levels >= 1)"}
+                7: "GlResidual", 8: "EllSgs (Gauss-Seidel colour sweep, levels >= 1)"}
 
 
 def log(msg):
