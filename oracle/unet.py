@@ -23,7 +23,8 @@ value by value:
   prediction      psi_pred = psi_b + dmu (o_re + i o_im): the network corrects
                   the base step (a zero network is the secant predictor).
 
-Loss of one sample (psi, psi_b, target) at (mu, dmu), the target already
+Loss of one sample (a design choice of this extension: the paper defines no
+network and no loss) (psi, psi_b, target) at (mu, dmu), the target already
 phase-aligned to psi, with w = (t - psi_b) / dmu the correction to learn:
 L = sum_i d_i |o_i - w_i|^2 / sum_i d_i (|w_i|^2 + EPS), i.e.
 ||D^(1/2)(psi_pred - t)||^2 relative to ||D^(1/2)(psi_b - t)||^2 (every
