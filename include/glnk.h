@@ -436,10 +436,14 @@ gl_status gl_batch_create(int count, gl_mesh *const *meshes, gl_batch **out);
 /* Newton (as gl_newton_solve) on every instance at once: psi_inout[i] is the
  * start and receives the result of instance i; infos (nullable) receives
  * count gl_newton_info records.  The preconditioner options and tile choices
- * apply to all instances.  Steps run in lock-step: one residual per instance,
- * one preconditioner setup, then the Jacobian solves of all unconverged
- * instances together.  Returns NOT_CONVERGED if any instance missed tol
- * (fixed_steps == 0), else the first failing status.  Synchronous. */
+ * apply to all instances.  Steps run in lock-step: the residuals, the
+ * numeric preconditioner setups (once an instance's preconditioner exists;
+ * it is built at the instance's first step, the hierarchy limits then fixed:
+ * INVALID_ARGUMENT if a later call changes max_coarse or max_levels), the
+ * Jacobian solves and the updates of all unconverged instances, each batched
+ * per shape group (one dispatch per kernel).  Returns NOT_CONVERGED if any
+ * instance missed tol (fixed_steps == 0), else the first failing status.
+ * Synchronous. */
 gl_status gl_batch_newton_solve(gl_batch *batch, void *const *psi_inout, const gl_newton_opts *opts,
                                 gl_newton_info *infos, gl_stream stream);
 
