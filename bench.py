@@ -34,6 +34,7 @@ SIDE = (10.0, 10.0)
 MU = 1.0
 NEWTON_STEPS = 4
 RTOL = 1e-10
+L0_TILED_NAME = "L0 Gauss-Seidel in LDS tiles (L0PreTile, L0PostTile)"
 KERNEL_NAMES = {1: "MinresJapply", 2: "L0 Gauss-Seidel sweeps (L0PreBlack, L0Sweep, L0Last)",
                 3: "L0Residual", 4: "level-0 transfers (CsrSpmv restriction, L0ProlongBlack)", 5: "MinresVupdate", 6: "k_minres_wx",
                 7: "GlResidual", 8: "EllSgs (Gauss-Seidel colour sweep, levels >= 1)"}
@@ -48,11 +49,15 @@ BATCH_HALVINGS = 3   # batched continuation: halvings of a step whose Newton fai
 # tiles of the single counter pass (--one-pass): the autotuner's choice for
 # this grid on MI355X, FP32 and FP64 alike (lane_shift, bottom_rows, dense_rows)
 ONE_PASS_TILES = (0, 64, 4096)
+# the autotuner's full choice without the profiler (--fixed-tiles): level 0 in
+# 16 x 16-node LDS tiles with the FP32 V-cycle, one dispatch per pass in FP64
+FIXED_TILES = {"fp32": ONE_PASS_TILES + (3,), "fp64": ONE_PASS_TILES + (0,)}
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
-# (calibrated on the copy), valid for the kernel sources with this fingerprint
-TRAFFIC = {"csrc_sha256": "49e7879a5aebd002295b37f536cb786fc707e8d8335266068a52c3e9ef979b7e",
-           8: 4980980.7, 2: 21191202.3}
+# (calibrated on the copy), valid for the kernel sources with this fingerprint;
+# "2t3": the level-0 class in 16 x 16 LDS tiles
+TRAFFIC = {"csrc_sha256": "8deb71f4605b6d2f61d213580b7921c52fafdf8c6883ae8d3f51251d7b7cf5ae",
+           8: 4967843.8, 2: 21190291.8, "2t3": 48790169.3}
 
 
 def csrc_fingerprint():
@@ -824,8 +829,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fixed-tiles", action="store_true",
                     help="jacobian: skip the autotuner and use the tiles it picks on MI355X for this grid "
-                         "(lane_shift 0, bottom_rows 64, dense_rows 4096, level 0 one dispatch per pass), "
-                         "so that a profiled run times the configuration of an unprofiled one")
+                         "(lane_shift 0, bottom_rows 64, dense_rows 4096; level 0 in 16 x 16 LDS tiles with "
+                         "the FP32 V-cycle, one dispatch per pass with FP64), so that a profiled run times "
+                         "the configuration of an unprofiled one")
     ap.add_argument("--profile-kernel", type=int, default=8,
                     help="internal kernel id for the roofline (see gl_profile_start)")
     ap.add_argument("--one-pass", action="store_true",
@@ -878,7 +884,7 @@ def main():
     tiles = {}
     for name, prec in (("fp32", glnk.GL_FP32), ("fp64", glnk.GL_FP64)):
         if args.fixed_tiles:
-            tiles[name] = ONE_PASS_TILES + (0,)
+            tiles[name] = FIXED_TILES[name]
         else:
             tiles[name] = autotune.tune(mesh, psi0, precision=prec, max_coarse=MAX_COARSE, cache=args.tile_cache,
                                         log=log)
@@ -923,15 +929,23 @@ def main():
     # HIP events on the stream they run on.  The coarse-level Gauss-Seidel
     # sweeps take the most GPU time (latency-bound small launches); the
     # level-0 sweeps move the most bytes.
+    # level 0 of the FP32 V-cycle: one dispatch per pass, or LDS tiles of
+    # shape l0_tiled (the same profile id; the counters are per form)
+    l0_form = tiles["fp32"][3] if len(tiles["fp32"]) > 3 else 0
+    names = dict(KERNEL_NAMES)
+    if l0_form:
+        names[2] = L0_TILED_NAME
+
     def profile(kid):
-        log(f"[bench] profiling kernel {kid} ({KERNEL_NAMES.get(kid)})")
+        log(f"[bench] profiling kernel {kid} ({names.get(kid)})")
         glnk.gl_profile_start(kid)
         run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, 1)
         ms, nbytes, launches = glnk.gl_profile_stop()
         avg_ms = ms / max(1, launches)
         achieved = (nbytes / max(1, launches)) / (avg_ms * 1e-3) / 1e9 if launches else 0.0
-        traffic = TRAFFIC.get(kid) if TRAFFIC["csrc_sha256"] == csrc_fingerprint() else None
-        return {"bound": "hbm", "kernel": KERNEL_NAMES.get(kid), "achieved": achieved, "peak": HBM_PEAK_GBS,
+        key = f"{kid}t{l0_form}" if kid == 2 and l0_form else kid
+        traffic = TRAFFIC.get(key) if TRAFFIC["csrc_sha256"] == csrc_fingerprint() else None
+        return {"bound": "hbm", "kernel": names.get(kid), "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "traffic_unit": "bytes per launch", "avg_launch_us": 1e3 * avg_ms,
                 "launches": launches, "bytes_per_launch": nbytes / max(1, launches),
@@ -947,7 +961,7 @@ def main():
         glnk.gl_profile_start(kid)
         infos = run_steps(glnk, torch, mesh, psi0, psi, h32, glnk.GL_FP32, 1)
         _, nbytes, _ = glnk.gl_profile_stop()
-        by_class[KERNEL_NAMES[kid]] = nbytes / max(1, sum(infos[-1]["krylov_iters"]))
+        by_class[names[kid]] = nbytes / max(1, sum(infos[-1]["krylov_iters"]))
     rest = iteration_bytes(glnk, h32, glnk.GL_FP32)
     bytes_iter = sum(by_class.values()) + rest
     t_iter32 = t32 / args.steps / sum(info32[-1]["krylov_iters"])

@@ -418,6 +418,36 @@ __device__ __forceinline__ void l0_pos(const L0TileAt &T0, int q, const int *N, 
     ring = min(min(lx, S::LX - 1 - lx), min(ly, S::LY - 1 - ly));
 }
 
+// Calls f(q, gx, gy) for the LDS nodes of colour col ((gx + gy) & 1) that
+// are at least rmin rings in from the LDS border and lie in the grid, the
+// threads taking them in turn: a pass visits only the nodes it updates, with
+// no lane idle on the other colour or outside its rings.
+template <class S, class F>
+__device__ __forceinline__ void l0_colour_nodes(const L0TileAt &T0, const int *N, int col, int rmin, F &&f)
+{
+    const int w = (S::LX - 2 * rmin) / 2, h = S::LY - 2 * rmin;
+    for (int k = threadIdx.x; k < w * h; k += S::threads) {
+        const int ly = rmin + k / w;
+        const int lx = rmin + 2 * (k % w) + ((col ^ (T0.x0 + T0.y0 + ly + rmin)) & 1);
+        const int gx = T0.x0 + lx, gy = T0.y0 + ly;
+        if (gx < 0 || gx >= N[0] || gy < 0 || gy >= N[1]) continue;
+        f(ly * S::LX + lx, gx, gy);
+    }
+}
+
+// Calls f(q, gx, gy) for the tile's own nodes (S::H rings in) that lie in the
+// grid.
+template <class S, class F>
+__device__ __forceinline__ void l0_tile_nodes(const L0TileAt &T0, const int *N, F &&f)
+{
+    for (int k = threadIdx.x; k < S::TX * S::TY; k += S::threads) {
+        const int ly = S::H + k / S::TX, lx = S::H + k % S::TX;
+        const int gx = T0.x0 + lx, gy = T0.y0 + ly;
+        if (gx >= N[0] || gy >= N[1]) continue;
+        f(ly * S::LX + lx, gx, gy);
+    }
+}
+
 // Down: b = round(v), red from zero, black, red, black residual (L0PreBlack,
 // L0Sweep(0), L0Residual); writes b and x of the tile's nodes and r of its
 // black nodes in the split layout.
@@ -456,32 +486,23 @@ struct L0PreTile {
         // black (exact one ring in), then red (two rings in)
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
-            const int col = pass == 0 ? 1 : 0;
-            for (int q = threadIdx.x; q < S::LN; q += S::threads) {
-                int gx, gy, ring;
-                bool in;
-                l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
-                if (!in || ring < pass + 1 || ((gx + gy) & 1) != col) continue;
+            l0_colour_nodes<S>(T0, g.N, pass == 0 ? 1 : 0, pass + 1, [&](int q, int gx, int gy) {
                 sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
-            }
+            });
             __syncthreads();
         }
         // the tile's nodes: b, x, and the black residual
         const int np = g.npair;
-        for (int q = threadIdx.x; q < S::LN; q += S::threads) {
-            int gx, gy, ring;
-            bool in;
-            l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
-            if (!in || ring < S::H) continue;
+        l0_tile_nodes<S>(T0, g.N, [&](int q, int gx, int gy) {
             const int col = (gx + gy) & 1;
             const int t = (gx >> 1) + g.hr * gy;
             C<T> ri = mk<T>(0, 0);
             if (col == 1) ri = csub(csub(sb[q], cscale(sx[q], sd[q])), l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy));
-            if (!gate_go) continue;
+            if (!gate_go) return;
             b[col * np + t] = sb[q];
             x[col * np + t] = sx[q];
             if (col == 1) r[np + t] = ri;
-        }
+        });
     }
 };
 
@@ -535,23 +556,14 @@ struct L0PostTile {
         // red (one ring in), black (two rings in)
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
-            const int col = pass;
-            for (int q = threadIdx.x; q < S::LN; q += S::threads) {
-                int gx, gy, ring;
-                bool in;
-                l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
-                if (!in || ring < pass + 1 || ((gx + gy) & 1) != col) continue;
+            l0_colour_nodes<S>(T0, g.N, pass, pass + 1, [&](int q, int gx, int gy) {
                 sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
-            }
+            });
             __syncthreads();
         }
         // last red on the tile, into z only; z on every node of the tile
         double part = 0.0;
-        for (int q = threadIdx.x; q < S::LN; q += S::threads) {
-            int gx, gy, ring;
-            bool in;
-            l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
-            if (!in || ring < S::H) continue;
+        l0_tile_nodes<S>(T0, g.N, [&](int q, int gx, int gy) {
             C<T> xi = sx[q];
             if (((gx + gy) & 1) == 0)
                 xi = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
@@ -560,7 +572,7 @@ struct L0PostTile {
             if (ADD) zi = cadd(z[i], zi);
             if (want_dot) part += redot(vdot[i], zi);
             if (gate_go) z[i] = zi;
-        }
+        });
         if (want_dot && gate_go) block_reduce_store(part, slot, sm, bx);
     }
 };
