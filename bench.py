@@ -55,9 +55,9 @@ FIXED_TILES = {"fp32": ONE_PASS_TILES + (3,), "fp64": ONE_PASS_TILES + (0,)}
 COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many bytes
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint;
-# "2t3": the level-0 class in 16 x 16 LDS tiles
+# "2t2", "2t3": the level-0 class in 32 x 16 and 16 x 16 LDS tiles
 TRAFFIC = {"csrc_sha256": "8deb71f4605b6d2f61d213580b7921c52fafdf8c6883ae8d3f51251d7b7cf5ae",
-           8: 4967843.8, 2: 21190291.8, "2t3": 48790169.3}
+           8: 4967843.8, 2: 21190291.8, "2t2": 48771832.3, "2t3": 48790169.3}
 
 
 def csrc_fingerprint():
