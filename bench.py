@@ -56,8 +56,8 @@ COPY_BYTES = 256 << 20   # counter calibration copy: reads and writes this many 
 # HBM bytes per launch from the FETCH_SIZE / WRITE_SIZE counter passes
 # (calibrated on the copy), valid for the kernel sources with this fingerprint;
 # "2t2", "2t3": the level-0 class in 32 x 16 and 16 x 16 LDS tiles
-TRAFFIC = {"csrc_sha256": "8deb71f4605b6d2f61d213580b7921c52fafdf8c6883ae8d3f51251d7b7cf5ae",
-           8: 4967843.8, 2: 21190291.8, "2t2": 48771832.3, "2t3": 48790169.3}
+TRAFFIC = {"csrc_sha256": "001a72ced063a46ec0329231d3fb9f116a665765e5dd16b1156c50e0eaf5befd",
+           8: 4971861.0, 2: 21189661.2, "2t2": 48767097.9, "2t3": 48785225.5}
 
 
 def csrc_fingerprint():

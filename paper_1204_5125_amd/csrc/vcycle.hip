@@ -376,20 +376,29 @@ __device__ __forceinline__ void l0_links(const GeomT<T> &g, const LinkTab<T> &U,
     uy = gy < g.N[1] - 1 ? link_u<2, T>(U, 1, c, gy) : mk<T>(0, 0);
 }
 
-// (sum_{j != i} H_ij x_j) of node (gx, gy) at LDS position q (2D); the link
-// of the edge towards the lower neighbour is that neighbour's forward link
-template <class T, int LX>
-__device__ __forceinline__ C<T> l0_offdiag_lds(const GeomT<T> &g, int gx, int gy, int q, const C<T> *sx,
-                                               const C<T> *ux, const C<T> *uy)
+// The edge coefficients alpha = |V| s_a / h_a^2 of node (gx, gy) along x and
+// y (the expression the one-pass kernels evaluate per node and pass), stored
+// per LDS node in the tile's load phase.
+template <class T>
+__device__ __forceinline__ void l0_alphas(const GeomT<T> &g, int gx, int gy, T &a0, T &a1)
 {
     const int c[3] = {gx, gy, 0};
     T s[3];
     const T d = node_volume<2, T>(g, c, s);
+    a0 = d * s[0] * g.inv_h2[0];
+    a1 = d * s[1] * g.inv_h2[1];
+}
+
+// (sum_{j != i} H_ij x_j) of node (gx, gy) at LDS position q (2D); the link
+// of the edge towards the lower neighbour is that neighbour's forward link
+template <class T, int LX>
+__device__ __forceinline__ C<T> l0_offdiag_lds(const GeomT<T> &g, int gx, int gy, int q, const C<T> *sx,
+                                               const C<T> *ux, const C<T> *uy, const T *sa0, const T *sa1)
+{
+    const T a0 = sa0[q], a1 = sa1[q];
     C<T> acc = mk<T>(0, 0);
-    const T a0 = d * s[0] * g.inv_h2[0];
     if (gx > 0) acc = csub(acc, cscale(cmul(ux[q - 1], sx[q - 1]), a0));
     if (gx < g.N[0] - 1) acc = csub(acc, cscale(cmulc(ux[q], sx[q + 1]), a0));
-    const T a1 = d * s[1] * g.inv_h2[1];
     if (gy > 0) acc = csub(acc, cscale(cmul(uy[q - LX], sx[q - LX]), a1));
     if (gy < g.N[1] - 1) acc = csub(acc, cscale(cmulc(uy[q], sx[q + LX]), a1));
     return acc;
@@ -464,7 +473,7 @@ struct L0PreTile {
     {
         GATE_LOAD();
         __shared__ C<T> sb[S::LN], sx[S::LN], ux[S::LN], uy[S::LN];
-        __shared__ T sd[S::LN];
+        __shared__ T sd[S::LN], sa0[S::LN], sa1[S::LN];
         const L0TileAt T0 = l0_tile<S>(xcd_tile(bx, nbx), ntx);
         for (int q = threadIdx.x; q < S::LN; q += S::threads) {
             int gx, gy, ring;
@@ -474,11 +483,17 @@ struct L0PreTile {
             const C<T> bi = in ? narrow<T>(v[i]) : mk<T>(0, 0);
             const T di = in ? hd[i] : (T)1;
             C<T> lx = mk<T>(0, 0), ly = lx;
-            if (in) l0_links<T>(g, U, gx, gy, lx, ly);
+            T a0 = (T)0, a1 = (T)0;
+            if (in) {
+                l0_links<T>(g, U, gx, gy, lx, ly);
+                l0_alphas<T>(g, gx, gy, a0, a1);
+            }
             sb[q] = bi;
             sd[q] = di;
             ux[q] = lx;
             uy[q] = ly;
+            sa0[q] = a0;
+            sa1[q] = a1;
             // red from zero: x = b / d
             sx[q] = in && ((gx + gy) & 1) == 0 ? cscale(bi, (T)1 / di) : mk<T>(0, 0);
         }
@@ -487,7 +502,7 @@ struct L0PreTile {
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             l0_colour_nodes<S>(T0, g.N, pass == 0 ? 1 : 0, pass + 1, [&](int q, int gx, int gy) {
-                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy, sa0, sa1)), (T)1 / sd[q]);
             });
             __syncthreads();
         }
@@ -497,7 +512,7 @@ struct L0PreTile {
             const int col = (gx + gy) & 1;
             const int t = (gx >> 1) + g.hr * gy;
             C<T> ri = mk<T>(0, 0);
-            if (col == 1) ri = csub(csub(sb[q], cscale(sx[q], sd[q])), l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy));
+            if (col == 1) ri = csub(csub(sb[q], cscale(sx[q], sd[q])), l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy, sa0, sa1));
             if (!gate_go) return;
             b[col * np + t] = sb[q];
             x[col * np + t] = sx[q];
@@ -527,7 +542,7 @@ struct L0PostTile {
     {
         GATE_LOAD();
         __shared__ C<T> sb[S::LN], sx[S::LN], ux[S::LN], uy[S::LN];
-        __shared__ T sd[S::LN];
+        __shared__ T sd[S::LN], sa0[S::LN], sa1[S::LN];
         __shared__ double sm[S::threads / 64];
         const L0TileAt T0 = l0_tile<S>(xcd_tile(bx, nbx), ntx);
         const int np = g.npair;
@@ -536,13 +551,14 @@ struct L0PostTile {
             bool in;
             l0_pos<S>(T0, q, g.N, gx, gy, in, ring);
             C<T> bi = mk<T>(0, 0), xi = mk<T>(0, 0), lx = xi, ly = xi;
-            T di = (T)1;
+            T di = (T)1, a0 = (T)0, a1 = (T)0;
             if (in) {
                 const int col = (gx + gy) & 1;
                 const int t = (gx >> 1) + g.hr * gy;
                 bi = b[col * np + t];
                 di = hd[gx + g.N[0] * gy];
                 l0_links<T>(g, U, gx, gy, lx, ly);
+                l0_alphas<T>(g, gx, gy, a0, a1);
                 // red values are recomputed from the black ones before any use
                 if (col == 1) xi = cadd(x[np + t], as_c<T>(prolong_row<TC>(prp, pci, pv, xc, t)));
             }
@@ -551,13 +567,15 @@ struct L0PostTile {
             sd[q] = di;
             ux[q] = lx;
             uy[q] = ly;
+            sa0[q] = a0;
+            sa1[q] = a1;
         }
         __syncthreads();
         // red (one ring in), black (two rings in)
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
             l0_colour_nodes<S>(T0, g.N, pass, pass + 1, [&](int q, int gx, int gy) {
-                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+                sx[q] = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy, sa0, sa1)), (T)1 / sd[q]);
             });
             __syncthreads();
         }
@@ -566,7 +584,7 @@ struct L0PostTile {
         l0_tile_nodes<S>(T0, g.N, [&](int q, int gx, int gy) {
             C<T> xi = sx[q];
             if (((gx + gy) & 1) == 0)
-                xi = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy)), (T)1 / sd[q]);
+                xi = cscale(csub(sb[q], l0_offdiag_lds<T, S::LX>(g, gx, gy, q, sx, ux, uy, sa0, sa1)), (T)1 / sd[q]);
             const int i = gx + g.N[0] * gy;
             double2 zi = widen(xi);
             if (ADD) zi = cadd(z[i], zi);
